@@ -1,0 +1,377 @@
+"""Pins of the CPU oracle against facts it does not compute itself.
+
+Each test checks the oracle against something fixed outside it: a value the
+paper prints, a closed form, a library routine on a special case, brute-force
+matrix exponentials, finite differences, or an invariant.  All run on CPU.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+from scipy.special import mathieu_a, mathieu_b
+
+import scp_inputs as si
+from oracle.single_mode import (DegenerateSpectrum, build_mode, displacement_matrix,
+                                dressed_truncation, fluxonium_basis, mode_derivatives,
+                                transmon_basis)
+from oracle.system import OracleSystem
+from oracle.rk4 import basis_columns, propagate
+from oracle.fidelity import average_gate_fidelity, cotangent, fidelity
+from oracle.adjoint import gradient, loss_and_grad, param_names
+from oracle.fd import fd_gradient
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TWO_PI = 2 * math.pi
+
+
+# ----------------------------------------------------------------------------
+# single-mode builders
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("ec,ratio", [(0.25, 50.0), (0.2, 40.0), (0.3, 60.0), (0.5, 3.0)])
+def test_transmon_levels_are_mathieu_characteristic_values(ec, ratio):
+    # At n_g = 0 the charge-basis levels are E_C {a0, b2, a2, b4, a4, ...}(q),
+    # q = -E_J / (2 E_C) (Mathieu characteristic values).
+    EC = ec * TWO_PI
+    EJ = EC * ratio
+    H, _, _, _ = transmon_basis(EC, EJ, 0.0, 21)
+    w = np.linalg.eigh(H)[0]
+    q = -EJ / (2 * EC)
+    ref = [EC * (mathieu_a(2 * ((k + 1) // 2), q) if k % 2 == 0 else mathieu_b(2 * ((k + 1) // 2), q))
+           for k in range(6)]
+    np.testing.assert_allclose(w[:6], ref, rtol=1e-10, atol=1e-9 * abs(ref[0]))
+
+
+def test_transmon_koch_asymptotic_frequency():
+    EC = 0.25 * TWO_PI
+    EJ = 50 * EC
+    m = build_mode({"kind": "transmon", "EC": EC, "EJ": EJ, "ng": 0.0, "basis_dim": 21, "trunc": 4})
+    approx = math.sqrt(8 * EJ * EC) - EC
+    assert abs(m["eps"][1] - approx) / approx < 5e-3
+
+
+def test_fluxonium_paper_printed_frequencies():
+    gold = json.load(open(os.path.join(GOLDEN, "fluxonium_omega01.json")))
+    for c in gold["cases"]:
+        m = build_mode({"kind": "fluxonium", "EC": c["EC"] * TWO_PI, "EJ": c["EJ"] * TWO_PI,
+                        "EL": c["EL"] * TWO_PI, "phiext": math.pi, "basis_dim": 80, "trunc": 5})
+        f01 = m["eps"][1] / TWO_PI
+        assert abs(f01 - c["omega01_ghz"]) <= gold["tolerance_ghz"], (c, f01)
+
+
+def test_displacement_elements_match_matrix_exponential():
+    # exp(i phi) from expm of the phase operator in a large HO basis agrees
+    # with the Laguerre closed form on the low block.
+    phi_osc = (8 * 1.0 / 0.9) ** 0.25
+    Kbig = 220
+    a = np.diag(np.sqrt(np.arange(1, Kbig)), k=1)
+    phi = phi_osc / math.sqrt(2) * (a + a.T)
+    ref = expm(1j * phi)[:40, :40]
+    got = displacement_matrix(1j * phi_osc / math.sqrt(2), 40, 40)
+    np.testing.assert_allclose(got, ref, atol=1e-11)
+
+
+def test_fluxonium_cos_from_eigendecomposition_of_phi():
+    # Alternative construction: cos(phi - phiext) = V cos(L - phiext) V^T from the
+    # eigendecomposition of a large truncated phi; low spectrum must agree.
+    EC, EJ, EL = 1.0 * TWO_PI, 4.0 * TWO_PI, 1.0 * TWO_PI
+    H, ops, _, _ = fluxonium_basis(EC, EJ, EL, math.pi, 80)
+    K = 200
+    phi_osc = (8 * EC / EL) ** 0.25
+    a = np.diag(np.sqrt(np.arange(1, K)), k=1)
+    phi = phi_osc / math.sqrt(2) * (a + a.T)
+    lam, V = np.linalg.eigh(phi)
+    cosm = (V * np.cos(lam - math.pi)) @ V.T
+    wp = math.sqrt(8 * EC * EL)
+    H2 = np.diag(wp * (np.arange(K) + 0.5)) - EJ * cosm
+    w1 = np.linalg.eigh(H)[0][:6]
+    w2 = np.linalg.eigh(H2)[0][:6]
+    np.testing.assert_allclose(w1 - w1[0], w2 - w2[0], atol=1e-7 * TWO_PI)
+
+
+def test_dressed_operator_symmetries_and_sign_convention():
+    m = build_mode({"kind": "fluxonium", "EC": TWO_PI, "EJ": 4 * TWO_PI, "EL": 0.9 * TWO_PI,
+                    "phiext": math.pi, "basis_dim": 80, "trunc": 5})
+    n, phi = m["ops"]["n"], m["ops"]["phi"]
+    np.testing.assert_allclose(n.real, 0, atol=1e-12)                 # i x antisymmetric
+    np.testing.assert_allclose(n, -n.T, atol=1e-12)
+    np.testing.assert_allclose(phi.imag, 0, atol=1e-12)               # real symmetric
+    np.testing.assert_allclose(phi, phi.T, atol=1e-12)
+    V = m["V"]
+    for c in range(V.shape[1]):
+        col = V[:, c]
+        mx = np.abs(col).max()
+        k = int(np.nonzero(np.abs(col) >= mx * (1 - 1e-12))[0][0])
+        assert col[k] > 0
+    # transmon odd states at n_g = 0: exact +-n tie resolved at the lowest index
+    t = build_mode({"kind": "transmon", "EC": 0.25 * TWO_PI, "EJ": 12.5 * TWO_PI, "ng": 0.0,
+                    "basis_dim": 21, "trunc": 4})
+    v1 = t["V"][:, 1]
+    k = int(np.argmax(np.abs(v1)))
+    assert v1[k] > 0 and abs(v1[20 - k]) == pytest.approx(abs(v1[k]), rel=1e-12)
+
+
+def test_degenerate_levels_raise():
+    with pytest.raises(DegenerateSpectrum):
+        dressed_truncation(np.diag([0.0, 1.0, 1.0, 2.0]), {"n": np.eye(4, dtype=complex)}, 3)
+
+
+@pytest.mark.parametrize("kind", ["transmon", "fluxonium"])
+def test_mode_derivatives_match_finite_differences(kind):
+    base = {"kind": kind, "EC": 0.9 * TWO_PI if kind == "fluxonium" else 0.25 * TWO_PI,
+            "EJ": 4.2 * TWO_PI if kind == "fluxonium" else 12.0 * TWO_PI,
+            "EL": 1.05 * TWO_PI if kind == "fluxonium" else 0.0, "ng": 0.0, "phiext": math.pi,
+            "basis_dim": 80 if kind == "fluxonium" else 21, "trunc": 4}
+    m0 = build_mode(base)
+    for p in ("EJ", "EC", "EL"):
+        if kind == "transmon" and p == "EL":
+            continue
+        hstep = 1e-5 * base[p]
+        mp = build_mode(dict(base, **{p: base[p] + hstep}))
+        mm = build_mode(dict(base, **{p: base[p] - hstep}))
+        np.testing.assert_allclose((mp["eps"] - mm["eps"]) / (2 * hstep), m0["deps"][p],
+                                   rtol=1e-6, atol=1e-9)
+        for name in m0["ops"]:
+            fd = (mp["ops"][name] - mm["ops"][name]) / (2 * hstep)
+            np.testing.assert_allclose(fd, m0["dops"][p][name], rtol=1e-5, atol=1e-8)
+
+
+# ----------------------------------------------------------------------------
+# RK4 propagation
+# ----------------------------------------------------------------------------
+def test_rabi_closed_form_and_fourth_order():
+    # Two-level system, energies (0, D), constant drive Omega sigma_x, no carrier:
+    # P1(T) = Omega^2/W^2 sin^2(W T), W = sqrt(Omega^2 + D^2/4).
+    delta, om, T = 0.7, 0.9, 3.0
+    W = math.sqrt(om ** 2 + delta ** 2 / 4)
+    P1 = om ** 2 / W ** 2 * math.sin(W * T) ** 2
+    errs = []
+    for N in (100, 200, 400):
+        U = propagate(OracleSystem(si.rabi_system(delta, om, T, N)))
+        errs.append(abs(abs(U[1, 0]) ** 2 - P1))
+    assert errs[-1] < 1e-10
+    assert 12 < errs[0] / errs[1] < 20 and 12 < errs[1] / errs[2] < 20
+
+
+def _kron_op(dims, op, m):
+    mats = [np.eye(d) for d in dims]
+    mats[m] = op
+    out = mats[0]
+    for M in mats[1:]:
+        out = np.kron(out, M)
+    return out
+
+
+def _dense_static(s):
+    H = sum(_kron_op(s.dims, np.diag(s.modes[m]["eps"]), m) for m in range(s.n_modes))
+    for c in s.couplings:
+        H = H + c["g"] * _kron_op(s.dims, s.op(c["i"], c["op_i"]), c["i"]) @ \
+            _kron_op(s.dims, s.op(c["j"], c["op_j"]), c["j"])
+    Hf = sum(_kron_op(s.dims, np.diag(s.frame[m]), m) for m in range(s.n_modes))
+    return H, Hf
+
+
+def test_constant_hamiltonian_matches_dense_exponential():
+    # Drives off and a frame that differs from the mode energies (so the diagonal
+    # term is active): exp(-i H_f T) U_I = expm(-i H0 T) from a dense matrix.
+    desc = si.config1()
+    desc["drives"] = []
+    desc["T"] = 4.0
+    desc["n_steps"] = 800
+    s0 = OracleSystem(desc)
+    for md, m in zip(desc["modes"], s0.modes):
+        md["frame_eps"] = m["eps"] * 1.0003
+    s = OracleSystem(desc)
+    U = propagate(s)
+    H, Hf = _dense_static(s)
+    ref = expm(1j * Hf * s.T) @ expm(-1j * H * s.T)
+    np.testing.assert_allclose(U, ref[:, desc["columns"]], atol=2e-7)
+
+
+def test_piecewise_constant_drive_matches_product_of_exponentials():
+    desc = si.random_raw_system(1, [2, 3, 2], 3, 2.0, 400, env="pwc", n_pieces=4)
+    s = OracleSystem(desc)
+    U = propagate(s)
+    H0, Hf = _dense_static(s)
+    Uf = np.eye(s.D, dtype=complex)
+    for p in range(4):
+        Hp = H0.copy()
+        for dr in s.drives:
+            Hp = Hp + dr["params"][p] * _kron_op(s.dims, s.op(dr["mode"], dr["op"]), dr["mode"])
+        Uf = expm(-1j * Hp * (s.T / 4)) @ Uf
+    ref = expm(1j * Hf * s.T) @ Uf
+    np.testing.assert_allclose(U, ref[:, desc["columns"]], atol=1e-10)
+
+
+def test_fourth_order_convergence_and_unitarity_with_carrier():
+    desc = si.random_raw_system(2, [3, 2], 1, 3.0, 1, env="gauss")
+    desc["columns"] = list(range(6))
+    ref_desc = dict(desc, n_steps=3200)
+    Uref = propagate(OracleSystem(ref_desc))
+    errs, unit = [], []
+    for N in (100, 200, 400):
+        U = propagate(OracleSystem(dict(desc, n_steps=N)))
+        errs.append(np.linalg.norm(U - Uref, 2))
+        unit.append(np.linalg.norm(U.conj().T @ U - np.eye(6), 2))
+    assert 13 < errs[0] / errs[1] < 19 and 13 < errs[1] / errs[2] < 19
+    assert unit[0] / unit[1] > 12 and unit[1] / unit[2] > 12
+
+
+# ----------------------------------------------------------------------------
+# fidelity
+# ----------------------------------------------------------------------------
+def _haar(n, rng):
+    z = (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) / math.sqrt(2)
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / abs(np.diag(r)))
+
+
+def test_fidelity_identities():
+    rng = np.random.default_rng(5)
+    Ut = _haar(4, rng)
+    rows, cols = [0, 1, 2, 3], [0, 1, 2, 3]
+    assert fidelity(Ut, rows, cols, Ut)[0] == pytest.approx(1.0, abs=1e-14)
+    U = _haar(4, rng)
+    F1, _ = fidelity(U, rows, cols, Ut)
+    F2, _ = fidelity(U * np.exp(0.37j), rows, cols, Ut)
+    assert F1 == pytest.approx(F2, abs=1e-14)
+    # diagonal target: F unchanged by any sign flip of basis vectors
+    T = np.diag(np.exp(1j * rng.uniform(0, 6, 4)))
+    S = np.diag([1, -1, -1, 1]).astype(complex)
+    assert fidelity(U, rows, cols, T)[0] == pytest.approx(fidelity(S @ U @ S, rows, cols, T)[0],
+                                                           abs=1e-14)
+
+
+def test_average_gate_fidelity_relation_against_operator_basis_formula():
+    # App. D: F_avg = (sum_j tr(U_j^dag E(U_j)) + D^2) / (D^2 (D+1)) over an
+    # orthonormal operator basis (Weyl basis here) equals (D F + 1)/(D + 1) for
+    # E(rho) = V rho V^dag with V = U_t^dag U.
+    rng = np.random.default_rng(11)
+    Dd = 3
+    Ut, U = _haar(Dd, rng), _haar(Dd, rng)
+    V = Ut.conj().T @ U
+    w = np.exp(2j * math.pi / Dd)
+    X = np.roll(np.eye(Dd), 1, axis=0)
+    Z = np.diag([w ** k for k in range(Dd)])
+    basis = [np.linalg.matrix_power(X, a) @ np.linalg.matrix_power(Z, b) / math.sqrt(Dd)
+             for a in range(Dd) for b in range(Dd)]
+    tot = sum(np.trace(Uj.conj().T @ V @ Uj @ V.conj().T) for Uj in basis)
+    Favg = (tot.real * Dd + Dd ** 2) / (Dd ** 2 * (Dd + 1))
+    F, _ = fidelity(U, range(Dd), range(Dd), Ut)
+    assert average_gate_fidelity(F, Dd) == pytest.approx(Favg, abs=1e-12)
+
+
+def test_cotangent_is_the_wirtinger_gradient():
+    rng = np.random.default_rng(3)
+    U = rng.normal(size=(6, 4)) + 1j * rng.normal(size=(6, 4))
+    rows, cols = [0, 2, 3, 5], [0, 1, 2, 3]
+    T = _haar(4, rng)
+    F, tau = fidelity(U, rows, cols, T)
+    lam = cotangent(U.shape, rows, cols, T, tau)
+    dU = rng.normal(size=U.shape) + 1j * rng.normal(size=U.shape)
+    e = 1e-6
+    Lp = 1 - fidelity(U + e * dU, rows, cols, T)[0]
+    Lm = 1 - fidelity(U - e * dU, rows, cols, T)[0]
+    assert (Lp - Lm) / (2 * e) == pytest.approx(2 * np.vdot(lam, dU).real, rel=1e-7)
+
+
+# ----------------------------------------------------------------------------
+# adjoint gradient
+# ----------------------------------------------------------------------------
+def _small_transmon():
+    desc = si.config1()
+    desc["T"], desc["n_steps"] = 10.0, 200
+    desc["drives"][0]["sigma"] = 2.5
+    return desc
+
+
+def _small_fluxonium():
+    desc = si.config3()
+    desc["modes"] = desc["modes"][:2]
+    desc["couplings"] = desc["couplings"][:2]
+    desc["drives"] = desc["drives"][:1]
+    desc["drives"][0]["params"] = desc["drives"][0]["params"][:3]
+    desc["drives"][0]["sigma"] = 5.0 / 3
+    desc["T"], desc["n_steps"] = 5.0, 100
+    return si._finish(desc, [5, 5], target=si.cz_target(2))
+
+
+@pytest.mark.parametrize("make", [_small_transmon, _small_fluxonium])
+def test_adjoint_gradient_matches_central_differences(make):
+    desc = make()
+    s = OracleSystem(desc)
+    L, F, tau, U, g = loss_and_grad(s)
+    fd = fd_gradient(desc, range(len(g)))
+    fdv = np.array([fd[i] for i in range(len(g))])
+    scale = np.abs(fdv).max()
+    assert np.abs(g - fdv).max() <= 1e-6 * scale
+    big = np.abs(fdv) > 1e-3 * scale
+    np.testing.assert_allclose(g[big], fdv[big], rtol=2e-6)
+
+
+def test_gradient_independent_of_checkpoint_interval():
+    desc = _small_transmon()
+    desc["n_steps"] = 49
+    s = OracleSystem(desc)
+    U = propagate(s)
+    F, tau = fidelity(U, desc["comp_rows"], desc["comp_cols"], desc["target"])
+    lam = cotangent(U.shape, desc["comp_rows"], desc["comp_cols"], desc["target"], tau)
+    gs = [gradient(s, lam, ckpt_every=c)[0] for c in (1, 7, 49)]
+    assert np.array_equal(gs[0], gs[1]) and np.array_equal(gs[1], gs[2])
+
+
+def test_gradient_matches_torch_autograd_through_rk4():
+    # Reverse-mode autodiff through the same RK4 steps (the paper's TAD
+    # comparison) for the drive amplitude and coupling, torch float64 on CPU.
+    torch = pytest.importorskip("torch")
+    desc = si.random_raw_system(4, [2, 3], 1, 1.5, 60, env="gauss")
+    s = OracleSystem(desc)
+    L, F, tau, U, g = loss_and_grad(s)
+    names = param_names(s)
+    amp = [torch.tensor(dr["params"][0], dtype=torch.float64, requires_grad=True) for dr in s.drives]
+    gc = torch.tensor(s.couplings[0]["g"], dtype=torch.float64, requires_grad=True)
+    dims, D = s.dims, s.D
+    ops = {(m, k): torch.tensor(s.modes[m]["ops"][k]) for m in range(2) for k in ("n", "phi")}
+    eye = [torch.eye(d, dtype=torch.complex128) for d in dims]
+
+    def full(op, m):
+        mats = list(eye)
+        mats[m] = op
+        return torch.kron(mats[0], mats[1])
+
+    def rot(m, op, t):
+        f = torch.tensor(s.frame[m])
+        return op * torch.exp(1j * (f[:, None] - f[None, :]) * t)
+
+    def V(n, st):
+        t = s.stage_time(n, st)
+        c = s.couplings[0]
+        out = gc * full(rot(c["i"], ops[(c["i"], c["op_i"])], t), c["i"]) @ \
+            full(rot(c["j"], ops[(c["j"], c["op_j"])], t), c["j"])
+        for k, dr in enumerate(s.drives):
+            sig = dr["sigma"]
+            env = amp[k] * math.exp(-((t - s.T / 2) ** 2) / (2 * sig * sig))
+            out = out + env * math.cos(dr["omega_d"] * t + dr["phase"]) * \
+                full(rot(dr["mode"], ops[(dr["mode"], dr["op"])], t), dr["mode"])
+        return out
+
+    psi = torch.tensor(basis_columns(D, desc["columns"]))
+    h = s.h
+    for n in range(s.N):
+        k1 = -1j * V(n, 0) @ psi
+        k2 = -1j * V(n, 1) @ (psi + h / 2 * k1)
+        k3 = -1j * V(n, 2) @ (psi + h / 2 * k2)
+        k4 = -1j * V(n, 3) @ (psi + h * k3)
+        psi = psi + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    P = psi[desc["comp_rows"]][:, desc["comp_cols"]]
+    T = torch.tensor(desc["target"])
+    tau_t = torch.sum(torch.conj(T) * P)
+    Lt = 1 - torch.abs(tau_t) ** 2 / len(desc["comp_rows"]) ** 2
+    Lt.backward()
+    assert float(Lt) == pytest.approx(L, abs=1e-13)
+    for k in range(len(s.drives)):
+        i = names.index(f"drive{k}.p0")
+        assert float(amp[k].grad) == pytest.approx(g[i], rel=1e-9, abs=1e-13)
+    assert float(gc.grad) == pytest.approx(g[names.index("coupling0.g")], rel=1e-9, abs=1e-13)
