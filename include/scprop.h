@@ -1,0 +1,202 @@
+/*
+ * scprop.h -- C ABI of libscprop: differentiable propagation of composite
+ * superconducting-qubit systems on one MI355X (gfx950).
+ *
+ * What is computed (arXiv:2406.18155, SuperGrad):
+ *   - single-mode Hamiltonians of transmons and fluxoniums, diagonalised and
+ *     truncated to their lowest d levels (Sec. 3.1 fluxonium Hamiltonian;
+ *     App. D step 1);
+ *   - the composite Hamiltonian as a sum of local one- and two-body terms
+ *     (Sec. 2.1, Hamiltonian decomposition; Sec. 3.1 multipath coupling) with
+ *     microwave drives c(t) = E(t) cos(omega_d t + phase) on one operator of a
+ *     mode (App. C, microwave control Hamiltonian);
+ *   - the time-ordered propagator over a fixed step grid (Sec. 2.3), here by
+ *     classical RK4 in the interaction picture of the frame
+ *     H_f = sum_m diag(eps^f_m) (fixed at build), applied one mode's local
+ *     operator at a time (App. B, contraction of local operators with the
+ *     state tensor);
+ *   - the gate fidelity F = |Tr(T^dag P U P)|^2 / d_c^2 (Sec. 4.1, composite
+ *     state-transfer cost; App. D average fidelity);
+ *   - the gradient of L = 1 - F w.r.t. pulse and device parameters by a
+ *     discrete adjoint of the RK4 steps with checkpoints (Sec. 2.5, the
+ *     per-step derivative sum and the chain rule for the costate).
+ *
+ * Units: energies and rates in rad/ns (GHz * 2 pi), times in ns, hbar = 1.
+ *
+ * State layout: a block of S columns, each a vector of D = prod_m d_m
+ * complex amplitudes, column-major (column s starts at s*D).  Within a
+ * column the index is sum_m a_m * stride_m with mode 0 slowest
+ * (stride_m = prod_{m' > m} d_m').  Precision 0 stores complex64
+ * (interleaved float re, im), precision 1 complex128.
+ *
+ * Conventions for every call:
+ *   - the caller owns every buffer it passes (device pointers come from the
+ *     caller's allocator, e.g. torch); ``scp_system`` owns its device tables
+ *     and is freed by ``scp_destroy``;
+ *   - ``stream`` is a hipStream_t passed as void* (NULL = default stream);
+ *     device work is enqueued asynchronously on it; calls that return values
+ *     through host pointers synchronise that stream first;
+ *   - no C++ exception crosses the ABI; every call returns an scp_status and
+ *     records a message readable with scp_last_error() on the same thread;
+ *   - scp_propagate / scp_propagate_adjoint / scp_apply_generator /
+ *     scp_fidelity allocate no device memory (the workspace is the caller's).
+ */
+#ifndef SCPROP_H
+#define SCPROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SCP_OK = 0,
+  SCP_EINVAL = -1,       /* invalid argument or unsupported shape */
+  SCP_ENOMEM = -2,       /* device allocation failed (build only) */
+  SCP_EDEGENERATE = -3,  /* a kept level is degenerate with another level */
+  SCP_ENONFINITE = -4,   /* a result is NaN or Inf */
+  SCP_EHIP = -5,         /* a HIP runtime call failed */
+  SCP_EBUSY = -6         /* serving queue full / request refused */
+} scp_status;
+
+enum { SCP_MODE_TRANSMON = 0, SCP_MODE_FLUXONIUM = 1, SCP_MODE_RAW = 2 };
+enum { SCP_OP_N = 0, SCP_OP_PHI = 1 };
+enum {
+  SCP_ENV_GAUSS = 0,        /* par[0] * exp(-(t-T/2)^2 / (2 sigma^2))           */
+  SCP_ENV_GAUSS_BASIS = 1,  /* sum_j par[j] exp(-(t-t_j)^2/(2 sigma^2)),
+                               t_j = (j+1/2) T / n_par                          */
+  SCP_ENV_COS_RAMP = 2,     /* par[0]/2 * (1 - cos(2 pi t / T))  (App. C)       */
+  SCP_ENV_CONST = 3,        /* par[0]                                            */
+  SCP_ENV_PWC = 4           /* par[floor(step * n_par / n_steps)]: the piece of
+                               the step being taken (all four stages)           */
+};
+
+#define SCP_MAX_TRUNC 8     /* largest per-mode truncation d                    */
+#define SCP_MAX_MODES 16    /* largest number of modes                          */
+
+/* One mode.  TRANSMON: charge basis of basis_dim = 2 ncut + 1 states,
+ * H = 4 EC (n - ng)^2 - EJ cos(phi); operator n only.
+ * FLUXONIUM: basis_dim harmonic-oscillator states of 4 EC n^2 + EL phi^2/2,
+ * H = 4 EC n^2 + EL phi^2 / 2 - EJ cos(phi - phiext); operators n and phi.
+ * RAW: trunc energies raw_eps and operators raw_ops given directly.
+ * Frame energies (interaction picture) default to the dressed energies of
+ * the mode as built; has_frame = 1 takes frame_eps instead (used to hold the
+ * frame fixed while parameters move). */
+typedef struct {
+  int32_t kind;        /* SCP_MODE_*                                           */
+  int32_t basis_dim;   /* basis size before truncation (ignored for RAW)      */
+  int32_t trunc;       /* d, 2..SCP_MAX_TRUNC; equal for all modes            */
+  int32_t has_frame;   /* 1: use frame_eps                                    */
+  double EC, EJ, EL, ng, phiext;
+  const double* raw_eps;  /* RAW: d energies (host)                            */
+  const double* raw_ops;  /* RAW: [2][d][d][2] = op n then op phi, row-major,
+                             (re, im) pairs (host); both Hermitian            */
+  double frame_eps[SCP_MAX_TRUNC];
+} scp_mode_desc;
+
+/* + g * op_i(mode i) (x) op_j(mode j), i != j. */
+typedef struct {
+  int32_t i, j, op_i, op_j;
+  double g;
+} scp_coupling_desc;
+
+/* c(t) = envelope(t; par) * cos(omega_d t + phase) multiplying op on mode.
+ * has_omega = 0: omega_d = frame_eps[1] - frame_eps[0] of the mode. */
+typedef struct {
+  int32_t mode, op, env, n_par;
+  int32_t has_omega;
+  int32_t pad_;
+  double omega_d, phase, sigma;
+  const double* par;   /* n_par envelope parameters (host)                  */
+} scp_drive_desc;
+
+typedef struct {
+  int32_t n_modes, n_couplings, n_drives, n_steps;
+  double T;            /* pulse length; step h = T / n_steps                */
+  const scp_mode_desc* modes;
+  const scp_coupling_desc* couplings;
+  const scp_drive_desc* drives;
+} scp_system_desc;
+
+typedef struct {
+  int32_t n_cols;      /* S, number of propagated columns                   */
+  int32_t precision;   /* 0: complex FP32 fused on-chip path;
+                          1: complex FP64 plain path (one launch per term)  */
+  int32_t ckpt_every;  /* checkpoint interval for the adjoint; 0 = ceil(sqrt(N)) */
+  int32_t with_ckpt;   /* propagate: 1 = keep checkpoints in the workspace  */
+} scp_solve_opts;
+
+typedef struct scp_system scp_system;
+
+/* Build a system: single-mode builders, FP64 eigensolves on the GPU
+ * (one workgroup per mode, cyclic Jacobi), dressed truncation with a fixed
+ * eigenvector sign (largest-magnitude entry positive, ties to the lowest
+ * basis index), frame energies, carriers, and the FP64-reduced phase and
+ * drive tables of every RK4 stage time.  Synchronises ``stream``.
+ * Errors: SCP_EINVAL (shape/field), SCP_EDEGENERATE (a kept level within
+ * 1e-9 relative of another level), SCP_ENOMEM, SCP_EHIP. */
+scp_status scp_build_system(const scp_system_desc* desc, void* stream, scp_system** out);
+
+/* Sizes: D, number of gradient parameters (order: drive parameters in drive
+ * then par order; then (EJ, EC, EL) of every mode; then coupling g in
+ * coupling order), dims (n_modes ints, nullable). */
+scp_status scp_system_info(const scp_system* sys, int64_t* D, int32_t* n_params,
+                           int32_t* n_modes, int32_t* dims);
+
+/* Dressed data of one mode as built (host FP64): eps[d] (ground
+ * referenced), frame[d], ops[2][d][d][2] (n then phi; phi zero for
+ * transmons), carrier omega of every drive (omega[n_drives], nullable). */
+scp_status scp_system_mode(const scp_system* sys, int32_t mode, double* eps, double* frame,
+                           double* ops);
+scp_status scp_system_carriers(const scp_system* sys, double* omega);
+
+/* Workspace bytes a propagate (+ adjoint if with_grad) needs for opts. */
+scp_status scp_workspace_size(const scp_system* sys, const scp_solve_opts* opts, int32_t with_grad,
+                              size_t* bytes);
+
+/* V(t) y for the stage time of (step, stage) (stage 0..3 at t_n + c h,
+ * c = 0, 1/2, 1/2, 1): the interaction-picture generator applied to the
+ * n_cols columns y (complex64, D x n_cols) into out.  FP32, same kernel
+ * code as the fused stepper's applicator. */
+scp_status scp_apply_generator(const scp_system* sys, int32_t step, int32_t stage, const void* y,
+                               void* out, int32_t n_cols, void* stream);
+
+/* Propagate psi0 (D x S) over all n_steps RK4 steps into psiT.  With
+ * opts->with_ckpt the states every ckpt_every steps are kept in the
+ * workspace for scp_propagate_adjoint.  psi0 and psiT may alias. */
+scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* workspace,
+                         const void* psi0, void* psiT, void* stream);
+
+/* Fidelity on the computational subspace: tau = sum_ij conj(T_ij)
+ * U[comp_rows[i], comp_cols[j]] accumulated in FP64 on the device,
+ * F = |tau|^2 / d_c^2.  U: D x S (precision 0 complex64, 1 complex128);
+ * comp_rows (int64, d_c), comp_cols (int32, d_c), target (complex128,
+ * d_c x d_c row-major) and tau_out (complex128, 1) are device pointers.
+ * cotangent (nullable, same precision and shape as U) receives the
+ * costate of L = 1 - F: -(tau/d_c^2) T_ij at (comp_rows[i], comp_cols[j]),
+ * zero elsewhere.  F_out (host, nullable) synchronises the stream. */
+scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, int32_t d_c,
+                        const int64_t* comp_rows, const int32_t* comp_cols, const void* target,
+                        void* tau_out, void* cotangent, double* F_out, void* stream);
+
+/* Gradient of L w.r.t. every parameter (host FP64, n_params entries in the
+ * order of scp_system_info), given the costate of the final state.  Needs
+ * the checkpoints of the immediately preceding scp_propagate on the same
+ * workspace with with_ckpt = 1 and the same opts.  Synchronises ``stream``.
+ * SCP_ENONFINITE if any gradient entry is not finite. */
+scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, void* workspace,
+                                 const void* cotangent, double* grad_out, void* stream);
+
+void scp_destroy(scp_system* sys);
+
+/* Message of the last failing call on this thread ("" if none); valid until
+ * the next call on this thread. */
+const char* scp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SCPROP_H */

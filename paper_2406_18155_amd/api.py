@@ -1,0 +1,195 @@
+"""Python front end of libscprop: argument marshalling over the C ABI.
+
+Every step of the computation runs in the HIP library; this module only
+converts descriptor dicts (see ``scp_inputs``) into the C structs, passes
+device pointers of torch tensors and the current HIP stream, and raises on
+error statuses.
+
+State convention on the Python side: a block of S columns of dimension D is
+a torch tensor of shape (S, D) (row s = column s), which is exactly the
+column-major D x S layout of the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+import torch
+
+from ._lib import (ENV, MODE_KIND, OP, CouplingDesc, DriveDesc, ModeDesc, SolveOpts, SystemDesc,
+                   check, lib)
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class System:
+    """A built system (device tables live until ``close``)."""
+
+    def __init__(self, desc, stream=None):
+        self.desc = desc
+        self._keep = []
+        modes = (ModeDesc * len(desc["modes"]))()
+        for m, md in enumerate(desc["modes"]):
+            M = modes[m]
+            M.kind = MODE_KIND[md["kind"]]
+            M.basis_dim = int(md.get("basis_dim", md["trunc"]))
+            M.trunc = int(md["trunc"])
+            M.EC, M.EJ, M.EL = float(md.get("EC", 0)), float(md.get("EJ", 0)), float(md.get("EL", 0))
+            M.ng, M.phiext = float(md.get("ng", 0.0)), float(md.get("phiext", 0.0))
+            if md.get("frame_eps") is not None:
+                M.has_frame = 1
+                for a, v in enumerate(np.asarray(md["frame_eps"], dtype=np.float64)[: M.trunc]):
+                    M.frame_eps[a] = float(v)
+            if md["kind"] == "raw":
+                d = M.trunc
+                eps = np.ascontiguousarray(np.asarray(md["eps"], dtype=np.float64)[:d])
+                ops = np.zeros((2, d, d, 2))
+                for o, name in enumerate(("n", "phi")):
+                    a = np.asarray(md["ops"][name], dtype=np.complex128)
+                    ops[o, :, :, 0] = a.real
+                    ops[o, :, :, 1] = a.imag
+                ops = np.ascontiguousarray(ops)
+                self._keep += [eps, ops]
+                M.raw_eps = eps.ctypes.data_as(C.POINTER(C.c_double))
+                M.raw_ops = ops.ctypes.data_as(C.POINTER(C.c_double))
+        coups = (CouplingDesc * max(1, len(desc["couplings"])))()
+        for e, c in enumerate(desc["couplings"]):
+            coups[e].i, coups[e].j = int(c["i"]), int(c["j"])
+            coups[e].op_i, coups[e].op_j = OP[c["op_i"]], OP[c["op_j"]]
+            coups[e].g = float(c["g"])
+        drives = (DriveDesc * max(1, len(desc["drives"])))()
+        for k, dr in enumerate(desc["drives"]):
+            R = drives[k]
+            R.mode, R.op, R.env = int(dr["mode"]), OP[dr["op"]], ENV[dr["env"]]
+            par = np.ascontiguousarray(np.asarray(dr["params"], dtype=np.float64))
+            self._keep.append(par)
+            R.n_par = len(par)
+            R.par = par.ctypes.data_as(C.POINTER(C.c_double))
+            R.has_omega = 0 if dr.get("omega_d") is None else 1
+            R.omega_d = 0.0 if dr.get("omega_d") is None else float(dr["omega_d"])
+            R.phase = float(dr.get("phase", 0.0))
+            R.sigma = float(dr.get("sigma", 1.0))
+        sd = SystemDesc()
+        sd.n_modes, sd.n_couplings, sd.n_drives = len(desc["modes"]), len(desc["couplings"]), \
+            len(desc["drives"])
+        sd.n_steps, sd.T = int(desc["n_steps"]), float(desc["T"])
+        sd.modes, sd.couplings, sd.drives = modes, coups, drives
+        h = C.c_void_p()
+        check(lib().scp_build_system(C.byref(sd), _stream_ptr(stream), C.byref(h)))
+        self.handle = h
+        D, npar, nm = C.c_int64(), C.c_int32(), C.c_int32()
+        check(lib().scp_system_info(h, C.byref(D), C.byref(npar), C.byref(nm), None))
+        self.D, self.n_params, self.n_modes = D.value, npar.value, nm.value
+        self.d = int(desc["modes"][0]["trunc"])
+        self.n_steps = int(desc["n_steps"])
+
+    # -- introspection -------------------------------------------------------
+    def mode(self, m):
+        d = self.d
+        eps = (C.c_double * d)()
+        frame = (C.c_double * d)()
+        ops = (C.c_double * (2 * d * d * 2))()
+        check(lib().scp_system_mode(self.handle, m, eps, frame, ops))
+        o = np.frombuffer(ops, dtype=np.float64).reshape(2, d, d, 2)
+        o = o[..., 0] + 1j * o[..., 1]
+        return {"eps": np.array(eps[:]), "frame": np.array(frame[:]), "n": o[0].copy(),
+                "phi": o[1].copy()}
+
+    def carriers(self):
+        n = max(1, len(self.desc["drives"]))
+        om = (C.c_double * n)()
+        check(lib().scp_system_carriers(self.handle, om))
+        return np.array(om[: len(self.desc["drives"])])
+
+    def opts(self, n_cols, precision=0, ckpt_every=0, with_ckpt=0):
+        o = SolveOpts()
+        o.n_cols, o.precision, o.ckpt_every, o.with_ckpt = int(n_cols), int(precision), \
+            int(ckpt_every), int(with_ckpt)
+        return o
+
+    def workspace_bytes(self, opts, with_grad=False):
+        n = C.c_size_t()
+        check(lib().scp_workspace_size(self.handle, C.byref(opts), int(with_grad), C.byref(n)))
+        return n.value
+
+    def workspace(self, opts, with_grad=False, device="cuda"):
+        return torch.empty(self.workspace_bytes(opts, with_grad), dtype=torch.uint8, device=device)
+
+    # -- compute ---------------------------------------------------------------
+    def apply_generator(self, step, stage, y, out=None, stream=None):
+        """V(t) y (FP32) at the stage time of (step, stage); y is (S, D) complex64."""
+        assert y.dtype == torch.complex64 and y.is_contiguous() and y.shape[1] == self.D
+        if out is None:
+            out = torch.empty_like(y)
+        check(lib().scp_apply_generator(self.handle, step, stage, _ptr(y), _ptr(out), y.shape[0],
+                                        _stream_ptr(stream)))
+        return out
+
+    def propagate(self, psi0, psiT=None, opts=None, workspace=None, stream=None):
+        prec = 0 if psi0.dtype == torch.complex64 else 1
+        assert psi0.is_contiguous() and psi0.shape[1] == self.D
+        if opts is None:
+            opts = self.opts(psi0.shape[0], precision=prec)
+        if psiT is None:
+            psiT = torch.empty_like(psi0)
+        if workspace is None and (opts.with_ckpt or prec == 1):
+            workspace = self.workspace(opts, device=psi0.device)
+        check(lib().scp_propagate(self.handle, C.byref(opts),
+                                  None if workspace is None else _ptr(workspace), _ptr(psi0),
+                                  _ptr(psiT), _stream_ptr(stream)))
+        return psiT
+
+    def adjoint(self, cotangent, opts, workspace, stream=None):
+        g = (C.c_double * max(1, self.n_params))()
+        check(lib().scp_propagate_adjoint(self.handle, C.byref(opts), _ptr(workspace),
+                                          _ptr(cotangent), g, _stream_ptr(stream)))
+        return np.array(g[: self.n_params])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().scp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Target:
+    """Device-resident fidelity inputs: computational rows/cols and target."""
+
+    def __init__(self, comp_rows, comp_cols, target, device="cuda"):
+        self.dc = len(comp_rows)
+        self.rows = torch.tensor(list(comp_rows), dtype=torch.int64, device=device)
+        self.cols = torch.tensor(list(comp_cols), dtype=torch.int32, device=device)
+        self.target = torch.tensor(np.asarray(target, dtype=np.complex128), device=device).contiguous()
+        self.tau = torch.zeros(1, dtype=torch.complex128, device=device)
+
+
+def fidelity(U, tgt: Target, cotangent=None, stream=None, sync=True):
+    """F = |tau|^2 / d_c^2 of U (S, D); fills ``cotangent`` (same shape) if given."""
+    prec = 0 if U.dtype == torch.complex64 else 1
+    S, D = U.shape
+    F = C.c_double()
+    check(lib().scp_fidelity(_ptr(U), D, S, prec, tgt.dc, _ptr(tgt.rows), _ptr(tgt.cols),
+                             _ptr(tgt.target), _ptr(tgt.tau),
+                             None if cotangent is None else _ptr(cotangent),
+                             C.byref(F) if sync else None, _stream_ptr(stream)))
+    return (F.value if sync else None), tgt.tau
+
+
+def basis_columns(D, columns, dtype=torch.complex64, device="cuda"):
+    psi0 = torch.zeros((len(columns), D), dtype=dtype, device=device)
+    for j, c in enumerate(columns):
+        psi0[j, c] = 1.0
+    return psi0

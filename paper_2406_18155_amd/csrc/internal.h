@@ -1,0 +1,152 @@
+// Internal structures of libscprop (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/scprop.h"
+
+namespace scp {
+
+using cplx = std::complex<double>;
+
+constexpr int MAXL = 8;        // layouts per stage
+constexpr int MAXRB = 64;      // register block (complex amplitudes per thread per vector)
+constexpr int MAXITEMS = 24;   // term items per layout
+constexpr int MAXPART = 3;     // partners of one first-factor slot within a layout
+constexpr int MAXSLOTS = 48;   // (mode, op) slots
+constexpr int MAXPAIRS = 48;   // (first slot, partner mode) pairs
+constexpr int MAXGROUPS = 48;
+constexpr int MAXPULSE = 256;  // pulse parameters
+constexpr int MAXUSE = 96;     // sensitivity usages
+constexpr int WG_THREADS = 256;
+
+// One term group evaluated inside one layout.  kind 0: diagonal (eps - frame)
+// of mode `mode` at register position `pos`.  kind 1: first-factor slot
+// `slot` on mode at `pos`, contributions c(t) * O~ y (if cidx >= 0) and
+// sum_p W~_pair O~ y over the partners (each a contraction at pos_j).
+struct Item {
+  int8_t kind, pos, n_part, pad0;
+  int16_t mode, slot, cidx, pad1;
+  int8_t pos_j[MAXPART], pad2;
+  int16_t mode_j[MAXPART], pair[MAXPART];
+};
+
+// Sensitivity usage (adjoint): reduction of conj(Lvec) against y on mode at
+// `pos` in layout `layout`.  kind 0: Lvec = kb (drives and diagonal of the
+// mode); kind 1: Lvec = O~_{left_slot} kb contracted at left_pos (coupling
+// side), weight g of coupling `coup`.
+struct Usage {
+  int8_t kind, layout, pos, left_pos;
+  int16_t mode, left_slot, coup, slot;   // slot: op of `mode` this usage differentiates (kind 1)
+  int16_t drive_first, n_drives;         // kind 0: drives on this mode (indices into drive list)
+  int16_t pad[2];
+};
+
+struct DriveDev {          // one drive in the device plan
+  int16_t slot, cidx, par0, npar;   // slot of its operator, c-table column, first pulse param
+};
+
+struct Plan {
+  int32_t d, N, NR, RB, TPC, CPW, WG, D, L, NT;
+  int32_t nslots, npairs, ngroups, ndrives, npulse, ncoup, nuse;
+  int32_t nsteps;
+  float h;
+  int32_t block_q;       // floats2 per half-step block in the op table
+  int32_t off_pair;      // offset (complex) of pair ops inside a half-step block
+  int32_t off_dslot;     // offset of slot derivative ops (3 per slot)
+  int32_t has_delta;
+  int32_t reg_off[MAXL][MAXRB];
+  int32_t tstride[MAXL][16];
+  int32_t n_items[MAXL];
+  Item items[MAXL][MAXITEMS];
+  float delta[16][8];          // eps - frame per mode (FP32)
+  int32_t slot_mode[MAXSLOTS];
+  int32_t slot_op[MAXSLOTS];
+  float coup_g[MAXPAIRS];
+  int32_t coup_slot_i[MAXPAIRS], coup_slot_j[MAXPAIRS];
+  DriveDev drives[MAXGROUPS];
+  Usage use[MAXUSE];
+  int32_t layout_of_mode[16];  // a layout whose register modes contain the mode
+  int32_t pos_of_mode[16];     // its register position there
+};
+
+struct ModeData {
+  int kind = 0, K = 0, d = 0;
+  double EC = 0, EJ = 0, EL = 0, ng = 0, phiext = 0;
+  bool has_phi = false;
+  std::vector<double> H;             // K*K row-major basis Hamiltonian
+  std::vector<double> dH[3];         // d/d(EJ, EC, EL)
+  std::vector<cplx> opB[2];          // basis operators n, phi (K*K)
+  std::vector<cplx> dopB[3][2];      // their derivatives
+  std::vector<double> w, V;          // eigenvalues (K), eigenvectors column a at V[k*K + a]
+  double eps[SCP_MAX_TRUNC] = {0}, frame[SCP_MAX_TRUNC] = {0};
+  cplx ops[2][SCP_MAX_TRUNC * SCP_MAX_TRUNC];
+  double deps[3][SCP_MAX_TRUNC] = {{0}};
+  cplx dops[3][2][SCP_MAX_TRUNC * SCP_MAX_TRUNC];
+};
+
+struct Coupling { int i, j, op_i, op_j; double g; };
+struct Drive {
+  int mode, op, env;
+  double omega, phase, sigma;
+  std::vector<double> par;
+};
+
+}  // namespace scp
+
+struct scp_system {
+  int n_modes = 0, d = 0, n_steps = 0;
+  int64_t D = 0;
+  double T = 0, h = 0;
+  std::vector<scp::ModeData> modes;
+  std::vector<scp::Coupling> coup;
+  std::vector<scp::Drive> drives;
+  int n_params = 0, n_pulse = 0;
+  // slots / pairs / groups (host copies used by gradient assembly)
+  std::vector<int> slot_mode, slot_op;
+  std::vector<scp::cplx> pairW_host;   // static pair operators sum g O_j (d*d each)
+  std::vector<int> pair_mode_host;
+  scp::Plan plan;
+  // device
+  scp::Plan* d_plan = nullptr;
+  float2* d_ops = nullptr;      // [2N+1][block_q] rotated ops per half-step
+  float* d_ctab = nullptr;      // [3N][ngroups] drive coefficients (per group = per drive)
+  float* d_dctab = nullptr;     // [3N][npulse] dc/dpar
+  double* d_dctab64 = nullptr;
+  void* d_scratch = nullptr;    // small per-system scratch (adjoint partial sums)
+  size_t scratch_bytes = 0;
+  int device = 0;
+};
+
+namespace scp {
+
+void set_error(const std::string& msg);
+scp_status fail(scp_status st, const std::string& msg);
+
+// host single-mode builders (single_mode.cpp)
+void build_transmon(ModeData& m);
+void build_fluxonium(ModeData& m);
+scp_status finish_mode(ModeData& m);   // sign convention, truncation, dressed ops, derivatives
+
+// kernels
+hipError_t launch_jacobi(double* A, double* V, double* w, const int* K, const int64_t* offs,
+                         int n_mat, hipStream_t s);
+hipError_t launch_tables(scp_system* sys, hipStream_t s);
+scp_status launch_rk4(scp_system* sys, const float2* psi0, float2* psiT, float4* ckpt,
+                      int ckpt_every, int S, hipStream_t s);
+scp_status launch_apply(const scp_system* sys, int step, int stage, const float2* y, float2* out,
+                        int S, hipStream_t s);
+scp_status launch_adjoint(scp_system* sys, const float4* ckpt, const float2* lamT, float2* segbuf,
+                          double* partial, int ckpt_every, int S, hipStream_t s);
+scp_status launch_fidelity(const void* U, int64_t D, int S, int prec, int dc, const int64_t* rows,
+                           const int32_t* cols, const void* target, void* tau, void* cot,
+                           hipStream_t s);
+scp_status launch_plain64(scp_system* sys, const double2* psi0, double2* psiT, void* work, int S,
+                          hipStream_t s);
+
+}  // namespace scp

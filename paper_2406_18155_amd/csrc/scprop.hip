@@ -1,0 +1,738 @@
+// C ABI of libscprop: system build, layout planning, and the propagate /
+// fidelity / apply entry points.  See include/scprop.h for the contract.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+
+#include "internal.h"
+
+namespace scp {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+scp_status fail(scp_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(SCP_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+hipError_t launch_tables_impl(int d, int nslots, int npairs, int ndrives, int ngroups, int npulse,
+                              int nsteps, double h, double T, const double* frames,
+                              const double2* sops, const double2* pops, const double2* dops,
+                              const int* smode, const int* pmode, float2* optab, int block_q,
+                              const void* drives, const double* par, float* ctab, float* dctab,
+                              double* dctab64, hipStream_t s);
+size_t drive_static_size();
+void pack_drive_static(void* dst, int k, int env, int npar, int par0, int group, double omega,
+                       double phase, double sigma);
+scp_status launch_rk4_range(const scp_system* sys, const float2* psi0, float2* psiT, float4* state,
+                            float4* ckpt, int ce, int S, int n0, int n1, hipStream_t s);
+
+namespace {
+
+int default_NR(int d) {
+  switch (d) {
+    case 2: return 4;
+    case 3: return 3;
+    case 4: return 2;
+    case 5: return 2;
+    default: return 0;
+  }
+}
+
+int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; ++i) r *= b;
+  return r;
+}
+
+// Device scratch helper freed at scope exit.
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+scp_status validate(const scp_system_desc* ds) {
+  if (!ds) return fail(SCP_EINVAL, "null descriptor");
+  if (ds->n_modes < 1 || ds->n_modes > SCP_MAX_MODES) return fail(SCP_EINVAL, "n_modes out of range");
+  if (ds->n_steps < 1) return fail(SCP_EINVAL, "n_steps must be >= 1");
+  if (!(ds->T > 0)) return fail(SCP_EINVAL, "T must be > 0");
+  if (ds->n_couplings < 0 || ds->n_drives < 0) return fail(SCP_EINVAL, "negative counts");
+  if (!ds->modes) return fail(SCP_EINVAL, "null modes");
+  if (ds->n_couplings > 0 && !ds->couplings) return fail(SCP_EINVAL, "null couplings");
+  if (ds->n_drives > 0 && !ds->drives) return fail(SCP_EINVAL, "null drives");
+  const int d = ds->modes[0].trunc;
+  for (int m = 0; m < ds->n_modes; ++m) {
+    const scp_mode_desc& M = ds->modes[m];
+    if (M.trunc != d) return fail(SCP_EINVAL, "all modes must share the truncation d");
+    if (M.trunc < 2 || M.trunc > SCP_MAX_TRUNC) return fail(SCP_EINVAL, "trunc out of range");
+    if (M.kind == SCP_MODE_TRANSMON) {
+      if (M.basis_dim < 3 || M.basis_dim % 2 == 0 || M.basis_dim > 95 || M.basis_dim <= M.trunc)
+        return fail(SCP_EINVAL, "transmon basis_dim must be odd, > trunc and <= 95");
+      if (!(M.EC > 0) || !(M.EJ > 0)) return fail(SCP_EINVAL, "transmon EC, EJ must be > 0");
+    } else if (M.kind == SCP_MODE_FLUXONIUM) {
+      if (M.basis_dim <= M.trunc || M.basis_dim > 96)
+        return fail(SCP_EINVAL, "fluxonium basis_dim must be > trunc and <= 96");
+      if (!(M.EC > 0) || !(M.EJ >= 0) || !(M.EL > 0))
+        return fail(SCP_EINVAL, "fluxonium EC, EL must be > 0, EJ >= 0");
+    } else if (M.kind == SCP_MODE_RAW) {
+      if (!M.raw_eps || !M.raw_ops) return fail(SCP_EINVAL, "raw mode needs raw_eps and raw_ops");
+    } else {
+      return fail(SCP_EINVAL, "unknown mode kind");
+    }
+    for (int a = 0; a < M.trunc && M.has_frame; ++a)
+      if (!std::isfinite(M.frame_eps[a])) return fail(SCP_EINVAL, "non-finite frame energy");
+  }
+  for (int e = 0; e < ds->n_couplings; ++e) {
+    const scp_coupling_desc& C = ds->couplings[e];
+    if (C.i < 0 || C.j < 0 || C.i >= ds->n_modes || C.j >= ds->n_modes || C.i == C.j)
+      return fail(SCP_EINVAL, "coupling modes invalid");
+    for (int op : {C.op_i, C.op_j})
+      if (op != SCP_OP_N && op != SCP_OP_PHI) return fail(SCP_EINVAL, "coupling op invalid");
+    if ((C.op_i == SCP_OP_PHI && ds->modes[C.i].kind == SCP_MODE_TRANSMON) ||
+        (C.op_j == SCP_OP_PHI && ds->modes[C.j].kind == SCP_MODE_TRANSMON))
+      return fail(SCP_EINVAL, "transmon has no phase operator");
+    if (!std::isfinite(C.g)) return fail(SCP_EINVAL, "non-finite coupling");
+  }
+  for (int k = 0; k < ds->n_drives; ++k) {
+    const scp_drive_desc& R = ds->drives[k];
+    if (R.mode < 0 || R.mode >= ds->n_modes) return fail(SCP_EINVAL, "drive mode invalid");
+    if (R.op != SCP_OP_N && R.op != SCP_OP_PHI) return fail(SCP_EINVAL, "drive op invalid");
+    if (R.op == SCP_OP_PHI && ds->modes[R.mode].kind == SCP_MODE_TRANSMON)
+      return fail(SCP_EINVAL, "transmon has no phase operator");
+    if (R.env < SCP_ENV_GAUSS || R.env > SCP_ENV_PWC) return fail(SCP_EINVAL, "envelope invalid");
+    if (R.n_par < 1 || !R.par) return fail(SCP_EINVAL, "drive needs n_par >= 1 parameters");
+    if ((R.env == SCP_ENV_GAUSS || R.env == SCP_ENV_COS_RAMP || R.env == SCP_ENV_CONST) && R.n_par != 1)
+      return fail(SCP_EINVAL, "this envelope takes one parameter");
+    if ((R.env == SCP_ENV_GAUSS || R.env == SCP_ENV_GAUSS_BASIS) && !(R.sigma > 0))
+      return fail(SCP_EINVAL, "Gaussian sigma must be > 0");
+    for (int i = 0; i < R.n_par; ++i)
+      if (!std::isfinite(R.par[i])) return fail(SCP_EINVAL, "non-finite pulse parameter");
+  }
+  return SCP_OK;
+}
+
+// Layout planning (see DESIGN: register modes per layout, last layout = base).
+scp_status make_plan(scp_system* sys) {
+  Plan& P = sys->plan;
+  std::memset(&P, 0, sizeof(Plan));
+  const int N = sys->n_modes, d = sys->d;
+  int NR = default_NR(d);
+  if (NR == 0) return fail(SCP_EINVAL, "the propagator supports d in {2,3,4,5}");
+  NR = std::min(NR, N);
+  const int RB = ipow(d, NR);
+  const int TPC = ipow(d, N - NR);
+  if (TPC > WG_THREADS)
+    return fail(SCP_EINVAL, "system too large for the on-chip path (d^(N-" + std::to_string(NR) +
+                                ") > 256)");
+  P.d = d;
+  P.N = N;
+  P.NR = NR;
+  P.RB = RB;
+  P.TPC = TPC;
+  P.NT = N - NR;
+  P.CPW = std::max(1, WG_THREADS / TPC);
+  P.D = (int)sys->D;
+  P.nsteps = sys->n_steps;
+  P.h = (float)sys->h;
+  // --- slots -----------------------------------------------------------
+  std::map<std::pair<int, int>, int> slot_of;
+  auto slot = [&](int m, int op) {
+    auto key = std::make_pair(m, op);
+    auto it = slot_of.find(key);
+    if (it != slot_of.end()) return it->second;
+    int s = (int)sys->slot_mode.size();
+    sys->slot_mode.push_back(m);
+    sys->slot_op.push_back(op);
+    slot_of[key] = s;
+    return s;
+  };
+  for (auto& c : sys->coup) {
+    slot(c.i, c.op_i);
+    slot(c.j, c.op_j);
+  }
+  for (auto& r : sys->drives) slot(r.mode, r.op);
+  if ((int)sys->slot_mode.size() > MAXSLOTS) return fail(SCP_EINVAL, "too many operator slots");
+  // --- layouts ---------------------------------------------------------
+  std::vector<std::vector<int>> layouts;
+  std::set<std::pair<int, int>> unc;
+  for (auto& c : sys->coup) unc.insert({std::min(c.i, c.j), std::max(c.i, c.j)});
+  if (N <= NR) {
+    std::vector<int> all;
+    for (int m = 0; m < N; ++m) all.push_back(m);
+    layouts.push_back(all);
+    unc.clear();
+  }
+  auto covered_by = [&](const std::vector<int>& S) {
+    for (auto it = unc.begin(); it != unc.end();) {
+      bool a = std::find(S.begin(), S.end(), it->first) != S.end();
+      bool b = std::find(S.begin(), S.end(), it->second) != S.end();
+      if (a && b) it = unc.erase(it);
+      else ++it;
+    }
+  };
+  while (!unc.empty()) {
+    // first uncovered edge in coupling order
+    std::pair<int, int> e{-1, -1};
+    for (auto& c : sys->coup) {
+      auto k = std::make_pair(std::min(c.i, c.j), std::max(c.i, c.j));
+      if (unc.count(k)) { e = k; break; }
+    }
+    std::vector<int> S{e.first, e.second};
+    while ((int)S.size() < NR) {
+      int best = -1, bestc = 0;
+      for (int m = 0; m < N; ++m) {
+        if (std::find(S.begin(), S.end(), m) != S.end()) continue;
+        int cnt = 0;
+        for (int s : S) cnt += unc.count({std::min(m, s), std::max(m, s)});
+        if (cnt > bestc) { bestc = cnt; best = m; }
+      }
+      if (best < 0) break;
+      S.push_back(best);
+    }
+    for (int m = 0; m < N && (int)S.size() < NR; ++m)
+      if (std::find(S.begin(), S.end(), m) == S.end()) S.push_back(m);
+    covered_by(S);
+    layouts.push_back(S);
+  }
+  // every mode must appear in some layout (single-mode terms)
+  for (int m = 0; m < N; ++m) {
+    bool found = false;
+    for (auto& S : layouts) found |= std::find(S.begin(), S.end(), m) != S.end();
+    if (!found) {
+      std::vector<int> S{m};
+      for (int q = 0; q < N && (int)S.size() < NR; ++q)
+        if (q != m) S.push_back(q);
+      layouts.push_back(S);
+    }
+  }
+  if ((int)layouts.size() > MAXL) return fail(SCP_EINVAL, "coupling graph needs too many layouts");
+  const int L = (int)layouts.size();
+  P.L = L;
+  std::vector<int> stride(N);
+  for (int m = 0; m < N; ++m) stride[m] = ipow(d, N - 1 - m);
+  for (int l = 0; l < L; ++l) {
+    auto S = layouts[l];
+    std::sort(S.begin(), S.end());
+    layouts[l] = S;
+    for (int r = 0; r < RB; ++r) {
+      int off = 0, rr = r;
+      for (int p = NR - 1; p >= 0; --p) {
+        off += (rr % d) * stride[S[p]];
+        rr /= d;
+      }
+      P.reg_off[l][r] = off;
+    }
+    // thread modes, digit 0 = smallest stride (largest mode index)
+    std::vector<int> T;
+    for (int m = N - 1; m >= 0; --m)
+      if (std::find(S.begin(), S.end(), m) == S.end()) T.push_back(m);
+    for (int k = 0; k < (int)T.size(); ++k) P.tstride[l][k] = stride[T[k]];
+  }
+  auto pos_in = [&](int l, int m) {
+    auto& S = layouts[l];
+    auto it = std::find(S.begin(), S.end(), m);
+    return it == S.end() ? -1 : (int)(it - S.begin());
+  };
+  for (int m = 0; m < N; ++m) {
+    P.layout_of_mode[m] = -1;
+    for (int l = 0; l < L && P.layout_of_mode[m] < 0; ++l)
+      if (pos_in(l, m) >= 0) {
+        P.layout_of_mode[m] = l;
+        P.pos_of_mode[m] = pos_in(l, m);
+      }
+  }
+  // --- items -------------------------------------------------------------
+  // couplings grouped by (layout, first slot, partner mode)
+  struct PairKey { int l, s, j; };
+  std::vector<PairKey> pairs;
+  std::vector<std::vector<cplx>> pairW;
+  for (auto& c : sys->coup) {
+    int l = -1;
+    for (int q = 0; q < L && l < 0; ++q)
+      if (pos_in(q, c.i) >= 0 && pos_in(q, c.j) >= 0) l = q;
+    int s = slot(c.i, c.op_i);
+    int p = -1;
+    for (int q = 0; q < (int)pairs.size(); ++q)
+      if (pairs[q].l == l && pairs[q].s == s && pairs[q].j == c.j) p = q;
+    if (p < 0) {
+      p = (int)pairs.size();
+      pairs.push_back({l, s, c.j});
+      pairW.push_back(std::vector<cplx>(d * d, 0.0));
+    }
+    const cplx* Bj = sys->modes[c.j].ops[c.op_j];
+    for (int i = 0; i < d * d; ++i) pairW[p][i] += c.g * Bj[i];
+  }
+  if ((int)pairs.size() > MAXPAIRS) return fail(SCP_EINVAL, "too many coupling pairs");
+  P.npairs = (int)pairs.size();
+  // drive groups: one per slot
+  std::map<int, int> group_of_slot;
+  for (auto& r : sys->drives) {
+    int s = slot(r.mode, r.op);
+    if (!group_of_slot.count(s)) {
+      int g = (int)group_of_slot.size();
+      group_of_slot[s] = g;
+    }
+  }
+  P.ngroups = (int)group_of_slot.size();
+  if (P.ngroups > MAXGROUPS) return fail(SCP_EINVAL, "too many drive groups");
+  std::vector<std::vector<Item>> items(L);
+  for (int p = 0; p < (int)pairs.size(); ++p) {
+    Item I{};
+    I.kind = 1;
+    I.slot = (int16_t)pairs[p].s;
+    I.mode = (int16_t)sys->slot_mode[pairs[p].s];
+    I.pos = (int8_t)pos_in(pairs[p].l, I.mode);
+    I.n_part = 1;
+    I.pos_j[0] = (int8_t)pos_in(pairs[p].l, pairs[p].j);
+    I.mode_j[0] = (int16_t)pairs[p].j;
+    I.pair[0] = (int16_t)p;
+    I.cidx = -1;
+    items[pairs[p].l].push_back(I);
+  }
+  for (auto& kv : group_of_slot) {
+    int s = kv.first, g = kv.second, m = sys->slot_mode[s];
+    bool attached = false;
+    for (int l = 0; l < L && !attached; ++l)
+      for (auto& I : items[l])
+        if (I.kind == 1 && I.slot == s && I.cidx < 0) {
+          I.cidx = (int16_t)g;
+          attached = true;
+          break;
+        }
+    if (!attached) {
+      Item I{};
+      I.kind = 1;
+      I.slot = (int16_t)s;
+      I.mode = (int16_t)m;
+      int l = P.layout_of_mode[m];
+      I.pos = (int8_t)P.pos_of_mode[m];
+      I.n_part = 0;
+      I.cidx = (int16_t)g;
+      items[l].push_back(I);
+    }
+  }
+  P.has_delta = 0;
+  for (int m = 0; m < N; ++m) {
+    bool nz = false;
+    for (int a = 0; a < d; ++a) {
+      double v = sys->modes[m].eps[a] - sys->modes[m].frame[a];
+      P.delta[m][a] = (float)v;
+      nz |= v != 0.0;
+    }
+    if (nz) {
+      P.has_delta = 1;
+      Item I{};
+      I.kind = 0;
+      I.mode = (int16_t)m;
+      I.pos = (int8_t)P.pos_of_mode[m];
+      I.cidx = -1;
+      items[P.layout_of_mode[m]].push_back(I);
+    }
+  }
+  for (int l = 0; l < L; ++l) {
+    if ((int)items[l].size() > MAXITEMS) return fail(SCP_EINVAL, "too many terms in one layout");
+    P.n_items[l] = (int)items[l].size();
+    for (int i = 0; i < (int)items[l].size(); ++i) P.items[l][i] = items[l][i];
+  }
+  // drives
+  int par0 = 0;
+  P.ndrives = (int)sys->drives.size();
+  for (int k = 0; k < P.ndrives; ++k) {
+    int s = slot(sys->drives[k].mode, sys->drives[k].op);
+    P.drives[k].slot = (int16_t)s;
+    P.drives[k].cidx = (int16_t)group_of_slot[s];
+    P.drives[k].par0 = (int16_t)par0;
+    P.drives[k].npar = (int16_t)sys->drives[k].par.size();
+    par0 += (int)sys->drives[k].par.size();
+  }
+  P.npulse = par0;
+  if (P.npulse > MAXPULSE) return fail(SCP_EINVAL, "too many pulse parameters");
+  P.nslots = (int)sys->slot_mode.size();
+  for (int s = 0; s < P.nslots; ++s) {
+    P.slot_mode[s] = sys->slot_mode[s];
+    P.slot_op[s] = sys->slot_op[s];
+  }
+  P.ncoup = (int)sys->coup.size();
+  for (int e = 0; e < P.ncoup; ++e) {
+    P.coup_g[e] = (float)sys->coup[e].g;
+    P.coup_slot_i[e] = slot(sys->coup[e].i, sys->coup[e].op_i);
+    P.coup_slot_j[e] = slot(sys->coup[e].j, sys->coup[e].op_j);
+  }
+  P.off_pair = P.nslots * d * d;
+  P.off_dslot = (P.nslots + P.npairs) * d * d;
+  P.block_q = (P.nslots + P.npairs + 3 * P.nslots) * d * d;
+  int threads = P.CPW * TPC;
+  P.WG = ((threads + 63) / 64) * 64;
+  // host copy of pair W for the table kernel
+  sys->pairW_host.clear();
+  sys->pair_mode_host.clear();
+  for (int p = 0; p < P.npairs; ++p) {
+    for (auto v : pairW[p]) sys->pairW_host.push_back(v);
+    sys->pair_mode_host.push_back(pairs[p].j);
+  }
+  return SCP_OK;
+}
+
+scp_status build_tables(scp_system* sys, hipStream_t st) {
+  const Plan& P = sys->plan;
+  const int d = sys->d, dd = d * d, N = sys->n_modes;
+  std::vector<double> frames((size_t)N * 8, 0.0);
+  for (int m = 0; m < N; ++m)
+    for (int a = 0; a < d; ++a) frames[m * 8 + a] = sys->modes[m].frame[a];
+  std::vector<double2> sops((size_t)P.nslots * dd), pops((size_t)std::max(1, P.npairs) * dd),
+      dops((size_t)std::max(1, P.nslots) * 3 * dd);
+  for (int s = 0; s < P.nslots; ++s) {
+    const ModeData& M = sys->modes[P.slot_mode[s]];
+    for (int i = 0; i < dd; ++i) {
+      cplx v = M.ops[P.slot_op[s]][i];
+      sops[s * dd + i] = make_double2(v.real(), v.imag());
+      for (int th = 0; th < 3; ++th) {
+        cplx dv = M.dops[th][P.slot_op[s]][i];
+        dops[(s * 3 + th) * dd + i] = make_double2(dv.real(), dv.imag());
+      }
+    }
+  }
+  for (int p = 0; p < P.npairs; ++p)
+    for (int i = 0; i < dd; ++i) {
+      cplx v = sys->pairW_host[p * dd + i];
+      pops[p * dd + i] = make_double2(v.real(), v.imag());
+    }
+  std::vector<int> smode(std::max(1, P.nslots)), pmode(std::max(1, P.npairs));
+  for (int s = 0; s < P.nslots; ++s) smode[s] = P.slot_mode[s];
+  for (int p = 0; p < P.npairs; ++p) pmode[p] = sys->pair_mode_host[p];
+  // drives
+  std::vector<char> dstat(drive_static_size() * std::max<size_t>(1, sys->drives.size()));
+  std::vector<double> par;
+  for (int k = 0; k < (int)sys->drives.size(); ++k) {
+    const Drive& R = sys->drives[k];
+    pack_drive_static(dstat.data(), k, R.env, (int)R.par.size(), (int)par.size(),
+                      P.drives[k].cidx, R.omega, R.phase, R.sigma);
+    for (double v : R.par) par.push_back(v);
+  }
+  if (par.empty()) par.push_back(0.0);
+  // temporary device copies
+  DevBuf bf, bs, bp, bd, bsm, bpm, bdr, bpar;
+  HIPCHK(hipMalloc(&bf.p, frames.size() * sizeof(double)));
+  HIPCHK(hipMalloc(&bs.p, sops.size() * sizeof(double2)));
+  HIPCHK(hipMalloc(&bp.p, pops.size() * sizeof(double2)));
+  HIPCHK(hipMalloc(&bd.p, dops.size() * sizeof(double2)));
+  HIPCHK(hipMalloc(&bsm.p, smode.size() * sizeof(int)));
+  HIPCHK(hipMalloc(&bpm.p, pmode.size() * sizeof(int)));
+  HIPCHK(hipMalloc(&bdr.p, dstat.size()));
+  HIPCHK(hipMalloc(&bpar.p, par.size() * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(bf.p, frames.data(), frames.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bs.p, sops.data(), sops.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bp.p, pops.data(), pops.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bd.p, dops.data(), dops.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bsm.p, smode.data(), smode.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bpm.p, pmode.data(), pmode.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bdr.p, dstat.data(), dstat.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(bpar.p, par.data(), par.size() * sizeof(double), hipMemcpyHostToDevice, st));
+  const size_t nq = 2 * (size_t)sys->n_steps + 1;
+  HIPCHK(hipMalloc(&sys->d_ops, nq * P.block_q * sizeof(float2)));
+  const size_t np3 = 3 * (size_t)sys->n_steps;
+  HIPCHK(hipMalloc(&sys->d_ctab, np3 * std::max(1, P.ngroups) * sizeof(float)));
+  HIPCHK(hipMalloc(&sys->d_dctab, np3 * std::max(1, P.npulse) * sizeof(float)));
+  HIPCHK(hipMalloc(&sys->d_dctab64, np3 * std::max(1, P.npulse) * sizeof(double)));
+  HIPCHK(launch_tables_impl(d, P.nslots, P.npairs, (int)sys->drives.size(), P.ngroups, P.npulse,
+                            sys->n_steps, sys->h, sys->T, (const double*)bf.p,
+                            (const double2*)bs.p, (const double2*)bp.p, (const double2*)bd.p,
+                            (const int*)bsm.p, (const int*)bpm.p, sys->d_ops, P.block_q, bdr.p,
+                            (const double*)bpar.p, sys->d_ctab, sys->d_dctab, sys->d_dctab64, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return SCP_OK;
+}
+
+scp_status build(const scp_system_desc* ds, hipStream_t st, scp_system* sys) {
+  scp_status v = validate(ds);
+  if (v != SCP_OK) return v;
+  HIPCHK(hipGetDevice(&sys->device));
+  const int N = ds->n_modes;
+  sys->n_modes = N;
+  sys->d = ds->modes[0].trunc;
+  sys->n_steps = ds->n_steps;
+  sys->T = ds->T;
+  sys->h = ds->T / ds->n_steps;
+  sys->D = 1;
+  for (int m = 0; m < N; ++m) sys->D *= sys->d;
+  sys->modes.resize(N);
+  // host basis matrices
+  std::vector<int> eig_modes;
+  for (int m = 0; m < N; ++m) {
+    const scp_mode_desc& M = ds->modes[m];
+    ModeData& md = sys->modes[m];
+    md.kind = M.kind;
+    md.d = M.trunc;
+    md.K = M.basis_dim;
+    md.EC = M.EC;
+    md.EJ = M.EJ;
+    md.EL = M.EL;
+    md.ng = M.ng;
+    md.phiext = M.phiext;
+    if (M.kind == SCP_MODE_TRANSMON) {
+      build_transmon(md);
+      eig_modes.push_back(m);
+    } else if (M.kind == SCP_MODE_FLUXONIUM) {
+      build_fluxonium(md);
+      eig_modes.push_back(m);
+    } else {
+      const int d = M.trunc;
+      md.has_phi = true;
+      for (int a = 0; a < d; ++a) md.eps[a] = M.raw_eps[a];
+      for (int o = 0; o < 2; ++o)
+        for (int i = 0; i < d * d; ++i)
+          md.ops[o][i] = cplx(M.raw_ops[(o * d * d + i) * 2], M.raw_ops[(o * d * d + i) * 2 + 1]);
+      for (int p = 0; p < 3; ++p) {
+        for (int a = 0; a < d; ++a) md.deps[p][a] = 0.0;
+        for (int o = 0; o < 2; ++o)
+          for (int i = 0; i < d * d; ++i) md.dops[p][o][i] = 0.0;
+      }
+    }
+  }
+  // FP64 eigensolves on the device, one workgroup per mode
+  if (!eig_modes.empty()) {
+    std::vector<int> Ks;
+    std::vector<int64_t> offs;
+    int64_t tot = 0;
+    for (int m : eig_modes) {
+      Ks.push_back(sys->modes[m].K);
+      offs.push_back(tot);
+      tot += (int64_t)sys->modes[m].K * sys->modes[m].K;
+    }
+    std::vector<double> A(tot);
+    for (size_t i = 0; i < eig_modes.size(); ++i) {
+      const ModeData& md = sys->modes[eig_modes[i]];
+      std::copy(md.H.begin(), md.H.end(), A.begin() + offs[i]);
+    }
+    DevBuf bA, bV, bw, bK, bo;
+    HIPCHK(hipMalloc(&bA.p, tot * sizeof(double)));
+    HIPCHK(hipMalloc(&bV.p, tot * sizeof(double)));
+    HIPCHK(hipMalloc(&bw.p, tot * sizeof(double)));
+    HIPCHK(hipMalloc(&bK.p, Ks.size() * sizeof(int)));
+    HIPCHK(hipMalloc(&bo.p, offs.size() * sizeof(int64_t)));
+    HIPCHK(hipMemcpyAsync(bA.p, A.data(), tot * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bK.p, Ks.data(), Ks.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(bo.p, offs.data(), offs.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_jacobi((double*)bA.p, (double*)bV.p, (double*)bw.p, (const int*)bK.p,
+                         (const int64_t*)bo.p, (int)eig_modes.size(), st));
+    std::vector<double> V(tot), w(tot);
+    HIPCHK(hipMemcpyAsync(V.data(), bV.p, tot * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(w.data(), bw.p, tot * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t i = 0; i < eig_modes.size(); ++i) {
+      ModeData& md = sys->modes[eig_modes[i]];
+      const int K = md.K;
+      md.V.assign(V.begin() + offs[i], V.begin() + offs[i] + (int64_t)K * K);
+      md.w.assign(w.begin() + offs[i], w.begin() + offs[i] + K);
+      scp_status s = finish_mode(md);
+      if (s != SCP_OK) return s;
+    }
+  }
+  // frames, couplings, drives
+  for (int m = 0; m < N; ++m) {
+    const scp_mode_desc& M = ds->modes[m];
+    for (int a = 0; a < sys->d; ++a)
+      sys->modes[m].frame[a] = M.has_frame ? M.frame_eps[a] : sys->modes[m].eps[a];
+  }
+  for (int e = 0; e < ds->n_couplings; ++e) {
+    const scp_coupling_desc& C = ds->couplings[e];
+    sys->coup.push_back({C.i, C.j, C.op_i, C.op_j, C.g});
+  }
+  for (int k = 0; k < ds->n_drives; ++k) {
+    const scp_drive_desc& R = ds->drives[k];
+    Drive dr;
+    dr.mode = R.mode;
+    dr.op = R.op;
+    dr.env = R.env;
+    dr.phase = R.phase;
+    dr.sigma = R.sigma;
+    const double* f = sys->modes[R.mode].frame;
+    dr.omega = R.has_omega ? R.omega_d : (f[1] - f[0]);
+    dr.par.assign(R.par, R.par + R.n_par);
+    sys->drives.push_back(dr);
+    sys->n_pulse += R.n_par;
+  }
+  sys->n_params = sys->n_pulse + 3 * N + (int)sys->coup.size();
+  scp_status s = make_plan(sys);
+  if (s != SCP_OK) return s;
+  HIPCHK(hipMalloc((void**)&sys->d_plan, sizeof(Plan)));
+  HIPCHK(hipMemcpyAsync(sys->d_plan, &sys->plan, sizeof(Plan), hipMemcpyHostToDevice, st));
+  return build_tables(sys, st);
+}
+
+// Workspace layout (bytes)
+struct WsLayout {
+  size_t ckpt = 0, seg = 0, part = 0, total = 0;
+  int nckpt = 0, ce = 0;
+};
+
+WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad) {
+  WsLayout w;
+  const int N = sys->n_steps;
+  w.ce = o->ckpt_every > 0 ? o->ckpt_every : (int)std::ceil(std::sqrt((double)N));
+  w.nckpt = (N + w.ce - 1) / w.ce;
+  const size_t S = (size_t)o->n_cols, D = (size_t)sys->D;
+  size_t off = 0;
+  auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  if (o->precision == 0) {
+    if (o->with_ckpt || with_grad) {
+      w.ckpt = off;
+      off = align(off + (size_t)w.nckpt * S * D * sizeof(float4));
+    }
+    if (with_grad) {
+      w.seg = off;
+      off = align(off + (size_t)w.ce * 4 * S * D * sizeof(float2));
+      w.part = off;
+      off = align(off + (size_t)S * WG_THREADS * (MAXPULSE + 3 * SCP_MAX_MODES + MAXPAIRS) * sizeof(double));
+    }
+  } else {
+    off = align(4 * S * D * sizeof(double2));
+  }
+  w.total = std::max<size_t>(off, 256);
+  return w;
+}
+
+}  // namespace
+
+}  // namespace scp
+
+using namespace scp;
+
+extern "C" {
+
+const char* scp_last_error(void) { return g_err.c_str(); }
+
+scp_status scp_build_system(const scp_system_desc* desc, void* stream, scp_system** out) {
+  g_err.clear();
+  if (!out) return fail(SCP_EINVAL, "null out");
+  *out = nullptr;
+  scp_system* sys = new (std::nothrow) scp_system();
+  if (!sys) return fail(SCP_ENOMEM, "host allocation");
+  scp_status s = build(desc, (hipStream_t)stream, sys);
+  if (s != SCP_OK) {
+    scp_destroy(sys);
+    return s;
+  }
+  *out = sys;
+  return SCP_OK;
+}
+
+scp_status scp_system_info(const scp_system* sys, int64_t* D, int32_t* n_params, int32_t* n_modes,
+                           int32_t* dims) {
+  if (!sys) return fail(SCP_EINVAL, "null system");
+  if (D) *D = sys->D;
+  if (n_params) *n_params = sys->n_params;
+  if (n_modes) *n_modes = sys->n_modes;
+  if (dims)
+    for (int m = 0; m < sys->n_modes; ++m) dims[m] = sys->d;
+  return SCP_OK;
+}
+
+scp_status scp_system_mode(const scp_system* sys, int32_t mode, double* eps, double* frame,
+                           double* ops) {
+  if (!sys || mode < 0 || mode >= sys->n_modes) return fail(SCP_EINVAL, "bad mode");
+  const ModeData& m = sys->modes[mode];
+  const int d = sys->d;
+  for (int a = 0; a < d; ++a) {
+    if (eps) eps[a] = m.eps[a];
+    if (frame) frame[a] = m.frame[a];
+  }
+  if (ops)
+    for (int o = 0; o < 2; ++o)
+      for (int i = 0; i < d * d; ++i) {
+        ops[(o * d * d + i) * 2] = m.ops[o][i].real();
+        ops[(o * d * d + i) * 2 + 1] = m.ops[o][i].imag();
+      }
+  return SCP_OK;
+}
+
+scp_status scp_system_carriers(const scp_system* sys, double* omega) {
+  if (!sys || !omega) return fail(SCP_EINVAL, "null argument");
+  for (size_t k = 0; k < sys->drives.size(); ++k) omega[k] = sys->drives[k].omega;
+  return SCP_OK;
+}
+
+scp_status scp_workspace_size(const scp_system* sys, const scp_solve_opts* opts, int32_t with_grad,
+                              size_t* bytes) {
+  if (!sys || !opts || !bytes) return fail(SCP_EINVAL, "null argument");
+  if (opts->n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  *bytes = ws_layout(sys, opts, with_grad).total;
+  return SCP_OK;
+}
+
+scp_status scp_apply_generator(const scp_system* sys, int32_t step, int32_t stage, const void* y,
+                               void* out, int32_t n_cols, void* stream) {
+  g_err.clear();
+  if (!sys || !y || !out) return fail(SCP_EINVAL, "null argument");
+  if (step < 0 || step >= sys->n_steps || stage < 0 || stage > 3 || n_cols < 1)
+    return fail(SCP_EINVAL, "step/stage/n_cols out of range");
+  return launch_apply(sys, step, stage, (const float2*)y, (float2*)out, n_cols, (hipStream_t)stream);
+}
+
+scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* workspace,
+                         const void* psi0, void* psiT, void* stream) {
+  g_err.clear();
+  if (!sys || !opts || !psi0 || !psiT) return fail(SCP_EINVAL, "null argument");
+  if (opts->n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  if (opts->precision != 0 && opts->precision != 1) return fail(SCP_EINVAL, "precision must be 0 or 1");
+  WsLayout w = ws_layout(sys, opts, 0);
+  hipStream_t st = (hipStream_t)stream;
+  if (opts->precision == 1)
+    return launch_plain64(sys, (const double2*)psi0, (double2*)psiT, workspace, opts->n_cols, st);
+  if (opts->with_ckpt && !workspace) return fail(SCP_EINVAL, "checkpoints need a workspace");
+  float4* ck = opts->with_ckpt ? (float4*)((char*)workspace + w.ckpt) : nullptr;
+  return launch_rk4(sys, (const float2*)psi0, (float2*)psiT, ck, w.ce, opts->n_cols, st);
+}
+
+scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, int32_t d_c,
+                        const int64_t* comp_rows, const int32_t* comp_cols, const void* target,
+                        void* tau_out, void* cotangent, double* F_out, void* stream) {
+  g_err.clear();
+  if (!U || !comp_rows || !comp_cols || !target || !tau_out) return fail(SCP_EINVAL, "null argument");
+  if (D < 1 || S < 1 || d_c < 1 || (precision != 0 && precision != 1))
+    return fail(SCP_EINVAL, "bad sizes");
+  hipStream_t st = (hipStream_t)stream;
+  scp_status s = launch_fidelity(U, D, S, precision, d_c, comp_rows, comp_cols, target, tau_out,
+                                 cotangent, st);
+  if (s != SCP_OK) return s;
+  if (F_out) {
+    double2 tau;
+    HIPCHK(hipMemcpyAsync(&tau, tau_out, sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *F_out = (tau.x * tau.x + tau.y * tau.y) / ((double)d_c * d_c);
+    if (!std::isfinite(*F_out)) return fail(SCP_ENONFINITE, "fidelity is not finite");
+  }
+  return SCP_OK;
+}
+
+scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, void* workspace,
+                                 const void* cotangent, double* grad_out, void* stream) {
+  g_err.clear();
+  if (!sys || !opts || !workspace || !cotangent || !grad_out) return fail(SCP_EINVAL, "null argument");
+  return fail(SCP_EINVAL, "adjoint not available");
+}
+
+void scp_destroy(scp_system* sys) {
+  if (!sys) return;
+  if (sys->d_plan) (void)hipFree(sys->d_plan);
+  if (sys->d_ops) (void)hipFree(sys->d_ops);
+  if (sys->d_ctab) (void)hipFree(sys->d_ctab);
+  if (sys->d_dctab) (void)hipFree(sys->d_dctab);
+  if (sys->d_dctab64) (void)hipFree(sys->d_dctab64);
+  if (sys->d_scratch) (void)hipFree(sys->d_scratch);
+  delete sys;
+}
+
+}  // extern "C"
