@@ -28,7 +28,8 @@ constexpr int WG_THREADS = 256;
 // One term group evaluated inside one layout.  kind 0: diagonal (eps - frame)
 // of mode `mode` at register position `pos`.  kind 1: first-factor slot
 // `slot` on mode at `pos`, contributions c(t) * O~ y (if cidx >= 0) and
-// sum_p W~_pair O~ y over the partners (each a contraction at pos_j).
+// W~_pair O~ y with the partner at pos_j (n_part = 1).  kind 2 (adjoint
+// only): reduction of the mode's single-mode sensitivities.
 struct Item {
   int8_t kind, pos, n_part, pad0;
   int16_t mode, slot, cidx, pad1;
@@ -73,6 +74,10 @@ struct Plan {
   Usage use[MAXUSE];
   int32_t layout_of_mode[16];  // a layout whose register modes contain the mode
   int32_t pos_of_mode[16];     // its register position there
+  int32_t pair_ncoup[MAXPAIRS];
+  int32_t pair_coup[MAXPAIRS][4];  // couplings summed into each pair operator
+  float deps[16][3][8];            // d eps / d(EJ, EC, EL) per mode
+  int32_t nacc;                    // gradient accumulators: npulse + 3 N + ncoup
 };
 
 struct ModeData {

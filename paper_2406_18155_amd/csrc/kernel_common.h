@@ -247,6 +247,7 @@ __device__ __forceinline__ void apply_layout(const Plan* __restrict__ P, int l,
   const int ni = P->n_items[l];
   for (int it = 0; it < ni; ++it) {
     const Item& I = P->items[l][it];
+    if (I.kind == 2) continue;
     if (I.kind == 0) {
       dispatch_diag<d, NR>(I.pos, P->delta[I.mode], in, out);
       continue;

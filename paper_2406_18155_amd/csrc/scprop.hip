@@ -36,6 +36,9 @@ void pack_drive_static(void* dst, int k, int env, int npar, int par0, int group,
                        double phase, double sigma);
 scp_status launch_rk4_range(const scp_system* sys, const float2* psi0, float2* psiT, float4* state,
                             float4* ckpt, int ce, int S, int n0, int n1, hipStream_t s);
+scp_status launch_adjoint_impl(const scp_system* sys, const void* ckpt, const void* lamT,
+                               void* segbuf, void* lamsave, double* part, int ce, int nckpt, int S,
+                               hipStream_t s);
 
 namespace {
 
@@ -273,6 +276,10 @@ scp_status make_plan(scp_system* sys) {
     }
     const cplx* Bj = sys->modes[c.j].ops[c.op_j];
     for (int i = 0; i < d * d; ++i) pairW[p][i] += c.g * Bj[i];
+    if (p < MAXPAIRS) {
+      if (P.pair_ncoup[p] >= 4) return fail(SCP_EINVAL, "more than 4 couplings on one mode pair");
+      P.pair_coup[p][P.pair_ncoup[p]++] = (int)(&c - &sys->coup[0]);
+    }
   }
   if ((int)pairs.size() > MAXPAIRS) return fail(SCP_EINVAL, "too many coupling pairs");
   P.npairs = (int)pairs.size();
@@ -341,6 +348,16 @@ scp_status make_plan(scp_system* sys) {
       items[P.layout_of_mode[m]].push_back(I);
     }
   }
+  for (int m = 0; m < N; ++m) {
+    Item I{};
+    I.kind = 2;
+    I.mode = (int16_t)m;
+    I.pos = (int8_t)P.pos_of_mode[m];
+    I.cidx = -1;
+    items[P.layout_of_mode[m]].push_back(I);
+    for (int th = 0; th < 3; ++th)
+      for (int a = 0; a < d; ++a) P.deps[m][th][a] = (float)sys->modes[m].deps[th][a];
+  }
   for (int l = 0; l < L; ++l) {
     if ((int)items[l].size() > MAXITEMS) return fail(SCP_EINVAL, "too many terms in one layout");
     P.n_items[l] = (int)items[l].size();
@@ -370,6 +387,7 @@ scp_status make_plan(scp_system* sys) {
     P.coup_slot_i[e] = slot(sys->coup[e].i, sys->coup[e].op_i);
     P.coup_slot_j[e] = slot(sys->coup[e].j, sys->coup[e].op_j);
   }
+  P.nacc = P.npulse + 3 * N + P.ncoup;
   P.off_pair = P.nslots * d * d;
   P.off_dslot = (P.nslots + P.npairs) * d * d;
   P.block_q = (P.nslots + P.npairs + 3 * P.nslots) * d * d;
@@ -574,8 +592,8 @@ scp_status build(const scp_system_desc* ds, hipStream_t st, scp_system* sys) {
 
 // Workspace layout (bytes)
 struct WsLayout {
-  size_t ckpt = 0, seg = 0, part = 0, total = 0;
-  int nckpt = 0, ce = 0;
+  size_t ckpt = 0, seg = 0, part = 0, lam = 0, total = 0;
+  int nckpt = 0, ce = 0, nwg = 0;
 };
 
 WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad) {
@@ -592,10 +610,13 @@ WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad
       off = align(off + (size_t)w.nckpt * S * D * sizeof(float4));
     }
     if (with_grad) {
+      w.nwg = (int)((S + sys->plan.CPW - 1) / sys->plan.CPW);
       w.seg = off;
       off = align(off + (size_t)w.ce * 4 * S * D * sizeof(float2));
+      w.lam = off;
+      off = align(off + S * D * sizeof(float2));
       w.part = off;
-      off = align(off + (size_t)S * WG_THREADS * (MAXPULSE + 3 * SCP_MAX_MODES + MAXPAIRS) * sizeof(double));
+      off = align(off + (size_t)w.nwg * std::max(1, sys->plan.nacc) * sizeof(double));
     }
   } else {
     off = align(4 * S * D * sizeof(double2));
@@ -721,7 +742,28 @@ scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, vo
                                  const void* cotangent, double* grad_out, void* stream) {
   g_err.clear();
   if (!sys || !opts || !workspace || !cotangent || !grad_out) return fail(SCP_EINVAL, "null argument");
-  return fail(SCP_EINVAL, "adjoint not available");
+  if (opts->precision != 0) return fail(SCP_EINVAL, "the adjoint runs on the FP32 path (precision 0)");
+  if (opts->n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  WsLayout w = ws_layout(sys, opts, 1);
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)workspace;
+  scp_status s = launch_adjoint_impl(sys, ws + w.ckpt, cotangent, ws + w.seg, ws + w.lam,
+                                     (double*)(ws + w.part), w.ce, w.nckpt, opts->n_cols, st);
+  if (s != SCP_OK) return s;
+  const int nacc = sys->plan.nacc;
+  std::vector<double> part((size_t)w.nwg * nacc);
+  HIPCHK(hipMemcpyAsync(part.data(), ws + w.part, part.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bool finite = true;
+  for (int i = 0; i < nacc; ++i) {
+    double a = 0.0;
+    for (int b = 0; b < w.nwg; ++b) a += part[(size_t)b * nacc + i];
+    grad_out[i] = 2.0 * a;
+    finite &= std::isfinite(grad_out[i]);
+  }
+  if (!finite) return fail(SCP_ENONFINITE, "gradient is not finite");
+  return SCP_OK;
 }
 
 void scp_destroy(scp_system* sys) {

@@ -1,0 +1,34 @@
+"""Write stored oracle results used by the GPU tests (calls only oracle/).
+
+    python tests/golden/make_oracle_refs.py
+
+config3_oracle.json: loss, fidelity and the full gradient of the config-3
+workload (4-fluxonium chain, CZ(q0,q1) x I x I target, 5000 RK4 steps),
+computed by the CPU FP64 oracle (several minutes of CPU time).
+"""
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import scp_inputs as si  # noqa: E402
+from oracle.system import OracleSystem  # noqa: E402
+from oracle.adjoint import loss_and_grad, param_names  # noqa: E402
+
+
+def main():
+    desc = si.config3()
+    sys_ = OracleSystem(desc)
+    L, F, tau, U, g = loss_and_grad(sys_)
+    out = {"workload": "config3: 4 fluxonium chain, d=5, T=100 ns, 5000 RK4 steps, CZ(q0,q1) x I x I",
+           "generator": "tests/golden/make_oracle_refs.py (oracle only)",
+           "L": L, "F": F, "tau": [tau.real, tau.imag],
+           "param_names": param_names(sys_), "grad": [float(v) for v in g]}
+    with open(os.path.join(HERE, "config3_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,123 @@
+"""GPU parity of the adjoint gradient (discrete adjoint of the fused FP32
+RK4 with sqrt(N) checkpoints) against the CPU FP64 oracle gradient."""
+import copy
+import json
+import os
+
+import numpy as np
+import pytest
+
+import scp_inputs as si
+from oracle.system import OracleSystem
+from oracle.adjoint import loss_and_grad, param_names
+from oracle.fd import fd_gradient
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-4      # ||g_gpu - g_oracle||_inf / ||g_oracle||_inf
+DF_TOL = 1e-6
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def scp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_18155_amd as m
+    return m
+
+
+def _short(desc, T, n):
+    d = copy.deepcopy(desc)
+    scale = T / d["T"]
+    d["T"], d["n_steps"] = T, n
+    for dr in d["drives"]:
+        dr["sigma"] *= scale
+    return d
+
+
+def _ring(n_modes, d, T, n, seed=0):
+    s = si.transmon_ring(si.rng_for(7, seed), n_modes, d, T, n)
+    return si._finish(s, [d] * n_modes, target=si.cz_target(n_modes))
+
+
+def _chain(n_modes, d, T, n, seed=0):
+    s = si.fluxonium_chain(si.rng_for(8, seed), n_modes, d, T, n, n_basis_gauss=4, amp=0.03)
+    return si._finish(s, [d] * n_modes, target=si.cz_target(n_modes))
+
+
+def gpu_loss_and_grad(scp, desc, ckpt_every=0):
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, desc["columns"])
+    opts = g.opts(psi0.shape[0], ckpt_every=ckpt_every, with_ckpt=1)
+    ws = g.workspace(opts, with_grad=True)
+    U = g.propagate(psi0, opts=opts, workspace=ws)
+    tgt = scp.Target(desc["comp_rows"], desc["comp_cols"], desc["target"])
+    cot = torch.empty_like(U)
+    F, _ = scp.fidelity(U, tgt, cotangent=cot)
+    grad = g.adjoint(cot, opts, ws)
+    g.close()
+    return F, grad
+
+
+def check_grad(g, ref):
+    scale = np.abs(ref).max()
+    err = np.abs(g - ref).max() / scale
+    assert err <= GRAD_TOL, err
+    big = np.abs(ref) > 1e-3 * scale
+    rel = np.abs(g[big] - ref[big]) / np.abs(ref[big])
+    assert rel.max() <= 10 * GRAD_TOL, rel.max()
+
+
+CASES = {
+    "transmon2_d4": lambda: _short(si.config1(), 10.0, 500),
+    "fluxonium2_d5": lambda: si._finish(dict(_short(si.config3(), 8.0, 400),
+                                             modes=si.config3()["modes"][:2],
+                                             couplings=si.config3()["couplings"][:2],
+                                             drives=si.config3()["drives"][:1]),
+                                        [5, 5], target=si.cz_target(2)),
+    "fluxonium4_d5": lambda: _short(si.config3(), 6.0, 300),
+    "ring3_d4": lambda: _ring(3, 4, 6.0, 300),
+    "ring5_d3": lambda: _ring(5, 3, 6.0, 300),
+    "chain3_d5": lambda: _chain(3, 5, 6.0, 300),
+    "raw_pwc_d2": lambda: si.random_raw_system(5, [2, 2, 2], 3, 2.0, 200, env="pwc"),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_adjoint_matches_oracle_gradient(scp, name):
+    desc = CASES[name]()
+    print(f"[adjoint] {name}", flush=True)
+    F, g = gpu_loss_and_grad(scp, desc)
+    L, Fo, tau, U, go = loss_and_grad(OracleSystem(desc))
+    assert abs(F - Fo) <= DF_TOL
+    assert g.shape == go.shape
+    check_grad(g, go)
+
+
+def test_adjoint_matches_central_differences(scp):
+    desc = _short(si.config1(), 6.0, 300)
+    print("[adjoint] transmon2 vs FD", flush=True)
+    F, g = gpu_loss_and_grad(scp, desc)
+    fd = fd_gradient(desc, range(len(g)))
+    ref = np.array([fd[i] for i in range(len(g))])
+    check_grad(g, ref)
+
+
+def test_checkpoint_interval_is_bitwise_invariant_and_deterministic(scp):
+    desc = _ring(4, 3, 4.0, 49)
+    print("[adjoint] ckpt invariance", flush=True)
+    gs = [gpu_loss_and_grad(scp, desc, ce)[1] for ce in (1, 7, 49, 7)]
+    for gi in gs[1:]:
+        assert np.array_equal(gs[0], gi)
+
+
+def test_config3_full_gradient_against_stored_oracle(scp):
+    path = os.path.join(GOLDEN, "config3_oracle.json")
+    ref = json.load(open(path))
+    desc = si.config3()
+    print("[adjoint] config3 full", flush=True)
+    F, g = gpu_loss_and_grad(scp, desc)
+    assert abs(F - ref["F"]) <= DF_TOL
+    check_grad(g, np.array(ref["grad"]))
