@@ -1,0 +1,233 @@
+"""Benchmark of the differentiable propagation hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input:
+build the system (single-mode builders, FP64 eigensolves, FP64 stage tables),
+propagate all columns with the fused RK4 (checkpoints kept), reduce the
+fidelity and seed the costate, run the adjoint and assemble the gradient.
+
+Workload: the 8-transmon ring (d=3, D=6561), 256 computational columns,
+T=60 ns, 3000 RK4 steps, 40 parameters.  Metric: RK4 steps * dim^2 / s,
+read as sum over solves of N * D * S per second (S = number of propagated
+columns).  Parity on the same run: the 8 seeded sampled columns against the
+stored CPU FP64 oracle result (fidelity restricted to those columns and its
+gradient).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32 = 157.3e12      # MI355X FP32 (vector incl. packed, and dense MFMA), FLOP/s
+PEAK_HBM = 8.0e12         # bytes/s
+
+
+def contraction_counts(desc):
+    """(C_fwd per generator application, sensitivity passes per adjoint stage)."""
+    pairs = set()
+    first = set()
+    for c in desc["couplings"]:
+        pairs.add(((c["i"], c["op_i"]), c["j"]))
+        first.add((c["i"], c["op_i"]))
+    drive_only = {(d["mode"], d["op"]) for d in desc["drives"]} - first
+    c_fwd = 2 * len(pairs) + len(drive_only)
+    sens = 3 * len(pairs) + len(desc["modes"])
+    return c_fwd, sens
+
+
+def flops(desc, S):
+    d = desc["modes"][0]["trunc"]
+    D = d ** len(desc["modes"])
+    N = desc["n_steps"]
+    c_fwd, sens = contraction_counts(desc)
+    per = 8.0 * D * S * d              # one contraction over all columns (complex MAC = 8 FLOP)
+    fwd = 4 * N * per * c_fwd
+    adj = 4 * N * per * (2 * c_fwd + sens)   # recompute + adjoint apply + sensitivities
+    return fwd, adj
+
+
+def sampled_desc(si, np):
+    desc = si.config5()
+    samp = si.sampled_columns(len(desc["columns"]), 8)
+    full_t = desc["target"]
+    desc["comp_rows"] = [desc["comp_rows"][j] for j in samp]
+    desc["columns"] = [desc["columns"][j] for j in samp]
+    desc["comp_cols"] = list(range(len(samp)))
+    desc["target"] = full_t[np.ix_(samp, samp)]
+    return desc
+
+
+def cpu_baseline(si, np, steps=300):
+    """Oracle (as written) on a bounded sample: one column of the workload,
+    ``steps`` RK4 steps forward + adjoint gradient."""
+    import copy
+    import torch
+    from oracle.system import OracleSystem
+    from oracle.rk4 import basis_columns, propagate
+    from oracle.fidelity import cotangent, fidelity
+    from oracle.adjoint import gradient
+    desc = copy.deepcopy(si.config5())
+    desc["n_steps"] = steps
+    desc["T"] = 60.0 * steps / 3000.0
+    for dr in desc["drives"]:
+        dr["sigma"] = 15.0
+    desc["columns"] = [desc["columns"][255]]
+    desc["comp_rows"] = [desc["comp_rows"][255]]
+    desc["comp_cols"] = [0]
+    desc["target"] = np.eye(1, dtype=complex)
+    t0 = time.perf_counter()
+    s = OracleSystem(desc)
+    psi0 = basis_columns(s.D, desc["columns"])
+    U = propagate(s, psi0)
+    F, tau = fidelity(U, desc["comp_rows"], desc["comp_cols"], desc["target"])
+    lam = cotangent(U.shape, desc["comp_rows"], desc["comp_cols"], desc["target"], tau)
+    gradient(s, lam, psi0)
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": steps * s.D * 1 / dt, "unit": "steps*dim^2/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"8-transmon ring, 1 column, {steps} of 3000 RK4 steps, forward + adjoint "
+                      f"gradient (40 params), numpy FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (columns shard with no communication; "
+              "see DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import scp_inputs as si
+    import paper_2406_18155_amd as scp
+
+    dev = torch.device("cuda:0")
+    desc = si.config5()
+    S = len(desc["columns"])
+    D = 3 ** 8
+    N = desc["n_steps"]
+    stream = torch.cuda.current_stream()
+
+    state = {}
+
+    def step(timed_kernels=False):
+        g = scp.System(desc)
+        psi0 = scp.basis_columns(g.D, desc["columns"], device=dev)
+        opts = g.opts(S, with_ckpt=1)
+        if "ws" not in state:
+            state["ws"] = g.workspace(opts, with_grad=True)
+            state["cot"] = torch.empty_like(psi0)
+            state["tgt"] = scp.Target(desc["comp_rows"], desc["comp_cols"], desc["target"])
+        ws = state["ws"]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(stream)
+        U = g.propagate(psi0, opts=opts, workspace=ws)
+        ev[1].record(stream)
+        F, _ = scp.fidelity(U, state["tgt"], cotangent=state["cot"], sync=False)
+        ev[2].record(stream)
+        grad = g.adjoint(state["cot"], opts, ws)
+        ev[3].record(stream)
+        if timed_kernels:
+            torch.cuda.synchronize()
+            state.setdefault("fwd_ms", []).append(ev[0].elapsed_time(ev[1]))
+            state.setdefault("adj_ms", []).append(ev[2].elapsed_time(ev[3]))
+        g.close()
+        return grad
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(timed_kernels=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+
+    fwd_flop, adj_flop = flops(desc, S)
+    fwd_ms = float(np.mean(state["fwd_ms"]))
+    adj_ms = float(np.mean(state["adj_ms"]))
+    value = N * D * S / dt
+
+    # parity on the same run: sampled columns vs the stored oracle result
+    parity = {}
+    if not args.no_check:
+        ref_path = os.path.join(ROOT, "tests", "golden", "config5_sampled_oracle.json")
+        if os.path.exists(ref_path):
+            ref = json.load(open(ref_path))
+            sd = sampled_desc(si, np)
+            g = scp.System(sd)
+            psi0 = scp.basis_columns(g.D, sd["columns"], device=dev)
+            opts = g.opts(len(sd["columns"]), with_ckpt=1)
+            ws = g.workspace(opts, with_grad=True)
+            U = g.propagate(psi0, opts=opts, workspace=ws)
+            cot = torch.empty_like(U)
+            F, _ = scp.fidelity(U, scp.Target(sd["comp_rows"], sd["comp_cols"], sd["target"]),
+                                cotangent=cot)
+            gr = g.adjoint(cot, opts, ws)
+            gref = np.array(ref["grad"])
+            parity = {"dF": abs(F - ref["F"]),
+                      "grad_rel_err": float(np.abs(gr - gref).max() / np.abs(gref).max()),
+                      "parity_sample": "8 seeded computational columns vs stored FP64 oracle"}
+            g.close()
+
+    ws_fwd = scp.System(desc)
+    o = ws_fwd.opts(S, with_ckpt=0)
+    m_fwd = 2 * S * D * 8
+    m_grad = m_fwd + ws_fwd.workspace_bytes(ws_fwd.opts(S, with_ckpt=1), with_grad=True)
+    ws_fwd.close()
+
+    out = {
+        "metric": "RK4 steps*dim^2/s (forward + adjoint gradient)",
+        "value": value,
+        "unit": "steps*dim^2/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "8-transmon ring, d=3, D=6561, 256 computational columns, "
+                               "T=60 ns, 3000 RK4 steps, 40 gradient parameters",
+                   "global_batch": S, "seq_len": N},
+        "roofline": {"bound": "alu", "achieved": adj_flop / (adj_ms * 1e-3) / 1e12,
+                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": adj_flop / (adj_ms * 1e-3) / PEAK_FP32, "traffic": None,
+                     "kernel": "adjoint_kernel<3,3>"},
+        "forward": {"kernel": "rk4_kernel<3,3>", "ms": fwd_ms,
+                    "tflops": fwd_flop / (fwd_ms * 1e-3) / 1e12,
+                    "frac": fwd_flop / (fwd_ms * 1e-3) / PEAK_FP32,
+                    "steps_dim2_per_s": N * D * S / (fwd_ms * 1e-3)},
+        "adjoint_ms": adj_ms,
+        "O_t": (fwd_ms + adj_ms) / fwd_ms,
+        "O_m": m_grad / m_fwd,
+    }
+    out.update(parity)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(si, np)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -140,7 +140,7 @@ class System:
             opts = self.opts(psi0.shape[0], precision=prec)
         if psiT is None:
             psiT = torch.empty_like(psi0)
-        if workspace is None and (opts.with_ckpt or prec == 1):
+        if workspace is None:
             workspace = self.workspace(opts, device=psi0.device)
         check(lib().scp_propagate(self.handle, C.byref(opts),
                                   None if workspace is None else _ptr(workspace), _ptr(psi0),

@@ -48,6 +48,16 @@ struct Usage {
   int16_t pad[2];
 };
 
+// Canonical per-layout term list: every pair term has its first factor at
+// register position p and its partner at p + 1 (layouts are ordered along
+// paths of the coupling graph).  Absent entries point at a zero operator.
+struct CPair {
+  int16_t slot, pair, cidx, mode_i, mode_j, pad;   // cidx < 0: no drive attached
+};
+struct CSingle {
+  int16_t slot, cidx;
+};
+
 struct DriveDev {          // one drive in the device plan
   int16_t slot, cidx, par0, npar;   // slot of its operator, c-table column, first pulse param
 };
@@ -62,10 +72,11 @@ struct Plan {
   int32_t off_dslot;     // offset of slot derivative ops (3 per slot)
   int32_t has_delta;
   int32_t reg_off[MAXL][MAXRB];
+  int32_t reg_stride[MAXL][8];   // natural-order stride of the mode at each register position
   int32_t tstride[MAXL][16];
   int32_t n_items[MAXL];
   Item items[MAXL][MAXITEMS];
-  float delta[16][8];          // eps - frame per mode (FP32)
+  float delta[17][8];          // eps - frame per mode (FP32); row 16 is zero
   int32_t slot_mode[MAXSLOTS];
   int32_t slot_op[MAXSLOTS];
   float coup_g[MAXPAIRS];
@@ -76,6 +87,15 @@ struct Plan {
   int32_t pos_of_mode[16];     // its register position there
   int32_t pair_ncoup[MAXPAIRS];
   int32_t pair_coup[MAXPAIRS][4];  // couplings summed into each pair operator
+  int32_t pair_pslot[MAXPAIRS][4]; // their partner-side operator slots
+  int32_t MP;                      // pair terms per position pair (compile-time variant)
+  CPair cpair[MAXL][4][2];         // [layout][p][m]
+  int32_t has_single[MAXL];
+  CSingle csingle[MAXL][8];        // drive-only terms at position p
+  int32_t has_diag[MAXL];
+  int32_t cdiag[MAXL][8];          // mode of the diagonal term at position p (16: none)
+  int32_t has_mode_pass[MAXL];
+  int32_t mode_pass[MAXL][8];      // adjoint: single-mode sensitivities of this mode at p (-1: none)
   float deps[16][3][8];            // d eps / d(EJ, EC, EL) per mode
   int32_t nacc;                    // gradient accumulators: npulse + 3 N + ncoup
 };
@@ -142,7 +162,7 @@ scp_status finish_mode(ModeData& m);   // sign convention, truncation, dressed o
 hipError_t launch_jacobi(double* A, double* V, double* w, const int* K, const int64_t* offs,
                          int n_mat, hipStream_t s);
 hipError_t launch_tables(scp_system* sys, hipStream_t s);
-scp_status launch_rk4(scp_system* sys, const float2* psi0, float2* psiT, float4* ckpt,
+scp_status launch_rk4(scp_system* sys, const float2* psi0, float2* psiT, float2* lo, float4* ckpt,
                       int ckpt_every, int S, hipStream_t s);
 scp_status launch_apply(const scp_system* sys, int step, int stage, const float2* y, float2* out,
                         int S, hipStream_t s);

@@ -48,24 +48,49 @@ struct c32x2 {   // compensated pair (hi.re, hi.im, lo.re, lo.im)
 // ----------------------------------------------------------------------------
 // layout switches through LDS
 // ----------------------------------------------------------------------------
-template <int RB>
-__device__ __forceinline__ void lds_put(c32* lds, int base, const int* __restrict__ roff,
+// Natural-order offset of register r: sum over positions p of digit_p(r) *
+// stride of the mode at p (the strides are per layout, uniform).
+template <int d, int NR>
+struct RegOff {
+  int s[NR];
+  __device__ __forceinline__ int operator()(int r) const {
+    int o = 0;
+#pragma unroll
+    for (int p = 0; p < NR; ++p) {
+      int q = r;
+      for (int k = p + 1; k < NR; ++k) q /= d;
+      o += (q % d) * s[p];
+    }
+    return o;
+  }
+};
+
+template <int d, int NR>
+__device__ __forceinline__ RegOff<d, NR> reg_off_of(const Plan* __restrict__ P, int l) {
+  RegOff<d, NR> R;
+#pragma unroll
+  for (int p = 0; p < NR; ++p) R.s[p] = P->reg_stride[l][p];
+  return R;
+}
+
+template <int d, int NR, int RB>
+__device__ __forceinline__ void lds_put(c32* lds, int base, const RegOff<d, NR>& R,
                                         const Vec<RB>& v) {
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     c32 t;
     t.x = v.re[r];
     t.y = v.im[r];
-    lds[base + roff[r]] = t;
+    lds[base + R(r)] = t;
   }
 }
 
-template <int RB>
-__device__ __forceinline__ void lds_get(const c32* lds, int base, const int* __restrict__ roff,
+template <int d, int NR, int RB>
+__device__ __forceinline__ void lds_get(const c32* lds, int base, const RegOff<d, NR>& R,
                                         Vec<RB>& v) {
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
-    c32 t = lds[base + roff[r]];
+    c32 t = lds[base + R(r)];
     v.re[r] = t.x;
     v.im[r] = t.y;
   }
@@ -196,77 +221,220 @@ __device__ __forceinline__ void diag_acc(const float* __restrict__ dl, const Vec
   }
 }
 
-// Dispatch on runtime register positions (uniform branches).
-template <int d, int NR, int RB>
-__device__ __forceinline__ void dispatch_single(int pi, const Op<d>& O, const Vec<RB>& in,
-                                                Vec<RB>& out) {
-  if constexpr (NR >= 1) if (pi == 0) { contract_acc<d, NR, 0>(O, in, out); return; }
-  if constexpr (NR >= 2) if (pi == 1) { contract_acc<d, NR, 1>(O, in, out); return; }
-  if constexpr (NR >= 3) if (pi == 2) { contract_acc<d, NR, 2>(O, in, out); return; }
-  if constexpr (NR >= 4) if (pi == 3) { contract_acc<d, NR, 3>(O, in, out); return; }
-  if constexpr (NR >= 5) if (pi == 4) { contract_acc<d, NR, 4>(O, in, out); return; }
+// Drive coefficient of a term (cidx < 0: none).  The index is clamped so the
+// (uniform) load never leaves the table.
+__device__ __forceinline__ float coef(const float* __restrict__ cq, int cidx) {
+  const float v = cq[cidx > 0 ? cidx : 0];
+  return cidx >= 0 ? v : 0.f;
 }
 
-template <int d, int NR, int PI, int RB>
-__device__ __forceinline__ void dispatch_pair_j(int pj, const Op<d>& O, const Op<d>& W, float c,
-                                                const Vec<RB>& in, Vec<RB>& out) {
-  if constexpr (NR >= 1 && PI != 0) if (pj == 0) { group_pair<d, NR, PI, 0>(O, W, c, in, out); return; }
-  if constexpr (NR >= 2 && PI != 1) if (pj == 1) { group_pair<d, NR, PI, 1>(O, W, c, in, out); return; }
-  if constexpr (NR >= 3 && PI != 2) if (pj == 2) { group_pair<d, NR, PI, 2>(O, W, c, in, out); return; }
-  if constexpr (NR >= 4 && PI != 3) if (pj == 3) { group_pair<d, NR, PI, 3>(O, W, c, in, out); return; }
-  if constexpr (NR >= 5 && PI != 4) if (pj == 4) { group_pair<d, NR, PI, 4>(O, W, c, in, out); return; }
-}
-
-template <int d, int NR, int RB>
-__device__ __forceinline__ void dispatch_pair(int pi, int pj, const Op<d>& O, const Op<d>& W,
-                                              float c, const Vec<RB>& in, Vec<RB>& out) {
-  if constexpr (NR >= 1) if (pi == 0) { dispatch_pair_j<d, NR, 0>(pj, O, W, c, in, out); return; }
-  if constexpr (NR >= 2) if (pi == 1) { dispatch_pair_j<d, NR, 1>(pj, O, W, c, in, out); return; }
-  if constexpr (NR >= 3) if (pi == 2) { dispatch_pair_j<d, NR, 2>(pj, O, W, c, in, out); return; }
-  if constexpr (NR >= 4) if (pi == 3) { dispatch_pair_j<d, NR, 3>(pj, O, W, c, in, out); return; }
-  if constexpr (NR >= 5) if (pi == 4) { dispatch_pair_j<d, NR, 4>(pj, O, W, c, in, out); return; }
-}
-
-template <int d, int NR, int RB>
-__device__ __forceinline__ void dispatch_diag(int pi, const float* dl, const Vec<RB>& in,
-                                              Vec<RB>& out) {
-  if constexpr (NR >= 1) if (pi == 0) { diag_acc<d, NR, 0>(dl, in, out); return; }
-  if constexpr (NR >= 2) if (pi == 1) { diag_acc<d, NR, 1>(dl, in, out); return; }
-  if constexpr (NR >= 3) if (pi == 2) { diag_acc<d, NR, 2>(dl, in, out); return; }
-  if constexpr (NR >= 4) if (pi == 3) { diag_acc<d, NR, 3>(dl, in, out); return; }
-  if constexpr (NR >= 5) if (pi == 4) { diag_acc<d, NR, 4>(dl, in, out); return; }
-}
-
-// Apply all items of layout l: out += V_l(t) in, for the half-step block
-// `ops` (rotated operators) and the drive coefficients `cq` of this stage.
-template <int d, int NR, int RB>
+// Apply all terms of layout l: out += V_l(t) in.  Positions are compile-time:
+// pair terms at (p, p+1), MP of them per position pair; drive-only and
+// diagonal terms behind one per-layout flag each.
+template <int d, int NR, int MP, int RB>
 __device__ __forceinline__ void apply_layout(const Plan* __restrict__ P, int l,
                                              const c32* __restrict__ ops,
                                              const float* __restrict__ cq, const Vec<RB>& in,
                                              Vec<RB>& out) {
-  const int ni = P->n_items[l];
-  for (int it = 0; it < ni; ++it) {
-    const Item& I = P->items[l][it];
-    if (I.kind == 2) continue;
-    if (I.kind == 0) {
-      dispatch_diag<d, NR>(I.pos, P->delta[I.mode], in, out);
-      continue;
-    }
-    Op<d> O;
-    load_op<d>(ops + I.slot * d * d, O);
-    const float c = I.cidx >= 0 ? cq[I.cidx] : 0.f;
-    if (I.n_part == 0) {
-      // c * O~ y
+  constexpr int dd = d * d;
+  static_for<NR - 1>([&](auto Pp) {
+    constexpr int p = decltype(Pp)::value;
+    static_for<MP>([&](auto Mm) {
+      constexpr int m = decltype(Mm)::value;
+      const CPair& C = P->cpair[l][p][m];
+      Op<d> O, W;
+      load_op<d>(ops + C.slot * dd, O);
+      load_op<d>(ops + P->off_pair + C.pair * dd, W);
+      group_pair<d, NR, p, p + 1>(O, W, coef(cq, C.cidx), in, out);
+    });
+  });
+  if (P->has_single[l]) {
+    static_for<NR>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      const CSingle& C1 = P->csingle[l][p];
+      Op<d> O;
+      load_op<d>(ops + C1.slot * dd, O);
+      const float c = coef(cq, C1.cidx);
 #pragma unroll
-      for (int i = 0; i < d * d; ++i) {
+      for (int i = 0; i < dd; ++i) {
         O.re[i] *= c;
         O.im[i] *= c;
       }
-      dispatch_single<d, NR>(I.pos, O, in, out);
-    } else {
-      Op<d> W;
-      load_op<d>(ops + P->off_pair + I.pair[0] * d * d, W);
-      dispatch_pair<d, NR>(I.pos, I.pos_j[0], O, W, c, in, out);
+      contract_acc<d, NR, p>(O, in, out);
+    });
+  }
+  if (P->has_diag[l]) {
+    static_for<NR>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      diag_acc<d, NR, p>(P->delta[P->cdiag[l][p]], in, out);
+    });
+  }
+}
+
+}  // namespace scp
+
+namespace scp {
+
+template <int d>
+__device__ __forceinline__ int thread_base(const Plan* __restrict__ P, int l, int tc) {
+  int b = 0, t = tc;
+  const int NT = P->NT;
+  for (int k = 0; k < NT; ++k) {
+    const int q = t / d;
+    b += (t - q * d) * P->tstride[l][k];
+    t = q;
+  }
+  return b;
+}
+
+// Layout switch of one or two vectors (WAR barrier, write, RAW barrier, read).
+template <int d, int NR, int RB>
+__device__ __forceinline__ void switch1(const Plan* __restrict__ P, c32* lds, int cbase,
+                                        bool lds_ok, int tc, int from, int to, Vec<RB>& v) {
+  __syncthreads();
+  if (lds_ok) lds_put<d, NR, RB>(lds, cbase + thread_base<d>(P, from, tc), reg_off_of<d, NR>(P, from), v);
+  __syncthreads();
+  if (lds_ok) lds_get<d, NR, RB>(lds, cbase + thread_base<d>(P, to, tc), reg_off_of<d, NR>(P, to), v);
+}
+
+template <int d, int NR, int RB>
+__device__ __forceinline__ void switch2(const Plan* __restrict__ P, c32* lds, int cbase,
+                                        int vstride, bool lds_ok, int tc, int from, int to,
+                                        Vec<RB>& v, Vec<RB>& w) {
+  __syncthreads();
+  if (lds_ok) {
+    const int b = cbase + thread_base<d>(P, from, tc);
+    const RegOff<d, NR> R = reg_off_of<d, NR>(P, from);
+    lds_put<d, NR, RB>(lds, b, R, v);
+    lds_put<d, NR, RB>(lds + vstride, b, R, w);
+  }
+  __syncthreads();
+  if (lds_ok) {
+    const int b = cbase + thread_base<d>(P, to, tc);
+    const RegOff<d, NR> R = reg_off_of<d, NR>(P, to);
+    lds_get<d, NR, RB>(lds, b, R, v);
+    lds_get<d, NR, RB>(lds + vstride, b, R, w);
+  }
+}
+
+// k = V(t) y for one stage; y enters and k leaves in the base layout (L-1);
+// y is left in an unspecified layout.
+template <int d, int NR, int MP, int RB>
+__device__ __forceinline__ void stage_apply(const Plan* __restrict__ P, c32* lds, int cbase,
+                                            int vstride, bool lds_ok, int tc,
+                                            const c32* __restrict__ ops,
+                                            const float* __restrict__ cq, Vec<RB>& y, Vec<RB>& k) {
+  const int L = P->L;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    k.re[r] = 0.f;
+    k.im[r] = 0.f;
+  }
+  if (L > 1) switch1<d, NR, RB>(P, lds, cbase, lds_ok, tc, L - 1, 0, y);
+  apply_layout<d, NR, MP, RB>(P, 0, ops, cq, y, k);
+  for (int l = 1; l < L; ++l) {
+    switch2<d, NR, RB>(P, lds, cbase, vstride, lds_ok, tc, l - 1, l, y, k);
+    apply_layout<d, NR, MP, RB>(P, l, ops, cq, y, k);
+  }
+}
+
+__device__ __forceinline__ int stage_q(int n, int s) { return 2 * n + (s == 0 ? 0 : (s == 3 ? 2 : 1)); }
+__device__ __forceinline__ int stage_c(int n, int s) { return 3 * n + (s == 0 ? 0 : (s == 3 ? 2 : 1)); }
+
+// Two-sum compensated x_hi + x_lo += dx (x_lo kept with |x_lo| <= ulp(x_hi)/2).
+__device__ __forceinline__ void comp_add(float& hi, float& lo, float dx) {
+  const float sx = hi + dx;
+  const float bp = sx - hi;
+  const float err = (hi - (sx - bp)) + (dx - bp);
+  const float l2 = lo + err;
+  const float s2 = sx + l2;
+  lo = l2 - (s2 - sx);
+  hi = s2;
+}
+
+// One classical RK4 step n on psi = hi + lo.  hi lives in registers; lo is
+// this thread's register-order slice in device memory (stride TPC), read and
+// written once per step; the RK accumulator is this thread's slice in LDS
+// (accs, stride TPC).  Stage inputs are formed from hi alone (the stage
+// increments are O(h |V|) of psi, so the dropped lo is below their rounding).
+// If ystore != nullptr the four stage inputs are written there (stride
+// ystride between stages) for the adjoint.
+template <int d, int NR, int MP, int RB>
+__device__ __forceinline__ void rk4_step(const Plan* __restrict__ P, c32* lds, int cbase,
+                                         int vstride, bool lds_ok, bool active, int tc, int TPC,
+                                         const c32* __restrict__ optab,
+                                         const float* __restrict__ ctab, int n, Vec<RB>& hi,
+                                         c32* __restrict__ lo, c32* accs, c32* __restrict__ ystore,
+                                         size_t ystride) {
+  const float h = P->h;
+  const int ng = P->ngroups;
+  const int bq = P->block_q;
+  Vec<RB> y, k;
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    y.re[r] = hi.re[r];
+    y.im[r] = hi.im[r];
+  }
+#pragma unroll 1
+  for (int s = 0; s < 4; ++s) {
+    if (ystore != nullptr && active) {
+      c32* dst = ystore + (size_t)s * ystride;
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        c32 v;
+        v.x = y.re[r];
+        v.y = y.im[r];
+        dst[(size_t)r * TPC] = v;
+      }
+    }
+    const c32* ops = optab + (size_t)stage_q(n, s) * bq;
+    const float* cq = ctab + (size_t)stage_c(n, s) * ng;
+    stage_apply<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, tc, ops, cq, y, k);
+    // k_s = -i V y;  acc (+)= w_s k_s;  y_{s+1} = hi + c_{s+1} h k_s
+    const float w = (s == 0 || s == 3) ? 1.f : 2.f;
+    const float ch = (s == 2) ? h : 0.5f * h;
+    if (lds_ok) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const float kr = k.im[r], ki = -k.re[r];
+        c32 a;
+        if (s == 0) {
+          a.x = kr;
+          a.y = ki;
+        } else {
+          a = accs[r * TPC];
+          a.x = fmaf(w, kr, a.x);
+          a.y = fmaf(w, ki, a.y);
+        }
+        accs[r * TPC] = a;
+        if (s < 3) {
+          y.re[r] = fmaf(ch, kr, hi.re[r]);
+          y.im[r] = fmaf(ch, ki, hi.im[r]);
+        }
+      }
+    }
+  }
+  // psi <- psi + h/6 acc, compensated (all loads issued before the updates)
+  const float h6 = h * (1.0f / 6.0f);
+  if (active) {
+    Vec<RB> lv, av;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const c32 l = lo[(size_t)r * TPC];
+      const c32 a = accs[r * TPC];
+      lv.re[r] = l.x;
+      lv.im[r] = l.y;
+      av.re[r] = a.x;
+      av.im[r] = a.y;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      comp_add(hi.re[r], lv.re[r], h6 * av.re[r]);
+      comp_add(hi.im[r], lv.im[r], h6 * av.im[r]);
+      c32 l;
+      l.x = lv.re[r];
+      l.y = lv.im[r];
+      lo[(size_t)r * TPC] = l;
     }
   }
 }

@@ -34,11 +34,11 @@ hipError_t launch_tables_impl(int d, int nslots, int npairs, int ndrives, int ng
 size_t drive_static_size();
 void pack_drive_static(void* dst, int k, int env, int npar, int par0, int group, double omega,
                        double phase, double sigma);
-scp_status launch_rk4_range(const scp_system* sys, const float2* psi0, float2* psiT, float4* state,
-                            float4* ckpt, int ce, int S, int n0, int n1, hipStream_t s);
+scp_status launch_rk4_range(const scp_system* sys, const float2* psi0, float2* psiT, float2* state,
+                            float2* lo, float4* ckpt, int ce, int S, int n0, int n1, hipStream_t s);
 scp_status launch_adjoint_impl(const scp_system* sys, const void* ckpt, const void* lamT,
-                               void* segbuf, void* lamsave, double* part, int ce, int nckpt, int S,
-                               hipStream_t s);
+                               void* segbuf, void* lo, void* sum, double* part, int ce, int nckpt,
+                               int S, hipStream_t s);
 
 namespace {
 
@@ -167,52 +167,43 @@ scp_status make_plan(scp_system* sys) {
   }
   for (auto& r : sys->drives) slot(r.mode, r.op);
   if ((int)sys->slot_mode.size() > MAXSLOTS) return fail(SCP_EINVAL, "too many operator slots");
-  // --- layouts ---------------------------------------------------------
+  // --- layouts: paths of the coupling graph ----------------------------
   std::vector<std::vector<int>> layouts;
   std::set<std::pair<int, int>> unc;
-  for (auto& c : sys->coup) unc.insert({std::min(c.i, c.j), std::max(c.i, c.j)});
-  if (N <= NR) {
-    std::vector<int> all;
-    for (int m = 0; m < N; ++m) all.push_back(m);
-    layouts.push_back(all);
-    unc.clear();
-  }
-  auto covered_by = [&](const std::vector<int>& S) {
-    for (auto it = unc.begin(); it != unc.end();) {
-      bool a = std::find(S.begin(), S.end(), it->first) != S.end();
-      bool b = std::find(S.begin(), S.end(), it->second) != S.end();
-      if (a && b) it = unc.erase(it);
-      else ++it;
-    }
+  auto key = [](int a, int b) { return std::make_pair(std::min(a, b), std::max(a, b)); };
+  for (auto& c : sys->coup) unc.insert(key(c.i, c.j));
+  auto in = [](const std::vector<int>& S, int m) {
+    return std::find(S.begin(), S.end(), m) != S.end();
   };
   while (!unc.empty()) {
-    // first uncovered edge in coupling order
     std::pair<int, int> e{-1, -1};
-    for (auto& c : sys->coup) {
-      auto k = std::make_pair(std::min(c.i, c.j), std::max(c.i, c.j));
-      if (unc.count(k)) { e = k; break; }
-    }
+    for (auto& c : sys->coup)
+      if (unc.count(key(c.i, c.j))) { e = std::make_pair(c.i, c.j); break; }
     std::vector<int> S{e.first, e.second};
-    while ((int)S.size() < NR) {
-      int best = -1, bestc = 0;
-      for (int m = 0; m < N; ++m) {
-        if (std::find(S.begin(), S.end(), m) != S.end()) continue;
-        int cnt = 0;
-        for (int s : S) cnt += unc.count({std::min(m, s), std::max(m, s)});
-        if (cnt > bestc) { bestc = cnt; best = m; }
+    unc.erase(key(e.first, e.second));
+    bool grew = true;
+    while ((int)S.size() < NR && grew) {
+      grew = false;
+      for (int side = 0; side < 2 && !grew && (int)S.size() < NR; ++side) {
+        const int end = side == 0 ? S.back() : S.front();
+        for (auto& c : sys->coup) {
+          int other = c.i == end ? c.j : (c.j == end ? c.i : -1);
+          if (other < 0 || in(S, other) || !unc.count(key(end, other))) continue;
+          unc.erase(key(end, other));
+          if (side == 0) S.push_back(other);
+          else S.insert(S.begin(), other);
+          grew = true;
+          break;
+        }
       }
-      if (best < 0) break;
-      S.push_back(best);
     }
     for (int m = 0; m < N && (int)S.size() < NR; ++m)
-      if (std::find(S.begin(), S.end(), m) == S.end()) S.push_back(m);
-    covered_by(S);
+      if (!in(S, m)) S.push_back(m);
     layouts.push_back(S);
   }
-  // every mode must appear in some layout (single-mode terms)
   for (int m = 0; m < N; ++m) {
     bool found = false;
-    for (auto& S : layouts) found |= std::find(S.begin(), S.end(), m) != S.end();
+    for (auto& S : layouts) found |= in(S, m);
     if (!found) {
       std::vector<int> S{m};
       for (int q = 0; q < N && (int)S.size() < NR; ++q)
@@ -226,9 +217,8 @@ scp_status make_plan(scp_system* sys) {
   std::vector<int> stride(N);
   for (int m = 0; m < N; ++m) stride[m] = ipow(d, N - 1 - m);
   for (int l = 0; l < L; ++l) {
-    auto S = layouts[l];
-    std::sort(S.begin(), S.end());
-    layouts[l] = S;
+    const auto& S = layouts[l];
+    for (int p = 0; p < NR; ++p) P.reg_stride[l][p] = stride[S[p]];
     for (int r = 0; r < RB; ++r) {
       int off = 0, rr = r;
       for (int p = NR - 1; p >= 0; --p) {
@@ -240,7 +230,7 @@ scp_status make_plan(scp_system* sys) {
     // thread modes, digit 0 = smallest stride (largest mode index)
     std::vector<int> T;
     for (int m = N - 1; m >= 0; --m)
-      if (std::find(S.begin(), S.end(), m) == S.end()) T.push_back(m);
+      if (!in(S, m)) T.push_back(m);
     for (int k = 0; k < (int)T.size(); ++k) P.tstride[l][k] = stride[T[k]];
   }
   auto pos_in = [&](int l, int m) {
@@ -256,81 +246,115 @@ scp_status make_plan(scp_system* sys) {
         P.pos_of_mode[m] = pos_in(l, m);
       }
   }
-  // --- items -------------------------------------------------------------
-  // couplings grouped by (layout, first slot, partner mode)
-  struct PairKey { int l, s, j; };
-  std::vector<PairKey> pairs;
+  // --- pair terms: first factor at position p, partner at p + 1 ----------
+  struct Grp { int l, p, s, j; };
+  std::vector<Grp> grps;
   std::vector<std::vector<cplx>> pairW;
-  for (auto& c : sys->coup) {
-    int l = -1;
-    for (int q = 0; q < L && l < 0; ++q)
-      if (pos_in(q, c.i) >= 0 && pos_in(q, c.j) >= 0) l = q;
-    int s = slot(c.i, c.op_i);
-    int p = -1;
-    for (int q = 0; q < (int)pairs.size(); ++q)
-      if (pairs[q].l == l && pairs[q].s == s && pairs[q].j == c.j) p = q;
-    if (p < 0) {
-      p = (int)pairs.size();
-      pairs.push_back({l, s, c.j});
+  for (int e = 0; e < (int)sys->coup.size(); ++e) {
+    const Coupling& c = sys->coup[e];
+    int l = -1, p = -1;
+    bool swapped = false;
+    for (int q = 0; q < L && l < 0; ++q) {
+      const int pi = pos_in(q, c.i), pj = pos_in(q, c.j);
+      if (pi >= 0 && pj >= 0 && (pj == pi + 1 || pi == pj + 1)) {
+        l = q;
+        p = std::min(pi, pj);
+        swapped = pj < pi;
+      }
+    }
+    if (l < 0) return fail(SCP_EINVAL, "coupling graph not supported by the fused path");
+    const int fm = swapped ? c.j : c.i, fop = swapped ? c.op_j : c.op_i;   // first factor
+    const int pm = swapped ? c.i : c.j, pop = swapped ? c.op_i : c.op_j;   // partner
+    const int s1 = slot(fm, fop);
+    int g = -1;
+    for (int q = 0; q < (int)grps.size(); ++q)
+      if (grps[q].l == l && grps[q].p == p && grps[q].s == s1) g = q;
+    if (g < 0) {
+      g = (int)grps.size();
+      if (g >= MAXPAIRS) return fail(SCP_EINVAL, "too many coupling pairs");
+      grps.push_back({l, p, s1, pm});
       pairW.push_back(std::vector<cplx>(d * d, 0.0));
     }
-    const cplx* Bj = sys->modes[c.j].ops[c.op_j];
-    for (int i = 0; i < d * d; ++i) pairW[p][i] += c.g * Bj[i];
-    if (p < MAXPAIRS) {
-      if (P.pair_ncoup[p] >= 4) return fail(SCP_EINVAL, "more than 4 couplings on one mode pair");
-      P.pair_coup[p][P.pair_ncoup[p]++] = (int)(&c - &sys->coup[0]);
+    const cplx* Bj = sys->modes[pm].ops[pop];
+    for (int i = 0; i < d * d; ++i) pairW[g][i] += c.g * Bj[i];
+    if (P.pair_ncoup[g] >= 4) return fail(SCP_EINVAL, "more than 4 couplings on one mode pair");
+    P.pair_pslot[g][P.pair_ncoup[g]] = slot(pm, pop);
+    P.pair_coup[g][P.pair_ncoup[g]++] = e;
+  }
+  P.npairs = (int)grps.size();
+  int MP = 1;
+  for (int l = 0; l < L; ++l)
+    for (int p = 0; p + 1 < NR; ++p) {
+      int cnt = 0;
+      for (auto& g : grps) cnt += (g.l == l && g.p == p);
+      MP = std::max(MP, cnt);
+    }
+  if (MP > 2) return fail(SCP_EINVAL, "more than two coupling terms per mode pair and layout");
+  P.MP = MP;
+  if ((int)sys->slot_mode.size() + 1 > MAXSLOTS) return fail(SCP_EINVAL, "too many operator slots");
+  const int zslot = (int)sys->slot_mode.size();   // zero operator slot
+  const int zpair = P.npairs;                       // zero pair operator
+  for (int l = 0; l < L; ++l) {
+    for (int p = 0; p < 4; ++p)
+      for (int m = 0; m < 2; ++m) {
+        CPair& C = P.cpair[l][p][m];
+        C.slot = (int16_t)zslot;
+        C.pair = (int16_t)zpair;
+        C.cidx = -1;
+        C.mode_i = C.mode_j = -1;
+      }
+    for (int p = 0; p < 8; ++p) {
+      P.csingle[l][p].slot = (int16_t)zslot;
+      P.csingle[l][p].cidx = -1;
+      P.cdiag[l][p] = 16;
+      P.mode_pass[l][p] = -1;
     }
   }
-  if ((int)pairs.size() > MAXPAIRS) return fail(SCP_EINVAL, "too many coupling pairs");
-  P.npairs = (int)pairs.size();
-  // drive groups: one per slot
+  {
+    std::vector<int> fill((size_t)L * 4, 0);
+    for (int g = 0; g < (int)grps.size(); ++g) {
+      const int m = fill[grps[g].l * 4 + grps[g].p]++;
+      CPair& C = P.cpair[grps[g].l][grps[g].p][m];
+      C.slot = (int16_t)grps[g].s;
+      C.pair = (int16_t)g;
+      C.mode_i = (int16_t)sys->slot_mode[grps[g].s];
+      C.mode_j = (int16_t)grps[g].j;
+    }
+  }
+  // --- drives: attach to a pair term with the same first factor, else a single term
   std::map<int, int> group_of_slot;
   for (auto& r : sys->drives) {
-    int s = slot(r.mode, r.op);
-    if (!group_of_slot.count(s)) {
+    int s1 = slot(r.mode, r.op);
+    if (!group_of_slot.count(s1)) {
       int g = (int)group_of_slot.size();
-      group_of_slot[s] = g;
+      group_of_slot[s1] = g;
     }
   }
   P.ngroups = (int)group_of_slot.size();
   if (P.ngroups > MAXGROUPS) return fail(SCP_EINVAL, "too many drive groups");
-  std::vector<std::vector<Item>> items(L);
-  for (int p = 0; p < (int)pairs.size(); ++p) {
-    Item I{};
-    I.kind = 1;
-    I.slot = (int16_t)pairs[p].s;
-    I.mode = (int16_t)sys->slot_mode[pairs[p].s];
-    I.pos = (int8_t)pos_in(pairs[p].l, I.mode);
-    I.n_part = 1;
-    I.pos_j[0] = (int8_t)pos_in(pairs[p].l, pairs[p].j);
-    I.mode_j[0] = (int16_t)pairs[p].j;
-    I.pair[0] = (int16_t)p;
-    I.cidx = -1;
-    items[pairs[p].l].push_back(I);
-  }
   for (auto& kv : group_of_slot) {
-    int s = kv.first, g = kv.second, m = sys->slot_mode[s];
+    const int s1 = kv.first, g = kv.second, m = sys->slot_mode[s1];
     bool attached = false;
     for (int l = 0; l < L && !attached; ++l)
-      for (auto& I : items[l])
-        if (I.kind == 1 && I.slot == s && I.cidx < 0) {
-          I.cidx = (int16_t)g;
-          attached = true;
-          break;
+      for (int p = 0; p + 1 < NR && !attached; ++p)
+        for (int q = 0; q < MP && !attached; ++q) {
+          CPair& C = P.cpair[l][p][q];
+          if (C.slot == s1 && C.cidx < 0) {
+            C.cidx = (int16_t)g;
+            attached = true;
+          }
         }
     if (!attached) {
-      Item I{};
-      I.kind = 1;
-      I.slot = (int16_t)s;
-      I.mode = (int16_t)m;
-      int l = P.layout_of_mode[m];
-      I.pos = (int8_t)P.pos_of_mode[m];
-      I.n_part = 0;
-      I.cidx = (int16_t)g;
-      items[l].push_back(I);
+      const int l = P.layout_of_mode[m], p = P.pos_of_mode[m];
+      if (P.csingle[l][p].slot != zslot)
+        return fail(SCP_EINVAL, "two drive-only operators on one mode");
+      P.csingle[l][p].slot = (int16_t)s1;
+      P.csingle[l][p].cidx = (int16_t)g;
+      P.has_single[l] = 1;
     }
   }
   P.has_delta = 0;
+  for (int a = 0; a < 8; ++a) P.delta[16][a] = 0.f;
   for (int m = 0; m < N; ++m) {
     bool nz = false;
     for (int a = 0; a < d; ++a) {
@@ -338,30 +362,16 @@ scp_status make_plan(scp_system* sys) {
       P.delta[m][a] = (float)v;
       nz |= v != 0.0;
     }
+    const int l = P.layout_of_mode[m], p = P.pos_of_mode[m];
     if (nz) {
       P.has_delta = 1;
-      Item I{};
-      I.kind = 0;
-      I.mode = (int16_t)m;
-      I.pos = (int8_t)P.pos_of_mode[m];
-      I.cidx = -1;
-      items[P.layout_of_mode[m]].push_back(I);
+      P.has_diag[l] = 1;
+      P.cdiag[l][p] = m;
     }
-  }
-  for (int m = 0; m < N; ++m) {
-    Item I{};
-    I.kind = 2;
-    I.mode = (int16_t)m;
-    I.pos = (int8_t)P.pos_of_mode[m];
-    I.cidx = -1;
-    items[P.layout_of_mode[m]].push_back(I);
+    P.mode_pass[l][p] = m;
+    P.has_mode_pass[l] = 1;
     for (int th = 0; th < 3; ++th)
       for (int a = 0; a < d; ++a) P.deps[m][th][a] = (float)sys->modes[m].deps[th][a];
-  }
-  for (int l = 0; l < L; ++l) {
-    if ((int)items[l].size() > MAXITEMS) return fail(SCP_EINVAL, "too many terms in one layout");
-    P.n_items[l] = (int)items[l].size();
-    for (int i = 0; i < (int)items[l].size(); ++i) P.items[l][i] = items[l][i];
   }
   // drives
   int par0 = 0;
@@ -376,8 +386,8 @@ scp_status make_plan(scp_system* sys) {
   }
   P.npulse = par0;
   if (P.npulse > MAXPULSE) return fail(SCP_EINVAL, "too many pulse parameters");
-  P.nslots = (int)sys->slot_mode.size();
-  for (int s = 0; s < P.nslots; ++s) {
+  P.nslots = (int)sys->slot_mode.size() + 1;   // + the zero slot
+  for (int s = 0; s < P.nslots - 1; ++s) {
     P.slot_mode[s] = sys->slot_mode[s];
     P.slot_op[s] = sys->slot_op[s];
   }
@@ -389,8 +399,17 @@ scp_status make_plan(scp_system* sys) {
   }
   P.nacc = P.npulse + 3 * N + P.ncoup;
   P.off_pair = P.nslots * d * d;
-  P.off_dslot = (P.nslots + P.npairs) * d * d;
-  P.block_q = (P.nslots + P.npairs + 3 * P.nslots) * d * d;
+  P.off_dslot = (P.nslots + P.npairs + 1) * d * d;
+  P.block_q = (P.nslots + P.npairs + 1 + 3 * P.nslots) * d * d;
+  // LDS per workgroup: two layout-switch vectors + one per-thread slice vector
+  // per column, plus the adjoint's FP64 accumulators (4 waves max).
+  {
+    const long budget = 163840 - 4L * 8 * std::max(1, P.nacc);
+    const long per_col = 3L * 8 * P.D;
+    const int cpw_lds = (int)(budget / per_col);
+    if (cpw_lds < 1) return fail(SCP_EINVAL, "system too large for the on-chip path (LDS)");
+    P.CPW = std::min(P.CPW, cpw_lds);
+  }
   int threads = P.CPW * TPC;
   P.WG = ((threads + 63) / 64) * 64;
   // host copy of pair W for the table kernel
@@ -398,20 +417,23 @@ scp_status make_plan(scp_system* sys) {
   sys->pair_mode_host.clear();
   for (int p = 0; p < P.npairs; ++p) {
     for (auto v : pairW[p]) sys->pairW_host.push_back(v);
-    sys->pair_mode_host.push_back(pairs[p].j);
+    sys->pair_mode_host.push_back(grps[p].j);
   }
+  for (int i = 0; i < d * d; ++i) sys->pairW_host.push_back(0.0);   // zero pair operator
+  sys->pair_mode_host.push_back(0);
   return SCP_OK;
 }
 
 scp_status build_tables(scp_system* sys, hipStream_t st) {
   const Plan& P = sys->plan;
   const int d = sys->d, dd = d * d, N = sys->n_modes;
+  const int ns = P.nslots, np1 = P.npairs + 1;   // both include a trailing zero operator
   std::vector<double> frames((size_t)N * 8, 0.0);
   for (int m = 0; m < N; ++m)
     for (int a = 0; a < d; ++a) frames[m * 8 + a] = sys->modes[m].frame[a];
-  std::vector<double2> sops((size_t)P.nslots * dd), pops((size_t)std::max(1, P.npairs) * dd),
-      dops((size_t)std::max(1, P.nslots) * 3 * dd);
-  for (int s = 0; s < P.nslots; ++s) {
+  std::vector<double2> sops((size_t)ns * dd, make_double2(0, 0)), pops((size_t)np1 * dd, make_double2(0, 0)),
+      dops((size_t)ns * 3 * dd, make_double2(0, 0));
+  for (int s = 0; s < ns - 1; ++s) {
     const ModeData& M = sys->modes[P.slot_mode[s]];
     for (int i = 0; i < dd; ++i) {
       cplx v = M.ops[P.slot_op[s]][i];
@@ -422,14 +444,14 @@ scp_status build_tables(scp_system* sys, hipStream_t st) {
       }
     }
   }
-  for (int p = 0; p < P.npairs; ++p)
+  for (int p = 0; p < np1; ++p)
     for (int i = 0; i < dd; ++i) {
       cplx v = sys->pairW_host[p * dd + i];
       pops[p * dd + i] = make_double2(v.real(), v.imag());
     }
-  std::vector<int> smode(std::max(1, P.nslots)), pmode(std::max(1, P.npairs));
-  for (int s = 0; s < P.nslots; ++s) smode[s] = P.slot_mode[s];
-  for (int p = 0; p < P.npairs; ++p) pmode[p] = sys->pair_mode_host[p];
+  std::vector<int> smode(ns, 0), pmode(np1, 0);
+  for (int s = 0; s < ns - 1; ++s) smode[s] = P.slot_mode[s];
+  for (int p = 0; p < np1; ++p) pmode[p] = sys->pair_mode_host[p];
   // drives
   std::vector<char> dstat(drive_static_size() * std::max<size_t>(1, sys->drives.size()));
   std::vector<double> par;
@@ -464,7 +486,7 @@ scp_status build_tables(scp_system* sys, hipStream_t st) {
   HIPCHK(hipMalloc(&sys->d_ctab, np3 * std::max(1, P.ngroups) * sizeof(float)));
   HIPCHK(hipMalloc(&sys->d_dctab, np3 * std::max(1, P.npulse) * sizeof(float)));
   HIPCHK(hipMalloc(&sys->d_dctab64, np3 * std::max(1, P.npulse) * sizeof(double)));
-  HIPCHK(launch_tables_impl(d, P.nslots, P.npairs, (int)sys->drives.size(), P.ngroups, P.npulse,
+  HIPCHK(launch_tables_impl(d, ns, np1, (int)sys->drives.size(), P.ngroups, P.npulse,
                             sys->n_steps, sys->h, sys->T, (const double*)bf.p,
                             (const double2*)bs.p, (const double2*)bp.p, (const double2*)bd.p,
                             (const int*)bsm.p, (const int*)bpm.p, sys->d_ops, P.block_q, bdr.p,
@@ -592,7 +614,7 @@ scp_status build(const scp_system_desc* ds, hipStream_t st, scp_system* sys) {
 
 // Workspace layout (bytes)
 struct WsLayout {
-  size_t ckpt = 0, seg = 0, part = 0, lam = 0, total = 0;
+  size_t lo = 0, ckpt = 0, seg = 0, part = 0, lam = 0, total = 0;
   int nckpt = 0, ce = 0, nwg = 0;
 };
 
@@ -605,6 +627,8 @@ WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad
   size_t off = 0;
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
   if (o->precision == 0) {
+    w.lo = off;
+    off = align(off + S * D * sizeof(float2));
     if (o->with_ckpt || with_grad) {
       w.ckpt = off;
       off = align(off + (size_t)w.nckpt * S * D * sizeof(float4));
@@ -712,9 +736,10 @@ scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* work
   hipStream_t st = (hipStream_t)stream;
   if (opts->precision == 1)
     return launch_plain64(sys, (const double2*)psi0, (double2*)psiT, workspace, opts->n_cols, st);
-  if (opts->with_ckpt && !workspace) return fail(SCP_EINVAL, "checkpoints need a workspace");
+  if (!workspace) return fail(SCP_EINVAL, "the FP32 path needs a workspace (scp_workspace_size)");
   float4* ck = opts->with_ckpt ? (float4*)((char*)workspace + w.ckpt) : nullptr;
-  return launch_rk4(sys, (const float2*)psi0, (float2*)psiT, ck, w.ce, opts->n_cols, st);
+  return launch_rk4(sys, (const float2*)psi0, (float2*)psiT, (float2*)((char*)workspace + w.lo), ck,
+                    w.ce, opts->n_cols, st);
 }
 
 scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, int32_t d_c,
@@ -747,7 +772,7 @@ scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, vo
   WsLayout w = ws_layout(sys, opts, 1);
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
-  scp_status s = launch_adjoint_impl(sys, ws + w.ckpt, cotangent, ws + w.seg, ws + w.lam,
+  scp_status s = launch_adjoint_impl(sys, ws + w.ckpt, cotangent, ws + w.seg, ws + w.lo, ws + w.lam,
                                      (double*)(ws + w.part), w.ce, w.nckpt, opts->n_cols, st);
   if (s != SCP_OK) return s;
   const int nacc = sys->plan.nacc;

@@ -1,6 +1,7 @@
 """Write stored oracle results used by the GPU tests (calls only oracle/).
 
-    python tests/golden/make_oracle_refs.py
+    python tests/golden/make_oracle_refs.py            # config3_oracle.json
+    python tests/golden/make_oracle_refs.py config5    # config5_sampled_oracle.json
 
 config3_oracle.json: loss, fidelity and the full gradient of the config-3
 workload (4-fluxonium chain, CZ(q0,q1) x I x I target, 5000 RK4 steps),
@@ -9,6 +10,8 @@ computed by the CPU FP64 oracle (several minutes of CPU time).
 import json
 import os
 import sys
+
+import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
@@ -30,5 +33,35 @@ def main():
         json.dump(out, f, indent=1)
 
 
-if __name__ == "__main__":
+if __name__ == "__main__" and len(sys.argv) == 1:
     main()
+
+
+def config5_sampled():
+    """Oracle F and gradient for the 8 seeded sampled columns of the 8-transmon
+    ring (fidelity restricted to the sampled computational states)."""
+    desc = sampled_config5_desc()
+    sys_ = OracleSystem(desc)
+    L, F, tau, U, g = loss_and_grad(sys_)
+    out = {"workload": "config5 sampled: 8-transmon ring d=3, T=60 ns, 3000 steps, 8 sampled "
+                       "computational columns, CZ(q0,q1) restricted to them",
+           "generator": "tests/golden/make_oracle_refs.py (oracle only)",
+           "columns": desc["columns"], "L": L, "F": F, "tau": [tau.real, tau.imag],
+           "param_names": param_names(sys_), "grad": [float(v) for v in g]}
+    with open(os.path.join(HERE, "config5_sampled_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+def sampled_config5_desc():
+    desc = si.config5()
+    samp = si.sampled_columns(len(desc["columns"]), 8)
+    full_t = desc["target"]
+    desc["comp_rows"] = [desc["comp_rows"][j] for j in samp]
+    desc["columns"] = [desc["columns"][j] for j in samp]
+    desc["comp_cols"] = list(range(len(samp)))
+    desc["target"] = full_t[np.ix_(samp, samp)]
+    return desc
+
+
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "config5":
+    config5_sampled()
