@@ -191,6 +191,53 @@ scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, vo
 
 void scp_destroy(scp_system* sys);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of propagation / gradient requests.
+ *
+ * Requests queue on the host and are admitted in arrival order while their
+ * device footprint (stage tables, states, checkpoints, adjoint buffers) fits
+ * hbm_budget_bytes and fewer than max_active requests run.  Each
+ * scp_server_step is one tick: admit, advance every running request by one
+ * chunk (forward steps, then adjoint segments) with one batched launch per
+ * size class (d, register modes, pair terms per position), reduce fidelities,
+ * finish gradients, release memory.  Work per tick per workgroup is about
+ * chunk_work cost units (0 = default).  A request's result is bitwise the same
+ * whether it runs alone or among others.  The server allocates device memory
+ * (at admission); it is not for callers that cannot allocate.
+ * ------------------------------------------------------------------------ */
+typedef struct scp_server scp_server;
+
+enum { SCP_REQ_QUEUED = 0, SCP_REQ_RUNNING = 1, SCP_REQ_DONE = 2, SCP_REQ_FAILED = 3 };
+
+scp_status scp_server_create(size_t hbm_budget_bytes, int32_t max_active, double chunk_work,
+                             void* stream, scp_server** out);
+
+/* Queue one request: the system description (deep-copied), the basis index of
+ * each propagated column (host, n_cols), the computational rows (host int64,
+ * d_c) and columns (host int32 positions in [0, n_cols), d_c), the target
+ * (host complex128, d_c x d_c row-major as (re, im) pairs) and whether the
+ * gradient is wanted.  SCP_EBUSY if the request alone exceeds the budget. */
+scp_status scp_server_submit(scp_server* sv, const scp_system_desc* desc, const int64_t* columns,
+                             int32_t n_cols, const int64_t* comp_rows, const int32_t* comp_cols,
+                             int32_t d_c, const double* target, int32_t want_grad,
+                             int64_t* id_out);
+
+/* Device footprint the server reserves for a request (admission unit). */
+scp_status scp_request_bytes(const scp_system_desc* desc, int32_t n_cols, int32_t want_grad,
+                             size_t* bytes);
+
+/* One tick (synchronises the server's stream once). */
+scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued);
+
+/* State (SCP_REQ_*), fidelity, gradient (n_params entries when done, order
+ * as scp_system_info; nullable) and the submit / admit / completion times in
+ * seconds since the server was created. */
+scp_status scp_server_result(scp_server* sv, int64_t id, int32_t* state, double* F, double* grad,
+                             int32_t* n_params, double* t_submit, double* t_admit,
+                             double* t_done);
+
+void scp_server_destroy(scp_server* sv);
+
 /* Message of the last failing call on this thread ("" if none); valid until
  * the next call on this thread. */
 const char* scp_last_error(void);

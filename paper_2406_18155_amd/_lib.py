@@ -66,6 +66,20 @@ EXPORTS = {
     "scp_propagate_adjoint": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
                                         C.POINTER(C.c_double), C.c_void_p]),
     "scp_destroy": (None, [C.c_void_p]),
+    "scp_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.c_double, C.c_void_p,
+                                    C.POINTER(C.c_void_p)]),
+    "scp_server_submit": (C.c_int, [C.c_void_p, C.POINTER(SystemDesc), C.POINTER(C.c_int64),
+                                    C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                    C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                    C.POINTER(C.c_int64)]),
+    "scp_request_bytes": (C.c_int, [C.POINTER(SystemDesc), C.c_int32, C.c_int32,
+                                    C.POINTER(C.c_size_t)]),
+    "scp_server_step": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "scp_server_result": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_int32), C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "scp_server_destroy": (None, [C.c_void_p]),
     "scp_last_error": (C.c_char_p, []),
 }
 

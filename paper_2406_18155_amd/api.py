@@ -30,58 +30,65 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def marshal(desc):
+    """(SystemDesc, keep-alive list) for a descriptor dict."""
+    keep = []
+    modes = (ModeDesc * len(desc["modes"]))()
+    for m, md in enumerate(desc["modes"]):
+        M = modes[m]
+        M.kind = MODE_KIND[md["kind"]]
+        M.basis_dim = int(md.get("basis_dim", md["trunc"]))
+        M.trunc = int(md["trunc"])
+        M.EC, M.EJ, M.EL = float(md.get("EC", 0)), float(md.get("EJ", 0)), float(md.get("EL", 0))
+        M.ng, M.phiext = float(md.get("ng", 0.0)), float(md.get("phiext", 0.0))
+        if md.get("frame_eps") is not None:
+            M.has_frame = 1
+            for a, v in enumerate(np.asarray(md["frame_eps"], dtype=np.float64)[: M.trunc]):
+                M.frame_eps[a] = float(v)
+        if md["kind"] == "raw":
+            d = M.trunc
+            eps = np.ascontiguousarray(np.asarray(md["eps"], dtype=np.float64)[:d])
+            ops = np.zeros((2, d, d, 2))
+            for o, name in enumerate(("n", "phi")):
+                a = np.asarray(md["ops"][name], dtype=np.complex128)
+                ops[o, :, :, 0] = a.real
+                ops[o, :, :, 1] = a.imag
+            ops = np.ascontiguousarray(ops)
+            keep += [eps, ops]
+            M.raw_eps = eps.ctypes.data_as(C.POINTER(C.c_double))
+            M.raw_ops = ops.ctypes.data_as(C.POINTER(C.c_double))
+    coups = (CouplingDesc * max(1, len(desc["couplings"])))()
+    for e, c in enumerate(desc["couplings"]):
+        coups[e].i, coups[e].j = int(c["i"]), int(c["j"])
+        coups[e].op_i, coups[e].op_j = OP[c["op_i"]], OP[c["op_j"]]
+        coups[e].g = float(c["g"])
+    drives = (DriveDesc * max(1, len(desc["drives"])))()
+    for k, dr in enumerate(desc["drives"]):
+        R = drives[k]
+        R.mode, R.op, R.env = int(dr["mode"]), OP[dr["op"]], ENV[dr["env"]]
+        par = np.ascontiguousarray(np.asarray(dr["params"], dtype=np.float64))
+        keep.append(par)
+        R.n_par = len(par)
+        R.par = par.ctypes.data_as(C.POINTER(C.c_double))
+        R.has_omega = 0 if dr.get("omega_d") is None else 1
+        R.omega_d = 0.0 if dr.get("omega_d") is None else float(dr["omega_d"])
+        R.phase = float(dr.get("phase", 0.0))
+        R.sigma = float(dr.get("sigma", 1.0))
+    sd = SystemDesc()
+    sd.n_modes, sd.n_couplings, sd.n_drives = len(desc["modes"]), len(desc["couplings"]), \
+        len(desc["drives"])
+    sd.n_steps, sd.T = int(desc["n_steps"]), float(desc["T"])
+    sd.modes, sd.couplings, sd.drives = modes, coups, drives
+    keep += [modes, coups, drives]
+    return sd, keep
+
+
 class System:
     """A built system (device tables live until ``close``)."""
 
     def __init__(self, desc, stream=None):
         self.desc = desc
-        self._keep = []
-        modes = (ModeDesc * len(desc["modes"]))()
-        for m, md in enumerate(desc["modes"]):
-            M = modes[m]
-            M.kind = MODE_KIND[md["kind"]]
-            M.basis_dim = int(md.get("basis_dim", md["trunc"]))
-            M.trunc = int(md["trunc"])
-            M.EC, M.EJ, M.EL = float(md.get("EC", 0)), float(md.get("EJ", 0)), float(md.get("EL", 0))
-            M.ng, M.phiext = float(md.get("ng", 0.0)), float(md.get("phiext", 0.0))
-            if md.get("frame_eps") is not None:
-                M.has_frame = 1
-                for a, v in enumerate(np.asarray(md["frame_eps"], dtype=np.float64)[: M.trunc]):
-                    M.frame_eps[a] = float(v)
-            if md["kind"] == "raw":
-                d = M.trunc
-                eps = np.ascontiguousarray(np.asarray(md["eps"], dtype=np.float64)[:d])
-                ops = np.zeros((2, d, d, 2))
-                for o, name in enumerate(("n", "phi")):
-                    a = np.asarray(md["ops"][name], dtype=np.complex128)
-                    ops[o, :, :, 0] = a.real
-                    ops[o, :, :, 1] = a.imag
-                ops = np.ascontiguousarray(ops)
-                self._keep += [eps, ops]
-                M.raw_eps = eps.ctypes.data_as(C.POINTER(C.c_double))
-                M.raw_ops = ops.ctypes.data_as(C.POINTER(C.c_double))
-        coups = (CouplingDesc * max(1, len(desc["couplings"])))()
-        for e, c in enumerate(desc["couplings"]):
-            coups[e].i, coups[e].j = int(c["i"]), int(c["j"])
-            coups[e].op_i, coups[e].op_j = OP[c["op_i"]], OP[c["op_j"]]
-            coups[e].g = float(c["g"])
-        drives = (DriveDesc * max(1, len(desc["drives"])))()
-        for k, dr in enumerate(desc["drives"]):
-            R = drives[k]
-            R.mode, R.op, R.env = int(dr["mode"]), OP[dr["op"]], ENV[dr["env"]]
-            par = np.ascontiguousarray(np.asarray(dr["params"], dtype=np.float64))
-            self._keep.append(par)
-            R.n_par = len(par)
-            R.par = par.ctypes.data_as(C.POINTER(C.c_double))
-            R.has_omega = 0 if dr.get("omega_d") is None else 1
-            R.omega_d = 0.0 if dr.get("omega_d") is None else float(dr["omega_d"])
-            R.phase = float(dr.get("phase", 0.0))
-            R.sigma = float(dr.get("sigma", 1.0))
-        sd = SystemDesc()
-        sd.n_modes, sd.n_couplings, sd.n_drives = len(desc["modes"]), len(desc["couplings"]), \
-            len(desc["drives"])
-        sd.n_steps, sd.T = int(desc["n_steps"]), float(desc["T"])
-        sd.modes, sd.couplings, sd.drives = modes, coups, drives
+        sd, self._keep = marshal(desc)
         h = C.c_void_p()
         check(lib().scp_build_system(C.byref(sd), _stream_ptr(stream), C.byref(h)))
         self.handle = h

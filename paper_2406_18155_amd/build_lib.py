@@ -5,6 +5,7 @@ import glob
 import os
 import subprocess
 import sys
+import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -25,18 +26,22 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     procs = []
     for src in srcs:
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+        log = obj + ".log"
         objs.append(obj)
         cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj]
         if src.endswith(".cpp"):
             cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", obj]
-        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        while sum(p.poll() is None for _, p in procs) >= jobs:
-            procs[[p.poll() is None for _, p in procs].index(True)][1].wait()
+        # compiler output goes to a file (a pipe could fill up and block the child)
+        with open(log, "w") as fh:
+            procs.append((src, log, subprocess.Popen(cmd, stdout=fh, stderr=subprocess.STDOUT)))
+        while sum(p.poll() is None for _, _, p in procs) >= jobs:
+            time.sleep(0.2)
     failed = False
-    for src, p in procs:
-        out, _ = p.communicate()
+    for src, log, p in procs:
+        p.wait()
+        out = open(log, errors="replace").read()
         if p.returncode != 0 or verbose:
-            sys.stderr.write(out.decode(errors="replace"))
+            sys.stderr.write(out)
         if p.returncode != 0:
             sys.stderr.write(f"compile failed: {src}\n")
             failed = True

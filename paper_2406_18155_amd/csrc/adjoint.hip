@@ -302,19 +302,25 @@ __device__ __forceinline__ void adj_stage(const Plan* __restrict__ P, c32* lds, 
 
 }  // namespace
 
+// Segments I.seg_hi down to I.seg_lo of column block I.cb.  first != 0: the
+// costate starts from the cotangent and the accumulators from zero; else both
+// continue from lamstate / part exactly (chunked runs are bitwise identical to
+// one launch).
 template <int d, int NR, int MP>
-__global__ void __launch_bounds__(WG_THREADS)
-adjoint_kernel(const Plan* __restrict__ P, const c32* __restrict__ optab,
-               const float* __restrict__ ctab, const float* __restrict__ dctab,
-               const c32x2* __restrict__ ckpt, const c32* __restrict__ lamT,
-               c32* __restrict__ segbuf, c32* __restrict__ lo_buf, c32* __restrict__ sum_buf,
-               double* __restrict__ part, int ce, int nckpt, int S) {
+__device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   constexpr int RB = Cfg<d, NR>::RB;
   extern __shared__ c32 lds[];
+  const Plan* __restrict__ P = I.P;
+  const c32* __restrict__ optab = (const c32*)I.optab;
+  const float* __restrict__ ctab = I.ctab;
+  const float* __restrict__ dctab = I.dctab;
+  const c32x2* __restrict__ ckpt = (const c32x2*)I.ckpt;
+  c32* __restrict__ segbuf = (c32*)I.segbuf;
+  const int ce = I.ce, S = I.S;
   const int TPC = P->TPC, CPW = P->CPW, D = P->D, L = P->L, N = P->nsteps;
   const int cw = threadIdx.x / TPC;
   const int tc = threadIdx.x - cw * TPC;
-  const int col = blockIdx.x * CPW + cw;
+  const int col = I.cb * CPW + cw;
   const bool lds_ok = cw < CPW;
   const bool active = lds_ok && col < S;
   const int cbase = cw * D;
@@ -329,11 +335,14 @@ adjoint_kernel(const Plan* __restrict__ P, const c32* __restrict__ optab,
   c32* slice = lds + 2 * (size_t)CPW * D + (lds_ok ? cw : 0) * D + tc;
   double* acc = reinterpret_cast<double*>(lds + 3 * (size_t)CPW * D);
   double* accw = acc + wave * nacc;
-  for (int i = threadIdx.x; i < nwaves * nacc; i += blockDim.x) acc[i] = 0.0;
+  double* partb = I.part + (size_t)I.cb * 4 * nacc;
+  for (int i = threadIdx.x; i < nwaves * nacc; i += blockDim.x)
+    acc[i] = (I.first || i >= 4 * nacc) ? 0.0 : partb[i];
 
   const size_t colreg = (size_t)(active ? col : 0) * D + tc;   // register-order slice
-  c32* lo = lo_buf + colreg;
-  c32* ysum = sum_buf + colreg;                // per-step sum of yb (device memory)
+  c32* lo = (c32*)I.lo + colreg;
+  c32* ysum = (c32*)I.sum + colreg;            // per-step sum of yb (device memory)
+  c32* lst = (c32*)I.lamstate + colreg;
   const size_t ystride = (size_t)S * D;        // between stages in the segment buffer
   // costate lambda lives in this thread's LDS slice (register order)
   if (lds_ok) {
@@ -343,13 +352,14 @@ adjoint_kernel(const Plan* __restrict__ P, const c32* __restrict__ optab,
       c32 v;
       v.x = 0.f;
       v.y = 0.f;
-      if (active) v = lamT[(size_t)col * D + tb + P->reg_off[base][r]];
+      if (active) v = I.first ? ((const c32*)I.lamT)[(size_t)col * D + tb + P->reg_off[base][r]]
+                              : lst[(size_t)r * TPC];
       slice[r * TPC] = v;
     }
   }
   __syncthreads();
 
-  for (int seg = nckpt - 1; seg >= 0; --seg) {
+  for (int seg = I.seg_hi; seg >= I.seg_lo; --seg) {
     const int start = seg * ce;
     const int stop = min(start + ce, N);
     // recompute the segment from its checkpoint; lambda moves out of LDS meanwhile
@@ -376,8 +386,8 @@ adjoint_kernel(const Plan* __restrict__ P, const c32* __restrict__ optab,
       }
       for (int n = start; n < stop; ++n)
         rk4_step<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, ctab, n, hi,
-                            lo, slice, segbuf + (size_t)((n - start) * 4) * ystride + colreg,
-                            ystride);
+                                lo, slice, segbuf + (size_t)((n - start) * 4) * ystride + colreg,
+                                ystride);
     }
     if (active) {
 #pragma unroll
@@ -414,7 +424,8 @@ adjoint_kernel(const Plan* __restrict__ P, const c32* __restrict__ optab,
         const c32* ops = optab + (size_t)stage_q(n, s) * bq;
         const float* cq = ctab + (size_t)stage_c(n, s) * ng;
         const float* dcq = dctab + (size_t)stage_c(n, s) * npl;
-        adj_stage<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, tc, lane, accw, ops, cq, dcq, kb, y, yb);
+        adj_stage<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, tc, lane, accw, ops, cq, dcq, kb,
+                                 y, yb);
         if (active) {
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
@@ -445,47 +456,86 @@ adjoint_kernel(const Plan* __restrict__ P, const c32* __restrict__ optab,
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nacc; i += blockDim.x) {
-    double s = 0.0;
-    for (int w = 0; w < nwaves; ++w) s += acc[w * nacc + i];
-    part[(size_t)blockIdx.x * nacc + i] = s;
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) lst[(size_t)r * TPC] = slice[r * TPC];
   }
+  for (int i = threadIdx.x; i < 4 * nacc; i += blockDim.x) partb[i] = i < nwaves * nacc ? acc[i] : 0.0;
+}
+
+template <int d, int NR, int MP>
+__global__ void __launch_bounds__(WG_THREADS) adjoint_kernel(AdjItem I) {
+  I.cb = blockIdx.x;
+  adjoint_block<d, NR, MP>(I);
+}
+
+template <int d, int NR, int MP>
+__global__ void __launch_bounds__(WG_THREADS) adjoint_batched_kernel(const AdjItem* __restrict__ items) {
+  adjoint_block<d, NR, MP>(items[blockIdx.x]);
 }
 
 namespace {
 
+size_t adj_lds_bytes(const Plan& P) {
+  return sizeof(c32) * 3 * (size_t)P.CPW * P.D + sizeof(double) * 4 * (size_t)P.nacc;
+}
+
 template <int d, int NR, int MP>
-hipError_t run_adj(const scp_system* sys, const c32x2* ckpt, const c32* lamT, c32* segbuf,
-                   c32* lo, c32* sum, double* part, int ce, int nckpt, int S, hipStream_t s) {
-  const Plan& P = sys->plan;
-  const int nwg = (S + P.CPW - 1) / P.CPW;
-  const size_t sh = sizeof(c32) * 3 * (size_t)P.CPW * P.D + sizeof(double) * (P.WG / 64) * P.nacc;
+hipError_t run_adj(const AdjItem& I0, int nwg, int wg, size_t sh, hipStream_t s) {
   if (sh > 160 * 1024) return hipErrorInvalidValue;
   hipFuncSetAttribute((const void*)adjoint_kernel<d, NR, MP>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL((adjoint_kernel<d, NR, MP>), dim3(nwg), dim3(P.WG), sh, s, sys->d_plan,
-                     (const c32*)sys->d_ops, sys->d_ctab, sys->d_dctab, ckpt, lamT, segbuf,
-                     lo, sum, part, ce, nckpt, S);
+  hipLaunchKernelGGL((adjoint_kernel<d, NR, MP>), dim3(nwg), dim3(wg), sh, s, I0);
+  return hipGetLastError();
+}
+
+template <int d, int NR, int MP>
+hipError_t run_adj_batched(const AdjItem* items, int nitems, int wg, size_t sh, hipStream_t s) {
+  if (sh > 160 * 1024) return hipErrorInvalidValue;
+  hipFuncSetAttribute((const void*)adjoint_batched_kernel<d, NR, MP>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  hipLaunchKernelGGL((adjoint_batched_kernel<d, NR, MP>), dim3(nitems), dim3(wg), sh, s, items);
   return hipGetLastError();
 }
 
 }  // namespace
 
+#define SCP_ADJ_ALL(X)                                                      \
+  X(2, 1, 1) X(2, 1, 2) X(2, 2, 1) X(2, 2, 2) X(2, 3, 1) X(2, 3, 2) X(2, 4, 1) X(2, 4, 2) \
+  X(3, 1, 1) X(3, 1, 2) X(3, 2, 1) X(3, 2, 2) X(3, 3, 1) X(3, 3, 2)                       \
+  X(4, 1, 1) X(4, 1, 2) X(4, 2, 1) X(4, 2, 2) X(5, 1, 1) X(5, 1, 2) X(5, 2, 1) X(5, 2, 2)
+
 scp_status launch_adjoint_impl(const scp_system* sys, const void* ckpt, const void* lamT,
-                               void* segbuf, void* lo, void* sum, double* part, int ce, int nckpt,
-                               int S, hipStream_t s) {
-  const int d = sys->plan.d, NR = sys->plan.NR, MP = sys->plan.MP;
+                               void* segbuf, void* lo, void* sum, void* lamstate, double* part,
+                               int ce, int nckpt, int S, hipStream_t s) {
+  const Plan& P = sys->plan;
+  const int d = P.d, NR = P.NR, MP = P.MP;
+  AdjItem I{sys->d_plan, sys->d_ops, sys->d_ctab, sys->d_dctab, (const float4*)ckpt,
+            (const float2*)lamT, (float2*)segbuf, (float2*)lo, (float2*)sum, (float2*)lamstate,
+            part, ce, nckpt, S, 0, nckpt - 1, 0, 1, 0};
+  const int nwg = (S + P.CPW - 1) / P.CPW;
+  const size_t sh = adj_lds_bytes(P);
   hipError_t e = hipErrorInvalidValue;
-#define SCP_ADJ(D_, NR_) \
-  if (d == D_ && NR == NR_ && MP == 1) e = run_adj<D_, NR_, 1>(sys, (const c32x2*)ckpt, (const c32*)lamT, (c32*)segbuf, (c32*)lo, (c32*)sum, part, ce, nckpt, S, s); \
-  if (d == D_ && NR == NR_ && MP == 2) e = run_adj<D_, NR_, 2>(sys, (const c32x2*)ckpt, (const c32*)lamT, (c32*)segbuf, (c32*)lo, (c32*)sum, part, ce, nckpt, S, s);
-  SCP_ADJ(2, 1) SCP_ADJ(2, 2) SCP_ADJ(2, 3) SCP_ADJ(2, 4)
-  SCP_ADJ(3, 1) SCP_ADJ(3, 2) SCP_ADJ(3, 3)
-  SCP_ADJ(4, 1) SCP_ADJ(4, 2)
-  SCP_ADJ(5, 1) SCP_ADJ(5, 2)
-#undef SCP_ADJ
+#define X(D_, NR_, MP_) \
+  if (d == D_ && NR == NR_ && MP == MP_) e = run_adj<D_, NR_, MP_>(I, nwg, P.WG, sh, s);
+  SCP_ADJ_ALL(X)
+#undef X
   if (e != hipSuccess) return fail(SCP_EHIP, std::string("adjoint launch: ") + hipGetErrorString(e));
   return SCP_OK;
 }
+
+scp_status launch_adjoint_batched(int d, int NR, int MP, const AdjItem* items, int nitems, int wg,
+                                  size_t sh, hipStream_t s) {
+  hipError_t e = hipErrorInvalidValue;
+#define X(D_, NR_, MP_) \
+  if (d == D_ && NR == NR_ && MP == MP_) e = run_adj_batched<D_, NR_, MP_>(items, nitems, wg, sh, s);
+  SCP_ADJ_ALL(X)
+#undef X
+  if (e != hipSuccess)
+    return fail(SCP_EHIP, std::string("batched adjoint launch: ") + hipGetErrorString(e));
+  return SCP_OK;
+}
+
+size_t adjoint_lds_bytes(const Plan& P) { return adj_lds_bytes(P); }
 
 }  // namespace scp

@@ -100,6 +100,37 @@ struct Plan {
   int32_t nacc;                    // gradient accumulators: npulse + 3 N + ncoup
 };
 
+// Work descriptor of one workgroup of a (possibly batched) forward launch:
+// CPW columns (column block cb) of one system for steps [n0, n1).
+struct FwdItem {
+  const Plan* P;
+  const float2* optab;
+  const float* ctab;
+  const float2* psi0;   // non-null: start from psi0 (natural order), lo = 0
+  float2* psiT;         // non-null: write hi + lo (natural order) at the end
+  float2* state_hi;     // register-order continuation state (nullable)
+  float2* lo;           // register-order compensation slices
+  float4* ckpt;         // nullable
+  int ce, S, cb, n0, n1, pad;
+};
+
+// Work descriptor of one workgroup of a (possibly batched) adjoint launch:
+// segments seg_hi down to seg_lo of column block cb.
+struct AdjItem {
+  const Plan* P;
+  const float2* optab;
+  const float* ctab;
+  const float* dctab;
+  const float4* ckpt;
+  const float2* lamT;   // cotangent (natural order), read when first != 0
+  float2* segbuf;
+  float2* lo;
+  float2* sum;
+  float2* lamstate;     // register-order costate carried between launches
+  double* part;         // [column block][4 waves][nacc] FP64 accumulators
+  int ce, nckpt, S, cb, seg_hi, seg_lo, first, pad;
+};
+
 struct ModeData {
   int kind = 0, K = 0, d = 0;
   double EC = 0, EJ = 0, EL = 0, ng = 0, phiext = 0;

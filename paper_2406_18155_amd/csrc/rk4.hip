@@ -19,17 +19,22 @@ namespace scp {
 // state_hi / lo (register order).  At the end: state_hi (if given) and psiT
 // (natural order, hi + lo, if given).  lo: S x D register-order slices.
 template <int d, int NR, int MP>
-__global__ void __launch_bounds__(WG_THREADS)
-rk4_kernel(const Plan* __restrict__ P, const c32* __restrict__ optab,
-           const float* __restrict__ ctab, const c32* __restrict__ psi0,
-           c32* __restrict__ psiT, c32* __restrict__ state_hi, c32* __restrict__ lo_buf,
-           c32x2* __restrict__ ckpt, int ckpt_every, int S, int n0, int n1) {
+__device__ __forceinline__ void rk4_block(const FwdItem& I) {
   constexpr int RB = Cfg<d, NR>::RB;
   extern __shared__ c32 lds[];
+  const Plan* __restrict__ P = I.P;
+  const c32* __restrict__ optab = (const c32*)I.optab;
+  const float* __restrict__ ctab = I.ctab;
+  const c32* __restrict__ psi0 = (const c32*)I.psi0;
+  c32* __restrict__ psiT = (c32*)I.psiT;
+  c32* __restrict__ state_hi = (c32*)I.state_hi;
+  c32* __restrict__ lo_buf = (c32*)I.lo;
+  c32x2* __restrict__ ckpt = (c32x2*)I.ckpt;
+  const int ckpt_every = I.ce, S = I.S, n0 = I.n0, n1 = I.n1;
   const int TPC = P->TPC, CPW = P->CPW, D = P->D, L = P->L;
   const int cw = threadIdx.x / TPC;
   const int tc = threadIdx.x - cw * TPC;
-  const int col = blockIdx.x * CPW + cw;
+  const int col = I.cb * CPW + cw;
   const bool lds_ok = cw < CPW;
   const bool active = lds_ok && col < S;
   const int cbase = cw * D;
@@ -113,6 +118,18 @@ rk4_kernel(const Plan* __restrict__ P, const c32* __restrict__ optab,
   }
 }
 
+template <int d, int NR, int MP>
+__global__ void __launch_bounds__(WG_THREADS) rk4_kernel(FwdItem I) {
+  I.cb = blockIdx.x;
+  rk4_block<d, NR, MP>(I);
+}
+
+// Batched launch: workgroup b runs items[b] (requests of one size class).
+template <int d, int NR, int MP>
+__global__ void __launch_bounds__(WG_THREADS) rk4_batched_kernel(const FwdItem* __restrict__ items) {
+  rk4_block<d, NR, MP>(items[blockIdx.x]);
+}
+
 // out = V(t) y at one stage time, through the same stage_apply as the stepper.
 template <int d, int NR, int MP>
 __global__ void __launch_bounds__(WG_THREADS)
@@ -169,9 +186,14 @@ struct Launch {
     const size_t sh = sizeof(c32) * 3 * (size_t)P.CPW * P.D;
     hipFuncSetAttribute((const void*)rk4_kernel<d, NR, MP>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((rk4_kernel<d, NR, MP>), dim3(nwg), dim3(P.WG), sh, s, sys->d_plan,
-                       (const c32*)sys->d_ops, sys->d_ctab, (const c32*)psi0, (c32*)psiT,
-                       (c32*)state, (c32*)lo, (c32x2*)ckpt, ce, S, n0, n1);
+    FwdItem I{sys->d_plan, sys->d_ops, sys->d_ctab, psi0, psiT, state, lo, ckpt, ce, S, 0, n0, n1, 0};
+    hipLaunchKernelGGL((rk4_kernel<d, NR, MP>), dim3(nwg), dim3(P.WG), sh, s, I);
+    return hipGetLastError();
+  }
+  static hipError_t batched(const FwdItem* items, int nitems, int wg, size_t sh, hipStream_t s) {
+    hipFuncSetAttribute((const void*)rk4_batched_kernel<d, NR, MP>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((rk4_batched_kernel<d, NR, MP>), dim3(nitems), dim3(wg), sh, s, items);
     return hipGetLastError();
   }
   static hipError_t apply(const scp_system* sys, const float2* ops, const float* cq,
@@ -229,4 +251,15 @@ scp_status launch_apply(const scp_system* sys, int step, int stage, const float2
   return SCP_OK;
 }
 
+}  // namespace scp
+
+namespace scp {
+scp_status launch_rk4_batched(int d, int NR, int MP, const FwdItem* items, int nitems, int wg,
+                              size_t sh, hipStream_t s) {
+  hipError_t e = dispatch(d, NR, MP, [&](auto L) {
+    return decltype(L)::batched(items, nitems, wg, sh, s);
+  });
+  if (e != hipSuccess) return fail(SCP_EHIP, std::string("batched rk4 launch: ") + hipGetErrorString(e));
+  return SCP_OK;
+}
 }  // namespace scp

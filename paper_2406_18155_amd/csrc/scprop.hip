@@ -37,8 +37,8 @@ void pack_drive_static(void* dst, int k, int env, int npar, int par0, int group,
 scp_status launch_rk4_range(const scp_system* sys, const float2* psi0, float2* psiT, float2* state,
                             float2* lo, float4* ckpt, int ce, int S, int n0, int n1, hipStream_t s);
 scp_status launch_adjoint_impl(const scp_system* sys, const void* ckpt, const void* lamT,
-                               void* segbuf, void* lo, void* sum, double* part, int ce, int nckpt,
-                               int S, hipStream_t s);
+                               void* segbuf, void* lo, void* sum, void* lamstate, double* part,
+                               int ce, int nckpt, int S, hipStream_t s);
 
 namespace {
 
@@ -614,7 +614,7 @@ scp_status build(const scp_system_desc* ds, hipStream_t st, scp_system* sys) {
 
 // Workspace layout (bytes)
 struct WsLayout {
-  size_t lo = 0, ckpt = 0, seg = 0, part = 0, lam = 0, total = 0;
+  size_t lo = 0, ckpt = 0, seg = 0, part = 0, lam = 0, lamstate = 0, total = 0;
   int nckpt = 0, ce = 0, nwg = 0;
 };
 
@@ -639,8 +639,10 @@ WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad
       off = align(off + (size_t)w.ce * 4 * S * D * sizeof(float2));
       w.lam = off;
       off = align(off + S * D * sizeof(float2));
+      w.lamstate = off;
+      off = align(off + S * D * sizeof(float2));
       w.part = off;
-      off = align(off + (size_t)w.nwg * std::max(1, sys->plan.nacc) * sizeof(double));
+      off = align(off + (size_t)w.nwg * 4 * std::max(1, sys->plan.nacc) * sizeof(double));
     }
   } else {
     off = align(4 * S * D * sizeof(double2));
@@ -773,17 +775,19 @@ scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, vo
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   scp_status s = launch_adjoint_impl(sys, ws + w.ckpt, cotangent, ws + w.seg, ws + w.lo, ws + w.lam,
-                                     (double*)(ws + w.part), w.ce, w.nckpt, opts->n_cols, st);
+                                     ws + w.lamstate, (double*)(ws + w.part), w.ce, w.nckpt,
+                                     opts->n_cols, st);
   if (s != SCP_OK) return s;
   const int nacc = sys->plan.nacc;
-  std::vector<double> part((size_t)w.nwg * nacc);
+  std::vector<double> part((size_t)w.nwg * 4 * nacc);
   HIPCHK(hipMemcpyAsync(part.data(), ws + w.part, part.size() * sizeof(double),
                         hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   bool finite = true;
   for (int i = 0; i < nacc; ++i) {
     double a = 0.0;
-    for (int b = 0; b < w.nwg; ++b) a += part[(size_t)b * nacc + i];
+    for (int b = 0; b < w.nwg; ++b)
+      for (int wv = 0; wv < 4; ++wv) a += part[((size_t)b * 4 + wv) * nacc + i];
     grad_out[i] = 2.0 * a;
     finite &= std::isfinite(grad_out[i]);
   }
