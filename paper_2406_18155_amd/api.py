@@ -145,6 +145,8 @@ class System:
         assert psi0.is_contiguous() and psi0.shape[1] == self.D
         if opts is None:
             opts = self.opts(psi0.shape[0], precision=prec)
+        if opts.precision != prec:
+            raise ValueError(f"opts.precision={opts.precision} but psi0 is {psi0.dtype}")
         if psiT is None:
             psiT = torch.empty_like(psi0)
         if workspace is None:

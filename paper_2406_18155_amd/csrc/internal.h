@@ -174,6 +174,7 @@ struct scp_system {
   float* d_ctab = nullptr;      // [3N][ngroups] drive coefficients (per group = per drive)
   float* d_dctab = nullptr;     // [3N][npulse] dc/dpar
   double* d_dctab64 = nullptr;
+  double* d_ctab64 = nullptr;   // [3N][n_drives] c(t) per drive, FP64 (plain path)
   void* d_scratch = nullptr;    // small per-system scratch (adjoint partial sums)
   size_t scratch_bytes = 0;
   int device = 0;
@@ -183,6 +184,13 @@ namespace scp {
 
 void set_error(const std::string& msg);
 scp_status fail(scp_status st, const std::string& msg);
+
+// Return SCP_EHIP with the failing call's text from a function returning scp_status.
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(SCP_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+  } while (0)
 
 // host single-mode builders (single_mode.cpp)
 void build_transmon(ModeData& m);

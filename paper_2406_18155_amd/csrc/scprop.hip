@@ -19,18 +19,13 @@ scp_status fail(scp_status st, const std::string& msg) {
   return st;
 }
 
-#define HIPCHK(expr)                                                                   \
-  do {                                                                                 \
-    hipError_t e_ = (expr);                                                            \
-    if (e_ != hipSuccess) return fail(SCP_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
-  } while (0)
 
 hipError_t launch_tables_impl(int d, int nslots, int npairs, int ndrives, int ngroups, int npulse,
                               int nsteps, double h, double T, const double* frames,
                               const double2* sops, const double2* pops, const double2* dops,
                               const int* smode, const int* pmode, float2* optab, int block_q,
                               const void* drives, const double* par, float* ctab, float* dctab,
-                              double* dctab64, hipStream_t s);
+                              double* dctab64, double* ctab64, hipStream_t s);
 size_t drive_static_size();
 void pack_drive_static(void* dst, int k, int env, int npar, int par0, int group, double omega,
                        double phase, double sigma);
@@ -486,11 +481,13 @@ scp_status build_tables(scp_system* sys, hipStream_t st) {
   HIPCHK(hipMalloc(&sys->d_ctab, np3 * std::max(1, P.ngroups) * sizeof(float)));
   HIPCHK(hipMalloc(&sys->d_dctab, np3 * std::max(1, P.npulse) * sizeof(float)));
   HIPCHK(hipMalloc(&sys->d_dctab64, np3 * std::max(1, P.npulse) * sizeof(double)));
+  HIPCHK(hipMalloc(&sys->d_ctab64, np3 * std::max<size_t>(1, sys->drives.size()) * sizeof(double)));
   HIPCHK(launch_tables_impl(d, ns, np1, (int)sys->drives.size(), P.ngroups, P.npulse,
                             sys->n_steps, sys->h, sys->T, (const double*)bf.p,
                             (const double2*)bs.p, (const double2*)bp.p, (const double2*)bd.p,
                             (const int*)bsm.p, (const int*)bpm.p, sys->d_ops, P.block_q, bdr.p,
-                            (const double*)bpar.p, sys->d_ctab, sys->d_dctab, sys->d_dctab64, st));
+                            (const double*)bpar.p, sys->d_ctab, sys->d_dctab, sys->d_dctab64,
+                            sys->d_ctab64, st));
   HIPCHK(hipStreamSynchronize(st));
   return SCP_OK;
 }
@@ -802,6 +799,7 @@ void scp_destroy(scp_system* sys) {
   if (sys->d_ctab) (void)hipFree(sys->d_ctab);
   if (sys->d_dctab) (void)hipFree(sys->d_dctab);
   if (sys->d_dctab64) (void)hipFree(sys->d_dctab64);
+  if (sys->d_ctab64) (void)hipFree(sys->d_ctab64);
   if (sys->d_scratch) (void)hipFree(sys->d_scratch);
   delete sys;
 }

@@ -10,7 +10,8 @@
 //
 // Drive coefficient tables at the three time points of every step
 // (t_n, t_n + h/2, t_n + h): c(t) = E(t) cos(omega_d t + phase) summed per
-// drive group, and dc/d(par) for every pulse parameter.
+// drive group, c(t) of every drive in FP64 (plain FP64 path), and dc/d(par)
+// for every pulse parameter.
 #include "internal.h"
 
 namespace scp {
@@ -67,7 +68,8 @@ struct DriveStatic {
 
 __global__ void ctable_kernel(TabStatic ts, const DriveStatic* __restrict__ dr,
                               const double* __restrict__ par, float* __restrict__ ctab,
-                              float* __restrict__ dctab, double* __restrict__ dctab64) {
+                              float* __restrict__ dctab, double* __restrict__ dctab64,
+                              double* __restrict__ ctab64) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= 3 * ts.nsteps) return;
   const int n = p / 3, j = p - 3 * n;
@@ -101,6 +103,7 @@ __global__ void ctable_kernel(TabStatic ts, const DriveStatic* __restrict__ dr,
       dctab64[(size_t)p * ts.npulse + D.par0 + i] = basis * carrier;
     }
     csum[D.group] += val * carrier;
+    ctab64[(size_t)p * ts.ndrives + k] = val * carrier;
   }
   for (int g = 0; g < ts.ngroups && g < 64; ++g) ctab[(size_t)p * ts.ngroups + g] = (float)csum[g];
 }
@@ -112,7 +115,7 @@ hipError_t launch_tables_impl(int d, int nslots, int npairs, int ndrives, int ng
                               const double2* sops, const double2* pops, const double2* dops,
                               const int* smode, const int* pmode, float2* optab, int block_q,
                               const void* drives, const double* par, float* ctab, float* dctab,
-                              double* dctab64, hipStream_t s) {
+                              double* dctab64, double* ctab64, hipStream_t s) {
   TabStatic ts{d, nslots, npairs, d * d, ndrives, ngroups, npulse, nsteps, h, T};
   hipLaunchKernelGGL(optable_kernel, dim3(2 * nsteps + 1), dim3(256), 0, s, ts, frames, sops, pops,
                      dops, smode, pmode, optab, block_q);
@@ -121,7 +124,7 @@ hipError_t launch_tables_impl(int d, int nslots, int npairs, int ndrives, int ng
   if (ndrives > 0) {
     const int n = 3 * nsteps;
     hipLaunchKernelGGL(ctable_kernel, dim3((n + 127) / 128), dim3(128), 0, s, ts,
-                       static_cast<const DriveStatic*>(drives), par, ctab, dctab, dctab64);
+                       static_cast<const DriveStatic*>(drives), par, ctab, dctab, dctab64, ctab64);
     e = hipGetLastError();
   }
   return e;
