@@ -375,3 +375,51 @@ def test_gradient_matches_torch_autograd_through_rk4():
         i = names.index(f"drive{k}.p0")
         assert float(amp[k].grad) == pytest.approx(g[i], rel=1e-9, abs=1e-13)
     assert float(gc.grad) == pytest.approx(g[names.index("coupling0.g")], rel=1e-9, abs=1e-13)
+
+
+# ----------------------------------------------------------------------------
+# Drive envelopes and carrier: closed-form values at known times
+# ----------------------------------------------------------------------------
+def test_envelopes_and_carrier_at_known_times():
+    T, N = 8.0, 80
+    desc = si.random_raw_system(2, [2, 2], 1, T, N, env="gauss")
+    o = OracleSystem(desc)
+    A, sig = 0.3, 1.7
+    g = {"env": "gauss", "params": [A], "sigma": sig}
+    assert o.envelope(g, 0, T / 2)[0] == pytest.approx(A, rel=1e-15)
+    assert o.envelope(g, 0, T / 2 + sig)[0] == pytest.approx(A * math.exp(-0.5), rel=1e-14)
+    half = T / 2 - sig * math.sqrt(2 * math.log(2))          # half maximum
+    assert o.envelope(g, 0, half)[0] == pytest.approx(A / 2, rel=1e-13)
+    # Gaussian basis: amplitude j alone peaks at t_j = (j + 1/2) T / n with value a_j
+    nb = 5
+    for j in range(nb):
+        p = [0.0] * nb
+        p[j] = 0.7
+        gb = {"env": "gauss_basis", "params": p, "sigma": T / nb}
+        v, dv = o.envelope(gb, 0, (j + 0.5) * T / nb)
+        assert v == pytest.approx(0.7, rel=1e-15)
+        assert dv[j] == pytest.approx(1.0, rel=1e-15)
+        # neighbour one centre away contributes exp(-1/2)
+        if j + 1 < nb:
+            assert dv[j + 1] == pytest.approx(math.exp(-0.5), rel=1e-14)
+    cr = {"env": "cos_ramp", "params": [A]}
+    assert o.envelope(cr, 0, 0.0)[0] == pytest.approx(0.0, abs=1e-16)
+    assert o.envelope(cr, 0, T / 2)[0] == pytest.approx(A, rel=1e-15)
+    assert o.envelope(cr, 0, T / 4)[0] == pytest.approx(A / 2, rel=1e-14)
+    assert o.envelope({"env": "const", "params": [A]}, 17, 3.3)[0] == A
+    # piecewise constant: 4 pieces over 80 steps, piece k covers steps 20k..20k+19
+    pw = {"env": "pwc", "params": [1.0, 2.0, 3.0, 4.0]}
+    for n, want in ((0, 1.0), (19, 1.0), (20, 2.0), (59, 3.0), (79, 4.0)):
+        assert o.envelope(pw, n, 0.0)[0] == want
+    # carrier: c = E(t) cos(omega t + phase); at omega t + phase = pi it is -E
+    k = 0
+    dr = o.drives[k]
+    n, s = 10, 1
+    t = o.stage_time(n, s)
+    assert t == pytest.approx((n + 0.5) * T / N, rel=1e-15)
+    c, dc = o.drive_coeff(k, n, s)
+    e, de = o.envelope(dr, n, t)
+    assert c == pytest.approx(e * math.cos(dr["omega_d"] * t + dr["phase"]), rel=1e-15)
+    dr2 = dict(dr, phase=math.pi - dr["omega_d"] * t)
+    o.drives[k] = dr2
+    assert o.drive_coeff(k, n, s)[0] == pytest.approx(-e, rel=1e-12)
