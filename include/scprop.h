@@ -226,7 +226,9 @@ scp_status scp_server_submit(scp_server* sv, const scp_system_desc* desc, const 
 scp_status scp_request_bytes(const scp_system_desc* desc, int32_t n_cols, int32_t want_grad,
                              size_t* bytes);
 
-/* One tick (synchronises the server's stream once). */
+/* One tick.  Size classes run concurrently on the server's four worker
+ * streams (created with the server, default priority); the tick ends by
+ * synchronising them.  Admission builds run on the stream given at creation. */
 scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued);
 
 /* State (SCP_REQ_*), fidelity, gradient (n_params entries when done, order

@@ -16,7 +16,8 @@
 // The per-request state (psi hi/lo, costate, per-wave FP64 accumulators) is
 // carried between ticks exactly, so a request's result does not depend on
 // what else is in flight or on the chunk boundaries.  Every launch is bounded
-// (no device-side waiting); a tick synchronises its stream once.
+// (no device-side waiting).  Size classes go round-robin to four worker
+// streams so that their launches overlap; a tick ends by synchronising them.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -104,6 +105,7 @@ struct Request {
   double t_submit = 0, t_admit = 0, t_done = 0;
   std::string err;
   double cost_step = 1.0;   // relative device time of one forward step of one workgroup
+  hipStream_t tick_stream = nullptr;   // worker stream of this tick's launch
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -115,7 +117,9 @@ struct scp_server {
   size_t budget = 0, used = 0;
   int max_active = 64;
   double chunk_work = 2.0e7;   // per-tick work budget per workgroup (cost units)
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;        // admission (builds and uploads)
+  static constexpr int kWork = 4;      // one per hardware queue
+  hipStream_t work[kWork] = {};        // size classes run concurrently on these
   int64_t next_id = 1;
   std::deque<scp::Request*> queue;
   std::vector<scp::Request*> active;
@@ -255,6 +259,12 @@ scp_status scp_server_create(size_t hbm_budget_bytes, int32_t max_active, double
   sv->max_active = max_active;
   if (chunk_work > 0) sv->chunk_work = chunk_work;
   sv->stream = (hipStream_t)stream;
+  for (int i = 0; i < scp_server::kWork; ++i)
+    if (hipStreamCreateWithFlags(&sv->work[i], hipStreamNonBlocking) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipStreamDestroy(sv->work[j]);
+      delete sv;
+      return fail(SCP_EHIP, "worker stream creation");
+    }
   sv->t0 = now_s();
   *out = sv;
   return SCP_OK;
@@ -304,7 +314,6 @@ scp_status scp_server_submit(scp_server* sv, const scp_system_desc* desc, const 
 
 scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued) {
   if (!sv) return fail(SCP_EINVAL, "null server");
-  hipStream_t st = sv->stream;
   // 1. admission by footprint, in arrival order
   while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active) {
     Request* r = sv->queue.front();
@@ -348,7 +357,9 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
     scp_status s = ensure_items(sv, need);
     if (s != SCP_OK) return s;
     size_t off = 0;
+    int ci = 0;
     for (auto& kv : classes) {
+      hipStream_t st = sv->work[ci++ % scp_server::kWork];
       const int kind = std::get<0>(kv.first), d = std::get<1>(kv.first), NR = std::get<2>(kv.first),
                 MP = std::get<3>(kv.first);
       int nit = 0, wg = 64;
@@ -392,16 +403,19 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
       for (auto& w : kv.second) {
         if (kind == 0) w.r->n_done = w.n1;
         else w.r->seg_next = w.s_lo - 1;
+        w.r->tick_stream = st;
       }
     }
     // 3. fidelity (and costate) for forward completions
     for (Request* r : sv->active)
       if (r->phase == 0 && r->n_done == r->sys->n_steps) {
         s = launch_fidelity(r->psi, r->sys->D, r->S, 0, r->d_c, r->d_rows, r->d_cols, r->d_target,
-                            r->d_tau, r->want_grad ? (void*)r->cot : nullptr, st);
+                            r->d_tau, r->want_grad ? (void*)r->cot : nullptr, r->tick_stream);
         if (s != SCP_OK) return s;
       }
-    if (hipStreamSynchronize(st) != hipSuccess) return fail(SCP_EHIP, "tick synchronisation");
+    for (int i = 0; i < scp_server::kWork; ++i)
+      if (hipStreamSynchronize(sv->work[i]) != hipSuccess)
+        return fail(SCP_EHIP, "tick synchronisation");
     const double t = now_s() - sv->t0;
     std::vector<Request*> keep;
     for (Request* r : sv->active) {
@@ -468,6 +482,8 @@ void scp_server_destroy(scp_server* sv) {
   for (Request* r : sv->active) release(sv, r);
   if (sv->d_items) (void)hipFree(sv->d_items);
   if (sv->h_items) (void)hipHostFree(sv->h_items);
+  for (int i = 0; i < scp_server::kWork; ++i)
+    if (sv->work[i]) (void)hipStreamDestroy(sv->work[i]);
   delete sv;
 }
 
