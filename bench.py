@@ -12,11 +12,20 @@ columns).  Parity on the same run: the 8 seeded sampled columns against the
 stored CPU FP64 oracle result (fidelity restricted to those columns and its
 gradient).
 
+Beside the timed steps (not part of ``value``): one forward of the same
+workload on the plain complex FP64 GPU path (the speedup denominator), and a
+serving replay of the first requests of the mixed request stream (2-6 modes,
+d in {3,4,5}, T in [20,200] ns, half with gradients): saturated throughput,
+then Poisson arrivals at 0.5x and 0.9x that throughput, with p50/p99 latency.
+
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--serve-requests R] [--no-plain64]
 """
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
@@ -54,6 +63,74 @@ def flops(desc, S):
     return fwd, adj
 
 
+def kernel_sources_sha():
+    """SHA-256 over the HIP/C++ sources of the library (sorted by name)."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2406_18155_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_tag):
+    """HBM bytes per launch from the counter summary in profiles/ (FETCH_SIZE +
+    WRITE_SIZE, copy-calibrated), or None when the kernel sources changed
+    since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("sources_sha256") != kernel_sources_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def plain64_forward_ms(scp, si, torch, desc, S):
+    """One forward of the workload on the plain complex FP64 path (ms)."""
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, desc["columns"], dtype=torch.complex128)
+    o = g.opts(S, precision=1)
+    ws = g.workspace(o)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.propagate(psi0, opts=o, workspace=ws)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    g.close()
+    return e0.elapsed_time(e1)
+
+
+def serving_leg(scp, si, torch, np, n_req):
+    """Continuous-batching replay of the first n_req requests of the mixed
+    request stream: saturated, then Poisson at 0.5x and 0.9x saturation."""
+    from paper_2406_18155_amd import serve
+    reqs = [si.serving_request(r) for r in range(n_req)]
+    budget = int(0.5 * torch.cuda.mem_get_info()[0])
+    keys = ("p50_s", "p99_s", "mean_s", "makespan_s", "requests_per_s", "steps_dim2_per_s",
+            "failed")
+    sat = serve.run_stream(reqs, [0.0] * n_req, budget, max_active=64)
+    out = {"requests": n_req, "hbm_budget_bytes": budget, "max_active": 64,
+           "saturated": {k: sat[k] for k in keys}}
+    for frac in (0.5, 0.9):
+        arr = si.poisson_arrivals(n_req, frac * sat["requests_per_s"])
+        r = serve.run_stream(reqs, arr, budget, max_active=64)
+        out[f"poisson_{frac}x"] = {k: r[k] for k in keys}
+    grads = sum(1 for q in reqs if q["want_grad"])
+    out["mix"] = (f"first {n_req} requests of the mixed stream: 2-6 modes, d in {{3,4,5}}, "
+                  f"D <= 3125, S = 2^modes, T in [20,200] ns at 50 steps/ns, "
+                  f"{grads} with gradient")
+    return out
+
+
 def sampled_desc(si, np):
     desc = si.config5()
     samp = si.sampled_columns(len(desc["columns"]), 8)
@@ -65,7 +142,7 @@ def sampled_desc(si, np):
     return desc
 
 
-def cpu_baseline(si, np, steps=300):
+def cpu_baseline(si, np, steps=600):
     """Oracle (as written) on a bounded sample: one column of the workload,
     ``steps`` RK4 steps forward + adjoint gradient."""
     import copy
@@ -109,6 +186,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-plain64", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (columns shard with no communication; "
@@ -213,9 +292,10 @@ def main():
                    "global_batch": S, "seq_len": N},
         "roofline": {"bound": "alu", "achieved": adj_flop / (adj_ms * 1e-3) / 1e12,
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": adj_flop / (adj_ms * 1e-3) / PEAK_FP32, "traffic": None,
-                     "kernel": "adjoint_kernel<3,3>"},
-        "forward": {"kernel": "rk4_kernel<3,3>", "ms": fwd_ms,
+                     "frac": adj_flop / (adj_ms * 1e-3) / PEAK_FP32,
+                     "traffic": measured_traffic("adjoint_ring8_d3"),
+                     "kernel": "adjoint_kernel<3,3,1>"},
+        "forward": {"kernel": "rk4_kernel<3,3,1>", "ms": fwd_ms,
                     "tflops": fwd_flop / (fwd_ms * 1e-3) / 1e12,
                     "frac": fwd_flop / (fwd_ms * 1e-3) / PEAK_FP32,
                     "steps_dim2_per_s": N * D * S / (fwd_ms * 1e-3)},
@@ -224,6 +304,12 @@ def main():
         "O_m": m_grad / m_fwd,
     }
     out.update(parity)
+    if not args.no_plain64:
+        p64 = plain64_forward_ms(scp, si, torch, desc, S)
+        out["plain_fp64"] = {"forward_ms": p64, "speedup_fused_fp32_forward": p64 / fwd_ms,
+                             "path": "complex FP64, one launch per local term"}
+    if args.serve_requests > 0:
+        out["serving"] = serving_leg(scp, si, torch, np, args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(si, np)
     print(json.dumps(out))
