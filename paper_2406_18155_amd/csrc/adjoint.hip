@@ -161,12 +161,11 @@ __device__ __forceinline__ void mode_reduce(const Vec<RB>& kb, const Vec<RB>& y,
 
 // Im( sum_ab X_ab M_ab ) for a uniform operator X from the table
 template <int d>
-__device__ __forceinline__ float im_dot(const c32* __restrict__ X, const Mat<d>& M) {
+__device__ __forceinline__ float im_dot(kptr<c32> X, const Mat<d>& M) {
   float s = 0.f;
 #pragma unroll
   for (int i = 0; i < d * d; ++i) {
-    const c32 x = X[i];
-    s = fmaf(x.x, M.im[i], fmaf(x.y, M.re[i], s));
+    s = fmaf(X[i].x, M.im[i], fmaf(X[i].y, M.re[i], s));
   }
   return s;
 }
@@ -186,18 +185,19 @@ __device__ __forceinline__ void fold(double* accw, int target, float v, int lane
 // One adjoint stage: yb = i V(t) kb (base layout out), with the parameter
 // folds of this stage.  kb and y enter in the base layout.
 template <int d, int NR, int MP, int RB>
-__device__ __forceinline__ void adj_stage(const Plan* __restrict__ P, c32* lds, int cbase,
+__device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
                                           int vstride, bool lds_ok, int tc, int lane,
-                                          double* accw, const c32* __restrict__ ops,
-                                          const float* __restrict__ cq,
-                                          const float* __restrict__ dcq, Vec<RB>& kb, Vec<RB>& y,
+                                          double* accw, kptr<c32> ops,
+                                          kptr<float> cq,
+                                          kptr<float> dcq, Vec<RB>& kb, Vec<RB>& y,
                                           Vec<RB>& yb) {
   constexpr int dd = d * d;
   const int L = P->L;
   const int npulse = P->npulse, N = P->N;
 #pragma unroll
   for (int r = 0; r < RB; ++r) yb.re[r] = yb.im[r] = 0.f;
-  for (int l = 0; l < L; ++l) {
+  for (int lv = 0; lv < L; ++lv) {
+    const int l = __builtin_amdgcn_readfirstlane(lv);
     if (l == 0) {
       if (L > 1) switch2<d, NR, RB>(P, lds, cbase, vstride, lds_ok, tc, L - 1, 0, kb, y);
     } else {
@@ -209,38 +209,43 @@ __device__ __forceinline__ void adj_stage(const Plan* __restrict__ P, c32* lds, 
       constexpr int p = decltype(Pp)::value;
       static_for<MP>([&](auto Mm) {
         constexpr int m = decltype(Mm)::value;
-        const CPair& C = P->cpair[l][p][m];
+        const auto& C = P->cpair[l][p][m];
         Op<d> O, W;
-        load_op<d>(ops + C.slot * dd, O);
-        load_op<d>(ops + P->off_pair + C.pair * dd, W);
+        const int c_slot = uni(C.slot), c_pair = uni(C.pair);
+        load_op<d>(ops + c_slot * dd, O);
+        load_op<d>(ops + uni(P->off_pair + c_pair * dd), W);
         Mat<d> G, H;
         zero(G);
         zero(H);
-        group_pair_adj<d, NR, p, p + 1>(O, W, coef(cq, C.cidx), kb, y, yb, G, H);
-        if (C.mode_i >= 0) {
+        group_pair_adj<d, NR, p, p + 1>(O, W, coef(cq, uni(C.cidx)), kb, y, yb, G, H);
+        const int mi = uni(C.mode_i);
+        if (mi >= 0) {
           // couplings of this pair term, the partner's and the first factor's operators
-          const int pr = C.pair, mi = C.mode_i, mj = C.mode_j;
-          for (int q = 0; q < P->pair_ncoup[pr]; ++q) {
-            const int e = P->pair_coup[pr][q];
-            const int sj = P->pair_pslot[pr][q];
+          const int pr = c_pair, mj = uni(C.mode_j);
+          const int nq = uni(P->pair_ncoup[pr]);
+          const int offd = uni(P->off_dslot);
+          for (int q = 0; q < nq; ++q) {
+            const int e = uni(P->pair_coup[pr][q]);
+            const int sj = uni(P->pair_pslot[pr][q]);
             fold(accw, npulse + 3 * N + e, im_dot<d>(ops + sj * dd, G), lane);
+            const float ge = unif(P->coup_g[e]);
             for (int th = 0; th < 3; ++th)
               fold(accw, npulse + 3 * mj + th,
-                   P->coup_g[e] * im_dot<d>(ops + P->off_dslot + (sj * 3 + th) * dd, G), lane);
+                   ge * im_dot<d>(ops + offd + (sj * 3 + th) * dd, G), lane);
           }
           for (int th = 0; th < 3; ++th)
             fold(accw, npulse + 3 * mi + th,
-                 im_dot<d>(ops + P->off_dslot + (C.slot * 3 + th) * dd, H), lane);
+                 im_dot<d>(ops + offd + (c_slot * 3 + th) * dd, H), lane);
         }
       });
     });
-    if (P->has_single[l]) {
+    if (uni(P->has_single[l])) {
       static_for<NR>([&](auto Pp) {
         constexpr int p = decltype(Pp)::value;
-        const CSingle& C1 = P->csingle[l][p];
+        const auto& C1 = P->csingle[l][p];
         Op<d> O;
-        load_op<d>(ops + C1.slot * dd, O);
-        const float c = coef(cq, C1.cidx);
+        load_op<d>(ops + uni(C1.slot) * dd, O);
+        const float c = coef(cq, uni(C1.cidx));
 #pragma unroll
         for (int i = 0; i < dd; ++i) {
           O.re[i] *= c;
@@ -249,17 +254,17 @@ __device__ __forceinline__ void adj_stage(const Plan* __restrict__ P, c32* lds, 
         contract_acc<d, NR, p>(O, kb, yb);
       });
     }
-    if (P->has_diag[l]) {
+    if (uni(P->has_diag[l])) {
       static_for<NR>([&](auto Pp) {
         constexpr int p = decltype(Pp)::value;
-        diag_acc<d, NR, p>(P->delta[P->cdiag[l][p]], kb, yb);
+        diag_acc<d, NR, p>(P->delta[uni(P->cdiag[l][p])], kb, yb);
       });
     }
     // single-mode sensitivities (drives and the diagonal) of the modes owned here
-    if (P->has_mode_pass[l]) {
+    if (uni(P->has_mode_pass[l])) {
       static_for<NR>([&](auto Pp) {
         constexpr int p = decltype(Pp)::value;
-        const int m = P->mode_pass[l][p];
+        const int m = uni(P->mode_pass[l][p]);
         if (m >= 0) {
           Mat<d> K;
           zero(K);
@@ -268,21 +273,24 @@ __device__ __forceinline__ void adj_stage(const Plan* __restrict__ P, c32* lds, 
 #pragma unroll
           for (int th = 0; th < 3; ++th)
 #pragma unroll
-            for (int a = 0; a < d; ++a) dev[th] = fmaf(P->deps[m][th][a], K.im[a * d + a], dev[th]);
-          for (int k = 0; k < P->ndrives; ++k) {
-            const DriveDev& R = P->drives[k];
-            if (P->slot_mode[R.slot] != m) continue;
-            const float s_im = wave_sum(im_dot<d>(ops + R.slot * dd, K));
+            for (int a = 0; a < d; ++a) dev[th] = fmaf(unif(P->deps[m][th][a]), K.im[a * d + a], dev[th]);
+          const int ndr = uni(P->ndrives), offd = uni(P->off_dslot);
+          for (int k = 0; k < ndr; ++k) {
+            const auto& R = P->drives[k];
+            const int rslot = uni(R.slot);
+            if (uni(P->slot_mode[rslot]) != m) continue;
+            const float s_im = wave_sum(im_dot<d>(ops + rslot * dd, K));
+            const int par0 = uni(R.par0), npar = uni(R.npar);
             if (lane == 0)
-              for (int q = 0; q < R.npar; ++q)
-                accw[R.par0 + q] += (double)dcq[R.par0 + q] * (double)s_im;
+              for (int q = 0; q < npar; ++q)
+                accw[par0 + q] += (double)dcq[par0 + q] * (double)s_im;
             bool first = true;   // one c(t) per slot: count the slot once
-            for (int k2 = 0; k2 < k; ++k2) first &= P->drives[k2].slot != R.slot;
+            for (int k2 = 0; k2 < k; ++k2) first &= uni(P->drives[k2].slot) != rslot;
             if (first) {
-              const float c = cq[R.cidx];
+              const float c = cq[uni(R.cidx)];
 #pragma unroll
               for (int th = 0; th < 3; ++th)
-                dev[th] = fmaf(c, im_dot<d>(ops + P->off_dslot + (R.slot * 3 + th) * dd, K), dev[th]);
+                dev[th] = fmaf(c, im_dot<d>(ops + offd + (rslot * 3 + th) * dd, K), dev[th]);
             }
           }
 #pragma unroll
@@ -310,10 +318,10 @@ template <int d, int NR, int MP>
 __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   constexpr int RB = Cfg<d, NR>::RB;
   extern __shared__ c32 lds[];
-  const Plan* __restrict__ P = I.P;
-  const c32* __restrict__ optab = (const c32*)I.optab;
-  const float* __restrict__ ctab = I.ctab;
-  const float* __restrict__ dctab = I.dctab;
+  kptr<Plan> P = kconst(I.P);
+  kptr<c32> optab = kconst((const c32*)I.optab);
+  kptr<float> ctab = kconst(I.ctab);
+  kptr<float> dctab = kconst(I.dctab);
   const c32x2* __restrict__ ckpt = (const c32x2*)I.ckpt;
   c32* __restrict__ segbuf = (c32*)I.segbuf;
   const int ce = I.ce, S = I.S;
@@ -399,7 +407,8 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
 #pragma unroll
       for (int r = 0; r < RB; ++r) yb.re[r] = yb.im[r] = 0.f;
 #pragma unroll 1
-      for (int s = 3; s >= 0; --s) {
+      for (int sv = 3; sv >= 0; --sv) {
+        const int s = __builtin_amdgcn_readfirstlane(sv);
         const float bs = (s == 0 || s == 3) ? h * (1.0f / 6.0f) : h * (1.0f / 3.0f);
         const float as = (s == 2) ? h : 0.5f * h;   // coefficient of yb_{s+1}; unused for s = 3
 #pragma unroll
@@ -421,9 +430,9 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
             y.im[r] = v.y;
           }
         }
-        const c32* ops = optab + (size_t)stage_q(n, s) * bq;
-        const float* cq = ctab + (size_t)stage_c(n, s) * ng;
-        const float* dcq = dctab + (size_t)stage_c(n, s) * npl;
+        auto ops = optab + (size_t)stage_q(n, s) * bq;
+        auto cq = ctab + (size_t)stage_c(n, s) * ng;
+        auto dcq = dctab + (size_t)stage_c(n, s) * npl;
         adj_stage<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, tc, lane, accw, ops, cq, dcq, kb,
                                  y, yb);
         if (active) {

@@ -18,6 +18,22 @@
 
 namespace scp {
 
+// Uniform read-only data (the plan, the stage tables, drive coefficients) is
+// read through the constant address space: the compiler may then keep it in
+// scalar registers and fetch it with scalar loads instead of per-lane loads.
+// Nothing writes these buffers while a kernel runs.
+template <typename T>
+using kptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ kptr<T> kconst(const T* p) {
+  return (kptr<T>)(uintptr_t)p;
+}
+// A value known to be the same in every lane, as a scalar.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float unif(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 template <int d, int NR>
 struct Cfg {
   static constexpr int RB = (NR == 1) ? d : (NR == 2) ? d * d : (NR == 3) ? d * d * d
@@ -38,10 +54,10 @@ struct Vec {
 };
 
 // Plain complex storage types for device memory (no vector-type punning).
-struct c32 {
+struct alignas(8) c32 {
   float x, y;
 };
-struct c32x2 {   // compensated pair (hi.re, hi.im, lo.re, lo.im)
+struct alignas(16) c32x2 {   // compensated pair (hi.re, hi.im, lo.re, lo.im)
   float x, y, z, w;
 };
 
@@ -66,7 +82,7 @@ struct RegOff {
 };
 
 template <int d, int NR>
-__device__ __forceinline__ RegOff<d, NR> reg_off_of(const Plan* __restrict__ P, int l) {
+__device__ __forceinline__ RegOff<d, NR> reg_off_of(kptr<Plan> P, int l) {
   RegOff<d, NR> R;
 #pragma unroll
   for (int p = 0; p < NR; ++p) R.s[p] = P->reg_stride[l][p];
@@ -106,12 +122,11 @@ struct Op {
 };
 
 template <int d>
-__device__ __forceinline__ void load_op(const c32* __restrict__ p, Op<d>& o) {
+__device__ __forceinline__ void load_op(kptr<c32> p, Op<d>& o) {
 #pragma unroll
   for (int i = 0; i < d * d; ++i) {
-    c32 t = p[i];
-    o.re[i] = t.x;
-    o.im[i] = t.y;
+    o.re[i] = p[i].x;
+    o.im[i] = p[i].y;
   }
 }
 
@@ -210,7 +225,7 @@ __device__ __forceinline__ void group_pair(const Op<d>& O, const Op<d>& W, float
 }
 
 template <int d, int NR, int P, int RB>
-__device__ __forceinline__ void diag_acc(const float* __restrict__ dl, const Vec<RB>& in,
+__device__ __forceinline__ void diag_acc(kptr<float> dl, const Vec<RB>& in,
                                          Vec<RB>& out) {
   using C = Cfg<d, NR>;
 #pragma unroll
@@ -223,7 +238,7 @@ __device__ __forceinline__ void diag_acc(const float* __restrict__ dl, const Vec
 
 // Drive coefficient of a term (cidx < 0: none).  The index is clamped so the
 // (uniform) load never leaves the table.
-__device__ __forceinline__ float coef(const float* __restrict__ cq, int cidx) {
+__device__ __forceinline__ float coef(kptr<float> cq, int cidx) {
   const float v = cq[cidx > 0 ? cidx : 0];
   return cidx >= 0 ? v : 0.f;
 }
@@ -232,29 +247,29 @@ __device__ __forceinline__ float coef(const float* __restrict__ cq, int cidx) {
 // pair terms at (p, p+1), MP of them per position pair; drive-only and
 // diagonal terms behind one per-layout flag each.
 template <int d, int NR, int MP, int RB>
-__device__ __forceinline__ void apply_layout(const Plan* __restrict__ P, int l,
-                                             const c32* __restrict__ ops,
-                                             const float* __restrict__ cq, const Vec<RB>& in,
+__device__ __forceinline__ void apply_layout(kptr<Plan> P, int l,
+                                             kptr<c32> ops,
+                                             kptr<float> cq, const Vec<RB>& in,
                                              Vec<RB>& out) {
   constexpr int dd = d * d;
   static_for<NR - 1>([&](auto Pp) {
     constexpr int p = decltype(Pp)::value;
     static_for<MP>([&](auto Mm) {
       constexpr int m = decltype(Mm)::value;
-      const CPair& C = P->cpair[l][p][m];
+      const auto& C = P->cpair[l][p][m];
       Op<d> O, W;
-      load_op<d>(ops + C.slot * dd, O);
-      load_op<d>(ops + P->off_pair + C.pair * dd, W);
-      group_pair<d, NR, p, p + 1>(O, W, coef(cq, C.cidx), in, out);
+      load_op<d>(ops + uni(C.slot) * dd, O);
+      load_op<d>(ops + uni(P->off_pair + C.pair * dd), W);
+      group_pair<d, NR, p, p + 1>(O, W, coef(cq, uni(C.cidx)), in, out);
     });
   });
-  if (P->has_single[l]) {
+  if (uni(P->has_single[l])) {
     static_for<NR>([&](auto Pp) {
       constexpr int p = decltype(Pp)::value;
-      const CSingle& C1 = P->csingle[l][p];
+      const auto& C1 = P->csingle[l][p];
       Op<d> O;
-      load_op<d>(ops + C1.slot * dd, O);
-      const float c = coef(cq, C1.cidx);
+      load_op<d>(ops + uni(C1.slot) * dd, O);
+      const float c = coef(cq, uni(C1.cidx));
 #pragma unroll
       for (int i = 0; i < dd; ++i) {
         O.re[i] *= c;
@@ -263,10 +278,10 @@ __device__ __forceinline__ void apply_layout(const Plan* __restrict__ P, int l,
       contract_acc<d, NR, p>(O, in, out);
     });
   }
-  if (P->has_diag[l]) {
+  if (uni(P->has_diag[l])) {
     static_for<NR>([&](auto Pp) {
       constexpr int p = decltype(Pp)::value;
-      diag_acc<d, NR, p>(P->delta[P->cdiag[l][p]], in, out);
+      diag_acc<d, NR, p>(P->delta[uni(P->cdiag[l][p])], in, out);
     });
   }
 }
@@ -275,21 +290,28 @@ __device__ __forceinline__ void apply_layout(const Plan* __restrict__ P, int l,
 
 namespace scp {
 
+// Natural-order offset of this thread's first element in layout l: the digits
+// of the thread index (digit 0 fastest) times the strides of the thread modes.
+// At most 8 thread modes (d^(thread modes) <= 256 threads per column).
 template <int d>
-__device__ __forceinline__ int thread_base(const Plan* __restrict__ P, int l, int tc) {
+__device__ __forceinline__ int thread_base(kptr<Plan> P, int l, int tc) {
+  const int NT = uni(P->NT);
   int b = 0, t = tc;
-  const int NT = P->NT;
-  for (int k = 0; k < NT; ++k) {
-    const int q = t / d;
-    b += (t - q * d) * P->tstride[l][k];
-    t = q;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int st = uni(P->tstride[l][k]);
+    if (k < NT) {
+      const int q = t / d;
+      b += (t - q * d) * st;
+      t = q;
+    }
   }
   return b;
 }
 
 // Layout switch of one or two vectors (WAR barrier, write, RAW barrier, read).
 template <int d, int NR, int RB>
-__device__ __forceinline__ void switch1(const Plan* __restrict__ P, c32* lds, int cbase,
+__device__ __forceinline__ void switch1(kptr<Plan> P, c32* lds, int cbase,
                                         bool lds_ok, int tc, int from, int to, Vec<RB>& v) {
   __syncthreads();
   if (lds_ok) lds_put<d, NR, RB>(lds, cbase + thread_base<d>(P, from, tc), reg_off_of<d, NR>(P, from), v);
@@ -298,7 +320,7 @@ __device__ __forceinline__ void switch1(const Plan* __restrict__ P, c32* lds, in
 }
 
 template <int d, int NR, int RB>
-__device__ __forceinline__ void switch2(const Plan* __restrict__ P, c32* lds, int cbase,
+__device__ __forceinline__ void switch2(kptr<Plan> P, c32* lds, int cbase,
                                         int vstride, bool lds_ok, int tc, int from, int to,
                                         Vec<RB>& v, Vec<RB>& w) {
   __syncthreads();
@@ -320,10 +342,10 @@ __device__ __forceinline__ void switch2(const Plan* __restrict__ P, c32* lds, in
 // k = V(t) y for one stage; y enters and k leaves in the base layout (L-1);
 // y is left in an unspecified layout.
 template <int d, int NR, int MP, int RB>
-__device__ __forceinline__ void stage_apply(const Plan* __restrict__ P, c32* lds, int cbase,
+__device__ __forceinline__ void stage_apply(kptr<Plan> P, c32* lds, int cbase,
                                             int vstride, bool lds_ok, int tc,
-                                            const c32* __restrict__ ops,
-                                            const float* __restrict__ cq, Vec<RB>& y, Vec<RB>& k) {
+                                            kptr<c32> ops,
+                                            kptr<float> cq, Vec<RB>& y, Vec<RB>& k) {
   const int L = P->L;
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
@@ -332,7 +354,8 @@ __device__ __forceinline__ void stage_apply(const Plan* __restrict__ P, c32* lds
   }
   if (L > 1) switch1<d, NR, RB>(P, lds, cbase, lds_ok, tc, L - 1, 0, y);
   apply_layout<d, NR, MP, RB>(P, 0, ops, cq, y, k);
-  for (int l = 1; l < L; ++l) {
+  for (int lv = 1; lv < L; ++lv) {
+    const int l = __builtin_amdgcn_readfirstlane(lv);
     switch2<d, NR, RB>(P, lds, cbase, vstride, lds_ok, tc, l - 1, l, y, k);
     apply_layout<d, NR, MP, RB>(P, l, ops, cq, y, k);
   }
@@ -360,10 +383,10 @@ __device__ __forceinline__ void comp_add(float& hi, float& lo, float dx) {
 // If ystore != nullptr the four stage inputs are written there (stride
 // ystride between stages) for the adjoint.
 template <int d, int NR, int MP, int RB>
-__device__ __forceinline__ void rk4_step(const Plan* __restrict__ P, c32* lds, int cbase,
+__device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase,
                                          int vstride, bool lds_ok, bool active, int tc, int TPC,
-                                         const c32* __restrict__ optab,
-                                         const float* __restrict__ ctab, int n, Vec<RB>& hi,
+                                         kptr<c32> optab,
+                                         kptr<float> ctab, int n, Vec<RB>& hi,
                                          c32* __restrict__ lo, c32* accs, c32* __restrict__ ystore,
                                          size_t ystride) {
   const float h = P->h;
@@ -376,7 +399,8 @@ __device__ __forceinline__ void rk4_step(const Plan* __restrict__ P, c32* lds, i
     y.im[r] = hi.im[r];
   }
 #pragma unroll 1
-  for (int s = 0; s < 4; ++s) {
+  for (int sv = 0; sv < 4; ++sv) {
+    const int s = __builtin_amdgcn_readfirstlane(sv);
     if (ystore != nullptr && active) {
       c32* dst = ystore + (size_t)s * ystride;
 #pragma unroll
@@ -387,8 +411,8 @@ __device__ __forceinline__ void rk4_step(const Plan* __restrict__ P, c32* lds, i
         dst[(size_t)r * TPC] = v;
       }
     }
-    const c32* ops = optab + (size_t)stage_q(n, s) * bq;
-    const float* cq = ctab + (size_t)stage_c(n, s) * ng;
+    auto ops = optab + (size_t)stage_q(n, s) * bq;
+    auto cq = ctab + (size_t)stage_c(n, s) * ng;
     stage_apply<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, tc, ops, cq, y, k);
     // k_s = -i V y;  acc (+)= w_s k_s;  y_{s+1} = hi + c_{s+1} h k_s
     const float w = (s == 0 || s == 3) ? 1.f : 2.f;

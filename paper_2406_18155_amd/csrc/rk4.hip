@@ -22,9 +22,9 @@ template <int d, int NR, int MP>
 __device__ __forceinline__ void rk4_block(const FwdItem& I) {
   constexpr int RB = Cfg<d, NR>::RB;
   extern __shared__ c32 lds[];
-  const Plan* __restrict__ P = I.P;
-  const c32* __restrict__ optab = (const c32*)I.optab;
-  const float* __restrict__ ctab = I.ctab;
+  kptr<Plan> P = kconst(I.P);
+  kptr<c32> optab = kconst((const c32*)I.optab);
+  kptr<float> ctab = kconst(I.ctab);
   const c32* __restrict__ psi0 = (const c32*)I.psi0;
   c32* __restrict__ psiT = (c32*)I.psiT;
   c32* __restrict__ state_hi = (c32*)I.state_hi;
@@ -133,9 +133,12 @@ __global__ void __launch_bounds__(WG_THREADS) rk4_batched_kernel(const FwdItem* 
 // out = V(t) y at one stage time, through the same stage_apply as the stepper.
 template <int d, int NR, int MP>
 __global__ void __launch_bounds__(WG_THREADS)
-apply_kernel(const Plan* __restrict__ P, const c32* __restrict__ ops,
-             const float* __restrict__ cq, const c32* __restrict__ yin, c32* __restrict__ out,
+apply_kernel(const Plan* __restrict__ Pg, const c32* __restrict__ opsg,
+             const float* __restrict__ cqg, const c32* __restrict__ yin, c32* __restrict__ out,
              int S) {
+  kptr<Plan> P = kconst(Pg);
+  kptr<c32> ops = kconst(opsg);
+  kptr<float> cq = kconst(cqg);
   constexpr int RB = Cfg<d, NR>::RB;
   extern __shared__ c32 lds[];
   const int TPC = P->TPC, CPW = P->CPW, D = P->D, L = P->L;
@@ -243,7 +246,7 @@ scp_status launch_apply(const scp_system* sys, int step, int stage, const float2
   const int q = 2 * step + (stage == 0 ? 0 : (stage == 3 ? 2 : 1));
   const int c = 3 * step + (stage == 0 ? 0 : (stage == 3 ? 2 : 1));
   const float2* ops = sys->d_ops + (size_t)q * sys->plan.block_q;
-  const float* cq = sys->d_ctab + (size_t)c * sys->plan.ngroups;
+  auto cq = sys->d_ctab + (size_t)c * sys->plan.ngroups;
   hipError_t e = dispatch(sys->plan.d, sys->plan.NR, sys->plan.MP, [&](auto L) {
     return decltype(L)::apply(sys, ops, cq, y, out, S, s);
   });
