@@ -287,19 +287,17 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
           for (int th = 0; th < 3; ++th)
 #pragma unroll
             for (int a = 0; a < d; ++a) dev[th] = fmaf(unif(P->deps[m][th][a]), K.im[a * d + a], dev[th]);
-          const int ndr = uni(P->ndrives), offd = uni(P->off_dslot);
-          for (int k = 0; k < ndr; ++k) {
-            const auto& R = P->drives[k];
+          const int offd = uni(P->off_dslot);
+          const int k0 = uni(P->mdrv_off[m]), k1 = uni(P->mdrv_off[m + 1]);
+          for (int kk = k0; kk < k1; ++kk) {
+            const auto& R = P->drives[uni(P->mdrv[kk])];
             const int rslot = uni(R.slot);
-            if (uni(P->slot_mode[rslot]) != m) continue;
             const float s_im = wave_sum(im_dot<d>(ops + rslot * dd, K));
             const int par0 = uni(R.par0), npar = uni(R.npar);
             if (lane == 0)
               for (int q = 0; q < npar; ++q)
                 accw[par0 + q] += (double)dcq[par0 + q] * (double)s_im;
-            bool first = true;   // one c(t) per slot: count the slot once
-            for (int k2 = 0; k2 < k; ++k2) first &= uni(P->drives[k2].slot) != rslot;
-            if (first) {
+            if (uni(P->mdrv_first[kk])) {   // one c(t) per slot: count the slot once
               const float c = cq[uni(R.cidx)];
 #pragma unroll
               for (int th = 0; th < 3; ++th)
@@ -352,7 +350,9 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   const int bq = P->block_q;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
-  // LDS: [2 CPW D] layout switches | [CPW D] per-thread slices | FP64 accumulators
+  // LDS: [2 CPW D] layout switches | [CPW D] per-thread slices of lambda | FP64
+  // accumulators.  The recompute uses all three CPW D regions (lambda is kept
+  // in device memory meanwhile).
   c32* slice = lds + 2 * (size_t)CPW * D + (lds_ok ? cw : 0) * D + tc;
   double* acc = reinterpret_cast<double*>(lds + 3 * (size_t)CPW * D);
   double* accw = acc + wave * nacc;
@@ -365,6 +365,9 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   c32* ysum = (c32*)I.sum + colreg;            // per-step sum of yb (device memory)
   c32* lst = (c32*)I.lamstate + colreg;
   const size_t ystride = (size_t)S * D;        // between stages in the segment buffer
+  c32* ycol0 = segbuf + (size_t)(active ? col : 0) * D;   // this column, natural order
+  const int tbB = thread_base<d>(P, base, tc);            // base-layout addressing
+  const RegOff<d, NR> RB_ = reg_off_of<d, NR>(P, base);
   // costate lambda lives in this thread's LDS slice (register order)
   if (lds_ok) {
     const int tb = thread_base<d>(P, base, tc);
@@ -373,7 +376,7 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
       c32 v;
       v.x = 0.f;
       v.y = 0.f;
-      if (active) v = I.first ? ((const c32*)I.lamT)[(size_t)col * D + tb + P->reg_off[base][r]]
+      if (active) v = I.first ? ((const c32*)I.lamT)[(size_t)col * D + tb + RB_(r)]
                               : lst[(size_t)r * TPC];
       slice[r * TPC] = v;
     }
@@ -388,6 +391,7 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
 #pragma unroll
       for (int r = 0; r < RB; ++r) ysum[(size_t)r * TPC] = slice[r * TPC];
     }
+    __syncthreads();
     {
       Vec<RB> hi;
 #pragma unroll
@@ -405,11 +409,13 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
           lo[(size_t)r * TPC] = l;
         }
       }
+      int iy = 0, ka = 1, kb = 2;
       for (int n = start; n < stop; ++n)
         rk4_step<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, ctab, n, hi,
-                                lo, slice, segbuf + (size_t)((n - start) * 4) * ystride + colreg,
+                                lo, iy, ka, kb, ycol0 + (size_t)((n - start) * 4) * ystride,
                                 ystride);
     }
+    __syncthreads();
     if (active) {
 #pragma unroll
       for (int r = 0; r < RB; ++r) slice[r * TPC] = ysum[(size_t)r * TPC];
@@ -435,10 +441,10 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
           y.re[r] = y.im[r] = 0.f;
         }
         if (active) {
-          const c32* src = segbuf + (size_t)((n - start) * 4 + s) * ystride + colreg;
+          const c32* src = ycol0 + (size_t)((n - start) * 4 + s) * ystride + tbB;
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
-            const c32 v = src[(size_t)r * TPC];
+            const c32 v = src[RB_(r)];
             y.re[r] = v.x;
             y.im[r] = v.y;
           }

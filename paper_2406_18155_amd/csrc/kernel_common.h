@@ -85,7 +85,7 @@ template <int d, int NR>
 __device__ __forceinline__ RegOff<d, NR> reg_off_of(kptr<Plan> P, int l) {
   RegOff<d, NR> R;
 #pragma unroll
-  for (int p = 0; p < NR; ++p) R.s[p] = P->reg_stride[l][p];
+  for (int p = 0; p < NR; ++p) R.s[p] = uni(P->reg_stride[l][p]);
   return R;
 }
 
@@ -339,24 +339,44 @@ __device__ __forceinline__ void switch2(kptr<Plan> P, c32* lds, int cbase,
   }
 }
 
-// k = V(t) y for one stage; y enters and k leaves in the base layout (L-1);
-// y is left in an unspecified layout.
+// k = V(t) y for one stage.  The stage input y is in natural order in LDS
+// region iy (regions are rstride elements apart; cbase selects the column)
+// and every layout reads its elements from there.  k accumulates layout by
+// layout in registers and moves to the next layout through region ka, then
+// kb, then ka, ... with one barrier per move: a region is written only after
+// a barrier that follows its last reads (the other k region was last read
+// before the previous barrier; y's region is never written during a stage).
+// k leaves in the base layout (L-1).  On return ka is the region that the
+// last move did not use, which may be written next without a barrier.
 template <int d, int NR, int MP, int RB>
-__device__ __forceinline__ void stage_apply(kptr<Plan> P, c32* lds, int cbase,
-                                            int vstride, bool lds_ok, int tc,
-                                            kptr<c32> ops,
-                                            kptr<float> cq, Vec<RB>& y, Vec<RB>& k) {
-  const int L = P->L;
+__device__ __forceinline__ void stage_apply(kptr<Plan> P, c32* lds, int cbase, int rstride,
+                                            bool lds_ok, int tc, kptr<c32> ops, kptr<float> cq,
+                                            int iy, int& ka, int& kb, Vec<RB>& k) {
+  const int L = uni(P->L);
+  const c32* ybuf = lds + iy * rstride + cbase;
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     k.re[r] = 0.f;
     k.im[r] = 0.f;
   }
-  if (L > 1) switch1<d, NR, RB>(P, lds, cbase, lds_ok, tc, L - 1, 0, y);
-  apply_layout<d, NR, MP, RB>(P, 0, ops, cq, y, k);
-  for (int lv = 1; lv < L; ++lv) {
-    const int l = __builtin_amdgcn_readfirstlane(lv);
-    switch2<d, NR, RB>(P, lds, cbase, vstride, lds_ok, tc, l - 1, l, y, k);
+  for (int lv = 0; lv < L; ++lv) {
+    const int l = uni(lv);
+    if (l > 0) {
+      c32* kbuf = lds + ka * rstride + cbase;
+      if (lds_ok) lds_put<d, NR, RB>(kbuf, thread_base<d>(P, l - 1, tc), reg_off_of<d, NR>(P, l - 1), k);
+      __syncthreads();
+      if (lds_ok) lds_get<d, NR, RB>(kbuf, thread_base<d>(P, l, tc), reg_off_of<d, NR>(P, l), k);
+      const int t = ka;
+      ka = kb;
+      kb = t;
+    }
+    Vec<RB> y;
+    if (lds_ok) {
+      lds_get<d, NR, RB>(ybuf, thread_base<d>(P, l, tc), reg_off_of<d, NR>(P, l), y);
+    } else {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) y.re[r] = y.im[r] = 0.f;
+    }
     apply_layout<d, NR, MP, RB>(P, l, ops, cq, y, k);
   }
 }
@@ -375,86 +395,99 @@ __device__ __forceinline__ void comp_add(float& hi, float& lo, float dx) {
   hi = s2;
 }
 
-// One classical RK4 step n on psi = hi + lo.  hi lives in registers; lo is
-// this thread's register-order slice in device memory (stride TPC), read and
-// written once per step; the RK accumulator is this thread's slice in LDS
-// (accs, stride TPC).  Stage inputs are formed from hi alone (the stage
-// increments are O(h |V|) of psi, so the dropped lo is below their rounding).
-// If ystore != nullptr the four stage inputs are written there (stride
-// ystride between stages) for the adjoint.
+// One classical RK4 step n on psi = hi + lo.  hi and the RK accumulator live
+// in registers (base layout); lo is this thread's register-order slice in
+// device memory (stride TPC), read and written once per step.  The stage
+// inputs y_s are written to LDS in natural order (region ka, which is free,
+// then one barrier) and read there by every layout of the stage; iy, ka, kb
+// are the LDS region indices carried from step to step (start with 0, 1, 2).
+// y_s are formed from hi alone (the stage increments are O(h |V|) of psi, so
+// the dropped lo is below their rounding).  If ystore != nullptr the four
+// stage inputs are also written there in natural order (ystore is the
+// column's base; stride ystride between stages) for the adjoint.
 template <int d, int NR, int MP, int RB>
-__device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase,
-                                         int vstride, bool lds_ok, bool active, int tc, int TPC,
-                                         kptr<c32> optab,
-                                         kptr<float> ctab, int n, Vec<RB>& hi,
-                                         c32* __restrict__ lo, c32* accs, c32* __restrict__ ystore,
-                                         size_t ystride) {
+__device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int rstride,
+                                         bool lds_ok, bool active, int tc, int TPC,
+                                         kptr<c32> optab, kptr<float> ctab, int n, Vec<RB>& hi,
+                                         c32* __restrict__ lo, int& iy, int& ka, int& kb,
+                                         c32* __restrict__ ystore, size_t ystride) {
   const float h = P->h;
-  const int ng = P->ngroups;
-  const int bq = P->block_q;
-  Vec<RB> y, k;
+  const int ng = uni(P->ngroups);
+  const int bq = uni(P->block_q);
+  const int L = uni(P->L);
+  const int tbB = thread_base<d>(P, L - 1, tc);
+  const RegOff<d, NR> RB_ = reg_off_of<d, NR>(P, L - 1);
+  // y_0 = hi
+  {
+    c32* yb = lds + ka * rstride + cbase + tbB;
+    c32* ys = ystore != nullptr ? ystore + tbB : nullptr;
 #pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    y.re[r] = hi.re[r];
-    y.im[r] = hi.im[r];
+    for (int r = 0; r < RB; ++r) {
+      c32 v;
+      v.x = hi.re[r];
+      v.y = hi.im[r];
+      if (lds_ok) yb[RB_(r)] = v;
+      if (ys != nullptr && active) ys[RB_(r)] = v;
+    }
+    __syncthreads();
+    const int t = iy;
+    iy = ka;
+    ka = t;
   }
+  Vec<RB> acc, k;
 #pragma unroll 1
   for (int sv = 0; sv < 4; ++sv) {
-    const int s = __builtin_amdgcn_readfirstlane(sv);
-    if (ystore != nullptr && active) {
-      c32* dst = ystore + (size_t)s * ystride;
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        c32 v;
-        v.x = y.re[r];
-        v.y = y.im[r];
-        dst[(size_t)r * TPC] = v;
-      }
-    }
+    const int s = uni(sv);
     auto ops = optab + (size_t)stage_q(n, s) * bq;
     auto cq = ctab + (size_t)stage_c(n, s) * ng;
-    stage_apply<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, tc, ops, cq, y, k);
+    stage_apply<d, NR, MP, RB>(P, lds, cbase, rstride, lds_ok, tc, ops, cq, iy, ka, kb, k);
     // k_s = -i V y;  acc (+)= w_s k_s;  y_{s+1} = hi + c_{s+1} h k_s
     const float w = (s == 0 || s == 3) ? 1.f : 2.f;
     const float ch = (s == 2) ? h : 0.5f * h;
-    if (lds_ok) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const float kr = k.im[r], ki = -k.re[r];
+      if (s == 0) {
+        acc.re[r] = kr;
+        acc.im[r] = ki;
+      } else {
+        acc.re[r] = fmaf(w, kr, acc.re[r]);
+        acc.im[r] = fmaf(w, ki, acc.im[r]);
+      }
+      k.re[r] = fmaf(ch, kr, hi.re[r]);   // k now holds y_{s+1}
+      k.im[r] = fmaf(ch, ki, hi.im[r]);
+    }
+    if (s < 3) {
+      c32* yb = lds + ka * rstride + cbase + tbB;
+      c32* ys = ystore != nullptr ? ystore + (size_t)(s + 1) * ystride + tbB : nullptr;
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
-        const float kr = k.im[r], ki = -k.re[r];
-        c32 a;
-        if (s == 0) {
-          a.x = kr;
-          a.y = ki;
-        } else {
-          a = accs[r * TPC];
-          a.x = fmaf(w, kr, a.x);
-          a.y = fmaf(w, ki, a.y);
-        }
-        accs[r * TPC] = a;
-        if (s < 3) {
-          y.re[r] = fmaf(ch, kr, hi.re[r]);
-          y.im[r] = fmaf(ch, ki, hi.im[r]);
-        }
+        c32 v;
+        v.x = k.re[r];
+        v.y = k.im[r];
+        if (lds_ok) yb[RB_(r)] = v;
+        if (ys != nullptr && active) ys[RB_(r)] = v;
       }
+      __syncthreads();
+      const int t = iy;
+      iy = ka;
+      ka = t;
     }
   }
   // psi <- psi + h/6 acc, compensated (all loads issued before the updates)
   const float h6 = h * (1.0f / 6.0f);
   if (active) {
-    Vec<RB> lv, av;
+    Vec<RB> lv;
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const c32 l = lo[(size_t)r * TPC];
-      const c32 a = accs[r * TPC];
       lv.re[r] = l.x;
       lv.im[r] = l.y;
-      av.re[r] = a.x;
-      av.im[r] = a.y;
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      comp_add(hi.re[r], lv.re[r], h6 * av.re[r]);
-      comp_add(hi.im[r], lv.im[r], h6 * av.im[r]);
+      comp_add(hi.re[r], lv.re[r], h6 * acc.re[r]);
+      comp_add(hi.im[r], lv.im[r], h6 * acc.im[r]);
       c32 l;
       l.x = lv.re[r];
       l.y = lv.im[r];

@@ -42,7 +42,6 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
   const int base = L - 1;
   const size_t colreg = (size_t)(active ? col : 0) * D + tc;   // register-order slice
   c32* lo = lo_buf + colreg;
-  c32* accs = lds + 2 * (size_t)CPW * D + (lds_ok ? cw : 0) * D + tc;   // RK accumulator slice
 
   Vec<RB> hi;
 #pragma unroll
@@ -77,6 +76,7 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
       lo[(size_t)r * TPC] = z;
     }
   }
+  int iy = 0, ka = 1, kb = 2;   // LDS regions: stage input, k moves
   for (int n = n0; n < n1; ++n) {
     if (ckpt != nullptr && n % ckpt_every == 0 && active) {
       c32x2* dst = ckpt + ((size_t)(n / ckpt_every) * S + col) * D + tc;
@@ -92,7 +92,7 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
       }
     }
     rk4_step<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, ctab, n, hi, lo,
-                        accs, nullptr, 0);
+                            iy, ka, kb, nullptr, 0);
   }
   if (!active) return;
   if (state_hi != nullptr) {
@@ -162,7 +162,13 @@ apply_kernel(const Plan* __restrict__ Pg, const c32* __restrict__ opsg,
 #pragma unroll
     for (int r = 0; r < RB; ++r) y.re[r] = y.im[r] = 0.f;
   }
-  stage_apply<d, NR, MP, RB>(P, lds, cw * D, CPW * D, lds_ok, tc, ops, cq, y, k);
+  if (lds_ok) {
+    const int tb = thread_base<d>(P, base, tc);
+    lds_put<d, NR, RB>(lds, cw * D + tb, reg_off_of<d, NR>(P, base), y);
+  }
+  __syncthreads();
+  int ka = 1, kb = 2;
+  stage_apply<d, NR, MP, RB>(P, lds, cw * D, CPW * D, lds_ok, tc, ops, cq, 0, ka, kb, k);
   if (!active) return;
   const int tb = thread_base<d>(P, base, tc);
   c32* dst = out + (size_t)col * D + tb;
@@ -203,7 +209,7 @@ struct Launch {
                           const float2* y, float2* out, int S, hipStream_t s) {
     const Plan& P = sys->plan;
     const int nwg = (S + P.CPW - 1) / P.CPW;
-    const size_t sh = sizeof(c32) * 2 * (size_t)P.CPW * P.D;
+    const size_t sh = sizeof(c32) * 3 * (size_t)P.CPW * P.D;
     hipFuncSetAttribute((const void*)apply_kernel<d, NR, MP>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     hipLaunchKernelGGL((apply_kernel<d, NR, MP>), dim3(nwg), dim3(P.WG), sh, s, sys->d_plan,

@@ -207,6 +207,21 @@ scp_status make_plan(scp_system* sys) {
     }
   }
   if ((int)layouts.size() > MAXL) return fail(SCP_EINVAL, "coupling graph needs too many layouts");
+  // The last layout is the base one (psi, checkpoints, the adjoint's natural-order
+  // stores).  Make it the layout whose register modes are the most significant,
+  // so that its thread modes are the fastest-varying ones and consecutive lanes
+  // touch consecutive elements; rotating keeps consecutive layouts adjacent.
+  {
+    auto weight = [&](const std::vector<int>& S) {
+      long w = 0;
+      for (int m : S) w += ipow(d, N - 1 - m);
+      return w;
+    };
+    int best = (int)layouts.size() - 1;
+    for (int l = 0; l < (int)layouts.size(); ++l)
+      if (weight(layouts[l]) > weight(layouts[best])) best = l;
+    std::rotate(layouts.begin(), layouts.begin() + best + 1, layouts.end());
+  }
   const int L = (int)layouts.size();
   P.L = L;
   std::vector<int> stride(N);
@@ -381,6 +396,22 @@ scp_status make_plan(scp_system* sys) {
   }
   P.npulse = par0;
   if (P.npulse > MAXPULSE) return fail(SCP_EINVAL, "too many pulse parameters");
+  // drives of each mode (adjoint mode pass), each slot's coefficient counted once
+  {
+    int q = 0;
+    for (int m = 0; m < N; ++m) {
+      P.mdrv_off[m] = q;
+      for (int k = 0; k < P.ndrives; ++k) {
+        if (sys->drives[k].mode != m) continue;
+        bool first = true;
+        for (int k2 = 0; k2 < k; ++k2) first &= P.drives[k2].slot != P.drives[k].slot;
+        P.mdrv[q] = (int16_t)k;
+        P.mdrv_first[q] = first ? 1 : 0;
+        ++q;
+      }
+    }
+    for (int m = N; m <= 16; ++m) P.mdrv_off[m] = q;
+  }
   P.nslots = (int)sys->slot_mode.size() + 1;   // + the zero slot
   for (int s = 0; s < P.nslots - 1; ++s) {
     P.slot_mode[s] = sys->slot_mode[s];
