@@ -18,9 +18,13 @@
 // into scalars, wave-reduced, and accumulated in FP64 per wave in LDS.
 // No atomics: the result is bitwise reproducible.
 //
-// One workgroup owns its columns for the whole adjoint: for each segment,
-// last to first, it recomputes the segment's steps from the checkpoint
-// (storing the four stage inputs of every step) and then walks them back.
+// Per segment, last to first, a recompute launch (the forward stepper started
+// from the segment's checkpoint) writes the four stage inputs of every step
+// to the segment buffer, then one launch of the kernel here walks the segment
+// back.  The costate, the FP64 accumulators and the running sums are carried
+// between launches in device memory, exactly.
+#include <algorithm>
+
 #include "kernel_common.h"
 
 namespace scp {
@@ -189,18 +193,38 @@ __device__ __forceinline__ float wave_sum(float v) {
   return ((r0 + r1) + r2) + r3;
 }
 
-// acc (this wave's LDS row) [target] += weight * sum over the wave of v
-__device__ __forceinline__ void fold(double* accw, int target, float v, int lane, double weight = 1.0) {
-  const float s = wave_sum(v);
-  if (lane == 0) accw[target] += weight * (double)s;
+// FP64 gradient accumulators of one wave.  Target t < 128 is held by lane
+// t & 63 of a[t >> 6] (every lane owns one target per register, so adding to
+// a target is a masked add, with no branch and no LDS round trip); targets
+// from 128 on live in this wave's LDS row.  Each target receives the same
+// sequence of FP64 additions in either place.
+struct LaneAcc {
+  double a0, a1;
+};
+
+__device__ __forceinline__ void acc_add(LaneAcc& A, double* accw, int target, double x,
+                                        int lane) {
+  if (target < 64) {
+    A.a0 += (lane == target) ? x : 0.0;
+  } else if (target < 128) {
+    A.a1 += (lane == target - 64) ? x : 0.0;
+  } else if (lane == 0) {
+    accw[target] += x;
+  }
 }
+
+// target += sum over the wave of v
+__device__ __forceinline__ void fold(LaneAcc& A, double* accw, int target, float v, int lane) {
+  acc_add(A, accw, target, (double)wave_sum(v), lane);
+}
+
 
 // One adjoint stage: yb = i V(t) kb (base layout out), with the parameter
 // folds of this stage.  kb and y enter in the base layout.
 template <int d, int NR, int MP, int RB>
 __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
                                           int vstride, bool lds_ok, int tc, int lane,
-                                          double* accw, kptr<c32> ops,
+                                          LaneAcc& A, double* accw, kptr<c32> ops,
                                           kptr<float> cq,
                                           kptr<float> dcq, Vec<RB>& kb, Vec<RB>& y,
                                           Vec<RB>& yb) {
@@ -240,14 +264,14 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
           for (int q = 0; q < nq; ++q) {
             const int e = uni(P->pair_coup[pr][q]);
             const int sj = uni(P->pair_pslot[pr][q]);
-            fold(accw, npulse + 3 * N + e, im_dot<d>(ops + sj * dd, G), lane);
+            fold(A, accw, npulse + 3 * N + e, im_dot<d>(ops + sj * dd, G), lane);
             const float ge = unif(P->coup_g[e]);
             for (int th = 0; th < 3; ++th)
-              fold(accw, npulse + 3 * mj + th,
+              fold(A, accw, npulse + 3 * mj + th,
                    ge * im_dot<d>(ops + offd + (sj * 3 + th) * dd, G), lane);
           }
           for (int th = 0; th < 3; ++th)
-            fold(accw, npulse + 3 * mi + th,
+            fold(A, accw, npulse + 3 * mi + th,
                  im_dot<d>(ops + offd + (c_slot * 3 + th) * dd, H), lane);
         }
       });
@@ -294,9 +318,8 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
             const int rslot = uni(R.slot);
             const float s_im = wave_sum(im_dot<d>(ops + rslot * dd, K));
             const int par0 = uni(R.par0), npar = uni(R.npar);
-            if (lane == 0)
-              for (int q = 0; q < npar; ++q)
-                accw[par0 + q] += (double)dcq[par0 + q] * (double)s_im;
+            for (int q = 0; q < npar; ++q)
+              acc_add(A, accw, par0 + q, (double)dcq[par0 + q] * (double)s_im, lane);
             if (uni(P->mdrv_first[kk])) {   // one c(t) per slot: count the slot once
               const float c = cq[uni(R.cidx)];
 #pragma unroll
@@ -305,7 +328,7 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
             }
           }
 #pragma unroll
-          for (int th = 0; th < 3; ++th) fold(accw, npulse + 3 * m + th, dev[th], lane);
+          for (int th = 0; th < 3; ++th) fold(A, accw, npulse + 3 * m + th, dev[th], lane);
         }
       });
     }
@@ -351,14 +374,17 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
   // LDS: [2 CPW D] layout switches | [CPW D] per-thread slices of lambda | FP64
-  // accumulators.  The recompute uses all three CPW D regions (lambda is kept
-  // in device memory meanwhile).
+  // accumulators of the waves (targets >= 128, and the hand-over to part).
   c32* slice = lds + 2 * (size_t)CPW * D + (lds_ok ? cw : 0) * D + tc;
   double* acc = reinterpret_cast<double*>(lds + 3 * (size_t)CPW * D);
   double* accw = acc + wave * nacc;
   double* partb = I.part + (size_t)I.cb * 4 * nacc;
   for (int i = threadIdx.x; i < nwaves * nacc; i += blockDim.x)
     acc[i] = (I.first || i >= 4 * nacc) ? 0.0 : partb[i];
+  __syncthreads();
+  LaneAcc A;
+  A.a0 = lane < nacc ? accw[lane] : 0.0;
+  A.a1 = lane + 64 < nacc ? accw[lane + 64] : 0.0;
 
   const size_t colreg = (size_t)(active ? col : 0) * D + tc;   // register-order slice
   c32* lo = (c32*)I.lo + colreg;
@@ -383,43 +409,10 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   }
   __syncthreads();
 
-  for (int seg = I.seg_hi; seg >= I.seg_lo; --seg) {
+  {
+    const int seg = I.seg_hi;
     const int start = seg * ce;
     const int stop = min(start + ce, N);
-    // recompute the segment from its checkpoint; lambda moves out of LDS meanwhile
-    if (active) {
-#pragma unroll
-      for (int r = 0; r < RB; ++r) ysum[(size_t)r * TPC] = slice[r * TPC];
-    }
-    __syncthreads();
-    {
-      Vec<RB> hi;
-#pragma unroll
-      for (int r = 0; r < RB; ++r) hi.re[r] = hi.im[r] = 0.f;
-      if (active) {
-        const c32x2* src = ckpt + ((size_t)seg * S + col) * D + tc;
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          const c32x2 v = src[(size_t)r * TPC];
-          hi.re[r] = v.x;
-          hi.im[r] = v.y;
-          c32 l;
-          l.x = v.z;
-          l.y = v.w;
-          lo[(size_t)r * TPC] = l;
-        }
-      }
-      int iy = 0, ka = 1, kb = 2;
-      for (int n = start; n < stop; ++n)
-        rk4_step<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, ctab, n, hi,
-                                lo, iy, ka, kb, ycol0 + (size_t)((n - start) * 4) * ystride,
-                                ystride);
-    }
-    __syncthreads();
-    if (active) {
-#pragma unroll
-      for (int r = 0; r < RB; ++r) slice[r * TPC] = ysum[(size_t)r * TPC];
-    }
     // walk the segment back
     for (int n = stop - 1; n >= start; --n) {
       Vec<RB> kb, y, yb;
@@ -452,8 +445,8 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
         auto ops = optab + (size_t)stage_q(n, s) * bq;
         auto cq = ctab + (size_t)stage_c(n, s) * ng;
         auto dcq = dctab + (size_t)stage_c(n, s) * npl;
-        adj_stage<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, tc, lane, accw, ops, cq, dcq, kb,
-                                 y, yb);
+        adj_stage<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, tc, lane, A, accw, ops, cq, dcq,
+                                 kb, y, yb);
         if (active) {
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
@@ -483,6 +476,9 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
       }
     }
   }
+  // hand the lane accumulators back to the LDS rows
+  if (lane < nacc) accw[lane] = A.a0;
+  if (lane + 64 < nacc) accw[lane + 64] = A.a1;
   __syncthreads();
   if (active) {
 #pragma unroll
@@ -533,22 +529,31 @@ hipError_t run_adj_batched(const AdjItem* items, int nitems, int wg, size_t sh, 
   X(3, 1, 1) X(3, 1, 2) X(3, 2, 1) X(3, 2, 2) X(3, 3, 1) X(3, 3, 2)                       \
   X(4, 1, 1) X(4, 1, 2) X(4, 2, 1) X(4, 2, 2) X(5, 1, 1) X(5, 1, 2) X(5, 2, 1) X(5, 2, 2)
 
+scp_status launch_rk4_recompute(const scp_system* sys, const float4* ckin, float2* lo,
+                                float2* ystore, int S, int n0, int n1, hipStream_t s);
+
 scp_status launch_adjoint_impl(const scp_system* sys, const void* ckpt, const void* lamT,
                                void* segbuf, void* lo, void* sum, void* lamstate, double* part,
                                int ce, int nckpt, int S, hipStream_t s) {
   const Plan& P = sys->plan;
-  const int d = P.d, NR = P.NR, MP = P.MP;
-  AdjItem I{sys->d_plan, sys->d_ops, sys->d_ctab, sys->d_dctab, (const float4*)ckpt,
-            (const float2*)lamT, (float2*)segbuf, (float2*)lo, (float2*)sum, (float2*)lamstate,
-            part, ce, nckpt, S, 0, nckpt - 1, 0, 1, 0};
+  const int d = P.d, NR = P.NR, MP = P.MP, N = P.nsteps;
   const int nwg = (S + P.CPW - 1) / P.CPW;
   const size_t sh = adj_lds_bytes(P);
-  hipError_t e = hipErrorInvalidValue;
+  for (int seg = nckpt - 1; seg >= 0; --seg) {
+    const int n0 = seg * ce, n1 = std::min(n0 + ce, N);
+    scp_status st = launch_rk4_recompute(sys, (const float4*)ckpt + (size_t)seg * S * P.D,
+                                         (float2*)lo, (float2*)segbuf, S, n0, n1, s);
+    if (st != SCP_OK) return st;
+    AdjItem I{sys->d_plan, sys->d_ops, sys->d_ctab, sys->d_dctab, (const float4*)ckpt,
+              (const float2*)lamT, (float2*)segbuf, (float2*)lo, (float2*)sum,
+              (float2*)lamstate, part, ce, nckpt, S, 0, seg, seg, seg == nckpt - 1 ? 1 : 0, 0};
+    hipError_t e = hipErrorInvalidValue;
 #define X(D_, NR_, MP_) \
   if (d == D_ && NR == NR_ && MP == MP_) e = run_adj<D_, NR_, MP_>(I, nwg, P.WG, sh, s);
-  SCP_ADJ_ALL(X)
+    SCP_ADJ_ALL(X)
 #undef X
-  if (e != hipSuccess) return fail(SCP_EHIP, std::string("adjoint launch: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail(SCP_EHIP, std::string("adjoint launch: ") + hipGetErrorString(e));
+  }
   return SCP_OK;
 }
 

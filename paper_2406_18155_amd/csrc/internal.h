@@ -114,11 +114,14 @@ struct FwdItem {
   float2* state_hi;     // register-order continuation state (nullable)
   float2* lo;           // register-order compensation slices
   float4* ckpt;         // nullable
+  const float4* ckin;   // recompute: start from this checkpoint slab (hi, lo; register order)
+  float2* ystore;       // recompute: stage inputs, natural order, 4 S D per step
   int ce, S, cb, n0, n1, pad;
 };
 
 // Work descriptor of one workgroup of a (possibly batched) adjoint launch:
-// segments seg_hi down to seg_lo of column block cb.
+// segment seg_hi (= seg_lo) of column block cb, whose stage inputs a recompute
+// launch has just written to segbuf.
 struct AdjItem {
   const Plan* P;
   const float2* optab;

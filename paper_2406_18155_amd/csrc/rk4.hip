@@ -18,7 +18,9 @@ namespace scp {
 // psi0 != nullptr: start from psi0 (natural order), lo = 0; else continue from
 // state_hi / lo (register order).  At the end: state_hi (if given) and psiT
 // (natural order, hi + lo, if given).  lo: S x D register-order slices.
-template <int d, int NR, int MP>
+// REC: the adjoint's recompute of one segment: start from the checkpoint slab
+// ckin and write the four stage inputs of every step to ystore.
+template <int d, int NR, int MP, bool REC>
 __device__ __forceinline__ void rk4_block(const FwdItem& I) {
   constexpr int RB = Cfg<d, NR>::RB;
   extern __shared__ c32 lds[];
@@ -46,7 +48,19 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
   Vec<RB> hi;
 #pragma unroll
   for (int r = 0; r < RB; ++r) hi.re[r] = hi.im[r] = 0.f;
-  if (active) {
+  if (REC && active) {
+    const c32x2* src = (const c32x2*)I.ckin + (size_t)col * D + tc;
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const c32x2 v = src[(size_t)r * TPC];
+      hi.re[r] = v.x;
+      hi.im[r] = v.y;
+      c32 l;
+      l.x = v.z;
+      l.y = v.w;
+      lo[(size_t)r * TPC] = l;
+    }
+  } else if (active) {
     if (psi0 != nullptr) {
       const int tb = thread_base<d>(P, base, tc);
       const c32* src = psi0 + (size_t)col * D + tb;
@@ -91,8 +105,15 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
         dst[(size_t)r * TPC] = v;
       }
     }
-    rk4_step<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, ctab, n, hi, lo,
-                            iy, ka, kb, nullptr, 0);
+    if (REC)
+      rk4_step<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, ctab, n, hi,
+                              lo, iy, ka, kb,
+                              (c32*)I.ystore + (size_t)(active ? col : 0) * D +
+                                  (size_t)(n - n0) * 4 * S * D,
+                              (size_t)S * D);
+    else
+      rk4_step<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, ctab, n, hi,
+                              lo, iy, ka, kb, nullptr, 0);
   }
   if (!active) return;
   if (state_hi != nullptr) {
@@ -118,16 +139,16 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
   }
 }
 
-template <int d, int NR, int MP>
+template <int d, int NR, int MP, bool REC>
 __global__ void __launch_bounds__(WG_THREADS) rk4_kernel(FwdItem I) {
   I.cb = blockIdx.x;
-  rk4_block<d, NR, MP>(I);
+  rk4_block<d, NR, MP, REC>(I);
 }
 
 // Batched launch: workgroup b runs items[b] (requests of one size class).
-template <int d, int NR, int MP>
+template <int d, int NR, int MP, bool REC>
 __global__ void __launch_bounds__(WG_THREADS) rk4_batched_kernel(const FwdItem* __restrict__ items) {
-  rk4_block<d, NR, MP>(items[blockIdx.x]);
+  rk4_block<d, NR, MP, REC>(items[blockIdx.x]);
 }
 
 // out = V(t) y at one stage time, through the same stage_apply as the stepper.
@@ -188,21 +209,41 @@ namespace {
 
 template <int d, int NR, int MP>
 struct Launch {
-  static hipError_t rk4(const scp_system* sys, const float2* psi0, float2* psiT, float2* state,
-                        float2* lo, float4* ckpt, int ce, int S, int n0, int n1, hipStream_t s) {
+  template <bool REC>
+  static hipError_t run(const scp_system* sys, const FwdItem& I, int S, hipStream_t s) {
     const Plan& P = sys->plan;
     const int nwg = (S + P.CPW - 1) / P.CPW;
     const size_t sh = sizeof(c32) * 3 * (size_t)P.CPW * P.D;
-    hipFuncSetAttribute((const void*)rk4_kernel<d, NR, MP>,
+    hipFuncSetAttribute((const void*)rk4_kernel<d, NR, MP, REC>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    FwdItem I{sys->d_plan, sys->d_ops, sys->d_ctab, psi0, psiT, state, lo, ckpt, ce, S, 0, n0, n1, 0};
-    hipLaunchKernelGGL((rk4_kernel<d, NR, MP>), dim3(nwg), dim3(P.WG), sh, s, I);
+    hipLaunchKernelGGL((rk4_kernel<d, NR, MP, REC>), dim3(nwg), dim3(P.WG), sh, s, I);
     return hipGetLastError();
   }
-  static hipError_t batched(const FwdItem* items, int nitems, int wg, size_t sh, hipStream_t s) {
-    hipFuncSetAttribute((const void*)rk4_batched_kernel<d, NR, MP>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((rk4_batched_kernel<d, NR, MP>), dim3(nitems), dim3(wg), sh, s, items);
+  static hipError_t rk4(const scp_system* sys, const float2* psi0, float2* psiT, float2* state,
+                        float2* lo, float4* ckpt, int ce, int S, int n0, int n1, hipStream_t s) {
+    FwdItem I{sys->d_plan, sys->d_ops, sys->d_ctab, psi0, psiT, state, lo, ckpt, nullptr, nullptr,
+              ce, S, 0, n0, n1, 0};
+    return run<false>(sys, I, S, s);
+  }
+  static hipError_t recompute(const scp_system* sys, const float4* ckin, float2* lo,
+                              float2* ystore, int S, int n0, int n1, hipStream_t s) {
+    FwdItem I{sys->d_plan, sys->d_ops, sys->d_ctab, nullptr, nullptr, nullptr, lo, nullptr, ckin,
+              ystore, 1, S, 0, n0, n1, 0};
+    return run<true>(sys, I, S, s);
+  }
+  static hipError_t batched(const FwdItem* items, int nitems, int wg, size_t sh, bool rec,
+                            hipStream_t s) {
+    if (rec) {
+      hipFuncSetAttribute((const void*)rk4_batched_kernel<d, NR, MP, true>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+      hipLaunchKernelGGL((rk4_batched_kernel<d, NR, MP, true>), dim3(nitems), dim3(wg), sh, s,
+                         items);
+    } else {
+      hipFuncSetAttribute((const void*)rk4_batched_kernel<d, NR, MP, false>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+      hipLaunchKernelGGL((rk4_batched_kernel<d, NR, MP, false>), dim3(nitems), dim3(wg), sh, s,
+                         items);
+    }
     return hipGetLastError();
   }
   static hipError_t apply(const scp_system* sys, const float2* ops, const float* cq,
@@ -247,6 +288,15 @@ scp_status launch_rk4(scp_system* sys, const float2* psi0, float2* psiT, float2*
   return launch_rk4_range(sys, psi0, psiT, nullptr, lo, ckpt, ckpt_every, S, 0, sys->n_steps, s);
 }
 
+scp_status launch_rk4_recompute(const scp_system* sys, const float4* ckin, float2* lo,
+                                float2* ystore, int S, int n0, int n1, hipStream_t s) {
+  hipError_t e = dispatch(sys->plan.d, sys->plan.NR, sys->plan.MP, [&](auto L) {
+    return decltype(L)::recompute(sys, ckin, lo, ystore, S, n0, n1, s);
+  });
+  if (e != hipSuccess) return fail(SCP_EHIP, std::string("recompute launch: ") + hipGetErrorString(e));
+  return SCP_OK;
+}
+
 scp_status launch_apply(const scp_system* sys, int step, int stage, const float2* y, float2* out,
                         int S, hipStream_t s) {
   const int q = 2 * step + (stage == 0 ? 0 : (stage == 3 ? 2 : 1));
@@ -264,9 +314,9 @@ scp_status launch_apply(const scp_system* sys, int step, int stage, const float2
 
 namespace scp {
 scp_status launch_rk4_batched(int d, int NR, int MP, const FwdItem* items, int nitems, int wg,
-                              size_t sh, hipStream_t s) {
+                              size_t sh, bool recompute, hipStream_t s) {
   hipError_t e = dispatch(d, NR, MP, [&](auto L) {
-    return decltype(L)::batched(items, nitems, wg, sh, s);
+    return decltype(L)::batched(items, nitems, wg, sh, recompute, s);
   });
   if (e != hipSuccess) return fail(SCP_EHIP, std::string("batched rk4 launch: ") + hipGetErrorString(e));
   return SCP_OK;

@@ -7,10 +7,11 @@
 //      (stage tables + states + checkpoints + adjoint buffers) fits the HBM
 //      budget and the active count is below max_active;
 //   2. advance every active request by one chunk: forward steps, or adjoint
-//      segments once the forward is done, with ONE batched launch per size
+//      segments once the forward is done, with batched launches per size
 //      class (d, NR, MP) in which every workgroup reads its own work
 //      descriptor (its request's tables and states, its column block, its
-//      step or segment range);
+//      step range or segment): one forward launch, or per adjoint segment a
+//      recompute launch and a reverse launch;
 //   3. reduce the fidelity of requests whose forward completed (and seed the
 //      costate of gradient requests), finish gradients, release memory.
 // The per-request state (psi hi/lo, costate, per-wave FP64 accumulators) is
@@ -31,7 +32,7 @@
 namespace scp {
 
 scp_status launch_rk4_batched(int d, int NR, int MP, const FwdItem* items, int nitems, int wg,
-                              size_t sh, hipStream_t s);
+                              size_t sh, bool recompute, hipStream_t s);
 scp_status launch_adjoint_batched(int d, int NR, int MP, const AdjItem* items, int nitems, int wg,
                                   size_t sh, hipStream_t s);
 size_t adjoint_lds_bytes(const Plan& P);
@@ -348,58 +349,96 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
         classes[{1, P.d, P.NR, P.MP}].push_back({r, 0, 0, s_hi, s_lo});
       }
     }
+    // staging: per class, the forward items, or per adjoint round (one segment
+    // of every request that has one left this tick) recompute + reverse items
     size_t need = 0;
     for (auto& kv : classes) {
-      size_t nit = 0;
-      for (auto& w : kv.second) nit += w.r->nwg;
-      need += align256(nit * std::max(sizeof(FwdItem), sizeof(AdjItem)));
+      size_t rounds = 1;
+      for (auto& w : kv.second) {
+        const size_t rw = std::get<0>(kv.first) == 0 ? 1 : (size_t)(w.s_hi - w.s_lo + 1);
+        need += rw * w.r->nwg * (sizeof(FwdItem) + sizeof(AdjItem));
+        rounds = std::max(rounds, rw);
+      }
+      need += 2 * 256 * rounds;   // alignment of every upload
     }
     scp_status s = ensure_items(sv, need);
     if (s != SCP_OK) return s;
     size_t off = 0;
     int ci = 0;
+    // upload n items at off and return the device pointer
+    auto stage = [&](const void* host, size_t bytes, hipStream_t st, void** dptr) -> bool {
+      *dptr = (char*)sv->d_items + off;
+      if (hipMemcpyAsync(*dptr, host, bytes, hipMemcpyHostToDevice, st) != hipSuccess) return false;
+      off += align256(bytes);
+      return true;
+    };
     for (auto& kv : classes) {
       hipStream_t st = sv->work[ci++ % scp_server::kWork];
       const int kind = std::get<0>(kv.first), d = std::get<1>(kv.first), NR = std::get<2>(kv.first),
                 MP = std::get<3>(kv.first);
-      int nit = 0, wg = 64;
-      size_t sh = 0;
-      char* hbase = (char*)sv->h_items + off;
+      int wg = 64;
+      size_t sh_f = 0, sh_a = 0;
+      for (auto& w : kv.second) {
+        const Plan& P = w.r->sys->plan;
+        wg = std::max(wg, P.WG);
+        sh_f = std::max(sh_f, sizeof(float2) * 3 * (size_t)P.CPW * P.D);
+        sh_a = std::max(sh_a, adjoint_lds_bytes(P));
+      }
       if (kind == 0) {
-        FwdItem* it = (FwdItem*)hbase;
+        FwdItem* it = (FwdItem*)((char*)sv->h_items + off);
+        int nit = 0;
         for (auto& w : kv.second) {
           Request* r = w.r;
-          const Plan& P = r->sys->plan;
-          wg = std::max(wg, P.WG);
-          sh = std::max(sh, sizeof(float2) * 3 * (size_t)P.CPW * P.D);
           for (int cb = 0; cb < r->nwg; ++cb)
             it[nit++] = FwdItem{r->sys->d_plan, r->sys->d_ops, r->sys->d_ctab,
                                 w.n0 == 0 ? r->psi : nullptr,
                                 w.n1 == r->sys->n_steps ? r->psi : nullptr, r->state_hi, r->lo,
-                                r->want_grad ? r->ckpt : nullptr, r->ce, r->S, cb, w.n0, w.n1, 0};
+                                r->want_grad ? r->ckpt : nullptr, nullptr, nullptr, r->ce, r->S,
+                                cb, w.n0, w.n1, 0};
         }
+        void* dptr = nullptr;
+        if (!stage(it, (size_t)nit * sizeof(FwdItem), st, &dptr)) return fail(SCP_EHIP, "item upload");
+        s = launch_rk4_batched(d, NR, MP, (const FwdItem*)dptr, nit, wg, sh_f, false, st);
+        if (s != SCP_OK) return s;
       } else {
-        AdjItem* it = (AdjItem*)hbase;
-        for (auto& w : kv.second) {
-          Request* r = w.r;
-          const Plan& P = r->sys->plan;
-          wg = std::max(wg, P.WG);
-          sh = std::max(sh, adjoint_lds_bytes(P));
-          for (int cb = 0; cb < r->nwg; ++cb)
-            it[nit++] = AdjItem{r->sys->d_plan, r->sys->d_ops, r->sys->d_ctab, r->sys->d_dctab,
-                                r->ckpt, r->cot, r->segbuf, r->lo, r->sum, r->lamstate, r->part,
-                                r->ce, r->nckpt, r->S, cb, w.s_hi, w.s_lo,
-                                w.s_hi == r->nckpt - 1 ? 1 : 0, 0};
+        // round j: segment s_hi - j of every request that still has one this tick
+        int rounds = 0;
+        for (auto& w : kv.second) rounds = std::max(rounds, w.s_hi - w.s_lo + 1);
+        for (int j = 0; j < rounds; ++j) {
+          FwdItem* fi = (FwdItem*)((char*)sv->h_items + off);
+          int nf = 0;
+          for (auto& w : kv.second) {
+            Request* r = w.r;
+            const int seg = w.s_hi - j;
+            if (seg < w.s_lo) continue;
+            const int n0 = seg * r->ce, n1 = std::min(n0 + r->ce, r->sys->n_steps);
+            for (int cb = 0; cb < r->nwg; ++cb)
+              fi[nf++] = FwdItem{r->sys->d_plan, r->sys->d_ops, r->sys->d_ctab, nullptr, nullptr,
+                                 nullptr, r->lo, nullptr,
+                                 r->ckpt + (size_t)seg * r->S * r->sys->D, r->segbuf, 1, r->S, cb,
+                                 n0, n1, 0};
+          }
+          void* dptr = nullptr;
+          if (!stage(fi, (size_t)nf * sizeof(FwdItem), st, &dptr)) return fail(SCP_EHIP, "item upload");
+          s = launch_rk4_batched(d, NR, MP, (const FwdItem*)dptr, nf, wg, sh_f, true, st);
+          if (s != SCP_OK) return s;
+          AdjItem* ai = (AdjItem*)((char*)sv->h_items + off);
+          int na = 0;
+          for (auto& w : kv.second) {
+            Request* r = w.r;
+            const int seg = w.s_hi - j;
+            if (seg < w.s_lo) continue;
+            for (int cb = 0; cb < r->nwg; ++cb)
+              ai[na++] = AdjItem{r->sys->d_plan, r->sys->d_ops, r->sys->d_ctab, r->sys->d_dctab,
+                                 r->ckpt, r->cot, r->segbuf, r->lo, r->sum, r->lamstate, r->part,
+                                 r->ce, r->nckpt, r->S, cb, seg, seg, seg == r->nckpt - 1 ? 1 : 0,
+                                 0};
+          }
+          if (!stage(ai, (size_t)na * sizeof(AdjItem), st, &dptr)) return fail(SCP_EHIP, "item upload");
+          s = launch_adjoint_batched(d, NR, MP, (const AdjItem*)dptr, na, wg, sh_a, st);
+          if (s != SCP_OK) return s;
         }
       }
-      const size_t bytes = (size_t)nit * (kind == 0 ? sizeof(FwdItem) : sizeof(AdjItem));
-      void* dptr = (char*)sv->d_items + off;
-      if (hipMemcpyAsync(dptr, hbase, bytes, hipMemcpyHostToDevice, st) != hipSuccess)
-        return fail(SCP_EHIP, "item upload");
-      s = kind == 0 ? launch_rk4_batched(d, NR, MP, (const FwdItem*)dptr, nit, wg, sh, st)
-                    : launch_adjoint_batched(d, NR, MP, (const AdjItem*)dptr, nit, wg, sh, st);
-      if (s != SCP_OK) return s;
-      off += align256(bytes);
       for (auto& w : kv.second) {
         if (kind == 0) w.r->n_done = w.n1;
         else w.r->seg_next = w.s_lo - 1;
