@@ -395,9 +395,8 @@ __device__ __forceinline__ void comp_add(float& hi, float& lo, float dx) {
   hi = s2;
 }
 
-// One classical RK4 step n on psi = hi + lo.  hi and the RK accumulator live
-// in registers (base layout); lo is this thread's register-order slice in
-// device memory (stride TPC), read and written once per step.  The stage
+// One classical RK4 step n on psi = hi + lo.  hi, lo and the RK accumulator
+// live in registers (base layout).  The stage
 // inputs y_s are written to LDS in natural order (region ka, which is free,
 // then one barrier) and read there by every layout of the stage; iy, ka, kb
 // are the LDS region indices carried from step to step (start with 0, 1, 2).
@@ -409,7 +408,7 @@ template <int d, int NR, int MP, int RB>
 __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int rstride,
                                          bool lds_ok, bool active, int tc, int TPC,
                                          kptr<c32> optab, kptr<float> ctab, int n, Vec<RB>& hi,
-                                         c32* __restrict__ lo, int& iy, int& ka, int& kb,
+                                         Vec<RB>& lo, int& iy, int& ka, int& kb,
                                          c32* __restrict__ ystore, size_t ystride) {
   const float h = P->h;
   const int ng = uni(P->ngroups);
@@ -474,25 +473,12 @@ __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int 
       ka = t;
     }
   }
-  // psi <- psi + h/6 acc, compensated (all loads issued before the updates)
+  // psi <- psi + h/6 acc, compensated
   const float h6 = h * (1.0f / 6.0f);
-  if (active) {
-    Vec<RB> lv;
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const c32 l = lo[(size_t)r * TPC];
-      lv.re[r] = l.x;
-      lv.im[r] = l.y;
-    }
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      comp_add(hi.re[r], lv.re[r], h6 * acc.re[r]);
-      comp_add(hi.im[r], lv.im[r], h6 * acc.im[r]);
-      c32 l;
-      l.x = lv.re[r];
-      l.y = lv.im[r];
-      lo[(size_t)r * TPC] = l;
-    }
+  for (int r = 0; r < RB; ++r) {
+    comp_add(hi.re[r], lo.re[r], h6 * acc.re[r]);
+    comp_add(hi.im[r], lo.im[r], h6 * acc.im[r]);
   }
 }
 

@@ -16,8 +16,9 @@ namespace scp {
 
 // Whole-run (or chunked) propagation of CPW columns per workgroup.
 // psi0 != nullptr: start from psi0 (natural order), lo = 0; else continue from
-// state_hi / lo (register order).  At the end: state_hi (if given) and psiT
-// (natural order, hi + lo, if given).  lo: S x D register-order slices.
+// state_hi / lo (register order).  At the end: state_hi and lo (if state_hi is
+// given) and psiT (natural order, hi + lo, if given).  lo: S x D
+// register-order slices, touched only at the start and the end of a run.
 // REC: the adjoint's recompute of one segment: start from the checkpoint slab
 // ckin and write the four stage inputs of every step to ystore.
 template <int d, int NR, int MP, bool REC>
@@ -43,11 +44,10 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
   const int vstride = CPW * D;
   const int base = L - 1;
   const size_t colreg = (size_t)(active ? col : 0) * D + tc;   // register-order slice
-  c32* lo = lo_buf + colreg;
 
-  Vec<RB> hi;
+  Vec<RB> hi, lo;   // psi = hi + lo, both kept in registers for the whole run
 #pragma unroll
-  for (int r = 0; r < RB; ++r) hi.re[r] = hi.im[r] = 0.f;
+  for (int r = 0; r < RB; ++r) hi.re[r] = hi.im[r] = lo.re[r] = lo.im[r] = 0.f;
   if (REC && active) {
     const c32x2* src = (const c32x2*)I.ckin + (size_t)col * D + tc;
 #pragma unroll
@@ -55,10 +55,8 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
       const c32x2 v = src[(size_t)r * TPC];
       hi.re[r] = v.x;
       hi.im[r] = v.y;
-      c32 l;
-      l.x = v.z;
-      l.y = v.w;
-      lo[(size_t)r * TPC] = l;
+      lo.re[r] = v.z;
+      lo.im[r] = v.w;
     }
   } else if (active) {
     if (psi0 != nullptr) {
@@ -74,20 +72,12 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const c32 v = state_hi[colreg + (size_t)r * TPC];
+        const c32 l = lo_buf[colreg + (size_t)r * TPC];
         hi.re[r] = v.x;
         hi.im[r] = v.y;
+        lo.re[r] = l.x;
+        lo.im[r] = l.y;
       }
-    }
-  }
-  // psi0 may alias psiT: every column of this workgroup is read before lo is cleared
-  __syncthreads();
-  if (active && psi0 != nullptr) {
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      c32 z;
-      z.x = 0.f;
-      z.y = 0.f;
-      lo[(size_t)r * TPC] = z;
     }
   }
   int iy = 0, ka = 1, kb = 2;   // LDS regions: stage input, k moves
@@ -96,12 +86,11 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
       c32x2* dst = ckpt + ((size_t)(n / ckpt_every) * S + col) * D + tc;
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
-        const c32 l = lo[(size_t)r * TPC];
         c32x2 v;
         v.x = hi.re[r];
         v.y = hi.im[r];
-        v.z = l.x;
-        v.w = l.y;
+        v.z = lo.re[r];
+        v.w = lo.im[r];
         dst[(size_t)r * TPC] = v;
       }
     }
@@ -119,10 +108,13 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
   if (state_hi != nullptr) {
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      c32 v;
+      c32 v, l;
       v.x = hi.re[r];
       v.y = hi.im[r];
+      l.x = lo.re[r];
+      l.y = lo.im[r];
       state_hi[colreg + (size_t)r * TPC] = v;
+      lo_buf[colreg + (size_t)r * TPC] = l;
     }
   }
   if (psiT != nullptr) {
@@ -130,10 +122,9 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
     c32* dst = psiT + (size_t)col * D + tb;
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
-      const c32 l = lo[(size_t)r * TPC];
       c32 v;
-      v.x = hi.re[r] + l.x;
-      v.y = hi.im[r] + l.y;
+      v.x = hi.re[r] + lo.re[r];
+      v.y = hi.im[r] + lo.im[r];
       dst[P->reg_off[base][r]] = v;
     }
   }
