@@ -279,6 +279,18 @@ def main():
             parity = {"dF": abs(F - ref["F"]),
                       "grad_rel_err": float(np.abs(gr - gref).max() / np.abs(gref).max()),
                       "parity_sample": "8 seeded computational columns vs stored FP64 oracle"}
+            nu = ref.get("near_unit")
+            if nu is not None:
+                # second target: the nearest unitary to the oracle's own 8x8 block
+                t1 = np.array(nu["target_re"]) + 1j * np.array(nu["target_im"])
+                U = g.propagate(psi0, opts=opts, workspace=ws)
+                F1, _ = scp.fidelity(U, scp.Target(sd["comp_rows"], sd["comp_cols"], t1),
+                                     cotangent=cot)
+                g1 = g.adjoint(cot, opts, ws)
+                gref1 = np.array(nu["grad"])
+                parity.update({"F_block_target": F1, "dF_block_target": abs(F1 - nu["F"]),
+                               "grad_rel_err_block_target":
+                                   float(np.abs(g1 - gref1).max() / np.abs(gref1).max())})
             g.close()
 
     ws_fwd = scp.System(desc)

@@ -39,15 +39,26 @@ if __name__ == "__main__" and len(sys.argv) == 1:
 
 def config5_sampled():
     """Oracle F and gradient for the 8 seeded sampled columns of the 8-transmon
-    ring (fidelity restricted to the sampled computational states)."""
+    ring (fidelity restricted to the sampled computational states), for two
+    targets: CZ(q0,q1) restricted to them, and the nearest unitary to the
+    oracle's own computational block (F ~ 1, where |dF| is most sensitive)."""
     desc = sampled_config5_desc()
     sys_ = OracleSystem(desc)
     L, F, tau, U, g = loss_and_grad(sys_)
+    block = U[np.ix_(desc["comp_rows"], desc["comp_cols"])]
+    u, _, vh = np.linalg.svd(block)
+    t1 = u @ vh
+    desc1 = dict(desc, target=t1)
+    L1, F1, tau1, _, g1 = loss_and_grad(OracleSystem(desc1))
     out = {"workload": "config5 sampled: 8-transmon ring d=3, T=60 ns, 3000 steps, 8 sampled "
                        "computational columns, CZ(q0,q1) restricted to them",
            "generator": "tests/golden/make_oracle_refs.py (oracle only)",
            "columns": desc["columns"], "L": L, "F": F, "tau": [tau.real, tau.imag],
-           "param_names": param_names(sys_), "grad": [float(v) for v in g]}
+           "param_names": param_names(sys_), "grad": [float(v) for v in g],
+           "block_re": block.real.tolist(), "block_im": block.imag.tolist(),
+           "near_unit": {"target_re": t1.real.tolist(), "target_im": t1.imag.tolist(),
+                         "L": L1, "F": F1, "tau": [tau1.real, tau1.imag],
+                         "grad": [float(v) for v in g1]}}
     with open(os.path.join(HERE, "config5_sampled_oracle.json"), "w") as f:
         json.dump(out, f, indent=1)
 
