@@ -78,7 +78,8 @@ __device__ __forceinline__ void group_pair_adj(const Op<d>& O, const Op<d>& W, f
     for (int ai = 0; ai < d; ++ai)
 #pragma unroll
       for (int aj = 0; aj < d; ++aj) {
-        float sr = c * tr[ai][aj], sim = c * ti[ai][aj];
+        float sr = fmaf(c, tr[ai][aj], yb.re[r0 + ai * si_ + aj * sj_]);
+        float sim = fmaf(c, ti[ai][aj], yb.im[r0 + ai * si_ + aj * sj_]);
 #pragma unroll
         for (int b = 0; b < d; ++b) {
           const float wr = W.re[aj * d + b], wi = W.im[aj * d + b];
@@ -87,8 +88,8 @@ __device__ __forceinline__ void group_pair_adj(const Op<d>& O, const Op<d>& W, f
           sim = fmaf(wr, ti[ai][b], sim);
           sim = fmaf(wi, tr[ai][b], sim);
         }
-        yb.re[r0 + ai * si_ + aj * sj_] += sr;
-        yb.im[r0 + ai * si_ + aj * sj_] += sim;
+        yb.re[r0 + ai * si_ + aj * sj_] = sr;
+        yb.im[r0 + ai * si_ + aj * sj_] = sim;
       }
     // G_ab += sum_ai conj(T[ai][a]) y[ai][b]
 #pragma unroll

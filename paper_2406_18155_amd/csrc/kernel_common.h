@@ -161,7 +161,7 @@ __device__ __forceinline__ void contract_acc(const Op<d>& O, const Vec<RB>& in, 
     constexpr int r0 = fiber_base<d, NR, P, -1>(decltype(B)::value);
 #pragma unroll
     for (int a = 0; a < d; ++a) {
-      float sr = 0.f, si = 0.f;
+      float sr = out.re[r0 + a * st], si = out.im[r0 + a * st];
 #pragma unroll
       for (int b = 0; b < d; ++b) {
         const float orr = O.re[a * d + b], oi = O.im[a * d + b];
@@ -171,8 +171,8 @@ __device__ __forceinline__ void contract_acc(const Op<d>& O, const Vec<RB>& in, 
         si = fmaf(orr, xi, si);
         si = fmaf(oi, xr, si);
       }
-      out.re[r0 + a * st] += sr;
-      out.im[r0 + a * st] += si;
+      out.re[r0 + a * st] = sr;
+      out.im[r0 + a * st] = si;
     }
   });
 }
@@ -209,7 +209,9 @@ __device__ __forceinline__ void group_pair(const Op<d>& O, const Op<d>& W, float
     for (int ai = 0; ai < d; ++ai)
 #pragma unroll
       for (int aj = 0; aj < d; ++aj) {
-        float sr = c * tr[ai][aj], sim = c * ti[ai][aj];
+        // out + c T + W T, accumulated in place
+        float sr = fmaf(c, tr[ai][aj], out.re[r0 + ai * si_ + aj * sj_]);
+        float sim = fmaf(c, ti[ai][aj], out.im[r0 + ai * si_ + aj * sj_]);
 #pragma unroll
         for (int b = 0; b < d; ++b) {
           const float wr = W.re[aj * d + b], wi = W.im[aj * d + b];
@@ -218,8 +220,8 @@ __device__ __forceinline__ void group_pair(const Op<d>& O, const Op<d>& W, float
           sim = fmaf(wr, ti[ai][b], sim);
           sim = fmaf(wi, tr[ai][b], sim);
         }
-        out.re[r0 + ai * si_ + aj * sj_] += sr;
-        out.im[r0 + ai * si_ + aj * sj_] += sim;
+        out.re[r0 + ai * si_ + aj * sj_] = sr;
+        out.im[r0 + ai * si_ + aj * sj_] = sim;
       }
   });
 }
