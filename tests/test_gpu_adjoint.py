@@ -70,6 +70,18 @@ def check_grad(g, ref):
     assert rel.max() <= 10 * GRAD_TOL, rel.max()
 
 
+def _offset_frame(desc):
+    """Frame energies moved off the dressed ones (carriers kept): the generator
+    gains sum_m diag(eps_m - frame_m), whose gradient flows through eps."""
+    d = copy.deepcopy(desc)
+    o = OracleSystem(desc)
+    for m, md in enumerate(d["modes"]):
+        md["frame_eps"] = list(o.modes[m]["eps"] + 0.01 * (m + 1) * np.arange(md["trunc"]))
+    for k, dr in enumerate(d["drives"]):
+        dr["omega_d"] = o.drives[k]["omega_d"]
+    return d
+
+
 CASES = {
     "transmon2_d4": lambda: _short(si.config1(), 10.0, 500),
     "fluxonium2_d5": lambda: si._finish(dict(_short(si.config3(), 8.0, 400),
@@ -82,6 +94,8 @@ CASES = {
     "ring5_d3": lambda: _ring(5, 3, 6.0, 300),
     "chain3_d5": lambda: _chain(3, 5, 6.0, 300),
     "raw_pwc_d2": lambda: si.random_raw_system(5, [2, 2, 2], 3, 2.0, 200, env="pwc"),
+    "ring3_d3_offset_frame": lambda: _offset_frame(_ring(3, 3, 6.0, 300)),
+    "chain2_d5_offset_frame": lambda: _offset_frame(_chain(2, 5, 4.0, 200)),
 }
 
 
