@@ -242,6 +242,11 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
       switch2<d, NR, RB>(P, lds, cbase, vstride, lds_ok, tc, l - 1, l, kb, y);
       switch1<d, NR, RB>(P, lds, cbase, lds_ok, tc, l - 1, l, yb);
     }
+    // derivative contributions to the (EJ, EC, EL) of the mode at each register
+    // position, summed per lane over this layout's terms and reduced once
+    float dacc[NR * 3];
+#pragma unroll
+    for (int i = 0; i < NR * 3; ++i) dacc[i] = 0.f;
     // pair terms
     static_for<NR - 1>([&](auto Pp) {
       constexpr int p = decltype(Pp)::value;
@@ -258,8 +263,9 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
         group_pair_adj<d, NR, p, p + 1>(O, W, coef(cq, uni(C.cidx)), kb, y, yb, G, H);
         const int mi = uni(C.mode_i);
         if (mi >= 0) {
-          // couplings of this pair term, the partner's and the first factor's operators
-          const int pr = c_pair, mj = uni(C.mode_j);
+          // couplings of this pair term; the partner's (position p + 1) and the
+          // first factor's (position p) operator derivatives
+          const int pr = c_pair;
           const int nq = uni(P->pair_ncoup[pr]);
           const int offd = uni(P->off_dslot);
           for (int q = 0; q < nq; ++q) {
@@ -267,13 +273,13 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
             const int sj = uni(P->pair_pslot[pr][q]);
             fold(A, accw, npulse + 3 * N + e, im_dot<d>(ops + sj * dd, G), lane);
             const float ge = unif(P->coup_g[e]);
+#pragma unroll
             for (int th = 0; th < 3; ++th)
-              fold(A, accw, npulse + 3 * mj + th,
-                   ge * im_dot<d>(ops + offd + (sj * 3 + th) * dd, G), lane);
+              dacc[(p + 1) * 3 + th] += ge * im_dot<d>(ops + offd + (sj * 3 + th) * dd, G);
           }
+#pragma unroll
           for (int th = 0; th < 3; ++th)
-            fold(A, accw, npulse + 3 * mi + th,
-                 im_dot<d>(ops + offd + (c_slot * 3 + th) * dd, H), lane);
+            dacc[p * 3 + th] += im_dot<d>(ops + offd + (c_slot * 3 + th) * dd, H);
         }
       });
     });
@@ -329,10 +335,18 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
             }
           }
 #pragma unroll
-          for (int th = 0; th < 3; ++th) fold(A, accw, npulse + 3 * m + th, dev[th], lane);
+          for (int th = 0; th < 3; ++th) dacc[p * 3 + th] += dev[th];
         }
       });
     }
+    static_for<NR>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      const int m = uni(P->lmode[l][p]);
+      if (m >= 0) {
+#pragma unroll
+        for (int th = 0; th < 3; ++th) fold(A, accw, npulse + 3 * m + th, dacc[p * 3 + th], lane);
+      }
+    });
   }
   // yb <- i * yb
 #pragma unroll

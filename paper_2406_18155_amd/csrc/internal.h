@@ -97,6 +97,7 @@ struct Plan {
   int32_t has_mode_pass[MAXL];
   int32_t mode_pass[MAXL][8];      // adjoint: single-mode sensitivities of this mode at p (-1: none)
   float deps[16][3][8];            // d eps / d(EJ, EC, EL) per mode
+  int32_t lmode[MAXL][8];          // mode at each register position of each layout (-1: none)
   int32_t mdrv_off[17];            // drives of mode m: mdrv[mdrv_off[m] .. mdrv_off[m+1])
   int16_t mdrv[MAXGROUPS];         // drive indices grouped by mode
   int16_t mdrv_first[MAXGROUPS];   // 1: first drive on its operator slot

@@ -228,6 +228,7 @@ scp_status make_plan(scp_system* sys) {
   for (int m = 0; m < N; ++m) stride[m] = ipow(d, N - 1 - m);
   for (int l = 0; l < L; ++l) {
     const auto& S = layouts[l];
+    for (int p = 0; p < 8; ++p) P.lmode[l][p] = p < NR ? S[p] : -1;
     for (int p = 0; p < NR; ++p) P.reg_stride[l][p] = stride[S[p]];
     for (int r = 0; r < RB; ++r) {
       int off = 0, rr = r;
