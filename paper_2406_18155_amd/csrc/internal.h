@@ -16,55 +16,29 @@ using cplx = std::complex<double>;
 
 constexpr int MAXL = 8;        // layouts per stage
 constexpr int MAXRB = 64;      // register block (complex amplitudes per thread per vector)
-constexpr int MAXITEMS = 24;   // term items per layout
-constexpr int MAXPART = 3;     // partners of one first-factor slot within a layout
 constexpr int MAXSLOTS = 48;   // (mode, op) slots
 constexpr int MAXPAIRS = 48;   // (first slot, partner mode) pairs
 constexpr int MAXGROUPS = 48;
 constexpr int MAXPULSE = 256;  // pulse parameters
-constexpr int MAXUSE = 96;     // sensitivity usages
 constexpr int WG_THREADS = 256;
-
-// One term group evaluated inside one layout.  kind 0: diagonal (eps - frame)
-// of mode `mode` at register position `pos`.  kind 1: first-factor slot
-// `slot` on mode at `pos`, contributions c(t) * O~ y (if cidx >= 0) and
-// W~_pair O~ y with the partner at pos_j (n_part = 1).  kind 2 (adjoint
-// only): reduction of the mode's single-mode sensitivities.
-struct Item {
-  int8_t kind, pos, n_part, pad0;
-  int16_t mode, slot, cidx, pad1;
-  int8_t pos_j[MAXPART], pad2;
-  int16_t mode_j[MAXPART], pair[MAXPART];
-};
-
-// Sensitivity usage (adjoint): reduction of conj(Lvec) against y on mode at
-// `pos` in layout `layout`.  kind 0: Lvec = kb (drives and diagonal of the
-// mode); kind 1: Lvec = O~_{left_slot} kb contracted at left_pos (coupling
-// side), weight g of coupling `coup`.
-struct Usage {
-  int8_t kind, layout, pos, left_pos;
-  int16_t mode, left_slot, coup, slot;   // slot: op of `mode` this usage differentiates (kind 1)
-  int16_t drive_first, n_drives;         // kind 0: drives on this mode (indices into drive list)
-  int16_t pad[2];
-};
 
 // Canonical per-layout term list: every pair term has its first factor at
 // register position p and its partner at p + 1 (layouts are ordered along
 // paths of the coupling graph).  Absent entries point at a zero operator.
 struct CPair {
-  int16_t slot, pair, cidx, mode_i, mode_j, pad;   // cidx < 0: no drive attached
+  int32_t slot, pair, cidx, mode_i, mode_j, pad;   // cidx < 0: no drive attached
 };
 struct CSingle {
-  int16_t slot, cidx;
+  int32_t slot, cidx;
 };
 
 struct DriveDev {          // one drive in the device plan
-  int16_t slot, cidx, par0, npar;   // slot of its operator, c-table column, first pulse param
+  int32_t slot, cidx, par0, npar;   // slot of its operator, c-table column, first pulse param
 };
 
 struct Plan {
   int32_t d, N, NR, RB, TPC, CPW, WG, D, L, NT;
-  int32_t nslots, npairs, ngroups, ndrives, npulse, ncoup, nuse;
+  int32_t nslots, npairs, ngroups, ndrives, npulse, ncoup;
   int32_t nsteps;
   float h;
   int32_t block_q;       // floats2 per half-step block in the op table
@@ -74,15 +48,12 @@ struct Plan {
   int32_t reg_off[MAXL][MAXRB];
   int32_t reg_stride[MAXL][8];   // natural-order stride of the mode at each register position
   int32_t tstride[MAXL][16];
-  int32_t n_items[MAXL];
-  Item items[MAXL][MAXITEMS];
   float delta[17][8];          // eps - frame per mode (FP32); row 16 is zero
   int32_t slot_mode[MAXSLOTS];
   int32_t slot_op[MAXSLOTS];
   float coup_g[MAXPAIRS];
   int32_t coup_slot_i[MAXPAIRS], coup_slot_j[MAXPAIRS];
   DriveDev drives[MAXGROUPS];
-  Usage use[MAXUSE];
   int32_t layout_of_mode[16];  // a layout whose register modes contain the mode
   int32_t pos_of_mode[16];     // its register position there
   int32_t pair_ncoup[MAXPAIRS];
@@ -99,8 +70,8 @@ struct Plan {
   float deps[16][3][8];            // d eps / d(EJ, EC, EL) per mode
   int32_t lmode[MAXL][8];          // mode at each register position of each layout (-1: none)
   int32_t mdrv_off[17];            // drives of mode m: mdrv[mdrv_off[m] .. mdrv_off[m+1])
-  int16_t mdrv[MAXGROUPS];         // drive indices grouped by mode
-  int16_t mdrv_first[MAXGROUPS];   // 1: first drive on its operator slot
+  int32_t mdrv[MAXGROUPS];         // drive indices grouped by mode
+  int32_t mdrv_first[MAXGROUPS];   // 1: first drive on its operator slot
   int32_t nacc;                    // gradient accumulators: npulse + 3 N + ncoup
 };
 

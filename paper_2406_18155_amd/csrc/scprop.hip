@@ -309,13 +309,13 @@ scp_status make_plan(scp_system* sys) {
     for (int p = 0; p < 4; ++p)
       for (int m = 0; m < 2; ++m) {
         CPair& C = P.cpair[l][p][m];
-        C.slot = (int16_t)zslot;
-        C.pair = (int16_t)zpair;
+        C.slot = (int32_t)zslot;
+        C.pair = (int32_t)zpair;
         C.cidx = -1;
         C.mode_i = C.mode_j = -1;
       }
     for (int p = 0; p < 8; ++p) {
-      P.csingle[l][p].slot = (int16_t)zslot;
+      P.csingle[l][p].slot = (int32_t)zslot;
       P.csingle[l][p].cidx = -1;
       P.cdiag[l][p] = 16;
       P.mode_pass[l][p] = -1;
@@ -326,10 +326,10 @@ scp_status make_plan(scp_system* sys) {
     for (int g = 0; g < (int)grps.size(); ++g) {
       const int m = fill[grps[g].l * 4 + grps[g].p]++;
       CPair& C = P.cpair[grps[g].l][grps[g].p][m];
-      C.slot = (int16_t)grps[g].s;
-      C.pair = (int16_t)g;
-      C.mode_i = (int16_t)sys->slot_mode[grps[g].s];
-      C.mode_j = (int16_t)grps[g].j;
+      C.slot = (int32_t)grps[g].s;
+      C.pair = (int32_t)g;
+      C.mode_i = (int32_t)sys->slot_mode[grps[g].s];
+      C.mode_j = (int32_t)grps[g].j;
     }
   }
   // --- drives: attach to a pair term with the same first factor, else a single term
@@ -351,7 +351,7 @@ scp_status make_plan(scp_system* sys) {
         for (int q = 0; q < MP && !attached; ++q) {
           CPair& C = P.cpair[l][p][q];
           if (C.slot == s1 && C.cidx < 0) {
-            C.cidx = (int16_t)g;
+            C.cidx = (int32_t)g;
             attached = true;
           }
         }
@@ -359,8 +359,8 @@ scp_status make_plan(scp_system* sys) {
       const int l = P.layout_of_mode[m], p = P.pos_of_mode[m];
       if (P.csingle[l][p].slot != zslot)
         return fail(SCP_EINVAL, "two drive-only operators on one mode");
-      P.csingle[l][p].slot = (int16_t)s1;
-      P.csingle[l][p].cidx = (int16_t)g;
+      P.csingle[l][p].slot = (int32_t)s1;
+      P.csingle[l][p].cidx = (int32_t)g;
       P.has_single[l] = 1;
     }
   }
@@ -389,10 +389,10 @@ scp_status make_plan(scp_system* sys) {
   P.ndrives = (int)sys->drives.size();
   for (int k = 0; k < P.ndrives; ++k) {
     int s = slot(sys->drives[k].mode, sys->drives[k].op);
-    P.drives[k].slot = (int16_t)s;
-    P.drives[k].cidx = (int16_t)group_of_slot[s];
-    P.drives[k].par0 = (int16_t)par0;
-    P.drives[k].npar = (int16_t)sys->drives[k].par.size();
+    P.drives[k].slot = (int32_t)s;
+    P.drives[k].cidx = (int32_t)group_of_slot[s];
+    P.drives[k].par0 = (int32_t)par0;
+    P.drives[k].npar = (int32_t)sys->drives[k].par.size();
     par0 += (int)sys->drives[k].par.size();
   }
   P.npulse = par0;
@@ -406,7 +406,7 @@ scp_status make_plan(scp_system* sys) {
         if (sys->drives[k].mode != m) continue;
         bool first = true;
         for (int k2 = 0; k2 < k; ++k2) first &= P.drives[k2].slot != P.drives[k].slot;
-        P.mdrv[q] = (int16_t)k;
+        P.mdrv[q] = (int32_t)k;
         P.mdrv_first[q] = first ? 1 : 0;
         ++q;
       }
