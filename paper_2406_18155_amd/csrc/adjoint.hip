@@ -175,23 +175,22 @@ __device__ __forceinline__ float im_dot(kptr<c32> X, const Mat<d>& M) {
   return s;
 }
 
-// Sum over the 64 lanes, the same in every lane: a butterfly inside each row
+// Sum over the 64 lanes (the result is uniform): a butterfly inside each row
 // of 16 lanes with DPP (quad xor 1, quad xor 2, half-row mirror, row mirror),
-// then the four row sums in a fixed order.  No LDS round trips; deterministic.
-template <int ctrl>
+// then row broadcasts 15 and 31 gather the four row sums into lane 63.  No LDS
+// round trips; the order is fixed, so the result is deterministic.
+template <int ctrl, int row_mask>
 __device__ __forceinline__ float dpp_f(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, row_mask, 0xF, false));
 }
 __device__ __forceinline__ float wave_sum(float v) {
-  v += dpp_f<0xB1>(v);    // quad_perm [1,0,3,2]
-  v += dpp_f<0x4E>(v);    // quad_perm [2,3,0,1]
-  v += dpp_f<0x141>(v);   // row_half_mirror
-  v += dpp_f<0x140>(v);   // row_mirror
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-  return ((r0 + r1) + r2) + r3;
+  v += dpp_f<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp_f<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp_f<0x141, 0xF>(v);   // row_half_mirror
+  v += dpp_f<0x140, 0xF>(v);   // row_mirror: every lane holds its row's sum
+  v += dpp_f<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_f<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 // FP64 gradient accumulators of one wave.  Target t < 128 is held by lane
