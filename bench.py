@@ -131,6 +131,54 @@ def serving_leg(scp, si, torch, np, n_req):
     return out
 
 
+def other_configs(scp, si, torch, np):
+    """Configs 1-3 on the GPU: forward and gradient times, rate, FP64 forward,
+    and parity against the stored oracle results where they exist (one JSON
+    line per config; not part of the default run)."""
+    import copy
+    lines = []
+    cases = [("config1: 2 transmons d=4, full 16x16 U, T=40 ns, 2000 steps", si.config1(), None),
+             ("config2/3: 4-fluxonium chain d=5, 16 columns, T=100 ns, 5000 steps, 58 params",
+              si.config3(), os.path.join(ROOT, "tests", "golden", "config3_oracle.json"))]
+    stream = torch.cuda.current_stream()
+    for name, desc, ref_path in cases:
+        g = scp.System(desc)
+        S = len(desc["columns"])
+        psi0 = scp.basis_columns(g.D, desc["columns"])
+        opts = g.opts(S, with_ckpt=1)
+        ws = g.workspace(opts, with_grad=True)
+        tgt = scp.Target(desc["comp_rows"], desc["comp_cols"], desc["target"])
+        cot = torch.empty_like(psi0)
+        res = []
+        for rep in range(3):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record(stream)
+            U = g.propagate(psi0, opts=opts, workspace=ws)
+            ev[1].record(stream)
+            F, _ = scp.fidelity(U, tgt, cotangent=cot)
+            grad = g.adjoint(cot, opts, ws)
+            ev[2].record(stream)
+            torch.cuda.synchronize()
+            res.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
+        fwd_ms = min(r[0] for r in res)
+        grad_ms = min(r[1] for r in res)
+        N = desc["n_steps"]
+        fwd_flop, adj_flop = flops(desc, S)
+        p64 = plain64_forward_ms(scp, si, torch, desc, S)
+        out = {"config": name, "forward_ms": fwd_ms, "fidelity_and_gradient_ms": grad_ms,
+               "steps_dim2_per_s_forward": N * g.D * S / (fwd_ms * 1e-3),
+               "forward_tflops": fwd_flop / (fwd_ms * 1e-3) / 1e12,
+               "plain_fp64_forward_ms": p64, "F": F, "n_params": len(grad)}
+        if ref_path and os.path.exists(ref_path):
+            ref = json.load(open(ref_path))
+            gref = np.array(ref["grad"])
+            out.update({"dF": abs(F - ref["F"]),
+                        "grad_rel_err": float(np.abs(grad - gref).max() / np.abs(gref).max())})
+        g.close()
+        lines.append(out)
+    return lines
+
+
 def sampled_desc(si, np):
     desc = si.config5()
     samp = si.sampled_columns(len(desc["columns"]), 8)
@@ -188,6 +236,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-plain64", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--configs", action="store_true",
+                    help="only time configs 1-3 (one JSON line each) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (to scale HBM counters)")
     args = ap.parse_args()
@@ -212,6 +262,10 @@ def main():
     import scp_inputs as si
     import paper_2406_18155_amd as scp
 
+    if args.configs:
+        for line in other_configs(scp, si, torch, np):
+            print(json.dumps(line), flush=True)
+        return
     dev = torch.device("cuda:0")
     desc = si.config5()
     S = len(desc["columns"])
