@@ -436,12 +436,23 @@ __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int 
     ka = t;
   }
   Vec<RB> acc, k;
+  // The next stage's rotated operators are read with scalar loads; one stage
+  // ahead, the first threads of each column touch every 64-byte line of that
+  // block with a vector load, so those scalar reads find the lines in L2.
+  const int pf_lines = (uni(P->off_dslot) * (int)sizeof(c32) + 63) / 64;
+  float pf_sink = 0.f;
 #pragma unroll 1
   for (int sv = 0; sv < 4; ++sv) {
     const int s = uni(sv);
     auto ops = optab + (size_t)stage_q(n, s) * bq;
     auto cq = ctab + (size_t)stage_c(n, s) * ng;
+    float pf = 0.f;
+    if (tc < pf_lines) {
+      const int qn = s < 3 ? stage_q(n, s + 1) : stage_q(n + 1, 0);   // <= 2 N
+      pf = ((const float*)(uintptr_t)(optab + (size_t)qn * bq))[tc * 16];
+    }
     stage_apply<d, NR, MP, RB>(P, lds, cbase, rstride, lds_ok, tc, ops, cq, iy, ka, kb, k);
+    pf_sink += pf;
     // k_s = -i V y;  acc (+)= w_s k_s;  y_{s+1} = hi + c_{s+1} h k_s
     const float w = (s == 0 || s == 3) ? 1.f : 2.f;
     const float ch = (s == 2) ? h : 0.5f * h;
@@ -475,6 +486,8 @@ __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int 
       ka = t;
     }
   }
+  // keeps the prefetch loads alive; the sum of table values is never this NaN pattern
+  if (__float_as_uint(pf_sink) == 0xffffffffu && n < 0) lo.re[0] += pf_sink;
   // psi <- psi + h/6 acc, compensated
   const float h6 = h * (1.0f / 6.0f);
 #pragma unroll
