@@ -94,6 +94,8 @@ CASES = {
     "ring5_d3": lambda: _ring(5, 3, 6.0, 300),
     "chain3_d5": lambda: _chain(3, 5, 6.0, 300),
     "raw_pwc_d2": lambda: si.random_raw_system(5, [2, 2, 2], 3, 2.0, 200, env="pwc"),
+    "raw5_d2_four_register_modes": lambda: si.random_raw_system(6, [2, 2, 2, 2, 2], 5, 1.5, 150,
+                                                               env="gauss"),
     "ring3_d3_offset_frame": lambda: _offset_frame(_ring(3, 3, 6.0, 300)),
     "chain2_d5_offset_frame": lambda: _offset_frame(_chain(2, 5, 4.0, 200)),
 }
