@@ -253,8 +253,9 @@ def main():
         print(json.dumps({"copy_bytes": 1 << 30}))
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (columns shard with no communication; "
-              "see DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        print("bench.py: runs on one GPU only (the columns would shard across GPUs with no "
+              "communication until the final fidelity and gradient sums). Use --gpus 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

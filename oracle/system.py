@@ -11,8 +11,9 @@ multipath form J_C n (x) n and J_L phi (x) phi (Sec. 3.1), each entered as
 +g op_i (x) op_j with the sign carried by g.  Drives follow the microwave
 control Hamiltonian of App. C: c(t) = E(t) cos(omega_d t + phase).
 
-Frame (reading of this build, stated in DESIGN): time stepping is done in the
-interaction picture of H_f = sum_m diag(eps^f_m), where the frame energies
+Frame (a reading: the paper does not say in which frame to step): time
+stepping is done in the interaction picture of H_f = sum_m diag(eps^f_m),
+where the frame energies
 eps^f and the drive carriers are fixed at build from the nominal parameters
 (a drive with no explicit carrier uses eps^f_1 - eps^f_0 of its mode).  At
 other parameter values the generator gains diag(eps_m - eps^f_m).

@@ -15,7 +15,8 @@
 // and per mode K_ab = <kb, E_ab y> gives the drive and diagonal ones.  They
 // are formed block by block inside the adjoint applicator, folded with the
 // rotated operators / operator derivatives of the stage (FP64-built tables)
-// into scalars, wave-reduced, and accumulated in FP64 per wave in LDS.
+// into scalars (summed per lane over a layout where they share a target),
+// wave-reduced, and accumulated in FP64 per wave, one target per lane.
 // No atomics: the result is bitwise reproducible.
 //
 // Per segment, last to first, a recompute launch (the forward stepper started

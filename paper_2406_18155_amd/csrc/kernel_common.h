@@ -8,7 +8,7 @@
 // digits of the other modes index the thread inside the column.  Element of
 // register r of thread t: tb[l](t) + reg_off[l][r] in the natural (mode-0
 // slowest) order.  A contraction on a register mode is local to the thread;
-// switching layouts goes through LDS in natural order.
+// moving a vector to another layout goes through LDS in natural order.
 #pragma once
 
 #include <utility>

@@ -2,14 +2,16 @@
 //
 // One workgroup owns CPW columns for the whole run (columns evolve
 // independently under the same H(t), so no inter-workgroup traffic).  Each
-// column's state stays in registers: psi as a compensated (hi, lo) pair, the
-// RK accumulator, the stage input y and the generator output k.  Per stage
-// the generator V(t) y = sum of local terms (App. B: one mode's local
-// operator contracted at a time) is evaluated layout by layout; between
-// layouts y and k pass through LDS.  Classical RK4 (nodes 0, 1/2, 1/2, 1;
-// weights 1/6, 1/3, 1/3, 1/6) on psi' = -i V(t) psi; the psi update is a
-// two-sum so that 10^4 steps do not drift in FP32.  Rotated operators and
-// drive coefficients come from tables reduced in FP64 at build.
+// column's state stays on chip: psi as a compensated (hi, lo) pair and the RK
+// accumulator in registers, the stage input y in natural order in LDS.  Per
+// stage the generator V(t) y = sum of local terms (App. B: one mode's local
+// operator contracted at a time) is evaluated layout by layout; the
+// accumulating k moves between layouts through LDS.  Classical RK4 (nodes 0,
+// 1/2, 1/2, 1; weights 1/6, 1/3, 1/3, 1/6) on psi' = -i V(t) psi; the psi
+// update is a two-sum so that 10^4 steps do not drift in FP32.  Rotated
+// operators and drive coefficients come from tables reduced in FP64 at build.
+// The same kernel, started from a checkpoint and recording every stage input
+// (REC), is the adjoint's recompute of one segment.
 #include "kernel_common.h"
 
 namespace scp {

@@ -121,7 +121,8 @@ scp_status validate(const scp_system_desc* ds) {
   return SCP_OK;
 }
 
-// Layout planning (see DESIGN: register modes per layout, last layout = base).
+// Layout planning: which modes sit in registers in each layout of a stage; the
+// last layout is the base one (psi, checkpoints and natural-order stores).
 scp_status make_plan(scp_system* sys) {
   Plan& P = sys->plan;
   std::memset(&P, 0, sizeof(Plan));
