@@ -168,6 +168,23 @@ def test_config2_full_near_unit_fidelity(scp):
     g.close()
 
 
+def test_longest_serving_run_keeps_fidelity_near_one(scp):
+    # 10^4 steps (T = 200 ns at 50 steps/ns, the longest serving request): the
+    # compensated FP32 update must keep |dF| <= 1e-6 where F ~ 1
+    desc = _short(si.config1(), T=200.0, n=10000)
+    print("[propagate] config1 T=200 ns, 10000 steps", flush=True)
+    g, U = _gpu_propagate(scp, desc)
+    Uo = oracle_propagate(OracleSystem(desc))
+    P = Uo[np.ix_(desc["comp_rows"], desc["comp_cols"])]
+    u, _, vh = np.linalg.svd(P)
+    d2 = dict(desc, target=u @ vh)
+    Fg = _gpu_fid(scp, U, d2)
+    Fo, _ = oracle_fidelity(Uo, desc["comp_rows"], desc["comp_cols"], d2["target"])
+    assert Fo > 0.99
+    assert abs(Fg - Fo) <= DF_TOL, (Fg, Fo)
+    g.close()
+
+
 def test_config5_sampled_columns(scp):
     # all 256 columns on the GPU; the oracle on 8 seeded columns (|0..0>, |1..1> included)
     desc = si.config5()
