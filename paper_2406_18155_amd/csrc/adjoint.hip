@@ -234,6 +234,9 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
   const int npulse = P->npulse, N = P->N;
 #pragma unroll
   for (int r = 0; r < RB; ++r) yb.re[r] = yb.im[r] = 0.f;
+  // per-lane derivative sums of a mode shared by the last register position
+  // of one layout and the first of the next are carried across the boundary
+  float carry[3] = {0.f, 0.f, 0.f};
   for (int lv = 0; lv < L; ++lv) {
     const int l = __builtin_amdgcn_readfirstlane(lv);
     if (l == 0) {
@@ -246,7 +249,7 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
     // position, summed per lane over this layout's terms and reduced once
     float dacc[NR * 3];
 #pragma unroll
-    for (int i = 0; i < NR * 3; ++i) dacc[i] = 0.f;
+    for (int i = 0; i < NR * 3; ++i) dacc[i] = i < 3 ? carry[i] : 0.f;
     // pair terms
     static_for<NR - 1>([&](auto Pp) {
       constexpr int p = decltype(Pp)::value;
@@ -339,14 +342,20 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
         }
       });
     }
+    // the last position's mode continues as the next layout's first one?
+    const bool pass_on = (NR > 1) && l + 1 < L &&
+                         uni(P->lmode[l][NR - 1]) == uni(P->lmode[l + 1][0]) &&
+                         uni(P->lmode[l][NR - 1]) >= 0;
     static_for<NR>([&](auto Pp) {
       constexpr int p = decltype(Pp)::value;
       const int m = uni(P->lmode[l][p]);
-      if (m >= 0) {
+      if (m >= 0 && !(p == NR - 1 && pass_on)) {
 #pragma unroll
         for (int th = 0; th < 3; ++th) fold(A, accw, npulse + 3 * m + th, dacc[p * 3 + th], lane);
       }
     });
+#pragma unroll
+    for (int th = 0; th < 3; ++th) carry[th] = pass_on ? dacc[(NR - 1) * 3 + th] : 0.f;
   }
   // yb <- i * yb
 #pragma unroll
