@@ -73,6 +73,13 @@ struct Plan {
   int32_t mdrv[MAXGROUPS];         // drive indices grouped by mode
   int32_t mdrv_first[MAXGROUPS];   // 1: first drive on its operator slot
   int32_t nacc;                    // gradient accumulators: npulse + 3 N + ncoup
+  // Real frame (all single-mode and pair operators real): the stepper applies
+  // the un-rotated operators (table block 0) between the diagonal frame
+  // rotations of y and k, whose phases come from a per-half-step table with
+  // ph_row entries (a multiple of 8): the RB register phases of the base
+  // layout, then from ph_thr the NT * d thread-position phases.
+  int32_t real_frame;
+  int32_t ph_row, ph_thr;
 };
 
 // Work descriptor of one workgroup of a (possibly batched) forward launch:
@@ -88,6 +95,8 @@ struct FwdItem {
   float4* ckpt;         // nullable
   const float4* ckin;   // recompute: start from this checkpoint slab (hi, lo; register order)
   float2* ystore;       // recompute: stage inputs, natural order, 4 S D per step
+  const float2* ph;     // real frame: phase table [2N+1][ph_row] (else unused)
+  const float* rops;    // real frame: the un-rotated operators (real parts, block layout)
   int ce, S, cb, n0, n1, pad;
 };
 
@@ -153,6 +162,8 @@ struct scp_system {
   float* d_dctab = nullptr;     // [3N][npulse] dc/dpar
   double* d_dctab64 = nullptr;
   double* d_ctab64 = nullptr;   // [3N][n_drives] c(t) per drive, FP64 (plain path)
+  float2* d_ph = nullptr;       // real frame: [2N+1][ph_row] frame phases (cos, sin)
+  float* d_rops = nullptr;      // real frame: [block_q] un-rotated operators (real parts)
   void* d_scratch = nullptr;    // small per-system scratch (adjoint partial sums)
   size_t scratch_bytes = 0;
   int device = 0;

@@ -288,6 +288,174 @@ __device__ __forceinline__ void apply_layout(kptr<Plan> P, int l,
   }
 }
 
+// ----------------------------------------------------------------------------
+// real frame: every operator real.  With D(t) = exp(i H_f t) (diagonal) the
+// interaction-picture generator is D(t) R D(t)^dag, R the sum of the
+// un-rotated terms, so k = D R (D^dag y): the contractions take real d x d
+// operators (two FMAs per complex amplitude and operator entry instead of four).
+// ----------------------------------------------------------------------------
+template <int d>
+struct ROp {
+  float v[d * d];
+};
+
+template <int d>
+__device__ __forceinline__ void load_rop(kptr<float> p, ROp<d>& o) {
+#pragma unroll
+  for (int i = 0; i < d * d; ++i) o.v[i] = p[i];
+}
+
+// out += (O at position P) in, O real
+template <int d, int NR, int P, int RB>
+__device__ __forceinline__ void contract_acc_real(const ROp<d>& O, const Vec<RB>& in, Vec<RB>& out) {
+  using C = Cfg<d, NR>;
+  constexpr int st = C::stride(P);
+  static_for<RB / d>([&](auto B) {
+    constexpr int r0 = fiber_base<d, NR, P, -1>(decltype(B)::value);
+#pragma unroll
+    for (int a = 0; a < d; ++a) {
+      float sr = out.re[r0 + a * st], si = out.im[r0 + a * st];
+#pragma unroll
+      for (int b = 0; b < d; ++b) {
+        const float o = O.v[a * d + b];
+        sr = fmaf(o, in.re[r0 + b * st], sr);
+        si = fmaf(o, in.im[r0 + b * st], si);
+      }
+      out.re[r0 + a * st] = sr;
+      out.im[r0 + a * st] = si;
+    }
+  });
+}
+
+// out += W(at PJ) O(at PI) in + c O(at PI) in, O and W real
+template <int d, int NR, int PI, int PJ, int RB>
+__device__ __forceinline__ void group_pair_real(const ROp<d>& O, const ROp<d>& W, float c,
+                                                const Vec<RB>& in, Vec<RB>& out) {
+  using C = Cfg<d, NR>;
+  constexpr int si_ = C::stride(PI);
+  constexpr int sj_ = C::stride(PJ);
+  static_for<RB / (d * d)>([&](auto B) {
+    constexpr int r0 = fiber_base<d, NR, PI, PJ>(decltype(B)::value);
+    float tr[d][d], ti[d][d];   // T[a_i][a_j] = sum_b O[a_i][b] in[b, a_j]
+#pragma unroll
+    for (int aj = 0; aj < d; ++aj)
+#pragma unroll
+      for (int ai = 0; ai < d; ++ai) {
+        float sr = 0.f, sim = 0.f;
+#pragma unroll
+        for (int b = 0; b < d; ++b) {
+          const float o = O.v[ai * d + b];
+          sr = fmaf(o, in.re[r0 + b * si_ + aj * sj_], sr);
+          sim = fmaf(o, in.im[r0 + b * si_ + aj * sj_], sim);
+        }
+        tr[ai][aj] = sr;
+        ti[ai][aj] = sim;
+      }
+#pragma unroll
+    for (int ai = 0; ai < d; ++ai)
+#pragma unroll
+      for (int aj = 0; aj < d; ++aj) {
+        float sr = fmaf(c, tr[ai][aj], out.re[r0 + ai * si_ + aj * sj_]);
+        float sim = fmaf(c, ti[ai][aj], out.im[r0 + ai * si_ + aj * sj_]);
+#pragma unroll
+        for (int b = 0; b < d; ++b) {
+          const float w = W.v[aj * d + b];
+          sr = fmaf(w, tr[ai][b], sr);
+          sim = fmaf(w, ti[ai][b], sim);
+        }
+        out.re[r0 + ai * si_ + aj * sj_] = sr;
+        out.im[r0 + ai * si_ + aj * sj_] = sim;
+      }
+  });
+}
+
+// apply_layout with the un-rotated (real) operators
+template <int d, int NR, int MP, int RB>
+__device__ __forceinline__ void apply_layout_real(kptr<Plan> P, int l, kptr<float> ops,
+                                                  kptr<float> cq, const Vec<RB>& in,
+                                                  Vec<RB>& out) {
+  constexpr int dd = d * d;
+  static_for<NR - 1>([&](auto Pp) {
+    constexpr int p = decltype(Pp)::value;
+    static_for<MP>([&](auto Mm) {
+      constexpr int m = decltype(Mm)::value;
+      const auto& C = P->cpair[l][p][m];
+      ROp<d> O, W;
+      load_rop<d>(ops + uni(C.slot) * dd, O);
+      load_rop<d>(ops + uni(P->off_pair + C.pair * dd), W);
+      group_pair_real<d, NR, p, p + 1>(O, W, coef(cq, uni(C.cidx)), in, out);
+    });
+  });
+  if (uni(P->has_single[l])) {
+    static_for<NR>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      const auto& C1 = P->csingle[l][p];
+      ROp<d> O;
+      load_rop<d>(ops + uni(C1.slot) * dd, O);
+      const float c = coef(cq, uni(C1.cidx));
+#pragma unroll
+      for (int i = 0; i < dd; ++i) O.v[i] *= c;
+      contract_acc_real<d, NR, p>(O, in, out);
+    });
+  }
+  if (uni(P->has_diag[l])) {
+    static_for<NR>([&](auto Pp) {
+      constexpr int p = decltype(Pp)::value;
+      diag_acc<d, NR, p>(P->delta[uni(P->cdiag[l][p])], in, out);
+    });
+  }
+}
+
+// Frame phase exp(i f t) of this thread's thread-position digits in the base
+// layout (row: the thread-position part of a half-step's phase row; entry
+// k*d + a is the phase of level a of the mode at thread position k).
+template <int d>
+__device__ __forceinline__ c32 thread_phase(kptr<c32> row, int NT, int tc) {
+  float pr = 1.f, pi = 0.f;
+  int t = tc;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (k < NT) {
+      const int q = t / d;
+      const int a = t - q * d;
+      t = q;
+      float vr = row[k * d].x, vi = row[k * d].y;
+#pragma unroll
+      for (int b = 1; b < d; ++b) {
+        const float ur = row[k * d + b].x, ui = row[k * d + b].y;
+        vr = a == b ? ur : vr;
+        vi = a == b ? ui : vi;
+      }
+      const float nr = pr * vr - pi * vi;
+      const float ni = fmaf(pr, vi, pi * vr);
+      pr = nr;
+      pi = ni;
+    }
+  }
+  c32 o;
+  o.x = pr;
+  o.y = pi;
+  return o;
+}
+
+// Eight phases of a row (rows are 64-byte aligned, so the register phases
+// arrive with wide scalar loads).
+struct alignas(64) c32x8 {
+  float v[16];
+};
+
+// The phase of base-layout register r: thread part pt times the register
+// part of the row (uniform); CONJ: its conjugate.
+template <bool CONJ>
+__device__ __forceinline__ c32 elem_phase(c32 pt, kptr<c32x8> preg, int r) {
+  const float gr = preg[r / 8].v[2 * (r % 8)], gi = preg[r / 8].v[2 * (r % 8) + 1];
+  c32 e;
+  e.x = pt.x * gr - pt.y * gi;
+  e.y = fmaf(pt.x, gi, pt.y * gr);
+  if (CONJ) e.y = -e.y;
+  return e;
+}
+
 }  // namespace scp
 
 namespace scp {
@@ -350,10 +518,10 @@ __device__ __forceinline__ void switch2(kptr<Plan> P, c32* lds, int cbase,
 // before the previous barrier; y's region is never written during a stage).
 // k leaves in the base layout (L-1).  On return ka is the region that the
 // last move did not use, which may be written next without a barrier.
-template <int d, int NR, int MP, int RB>
+template <int d, int NR, int MP, int RB, bool RF = false>
 __device__ __forceinline__ void stage_apply(kptr<Plan> P, c32* lds, int cbase, int rstride,
-                                            bool lds_ok, int tc, kptr<c32> ops, kptr<float> cq,
-                                            int iy, int& ka, int& kb, Vec<RB>& k) {
+                                            bool lds_ok, int tc, kptr<c32> ops, kptr<float> rops,
+                                            kptr<float> cq, int iy, int& ka, int& kb, Vec<RB>& k) {
   const int L = uni(P->L);
   const c32* ybuf = lds + iy * rstride + cbase;
 #pragma unroll
@@ -379,7 +547,10 @@ __device__ __forceinline__ void stage_apply(kptr<Plan> P, c32* lds, int cbase, i
 #pragma unroll
       for (int r = 0; r < RB; ++r) y.re[r] = y.im[r] = 0.f;
     }
-    apply_layout<d, NR, MP, RB>(P, l, ops, cq, y, k);
+    if constexpr (RF)
+      apply_layout_real<d, NR, MP, RB>(P, l, rops, cq, y, k);
+    else
+      apply_layout<d, NR, MP, RB>(P, l, ops, cq, y, k);
   }
 }
 
@@ -406,29 +577,44 @@ __device__ __forceinline__ void comp_add(float& hi, float& lo, float dx) {
 // the dropped lo is below their rounding).  If ystore != nullptr the four
 // stage inputs are also written there in natural order (ystore is the
 // column's base; stride ystride between stages) for the adjoint.
-template <int d, int NR, int MP, int RB>
+// RF (real frame): LDS receives D(t_s)^dag y_s, the layouts apply the
+// un-rotated real operators (table block 0), and k_s = D(t_s) (R y'_s); the
+// phases come from the half-step rows of ph.  ystore still receives y_s.
+template <int d, int NR, int MP, int RB, bool RF = false>
 __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int rstride,
                                          bool lds_ok, bool active, int tc, int TPC,
-                                         kptr<c32> optab, kptr<float> ctab, int n, Vec<RB>& hi,
-                                         Vec<RB>& lo, int& iy, int& ka, int& kb,
+                                         kptr<c32> optab, kptr<float> rops, kptr<float> ctab,
+                                         kptr<c32> ph, int n,
+                                         Vec<RB>& hi, Vec<RB>& lo, int& iy, int& ka, int& kb,
                                          c32* __restrict__ ystore, size_t ystride) {
   const float h = P->h;
   const int ng = uni(P->ngroups);
   const int bq = uni(P->block_q);
   const int L = uni(P->L);
+  const int NT = uni(P->NT);
+  const int prow = RF ? uni(P->ph_row) : 0;
+  const int pthr = RF ? uni(P->ph_thr) : 0;
   const int tbB = thread_base<d>(P, L - 1, tc);
   const RegOff<d, NR> RB_ = reg_off_of<d, NR>(P, L - 1);
   // y_0 = hi
   {
     c32* yb = lds + ka * rstride + cbase + tbB;
     c32* ys = ystore != nullptr ? ystore + tbB : nullptr;
+    kptr<c32> row = ph + (size_t)stage_q(n, 0) * prow;
+    const c32 pt = RF ? thread_phase<d>(row + pthr, NT, tc) : c32{1.f, 0.f};
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       c32 v;
       v.x = hi.re[r];
       v.y = hi.im[r];
-      if (lds_ok) yb[RB_(r)] = v;
       if (ys != nullptr && active) ys[RB_(r)] = v;
+      if (RF) {
+        const c32 e = elem_phase<true>(pt, (kptr<c32x8>)row, r);
+        const c32 u = v;
+        v.x = e.x * u.x - e.y * u.y;
+        v.y = fmaf(e.x, u.y, e.y * u.x);
+      }
+      if (lds_ok) yb[RB_(r)] = v;
     }
     __syncthreads();
     const int t = iy;
@@ -436,23 +622,40 @@ __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int 
     ka = t;
   }
   Vec<RB> acc, k;
-  // The next stage's rotated operators are read with scalar loads; one stage
-  // ahead, the first threads of each column touch every 64-byte line of that
-  // block with a vector load, so those scalar reads find the lines in L2.
-  const int pf_lines = (uni(P->off_dslot) * (int)sizeof(c32) + 63) / 64;
+  // The next stage's rotated operators (real frame: its phase row) are read
+  // with scalar loads; one stage ahead, the first threads of each column touch
+  // every 64-byte line of that block with a vector load, so those scalar reads
+  // find the lines in L2.
+  const int pf_lines = RF ? (prow * (int)sizeof(c32) + 63) / 64
+                          : (uni(P->off_dslot) * (int)sizeof(c32) + 63) / 64;
+  const kptr<c32> pf_base = RF ? ph : optab;
+  const int pf_stride = RF ? prow : bq;
   float pf_sink = 0.f;
 #pragma unroll 1
   for (int sv = 0; sv < 4; ++sv) {
     const int s = uni(sv);
-    auto ops = optab + (size_t)stage_q(n, s) * bq;
+    auto ops = optab + (RF ? 0 : (size_t)stage_q(n, s) * bq);
     auto cq = ctab + (size_t)stage_c(n, s) * ng;
     float pf = 0.f;
     if (tc < pf_lines) {
       const int qn = s < 3 ? stage_q(n, s + 1) : stage_q(n + 1, 0);   // <= 2 N
-      pf = ((const float*)(uintptr_t)(optab + (size_t)qn * bq))[tc * 16];
+      pf = ((const float*)(uintptr_t)(pf_base + (size_t)qn * pf_stride))[tc * 16];
     }
-    stage_apply<d, NR, MP, RB>(P, lds, cbase, rstride, lds_ok, tc, ops, cq, iy, ka, kb, k);
+    stage_apply<d, NR, MP, RB, RF>(P, lds, cbase, rstride, lds_ok, tc, ops, rops, cq, iy, ka, kb,
+                                   k);
     pf_sink += pf;
+    if (RF) {
+      // back to the interaction picture: k <- D(t_s) k
+      kptr<c32> row = ph + (size_t)stage_q(n, s) * prow;
+      const c32 pt = thread_phase<d>(row + pthr, NT, tc);
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const c32 e = elem_phase<false>(pt, (kptr<c32x8>)row, r);
+        const float xr = k.re[r], xi = k.im[r];
+        k.re[r] = e.x * xr - e.y * xi;
+        k.im[r] = fmaf(e.x, xi, e.y * xr);
+      }
+    }
     // k_s = -i V y;  acc (+)= w_s k_s;  y_{s+1} = hi + c_{s+1} h k_s
     const float w = (s == 0 || s == 3) ? 1.f : 2.f;
     const float ch = (s == 2) ? h : 0.5f * h;
@@ -472,13 +675,21 @@ __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int 
     if (s < 3) {
       c32* yb = lds + ka * rstride + cbase + tbB;
       c32* ys = ystore != nullptr ? ystore + (size_t)(s + 1) * ystride + tbB : nullptr;
+      kptr<c32> row = ph + (size_t)stage_q(n, s + 1) * prow;
+      const c32 pt = RF ? thread_phase<d>(row + pthr, NT, tc) : c32{1.f, 0.f};
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         c32 v;
         v.x = k.re[r];
         v.y = k.im[r];
-        if (lds_ok) yb[RB_(r)] = v;
         if (ys != nullptr && active) ys[RB_(r)] = v;
+        if (RF) {
+          const c32 e = elem_phase<true>(pt, (kptr<c32x8>)row, r);
+          const c32 u = v;
+          v.x = e.x * u.x - e.y * u.y;
+          v.y = fmaf(e.x, u.y, e.y * u.x);
+        }
+        if (lds_ok) yb[RB_(r)] = v;
       }
       __syncthreads();
       const int t = iy;

@@ -11,7 +11,11 @@
 // update is a two-sum so that 10^4 steps do not drift in FP32.  Rotated
 // operators and drive coefficients come from tables reduced in FP64 at build.
 // The same kernel, started from a checkpoint and recording every stage input
-// (REC), is the adjoint's recompute of one segment.
+// (REC), is the adjoint's recompute of one segment.  When every operator is
+// real (transmon devices: the dressed charge operator is real symmetric) the
+// real-frame variant (RF) applies the un-rotated operators between diagonal
+// frame rotations of the stage input and of k, which halves the FMAs of every
+// contraction.
 #include "kernel_common.h"
 
 namespace scp {
@@ -23,13 +27,16 @@ namespace scp {
 // register-order slices, touched only at the start and the end of a run.
 // REC: the adjoint's recompute of one segment: start from the checkpoint slab
 // ckin and write the four stage inputs of every step to ystore.
-template <int d, int NR, int MP, bool REC>
+// RF: the real-frame stepper (all operators real; frame phases from I.ph).
+template <int d, int NR, int MP, bool REC, bool RF>
 __device__ __forceinline__ void rk4_block(const FwdItem& I) {
   constexpr int RB = Cfg<d, NR>::RB;
   extern __shared__ c32 lds[];
   kptr<Plan> P = kconst(I.P);
   kptr<c32> optab = kconst((const c32*)I.optab);
   kptr<float> ctab = kconst(I.ctab);
+  kptr<c32> ph = kconst((const c32*)I.ph);
+  kptr<float> rops = kconst(I.rops);
   const c32* __restrict__ psi0 = (const c32*)I.psi0;
   c32* __restrict__ psiT = (c32*)I.psiT;
   c32* __restrict__ state_hi = (c32*)I.state_hi;
@@ -97,14 +104,14 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
       }
     }
     if (REC)
-      rk4_step<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, ctab, n, hi,
-                              lo, iy, ka, kb,
-                              (c32*)I.ystore + (size_t)(active ? col : 0) * D +
-                                  (size_t)(n - n0) * 4 * S * D,
-                              (size_t)S * D);
+      rk4_step<d, NR, MP, RB, RF>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, rops,
+                                  ctab, ph, n, hi, lo, iy, ka, kb,
+                                  (c32*)I.ystore + (size_t)(active ? col : 0) * D +
+                                      (size_t)(n - n0) * 4 * S * D,
+                                  (size_t)S * D);
     else
-      rk4_step<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, ctab, n, hi,
-                              lo, iy, ka, kb, nullptr, 0);
+      rk4_step<d, NR, MP, RB, RF>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, rops,
+                                  ctab, ph, n, hi, lo, iy, ka, kb, nullptr, 0);
   }
   if (!active) return;
   if (state_hi != nullptr) {
@@ -132,16 +139,16 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
   }
 }
 
-template <int d, int NR, int MP, bool REC>
+template <int d, int NR, int MP, bool REC, bool RF>
 __global__ void __launch_bounds__(WG_THREADS) rk4_kernel(FwdItem I) {
   I.cb = blockIdx.x;
-  rk4_block<d, NR, MP, REC>(I);
+  rk4_block<d, NR, MP, REC, RF>(I);
 }
 
 // Batched launch: workgroup b runs items[b] (requests of one size class).
-template <int d, int NR, int MP, bool REC>
+template <int d, int NR, int MP, bool REC, bool RF>
 __global__ void __launch_bounds__(WG_THREADS) rk4_batched_kernel(const FwdItem* __restrict__ items) {
-  rk4_block<d, NR, MP, REC>(items[blockIdx.x]);
+  rk4_block<d, NR, MP, REC, RF>(items[blockIdx.x]);
 }
 
 // out = V(t) y at one stage time, through the same stage_apply as the stepper.
@@ -182,7 +189,8 @@ apply_kernel(const Plan* __restrict__ Pg, const c32* __restrict__ opsg,
   }
   __syncthreads();
   int ka = 1, kb = 2;
-  stage_apply<d, NR, MP, RB>(P, lds, cw * D, CPW * D, lds_ok, tc, ops, cq, 0, ka, kb, k);
+  stage_apply<d, NR, MP, RB>(P, lds, cw * D, CPW * D, lds_ok, tc, ops, kconst((const float*)nullptr),
+                             cq, 0, ka, kb, k);
   if (!active) return;
   const int tb = thread_base<d>(P, base, tc);
   c32* dst = out + (size_t)col * D + tb;
@@ -202,41 +210,59 @@ namespace {
 
 template <int d, int NR, int MP>
 struct Launch {
-  template <bool REC>
-  static hipError_t run(const scp_system* sys, const FwdItem& I, int S, hipStream_t s) {
+  template <bool REC, bool RF>
+  static hipError_t run1(const scp_system* sys, const FwdItem& I, int S, hipStream_t s) {
     const Plan& P = sys->plan;
     const int nwg = (S + P.CPW - 1) / P.CPW;
     const size_t sh = sizeof(c32) * 3 * (size_t)P.CPW * P.D;
-    hipFuncSetAttribute((const void*)rk4_kernel<d, NR, MP, REC>,
+    hipFuncSetAttribute((const void*)rk4_kernel<d, NR, MP, REC, RF>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((rk4_kernel<d, NR, MP, REC>), dim3(nwg), dim3(P.WG), sh, s, I);
+    hipLaunchKernelGGL((rk4_kernel<d, NR, MP, REC, RF>), dim3(nwg), dim3(P.WG), sh, s, I);
     return hipGetLastError();
+  }
+  // the real-frame kernels exist for one pair term per position pair
+  template <bool REC>
+  static hipError_t run(const scp_system* sys, const FwdItem& I, int S, hipStream_t s) {
+    if constexpr (MP == 1) {
+      if (sys->plan.real_frame) return run1<REC, true>(sys, I, S, s);
+    }
+    return run1<REC, false>(sys, I, S, s);
   }
   static hipError_t rk4(const scp_system* sys, const float2* psi0, float2* psiT, float2* state,
                         float2* lo, float4* ckpt, int ce, int S, int n0, int n1, hipStream_t s) {
     FwdItem I{sys->d_plan, sys->d_ops, sys->d_ctab, psi0, psiT, state, lo, ckpt, nullptr, nullptr,
-              ce, S, 0, n0, n1, 0};
+              sys->d_ph, sys->d_rops, ce, S, 0, n0, n1, 0};
     return run<false>(sys, I, S, s);
   }
   static hipError_t recompute(const scp_system* sys, const float4* ckin, float2* lo,
                               float2* ystore, int S, int n0, int n1, hipStream_t s) {
     FwdItem I{sys->d_plan, sys->d_ops, sys->d_ctab, nullptr, nullptr, nullptr, lo, nullptr, ckin,
-              ystore, 1, S, 0, n0, n1, 0};
+              ystore, sys->d_ph, sys->d_rops, 1, S, 0, n0, n1, 0};
     return run<true>(sys, I, S, s);
   }
+  template <bool REC, bool RF>
+  static void batched1(const FwdItem* items, int nitems, int wg, size_t sh, hipStream_t s) {
+    hipFuncSetAttribute((const void*)rk4_batched_kernel<d, NR, MP, REC, RF>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((rk4_batched_kernel<d, NR, MP, REC, RF>), dim3(nitems), dim3(wg), sh, s,
+                       items);
+  }
   static hipError_t batched(const FwdItem* items, int nitems, int wg, size_t sh, bool rec,
-                            hipStream_t s) {
-    if (rec) {
-      hipFuncSetAttribute((const void*)rk4_batched_kernel<d, NR, MP, true>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-      hipLaunchKernelGGL((rk4_batched_kernel<d, NR, MP, true>), dim3(nitems), dim3(wg), sh, s,
-                         items);
-    } else {
-      hipFuncSetAttribute((const void*)rk4_batched_kernel<d, NR, MP, false>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-      hipLaunchKernelGGL((rk4_batched_kernel<d, NR, MP, false>), dim3(nitems), dim3(wg), sh, s,
-                         items);
+                            bool rf, hipStream_t s) {
+    if constexpr (MP == 1) {
+      if (rf) {
+        if (rec)
+          batched1<true, true>(items, nitems, wg, sh, s);
+        else
+          batched1<false, true>(items, nitems, wg, sh, s);
+        return hipGetLastError();
+      }
     }
+    if (rf) return hipErrorInvalidValue;
+    if (rec)
+      batched1<true, false>(items, nitems, wg, sh, s);
+    else
+      batched1<false, false>(items, nitems, wg, sh, s);
     return hipGetLastError();
   }
   static hipError_t apply(const scp_system* sys, const float2* ops, const float* cq,
@@ -306,10 +332,10 @@ scp_status launch_apply(const scp_system* sys, int step, int stage, const float2
 }  // namespace scp
 
 namespace scp {
-scp_status launch_rk4_batched(int d, int NR, int MP, const FwdItem* items, int nitems, int wg,
-                              size_t sh, bool recompute, hipStream_t s) {
+scp_status launch_rk4_batched(int d, int NR, int MP, bool rf, const FwdItem* items, int nitems,
+                              int wg, size_t sh, bool recompute, hipStream_t s) {
   hipError_t e = dispatch(d, NR, MP, [&](auto L) {
-    return decltype(L)::batched(items, nitems, wg, sh, recompute, s);
+    return decltype(L)::batched(items, nitems, wg, sh, recompute, rf, s);
   });
   if (e != hipSuccess) return fail(SCP_EHIP, std::string("batched rk4 launch: ") + hipGetErrorString(e));
   return SCP_OK;

@@ -26,6 +26,9 @@ hipError_t launch_tables_impl(int d, int nslots, int npairs, int ndrives, int ng
                               const int* smode, const int* pmode, float2* optab, int block_q,
                               const void* drives, const double* par, float* ctab, float* dctab,
                               double* dctab64, double* ctab64, hipStream_t s);
+hipError_t launch_phase_table(int d, int NT, int NR, int RB, int thr, int row, int nsteps,
+                              double h, const double* frames, const int* tmode, const int* rmode,
+                              float2* ph, hipStream_t s);
 size_t drive_static_size();
 void pack_drive_static(void* dst, int k, int env, int npar, int par0, int group, double omega,
                        double phase, double sigma);
@@ -454,6 +457,16 @@ scp_status make_plan(scp_system* sys) {
   }
   for (int i = 0; i < d * d; ++i) sys->pairW_host.push_back(0.0);   // zero pair operator
   sys->pair_mode_host.push_back(0);
+  // real frame: every single-mode operator and every pair operator real, and
+  // one pair term per position pair
+  bool real = P.MP == 1;
+  for (size_t s = 0; s < sys->slot_mode.size(); ++s)
+    for (int i = 0; i < d * d; ++i)
+      real = real && sys->modes[sys->slot_mode[s]].ops[sys->slot_op[s]][i].imag() == 0.0;
+  for (const cplx& v : sys->pairW_host) real = real && v.imag() == 0.0;
+  P.real_frame = real ? 1 : 0;
+  P.ph_thr = (P.RB + 7) / 8 * 8;
+  P.ph_row = (P.ph_thr + P.NT * d + 7) / 8 * 8;
   return SCP_OK;
 }
 
@@ -526,6 +539,32 @@ scp_status build_tables(scp_system* sys, hipStream_t st) {
                             (const int*)bsm.p, (const int*)bpm.p, sys->d_ops, P.block_q, bdr.p,
                             (const double*)bpar.p, sys->d_ctab, sys->d_dctab, sys->d_dctab64,
                             sys->d_ctab64, st));
+  DevBuf bmodes;
+  if (P.real_frame) {
+    // modes at the thread positions (by natural stride) and at the register
+    // positions of the base layout
+    const int base = P.L - 1;
+    std::vector<int> modes(P.NT + P.NR, 0);
+    for (int k = 0; k < P.NT; ++k)
+      for (int m = 0; m < N; ++m) {
+        int64_t st_m = 1;
+        for (int q = m + 1; q < N; ++q) st_m *= d;
+        if (st_m == P.tstride[base][k]) modes[k] = m;
+      }
+    for (int p = 0; p < P.NR; ++p) modes[P.NT + p] = P.lmode[base][p];
+    HIPCHK(hipMalloc(&bmodes.p, modes.size() * sizeof(int)));
+    HIPCHK(hipMemcpyAsync(bmodes.p, modes.data(), modes.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMalloc(&sys->d_ph, nq * P.ph_row * sizeof(float2)));
+    // the operators at t = 0 (the table's block 0 rounds them the same way)
+    std::vector<float> rops(P.block_q, 0.f);
+    for (size_t i = 0; i < sops.size(); ++i) rops[i] = (float)sops[i].x;
+    for (size_t i = 0; i < pops.size(); ++i) rops[P.off_pair + i] = (float)pops[i].x;
+    HIPCHK(hipMalloc(&sys->d_rops, rops.size() * sizeof(float)));
+    HIPCHK(hipMemcpyAsync(sys->d_rops, rops.data(), rops.size() * sizeof(float), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_phase_table(d, P.NT, P.NR, P.RB, P.ph_thr, P.ph_row, sys->n_steps, sys->h,
+                              (const double*)bf.p, (const int*)bmodes.p,
+                              (const int*)bmodes.p + P.NT, sys->d_ph, st));
+  }
   HIPCHK(hipStreamSynchronize(st));
   return SCP_OK;
 }
@@ -838,6 +877,8 @@ void scp_destroy(scp_system* sys) {
   if (sys->d_dctab) (void)hipFree(sys->d_dctab);
   if (sys->d_dctab64) (void)hipFree(sys->d_dctab64);
   if (sys->d_ctab64) (void)hipFree(sys->d_ctab64);
+  if (sys->d_ph) (void)hipFree(sys->d_ph);
+  if (sys->d_rops) (void)hipFree(sys->d_rops);
   if (sys->d_scratch) (void)hipFree(sys->d_scratch);
   delete sys;
 }

@@ -31,7 +31,7 @@
 
 namespace scp {
 
-scp_status launch_rk4_batched(int d, int NR, int MP, const FwdItem* items, int nitems, int wg,
+scp_status launch_rk4_batched(int d, int NR, int MP, bool rf, const FwdItem* items, int nitems, int wg,
                               size_t sh, bool recompute, hipStream_t s);
 scp_status launch_adjoint_batched(int d, int NR, int MP, const AdjItem* items, int nitems, int wg,
                                   size_t sh, hipStream_t s);
@@ -335,18 +335,19 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
   if (!sv->active.empty()) {
     // 2. one chunk for everyone, one launch per (kind, size class)
     struct Work { Request* r; int n0, n1, s_hi, s_lo; };
-    std::map<std::tuple<int, int, int, int>, std::vector<Work>> classes;   // (kind, d, NR, MP)
+    // (kind, d, NR, MP, real frame)
+    std::map<std::tuple<int, int, int, int, int>, std::vector<Work>> classes;
     for (Request* r : sv->active) {
       const Plan& P = r->sys->plan;
       const double per_wg_step = r->cost_step;
       const int steps = std::max(8, (int)(sv->chunk_work / per_wg_step));
       if (r->phase == 0) {
         const int n0 = r->n_done, n1 = std::min(r->sys->n_steps, n0 + steps);
-        classes[{0, P.d, P.NR, P.MP}].push_back({r, n0, n1, 0, 0});
+        classes[{0, P.d, P.NR, P.MP, P.real_frame}].push_back({r, n0, n1, 0, 0});
       } else {
         const int segs = std::max(1, steps / (4 * r->ce));
         const int s_hi = r->seg_next, s_lo = std::max(0, s_hi - segs + 1);
-        classes[{1, P.d, P.NR, P.MP}].push_back({r, 0, 0, s_hi, s_lo});
+        classes[{1, P.d, P.NR, P.MP, P.real_frame}].push_back({r, 0, 0, s_hi, s_lo});
       }
     }
     // staging: per class, the forward items, or per adjoint round (one segment
@@ -376,6 +377,7 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
       hipStream_t st = sv->work[ci++ % scp_server::kWork];
       const int kind = std::get<0>(kv.first), d = std::get<1>(kv.first), NR = std::get<2>(kv.first),
                 MP = std::get<3>(kv.first);
+      const bool rf = std::get<4>(kv.first) != 0;
       int wg = 64;
       size_t sh_f = 0, sh_a = 0;
       for (auto& w : kv.second) {
@@ -393,12 +395,12 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
             it[nit++] = FwdItem{r->sys->d_plan, r->sys->d_ops, r->sys->d_ctab,
                                 w.n0 == 0 ? r->psi : nullptr,
                                 w.n1 == r->sys->n_steps ? r->psi : nullptr, r->state_hi, r->lo,
-                                r->want_grad ? r->ckpt : nullptr, nullptr, nullptr, r->ce, r->S,
-                                cb, w.n0, w.n1, 0};
+                                r->want_grad ? r->ckpt : nullptr, nullptr, nullptr,
+                                r->sys->d_ph, r->sys->d_rops, r->ce, r->S, cb, w.n0, w.n1, 0};
         }
         void* dptr = nullptr;
         if (!stage(it, (size_t)nit * sizeof(FwdItem), st, &dptr)) return fail(SCP_EHIP, "item upload");
-        s = launch_rk4_batched(d, NR, MP, (const FwdItem*)dptr, nit, wg, sh_f, false, st);
+        s = launch_rk4_batched(d, NR, MP, rf, (const FwdItem*)dptr, nit, wg, sh_f, false, st);
         if (s != SCP_OK) return s;
       } else {
         // round j: segment s_hi - j of every request that still has one this tick
@@ -415,12 +417,12 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
             for (int cb = 0; cb < r->nwg; ++cb)
               fi[nf++] = FwdItem{r->sys->d_plan, r->sys->d_ops, r->sys->d_ctab, nullptr, nullptr,
                                  nullptr, r->lo, nullptr,
-                                 r->ckpt + (size_t)seg * r->S * r->sys->D, r->segbuf, 1, r->S, cb,
-                                 n0, n1, 0};
+                                 r->ckpt + (size_t)seg * r->S * r->sys->D, r->segbuf,
+                                 r->sys->d_ph, r->sys->d_rops, 1, r->S, cb, n0, n1, 0};
           }
           void* dptr = nullptr;
           if (!stage(fi, (size_t)nf * sizeof(FwdItem), st, &dptr)) return fail(SCP_EHIP, "item upload");
-          s = launch_rk4_batched(d, NR, MP, (const FwdItem*)dptr, nf, wg, sh_f, true, st);
+          s = launch_rk4_batched(d, NR, MP, rf, (const FwdItem*)dptr, nf, wg, sh_f, true, st);
           if (s != SCP_OK) return s;
           AdjItem* ai = (AdjItem*)((char*)sv->h_items + off);
           int na = 0;

@@ -61,6 +61,33 @@ __global__ void optable_kernel(TabStatic ts, const double* __restrict__ frames,
   }
 }
 
+// Frame phases of the real-frame stepper, row q (t_q = q h / 2): entry r < RB
+// is exp(i sum_p f_{a_p} t) over the register positions p of register r
+// (position 0 most significant); entry thr + k*d + a is exp(i f_a t) of the
+// mode at base-layout thread position k; the rest is padding.  Angles summed
+// and reduced in FP64.
+__global__ void phase_kernel(int d, int NT, int NR, int RB, int thr, int row, double h,
+                             const double* __restrict__ frames, const int* __restrict__ tmode,
+                             const int* __restrict__ rmode, float2* __restrict__ out) {
+  const int q = blockIdx.x;
+  const double t = q * (0.5 * h);
+  for (int e = threadIdx.x; e < row; e += blockDim.x) {
+    double f = 0.0;
+    if (e < RB) {
+      int rr = e;
+      for (int p = NR - 1; p >= 0; --p) {
+        f += frames[rmode[p] * 8 + rr % d];
+        rr /= d;
+      }
+    } else if (e >= thr && e < thr + NT * d) {
+      f = frames[tmode[(e - thr) / d] * 8 + (e - thr) % d];
+    }
+    double sn, cs;
+    sincos(reduce_angle(f * t), &sn, &cs);
+    out[(size_t)q * row + e] = make_float2((float)cs, (float)sn);
+  }
+}
+
 struct DriveStatic {
   int env, npar, par0, group;
   double omega, phase, sigma;
@@ -128,6 +155,14 @@ hipError_t launch_tables_impl(int d, int nslots, int npairs, int ndrives, int ng
     e = hipGetLastError();
   }
   return e;
+}
+
+hipError_t launch_phase_table(int d, int NT, int NR, int RB, int thr, int row, int nsteps,
+                              double h, const double* frames, const int* tmode, const int* rmode,
+                              float2* ph, hipStream_t s) {
+  hipLaunchKernelGGL(phase_kernel, dim3(2 * nsteps + 1), dim3(64), 0, s, d, NT, NR, RB, thr, row,
+                     h, frames, tmode, rmode, ph);
+  return hipGetLastError();
 }
 
 size_t drive_static_size() { return sizeof(DriveStatic); }
