@@ -19,6 +19,12 @@
 // wave-reduced, and accumulated in FP64 per wave, one target per lane.
 // No atomics: the result is bitwise reproducible.
 //
+// Real frame (every operator real): kb and y are rotated by D(t)^dag at each
+// stage, the items use the un-rotated real operators, and the folds with the
+// real derivative tables need only the imaginary parts of G, H and K; yb is
+// rotated back by D(t).  The frame is held fixed, so <kb, D dR D^dag y> =
+// <D^dag kb, dR D^dag y> and the sensitivities are unchanged.
+//
 // Per segment, last to first, a recompute launch (the forward stepper started
 // from the segment's checkpoint) writes the four stage inputs of every step
 // to the segment buffer, then one launch of the kernel here walks the segment
@@ -165,6 +171,106 @@ __device__ __forceinline__ void mode_reduce(const Vec<RB>& kb, const Vec<RB>& y,
   });
 }
 
+// Real frame (real operators, vectors rotated by D(t)^dag): the same items
+// with real O and W; the folds with real tables need only Im G, Im H, Im K.
+template <int d, int NR, int PI, int PJ, int RB>
+__device__ __forceinline__ void group_pair_adj_real(const ROp<d>& O, const ROp<d>& W, float c,
+                                                    const Vec<RB>& kb, const Vec<RB>& y,
+                                                    Vec<RB>& yb, Mat<d>& G, Mat<d>& H) {
+  using C = Cfg<d, NR>;
+  constexpr int si_ = C::stride(PI);
+  constexpr int sj_ = C::stride(PJ);
+  static_for<RB / (d * d)>([&](auto B) {
+    constexpr int r0 = fiber_base<d, NR, PI, PJ>(decltype(B)::value);
+    float tr[d][d], ti[d][d];
+#pragma unroll
+    for (int aj = 0; aj < d; ++aj)
+#pragma unroll
+      for (int ai = 0; ai < d; ++ai) {
+        float sr = 0.f, sim = 0.f;
+#pragma unroll
+        for (int b = 0; b < d; ++b) {
+          const float o = O.v[ai * d + b];
+          sr = fmaf(o, kb.re[r0 + b * si_ + aj * sj_], sr);
+          sim = fmaf(o, kb.im[r0 + b * si_ + aj * sj_], sim);
+        }
+        tr[ai][aj] = sr;
+        ti[ai][aj] = sim;
+      }
+#pragma unroll
+    for (int ai = 0; ai < d; ++ai)
+#pragma unroll
+      for (int aj = 0; aj < d; ++aj) {
+        float sr = fmaf(c, tr[ai][aj], yb.re[r0 + ai * si_ + aj * sj_]);
+        float sim = fmaf(c, ti[ai][aj], yb.im[r0 + ai * si_ + aj * sj_]);
+#pragma unroll
+        for (int b = 0; b < d; ++b) {
+          const float w = W.v[aj * d + b];
+          sr = fmaf(w, tr[ai][b], sr);
+          sim = fmaf(w, ti[ai][b], sim);
+        }
+        yb.re[r0 + ai * si_ + aj * sj_] = sr;
+        yb.im[r0 + ai * si_ + aj * sj_] = sim;
+      }
+    // Im G_ab += sum_ai Im(conj(T[ai][a]) y[ai][b])
+#pragma unroll
+    for (int a = 0; a < d; ++a)
+#pragma unroll
+      for (int b = 0; b < d; ++b) {
+        float gi = G.im[a * d + b];
+#pragma unroll
+        for (int ai = 0; ai < d; ++ai) {
+          gi = fmaf(tr[ai][a], y.im[r0 + ai * si_ + b * sj_], gi);
+          gi = fmaf(-ti[ai][a], y.re[r0 + ai * si_ + b * sj_], gi);
+        }
+        G.im[a * d + b] = gi;
+      }
+    // X'[ai][aj] = sum_b W[aj][b] kb[ai][b]; Im H_ab += sum_aj Im(conj(X'[a][aj]) y[b][aj])
+#pragma unroll
+    for (int ai = 0; ai < d; ++ai)
+#pragma unroll
+      for (int aj = 0; aj < d; ++aj) {
+        float sr = 0.f, sim = 0.f;
+#pragma unroll
+        for (int b = 0; b < d; ++b) {
+          const float w = W.v[aj * d + b];
+          sr = fmaf(w, kb.re[r0 + ai * si_ + b * sj_], sr);
+          sim = fmaf(w, kb.im[r0 + ai * si_ + b * sj_], sim);
+        }
+        tr[ai][aj] = sr;
+        ti[ai][aj] = sim;
+      }
+#pragma unroll
+    for (int a = 0; a < d; ++a)
+#pragma unroll
+      for (int b = 0; b < d; ++b) {
+        float hi = H.im[a * d + b];
+#pragma unroll
+        for (int aj = 0; aj < d; ++aj) {
+          hi = fmaf(tr[a][aj], y.im[r0 + b * si_ + aj * sj_], hi);
+          hi = fmaf(-ti[a][aj], y.re[r0 + b * si_ + aj * sj_], hi);
+        }
+        H.im[a * d + b] = hi;
+      }
+  });
+}
+
+// Im K_ab += sum over fibers along P of Im(conj(kb[a]) y[b])
+template <int d, int NR, int P, int RB>
+__device__ __forceinline__ void mode_reduce_real(const Vec<RB>& kb, const Vec<RB>& y, Mat<d>& K) {
+  using C = Cfg<d, NR>;
+  constexpr int st = C::stride(P);
+  static_for<RB / d>([&](auto B) {
+    constexpr int r0 = fiber_base<d, NR, P, -1>(decltype(B)::value);
+#pragma unroll
+    for (int a = 0; a < d; ++a)
+#pragma unroll
+      for (int b = 0; b < d; ++b)
+        K.im[a * d + b] = fmaf(kb.re[r0 + a * st], y.im[r0 + b * st],
+                               fmaf(-kb.im[r0 + a * st], y.re[r0 + b * st], K.im[a * d + b]));
+  });
+}
+
 // Im( sum_ab X_ab M_ab ) for a uniform operator X from the table
 template <int d>
 __device__ __forceinline__ float im_dot(kptr<c32> X, const Mat<d>& M) {
@@ -174,6 +280,20 @@ __device__ __forceinline__ float im_dot(kptr<c32> X, const Mat<d>& M) {
     s = fmaf(X[i].x, M.im[i], fmaf(X[i].y, M.re[i], s));
   }
   return s;
+}
+
+// Im( sum_ab X_ab M_ab ) with X at element offset off of the stage's complex
+// table, or (real frame) of the real table.
+template <int d, bool RF>
+__device__ __forceinline__ float tdot(kptr<c32> ops, kptr<float> rops, int off, const Mat<d>& M) {
+  if constexpr (RF) {
+    float s = 0.f;
+#pragma unroll
+    for (int i = 0; i < d * d; ++i) s = fmaf(rops[off + i], M.im[i], s);
+    return s;
+  } else {
+    return im_dot<d>(ops + off, M);
+  }
 }
 
 // Sum over the 64 lanes (the result is uniform): a butterfly inside each row
@@ -222,11 +342,11 @@ __device__ __forceinline__ void fold(LaneAcc& A, double* accw, int target, float
 
 // One adjoint stage: yb = i V(t) kb (base layout out), with the parameter
 // folds of this stage.  kb and y enter in the base layout.
-template <int d, int NR, int MP, int RB>
+template <int d, int NR, int MP, int RB, bool RF>
 __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
                                           int vstride, bool lds_ok, int tc, int lane,
                                           LaneAcc& A, double* accw, kptr<c32> ops,
-                                          kptr<float> cq,
+                                          kptr<float> rops, kptr<float> cq,
                                           kptr<float> dcq, Vec<RB>& kb, Vec<RB>& y,
                                           Vec<RB>& yb) {
   constexpr int dd = d * d;
@@ -256,14 +376,21 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
       static_for<MP>([&](auto Mm) {
         constexpr int m = decltype(Mm)::value;
         const auto& C = P->cpair[l][p][m];
-        Op<d> O, W;
         const int c_slot = uni(C.slot), c_pair = uni(C.pair);
-        load_op<d>(ops + c_slot * dd, O);
-        load_op<d>(ops + uni(P->off_pair + c_pair * dd), W);
         Mat<d> G, H;
         zero(G);
         zero(H);
-        group_pair_adj<d, NR, p, p + 1>(O, W, coef(cq, uni(C.cidx)), kb, y, yb, G, H);
+        if constexpr (RF) {
+          ROp<d> O, W;
+          load_rop<d>(rops + c_slot * dd, O);
+          load_rop<d>(rops + uni(P->off_pair + c_pair * dd), W);
+          group_pair_adj_real<d, NR, p, p + 1>(O, W, coef(cq, uni(C.cidx)), kb, y, yb, G, H);
+        } else {
+          Op<d> O, W;
+          load_op<d>(ops + c_slot * dd, O);
+          load_op<d>(ops + uni(P->off_pair + c_pair * dd), W);
+          group_pair_adj<d, NR, p, p + 1>(O, W, coef(cq, uni(C.cidx)), kb, y, yb, G, H);
+        }
         const int mi = uni(C.mode_i);
         if (mi >= 0) {
           // couplings of this pair term; the partner's (position p + 1) and the
@@ -274,15 +401,15 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
           for (int q = 0; q < nq; ++q) {
             const int e = uni(P->pair_coup[pr][q]);
             const int sj = uni(P->pair_pslot[pr][q]);
-            fold(A, accw, npulse + 3 * N + e, im_dot<d>(ops + sj * dd, G), lane);
+            fold(A, accw, npulse + 3 * N + e, tdot<d, RF>(ops, rops, sj * dd, G), lane);
             const float ge = unif(P->coup_g[e]);
 #pragma unroll
             for (int th = 0; th < 3; ++th)
-              dacc[(p + 1) * 3 + th] += ge * im_dot<d>(ops + offd + (sj * 3 + th) * dd, G);
+              dacc[(p + 1) * 3 + th] += ge * tdot<d, RF>(ops, rops, offd + (sj * 3 + th) * dd, G);
           }
 #pragma unroll
           for (int th = 0; th < 3; ++th)
-            dacc[p * 3 + th] += im_dot<d>(ops + offd + (c_slot * 3 + th) * dd, H);
+            dacc[p * 3 + th] += tdot<d, RF>(ops, rops, offd + (c_slot * 3 + th) * dd, H);
         }
       });
     });
@@ -290,15 +417,23 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
       static_for<NR>([&](auto Pp) {
         constexpr int p = decltype(Pp)::value;
         const auto& C1 = P->csingle[l][p];
-        Op<d> O;
-        load_op<d>(ops + uni(C1.slot) * dd, O);
         const float c = coef(cq, uni(C1.cidx));
+        if constexpr (RF) {
+          ROp<d> O;
+          load_rop<d>(rops + uni(C1.slot) * dd, O);
 #pragma unroll
-        for (int i = 0; i < dd; ++i) {
-          O.re[i] *= c;
-          O.im[i] *= c;
+          for (int i = 0; i < dd; ++i) O.v[i] *= c;
+          contract_acc_real<d, NR, p>(O, kb, yb);
+        } else {
+          Op<d> O;
+          load_op<d>(ops + uni(C1.slot) * dd, O);
+#pragma unroll
+          for (int i = 0; i < dd; ++i) {
+            O.re[i] *= c;
+            O.im[i] *= c;
+          }
+          contract_acc<d, NR, p>(O, kb, yb);
         }
-        contract_acc<d, NR, p>(O, kb, yb);
       });
     }
     if (uni(P->has_diag[l])) {
@@ -315,7 +450,10 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
         if (m >= 0) {
           Mat<d> K;
           zero(K);
-          mode_reduce<d, NR, p>(kb, y, K);
+          if constexpr (RF)
+            mode_reduce_real<d, NR, p>(kb, y, K);
+          else
+            mode_reduce<d, NR, p>(kb, y, K);
           float dev[3] = {0.f, 0.f, 0.f};
 #pragma unroll
           for (int th = 0; th < 3; ++th)
@@ -326,7 +464,7 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
           for (int kk = k0; kk < k1; ++kk) {
             const auto& R = P->drives[uni(P->mdrv[kk])];
             const int rslot = uni(R.slot);
-            const float s_im = wave_sum(im_dot<d>(ops + rslot * dd, K));
+            const float s_im = wave_sum(tdot<d, RF>(ops, rops, rslot * dd, K));
             const int par0 = uni(R.par0), npar = uni(R.npar);
             for (int q = 0; q < npar; ++q)
               acc_add(A, accw, par0 + q, (double)dcq[par0 + q] * (double)s_im, lane);
@@ -334,7 +472,7 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
               const float c = cq[uni(R.cidx)];
 #pragma unroll
               for (int th = 0; th < 3; ++th)
-                dev[th] = fmaf(c, im_dot<d>(ops + offd + (rslot * 3 + th) * dd, K), dev[th]);
+                dev[th] = fmaf(c, tdot<d, RF>(ops, rops, offd + (rslot * 3 + th) * dd, K), dev[th]);
             }
           }
 #pragma unroll
@@ -372,12 +510,19 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
 // costate starts from the cotangent and the accumulators from zero; else both
 // continue from lamstate / part exactly (chunked runs are bitwise identical to
 // one launch).
-template <int d, int NR, int MP>
+// RF: the real frame (vectors rotated by D(t)^dag at every stage, real
+// operator and derivative tables; yb rotated back).
+template <int d, int NR, int MP, bool RF>
 __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   constexpr int RB = Cfg<d, NR>::RB;
   extern __shared__ c32 lds[];
   kptr<Plan> P = kconst(I.P);
   kptr<c32> optab = kconst((const c32*)I.optab);
+  kptr<c32> ph = kconst((const c32*)I.ph);
+  kptr<float> rops = kconst(I.rops);
+  const int NT = uni(P->NT);
+  const int prow = RF ? uni(P->ph_row) : 0;
+  const int pthr = RF ? uni(P->ph_thr) : 0;
   kptr<float> ctab = kconst(I.ctab);
   kptr<float> dctab = kconst(I.dctab);
   const c32x2* __restrict__ ckpt = (const c32x2*)I.ckpt;
@@ -441,7 +586,9 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
     // walk the segment back.  As in the stepper, one stage ahead the first
     // threads of each column touch every 64-byte line of the next (earlier)
     // stage's operator block, so its scalar reads find the lines in L2.
-    const int pf_lines = (bq * (int)sizeof(c32) + 63) / 64;
+    const int pf_lines = RF ? (prow * (int)sizeof(c32) + 63) / 64 : (bq * (int)sizeof(c32) + 63) / 64;
+    const kptr<c32> pf_base = RF ? ph : optab;
+    const int pf_stride = RF ? prow : bq;
     for (int n = stop - 1; n >= start; --n) {
       Vec<RB> kb, y, yb;
 #pragma unroll
@@ -470,16 +617,43 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
             y.im[r] = v.y;
           }
         }
-        auto ops = optab + (size_t)stage_q(n, s) * bq;
+        kptr<c32> prw = ph + (size_t)stage_q(n, s) * prow;
+        if constexpr (RF) {
+          // into the frame: kb <- D^dag kb, y <- D^dag y
+          const c32 pt = thread_phase<d>(prw + pthr, NT, tc);
+#pragma unroll
+          for (int r = 0; r < RB; ++r) {
+            const c32 e = elem_phase<true>(pt, (kptr<c32x8>)prw, r);
+            float xr = kb.re[r], xi = kb.im[r];
+            kb.re[r] = e.x * xr - e.y * xi;
+            kb.im[r] = fmaf(e.x, xi, e.y * xr);
+            xr = y.re[r];
+            xi = y.im[r];
+            y.re[r] = e.x * xr - e.y * xi;
+            y.im[r] = fmaf(e.x, xi, e.y * xr);
+          }
+        }
+        auto ops = optab + (RF ? 0 : (size_t)stage_q(n, s) * bq);
         auto cq = ctab + (size_t)stage_c(n, s) * ng;
         auto dcq = dctab + (size_t)stage_c(n, s) * npl;
         float pf = 0.f;
         if (tc < pf_lines) {
           const int qn = s > 0 ? stage_q(n, s - 1) : stage_q(n - 1, 3);   // >= 0
-          pf = ((const float*)(uintptr_t)(optab + (size_t)qn * bq))[tc * 16];
+          pf = ((const float*)(uintptr_t)(pf_base + (size_t)qn * pf_stride))[tc * 16];
         }
-        adj_stage<d, NR, MP, RB>(P, lds, cbase, vstride, lds_ok, tc, lane, A, accw, ops, cq, dcq,
-                                 kb, y, yb);
+        adj_stage<d, NR, MP, RB, RF>(P, lds, cbase, vstride, lds_ok, tc, lane, A, accw, ops, rops,
+                                     cq, dcq, kb, y, yb);
+        if constexpr (RF) {
+          // back to the interaction picture: yb <- D yb
+          const c32 pt = thread_phase<d>(prw + pthr, NT, tc);
+#pragma unroll
+          for (int r = 0; r < RB; ++r) {
+            const c32 e = elem_phase<false>(pt, (kptr<c32x8>)prw, r);
+            const float xr = yb.re[r], xi = yb.im[r];
+            yb.re[r] = e.x * xr - e.y * xi;
+            yb.im[r] = fmaf(e.x, xi, e.y * xr);
+          }
+        }
         pf_sink += pf;
         if (active) {
 #pragma unroll
@@ -523,15 +697,15 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   for (int i = threadIdx.x; i < 4 * nacc; i += blockDim.x) partb[i] = i < nwaves * nacc ? acc[i] : 0.0;
 }
 
-template <int d, int NR, int MP>
+template <int d, int NR, int MP, bool RF>
 __global__ void __launch_bounds__(WG_THREADS) adjoint_kernel(AdjItem I) {
   I.cb = blockIdx.x;
-  adjoint_block<d, NR, MP>(I);
+  adjoint_block<d, NR, MP, RF>(I);
 }
 
-template <int d, int NR, int MP>
+template <int d, int NR, int MP, bool RF>
 __global__ void __launch_bounds__(WG_THREADS) adjoint_batched_kernel(const AdjItem* __restrict__ items) {
-  adjoint_block<d, NR, MP>(items[blockIdx.x]);
+  adjoint_block<d, NR, MP, RF>(items[blockIdx.x]);
 }
 
 namespace {
@@ -540,22 +714,42 @@ size_t adj_lds_bytes(const Plan& P) {
   return sizeof(c32) * 3 * (size_t)P.CPW * P.D + sizeof(double) * 4 * (size_t)P.nacc;
 }
 
-template <int d, int NR, int MP>
-hipError_t run_adj(const AdjItem& I0, int nwg, int wg, size_t sh, hipStream_t s) {
-  if (sh > 160 * 1024) return hipErrorInvalidValue;
-  hipFuncSetAttribute((const void*)adjoint_kernel<d, NR, MP>,
+template <int d, int NR, int MP, bool RF>
+hipError_t run_adj1(const AdjItem& I0, int nwg, int wg, size_t sh, hipStream_t s) {
+  hipFuncSetAttribute((const void*)adjoint_kernel<d, NR, MP, RF>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL((adjoint_kernel<d, NR, MP>), dim3(nwg), dim3(wg), sh, s, I0);
+  hipLaunchKernelGGL((adjoint_kernel<d, NR, MP, RF>), dim3(nwg), dim3(wg), sh, s, I0);
+  return hipGetLastError();
+}
+
+// the real-frame kernels exist for one pair term per position pair
+template <int d, int NR, int MP>
+hipError_t run_adj(const AdjItem& I0, int nwg, int wg, size_t sh, bool rf, hipStream_t s) {
+  if (sh > 160 * 1024) return hipErrorInvalidValue;
+  if constexpr (MP == 1) {
+    if (rf) return run_adj1<d, NR, MP, true>(I0, nwg, wg, sh, s);
+  }
+  if (rf) return hipErrorInvalidValue;
+  return run_adj1<d, NR, MP, false>(I0, nwg, wg, sh, s);
+}
+
+template <int d, int NR, int MP, bool RF>
+hipError_t run_adj_batched1(const AdjItem* items, int nitems, int wg, size_t sh, hipStream_t s) {
+  hipFuncSetAttribute((const void*)adjoint_batched_kernel<d, NR, MP, RF>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  hipLaunchKernelGGL((adjoint_batched_kernel<d, NR, MP, RF>), dim3(nitems), dim3(wg), sh, s, items);
   return hipGetLastError();
 }
 
 template <int d, int NR, int MP>
-hipError_t run_adj_batched(const AdjItem* items, int nitems, int wg, size_t sh, hipStream_t s) {
+hipError_t run_adj_batched(const AdjItem* items, int nitems, int wg, size_t sh, bool rf,
+                           hipStream_t s) {
   if (sh > 160 * 1024) return hipErrorInvalidValue;
-  hipFuncSetAttribute((const void*)adjoint_batched_kernel<d, NR, MP>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL((adjoint_batched_kernel<d, NR, MP>), dim3(nitems), dim3(wg), sh, s, items);
-  return hipGetLastError();
+  if constexpr (MP == 1) {
+    if (rf) return run_adj_batched1<d, NR, MP, true>(items, nitems, wg, sh, s);
+  }
+  if (rf) return hipErrorInvalidValue;
+  return run_adj_batched1<d, NR, MP, false>(items, nitems, wg, sh, s);
 }
 
 }  // namespace
@@ -582,10 +776,12 @@ scp_status launch_adjoint_impl(const scp_system* sys, const void* ckpt, const vo
     if (st != SCP_OK) return st;
     AdjItem I{sys->d_plan, sys->d_ops, sys->d_ctab, sys->d_dctab, (const float4*)ckpt,
               (const float2*)lamT, (float2*)segbuf, (float2*)lo, (float2*)sum,
-              (float2*)lamstate, part, ce, nckpt, S, 0, seg, seg, seg == nckpt - 1 ? 1 : 0, 0};
+              (float2*)lamstate, part, sys->d_ph, sys->d_rops, ce, nckpt, S, 0, seg, seg,
+              seg == nckpt - 1 ? 1 : 0, 0};
     hipError_t e = hipErrorInvalidValue;
+    const bool rf = P.real_frame != 0;
 #define X(D_, NR_, MP_) \
-  if (d == D_ && NR == NR_ && MP == MP_) e = run_adj<D_, NR_, MP_>(I, nwg, P.WG, sh, s);
+  if (d == D_ && NR == NR_ && MP == MP_) e = run_adj<D_, NR_, MP_>(I, nwg, P.WG, sh, rf, s);
     SCP_ADJ_ALL(X)
 #undef X
     if (e != hipSuccess) return fail(SCP_EHIP, std::string("adjoint launch: ") + hipGetErrorString(e));
@@ -593,11 +789,11 @@ scp_status launch_adjoint_impl(const scp_system* sys, const void* ckpt, const vo
   return SCP_OK;
 }
 
-scp_status launch_adjoint_batched(int d, int NR, int MP, const AdjItem* items, int nitems, int wg,
-                                  size_t sh, hipStream_t s) {
+scp_status launch_adjoint_batched(int d, int NR, int MP, bool rf, const AdjItem* items, int nitems,
+                                  int wg, size_t sh, hipStream_t s) {
   hipError_t e = hipErrorInvalidValue;
 #define X(D_, NR_, MP_) \
-  if (d == D_ && NR == NR_ && MP == MP_) e = run_adj_batched<D_, NR_, MP_>(items, nitems, wg, sh, s);
+  if (d == D_ && NR == NR_ && MP == MP_) e = run_adj_batched<D_, NR_, MP_>(items, nitems, wg, sh, rf, s);
   SCP_ADJ_ALL(X)
 #undef X
   if (e != hipSuccess)

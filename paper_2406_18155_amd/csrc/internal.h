@@ -115,6 +115,8 @@ struct AdjItem {
   float2* sum;
   float2* lamstate;     // register-order costate carried between launches
   double* part;         // [column block][4 waves][nacc] FP64 accumulators
+  const float2* ph;     // real frame: phase table (as in FwdItem)
+  const float* rops;    // real frame: un-rotated operators and their derivatives
   int ce, nckpt, S, cb, seg_hi, seg_lo, first, pad;
 };
 

@@ -464,6 +464,10 @@ scp_status make_plan(scp_system* sys) {
     for (int i = 0; i < d * d; ++i)
       real = real && sys->modes[sys->slot_mode[s]].ops[sys->slot_op[s]][i].imag() == 0.0;
   for (const cplx& v : sys->pairW_host) real = real && v.imag() == 0.0;
+  for (size_t s = 0; s < sys->slot_mode.size(); ++s)   // and their parameter derivatives
+    for (int th = 0; th < 3; ++th)
+      for (int i = 0; i < d * d; ++i)
+        real = real && sys->modes[sys->slot_mode[s]].dops[th][sys->slot_op[s]][i].imag() == 0.0;
   P.real_frame = real ? 1 : 0;
   P.ph_thr = (P.RB + 7) / 8 * 8;
   P.ph_row = (P.ph_thr + P.NT * d + 7) / 8 * 8;
@@ -559,6 +563,7 @@ scp_status build_tables(scp_system* sys, hipStream_t st) {
     std::vector<float> rops(P.block_q, 0.f);
     for (size_t i = 0; i < sops.size(); ++i) rops[i] = (float)sops[i].x;
     for (size_t i = 0; i < pops.size(); ++i) rops[P.off_pair + i] = (float)pops[i].x;
+    for (size_t i = 0; i < dops.size(); ++i) rops[P.off_dslot + i] = (float)dops[i].x;
     HIPCHK(hipMalloc(&sys->d_rops, rops.size() * sizeof(float)));
     HIPCHK(hipMemcpyAsync(sys->d_rops, rops.data(), rops.size() * sizeof(float), hipMemcpyHostToDevice, st));
     HIPCHK(launch_phase_table(d, P.NT, P.NR, P.RB, P.ph_thr, P.ph_row, sys->n_steps, sys->h,

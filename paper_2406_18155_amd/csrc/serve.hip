@@ -33,7 +33,7 @@ namespace scp {
 
 scp_status launch_rk4_batched(int d, int NR, int MP, bool rf, const FwdItem* items, int nitems, int wg,
                               size_t sh, bool recompute, hipStream_t s);
-scp_status launch_adjoint_batched(int d, int NR, int MP, const AdjItem* items, int nitems, int wg,
+scp_status launch_adjoint_batched(int d, int NR, int MP, bool rf, const AdjItem* items, int nitems, int wg,
                                   size_t sh, hipStream_t s);
 size_t adjoint_lds_bytes(const Plan& P);
 
@@ -433,11 +433,11 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
             for (int cb = 0; cb < r->nwg; ++cb)
               ai[na++] = AdjItem{r->sys->d_plan, r->sys->d_ops, r->sys->d_ctab, r->sys->d_dctab,
                                  r->ckpt, r->cot, r->segbuf, r->lo, r->sum, r->lamstate, r->part,
-                                 r->ce, r->nckpt, r->S, cb, seg, seg, seg == r->nckpt - 1 ? 1 : 0,
-                                 0};
+                                 r->sys->d_ph, r->sys->d_rops, r->ce, r->nckpt, r->S, cb, seg, seg,
+                                 seg == r->nckpt - 1 ? 1 : 0, 0};
           }
           if (!stage(ai, (size_t)na * sizeof(AdjItem), st, &dptr)) return fail(SCP_EHIP, "item upload");
-          s = launch_adjoint_batched(d, NR, MP, (const AdjItem*)dptr, na, wg, sh_a, st);
+          s = launch_adjoint_batched(d, NR, MP, rf, (const AdjItem*)dptr, na, wg, sh_a, st);
           if (s != SCP_OK) return s;
         }
       }
