@@ -375,11 +375,11 @@ def main():
                      "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": fwd_flop / (fwd_ms * 1e-3) / PEAK_FP32,
                      "traffic": measured_traffic("rk4_ring8_d3"),
-                     "kernel": "rk4_kernel<3,3,1,false>", "launch_ms": fwd_ms,
+                     "kernel": "rk4_kernel<3,3,1,false,true>", "launch_ms": fwd_ms,
                      "algorithmic_flop_per_launch": fwd_flop},
         "forward": {"ms": fwd_ms, "steps_dim2_per_s": N * D * S / (fwd_ms * 1e-3)},
-        # per segment a recompute launch (rk4_kernel<3,3,1,true>) and a reverse
-        # launch (adjoint_kernel<3,3,1>); algorithmic work of the whole call
+        # per segment a recompute launch (rk4_kernel<3,3,1,true,true>) and a reverse
+        # launch (adjoint_kernel<3,3,1,true>); algorithmic work of the whole call
         "adjoint": {"ms": adj_ms, "tflops": adj_flop / (adj_ms * 1e-3) / 1e12,
                     "frac": adj_flop / (adj_ms * 1e-3) / PEAK_FP32,
                     "algorithmic_flop": adj_flop},
