@@ -152,6 +152,21 @@ scp_status scp_system_mode(const scp_system* sys, int32_t mode, double* eps, dou
                            double* ops);
 scp_status scp_system_carriers(const scp_system* sys, double* omega);
 
+/* Evaluation of the FP32 stage generator.  With D(t) = exp(i H_f t) the
+ * interaction-picture generator is D(t) R(t) D(t)^dag, R the sum of the
+ * un-rotated local terms (Sec. 2.1; App. B).  When every single-mode operator,
+ * pair operator and operator derivative is real and each register position
+ * pair holds one pair term (transmon devices), the FP32 path applies R with
+ * real operators between diagonal rotations of the stage vectors (the "real
+ * frame", *real_frame = 1); otherwise it applies the rotated complex
+ * operators (*real_frame = 0).  Both evaluate the same map; they differ by
+ * FP32 rounding.  scp_system_set_frame(sys, 0) makes a real-frame system use
+ * the complex evaluation, 1 restores the real frame (SCP_EINVAL if the
+ * system does not allow it).  Not while a call on the system is in flight;
+ * synchronous. */
+scp_status scp_system_frame(const scp_system* sys, int32_t* real_frame);
+scp_status scp_system_set_frame(scp_system* sys, int32_t real_frame);
+
 /* Workspace bytes a propagate (+ adjoint if with_grad) needs for opts. */
 scp_status scp_workspace_size(const scp_system* sys, const scp_solve_opts* opts, int32_t with_grad,
                               size_t* bytes);

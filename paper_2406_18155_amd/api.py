@@ -116,6 +116,17 @@ class System:
         check(lib().scp_system_carriers(self.handle, om))
         return np.array(om[: len(self.desc["drives"])])
 
+    @property
+    def real_frame(self):
+        """True if the FP32 path applies real operators between frame rotations."""
+        v = C.c_int32()
+        check(lib().scp_system_frame(self.handle, C.byref(v)))
+        return bool(v.value)
+
+    def set_real_frame(self, enable):
+        """Choose the real-frame (True) or the complex (False) evaluation."""
+        check(lib().scp_system_set_frame(self.handle, 1 if enable else 0))
+
     def opts(self, n_cols, precision=0, ckpt_every=0, with_ckpt=0):
         o = SolveOpts()
         o.n_cols, o.precision, o.ckpt_every, o.with_ckpt = int(n_cols), int(precision), \

@@ -169,6 +169,7 @@ struct scp_system {
   void* d_scratch = nullptr;    // small per-system scratch (adjoint partial sums)
   size_t scratch_bytes = 0;
   int device = 0;
+  bool real_ok = false;         // the real frame is allowed (tables built)
 };
 
 namespace scp {

@@ -544,6 +544,7 @@ scp_status build_tables(scp_system* sys, hipStream_t st) {
                             (const double*)bpar.p, sys->d_ctab, sys->d_dctab, sys->d_dctab64,
                             sys->d_ctab64, st));
   DevBuf bmodes;
+  sys->real_ok = P.real_frame != 0;
   if (P.real_frame) {
     // modes at the thread positions (by natural stride) and at the register
     // positions of the base layout
@@ -787,6 +788,23 @@ scp_status scp_system_mode(const scp_system* sys, int32_t mode, double* eps, dou
 scp_status scp_system_carriers(const scp_system* sys, double* omega) {
   if (!sys || !omega) return fail(SCP_EINVAL, "null argument");
   for (size_t k = 0; k < sys->drives.size(); ++k) omega[k] = sys->drives[k].omega;
+  return SCP_OK;
+}
+
+scp_status scp_system_frame(const scp_system* sys, int32_t* real_frame) {
+  if (!sys || !real_frame) return fail(SCP_EINVAL, "null argument");
+  *real_frame = sys->plan.real_frame;
+  return SCP_OK;
+}
+
+scp_status scp_system_set_frame(scp_system* sys, int32_t real_frame) {
+  g_err.clear();
+  if (!sys) return fail(SCP_EINVAL, "null argument");
+  if (real_frame != 0 && real_frame != 1) return fail(SCP_EINVAL, "real_frame must be 0 or 1");
+  if (real_frame && !sys->real_ok) return fail(SCP_EINVAL, "the system has complex operators");
+  sys->plan.real_frame = real_frame;
+  HIPCHK(hipMemcpy(&sys->d_plan->real_frame, &sys->plan.real_frame, sizeof(int32_t),
+                   hipMemcpyHostToDevice));
   return SCP_OK;
 }
 

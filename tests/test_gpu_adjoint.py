@@ -137,3 +137,55 @@ def test_config3_full_gradient_against_stored_oracle(scp):
     F, g = gpu_loss_and_grad(scp, desc)
     assert abs(F - ref["F"]) <= DF_TOL
     check_grad(g, np.array(ref["grad"]))
+
+
+def _loss_grad_frame(scp, desc, real_frame):
+    """F, gradient and U with the real-frame or the complex evaluation."""
+    g = scp.System(desc)
+    g.set_real_frame(real_frame)
+    assert g.real_frame == real_frame
+    psi0 = scp.basis_columns(g.D, desc["columns"])
+    opts = g.opts(psi0.shape[0], with_ckpt=1)
+    ws = g.workspace(opts, with_grad=True)
+    U = g.propagate(psi0, opts=opts, workspace=ws)
+    tgt = scp.Target(desc["comp_rows"], desc["comp_cols"], desc["target"])
+    cot = torch.empty_like(U)
+    F, _ = scp.fidelity(U, tgt, cotangent=cot)
+    grad = g.adjoint(cot, opts, ws)
+    Uc = U.cpu().numpy()
+    g.close()
+    return F, grad, Uc
+
+
+def test_frame_choice_follows_the_operators(scp):
+    """Transmon devices (real dressed n) take the real frame; fluxonium
+    devices (imaginary n) and complex raw operators keep the complex path,
+    and asking them for the real frame is an error."""
+    for desc, real in ((_ring(4, 3, 2.0, 20), True), (_short(si.config1(), 2.0, 20), True),
+                       (_chain(2, 5, 2.0, 20), False),
+                       (si.random_raw_system(5, [2, 2, 2], 3, 1.0, 20, env="gauss"), False)):
+        g = scp.System(desc)
+        assert g.real_frame == real
+        if not real:
+            with pytest.raises(scp.ScpError):
+                g.set_real_frame(True)
+        g.close()
+
+
+@pytest.mark.parametrize("name", ["ring5_d3", "transmon2_d4", "ring3_d3_offset_frame"])
+def test_real_and_complex_frames_agree(scp, name):
+    """The same transmon system through both evaluations of the generator:
+    each against the oracle, and the two against each other to FP32 rounding."""
+    desc = CASES[name]()
+    print(f"[adjoint] frames {name}", flush=True)
+    L, Fo, tau, Uo, go = loss_and_grad(OracleSystem(desc))
+    res = {}
+    for rf in (True, False):
+        F, g, U = _loss_grad_frame(scp, desc, rf)
+        assert abs(F - Fo) <= DF_TOL
+        check_grad(g, go)
+        res[rf] = (F, g, U)
+    assert np.abs(res[True][2] - res[False][2]).max() <= 1e-5
+    assert abs(res[True][0] - res[False][0]) <= 1e-7
+    scale = np.abs(res[False][1]).max()
+    assert np.abs(res[True][1] - res[False][1]).max() <= 1e-5 * scale

@@ -108,6 +108,9 @@ def test_null_arguments_are_refused():
     srv = C.c_void_p()
     assert lib().scp_server_create(0, 4, 0.0, None, C.byref(srv)) == SCP_EINVAL
     assert lib().scp_server_create(1 << 30, 0, 0.0, None, C.byref(srv)) == SCP_EINVAL
+    rf = C.c_int32()
+    assert lib().scp_system_frame(None, C.byref(rf)) == SCP_EINVAL
+    assert lib().scp_system_set_frame(None, 0) == SCP_EINVAL
 
 
 def test_request_footprint_grows_with_columns_steps_and_gradient():
