@@ -189,3 +189,63 @@ def test_real_and_complex_frames_agree(scp, name):
     assert abs(res[True][0] - res[False][0]) <= 1e-7
     scale = np.abs(res[False][1]).max()
     assert np.abs(res[True][1] - res[False][1]).max() <= 1e-5 * scale
+
+
+def _torch_infidelity(U, desc):
+    """1 - |sum_ij conj(T_ij) U[c_j, r_i]|^2 / d_c^2 with torch ops (complex128)."""
+    rows = torch.tensor(desc["comp_rows"], device=U.device)
+    cols = torch.tensor(desc["comp_cols"], device=U.device)
+    T = torch.tensor(np.asarray(desc["target"]), dtype=torch.complex128, device=U.device)
+    sub = U.to(torch.complex128)[cols][:, rows]          # sub[j, i] = U[c_j, r_i]
+    tau = (T.conj() * sub.transpose(0, 1)).sum()
+    dc = len(desc["comp_rows"])
+    return 1.0 - (tau.abs() ** 2) / dc ** 2
+
+
+@pytest.mark.parametrize("name", ["ring3_d4", "fluxonium2_d5"])
+def test_autograd_function_matches_explicit_adjoint_and_oracle(scp, name):
+    """theta -> U through torch.autograd (backward = the adjoint kernel), the
+    loss in torch: the same gradient as the explicit call and the oracle."""
+    desc = CASES[name]()
+    print(f"[adjoint] autograd {name}", flush=True)
+    model = scp.autograd.Model(desc)
+    theta = torch.tensor(model.theta0, dtype=torch.float64, requires_grad=True)
+    psi0 = scp.basis_columns(model.D, desc["columns"])
+    U = scp.autograd.propagate(model, theta, psi0)
+    L = _torch_infidelity(U, desc)
+    L.backward()
+    g_auto = theta.grad.numpy()
+    F, g_expl = gpu_loss_and_grad(scp, desc)
+    assert abs((1.0 - L.item()) - F) <= 1e-9
+    scale = np.abs(g_expl).max()
+    assert np.abs(g_auto - g_expl).max() <= 1e-6 * scale
+    Lo, Fo, tau, Uo, go = loss_and_grad(OracleSystem(desc))
+    assert abs((1.0 - L.item()) - Fo) <= DF_TOL
+    check_grad(g_auto, go)
+
+
+def test_autograd_function_follows_theta(scp):
+    """A forward at a moved theta rebuilds the system there (frame and carriers
+    frozen): bitwise the explicit solve of that description, and its loss moves
+    by the gradient to first order (FP32 central difference, 2 %)."""
+    desc = CASES["ring3_d4"]()
+    model = scp.autograd.Model(desc)
+    psi0 = scp.basis_columns(model.D, desc["columns"])
+    theta = torch.tensor(model.theta0, dtype=torch.float64, requires_grad=True)
+    L0 = _torch_infidelity(scp.autograd.propagate(model, theta, psi0), desc)
+    L0.backward()
+    g = theta.grad.numpy().copy()
+    k = int(np.argmax(np.abs(g)))
+    h = 1e-3 * max(1.0, abs(model.theta0[k]))
+    th1, th2 = model.theta0.copy(), model.theta0.copy()
+    th1[k] += h
+    th2[k] -= h
+    with torch.no_grad():
+        U1 = scp.autograd.propagate(model, torch.tensor(th1), psi0)
+        U2 = scp.autograd.propagate(model, torch.tensor(th2), psi0)
+    sysm = scp.System(model.desc_at(th1))
+    U1e = sysm.propagate(psi0.clone())
+    sysm.close()
+    assert torch.equal(U1, U1e)
+    fd = (_torch_infidelity(U1, desc).item() - _torch_infidelity(U2, desc).item()) / (2 * h)
+    assert abs(fd - g[k]) <= 2e-2 * abs(g[k])
