@@ -124,6 +124,29 @@ def serving_leg(scp, si, torch, np, n_req):
         arr = si.poisson_arrivals(n_req, frac * sat["requests_per_s"])
         r = serve.run_stream(reqs, arr, budget, max_active=64)
         out[f"poisson_{frac}x"] = {k: r[k] for k in keys}
+    # the same requests alone, FP32 fused path against the plain FP64 path
+    # (forward only: the FP64 path has no adjoint), on a bounded sample
+    n_cmp = min(6, n_req)
+    t32, t64 = [], []
+    stream = torch.cuda.current_stream()
+    for q in reqs[:n_cmp]:
+        g = scp.System(q)
+        S = len(q["columns"])
+        for prec, dt, acc in ((0, torch.complex64, t32), (1, torch.complex128, t64)):
+            psi0 = scp.basis_columns(g.D, q["columns"], dtype=dt)
+            o = g.opts(S, precision=prec)
+            ws = g.workspace(o)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            g.propagate(psi0, opts=o, workspace=ws)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            acc.append(e0.elapsed_time(e1))
+        g.close()
+    out["fp32_vs_fp64"] = {"requests": n_cmp, "what": "forward of each of the first requests "
+                           "alone; the FP64 path has no adjoint",
+                           "fp32_ms": sum(t32), "fp64_ms": sum(t64),
+                           "speedup": sum(t64) / sum(t32)}
     grads = sum(1 for q in reqs if q["want_grad"])
     out["mix"] = (f"first {n_req} requests of the mixed stream: 2-6 modes, d in {{3,4,5}}, "
                   f"D <= 3125, S = 2^modes, T in [20,200] ns at 50 steps/ns, "
