@@ -154,10 +154,12 @@ scp_status scp_system_carriers(const scp_system* sys, double* omega);
 
 /* Evaluation of the FP32 stage generator.  With D(t) = exp(i H_f t) the
  * interaction-picture generator is D(t) R(t) D(t)^dag, R the sum of the
- * un-rotated local terms (Sec. 2.1; App. B).  When every single-mode operator,
- * pair operator and operator derivative is real and each register position
- * pair holds one pair term (transmon devices), the FP32 path applies R with
- * real operators between diagonal rotations of the stage vectors (the "real
+ * un-rotated local terms (Sec. 2.1; App. B).  When every term of R is real --
+ * each single-mode operator (with its parameter derivatives) real or i times
+ * real, both factors of a coupling term of the same kind, drives on real
+ * operators: transmon devices, and fluxonium devices with n(x)n and
+ * phi(x)phi couplings and phi drives -- the FP32 path applies R with real
+ * operators between diagonal rotations of the stage vectors (the "real
  * frame", *real_frame = 1); otherwise it applies the rotated complex
  * operators (*real_frame = 0).  Both evaluate the same map; they differ by
  * FP32 rounding.  scp_system_set_frame(sys, 0) makes a real-frame system use

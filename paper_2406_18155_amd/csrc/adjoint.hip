@@ -19,10 +19,13 @@
 // wave-reduced, and accumulated in FP64 per wave, one target per lane.
 // No atomics: the result is bitwise reproducible.
 //
-// Real frame (every operator real): kb and y are rotated by D(t)^dag at each
-// stage, the items use the un-rotated real operators, and the folds with the
-// real derivative tables need only the imaginary parts of G, H and K; yb is
-// rotated back by D(t).  The frame is held fixed, so <kb, D dR D^dag y> =
+// Real frame (every term real: each operator real or i times real, both
+// factors of a pair term of one kind, drives on real operators): kb and y are
+// rotated by D(t)^dag at each stage, the items use the un-rotated real
+// operators (a pair term of imaginary factors carries i^2 = -1 in its pair
+// table), and the folds with the real derivative tables need only the
+// imaginary parts of G, H and K (the first factor's folds of an imaginary
+// term take the sign -1); yb is rotated back by D(t).  The frame is held fixed, so <kb, D dR D^dag y> =
 // <D^dag kb, dR D^dag y> and the sensitivities are unchanged.
 //
 // Per segment, last to first, a recompute launch (the forward stepper started
@@ -407,9 +410,11 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
             for (int th = 0; th < 3; ++th)
               dacc[(p + 1) * 3 + th] += ge * tdot<d, RF>(ops, rops, offd + (sj * 3 + th) * dd, G);
           }
+          // real frame, first factor i times real: its folds change sign (i^2)
+          const float hs = RF ? (float)uni(C.hsign) : 1.f;
 #pragma unroll
           for (int th = 0; th < 3; ++th)
-            dacc[p * 3 + th] += tdot<d, RF>(ops, rops, offd + (c_slot * 3 + th) * dd, H);
+            dacc[p * 3 + th] += hs * tdot<d, RF>(ops, rops, offd + (c_slot * 3 + th) * dd, H);
         }
       });
     });
@@ -722,14 +727,10 @@ hipError_t run_adj1(const AdjItem& I0, int nwg, int wg, size_t sh, hipStream_t s
   return hipGetLastError();
 }
 
-// the real-frame kernels exist for one pair term per position pair
 template <int d, int NR, int MP>
 hipError_t run_adj(const AdjItem& I0, int nwg, int wg, size_t sh, bool rf, hipStream_t s) {
   if (sh > 160 * 1024) return hipErrorInvalidValue;
-  if constexpr (MP == 1) {
-    if (rf) return run_adj1<d, NR, MP, true>(I0, nwg, wg, sh, s);
-  }
-  if (rf) return hipErrorInvalidValue;
+  if (rf) return run_adj1<d, NR, MP, true>(I0, nwg, wg, sh, s);
   return run_adj1<d, NR, MP, false>(I0, nwg, wg, sh, s);
 }
 
@@ -745,10 +746,7 @@ template <int d, int NR, int MP>
 hipError_t run_adj_batched(const AdjItem* items, int nitems, int wg, size_t sh, bool rf,
                            hipStream_t s) {
   if (sh > 160 * 1024) return hipErrorInvalidValue;
-  if constexpr (MP == 1) {
-    if (rf) return run_adj_batched1<d, NR, MP, true>(items, nitems, wg, sh, s);
-  }
-  if (rf) return hipErrorInvalidValue;
+  if (rf) return run_adj_batched1<d, NR, MP, true>(items, nitems, wg, sh, s);
   return run_adj_batched1<d, NR, MP, false>(items, nitems, wg, sh, s);
 }
 

@@ -26,7 +26,8 @@ constexpr int WG_THREADS = 256;
 // register position p and its partner at p + 1 (layouts are ordered along
 // paths of the coupling graph).  Absent entries point at a zero operator.
 struct CPair {
-  int32_t slot, pair, cidx, mode_i, mode_j, pad;   // cidx < 0: no drive attached
+  int32_t slot, pair, cidx, mode_i, mode_j;   // cidx < 0: no drive attached
+  int32_t hsign;   // real frame: kappa^2 of the item's kind (the first-factor folds' sign)
 };
 struct CSingle {
   int32_t slot, cidx;
@@ -73,10 +74,11 @@ struct Plan {
   int32_t mdrv[MAXGROUPS];         // drive indices grouped by mode
   int32_t mdrv_first[MAXGROUPS];   // 1: first drive on its operator slot
   int32_t nacc;                    // gradient accumulators: npulse + 3 N + ncoup
-  // Real frame (all single-mode and pair operators real): the stepper applies
-  // the un-rotated operators (table block 0) between the diagonal frame
-  // rotations of y and k, whose phases come from a per-half-step table with
-  // ph_row entries (a multiple of 8): the RB register phases of the base
+  // Real frame (every term a real operator: each operator is real or i times
+  // real, both factors of a pair term of one kind, drives on real operators):
+  // the stepper applies the un-rotated real operators between the diagonal
+  // frame rotations of y and k, whose phases come from a per-half-step table
+  // with ph_row entries (a multiple of 8): the RB register phases of the base
   // layout, then from ph_thr the NT * d thread-position phases.
   int32_t real_frame;
   int32_t ph_row, ph_thr;
@@ -156,6 +158,8 @@ struct scp_system {
   std::vector<int> slot_mode, slot_op;
   std::vector<scp::cplx> pairW_host;   // static pair operators sum g O_j (d*d each)
   std::vector<int> pair_mode_host;
+  std::vector<int> slot_imag;          // real frame: slot operator (and derivatives) i * real
+  std::vector<int> pair_imag;          // real frame: pair operator i * real (table sign -1)
   scp::Plan plan;
   // device
   scp::Plan* d_plan = nullptr;

@@ -11,11 +11,12 @@
 // update is a two-sum so that 10^4 steps do not drift in FP32.  Rotated
 // operators and drive coefficients come from tables reduced in FP64 at build.
 // The same kernel, started from a checkpoint and recording every stage input
-// (REC), is the adjoint's recompute of one segment.  When every operator is
-// real (transmon devices: the dressed charge operator is real symmetric) the
-// real-frame variant (RF) applies the un-rotated operators between diagonal
-// frame rotations of the stage input and of k, which halves the FMAs of every
-// contraction.
+// (REC), is the adjoint's recompute of one segment.  When every term is real
+// (transmons: the dressed charge operator is real symmetric; fluxoniums: n is
+// i times a real antisymmetric matrix and phi is real, so n(x)n and
+// phi(x)phi terms are real) the real-frame variant (RF) applies the un-rotated
+// real operators between diagonal frame rotations of the stage input and of k,
+// which halves the FMAs of every contraction.
 #include "kernel_common.h"
 
 namespace scp {
@@ -27,7 +28,7 @@ namespace scp {
 // register-order slices, touched only at the start and the end of a run.
 // REC: the adjoint's recompute of one segment: start from the checkpoint slab
 // ckin and write the four stage inputs of every step to ystore.
-// RF: the real-frame stepper (all operators real; frame phases from I.ph).
+// RF: the real-frame stepper (all terms real; frame phases from I.ph).
 template <int d, int NR, int MP, bool REC, bool RF>
 __device__ __forceinline__ void rk4_block(const FwdItem& I) {
   constexpr int RB = Cfg<d, NR>::RB;
@@ -220,12 +221,9 @@ struct Launch {
     hipLaunchKernelGGL((rk4_kernel<d, NR, MP, REC, RF>), dim3(nwg), dim3(P.WG), sh, s, I);
     return hipGetLastError();
   }
-  // the real-frame kernels exist for one pair term per position pair
   template <bool REC>
   static hipError_t run(const scp_system* sys, const FwdItem& I, int S, hipStream_t s) {
-    if constexpr (MP == 1) {
-      if (sys->plan.real_frame) return run1<REC, true>(sys, I, S, s);
-    }
+    if (sys->plan.real_frame) return run1<REC, true>(sys, I, S, s);
     return run1<REC, false>(sys, I, S, s);
   }
   static hipError_t rk4(const scp_system* sys, const float2* psi0, float2* psiT, float2* state,
@@ -249,16 +247,13 @@ struct Launch {
   }
   static hipError_t batched(const FwdItem* items, int nitems, int wg, size_t sh, bool rec,
                             bool rf, hipStream_t s) {
-    if constexpr (MP == 1) {
-      if (rf) {
-        if (rec)
-          batched1<true, true>(items, nitems, wg, sh, s);
-        else
-          batched1<false, true>(items, nitems, wg, sh, s);
-        return hipGetLastError();
-      }
+    if (rf) {
+      if (rec)
+        batched1<true, true>(items, nitems, wg, sh, s);
+      else
+        batched1<false, true>(items, nitems, wg, sh, s);
+      return hipGetLastError();
     }
-    if (rf) return hipErrorInvalidValue;
     if (rec)
       batched1<true, false>(items, nitems, wg, sh, s);
     else

@@ -322,6 +322,7 @@ scp_status make_plan(scp_system* sys) {
         C.pair = (int32_t)zpair;
         C.cidx = -1;
         C.mode_i = C.mode_j = -1;
+        C.hsign = 1;
       }
     for (int p = 0; p < 8; ++p) {
       P.csingle[l][p].slot = (int32_t)zslot;
@@ -457,18 +458,48 @@ scp_status make_plan(scp_system* sys) {
   }
   for (int i = 0; i < d * d; ++i) sys->pairW_host.push_back(0.0);   // zero pair operator
   sys->pair_mode_host.push_back(0);
-  // real frame: every single-mode operator and every pair operator real, and
-  // one pair term per position pair
-  bool real = P.MP == 1;
-  for (size_t s = 0; s < sys->slot_mode.size(); ++s)
-    for (int i = 0; i < d * d; ++i)
-      real = real && sys->modes[sys->slot_mode[s]].ops[sys->slot_op[s]][i].imag() == 0.0;
-  for (const cplx& v : sys->pairW_host) real = real && v.imag() == 0.0;
-  for (size_t s = 0; s < sys->slot_mode.size(); ++s)   // and their parameter derivatives
-    for (int th = 0; th < 3; ++th)
-      for (int i = 0; i < d * d; ++i)
-        real = real && sys->modes[sys->slot_mode[s]].dops[th][sys->slot_op[s]][i].imag() == 0.0;
+  // real frame: every operator real (kind 1) or i times real (kind 2), zero
+  // operators both (3); a slot's derivatives share its kind, the partner
+  // operators of a pair term share the first factor's kind (the term is then
+  // +-1 times a real one), and drives sit on real operators
+  auto kind_of = [&](const cplx* o) {
+    bool re0 = true, im0 = true;
+    for (int i = 0; i < d * d; ++i) {
+      re0 = re0 && o[i].real() == 0.0;
+      im0 = im0 && o[i].imag() == 0.0;
+    }
+    return (im0 ? 1 : 0) | (re0 ? 2 : 0);
+  };
+  const int nsl = (int)sys->slot_mode.size();
+  std::vector<int> skind(nsl + 1, 3);   // + the zero slot
+  for (int s = 0; s < nsl; ++s) {
+    const ModeData& M = sys->modes[sys->slot_mode[s]];
+    int k = kind_of(M.ops[sys->slot_op[s]]);
+    for (int th = 0; th < 3; ++th) k &= kind_of(M.dops[th][sys->slot_op[s]]);
+    skind[s] = k;
+  }
+  bool real = true;
+  std::vector<int> pkind(P.npairs + 1, 3);
+  for (int g = 0; g < P.npairs; ++g) {
+    int k = skind[grps[g].s];
+    for (int q = 0; q < P.pair_ncoup[g]; ++q) k &= skind[P.pair_pslot[g][q]];
+    pkind[g] = k;
+    real = real && k != 0;
+  }
+  for (int k = 0; k < P.ndrives; ++k) real = real && (skind[P.drives[k].slot] & 1) != 0;
   P.real_frame = real ? 1 : 0;
+  sys->slot_imag.assign(nsl + 1, 0);
+  sys->pair_imag.assign(P.npairs + 1, 0);
+  if (real) {
+    for (int s = 0; s <= nsl; ++s) sys->slot_imag[s] = skind[s] == 2;
+    for (int g = 0; g < P.npairs; ++g) sys->pair_imag[g] = pkind[g] == 2;
+    for (int l = 0; l < P.L; ++l)
+      for (int p = 0; p < 4; ++p)
+        for (int m = 0; m < 2; ++m) {
+          CPair& C = P.cpair[l][p][m];
+          C.hsign = (C.pair < P.npairs && sys->pair_imag[C.pair]) ? -1 : 1;
+        }
+  }
   P.ph_thr = (P.RB + 7) / 8 * 8;
   P.ph_row = (P.ph_thr + P.NT * d + 7) / 8 * 8;
   return SCP_OK;
@@ -561,10 +592,22 @@ scp_status build_tables(scp_system* sys, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(bmodes.p, modes.data(), modes.size() * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipMalloc(&sys->d_ph, nq * P.ph_row * sizeof(float2)));
     // the operators at t = 0 (the table's block 0 rounds them the same way)
+    // (kind 2: the imaginary parts; a pair term of kind 2 is i^2 = -1 times the
+    // product of the real parts, folded into the pair operator's sign)
     std::vector<float> rops(P.block_q, 0.f);
-    for (size_t i = 0; i < sops.size(); ++i) rops[i] = (float)sops[i].x;
-    for (size_t i = 0; i < pops.size(); ++i) rops[P.off_pair + i] = (float)pops[i].x;
-    for (size_t i = 0; i < dops.size(); ++i) rops[P.off_dslot + i] = (float)dops[i].x;
+    for (int s = 0; s < ns; ++s)
+      for (int i = 0; i < dd; ++i) {
+        const bool im = sys->slot_imag[s] != 0;
+        rops[s * dd + i] = (float)(im ? sops[s * dd + i].y : sops[s * dd + i].x);
+        for (int th = 0; th < 3; ++th) {
+          const double2 v = dops[(s * 3 + th) * dd + i];
+          rops[P.off_dslot + (s * 3 + th) * dd + i] = (float)(im ? v.y : v.x);
+        }
+      }
+    for (int p = 0; p < np1; ++p)
+      for (int i = 0; i < dd; ++i)
+        rops[P.off_pair + p * dd + i] =
+            sys->pair_imag[p] ? (float)(-pops[p * dd + i].y) : (float)pops[p * dd + i].x;
     HIPCHK(hipMalloc(&sys->d_rops, rops.size() * sizeof(float)));
     HIPCHK(hipMemcpyAsync(sys->d_rops, rops.data(), rops.size() * sizeof(float), hipMemcpyHostToDevice, st));
     HIPCHK(launch_phase_table(d, P.NT, P.NR, P.RB, P.ph_thr, P.ph_row, sys->n_steps, sys->h,

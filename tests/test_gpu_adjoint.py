@@ -157,12 +157,22 @@ def _loss_grad_frame(scp, desc, real_frame):
     return F, grad, Uc
 
 
+def _flux_n_drive(desc):
+    """The same fluxonium device driven on n (i times real): not a real term."""
+    d = copy.deepcopy(desc)
+    for dr in d["drives"]:
+        dr["op"] = "n"
+    return d
+
+
 def test_frame_choice_follows_the_operators(scp):
-    """Transmon devices (real dressed n) take the real frame; fluxonium
-    devices (imaginary n) and complex raw operators keep the complex path,
+    """Transmon devices (real dressed n) and fluxonium devices with n(x)n and
+    phi(x)phi couplings and phi drives (every term real) take the real frame;
+    a fluxonium drive on n and complex raw operators keep the complex path,
     and asking them for the real frame is an error."""
     for desc, real in ((_ring(4, 3, 2.0, 20), True), (_short(si.config1(), 2.0, 20), True),
-                       (_chain(2, 5, 2.0, 20), False),
+                       (_chain(2, 5, 2.0, 20), True),
+                       (_flux_n_drive(_chain(2, 5, 2.0, 20)), False),
                        (si.random_raw_system(5, [2, 2, 2], 3, 1.0, 20, env="gauss"), False)):
         g = scp.System(desc)
         assert g.real_frame == real
@@ -172,7 +182,8 @@ def test_frame_choice_follows_the_operators(scp):
         g.close()
 
 
-@pytest.mark.parametrize("name", ["ring5_d3", "transmon2_d4", "ring3_d3_offset_frame"])
+@pytest.mark.parametrize("name", ["ring5_d3", "transmon2_d4", "ring3_d3_offset_frame",
+                                  "fluxonium2_d5", "chain3_d5", "chain2_d5_offset_frame"])
 def test_real_and_complex_frames_agree(scp, name):
     """The same transmon system through both evaluations of the generator:
     each against the oracle, and the two against each other to FP32 rounding."""
