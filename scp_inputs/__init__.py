@@ -1,7 +1,7 @@
 """Seeded synthetic device / pulse descriptions (pure data, no physics).
 
 This module is the only code shared by the CPU oracle, the tests, the
-benchmark and the serving driver.  It draws device and pulse parameters from
+benchmark and the serving replay.  It draws device and pulse parameters from
 seeded numpy PCG64 generators and returns plain Python dicts; it performs none
 of the simulation's arithmetic (no Hamiltonians, no eigensolves, no carriers:
 a drive whose ``omega_d`` is ``None`` asks the consumer to use the dressed 0-1
