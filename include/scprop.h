@@ -175,8 +175,10 @@ scp_status scp_workspace_size(const scp_system* sys, const scp_solve_opts* opts,
 
 /* V(t) y for the stage time of (step, stage) (stage 0..3 at t_n + c h,
  * c = 0, 1/2, 1/2, 1): the interaction-picture generator applied to the
- * n_cols columns y (complex64, D x n_cols) into out.  FP32, same kernel
- * code as the fused stepper's applicator. */
+ * n_cols columns y (complex64, D x n_cols) into out.  FP32, the fused
+ * stepper's applicator code with the rotated complex operators (its complex
+ * evaluation; a real-frame system's stepper evaluates the same map with real
+ * operators between frame rotations, see scp_system_frame). */
 scp_status scp_apply_generator(const scp_system* sys, int32_t step, int32_t stage, const void* y,
                                void* out, int32_t n_cols, void* stream);
 
