@@ -343,15 +343,29 @@ __device__ __forceinline__ void fold(LaneAcc& A, double* accw, int target, float
 }
 
 
+// A device-memory pointer the compiler cannot see through: the addresses
+// derived from it are formed where they are used instead of being hoisted out
+// of the step loop (27 live 64-bit addresses per array otherwise).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> fresh(T* p) {
+  uintptr_t u = (uintptr_t)p;
+  asm volatile("" : "+v"(u));
+  return (gptr<T>)u;
+}
+
 // One adjoint stage: yb = i V(t) kb (base layout out), with the parameter
-// folds of this stage.  kb and y enter in the base layout.
+// folds of this stage.  kb and y are in natural order in LDS regions 0 and 1
+// (read only during the stage), and every layout gathers its elements from
+// there; yb accumulates layout by layout and moves to the next layout
+// through region 2.
 template <int d, int NR, int MP, int RB, bool RF>
 __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
                                           int vstride, bool lds_ok, int tc, int lane,
                                           LaneAcc& A, double* accw, kptr<c32> ops,
                                           kptr<float> rops, kptr<float> cq,
-                                          kptr<float> dcq, Vec<RB>& kb, Vec<RB>& y,
-                                          Vec<RB>& yb) {
+                                          kptr<float> dcq, Vec<RB>& yb) {
   constexpr int dd = d * d;
   const int L = P->L;
   const int npulse = P->npulse, N = P->N;
@@ -362,11 +376,16 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
   float carry[3] = {0.f, 0.f, 0.f};
   for (int lv = 0; lv < L; ++lv) {
     const int l = __builtin_amdgcn_readfirstlane(lv);
-    if (l == 0) {
-      if (L > 1) switch2<d, NR, RB>(P, lds, cbase, vstride, lds_ok, tc, L - 1, 0, kb, y);
+    if (l > 0) switch1<d, NR, RB>(P, lds + 2 * vstride, cbase, lds_ok, tc, l - 1, l, yb);
+    Vec<RB> kb, y;
+    if (lds_ok) {
+      const int tb = cbase + thread_base<d>(P, l, tc);
+      const RegOff<d, NR> R = reg_off_of<d, NR>(P, l);
+      lds_get<d, NR, RB>(lds, tb, R, kb);
+      lds_get<d, NR, RB>(lds + vstride, tb, R, y);
     } else {
-      switch2<d, NR, RB>(P, lds, cbase, vstride, lds_ok, tc, l - 1, l, kb, y);
-      switch1<d, NR, RB>(P, lds, cbase, lds_ok, tc, l - 1, l, yb);
+#pragma unroll
+      for (int r = 0; r < RB; ++r) kb.re[r] = kb.im[r] = y.re[r] = y.im[r] = 0.f;
     }
     // derivative contributions to the (EJ, EC, EL) of the mode at each register
     // position, summed per lane over this layout's terms and reduced once
@@ -547,9 +566,9 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   const int bq = P->block_q;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = blockDim.x >> 6;
-  // LDS: [2 CPW D] layout switches | [CPW D] per-thread slices of lambda | FP64
-  // accumulators of the waves (targets >= 128, and the hand-over to part).
-  c32* slice = lds + 2 * (size_t)CPW * D + (lds_ok ? cw : 0) * D + tc;
+  // LDS: [CPW D] kb and [CPW D] y of the stage in natural order | [CPW D] the
+  // layout moves of yb | FP64 accumulators of the waves (targets >= 128, and
+  // the hand-over to part).
   double* acc = reinterpret_cast<double*>(lds + 3 * (size_t)CPW * D);
   double* accw = acc + wave * nacc;
   double* partb = I.part + (size_t)I.cb * 4 * nacc;
@@ -561,27 +580,18 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   A.a1 = lane + 64 < nacc ? accw[lane + 64] : 0.0;
 
   const size_t colreg = (size_t)(active ? col : 0) * D + tc;   // register-order slice
-  c32* lo = (c32*)I.lo + colreg;
   c32* ysum = (c32*)I.sum + colreg;            // per-step sum of yb (device memory)
-  c32* lst = (c32*)I.lamstate + colreg;
+  c32* lst = (c32*)I.lamstate + colreg;        // costate lambda (device memory)
   const size_t ystride = (size_t)S * D;        // between stages in the segment buffer
   c32* ycol0 = segbuf + (size_t)(active ? col : 0) * D;   // this column, natural order
   const int tbB = thread_base<d>(P, base, tc);            // base-layout addressing
   const RegOff<d, NR> RB_ = reg_off_of<d, NR>(P, base);
-  // costate lambda lives in this thread's LDS slice (register order)
-  if (lds_ok) {
-    const int tb = thread_base<d>(P, base, tc);
+  // the costate starts from the cotangent (natural order) on the first launch
+  if (active && I.first) {
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      c32 v;
-      v.x = 0.f;
-      v.y = 0.f;
-      if (active) v = I.first ? ((const c32*)I.lamT)[(size_t)col * D + tb + RB_(r)]
-                              : lst[(size_t)r * TPC];
-      slice[r * TPC] = v;
-    }
+    for (int r = 0; r < RB; ++r)
+      lst[(size_t)r * TPC] = ((const c32*)I.lamT)[(size_t)col * D + tbB + RB_(r)];
   }
-  __syncthreads();
 
   float pf_sink = 0.f;
   {
@@ -595,7 +605,7 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
     const kptr<c32> pf_base = RF ? ph : optab;
     const int pf_stride = RF ? prow : bq;
     for (int n = stop - 1; n >= start; --n) {
-      Vec<RB> kb, y, yb;
+      Vec<RB> yb;
 #pragma unroll
       for (int r = 0; r < RB; ++r) yb.re[r] = yb.im[r] = 0.f;
 #pragma unroll 1
@@ -603,23 +613,24 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
         const int s = __builtin_amdgcn_readfirstlane(sv);
         const float bs = (s == 0 || s == 3) ? h * (1.0f / 6.0f) : h * (1.0f / 3.0f);
         const float as = (s == 2) ? h : 0.5f * h;   // coefficient of yb_{s+1}; unused for s = 3
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          c32 lm;
-          lm.x = 0.f;
-          lm.y = 0.f;
-          if (lds_ok) lm = slice[r * TPC];
-          kb.re[r] = s == 3 ? bs * lm.x : fmaf(as, yb.re[r], bs * lm.x);
-          kb.im[r] = s == 3 ? bs * lm.y : fmaf(as, yb.im[r], bs * lm.y);
-          y.re[r] = y.im[r] = 0.f;
-        }
-        if (active) {
-          const c32* src = ycol0 + (size_t)((n - start) * 4 + s) * ystride + tbB;
+        // kb = bs lambda + as yb_{s+1} and the stage input y (base layout)
+        Vec<RB> kb, y;
+        {
+          const gptr<c32> lm_p = fresh(lst);
+          const gptr<c32> y_p = fresh(ycol0 + (size_t)((n - start) * 4 + s) * ystride + tbB);
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
-            const c32 v = src[RB_(r)];
-            y.re[r] = v.x;
-            y.im[r] = v.y;
+            float lx = 0.f, ly = 0.f, vx = 0.f, vy = 0.f;
+            if (active) {
+              lx = lm_p[(size_t)r * TPC].x;
+              ly = lm_p[(size_t)r * TPC].y;
+              vx = y_p[RB_(r)].x;
+              vy = y_p[RB_(r)].y;
+            }
+            kb.re[r] = s == 3 ? bs * lx : fmaf(as, yb.re[r], bs * lx);
+            kb.im[r] = s == 3 ? bs * ly : fmaf(as, yb.im[r], bs * ly);
+            y.re[r] = vx;
+            y.im[r] = vy;
           }
         }
         kptr<c32> prw = ph + (size_t)stage_q(n, s) * prow;
@@ -638,6 +649,13 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
             y.im[r] = fmaf(e.x, xi, e.y * xr);
           }
         }
+        // regions 0 and 1 were last read before this barrier (previous stage)
+        __syncthreads();
+        if (lds_ok) {
+          lds_put<d, NR, RB>(lds, cbase + tbB, RB_, kb);
+          lds_put<d, NR, RB>(lds + vstride, cbase + tbB, RB_, y);
+        }
+        __syncthreads();
         auto ops = optab + (RF ? 0 : (size_t)stage_q(n, s) * bq);
         auto cq = ctab + (size_t)stage_c(n, s) * ng;
         auto dcq = dctab + (size_t)stage_c(n, s) * npl;
@@ -647,7 +665,7 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
           pf = ((const float*)(uintptr_t)(pf_base + (size_t)qn * pf_stride))[tc * 16];
         }
         adj_stage<d, NR, MP, RB, RF>(P, lds, cbase, vstride, lds_ok, tc, lane, A, accw, ops, rops,
-                                     cq, dcq, kb, y, yb);
+                                     cq, dcq, yb);
         if constexpr (RF) {
           // back to the interaction picture: yb <- D yb
           const c32 pt = thread_phase<d>(prw + pthr, NT, tc);
@@ -661,30 +679,26 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
         }
         pf_sink += pf;
         if (active) {
+          // sum of the yb of this step; after its last stage lambda <- lambda + sum
+          const gptr<c32> ys_p = fresh(ysum);
+          const gptr<c32> lm_p = fresh(lst);
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
-            c32 v;
-            if (s == 3) {
-              v.x = yb.re[r];
-              v.y = yb.im[r];
-            } else {
-              v = ysum[(size_t)r * TPC];
-              v.x += yb.re[r];
-              v.y += yb.im[r];
+            float vx = yb.re[r], vy = yb.im[r];
+            if (s != 3) {
+              vx = ys_p[(size_t)r * TPC].x + vx;
+              vy = ys_p[(size_t)r * TPC].y + vy;
             }
-            ysum[(size_t)r * TPC] = v;
+            if (s == 0) {
+              const float lx = lm_p[(size_t)r * TPC].x + vx;
+              const float ly = lm_p[(size_t)r * TPC].y + vy;
+              lm_p[(size_t)r * TPC].x = lx;
+              lm_p[(size_t)r * TPC].y = ly;
+            } else {
+              ys_p[(size_t)r * TPC].x = vx;
+              ys_p[(size_t)r * TPC].y = vy;
+            }
           }
-        }
-      }
-      // lambda <- lambda + sum_s yb_s
-      if (active) {
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-          const c32 v = ysum[(size_t)r * TPC];
-          c32 lm = slice[r * TPC];
-          lm.x += v.x;
-          lm.y += v.y;
-          slice[r * TPC] = lm;
         }
       }
     }
@@ -695,10 +709,6 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   if (lane < nacc) accw[lane] = A.a0;
   if (lane + 64 < nacc) accw[lane + 64] = A.a1;
   __syncthreads();
-  if (active) {
-#pragma unroll
-    for (int r = 0; r < RB; ++r) lst[(size_t)r * TPC] = slice[r * TPC];
-  }
   for (int i = threadIdx.x; i < 4 * nacc; i += blockDim.x) partb[i] = i < nwaves * nacc ? acc[i] : 0.0;
 }
 
