@@ -358,8 +358,8 @@ __device__ __forceinline__ gptr<T> fresh(T* p) {
 // One adjoint stage: yb = i V(t) kb (base layout out), with the parameter
 // folds of this stage.  kb and y are in natural order in LDS regions 0 and 1
 // (read only during the stage), and every layout gathers its elements from
-// there; yb accumulates layout by layout and moves to the next layout
-// through region 2.
+// there; yb accumulates layout by layout and passes to the next layout in
+// natural order through region 2.
 template <int d, int NR, int MP, int RB, bool RF>
 __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
                                           int vstride, bool lds_ok, int tc, int lane,
@@ -376,11 +376,15 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
   float carry[3] = {0.f, 0.f, 0.f};
   for (int lv = 0; lv < L; ++lv) {
     const int l = __builtin_amdgcn_readfirstlane(lv);
-    if (l > 0) switch1<d, NR, RB>(P, lds + 2 * vstride, cbase, lds_ok, tc, l - 1, l, yb);
+    const int tb = cbase + thread_base<d>(P, l, tc);
+    const RegOff<d, NR> R = reg_off_of<d, NR>(P, l);
+    if (l > 0) {
+      // the previous layout's yb (natural order in region 2) is visible
+      __syncthreads();
+      if (lds_ok) lds_get<d, NR, RB>(lds + 2 * vstride, tb, R, yb);
+    }
     Vec<RB> kb, y;
     if (lds_ok) {
-      const int tb = cbase + thread_base<d>(P, l, tc);
-      const RegOff<d, NR> R = reg_off_of<d, NR>(P, l);
       lds_get<d, NR, RB>(lds, tb, R, kb);
       lds_get<d, NR, RB>(lds + vstride, tb, R, y);
     } else {
@@ -466,6 +470,9 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
         diag_acc<d, NR, p>(P->delta[uni(P->cdiag[l][p])], kb, yb);
       });
     }
+    // yb is complete for this layout: hand it to the next one (each element has
+    // one owner per layout, so one barrier per layout boundary suffices)
+    if (l + 1 < L && lds_ok) lds_put<d, NR, RB>(lds + 2 * vstride, tb, R, yb);
     // single-mode sensitivities (drives and the diagonal) of the modes owned here
     if (uni(P->has_mode_pass[l])) {
       static_for<NR>([&](auto Pp) {
