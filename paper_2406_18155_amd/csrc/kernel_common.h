@@ -479,36 +479,6 @@ __device__ __forceinline__ int thread_base(kptr<Plan> P, int l, int tc) {
   return b;
 }
 
-// Layout switch of one or two vectors (WAR barrier, write, RAW barrier, read).
-template <int d, int NR, int RB>
-__device__ __forceinline__ void switch1(kptr<Plan> P, c32* lds, int cbase,
-                                        bool lds_ok, int tc, int from, int to, Vec<RB>& v) {
-  __syncthreads();
-  if (lds_ok) lds_put<d, NR, RB>(lds, cbase + thread_base<d>(P, from, tc), reg_off_of<d, NR>(P, from), v);
-  __syncthreads();
-  if (lds_ok) lds_get<d, NR, RB>(lds, cbase + thread_base<d>(P, to, tc), reg_off_of<d, NR>(P, to), v);
-}
-
-template <int d, int NR, int RB>
-__device__ __forceinline__ void switch2(kptr<Plan> P, c32* lds, int cbase,
-                                        int vstride, bool lds_ok, int tc, int from, int to,
-                                        Vec<RB>& v, Vec<RB>& w) {
-  __syncthreads();
-  if (lds_ok) {
-    const int b = cbase + thread_base<d>(P, from, tc);
-    const RegOff<d, NR> R = reg_off_of<d, NR>(P, from);
-    lds_put<d, NR, RB>(lds, b, R, v);
-    lds_put<d, NR, RB>(lds + vstride, b, R, w);
-  }
-  __syncthreads();
-  if (lds_ok) {
-    const int b = cbase + thread_base<d>(P, to, tc);
-    const RegOff<d, NR> R = reg_off_of<d, NR>(P, to);
-    lds_get<d, NR, RB>(lds, b, R, v);
-    lds_get<d, NR, RB>(lds + vstride, b, R, w);
-  }
-}
-
 // k = V(t) y for one stage.  The stage input y is in natural order in LDS
 // region iy (regions are rstride elements apart; cbase selects the column)
 // and every layout reads its elements from there.  k accumulates layout by
