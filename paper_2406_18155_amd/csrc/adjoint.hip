@@ -25,14 +25,17 @@
 // operators (a pair term of imaginary factors carries i^2 = -1 in its pair
 // table), and the folds with the real derivative tables need only the
 // imaginary parts of G, H and K (the first factor's folds of an imaginary
-// term take the sign -1); yb is rotated back by D(t).  The frame is held fixed, so <kb, D dR D^dag y> =
-// <D^dag kb, dR D^dag y> and the sensitivities are unchanged.
+// term take the sign -1); yb is rotated back by D(t).  The frame is held
+// fixed, so <kb, D dR D^dag y> = <D^dag kb, dR D^dag y> and the
+// sensitivities are unchanged.
 //
 // Per segment, last to first, a recompute launch (the forward stepper started
 // from the segment's checkpoint) writes the four stage inputs of every step
 // to the segment buffer, then one launch of the kernel here walks the segment
-// back.  The costate, the FP64 accumulators and the running sums are carried
-// between launches in device memory, exactly.
+// back.  Within a stage kb and y sit in LDS in natural order and every layout
+// gathers its elements; yb passes from layout to layout in natural order.
+// The costate, the running sum of yb and the FP64 accumulators live in device
+// memory and carry between launches exactly.
 #include <algorithm>
 
 #include "kernel_common.h"

@@ -438,8 +438,9 @@ scp_status make_plan(scp_system* sys) {
   P.off_pair = P.nslots * d * d;
   P.off_dslot = (P.nslots + P.npairs + 1) * d * d;
   P.block_q = (P.nslots + P.npairs + 1 + 3 * P.nslots) * d * d;
-  // LDS per workgroup: two layout-switch vectors + one per-thread slice vector
-  // per column, plus the adjoint's FP64 accumulators (4 waves max).
+  // LDS per workgroup: three column-sized regions per column (stepper: the
+  // stage input and two regions for the moves of k; adjoint: kb, y and the
+  // pass of yb), plus the adjoint's FP64 accumulators (4 waves max).
   {
     const long budget = 163840 - 4L * 8 * std::max(1, P.nacc);
     const long per_col = 3L * 8 * P.D;
