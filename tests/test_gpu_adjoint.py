@@ -260,3 +260,35 @@ def test_autograd_function_follows_theta(scp):
     assert torch.equal(U1, U1e)
     fd = (_torch_infidelity(U1, desc).item() - _torch_infidelity(U2, desc).item()) / (2 * h)
     assert abs(fd - g[k]) <= 2e-2 * abs(g[k])
+
+
+def _config5_sampled_desc():
+    """Config 5 (8-transmon ring, 3000 steps) on its 8 seeded sampled columns,
+    the fidelity restricted to the sampled computational states (the recipe of
+    tests/golden/make_oracle_refs.py)."""
+    desc = si.config5()
+    samp = si.sampled_columns(len(desc["columns"]), 8)
+    full_t = desc["target"]
+    desc["comp_rows"] = [desc["comp_rows"][j] for j in samp]
+    desc["columns"] = [desc["columns"][j] for j in samp]
+    desc["comp_cols"] = list(range(len(samp)))
+    desc["target"] = full_t[np.ix_(samp, samp)]
+    return desc
+
+
+def test_config5_full_length_gradient_against_stored_oracle(scp):
+    """The full 3000-step config-5 gradient (40 parameters) on the sampled
+    columns against the stored FP64 oracle, for the CZ target and for the
+    near-unit block target."""
+    ref = json.load(open(os.path.join(GOLDEN, "config5_sampled_oracle.json")))
+    desc = _config5_sampled_desc()
+    print("[adjoint] config5 sampled, 3000 steps", flush=True)
+    F, g = gpu_loss_and_grad(scp, desc)
+    assert abs(F - ref["F"]) <= DF_TOL
+    check_grad(g, np.array(ref["grad"]))
+    nu = ref["near_unit"]
+    d1 = copy.deepcopy(desc)
+    d1["target"] = np.array(nu["target_re"]) + 1j * np.array(nu["target_im"])
+    F1, g1 = gpu_loss_and_grad(scp, d1)
+    assert abs(F1 - nu["F"]) <= DF_TOL
+    check_grad(g1, np.array(nu["grad"]))
