@@ -82,6 +82,14 @@ def _offset_frame(desc):
     return d
 
 
+def _flux_n_drive(desc):
+    """The same fluxonium device driven on n (i times real): not a real term."""
+    d = copy.deepcopy(desc)
+    for dr in d["drives"]:
+        dr["op"] = "n"
+    return d
+
+
 CASES = {
     "transmon2_d4": lambda: _short(si.config1(), 10.0, 500),
     "fluxonium2_d5": lambda: si._finish(dict(_short(si.config3(), 8.0, 400),
@@ -98,6 +106,8 @@ CASES = {
                                                                env="gauss"),
     "ring3_d3_offset_frame": lambda: _offset_frame(_ring(3, 3, 6.0, 300)),
     "chain2_d5_offset_frame": lambda: _offset_frame(_chain(2, 5, 4.0, 200)),
+    # a drive on n (i times real) keeps a fluxonium device on the complex path
+    "chain2_d5_n_drive": lambda: _flux_n_drive(_chain(2, 5, 4.0, 200)),
 }
 
 
@@ -155,14 +165,6 @@ def _loss_grad_frame(scp, desc, real_frame):
     Uc = U.cpu().numpy()
     g.close()
     return F, grad, Uc
-
-
-def _flux_n_drive(desc):
-    """The same fluxonium device driven on n (i times real): not a real term."""
-    d = copy.deepcopy(desc)
-    for dr in d["drives"]:
-        dr["op"] = "n"
-    return d
 
 
 def test_frame_choice_follows_the_operators(scp):
