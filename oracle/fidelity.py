@@ -36,3 +36,82 @@ def cotangent(shape, comp_rows, comp_cols, target, tau):
         for j, c in enumerate(comp_cols):
             lam[r, c] = -(tau / dc ** 2) * target[i, j]
     return lam
+
+
+def comp_bits(n_q):
+    """bits[i, q] = bit of qubit q in computational index i (qubit 0 most
+    significant, the binary order of the computational states)."""
+    dc = 2 ** n_q
+    return np.array([[(i >> (n_q - 1 - q)) & 1 for q in range(n_q)] for i in range(dc)],
+                    dtype=np.int64)
+
+
+def zcomp_overlap(M, target, a, c):
+    """tau(a, c) = sum_ij conj(T_ij) e^{i theta_i} M_ij e^{i chi_j} with
+    theta_i = sum_q a_q bit_q(i) (phases after the gate) and chi_j = sum_q c_q
+    bit_q(j) (phases before it)."""
+    bits = comp_bits(len(a))
+    th = bits @ np.asarray(a, dtype=np.float64)
+    ch = bits @ np.asarray(c, dtype=np.float64)
+    W = np.conj(target) * M
+    return complex(np.sum(np.exp(1j * th)[:, None] * W * np.exp(1j * ch)[None, :]))
+
+
+def zcomp_fidelity(M, target, n_q, max_sweeps=200, tol=1e-14):
+    """Fidelity with error-free single-qubit phase gates before and after the
+    gate (the compensation of App. D, restricted to Z rotations: virtual Z),
+    F = max_{a,c} |tau(a, c)|^2 / d_c^2 for the d_c x d_c computational block
+    M.  The maximum is sought by coordinate ascent from zero phases: in turn
+    a_0..a_{n-1}, then c_0..c_{n-1}, each phase is set to its optimum with the
+    others fixed.  Writing tau = A + e^{i p} B, where B collects the terms whose
+    bit of that qubit is set, |tau| is largest at p = arg A - arg B (a phase
+    whose A or B vanishes is left as it is).  Sweeps repeat until |tau| grows by
+    at most tol (relative) or max_sweeps is reached.  Returns (F, a, c, tau)."""
+    M = np.asarray(M, dtype=np.complex128)
+    target = np.asarray(target, dtype=np.complex128)
+    dc = 2 ** n_q
+    assert M.shape == (dc, dc) and target.shape == (dc, dc)
+    bits = comp_bits(n_q)
+    W = np.conj(target) * M
+    a = np.zeros(n_q)
+    c = np.zeros(n_q)
+    best = abs(zcomp_overlap(M, target, a, c))
+    for _ in range(max_sweeps):
+        for side in (0, 1):
+            for q in range(n_q):
+                th = bits @ a
+                ch = bits @ c
+                if side == 0:
+                    th = th - a[q] * bits[:, q]
+                    X = np.exp(1j * th)[:, None] * W * np.exp(1j * ch)[None, :]
+                    A = X[bits[:, q] == 0, :].sum()
+                    B = X[bits[:, q] == 1, :].sum()
+                else:
+                    ch = ch - c[q] * bits[:, q]
+                    X = np.exp(1j * th)[:, None] * W * np.exp(1j * ch)[None, :]
+                    A = X[:, bits[:, q] == 0].sum()
+                    B = X[:, bits[:, q] == 1].sum()
+                if A != 0 and B != 0:
+                    p = np.angle(A) - np.angle(B)
+                    if side == 0:
+                        a[q] = p
+                    else:
+                        c[q] = p
+        t = abs(zcomp_overlap(M, target, a, c))
+        done = t - best <= tol * max(1.0, t)
+        best = max(best, t)
+        if done:
+            break
+    tau = zcomp_overlap(M, target, a, c)
+    return abs(tau) ** 2 / dc ** 2, a, c, tau
+
+
+def zcomp_target(target, a, c):
+    """The target rephased by the optimal phases, T'_ij = T_ij e^{-i theta_i}
+    e^{-i chi_j}: at the optimum the compensated loss has the plain loss's
+    cotangent with T' (the phases are stationary, so they carry no
+    derivative)."""
+    bits = comp_bits(len(a))
+    th = bits @ np.asarray(a, dtype=np.float64)
+    ch = bits @ np.asarray(c, dtype=np.float64)
+    return np.asarray(target) * np.exp(-1j * th)[:, None] * np.exp(-1j * ch)[None, :]

@@ -423,3 +423,87 @@ def test_envelopes_and_carrier_at_known_times():
     dr2 = dict(dr, phase=math.pi - dr["omega_d"] * t)
     o.drives[k] = dr2
     assert o.drive_coeff(k, n, s)[0] == pytest.approx(-e, rel=1e-12)
+
+
+# --- phase (virtual-Z) compensation of the fidelity --------------------------
+
+def _haar(rng, n):
+    z = (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) / np.sqrt(2)
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))
+
+
+def _rephase(T, a, c):
+    from oracle.fidelity import comp_bits
+    b = comp_bits(len(a))
+    return np.exp(-1j * (b @ a))[:, None] * T * np.exp(-1j * (b @ c))[None, :]
+
+
+def test_zcomp_recovers_phase_rephased_targets():
+    """A block that equals the target up to single-qubit phases before and
+    after is compensated to F = 1 (CZ, CNOT, Haar-random 2- and 3-qubit)."""
+    from oracle.fidelity import zcomp_fidelity, fidelity
+    rng = np.random.default_rng(11)
+    cz = np.diag([1, 1, 1, -1]).astype(complex)
+    cnot = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], complex)
+    for T in (cz, cnot, _haar(rng, 4), _haar(rng, 8)):
+        n = int(np.log2(T.shape[0]))
+        a0, c0 = rng.uniform(0, 2 * np.pi, n), rng.uniform(0, 2 * np.pi, n)
+        M = _rephase(T, a0, c0)
+        F, a, c, tau = zcomp_fidelity(M, T, n)
+        assert abs(F - 1.0) <= 1e-12
+        assert fidelity(M, range(len(T)), range(len(T)), T)[0] < 1.0 - 1e-3
+
+
+def test_zcomp_matches_brute_force_grid():
+    """On one and two qubits the coordinate ascent reaches the maximum of a
+    dense grid over all phases (noisy, non-unitary blocks near a target)."""
+    import itertools
+    from oracle.fidelity import zcomp_fidelity, zcomp_overlap
+    rng = np.random.default_rng(12)
+    for n, grid in ((1, 256), (2, 24)):
+        dc = 2 ** n
+        T = _haar(rng, dc)
+        M = _rephase(T, rng.uniform(0, 6.3, n), rng.uniform(0, 6.3, n))
+        M = M + 0.15 * (rng.normal(size=(dc, dc)) + 1j * rng.normal(size=(dc, dc)))
+        F, a, c, tau = zcomp_fidelity(M, T, n)
+        ps = np.linspace(0, 2 * np.pi, grid, endpoint=False)
+        best = 0.0
+        for p in itertools.product(ps, repeat=2 * n):
+            best = max(best, abs(zcomp_overlap(M, T, p[:n], p[n:])) ** 2 / dc ** 2)
+        assert F >= best - 1e-12
+        # the grid step bounds how far its best point can sit below the maximum
+        step = 2 * np.pi / grid
+        assert F - best <= 2 * n * step ** 2 * np.abs(M).sum() ** 2 / dc ** 2
+
+
+def test_zcomp_is_never_below_the_plain_fidelity():
+    from oracle.fidelity import zcomp_fidelity, fidelity
+    rng = np.random.default_rng(13)
+    for _ in range(20):
+        M = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+        T = _haar(rng, 4)
+        F0 = fidelity(M, range(4), range(4), T)[0]
+        assert zcomp_fidelity(M, T, 2)[0] >= F0 - 1e-15
+
+
+def test_zcomp_cotangent_is_the_plain_one_of_the_rephased_target():
+    """At the optimum the phases are stationary: the compensated loss has the
+    plain cotangent of the rephased target (central differences, re-optimised
+    at every point)."""
+    from oracle.fidelity import zcomp_fidelity, zcomp_target, cotangent, overlap
+    rng = np.random.default_rng(14)
+    T = _haar(rng, 4)
+    M = _rephase(T, rng.uniform(0, 6.3, 2), rng.uniform(0, 6.3, 2))
+    M = M + 0.1 * (rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4)))
+    F, a, c, tau = zcomp_fidelity(M, T, 2)
+    Tp = zcomp_target(T, a, c)
+    assert abs(overlap(M, range(4), range(4), Tp) - tau) <= 1e-12
+    lam = cotangent(M.shape, range(4), range(4), Tp, tau)
+    E = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
+    h = 1e-6
+    Lp = 1.0 - zcomp_fidelity(M + h * E, T, 2)[0]
+    Lm = 1.0 - zcomp_fidelity(M - h * E, T, 2)[0]
+    fd = (Lp - Lm) / (2 * h)
+    lin = 2.0 * np.real(np.sum(np.conj(lam) * E))
+    assert abs(fd - lin) <= 1e-6 * max(1.0, abs(lin))
