@@ -205,6 +205,31 @@ scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, 
  * the checkpoints of the immediately preceding scp_propagate on the same
  * workspace with with_ckpt = 1 and the same opts.  Synchronises ``stream``.
  * SCP_ENONFINITE if any gradient entry is not finite. */
+/* Fidelity with error-free single-qubit phase gates before and after the
+ * gate (the compensation of App. D, restricted to Z rotations: virtual Z).
+ * d_c = 2^n_qubits computational states, in binary order with qubit 0 most
+ * significant (comp_rows / comp_cols as for scp_fidelity).  The block
+ * M_ij = U[comp_rows[i], comp_cols[j]] is gathered on the device into
+ * block_out (complex128, d_c x d_c row-major, device, caller-owned); on the
+ * host the phases a (after the gate) and c (before it) that maximise |tau|,
+ *   tau = sum_ij conj(T_ij) e^{i theta_i} M_ij e^{i chi_j},
+ *   theta_i = sum_q a_q bit_q(i),  chi_j = sum_q c_q bit_q(j),
+ * are found by coordinate ascent from zero: in turn a_0..a_{n-1}, then
+ * c_0..c_{n-1}, each phase is set to arg A - arg B where tau = A + e^{i p} B
+ * (B: the terms whose bit of that qubit is set), until |tau| grows by at most
+ * 1e-14 relative or after 200 sweeps.  F_out (host, required) =
+ * |tau|^2 / d_c^2; phases_out (host, 2 n_qubits, nullable): a then c;
+ * tau_out (device complex128, nullable).  cotangent (nullable, as for
+ * scp_fidelity) receives the costate of L = 1 - F at the optimum,
+ * -(tau/d_c^2) T_ij e^{-i theta_i} e^{-i chi_j} (the phases are stationary
+ * there, so scp_propagate_adjoint then gives dL/dtheta of the compensated
+ * loss).  target is a device pointer as for scp_fidelity.  Synchronises the
+ * stream.  n_qubits: 1..6.  Errors: SCP_EINVAL, SCP_ENONFINITE, SCP_EHIP. */
+scp_status scp_fidelity_zcomp(const void* U, int64_t D, int32_t S, int32_t precision,
+                              int32_t n_qubits, const int64_t* comp_rows, const int32_t* comp_cols,
+                              const void* target, void* block_out, void* tau_out, double* F_out,
+                              double* phases_out, void* cotangent, void* stream);
+
 scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, void* workspace,
                                  const void* cotangent, double* grad_out, void* stream);
 

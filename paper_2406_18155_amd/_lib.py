@@ -55,6 +55,10 @@ EXPORTS = {
                                   C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "scp_system_carriers": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "scp_system_frame": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
+    "scp_fidelity_zcomp": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p,
+                                     C.c_void_p]),
     "scp_system_set_frame": (C.c_int, [C.c_void_p, C.c_int32]),
     "scp_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32,
                                      C.POINTER(C.c_size_t)]),

@@ -208,6 +208,25 @@ def fidelity(U, tgt: Target, cotangent=None, stream=None, sync=True):
     return (F.value if sync else None), tgt.tau
 
 
+def fidelity_zcomp(U, tgt: Target, n_qubits, cotangent=None, stream=None):
+    """Fidelity with single-qubit phase compensation before and after the gate
+    (F, phases after, phases before); fills ``cotangent`` (the costate of
+    1 - F at the optimal phases) if given."""
+    prec = 0 if U.dtype == torch.complex64 else 1
+    S, D = U.shape
+    if tgt.dc != 2 ** int(n_qubits):
+        raise ValueError(f"{tgt.dc} computational states are not 2^{n_qubits}")
+    block = torch.empty((tgt.dc, tgt.dc), dtype=torch.complex128, device=U.device)
+    F = C.c_double()
+    ph = (C.c_double * (2 * int(n_qubits)))()
+    check(lib().scp_fidelity_zcomp(_ptr(U), D, S, prec, int(n_qubits), _ptr(tgt.rows),
+                                   _ptr(tgt.cols), _ptr(tgt.target), _ptr(block), _ptr(tgt.tau),
+                                   C.byref(F), ph, None if cotangent is None else _ptr(cotangent),
+                                   _stream_ptr(stream)))
+    n = int(n_qubits)
+    return F.value, np.array(ph[:n]), np.array(ph[n:])
+
+
 def basis_columns(D, columns, dtype=torch.complex64, device="cuda"):
     psi0 = torch.zeros((len(columns), D), dtype=dtype, device=device)
     for j, c in enumerate(columns):

@@ -6,6 +6,15 @@
 // fixed-shape LDS tree (deterministic).  The cotangent of L = 1 - |tau|^2/d_c^2
 // with dL = 2 Re <lambda, dU> is lambda = -(tau / d_c^2) T_ij at the
 // computational entries and zero elsewhere.
+//
+// With single-qubit phase compensation (App. D compensation, restricted to Z
+// rotations before and after the gate): the d_c x d_c block is gathered in
+// FP64, the phases maximising |tau| are found on the host (a few hundred
+// FP64 operations per phase update), and the cotangent is that of the target
+// rephased by the optimal phases (they are stationary at the optimum).
+#include <complex>
+#include <vector>
+
 #include "internal.h"
 
 namespace scp {
@@ -104,7 +113,178 @@ hipError_t run(const void* U, int64_t D, int S, int dc, const int64_t* rows, con
   return hipGetLastError();
 }
 
+// M_ij = U[comp_rows[i], comp_cols[j]] (FP64, row-major) for the host-side
+// phase compensation.
+template <typename T2>
+__global__ void block_kernel(const T2* __restrict__ U, int64_t D, int S, int dc,
+                             const int64_t* __restrict__ rows, const int32_t* __restrict__ cols,
+                             double2* __restrict__ out) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= dc * dc) return;
+  const int i = e / dc, j = e - i * dc;
+  const int64_t r = rows[i];
+  const int c = cols[j];
+  out[e] = (r < 0 || r >= D || c < 0 || c >= S) ? make_double2(__builtin_nan(""), 0.0)
+                                                 : ld(U, (size_t)c * D + r);
+}
+
+// Compensation phases of the computational rows (after the gate) and
+// columns (before it), passed by value.
+struct ZPhases {
+  double th[64], ch[64];
+};
+
+// cotangent at the optimum: -(tau/dc^2) T_ij e^{-i th_i} e^{-i ch_j}
+template <typename T2>
+__global__ void cot_zcomp_kernel(T2* __restrict__ cot, int64_t D, int S, int dc,
+                                 const int64_t* __restrict__ rows,
+                                 const int32_t* __restrict__ cols,
+                                 const double2* __restrict__ target, ZPhases ph, double2 tau) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= dc * dc) return;
+  const int i = e / dc, j = e - i * dc;
+  if (rows[i] < 0 || rows[i] >= D || cols[j] < 0 || cols[j] >= S) return;
+  const double2 t = target[e];
+  double sn, cs;
+  sincos(-(ph.th[i] + ph.ch[j]), &sn, &cs);
+  const double tr = t.x * cs - t.y * sn, ti = t.x * sn + t.y * cs;   // T'_ij
+  const double sc = -1.0 / ((double)dc * dc);
+  T2 v;
+  v.x = sc * (tau.x * tr - tau.y * ti);
+  v.y = sc * (tau.x * ti + tau.y * tr);
+  cot[(size_t)cols[j] * D + rows[i]] = v;
+}
+
+template <typename T2>
+hipError_t run_zcomp_block(const void* U, int64_t D, int S, int dc, const int64_t* rows,
+                           const int32_t* cols, void* block, hipStream_t s) {
+  hipLaunchKernelGGL(block_kernel<T2>, dim3((dc * dc + 255) / 256), dim3(256), 0, s,
+                     (const T2*)U, D, S, dc, rows, cols, (double2*)block);
+  return hipGetLastError();
+}
+
+template <typename T2>
+hipError_t run_zcomp_cot(void* cot, int64_t D, int S, int dc, const int64_t* rows,
+                         const int32_t* cols, const void* target, const ZPhases& ph,
+                         double2 tau, hipStream_t s) {
+  const size_t n = (size_t)D * S;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_zero_kernel<T2>, dim3(blocks), dim3(256), 0, s, (T2*)cot, n);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cot_zcomp_kernel<T2>, dim3((dc * dc + 255) / 256), dim3(256), 0, s, (T2*)cot,
+                     D, S, dc, rows, cols, (const double2*)target, ph, tau);
+  return hipGetLastError();
+}
+
+using cd = std::complex<double>;
+
+// tau(a, c) = sum_ij W_ij e^{i theta_i} e^{i chi_j}, W_ij = conj(T_ij) M_ij
+cd zcomp_tau(const std::vector<cd>& W, int nq, const std::vector<double>& a,
+             const std::vector<double>& c) {
+  const int dc = 1 << nq;
+  cd t = 0.0;
+  for (int i = 0; i < dc; ++i) {
+    double th = 0.0;
+    for (int q = 0; q < nq; ++q) th += ((i >> (nq - 1 - q)) & 1) ? a[q] : 0.0;
+    for (int j = 0; j < dc; ++j) {
+      double ch = 0.0;
+      for (int q = 0; q < nq; ++q) ch += ((j >> (nq - 1 - q)) & 1) ? c[q] : 0.0;
+      t += W[(size_t)i * dc + j] * std::polar(1.0, th + ch);
+    }
+  }
+  return t;
+}
+
 }  // namespace
+
+// Phase compensation on the host (FP64): coordinate ascent from zero phases
+// over a_0..a_{n-1} (after the gate), then c_0..c_{n-1} (before it); each phase
+// goes to arg A - arg B, where tau = A + e^{i p} B with B the terms whose bit of
+// that qubit is set and the other phases fixed (left unchanged if A or B is
+// zero); sweeps end when |tau| grows by at most 1e-14 relative, or after 200.
+void zcomp_optimise(const std::vector<cd>& W, int nq, std::vector<double>& a,
+                    std::vector<double>& c, cd& tau) {
+  const int dc = 1 << nq;
+  a.assign(nq, 0.0);
+  c.assign(nq, 0.0);
+  double best = std::abs(zcomp_tau(W, nq, a, c));
+  auto bit = [&](int i, int q) { return (i >> (nq - 1 - q)) & 1; };
+  for (int sweep = 0; sweep < 200; ++sweep) {
+    for (int side = 0; side < 2; ++side)
+      for (int q = 0; q < nq; ++q) {
+        cd A = 0.0, B = 0.0;
+        for (int i = 0; i < dc; ++i) {
+          double th = 0.0;
+          for (int k = 0; k < nq; ++k)
+            if (bit(i, k) && !(side == 0 && k == q)) th += a[k];
+          for (int j = 0; j < dc; ++j) {
+            double ch = 0.0;
+            for (int k = 0; k < nq; ++k)
+              if (bit(j, k) && !(side == 1 && k == q)) ch += c[k];
+            const cd x = W[(size_t)i * dc + j] * std::polar(1.0, th + ch);
+            if ((side == 0 ? bit(i, q) : bit(j, q)) != 0)
+              B += x;
+            else
+              A += x;
+          }
+        }
+        if (A != 0.0 && B != 0.0) (side == 0 ? a : c)[q] = std::arg(A) - std::arg(B);
+      }
+    const double t = std::abs(zcomp_tau(W, nq, a, c));
+    const bool done = t - best <= 1e-14 * std::max(1.0, t);
+    best = std::max(best, t);
+    if (done) break;
+  }
+  tau = zcomp_tau(W, nq, a, c);
+}
+
+scp_status launch_zcomp(const void* U, int64_t D, int S, int prec, int nq, const int64_t* rows,
+                        const int32_t* cols, const void* target, void* block, void* tau_out,
+                        double* F_out, double* phases_out, void* cot, hipStream_t s) {
+  const int dc = 1 << nq;
+  hipError_t e = prec == 0 ? run_zcomp_block<float2>(U, D, S, dc, rows, cols, block, s)
+                           : run_zcomp_block<double2>(U, D, S, dc, rows, cols, block, s);
+  if (e != hipSuccess) return fail(SCP_EHIP, std::string("zcomp block: ") + hipGetErrorString(e));
+  std::vector<cd> M((size_t)dc * dc), T((size_t)dc * dc), W((size_t)dc * dc);
+  HIPCHK(hipMemcpyAsync(M.data(), block, M.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(T.data(), target, T.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (size_t k = 0; k < W.size(); ++k) W[k] = std::conj(T[k]) * M[k];
+  std::vector<double> a, c;
+  cd tau;
+  zcomp_optimise(W, nq, a, c, tau);
+  *F_out = std::norm(tau) / ((double)dc * dc);
+  if (!std::isfinite(*F_out)) return fail(SCP_ENONFINITE, "fidelity is not finite");
+  if (phases_out) {
+    for (int q = 0; q < nq; ++q) {
+      phases_out[q] = a[q];
+      phases_out[nq + q] = c[q];
+    }
+  }
+  const double2 t2 = make_double2(tau.real(), tau.imag());
+  if (tau_out) {
+    HIPCHK(hipMemcpyAsync(tau_out, &t2, sizeof(double2), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  if (cot) {
+    ZPhases ph;
+    for (int i = 0; i < dc; ++i) {
+      double th = 0.0, ch = 0.0;
+      for (int q = 0; q < nq; ++q)
+        if ((i >> (nq - 1 - q)) & 1) {
+          th += a[q];
+          ch += c[q];
+        }
+      ph.th[i] = th;
+      ph.ch[i] = ch;
+    }
+    e = prec == 0 ? run_zcomp_cot<float2>(cot, D, S, dc, rows, cols, target, ph, t2, s)
+                  : run_zcomp_cot<double2>(cot, D, S, dc, rows, cols, target, ph, t2, s);
+    if (e != hipSuccess) return fail(SCP_EHIP, std::string("zcomp cotangent: ") + hipGetErrorString(e));
+  }
+  return SCP_OK;
+}
 
 scp_status launch_fidelity(const void* U, int64_t D, int S, int prec, int dc, const int64_t* rows,
                            const int32_t* cols, const void* target, void* tau, void* cot,

@@ -26,6 +26,9 @@ hipError_t launch_tables_impl(int d, int nslots, int npairs, int ndrives, int ng
                               const int* smode, const int* pmode, float2* optab, int block_q,
                               const void* drives, const double* par, float* ctab, float* dctab,
                               double* dctab64, double* ctab64, hipStream_t s);
+scp_status launch_zcomp(const void* U, int64_t D, int S, int prec, int nq, const int64_t* rows,
+                        const int32_t* cols, const void* target, void* block, void* tau_out,
+                        double* F_out, double* phases_out, void* cot, hipStream_t s);
 hipError_t launch_phase_table(int d, int NT, int NR, int RB, int thr, int row, int nsteps,
                               double h, const double* frames, const int* tmode, const int* rmode,
                               float2* ph, hipStream_t s);
@@ -904,6 +907,19 @@ scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, 
     if (!std::isfinite(*F_out)) return fail(SCP_ENONFINITE, "fidelity is not finite");
   }
   return SCP_OK;
+}
+
+scp_status scp_fidelity_zcomp(const void* U, int64_t D, int32_t S, int32_t precision,
+                              int32_t n_qubits, const int64_t* comp_rows, const int32_t* comp_cols,
+                              const void* target, void* block_out, void* tau_out, double* F_out,
+                              double* phases_out, void* cotangent, void* stream) {
+  g_err.clear();
+  if (!U || !comp_rows || !comp_cols || !target || !block_out || !F_out)
+    return fail(SCP_EINVAL, "null argument");
+  if (D < 1 || S < 1 || n_qubits < 1 || n_qubits > 6 || (precision != 0 && precision != 1))
+    return fail(SCP_EINVAL, "bad sizes (n_qubits must be 1..6)");
+  return launch_zcomp(U, D, S, precision, n_qubits, comp_rows, comp_cols, target, block_out,
+                      tau_out, F_out, phases_out, cotangent, (hipStream_t)stream);
 }
 
 scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, void* workspace,

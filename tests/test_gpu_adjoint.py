@@ -294,3 +294,64 @@ def test_config5_full_length_gradient_against_stored_oracle(scp):
     F1, g1 = gpu_loss_and_grad(scp, d1)
     assert abs(F1 - nu["F"]) <= DF_TOL
     check_grad(g1, np.array(nu["grad"]))
+
+
+def _wrap(x):
+    return (np.asarray(x) + np.pi) % (2 * np.pi) - np.pi
+
+
+def test_zcomp_fidelity_matches_oracle_on_the_same_block(scp):
+    """The library's gather and host-side phase search against the oracle's on
+    the same FP32 block (a phase-rephased target plus noise, 3 qubits)."""
+    from oracle.fidelity import zcomp_fidelity, comp_bits
+    rng = np.random.default_rng(21)
+    n, D, S = 3, 40, 8
+    z = rng.normal(size=(8, 8)) + 1j * rng.normal(size=(8, 8))
+    T, r = np.linalg.qr(z)
+    T = T * (np.diag(r) / np.abs(np.diag(r)))
+    b = comp_bits(n)
+    M = np.exp(-1j * (b @ rng.uniform(0, 6.3, n)))[:, None] * T * \
+        np.exp(-1j * (b @ rng.uniform(0, 6.3, n)))[None, :]
+    M = M + 0.05 * (rng.normal(size=(8, 8)) + 1j * rng.normal(size=(8, 8)))
+    rows = [3, 7, 11, 12, 20, 25, 31, 39]
+    U = np.zeros((S, D), dtype=np.complex64)
+    for i, rr in enumerate(rows):
+        for j in range(S):
+            U[j, rr] = M[i, j]
+    Ug = torch.tensor(U, device="cuda")
+    tgt = scp.Target(rows, list(range(S)), T)
+    F, a, c = scp.fidelity_zcomp(Ug, tgt, n)
+    Fo, ao, co, tau = zcomp_fidelity(U[:, rows].T.astype(np.complex128), T, n)
+    assert abs(F - Fo) <= 1e-12
+    assert np.abs(_wrap(a - ao)).max() <= 1e-9 and np.abs(_wrap(c - co)).max() <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["ring3_d4", "fluxonium2_d5"])
+def test_zcomp_gradient_matches_oracle(scp, name):
+    """Compensated infidelity and its gradient (the adjoint seeded with the
+    costate at the optimal phases) against the oracle's."""
+    from oracle.fidelity import zcomp_fidelity, zcomp_target
+    desc = CASES[name]()
+    n = int(np.log2(len(desc["comp_rows"])))
+    print(f"[adjoint] zcomp {name}", flush=True)
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, desc["columns"])
+    opts = g.opts(psi0.shape[0], with_ckpt=1)
+    ws = g.workspace(opts, with_grad=True)
+    U = g.propagate(psi0, opts=opts, workspace=ws)
+    cot = torch.empty_like(U)
+    tgt = scp.Target(desc["comp_rows"], desc["comp_cols"], desc["target"])
+    F, a, c = scp.fidelity_zcomp(U, tgt, n, cotangent=cot)
+    grad = g.adjoint(cot, opts, ws)
+    g.close()
+    o = OracleSystem(desc)
+    Lo, Fo_plain, tau, Uo, _ = loss_and_grad(o)
+    Mo = Uo[np.ix_(desc["comp_rows"], desc["comp_cols"])]
+    Fo, ao, co, _ = zcomp_fidelity(Mo, desc["target"], n)
+    assert Fo >= Fo_plain
+    assert abs(F - Fo) <= DF_TOL
+    d2 = copy.deepcopy(desc)
+    d2["target"] = zcomp_target(desc["target"], ao, co)
+    _, F2, _, _, go = loss_and_grad(OracleSystem(d2))
+    assert abs(F2 - Fo) <= 1e-12
+    check_grad(grad, go)

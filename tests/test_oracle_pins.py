@@ -427,7 +427,7 @@ def test_envelopes_and_carrier_at_known_times():
 
 # --- phase (virtual-Z) compensation of the fidelity --------------------------
 
-def _haar(rng, n):
+def _haar_u(rng, n):
     z = (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) / np.sqrt(2)
     q, r = np.linalg.qr(z)
     return q * (np.diag(r) / np.abs(np.diag(r)))
@@ -446,7 +446,7 @@ def test_zcomp_recovers_phase_rephased_targets():
     rng = np.random.default_rng(11)
     cz = np.diag([1, 1, 1, -1]).astype(complex)
     cnot = np.array([[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 0, 1], [0, 0, 1, 0]], complex)
-    for T in (cz, cnot, _haar(rng, 4), _haar(rng, 8)):
+    for T in (cz, cnot, _haar_u(rng, 4), _haar_u(rng, 8)):
         n = int(np.log2(T.shape[0]))
         a0, c0 = rng.uniform(0, 2 * np.pi, n), rng.uniform(0, 2 * np.pi, n)
         M = _rephase(T, a0, c0)
@@ -463,7 +463,7 @@ def test_zcomp_matches_brute_force_grid():
     rng = np.random.default_rng(12)
     for n, grid in ((1, 256), (2, 24)):
         dc = 2 ** n
-        T = _haar(rng, dc)
+        T = _haar_u(rng, dc)
         M = _rephase(T, rng.uniform(0, 6.3, n), rng.uniform(0, 6.3, n))
         M = M + 0.15 * (rng.normal(size=(dc, dc)) + 1j * rng.normal(size=(dc, dc)))
         F, a, c, tau = zcomp_fidelity(M, T, n)
@@ -482,7 +482,7 @@ def test_zcomp_is_never_below_the_plain_fidelity():
     rng = np.random.default_rng(13)
     for _ in range(20):
         M = rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4))
-        T = _haar(rng, 4)
+        T = _haar_u(rng, 4)
         F0 = fidelity(M, range(4), range(4), T)[0]
         assert zcomp_fidelity(M, T, 2)[0] >= F0 - 1e-15
 
@@ -493,7 +493,7 @@ def test_zcomp_cotangent_is_the_plain_one_of_the_rephased_target():
     at every point)."""
     from oracle.fidelity import zcomp_fidelity, zcomp_target, cotangent, overlap
     rng = np.random.default_rng(14)
-    T = _haar(rng, 4)
+    T = _haar_u(rng, 4)
     M = _rephase(T, rng.uniform(0, 6.3, 2), rng.uniform(0, 6.3, 2))
     M = M + 0.1 * (rng.normal(size=(4, 4)) + 1j * rng.normal(size=(4, 4)))
     F, a, c, tau = zcomp_fidelity(M, T, 2)
