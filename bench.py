@@ -192,6 +192,19 @@ def other_configs(scp, si, torch, np):
                "steps_dim2_per_s_forward": N * g.D * S / (fwd_ms * 1e-3),
                "forward_tflops": fwd_flop / (fwd_ms * 1e-3) / 1e12,
                "plain_fp64_forward_ms": p64, "F": F, "n_params": len(grad)}
+        # plain and phase-compensated fidelity of the same U (wall time of the
+        # calls, each synchronising: gather on the device, phase search on the host)
+        nq = int(round(np.log2(len(desc["comp_rows"]))))
+        if 2 ** nq == len(desc["comp_rows"]) and nq <= 6:
+            tf = []
+            for fn in (lambda: scp.fidelity(U, tgt, cotangent=cot),
+                       lambda: scp.fidelity_zcomp(U, tgt, nq, cotangent=cot)):
+                fn()
+                t0 = time.perf_counter()
+                for _ in range(10):
+                    r = fn()
+                tf.append((time.perf_counter() - t0) / 10 * 1e3)
+            out.update({"fidelity_ms": tf[0], "fidelity_zcomp_ms": tf[1], "F_zcomp": r[0]})
         if ref_path and os.path.exists(ref_path):
             ref = json.load(open(ref_path))
             gref = np.array(ref["grad"])
