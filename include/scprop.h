@@ -169,6 +169,24 @@ scp_status scp_system_carriers(const scp_system* sys, double* omega);
 scp_status scp_system_frame(const scp_system* sys, int32_t* real_frame);
 scp_status scp_system_set_frame(scp_system* sys, int32_t real_frame);
 
+/* Static spectrum (Sec. 3.2): the composite static Hamiltonian
+ * H0 = sum_m diag(eps_m) + sum_e g_e A_i (x) B_j in the dressed single-mode
+ * bases (drives excluded) is diagonalised in FP64 on the device (D <= 96).
+ * Every bare product state k (natural order, mode 0 slowest) is labelled
+ * with the eigenvector of largest overlap |<k|v>|^2 (ties to the lowest
+ * eigenvector index).  scp_energy_tensor writes the labelled energies
+ * E_out[k] (host, D doubles, rad/ns).  scp_static_zz writes the static
+ * longitudinal coupling of modes (qi, qj) with every other mode in its
+ * ground state, zeta = E(0) + E(1_i 1_j) - E(1_i) - E(1_j) (rad/ns), and
+ * (grad_out, host, nullable, n_params doubles in the gradient order of
+ * scp_system_info) d zeta / d theta from <v| dH0 |v> over the four levels
+ * (Hellmann-Feynman; drive parameters get 0).  Both synchronise the stream
+ * and allocate temporary device memory.  Errors: SCP_EINVAL (D > 96, a
+ * complex static Hamiltonian, a bad pair), SCP_ENONFINITE, SCP_EHIP. */
+scp_status scp_energy_tensor(const scp_system* sys, double* E_out, void* stream);
+scp_status scp_static_zz(const scp_system* sys, int32_t qi, int32_t qj, double* zeta_out,
+                         double* grad_out, void* stream);
+
 /* Workspace bytes a propagate (+ adjoint if with_grad) needs for opts. */
 scp_status scp_workspace_size(const scp_system* sys, const scp_solve_opts* opts, int32_t with_grad,
                               size_t* bytes);

@@ -127,6 +127,21 @@ class System:
         """Choose the real-frame (True) or the complex (False) evaluation."""
         check(lib().scp_system_set_frame(self.handle, 1 if enable else 0))
 
+    def energy_tensor(self, stream=None):
+        """Dressed energies labelled by bare product states (D,), rad/ns."""
+        E = (C.c_double * int(self.D))()
+        check(lib().scp_energy_tensor(self.handle, E, _stream_ptr(stream)))
+        return np.array(E[:])
+
+    def static_zz(self, i, j, with_grad=False, stream=None):
+        """Static ZZ coupling of modes (i, j) (rad/ns) and, optionally, its
+        gradient in the library's parameter order."""
+        z = C.c_double()
+        g = (C.c_double * max(1, self.n_params))() if with_grad else None
+        check(lib().scp_static_zz(self.handle, int(i), int(j), C.byref(z), g,
+                                  _stream_ptr(stream)))
+        return (z.value, np.array(g[: self.n_params])) if with_grad else z.value
+
     def opts(self, n_cols, precision=0, ckpt_every=0, with_ckpt=0):
         o = SolveOpts()
         o.n_cols, o.precision, o.ckpt_every, o.with_ckpt = int(n_cols), int(precision), \

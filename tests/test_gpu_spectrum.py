@@ -1,0 +1,102 @@
+"""GPU parity of the static spectrum (bare-labelled dressed energies and the
+static ZZ coupling with its gradient) against the CPU FP64 oracle."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import scp_inputs as si
+from oracle.system import OracleSystem
+from oracle.spectrum import dressed_energies, static_zz, static_zz_grad
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def scp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_18155_amd as m
+    return m
+
+
+def _multipath_chain(jc_mhz, jl_mhz, d):
+    fix = json.load(open(os.path.join(GOLDEN, "static_zz_paper.json")))
+    modes = [{"kind": "fluxonium", "EC": q["EC"] * 2 * np.pi, "EJ": q["EJ"] * 2 * np.pi,
+              "EL": q["EL"] * 2 * np.pi, "phiext": np.pi, "basis_dim": 80, "trunc": d}
+             for q in fix["fluxonium"]]
+    coup = []
+    for (i, j) in ((0, 1), (1, 2)):
+        coup.append({"i": i, "j": j, "op_i": "n", "op_j": "n", "g": jc_mhz * 1e-3 * 2 * np.pi})
+        coup.append({"i": i, "j": j, "op_i": "phi", "op_j": "phi",
+                     "g": -jl_mhz * 1e-3 * 2 * np.pi})
+    return {"modes": modes, "couplings": coup, "drives": [], "T": 1.0, "n_steps": 1}
+
+
+def _ring(n_modes, d):
+    s = si.transmon_ring(si.rng_for(7, 3), n_modes, d, 2.0, 10)
+    return si._finish(s, [d] * n_modes, target=si.cz_target(n_modes))
+
+
+CASES = {
+    "transmon2_d4": lambda: si.config1(),
+    "fluxonium3_d4_paper_chain": lambda: _multipath_chain(12.0, 2.0, 4),
+    "ring4_d3": lambda: _ring(4, 3),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_energy_tensor_and_static_zz_match_oracle(scp, name):
+    desc = CASES[name]()
+    print(f"[spectrum] {name}", flush=True)
+    g = scp.System(desc)
+    E = g.energy_tensor()
+    o = OracleSystem(desc)
+    Eo = dressed_energies(o)[0]
+    assert np.abs(E - Eo).max() <= 1e-10 * np.abs(Eo).max()
+    for (i, j) in ((0, 1), (1, g.n_modes - 1)):
+        if i == j:
+            continue
+        z, gz = g.static_zz(i, j, with_grad=True)
+        zo = static_zz(o, i, j)
+        go = static_zz_grad(o, i, j)
+        # zeta is a difference of four energies: its error scales with them
+        assert abs(z - zo) <= 1e-12 * np.abs(Eo).max()
+        assert gz.shape == go.shape
+        assert np.abs(gz - go).max() <= 1e-7 * np.abs(go).max()
+    g.close()
+
+
+def test_static_zz_zero_matches_the_oracle(scp):
+    """The J_C zeroing zeta_ZZI of the paper's chain (d = 4) from GPU
+    evaluations equals the oracle's (the oracle meets the paper's 12.25 MHz
+    at d = 5)."""
+    from scipy.optimize import brentq
+
+    def zg(jc):
+        s = scp.System(_multipath_chain(jc, 2.0, 4))
+        z = s.static_zz(0, 1)
+        s.close()
+        return z
+
+    zo = lambda jc: static_zz(OracleSystem(_multipath_chain(jc, 2.0, 4)), 0, 1)
+    rg = brentq(zg, 5.0, 20.0, xtol=1e-7)
+    ro = brentq(zo, 5.0, 20.0, xtol=1e-7)
+    assert abs(rg - ro) <= 1e-5
+
+
+def test_static_spectrum_refuses_large_or_complex_systems(scp):
+    big = _ring(5, 3)                         # D = 243 > 96
+    g = scp.System(big)
+    with pytest.raises(scp.ScpError):
+        g.static_zz(0, 1)
+    g.close()
+    raw = si.random_raw_system(5, [2, 2, 2], 3, 1.0, 20, env="gauss")   # complex operators
+    g = scp.System(raw)
+    with pytest.raises(scp.ScpError):
+        g.energy_tensor()
+    g.close()
