@@ -212,7 +212,54 @@ def other_configs(scp, si, torch, np):
                         "grad_rel_err": float(np.abs(grad - gref).max() / np.abs(gref).max())})
         g.close()
         lines.append(out)
+    lines.append(static_spectrum_line(scp, np))
     return lines
+
+
+def static_spectrum_line(scp, np):
+    """Static ZZ of the paper's three-fluxonium multipath chain (Sec. 3.2) at
+    d = 4 (D = 64): call times on the GPU path and of the oracle, and the J_C
+    that zeroes zeta_ZZI at J_L = 2 MHz from GPU evaluations."""
+    from scipy.optimize import brentq
+    from oracle.system import OracleSystem
+    from oracle.spectrum import static_zz, static_zz_grad
+    fix = json.load(open(os.path.join(ROOT, "tests", "golden", "static_zz_paper.json")))
+
+    def chain(jc):
+        modes = [{"kind": "fluxonium", "EC": q["EC"] * 2 * math.pi, "EJ": q["EJ"] * 2 * math.pi,
+                  "EL": q["EL"] * 2 * math.pi, "phiext": math.pi, "basis_dim": 80, "trunc": 4}
+                 for q in fix["fluxonium"]]
+        coup = []
+        for (i, j) in ((0, 1), (1, 2)):
+            coup.append({"i": i, "j": j, "op_i": "n", "op_j": "n", "g": jc * 1e-3 * 2 * math.pi})
+            coup.append({"i": i, "j": j, "op_i": "phi", "op_j": "phi",
+                         "g": -fix["J_L_MHz"] * 1e-3 * 2 * math.pi})
+        return {"modes": modes, "couplings": coup, "drives": [], "T": 1.0, "n_steps": 1}
+
+    g = scp.System(chain(12.0))
+    g.static_zz(0, 1, with_grad=True)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        g.static_zz(0, 1, with_grad=True)
+    gpu_ms = (time.perf_counter() - t0) / 10 * 1e3
+    g.close()
+    o = OracleSystem(chain(12.0))
+    t0 = time.perf_counter()
+    static_zz(o, 0, 1)
+    static_zz_grad(o, 0, 1)
+    oracle_ms = (time.perf_counter() - t0) * 1e3
+
+    def zg(jc):
+        s = scp.System(chain(jc))
+        z = s.static_zz(0, 1)
+        s.close()
+        return z
+
+    return {"config": "static ZZ: paper's 3-fluxonium multipath chain, d=4 (D=64), J_L=2 MHz",
+            "static_zz_with_grad_ms": gpu_ms, "oracle_static_zz_with_grad_ms": oracle_ms,
+            "J_C_zero_MHz_d4": brentq(zg, 5.0, 20.0, xtol=1e-6),
+            "paper_J_C_MHz": fix["J_C_opt_MHz"],
+            "note": "the oracle at d=5 gives 12.250 MHz (pinned); d=4 truncates the chain"}
 
 
 def sampled_desc(si, np):
