@@ -174,7 +174,9 @@ scp_status scp_system_set_frame(scp_system* sys, int32_t real_frame);
  * bases (drives excluded) is diagonalised in FP64 on the device (D <= 96).
  * Every bare product state k (natural order, mode 0 slowest) is labelled
  * with the eigenvector of largest overlap |<k|v>|^2 (ties to the lowest
- * eigenvector index).  scp_energy_tensor writes the labelled energies
+ * eigenvector index; labels are not forced to be distinct, so near a
+ * degeneracy two bare states can share an eigenvector and zeta loses its
+ * meaning).  scp_energy_tensor writes the labelled energies
  * E_out[k] (host, D doubles, rad/ns).  scp_static_zz writes the static
  * longitudinal coupling of modes (qi, qj) with every other mode in its
  * ground state, zeta = E(0) + E(1_i 1_j) - E(1_i) - E(1_j) (rad/ns), and
