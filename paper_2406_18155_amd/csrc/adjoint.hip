@@ -644,9 +644,11 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
           }
         }
         kptr<c32> prw = ph + (size_t)stage_q(n, s) * prow;
+        // thread part of the stage's frame phase (also for yb at the end)
+        c32 pt{1.f, 0.f};
+        if constexpr (RF) pt = thread_phase<d>(prw + pthr, NT, tc);
         if constexpr (RF) {
           // into the frame: kb <- D^dag kb, y <- D^dag y
-          const c32 pt = thread_phase<d>(prw + pthr, NT, tc);
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
             const c32 e = elem_phase<true>(pt, (kptr<c32x8>)prw, r);
@@ -678,7 +680,6 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
                                      cq, dcq, yb);
         if constexpr (RF) {
           // back to the interaction picture: yb <- D yb
-          const c32 pt = thread_phase<d>(prw + pthr, NT, tc);
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
             const c32 e = elem_phase<false>(pt, (kptr<c32x8>)prw, r);

@@ -556,7 +556,8 @@ __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int 
                                          kptr<c32> optab, kptr<float> rops, kptr<float> ctab,
                                          kptr<c32> ph, int n,
                                          Vec<RB>& hi, Vec<RB>& lo, int& iy, int& ka, int& kb,
-                                         c32* __restrict__ ystore, size_t ystride) {
+                                         c32* __restrict__ ystore, size_t ystride,
+                                         int& pq, c32& pt_q) {
   const float h = P->h;
   const int ng = uni(P->ngroups);
   const int bq = uni(P->block_q);
@@ -566,12 +567,22 @@ __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int 
   const int pthr = RF ? uni(P->ph_thr) : 0;
   const int tbB = thread_base<d>(P, L - 1, tc);
   const RegOff<d, NR> RB_ = reg_off_of<d, NR>(P, L - 1);
+  // the thread part of the frame phase of half-step row q, recomputed only
+  // when the row changes (y_s and k_s share a row, stages 1 and 2 share one,
+  // and a step's last row is the next step's first); pq < 0: none cached
+  auto tphase = [&](int q) -> c32 {
+    if (q != pq) {
+      pt_q = thread_phase<d>(ph + (size_t)q * prow + pthr, NT, tc);
+      pq = q;
+    }
+    return pt_q;
+  };
   // y_0 = hi
   {
     c32* yb = lds + ka * rstride + cbase + tbB;
     c32* ys = ystore != nullptr ? ystore + tbB : nullptr;
     kptr<c32> row = ph + (size_t)stage_q(n, 0) * prow;
-    const c32 pt = RF ? thread_phase<d>(row + pthr, NT, tc) : c32{1.f, 0.f};
+    const c32 pt = RF ? tphase(stage_q(n, 0)) : c32{1.f, 0.f};
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       c32 v;
@@ -617,7 +628,7 @@ __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int 
     if (RF) {
       // back to the interaction picture: k <- D(t_s) k
       kptr<c32> row = ph + (size_t)stage_q(n, s) * prow;
-      const c32 pt = thread_phase<d>(row + pthr, NT, tc);
+      const c32 pt = tphase(stage_q(n, s));
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const c32 e = elem_phase<false>(pt, (kptr<c32x8>)row, r);
@@ -646,7 +657,7 @@ __device__ __forceinline__ void rk4_step(kptr<Plan> P, c32* lds, int cbase, int 
       c32* yb = lds + ka * rstride + cbase + tbB;
       c32* ys = ystore != nullptr ? ystore + (size_t)(s + 1) * ystride + tbB : nullptr;
       kptr<c32> row = ph + (size_t)stage_q(n, s + 1) * prow;
-      const c32 pt = RF ? thread_phase<d>(row + pthr, NT, tc) : c32{1.f, 0.f};
+      const c32 pt = RF ? tphase(stage_q(n, s + 1)) : c32{1.f, 0.f};
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         c32 v;

@@ -91,6 +91,8 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
     }
   }
   int iy = 0, ka = 1, kb = 2;   // LDS regions: stage input, k moves
+  int pq = -1;                  // real frame: half-step row of the cached thread phase
+  c32 pt_q{1.f, 0.f};
   for (int n = n0; n < n1; ++n) {
     if (ckpt != nullptr && n % ckpt_every == 0 && active) {
       c32x2* dst = ckpt + ((size_t)(n / ckpt_every) * S + col) * D + tc;
@@ -109,10 +111,10 @@ __device__ __forceinline__ void rk4_block(const FwdItem& I) {
                                   ctab, ph, n, hi, lo, iy, ka, kb,
                                   (c32*)I.ystore + (size_t)(active ? col : 0) * D +
                                       (size_t)(n - n0) * 4 * S * D,
-                                  (size_t)S * D);
+                                  (size_t)S * D, pq, pt_q);
     else
       rk4_step<d, NR, MP, RB, RF>(P, lds, cbase, vstride, lds_ok, active, tc, TPC, optab, rops,
-                                  ctab, ph, n, hi, lo, iy, ka, kb, nullptr, 0);
+                                  ctab, ph, n, hi, lo, iy, ka, kb, nullptr, 0, pq, pt_q);
   }
   if (!active) return;
   if (state_hi != nullptr) {
