@@ -220,11 +220,6 @@ scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, 
                         const int64_t* comp_rows, const int32_t* comp_cols, const void* target,
                         void* tau_out, void* cotangent, double* F_out, void* stream);
 
-/* Gradient of L w.r.t. every parameter (host FP64, n_params entries in the
- * order of scp_system_info), given the costate of the final state.  Needs
- * the checkpoints of the immediately preceding scp_propagate on the same
- * workspace with with_ckpt = 1 and the same opts.  Synchronises ``stream``.
- * SCP_ENONFINITE if any gradient entry is not finite. */
 /* Fidelity with error-free single-qubit phase gates before and after the
  * gate (the compensation of App. D, restricted to Z rotations: virtual Z).
  * d_c = 2^n_qubits computational states, in binary order with qubit 0 most
@@ -250,8 +245,50 @@ scp_status scp_fidelity_zcomp(const void* U, int64_t D, int32_t S, int32_t preci
                               const void* target, void* block_out, void* tau_out, double* F_out,
                               double* phases_out, void* cotangent, void* stream);
 
+/* Gradient of L w.r.t. every parameter (host FP64, n_params entries in the
+ * order of scp_system_info), given the costate of the final state.  Needs
+ * the checkpoints of the immediately preceding scp_propagate on the same
+ * workspace with with_ckpt = 1 and the same opts.  Synchronises ``stream``.
+ * SCP_ENONFINITE if any gradient entry is not finite. */
 scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, void* workspace,
                                  const void* cotangent, double* grad_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Suzuki-Trotter product formulas (Sec. 2.3 Trotterization solver, App. A).
+ *
+ * The step propagator is a product of exponentials of local terms, in this
+ * order: one single-mode term per mode (lab frame),
+ *   H_m(t) = diag(eps_m) + sum_{drives k on m} c_k(t) O_k,
+ * then one two-body term g_e A_i (x) B_j per coupling.  Q1 applies
+ * exp(-i H_k dt) for k = 1..K; the symmetric piece Q2(a dt) applies
+ * exp(-i a H_k dt/2) for k = 1..K and then k = K..1; Q2 is one piece with
+ * a = 1, Q4 the pieces a = (p, 1-2p, p) with p = 1/(2 - 2^(1/3)), Q4J the
+ * pieces a = (p, conj p) with p = (3 - i sqrt 3)/6.  Time-dependent terms
+ * are frozen at the middle of their piece (Q4J: of the step).  Q4J is not
+ * unitary; as printed it is third order for static terms and second order
+ * for driven ones (Q1: first, Q2: second, Q4: fourth).
+ * ------------------------------------------------------------------------ */
+enum { SCP_TROTTER_Q1 = 0, SCP_TROTTER_Q2 = 1, SCP_TROTTER_Q4 = 2, SCP_TROTTER_Q4J = 3 };
+
+/* Device workspace bytes of scp_propagate_trotter: inputs, the pair gates
+ * of every (piece, coupling) and the single-mode gates of every (step,
+ * piece, mode), all complex FP64.  SCP_EINVAL for an unknown order or a
+ * system outside the path's limits (d = 2..5, 16 D bytes <= 160 KiB,
+ * <= 48 couplings, <= 32 drives). */
+scp_status scp_trotter_workspace_size(const scp_system* sys, int32_t order, size_t* bytes);
+
+/* Propagate the n_cols columns psi0 (device, complex128, D x n_cols
+ * column-major) over the system's n_steps steps of dt = T / n_steps with
+ * the product formula ``order`` into psiT (same layout; may alias psi0).
+ * Everything is complex FP64 on the device: the gates are formed by Taylor
+ * scaling and squaring, and one workgroup per column keeps the column in
+ * LDS.  The result is rotated into the frame of scp_propagate,
+ * psi_I(T) = exp(i H_f T) psi_lab(T), so both paths compare directly.
+ * workspace: device, scp_trotter_workspace_size bytes, caller-owned.
+ * Synchronises the stream once, before the first kernel (upload of the
+ * inputs).  Errors: SCP_EINVAL, SCP_EHIP. */
+scp_status scp_propagate_trotter(scp_system* sys, int32_t order, int32_t n_cols, void* workspace,
+                                 const void* psi0, void* psiT, void* stream);
 
 void scp_destroy(scp_system* sys);
 

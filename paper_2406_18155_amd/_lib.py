@@ -56,6 +56,9 @@ EXPORTS = {
     "scp_system_carriers": (C.c_int, [C.c_void_p, C.POINTER(C.c_double)]),
     "scp_system_frame": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "scp_energy_tensor": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "scp_trotter_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_size_t)]),
+    "scp_propagate_trotter": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]),
     "scp_static_zz": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                 C.POINTER(C.c_double), C.c_void_p]),
     "scp_fidelity_zcomp": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,

@@ -142,6 +142,28 @@ class System:
                                   _stream_ptr(stream)))
         return (z.value, np.array(g[: self.n_params])) if with_grad else z.value
 
+    # -- Suzuki-Trotter product formulas (complex FP64) -------------------
+    TROTTER = {"q1": 0, "q2": 1, "q4": 2, "q4j": 3}
+
+    def trotter_workspace_bytes(self, order):
+        n = C.c_size_t()
+        check(lib().scp_trotter_workspace_size(self.handle, self.TROTTER[order], C.byref(n)))
+        return n.value
+
+    def propagate_trotter(self, psi0, order="q2", psiT=None, workspace=None, stream=None):
+        """psi_I(T) of the columns psi0 (S, D) complex128 by a product formula
+        ("q1", "q2", "q4", "q4j"), in the frame of ``propagate``."""
+        assert psi0.dtype == torch.complex128 and psi0.is_contiguous() and psi0.shape[1] == self.D
+        if psiT is None:
+            psiT = torch.empty_like(psi0)
+        if workspace is None:
+            workspace = torch.empty(self.trotter_workspace_bytes(order), dtype=torch.uint8,
+                                    device=psi0.device)
+        check(lib().scp_propagate_trotter(self.handle, self.TROTTER[order], psi0.shape[0],
+                                          _ptr(workspace), _ptr(psi0), _ptr(psiT),
+                                          _stream_ptr(stream)))
+        return psiT
+
     def opts(self, n_cols, precision=0, ckpt_every=0, with_ckpt=0):
         o = SolveOpts()
         o.n_cols, o.precision, o.ckpt_every, o.with_ckpt = int(n_cols), int(precision), \

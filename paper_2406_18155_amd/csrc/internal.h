@@ -138,6 +138,24 @@ struct ModeData {
 };
 
 struct Coupling { int i, j, op_i, op_j; double g; };
+
+// Basis function i of a drive envelope at time t of step n (App. C pulse
+// shapes): the envelope is sum_i par_i * envelope_basis(.., i, ..).
+__device__ inline double envelope_basis(int env, int i, int npar, long n, int nsteps, double t,
+                                        double T, double sigma) {
+  if (env == SCP_ENV_GAUSS) {
+    const double u = (t - 0.5 * T) / sigma;
+    return exp(-0.5 * u * u);
+  }
+  if (env == SCP_ENV_GAUSS_BASIS) {
+    const double u = (t - (i + 0.5) * T / npar) / sigma;
+    return exp(-0.5 * u * u);
+  }
+  if (env == SCP_ENV_COS_RAMP) return 0.5 * (1.0 - cos(6.283185307179586476925286766559 * t / T));
+  if (env == SCP_ENV_CONST) return 1.0;
+  const long piece = (n * npar) / nsteps;   // SCP_ENV_PWC: the piece of step n
+  return (piece == i) ? 1.0 : 0.0;
+}
 struct Drive {
   int mode, op, env;
   double omega, phase, sigma;
@@ -208,5 +226,9 @@ scp_status launch_fidelity(const void* U, int64_t D, int S, int prec, int dc, co
                            hipStream_t s);
 scp_status launch_plain64(scp_system* sys, const double2* psi0, double2* psiT, void* work, int S,
                           hipStream_t s);
+scp_status trotter_check(const scp_system* sys, int order);
+size_t trotter_workspace_bytes(const scp_system* sys, int order);
+scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const double2* psi0,
+                          double2* psiT, hipStream_t st);
 
 }  // namespace scp

@@ -888,6 +888,24 @@ scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* work
                     w.ce, opts->n_cols, st);
 }
 
+scp_status scp_trotter_workspace_size(const scp_system* sys, int32_t order, size_t* bytes) {
+  g_err.clear();
+  if (!sys || !bytes) return fail(SCP_EINVAL, "null argument");
+  scp_status st = trotter_check(sys, order);
+  if (st != SCP_OK) return st;
+  *bytes = trotter_workspace_bytes(sys, order);
+  return SCP_OK;
+}
+
+scp_status scp_propagate_trotter(scp_system* sys, int32_t order, int32_t n_cols, void* workspace,
+                                 const void* psi0, void* psiT, void* stream) {
+  g_err.clear();
+  if (!sys || !workspace || !psi0 || !psiT) return fail(SCP_EINVAL, "null argument");
+  if (n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  return launch_trotter(sys, order, n_cols, workspace, (const double2*)psi0, (double2*)psiT,
+                        (hipStream_t)stream);
+}
+
 scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, int32_t d_c,
                         const int64_t* comp_rows, const int32_t* comp_cols, const void* target,
                         void* tau_out, void* cotangent, double* F_out, void* stream) {

@@ -110,21 +110,7 @@ __global__ void ctable_kernel(TabStatic ts, const DriveStatic* __restrict__ dr,
     const double* pp = par + D.par0;
     double val = 0.0;
     for (int i = 0; i < D.npar; ++i) {
-      double basis = 0.0;
-      if (D.env == SCP_ENV_GAUSS) {
-        const double u = (t - 0.5 * ts.T) / D.sigma;
-        basis = exp(-0.5 * u * u);
-      } else if (D.env == SCP_ENV_GAUSS_BASIS) {
-        const double u = (t - (i + 0.5) * ts.T / D.npar) / D.sigma;
-        basis = exp(-0.5 * u * u);
-      } else if (D.env == SCP_ENV_COS_RAMP) {
-        basis = 0.5 * (1.0 - cos(6.283185307179586476925286766559 * t / ts.T));
-      } else if (D.env == SCP_ENV_CONST) {
-        basis = 1.0;
-      } else {  // SCP_ENV_PWC: the piece of step n
-        const long piece = ((long)n * D.npar) / ts.nsteps;
-        basis = (piece == i) ? 1.0 : 0.0;
-      }
+      const double basis = envelope_basis(D.env, i, D.npar, n, ts.nsteps, t, ts.T, D.sigma);
       val += pp[i] * basis;
       dctab[(size_t)p * ts.npulse + D.par0 + i] = (float)(basis * carrier);
       dctab64[(size_t)p * ts.npulse + D.par0 + i] = basis * carrier;

@@ -1,0 +1,472 @@
+// Suzuki-Trotter product formulas in complex FP64 (Sec. 2.3 Trotterization
+// solver, App. A higher-order decompositions, App. B local contractions).
+//
+// Local terms, in this order: one single-mode term per mode (lab frame),
+//   H_m(t) = diag(eps_m) + sum_{drives k on m} c_k(t) O_k,
+// then one two-body term g_e A_i (x) B_j per coupling.  A step is the
+// sequence of pieces of the chosen formula.  Q1 applies exp(-i H_k dt) for
+// k = 1..K; the symmetric piece Q2(a dt) applies exp(-i a H_k dt/2) for
+// k = 1..K and then for k = K..1.
+//   Q1, Q2: one piece, a = 1;
+//   Q4:  a = (p, 1 - 2p, p), p = 1 / (2 - 2^(1/3));
+//   Q4j: a = (p, conj p), p = (3 - i sqrt 3) / 6 (the printed value is
+//        garbled; this one satisfies p + conj p = 1 and p^3 + conj p^3 = 0).
+// A time-dependent term is frozen at the middle of its piece (real
+// coefficients) or of the step (Q4j, whose complex pieces have no real
+// middle).  The result is rotated into the frame of the RK4 path,
+// psi_I(T) = exp(i H_f T) psi_lab(T), H_f = sum_m diag(frame_m).
+//
+// Device work, all FP64:
+//   1. pair gates exp(-i a tau g A (x) B) for every (piece, coupling) and
+//      single-mode gates exp(-i a tau H_m(t)) for every (step, piece, mode),
+//      one workgroup per gate, by Taylor scaling and squaring in LDS (Moler
+//      and Van Loan, "Nineteen dubious ways to compute the exponential of a
+//      matrix, twenty-five years later", SIAM Review 2003, Sec. 3): halve
+//      until the 1-norm is at most 1/2, sum the series to degree 18
+//      (truncation below 1e-22 relative), square back;
+//   2. the propagation: one workgroup per state column keeps the column in
+//      LDS (16 D bytes) for all steps and applies the gates in sequence.  A
+//      thread owns whole fibres of the contracted mode(s), so a gate needs no
+//      synchronisation inside it, only a barrier before the next gate.
+#include <cmath>
+
+#include "internal.h"
+
+namespace scp {
+
+namespace {
+
+constexpr int TR_MAXD = 5;        // largest d (pair gates of dimension d^2 <= 25)
+constexpr int TR_MAXDRV = 32;
+constexpr int TR_MAXE = 48;
+constexpr int TR_MAXPIECE = 3;
+constexpr int TR_THREADS = 512;   // propagation workgroup
+constexpr int TR_MAXLDS = 160 * 1024;
+
+struct TrDrive {
+  int mode, op, env, npar, par0;
+  double omega, phase, sigma;
+};
+
+struct TrGen {
+  int d, M, E, N, r, sym, ndrives;
+  double dt, T, tau;
+  double a_re[TR_MAXPIECE], a_im[TR_MAXPIECE], mid[TR_MAXPIECE];
+  TrDrive dr[TR_MAXDRV];
+  int ci[TR_MAXE], cj[TR_MAXE], coi[TR_MAXE], coj[TR_MAXE];
+  double g[TR_MAXE];
+};
+
+struct TrRun {
+  int M, E, N, r, sym, D;
+  int stride[SCP_MAX_MODES];   // stride of mode m inside a column (mode 0 slowest)
+  int ci[TR_MAXE], cj[TR_MAXE];
+  double fT[SCP_MAX_MODES][SCP_MAX_TRUNC];   // frame energy times T, reduced mod 2 pi
+};
+
+__device__ inline double wrap_2pi(double x) {
+  const double twopi = 6.283185307179586476925286766559;
+  return x - twopi * rint(x / twopi);
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// exp(X) for the n x n matrix X (row-major, LDS) into E; T and W are LDS
+// scratch of n*n.  Every thread of the block takes part; X is overwritten.
+__device__ void expm_taylor(int n, double2* X, double2* E, double2* T, double2* W) {
+  const int nn = n * n;
+  double nrm = 0.0;
+  for (int c = 0; c < n; ++c) {
+    double s = 0.0;
+    for (int r = 0; r < n; ++r) s += sqrt(X[r * n + c].x * X[r * n + c].x + X[r * n + c].y * X[r * n + c].y);
+    nrm = fmax(nrm, s);
+  }
+  int sq = 0;
+  while (nrm > 0.5 && sq < 64) {
+    nrm *= 0.5;
+    ++sq;
+  }
+  const double scale = ldexp(1.0, -sq);
+  __syncthreads();   // every thread has read X
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    X[e].x *= scale;
+    X[e].y *= scale;
+    const double one = (e / n == e % n) ? 1.0 : 0.0;
+    E[e] = make_double2(one, 0.0);
+    T[e] = make_double2(one, 0.0);
+  }
+  __syncthreads();
+  for (int k = 1; k <= 18; ++k) {
+    const double inv = 1.0 / k;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+      const int r = e / n, c = e % n;
+      double re = 0.0, im = 0.0;
+      for (int l = 0; l < n; ++l) {
+        const double2 a = T[r * n + l], b = X[l * n + c];
+        re += a.x * b.x - a.y * b.y;
+        im += a.x * b.y + a.y * b.x;
+      }
+      W[e] = make_double2(re * inv, im * inv);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+      T[e] = W[e];
+      E[e].x += W[e].x;
+      E[e].y += W[e].y;
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < sq; ++q) {
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+      const int r = e / n, c = e % n;
+      double re = 0.0, im = 0.0;
+      for (int l = 0; l < n; ++l) {
+        const double2 a = E[r * n + l], b = E[l * n + c];
+        re += a.x * b.x - a.y * b.y;
+        im += a.x * b.y + a.y * b.x;
+      }
+      W[e] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) E[e] = W[e];
+    __syncthreads();
+  }
+}
+
+// -i a tau (times g for a pair gate): the factor of the generator.
+__device__ inline double2 gate_factor(const TrGen& G, int j, double g) {
+  return make_double2(G.a_im[j] * G.tau * g, -G.a_re[j] * G.tau * g);
+}
+
+// Pair gates: block b = j * E + e; row and column index (a_i d + a_j).
+// ops: [mode][op][d*d] dressed operators.
+__global__ void __launch_bounds__(256) tr_pair_gate_kernel(TrGen G, const double2* __restrict__ ops,
+                                                           double2* __restrict__ out) {
+  extern __shared__ double2 sh[];
+  const int d = G.d, dd = d * d, n = dd, nn = n * n;
+  double2 *X = sh, *E = sh + nn, *T = sh + 2 * nn, *W = sh + 3 * nn;
+  const int b = blockIdx.x, j = b / G.E, e = b % G.E;
+  const double2 w = gate_factor(G, j, G.g[e]);
+  const double2* A = ops + (size_t)(G.ci[e] * 2 + G.coi[e]) * dd;
+  const double2* B = ops + (size_t)(G.cj[e] * 2 + G.coj[e]) * dd;
+  for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
+    const int row = idx / n, col = idx % n;
+    const double2 ab = cmul(A[(row / d) * d + col / d], B[(row % d) * d + col % d]);
+    X[idx] = cmul(w, ab);
+  }
+  __syncthreads();
+  expm_taylor(n, X, E, T, W);
+  for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) out[(size_t)b * nn + idx] = E[idx];
+}
+
+// Single-mode gates: block b = (step * r + j) * M + m.
+__global__ void __launch_bounds__(64) tr_single_gate_kernel(TrGen G, const double* __restrict__ eps,
+                                                            const double2* __restrict__ ops,
+                                                            const double* __restrict__ par,
+                                                            double2* __restrict__ out) {
+  extern __shared__ double2 sh[];
+  const int d = G.d, n = d, nn = n * n;
+  double2 *X = sh, *E = sh + nn, *T = sh + 2 * nn, *W = sh + 3 * nn;
+  double* ck = reinterpret_cast<double*>(sh + 4 * nn);   // TR_MAXDRV drive values
+  const int b = blockIdx.x, m = b % G.M, q = b / G.M, j = q % G.r;
+  const long step = q / G.r;
+  const double t = step * G.dt + G.mid[j];
+  for (int k = threadIdx.x; k < G.ndrives; k += blockDim.x) {
+    const TrDrive R = G.dr[k];
+    double v = 0.0;
+    if (R.mode == m) {
+      for (int i = 0; i < R.npar; ++i)
+        v += par[R.par0 + i] * envelope_basis(R.env, i, R.npar, step, G.N, t, G.T, R.sigma);
+      v *= cos(wrap_2pi(R.omega * t + R.phase));
+    }
+    ck[k] = v;
+  }
+  __syncthreads();
+  const double2 w = gate_factor(G, j, 1.0);
+  for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
+    const int row = idx / n, col = idx % n;
+    double2 h = make_double2(row == col ? eps[m * d + row] : 0.0, 0.0);
+    for (int k = 0; k < G.ndrives; ++k) {
+      if (G.dr[k].mode != m) continue;
+      const double2 o = ops[(size_t)(m * 2 + G.dr[k].op) * nn + idx];
+      h.x += ck[k] * o.x;
+      h.y += ck[k] * o.y;
+    }
+    X[idx] = cmul(w, h);
+  }
+  __syncthreads();
+  expm_taylor(n, X, E, T, W);
+  for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) out[(size_t)b * nn + idx] = E[idx];
+}
+
+// One single-mode gate on the mode of stride s: fibre f = (hi, lo) holds the
+// d amplitudes hi*s*d + a*s + lo.
+template <int d>
+__device__ inline void tr_apply1(double2* L, int D, int s, const double2* __restrict__ Gt) {
+  const int nf = D / d;
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+    const int lo = f % s, hi = f / s;
+    const int base = hi * s * d + lo;
+    double2 x[d];
+#pragma unroll
+    for (int a = 0; a < d; ++a) x[a] = L[base + a * s];
+#pragma unroll
+    for (int r = 0; r < d; ++r) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int c = 0; c < d; ++c) {
+        const double2 g = Gt[r * d + c];
+        re += g.x * x[c].x - g.y * x[c].y;
+        im += g.x * x[c].y + g.y * x[c].x;
+      }
+      L[base + r * s] = make_double2(re, im);
+    }
+  }
+}
+
+// One pair gate on modes of strides si (row digit a) and sj (digit b):
+// fibre f holds the d^2 amplitudes base + a*si + b*sj.
+template <int d>
+__device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double2* __restrict__ Gt) {
+  constexpr int dd = d * d;
+  const int sp = si > sj ? si : sj, sq = si > sj ? sj : si;
+  const int w = sp / (sq * d);
+  const int nf = D / dd;
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+    const int lo = f % sq, t = f / sq, mid = t % w, hi = t / w;
+    const int base = hi * sp * d + mid * sq * d + lo;
+    double2 x[dd];
+#pragma unroll
+    for (int a = 0; a < d; ++a)
+#pragma unroll
+      for (int b = 0; b < d; ++b) x[a * d + b] = L[base + a * si + b * sj];
+#pragma unroll
+    for (int a = 0; a < d; ++a)
+#pragma unroll
+      for (int b = 0; b < d; ++b) {
+        const int r = a * d + b;
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int c = 0; c < dd; ++c) {
+          const double2 g = Gt[r * dd + c];
+          re += g.x * x[c].x - g.y * x[c].y;
+          im += g.x * x[c].y + g.y * x[c].x;
+        }
+        L[base + a * si + b * sj] = make_double2(re, im);
+      }
+  }
+}
+
+// Workgroup = one column; sg: [N][r][M][d*d] single-mode gates, pg: [r][E][d^4].
+template <int d>
+__global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const double2* __restrict__ psi0,
+                                                             double2* __restrict__ psiT,
+                                                             const double2* __restrict__ sg,
+                                                             const double2* __restrict__ pg) {
+  extern __shared__ double2 L[];
+  constexpr int dd = d * d;
+  const size_t off = (size_t)blockIdx.x * R.D;
+  for (int i = threadIdx.x; i < R.D; i += blockDim.x) L[i] = psi0[off + i];
+  __syncthreads();
+  const int K = R.M + R.E;
+  const int passes = R.sym ? 2 : 1;
+  for (int n = 0; n < R.N; ++n) {
+    for (int j = 0; j < R.r; ++j) {
+      const double2* sgj = sg + ((size_t)n * R.r + j) * R.M * dd;
+      const double2* pgj = pg + (size_t)j * R.E * dd * dd;
+      for (int pass = 0; pass < passes; ++pass) {
+        for (int q = 0; q < K; ++q) {
+          const int k = pass == 0 ? q : K - 1 - q;
+          if (k < R.M)
+            tr_apply1<d>(L, R.D, R.stride[k], sgj + (size_t)k * dd);
+          else
+            tr_apply2<d>(L, R.D, R.stride[R.ci[k - R.M]], R.stride[R.cj[k - R.M]],
+                         pgj + (size_t)(k - R.M) * dd * dd);
+          __syncthreads();
+        }
+      }
+    }
+  }
+  for (int i = threadIdx.x; i < R.D; i += blockDim.x) {
+    int r = i;
+    double th = 0.0;
+    for (int m = R.M - 1; m >= 0; --m) {
+      th += R.fT[m][r % d];
+      r /= d;
+    }
+    double sn, cs;
+    sincos(wrap_2pi(th), &sn, &cs);
+    const double2 v = L[i];
+    psiT[off + i] = make_double2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+  }
+}
+
+template <int d>
+hipError_t run_trotter(const TrRun& R, int S, const double2* psi0, double2* psiT, const double2* sg,
+                       const double2* pg, hipStream_t st) {
+  const size_t sh = (size_t)R.D * sizeof(double2);
+  hipError_t e = hipFuncSetAttribute((const void*)trotter_kernel<d>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(trotter_kernel<d>, dim3(S), dim3(TR_THREADS), sh, st, R, psi0, psiT, sg, pg);
+  return hipGetLastError();
+}
+
+struct TrLayout {
+  size_t eps, ops, par, pg, sg, total;
+  int r, sym, npar;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+TrLayout tr_layout(const scp_system* sys, int order) {
+  TrLayout L{};
+  L.r = order == SCP_TROTTER_Q4 ? 3 : (order == SCP_TROTTER_Q4J ? 2 : 1);
+  L.sym = order != SCP_TROTTER_Q1;
+  L.npar = 0;
+  for (const Drive& R : sys->drives) L.npar += (int)R.par.size();
+  const size_t d = sys->d, M = sys->n_modes, E = sys->coup.size();
+  size_t o = 0;
+  L.eps = o;
+  o = align256(o + M * d * sizeof(double));
+  L.ops = o;
+  o = align256(o + M * 2 * d * d * sizeof(double2));
+  L.par = o;
+  o = align256(o + std::max(1, L.npar) * sizeof(double));
+  L.pg = o;
+  o = align256(o + (size_t)L.r * std::max<size_t>(1, E) * d * d * d * d * sizeof(double2));
+  L.sg = o;
+  o = align256(o + (size_t)sys->n_steps * L.r * M * d * d * sizeof(double2));
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+scp_status trotter_check(const scp_system* sys, int order) {
+  if (order < SCP_TROTTER_Q1 || order > SCP_TROTTER_Q4J)
+    return fail(SCP_EINVAL, "order must be one of SCP_TROTTER_Q1, Q2, Q4, Q4J");
+  if (sys->d < 2 || sys->d > TR_MAXD) return fail(SCP_EINVAL, "the Trotter path takes d = 2..5");
+  if (sys->D * (int64_t)sizeof(double2) > TR_MAXLDS)
+    return fail(SCP_EINVAL, "the Trotter path keeps a column in LDS: 16 D bytes must be <= 160 KiB");
+  if ((int)sys->coup.size() > TR_MAXE) return fail(SCP_EINVAL, "the Trotter path takes <= 48 couplings");
+  if ((int)sys->drives.size() > TR_MAXDRV) return fail(SCP_EINVAL, "the Trotter path takes <= 32 drives");
+  return SCP_OK;
+}
+
+size_t trotter_workspace_bytes(const scp_system* sys, int order) { return tr_layout(sys, order).total; }
+
+scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const double2* psi0,
+                          double2* psiT, hipStream_t st) {
+  scp_status chk = trotter_check(sys, order);
+  if (chk != SCP_OK) return chk;
+  const TrLayout W = tr_layout(sys, order);
+  const int d = sys->d, M = sys->n_modes, E = (int)sys->coup.size(), N = sys->n_steps;
+  char* base = static_cast<char*>(ws);
+  // inputs: energies, dressed operators, pulse parameters
+  std::vector<char> in(W.pg, 0);
+  double* ieps = reinterpret_cast<double*>(in.data() + W.eps);
+  double2* iops = reinterpret_cast<double2*>(in.data() + W.ops);
+  double* ipar = reinterpret_cast<double*>(in.data() + W.par);
+  for (int m = 0; m < M; ++m) {
+    for (int a = 0; a < d; ++a) ieps[m * d + a] = sys->modes[m].eps[a];
+    for (int op = 0; op < 2; ++op)
+      for (int i = 0; i < d * d; ++i) {
+        const cplx v = sys->modes[m].ops[op][i];
+        iops[(m * 2 + op) * d * d + i] = make_double2(v.real(), v.imag());
+      }
+  }
+  TrGen G{};
+  G.d = d;
+  G.M = M;
+  G.E = E;
+  G.N = N;
+  G.r = W.r;
+  G.sym = W.sym;
+  G.ndrives = (int)sys->drives.size();
+  G.dt = sys->h;
+  G.T = sys->T;
+  G.tau = W.sym ? 0.5 * sys->h : sys->h;
+  double are[3] = {1.0, 0.0, 0.0}, aim[3] = {0.0, 0.0, 0.0};
+  if (order == SCP_TROTTER_Q4) {
+    const double p = 1.0 / (2.0 - std::cbrt(2.0));
+    are[0] = p;
+    are[1] = 1.0 - 2.0 * p;
+    are[2] = p;
+  } else if (order == SCP_TROTTER_Q4J) {
+    are[0] = are[1] = 0.5;
+    aim[0] = -std::sqrt(3.0) / 6.0;
+    aim[1] = std::sqrt(3.0) / 6.0;
+  }
+  double start = 0.0;
+  for (int j = 0; j < W.r; ++j) {
+    G.a_re[j] = are[j];
+    G.a_im[j] = aim[j];
+    G.mid[j] = order == SCP_TROTTER_Q4J ? 0.5 * sys->h : start + 0.5 * are[j] * sys->h;
+    start += are[j] * sys->h;
+  }
+  int np = 0;
+  for (int k = 0; k < G.ndrives; ++k) {
+    const Drive& R = sys->drives[k];
+    G.dr[k] = TrDrive{R.mode, R.op, R.env, (int)R.par.size(), np, R.omega, R.phase, R.sigma};
+    for (double v : R.par) ipar[np++] = v;
+  }
+  for (int e = 0; e < E; ++e) {
+    const Coupling& c = sys->coup[e];
+    G.ci[e] = c.i;
+    G.cj[e] = c.j;
+    G.coi[e] = c.op_i;
+    G.coj[e] = c.op_j;
+    G.g[e] = c.g;
+  }
+  HIPCHK(hipMemcpyAsync(base, in.data(), in.size(), hipMemcpyHostToDevice, st));
+  // the staging vector must outlive the copy
+  HIPCHK(hipStreamSynchronize(st));
+  const double* deps = reinterpret_cast<const double*>(base + W.eps);
+  const double2* dops = reinterpret_cast<const double2*>(base + W.ops);
+  const double* dpar = reinterpret_cast<const double*>(base + W.par);
+  double2* pg = reinterpret_cast<double2*>(base + W.pg);
+  double2* sg = reinterpret_cast<double2*>(base + W.sg);
+  if (E > 0) {
+    const int n = d * d;
+    hipLaunchKernelGGL(tr_pair_gate_kernel, dim3(W.r * E), dim3(256), 4 * n * n * sizeof(double2), st,
+                       G, dops, pg);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(tr_single_gate_kernel, dim3((unsigned)((size_t)N * W.r * M)), dim3(64),
+                     4 * d * d * sizeof(double2) + TR_MAXDRV * sizeof(double), st, G, deps, dops, dpar,
+                     sg);
+  HIPCHK(hipGetLastError());
+  TrRun R{};
+  R.M = M;
+  R.E = E;
+  R.N = N;
+  R.r = W.r;
+  R.sym = W.sym;
+  R.D = (int)sys->D;
+  int s = 1;
+  for (int m = M - 1; m >= 0; --m) {
+    R.stride[m] = s;
+    s *= d;
+  }
+  for (int e = 0; e < E; ++e) {
+    R.ci[e] = sys->coup[e].i;
+    R.cj[e] = sys->coup[e].j;
+  }
+  const double twopi = 6.283185307179586476925286766559;
+  for (int m = 0; m < M; ++m)
+    for (int a = 0; a < d; ++a) R.fT[m][a] = std::remainder(sys->modes[m].frame[a] * N * sys->h, twopi);
+  hipError_t e;
+  switch (d) {
+    case 2: e = run_trotter<2>(R, S, psi0, psiT, sg, pg, st); break;
+    case 3: e = run_trotter<3>(R, S, psi0, psiT, sg, pg, st); break;
+    case 4: e = run_trotter<4>(R, S, psi0, psiT, sg, pg, st); break;
+    default: e = run_trotter<5>(R, S, psi0, psiT, sg, pg, st); break;
+  }
+  HIPCHK(e);
+  return SCP_OK;
+}
+
+}  // namespace scp
