@@ -213,7 +213,79 @@ def other_configs(scp, si, torch, np):
         g.close()
         lines.append(out)
     lines.append(static_spectrum_line(scp, np))
+    lines += trotter_lines(scp, si, torch, np)
     return lines
+
+
+def trotter_flop(desc, order):
+    """Algorithmic FP64 FLOP of one product-formula propagation: every gate
+    application is a d x d (single-mode) or d^2 x d^2 (pair) complex matrix
+    on every fibre of a column, 8 FLOP per complex multiply-add."""
+    d = desc["modes"][0]["trunc"]
+    M, E = len(desc["modes"]), len(desc["couplings"])
+    D = d ** M
+    pieces = {"q1": 1, "q2": 2, "q4": 6, "q4j": 4}[order]   # passes over the terms per step
+    cmac = pieces * (M * D * d + E * D * d * d)
+    return 8.0 * cmac * desc["n_steps"] * len(desc["columns"])
+
+
+def trotter_lines(scp, si, torch, np, orders=("q1", "q2", "q4", "q4j")):
+    """Suzuki-Trotter product formulas on the 8-transmon ring (D = 6561, 256
+    columns, 3000 steps), the 4-fluxonium chain (D = 625, 16 columns, 5000
+    steps) and the 6-fluxonium X^6 chain (D = 4096, 64 columns, 5000 steps):
+    call time (gate exponentials + propagation, HIP events on the
+    launch stream), algorithmic FP64 rate against the 78.6 TFLOP/s vector
+    peak, distance to the FP32 RK4 result, and the oracle on a bounded
+    sample (the ring's first 10 steps, 8 columns)."""
+    from oracle import trotter as otr
+    from oracle.system import OracleSystem
+    out = []
+    stream = torch.cuda.current_stream()
+    for name, desc, ords in (("ring8_d3: 8-transmon ring d=3, D=6561, 256 columns, 3000 steps",
+                              si.config5(), orders),
+                             ("chain4_d5: 4-fluxonium chain d=5, D=625, 16 columns, 5000 steps",
+                              si.config2(), ("q2", "q4")),
+                             ("x6_chain6_d4: 6-fluxonium multipath chain d=4, D=4096, 64 columns, "
+                              "T=50 ns, 5000 steps of 0.01 ns (the paper's X^6 benchmark shape)",
+                              si.fluxonium6_x6(), ("q2",))):
+        g = scp.System(desc)
+        S = len(desc["columns"])
+        psi0 = scp.basis_columns(g.D, desc["columns"], dtype=torch.complex128)
+        rk = g.propagate(scp.basis_columns(g.D, desc["columns"])).to(torch.complex128)
+        for order in ords:
+            ws = torch.empty(g.trotter_workspace_bytes(order), dtype=torch.uint8, device="cuda")
+            U = g.propagate_trotter(psi0, order, workspace=ws)
+            ms = []
+            for _ in range(3):
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                ev[0].record(stream)
+                U = g.propagate_trotter(psi0, order, workspace=ws)
+                ev[1].record(stream)
+                torch.cuda.synchronize()
+                ms.append(ev[0].elapsed_time(ev[1]))
+            t = min(ms)
+            fl = trotter_flop(desc, order)
+            out.append({"config": "trotter " + name, "order": order, "call_ms": t,
+                        "steps_columns_per_s": desc["n_steps"] * S / (t * 1e-3),
+                        "fp64_tflops": fl / (t * 1e-3) / 1e12,
+                        "frac_fp64_peak": fl / (t * 1e-3) / 78.6e12,
+                        "max_abs_diff_vs_rk4_fp32": float((U - rk).abs().max()),
+                        "workspace_mib": ws.numel() / 2 ** 20})
+            if name.startswith("x6_"):
+                out[-1]["paper_forward_s_context"] = 2.02
+                out[-1]["paper_context"] = ("SuperGrad Q2 forward of its X^6 task on a 32-core "
+                                            "EPYC 7513, truncation not stated (Sec. 4.2 table)")
+        g.close()
+    # oracle on a bounded sample of the ring
+    desc = si.config5()
+    cols = np.asarray(desc["columns"])[si.sampled_columns(len(desc["columns"]))]
+    o = OracleSystem(desc)
+    t0 = time.perf_counter()
+    otr.propagate(o, "q2", psi0=np.eye(o.D)[:, cols], n_steps=10)
+    dt = time.perf_counter() - t0
+    out.append({"config": "trotter oracle (CPU, FP64, q2)", "sample": "ring8_d3, 10 steps x 8 columns",
+                "steps_columns_per_s": 10 * len(cols) / dt, "cores": 1})
+    return out
 
 
 def static_spectrum_line(scp, np):
@@ -321,6 +393,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--configs", action="store_true",
                     help="only time configs 1-3 (one JSON line each) and exit")
+    ap.add_argument("--trotter", action="store_true",
+                    help="only time the Suzuki-Trotter product formulas (one JSON line each) and exit")
+    ap.add_argument("--trotter-orders", default="q1,q2,q4,q4j")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (to scale HBM counters)")
     args = ap.parse_args()
@@ -346,6 +421,10 @@ def main():
     import scp_inputs as si
     import paper_2406_18155_amd as scp
 
+    if args.trotter:
+        for line in trotter_lines(scp, si, torch, np, tuple(args.trotter_orders.split(","))):
+            print(json.dumps(line), flush=True)
+        return
     if args.configs:
         for line in other_configs(scp, si, torch, np):
             print(json.dumps(line), flush=True)

@@ -25,9 +25,13 @@
 //      until the 1-norm is at most 1/2, sum the series to degree 18
 //      (truncation below 1e-22 relative), square back;
 //   2. the propagation: one workgroup per state column keeps the column in
-//      LDS (16 D bytes) for all steps and applies the gates in sequence.  A
-//      thread owns whole fibres of the contracted mode(s), so a gate needs no
-//      synchronisation inside it, only a barrier before the next gate.
+//      LDS (16 D bytes) for all steps and applies the gates in sequence, one
+//      barrier between gates.  A gate kind with at least as many fibres as
+//      threads runs in place, a thread owning whole fibres of the contracted
+//      mode(s).  With fewer fibres (small D, pair gates) and room for a second
+//      column buffer (32 D bytes <= 160 KiB), a thread computes one output
+//      row of one fibre from one buffer into the other, which keeps d or d^2
+//      times more threads busy; the buffers swap after such a gate.
 #include <cmath>
 
 #include "internal.h"
@@ -59,6 +63,7 @@ struct TrGen {
 
 struct TrRun {
   int M, E, N, r, sym, D;
+  int split1, split2;          // single-mode / pair gates by output row (two buffers)
   int stride[SCP_MAX_MODES];   // stride of mode m inside a column (mode 0 slowest)
   int ci[TR_MAXE], cj[TR_MAXE];
   double fT[SCP_MAX_MODES][SCP_MAX_TRUNC];   // frame energy times T, reduced mod 2 pi
@@ -259,15 +264,62 @@ __device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double
   }
 }
 
+// Row-split forms: work item w = (row, fibre) reads the fibre from ``in``
+// and writes its one output row to ``out`` (a different buffer).
+template <int d>
+__device__ inline void tr_apply1_rows(const double2* in, double2* out, int D, int s,
+                                      const double2* __restrict__ Gt) {
+  const int nf = D / d;
+  for (int w = threadIdx.x; w < D; w += blockDim.x) {
+    const int r = w / nf, f = w - r * nf;
+    const int lo = f % s, hi = f / s;
+    const int base = hi * s * d + lo;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int c = 0; c < d; ++c) {
+      const double2 g = Gt[r * d + c], x = in[base + c * s];
+      re += g.x * x.x - g.y * x.y;
+      im += g.x * x.y + g.y * x.x;
+    }
+    out[base + r * s] = make_double2(re, im);
+  }
+}
+
+template <int d>
+__device__ inline void tr_apply2_rows(const double2* in, double2* out, int D, int si, int sj,
+                                      const double2* __restrict__ Gt) {
+  constexpr int dd = d * d;
+  const int sp = si > sj ? si : sj, sq = si > sj ? sj : si;
+  const int w0 = sp / (sq * d);
+  const int nf = D / dd;
+  for (int w = threadIdx.x; w < D; w += blockDim.x) {
+    const int r = w / nf, f = w - r * nf;
+    const int lo = f % sq, t = f / sq, mid = t % w0, hi = t / w0;
+    const int base = hi * sp * d + mid * sq * d + lo;
+    double re = 0.0, im = 0.0;
+#pragma unroll
+    for (int a = 0; a < d; ++a)
+#pragma unroll
+      for (int b = 0; b < d; ++b) {
+        const double2 g = Gt[r * dd + a * d + b], x = in[base + a * si + b * sj];
+        re += g.x * x.x - g.y * x.y;
+        im += g.x * x.y + g.y * x.x;
+      }
+    out[base + (r / d) * si + (r % d) * sj] = make_double2(re, im);
+  }
+}
+
 // Workgroup = one column; sg: [N][r][M][d*d] single-mode gates, pg: [r][E][d^4].
 template <int d>
 __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const double2* __restrict__ psi0,
                                                              double2* __restrict__ psiT,
                                                              const double2* __restrict__ sg,
                                                              const double2* __restrict__ pg) {
-  extern __shared__ double2 L[];
+  extern __shared__ double2 lds[];
   constexpr int dd = d * d;
   const size_t off = (size_t)blockIdx.x * R.D;
+  double2* L = lds;                 // current buffer
+  double2* Lo = lds + R.D;          // the other one (allocated only if a gate kind splits)
   for (int i = threadIdx.x; i < R.D; i += blockDim.x) L[i] = psi0[off + i];
   __syncthreads();
   const int K = R.M + R.E;
@@ -279,11 +331,29 @@ __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const doub
       for (int pass = 0; pass < passes; ++pass) {
         for (int q = 0; q < K; ++q) {
           const int k = pass == 0 ? q : K - 1 - q;
-          if (k < R.M)
-            tr_apply1<d>(L, R.D, R.stride[k], sgj + (size_t)k * dd);
-          else
-            tr_apply2<d>(L, R.D, R.stride[R.ci[k - R.M]], R.stride[R.cj[k - R.M]],
-                         pgj + (size_t)(k - R.M) * dd * dd);
+          bool swap = false;
+          if (k < R.M) {
+            if (R.split1) {
+              tr_apply1_rows<d>(L, Lo, R.D, R.stride[k], sgj + (size_t)k * dd);
+              swap = true;
+            } else {
+              tr_apply1<d>(L, R.D, R.stride[k], sgj + (size_t)k * dd);
+            }
+          } else {
+            const int si = R.stride[R.ci[k - R.M]], sj = R.stride[R.cj[k - R.M]];
+            const double2* gt = pgj + (size_t)(k - R.M) * dd * dd;
+            if (R.split2) {
+              tr_apply2_rows<d>(L, Lo, R.D, si, sj, gt);
+              swap = true;
+            } else {
+              tr_apply2<d>(L, R.D, si, sj, gt);
+            }
+          }
+          if (swap) {
+            double2* t = L;
+            L = Lo;
+            Lo = t;
+          }
           __syncthreads();
         }
       }
@@ -306,7 +376,7 @@ __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const doub
 template <int d>
 hipError_t run_trotter(const TrRun& R, int S, const double2* psi0, double2* psiT, const double2* sg,
                        const double2* pg, hipStream_t st) {
-  const size_t sh = (size_t)R.D * sizeof(double2);
+  const size_t sh = (size_t)R.D * sizeof(double2) * ((R.split1 || R.split2) ? 2 : 1);
   hipError_t e = hipFuncSetAttribute((const void*)trotter_kernel<d>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
@@ -446,6 +516,11 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
   R.r = W.r;
   R.sym = W.sym;
   R.D = (int)sys->D;
+  {
+    const bool two = 2 * sys->D * (int64_t)sizeof(double2) <= TR_MAXLDS;
+    R.split1 = two && sys->D / d < TR_THREADS;
+    R.split2 = two && E > 0 && sys->D / (d * d) < TR_THREADS;
+  }
   int s = 1;
   for (int m = M - 1; m >= 0; --m) {
     R.stride[m] = s;

@@ -165,6 +165,20 @@ def config3(seed_offset: int = 0):
     return s
 
 
+def fluxonium6_x6(seed_offset: int = 0, d: int = 4):
+    """The shape of the paper's simultaneous X^(x)6 benchmark (Sec. 4.2): a
+    6-fluxonium multipath chain (n(x)n and phi(x)phi per edge), phi drives on
+    every mode, T = 50 ns in 5000 steps of 0.01 ns, the 64 computational
+    columns and the X on every qubit as target.  The paper does not state the
+    truncation; d = 4 gives D = 4096."""
+    rng = rng_for(6, seed_offset)
+    s = fluxonium_chain(rng, 6, d, 50.0, 5000, drive_modes=tuple(range(6)))
+    x6 = np.zeros((64, 64), dtype=np.complex128)
+    for j in range(64):
+        x6[j ^ 63, j] = 1.0
+    return _finish(s, [d] * 6, target=x6)
+
+
 def transmon_ring(rng, n_modes, d, T, n_steps, g_range=(5e-3, 15e-3), ring=True):
     modes = [transmon_mode(rng, d) for _ in range(n_modes)]
     couplings = []

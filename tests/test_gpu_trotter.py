@@ -150,3 +150,23 @@ def test_trotter_ring8_workload_sampled_columns(scp):
         out = g.propagate_trotter(psi0, order)
         gram = (out.conj() @ out.T).cpu().numpy()
         assert np.abs(gram - np.eye(len(full["columns"]))).max() < 1e-11, order
+
+
+def test_trotter_x6_fluxonium_workload_sampled_columns(scp):
+    # The shape of the paper's X^(x)6 benchmark: a 6-fluxonium multipath chain
+    # at d = 4 (D = 4096, 64 columns, steps of 0.01 ns).  Its pair gates run
+    # split by output row between two LDS buffers and its single-mode gates
+    # in place: 8 sampled columns of the first 60 steps against the oracle.
+    desc = _prefix(si.fluxonium6_x6(), 60)
+    print("[trotter] X6 chain 6 x d4, 64 columns, 60 steps, q2 and q4", flush=True)
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, desc["columns"], dtype=torch.complex128)
+    pick = si.sampled_columns(len(desc["columns"]))
+    cols = np.asarray(desc["columns"])[pick]
+    o = OracleSystem(desc)
+    for order in ("q2", "q4"):
+        out = g.propagate_trotter(psi0, order)
+        torch.cuda.synchronize()
+        U = out[pick].cpu().numpy().T
+        ref = trotter.propagate(o, order, psi0=np.eye(o.D)[:, cols])
+        assert np.abs(U - ref).max() <= TOL, order
