@@ -29,9 +29,10 @@
 //      barrier between gates.  A gate kind with at least as many fibres as
 //      threads runs in place, a thread owning whole fibres of the contracted
 //      mode(s).  With fewer fibres (small D, pair gates) and room for a second
-//      column buffer (32 D bytes <= 160 KiB), a thread computes one output
-//      row of one fibre from one buffer into the other, which keeps d or d^2
-//      times more threads busy; the buffers swap after such a gate.
+//      column buffer (32 D bytes <= 160 KiB), a work item computes d output
+//      rows (pair gates, when that fills the block) or one output row of one
+//      fibre from one buffer into the other, which keeps up to d^2 times more
+//      threads busy; the buffers swap after such a gate.
 #include <cmath>
 
 #include "internal.h"
@@ -63,7 +64,8 @@ struct TrGen {
 
 struct TrRun {
   int M, E, N, r, sym, D;
-  int split1, split2;          // single-mode / pair gates by output row (two buffers)
+  int mode1;                   // single-mode gates: 0 in place, 1 one output row per item
+  int mode2;                   // pair gates: 0 in place, 1 one row, 2 d rows per item
   int stride[SCP_MAX_MODES];   // stride of mode m inside a column (mode 0 slowest)
   int ci[TR_MAXE], cj[TR_MAXE];
   double fT[SCP_MAX_MODES][SCP_MAX_TRUNC];   // frame energy times T, reduced mod 2 pi
@@ -206,42 +208,61 @@ __global__ void __launch_bounds__(64) tr_single_gate_kernel(TrGen G, const doubl
   for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) out[(size_t)b * nn + idx] = E[idx];
 }
 
-// One single-mode gate on the mode of stride s: fibre f = (hi, lo) holds the
-// d amplitudes hi*s*d + a*s + lo.
+// floor(x / n) for 0 <= x, n < 2^26 from inv = 1/n: (x + 1/2) / n lies at
+// least 1/(2n) from an integer, far beyond the rounding of the product.
+__device__ inline int qdiv(int x, double inv) { return (int)(((double)x + 0.5) * inv); }
+
+// Fibre f of a single-mode gate on the mode of stride s: the d amplitudes
+// base + a*s, base = hi*s*d + lo with f = hi*s + lo.
+template <int d>
+__device__ inline int fibre1(int f, int s, double inv_s) {
+  const int hi = qdiv(f, inv_s);
+  return hi * s * d + (f - hi * s);
+}
+
+// Fibre f of a pair gate on modes of strides si (row digit a) and sj (digit
+// b), sp = max, sq = min, w = sp / (sq d): the d^2 amplitudes
+// base + a*si + b*sj, base = hi*sp*d + mid*sq*d + lo with f = (hi*w + mid)*sq + lo.
+template <int d>
+__device__ inline int fibre2(int f, int sp, int sq, int w, double inv_sq, double inv_w) {
+  const int t = qdiv(f, inv_sq), hi = qdiv(t, inv_w);
+  return hi * sp * d + (t - hi * w) * sq * d + (f - t * sq);
+}
+
+template <int d>
+__device__ inline double2 crow(const double2* __restrict__ g, const double2* x, int n) {
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < n; ++c) {
+    re += g[c].x * x[c].x - g[c].y * x[c].y;
+    im += g[c].x * x[c].y + g[c].y * x[c].x;
+  }
+  return make_double2(re, im);
+}
+
+// In place: a thread owns whole fibres of a single-mode gate.
 template <int d>
 __device__ inline void tr_apply1(double2* L, int D, int s, const double2* __restrict__ Gt) {
   const int nf = D / d;
+  const double is = 1.0 / s;
   for (int f = threadIdx.x; f < nf; f += blockDim.x) {
-    const int lo = f % s, hi = f / s;
-    const int base = hi * s * d + lo;
+    const int base = fibre1<d>(f, s, is);
     double2 x[d];
 #pragma unroll
     for (int a = 0; a < d; ++a) x[a] = L[base + a * s];
 #pragma unroll
-    for (int r = 0; r < d; ++r) {
-      double re = 0.0, im = 0.0;
-#pragma unroll
-      for (int c = 0; c < d; ++c) {
-        const double2 g = Gt[r * d + c];
-        re += g.x * x[c].x - g.y * x[c].y;
-        im += g.x * x[c].y + g.y * x[c].x;
-      }
-      L[base + r * s] = make_double2(re, im);
-    }
+    for (int r = 0; r < d; ++r) L[base + r * s] = crow<d>(Gt + r * d, x, d);
   }
 }
 
-// One pair gate on modes of strides si (row digit a) and sj (digit b):
-// fibre f holds the d^2 amplitudes base + a*si + b*sj.
+// In place: a thread owns whole fibres of a pair gate.
 template <int d>
 __device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double2* __restrict__ Gt) {
   constexpr int dd = d * d;
-  const int sp = si > sj ? si : sj, sq = si > sj ? sj : si;
-  const int w = sp / (sq * d);
+  const int sp = si > sj ? si : sj, sq = si > sj ? sj : si, w = sp / (sq * d);
+  const double isq = 1.0 / sq, iw = 1.0 / w;
   const int nf = D / dd;
   for (int f = threadIdx.x; f < nf; f += blockDim.x) {
-    const int lo = f % sq, t = f / sq, mid = t % w, hi = t / w;
-    const int base = hi * sp * d + mid * sq * d + lo;
+    const int base = fibre2<d>(f, sp, sq, w, isq, iw);
     double2 x[dd];
 #pragma unroll
     for (int a = 0; a < d; ++a)
@@ -250,62 +271,51 @@ __device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double
 #pragma unroll
     for (int a = 0; a < d; ++a)
 #pragma unroll
-      for (int b = 0; b < d; ++b) {
-        const int r = a * d + b;
-        double re = 0.0, im = 0.0;
-#pragma unroll
-        for (int c = 0; c < dd; ++c) {
-          const double2 g = Gt[r * dd + c];
-          re += g.x * x[c].x - g.y * x[c].y;
-          im += g.x * x[c].y + g.y * x[c].x;
-        }
-        L[base + a * si + b * sj] = make_double2(re, im);
-      }
+      for (int b = 0; b < d; ++b) L[base + a * si + b * sj] = crow<d>(Gt + (a * d + b) * dd, x, dd);
   }
 }
 
-// Row-split forms: work item w = (row, fibre) reads the fibre from ``in``
-// and writes its one output row to ``out`` (a different buffer).
+// Split forms read ``in`` and write ``out`` (the other buffer).  Single-mode
+// gate, one output row per work item w = r * nf + f.
 template <int d>
 __device__ inline void tr_apply1_rows(const double2* in, double2* out, int D, int s,
                                       const double2* __restrict__ Gt) {
   const int nf = D / d;
+  const double is = 1.0 / s, inf = 1.0 / nf;
   for (int w = threadIdx.x; w < D; w += blockDim.x) {
-    const int r = w / nf, f = w - r * nf;
-    const int lo = f % s, hi = f / s;
-    const int base = hi * s * d + lo;
-    double re = 0.0, im = 0.0;
+    const int r = qdiv(w, inf);
+    const int base = fibre1<d>(w - r * nf, s, is);
+    double2 x[d];
 #pragma unroll
-    for (int c = 0; c < d; ++c) {
-      const double2 g = Gt[r * d + c], x = in[base + c * s];
-      re += g.x * x.x - g.y * x.y;
-      im += g.x * x.y + g.y * x.x;
-    }
-    out[base + r * s] = make_double2(re, im);
+    for (int c = 0; c < d; ++c) x[c] = in[base + c * s];
+    out[base + r * s] = crow<d>(Gt + r * d, x, d);
   }
 }
 
-template <int d>
+// Pair gate, RPI output rows per work item: RPI = d computes the rows
+// (a, 0..d-1) of one fibre (w = a * nf + f), RPI = 1 one row (w = r * nf + f).
+template <int d, int RPI>
 __device__ inline void tr_apply2_rows(const double2* in, double2* out, int D, int si, int sj,
                                       const double2* __restrict__ Gt) {
   constexpr int dd = d * d;
-  const int sp = si > sj ? si : sj, sq = si > sj ? sj : si;
-  const int w0 = sp / (sq * d);
+  const int sp = si > sj ? si : sj, sq = si > sj ? sj : si, w0 = sp / (sq * d);
+  const double isq = 1.0 / sq, iw = 1.0 / w0;
   const int nf = D / dd;
-  for (int w = threadIdx.x; w < D; w += blockDim.x) {
-    const int r = w / nf, f = w - r * nf;
-    const int lo = f % sq, t = f / sq, mid = t % w0, hi = t / w0;
-    const int base = hi * sp * d + mid * sq * d + lo;
-    double re = 0.0, im = 0.0;
+  const double inf = 1.0 / nf;
+  const int items = nf * (dd / RPI);
+  for (int w = threadIdx.x; w < items; w += blockDim.x) {
+    const int g = qdiv(w, inf);               // row group
+    const int base = fibre2<d>(w - g * nf, sp, sq, w0, isq, iw);
+    double2 x[dd];
 #pragma unroll
     for (int a = 0; a < d; ++a)
 #pragma unroll
-      for (int b = 0; b < d; ++b) {
-        const double2 g = Gt[r * dd + a * d + b], x = in[base + a * si + b * sj];
-        re += g.x * x.x - g.y * x.y;
-        im += g.x * x.y + g.y * x.x;
-      }
-    out[base + (r / d) * si + (r % d) * sj] = make_double2(re, im);
+      for (int b = 0; b < d; ++b) x[a * d + b] = in[base + a * si + b * sj];
+#pragma unroll
+    for (int k = 0; k < RPI; ++k) {
+      const int r = g * RPI + k;
+      out[base + (r / d) * si + (r % d) * sj] = crow<d>(Gt + r * dd, x, dd);
+    }
   }
 }
 
@@ -333,7 +343,7 @@ __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const doub
           const int k = pass == 0 ? q : K - 1 - q;
           bool swap = false;
           if (k < R.M) {
-            if (R.split1) {
+            if (R.mode1) {
               tr_apply1_rows<d>(L, Lo, R.D, R.stride[k], sgj + (size_t)k * dd);
               swap = true;
             } else {
@@ -342,8 +352,11 @@ __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const doub
           } else {
             const int si = R.stride[R.ci[k - R.M]], sj = R.stride[R.cj[k - R.M]];
             const double2* gt = pgj + (size_t)(k - R.M) * dd * dd;
-            if (R.split2) {
-              tr_apply2_rows<d>(L, Lo, R.D, si, sj, gt);
+            if (R.mode2 == 2) {
+              tr_apply2_rows<d, d>(L, Lo, R.D, si, sj, gt);
+              swap = true;
+            } else if (R.mode2 == 1) {
+              tr_apply2_rows<d, 1>(L, Lo, R.D, si, sj, gt);
               swap = true;
             } else {
               tr_apply2<d>(L, R.D, si, sj, gt);
@@ -376,7 +389,7 @@ __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const doub
 template <int d>
 hipError_t run_trotter(const TrRun& R, int S, const double2* psi0, double2* psiT, const double2* sg,
                        const double2* pg, hipStream_t st) {
-  const size_t sh = (size_t)R.D * sizeof(double2) * ((R.split1 || R.split2) ? 2 : 1);
+  const size_t sh = (size_t)R.D * sizeof(double2) * ((R.mode1 || R.mode2) ? 2 : 1);
   hipError_t e = hipFuncSetAttribute((const void*)trotter_kernel<d>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
@@ -518,8 +531,9 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
   R.D = (int)sys->D;
   {
     const bool two = 2 * sys->D * (int64_t)sizeof(double2) <= TR_MAXLDS;
-    R.split1 = two && sys->D / d < TR_THREADS;
-    R.split2 = two && E > 0 && sys->D / (d * d) < TR_THREADS;
+    const int64_t nf1 = sys->D / d, nf2 = sys->D / (d * d);
+    R.mode1 = (two && nf1 < TR_THREADS) ? 1 : 0;
+    R.mode2 = (!two || E == 0 || nf2 >= TR_THREADS) ? 0 : (nf2 * d >= TR_THREADS ? 2 : 1);
   }
   int s = 1;
   for (int m = M - 1; m >= 0; --m) {
