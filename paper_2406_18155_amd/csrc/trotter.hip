@@ -34,6 +34,7 @@
 //      fibre from one buffer into the other, which keeps up to d^2 times more
 //      threads busy; the buffers swap after such a gate.
 #include <cmath>
+#include <cstring>
 
 #include "internal.h"
 
@@ -47,6 +48,8 @@ constexpr int TR_MAXE = 48;
 constexpr int TR_MAXPIECE = 3;
 constexpr int TR_THREADS = 512;   // propagation workgroup
 constexpr int TR_MAXLDS = 160 * 1024;
+constexpr int TR_MAXOPS = 64;     // fused operations per pass
+constexpr int TR_MAXC = 8;        // gates fused into one operation
 
 struct TrDrive {
   int mode, op, env, npar, par0;
@@ -62,12 +65,29 @@ struct TrGen {
   double g[TR_MAXE];
 };
 
+// Fused operations of one pass.  An operation acts on one mode pair
+// (kind 1, digits (mi, mj)) or on one mode (kind 0, mi); its constituents
+// act in the listed order: ctype 1 = pair gate e = cidx (same orientation),
+// ctype 0 = single-mode gate of mode cidx on digit cdig (0: mi, 1: mj).
+struct TrOp {
+  int kind, mi, mj, nc;
+  int stat;   // no single-mode factor: the same gate every step, in static slot sid
+  int sid, own;   // own: this operation forms the slot (equal products share one)
+  int ctype[TR_MAXC], cidx[TR_MAXC], cdig[TR_MAXC];
+};
+struct TrPlan {
+  int nop[2], nslot;
+  TrOp op[2][TR_MAXOPS];
+};
+
 struct TrRun {
-  int M, E, N, r, sym, D;
+  int M, E, N, r, sym, D, H, nopmax, nslot;
+  int nop[2];
+  int opk[2][TR_MAXOPS], opi[2][TR_MAXOPS], opj[2][TR_MAXOPS];
+  int ops[2][TR_MAXOPS];   // static slot + 1, or 0
   int mode1;                   // single-mode gates: 0 in place, 1 one output row per item
   int mode2;                   // pair gates: 0 in place, 1 one row, 2 d rows per item
   int stride[SCP_MAX_MODES];   // stride of mode m inside a column (mode 0 slowest)
-  int ci[TR_MAXE], cj[TR_MAXE];
   double fT[SCP_MAX_MODES][SCP_MAX_TRUNC];   // frame energy times T, reduced mod 2 pi
 };
 
@@ -208,6 +228,69 @@ __global__ void __launch_bounds__(64) tr_single_gate_kernel(TrGen G, const doubl
   for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) out[(size_t)b * nn + idx] = E[idx];
 }
 
+// Fused gates: block b = ((step * r + j) * H + h) * nopmax + o multiplies the
+// constituents of operation o of pass h, in action order, into a d^2 x d^2
+// (pair) or d x d (single) matrix at slot b (d^4 complex per slot).
+__global__ void __launch_bounds__(256) tr_fuse_kernel(int d, int r, int H, int nopmax, int M, int E,
+                                                      const TrPlan* __restrict__ plan,
+                                                      const double2* __restrict__ sg,
+                                                      const double2* __restrict__ pg,
+                                                      double2* __restrict__ out,
+                                                      double2* __restrict__ out_static) {
+  extern __shared__ double2 sh[];
+  const int b = blockIdx.x, o = b % nopmax, h = (b / nopmax) % H, q = b / (nopmax * H);
+  const int j = q % r;
+  const long step = q / r;
+  const int dd = d * d;
+  if (o >= plan->nop[h]) return;   // the whole block leaves together
+  const TrOp& op = plan->op[h][o];
+  // a lone single-mode operation reads the single-mode table directly; a
+  // static operation is formed once, into the table of (piece, pass, operation)
+  if (op.kind == 0 || (op.stat && (step > 0 || !op.own))) return;
+  double2* slot = op.stat ? out_static + ((size_t)j * plan->nslot + op.sid) * dd * dd
+                          : out + (size_t)b * dd * dd;
+  const int n = op.kind ? dd : d, nn = n * n;
+  double2 *A = sh, *W = sh + nn;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x)
+    A[e] = make_double2((e / n == e % n) ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  for (int c = 0; c < op.nc; ++c) {
+    const int ty = op.ctype[c], ix = op.cidx[c], dg = op.cdig[c];
+    const double2* S = sg + ((size_t)step * r + j) * M * dd + (size_t)ix * dd;
+    const double2* P = pg + ((size_t)j * E + ix) * dd * dd;
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+      const int row = e / n, col = e % n;
+      double re = 0.0, im = 0.0;
+      if (ty == 1) {                       // pair gate times A
+        for (int k = 0; k < n; ++k) {
+          const double2 g = P[row * n + k], a = A[k * n + col];
+          re += g.x * a.x - g.y * a.y;
+          im += g.x * a.y + g.y * a.x;
+        }
+      } else if (!op.kind) {               // single on a single operation
+        for (int k = 0; k < d; ++k) {
+          const double2 g = S[row * d + k], a = A[k * n + col];
+          re += g.x * a.x - g.y * a.y;
+          im += g.x * a.y + g.y * a.x;
+        }
+      } else {                             // single embedded on digit dg of a pair
+        const int ra = row / d, rb = row % d;
+        for (int k = 0; k < d; ++k) {
+          const double2 g = dg == 0 ? S[ra * d + k] : S[rb * d + k];
+          const double2 a = dg == 0 ? A[(k * d + rb) * n + col] : A[(ra * d + k) * n + col];
+          re += g.x * a.x - g.y * a.y;
+          im += g.x * a.y + g.y * a.x;
+        }
+      }
+      W[e] = make_double2(re, im);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nn; e += blockDim.x) A[e] = W[e];
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) slot[e] = A[e];
+}
+
 // floor(x / n) for 0 <= x, n < 2^26 from inv = 1/n: (x + 1/2) / n lies at
 // least 1/(2n) from an integer, far beyond the rounding of the product.
 __device__ inline int qdiv(int x, double inv) { return (int)(((double)x + 0.5) * inv); }
@@ -319,12 +402,15 @@ __device__ inline void tr_apply2_rows(const double2* in, double2* out, int D, in
   }
 }
 
-// Workgroup = one column; sg: [N][r][M][d*d] single-mode gates, pg: [r][E][d^4].
+// Workgroup = one column; fg: fused gates [N][r][H][nopmax][d^4] of pair
+// operations with a single-mode factor, fs: [r][nslot][d^4] of the static
+// ones, sg: [N][r][M][d^2] single-mode gates (lone single-mode operations).
 template <int d>
 __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const double2* __restrict__ psi0,
                                                              double2* __restrict__ psiT,
-                                                             const double2* __restrict__ sg,
-                                                             const double2* __restrict__ pg) {
+                                                             const double2* __restrict__ fg,
+                                                             const double2* __restrict__ fs,
+                                                             const double2* __restrict__ sg) {
   extern __shared__ double2 lds[];
   constexpr int dd = d * d;
   const size_t off = (size_t)blockIdx.x * R.D;
@@ -332,26 +418,27 @@ __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const doub
   double2* Lo = lds + R.D;          // the other one (allocated only if a gate kind splits)
   for (int i = threadIdx.x; i < R.D; i += blockDim.x) L[i] = psi0[off + i];
   __syncthreads();
-  const int K = R.M + R.E;
-  const int passes = R.sym ? 2 : 1;
   for (int n = 0; n < R.N; ++n) {
     for (int j = 0; j < R.r; ++j) {
-      const double2* sgj = sg + ((size_t)n * R.r + j) * R.M * dd;
-      const double2* pgj = pg + (size_t)j * R.E * dd * dd;
-      for (int pass = 0; pass < passes; ++pass) {
-        for (int q = 0; q < K; ++q) {
-          const int k = pass == 0 ? q : K - 1 - q;
+      for (int h = 0; h < R.H; ++h) {
+        const double2* fgh = fg + (((size_t)n * R.r + j) * R.H + h) * R.nopmax * dd * dd;
+        const double2* fsj = fs + (size_t)j * R.nslot * dd * dd;
+        const double2* sgj = sg + ((size_t)n * R.r + j) * R.M * dd;
+        for (int o = 0; o < R.nop[h]; ++o) {
+          const double2* gt = !R.opk[h][o]  ? sgj + (size_t)R.opi[h][o] * dd
+                              : R.ops[h][o] ? fsj + (size_t)(R.ops[h][o] - 1) * dd * dd
+                                            : fgh + (size_t)o * dd * dd;
           bool swap = false;
-          if (k < R.M) {
+          if (!R.opk[h][o]) {
+            const int sm = R.stride[R.opi[h][o]];
             if (R.mode1) {
-              tr_apply1_rows<d>(L, Lo, R.D, R.stride[k], sgj + (size_t)k * dd);
+              tr_apply1_rows<d>(L, Lo, R.D, sm, gt);
               swap = true;
             } else {
-              tr_apply1<d>(L, R.D, R.stride[k], sgj + (size_t)k * dd);
+              tr_apply1<d>(L, R.D, sm, gt);
             }
           } else {
-            const int si = R.stride[R.ci[k - R.M]], sj = R.stride[R.cj[k - R.M]];
-            const double2* gt = pgj + (size_t)(k - R.M) * dd * dd;
+            const int si = R.stride[R.opi[h][o]], sj = R.stride[R.opj[h][o]];
             if (R.mode2 == 2) {
               tr_apply2_rows<d, d>(L, Lo, R.D, si, sj, gt);
               swap = true;
@@ -387,20 +474,131 @@ __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const doub
 }
 
 template <int d>
-hipError_t run_trotter(const TrRun& R, int S, const double2* psi0, double2* psiT, const double2* sg,
-                       const double2* pg, hipStream_t st) {
+hipError_t run_trotter(const TrRun& R, int S, const double2* psi0, double2* psiT, const double2* fg,
+                       const double2* fs, const double2* sg, hipStream_t st) {
   const size_t sh = (size_t)R.D * sizeof(double2) * ((R.mode1 || R.mode2) ? 2 : 1);
   hipError_t e = hipFuncSetAttribute((const void*)trotter_kernel<d>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(trotter_kernel<d>, dim3(S), dim3(TR_THREADS), sh, st, R, psi0, psiT, sg, pg);
+  hipLaunchKernelGGL(trotter_kernel<d>, dim3(S), dim3(TR_THREADS), sh, st, R, psi0, psiT, fg, fs, sg);
   return hipGetLastError();
 }
 
 struct TrLayout {
-  size_t eps, ops, par, pg, sg, total;
-  int r, sym, npar;
+  size_t eps, ops, par, plan, pg, sg, fg, fs, total;
+  int r, sym, npar, H, nopmax, mode1, mode2;
+  TrPlan P;
 };
+
+// Fusion plan.  Adjacent couplings on the same ordered mode pair form one
+// operation.  With ``absorb``, in the first pass (terms in order) every
+// single-mode gate commutes with the gates that do not touch its mode, so it
+// moves forward to the first pair operation on its mode and joins it as its
+// first factor; in the second pass (terms in reverse) it moves back to the
+// last pair operation on its mode and joins it as its last factor.  Without
+// it, or for a mode without a coupling, a single-mode gate stays an
+// operation of its own, where the unfused sequence has it.  Absorbing halves
+// the operations per step but makes the pair operations step-dependent
+// tables; it pays where a step is latency-bound (few fibres per gate).
+void build_plan(const scp_system* sys, int H, bool absorb, TrPlan& P) {
+  const int M = sys->n_modes, E = (int)sys->coup.size();
+  for (int h = 0; h < H; ++h) {
+    int nop = 0;
+    TrOp lone[SCP_MAX_MODES];
+    int nlone = 0;
+    for (int q = 0; q < E; ++q) {
+      const int e = h == 0 ? q : E - 1 - q;
+      const Coupling& c = sys->coup[e];
+      const bool join = nop > 0 && P.op[h][nop - 1].kind == 1 && P.op[h][nop - 1].mi == c.i &&
+                        P.op[h][nop - 1].mj == c.j && P.op[h][nop - 1].nc < TR_MAXC - 2;
+      if (!join) {
+        TrOp& o = P.op[h][nop++];
+        o = TrOp{};
+        o.kind = 1;
+        o.mi = c.i;
+        o.mj = c.j;
+      }
+      TrOp& o = P.op[h][nop - 1];
+      o.ctype[o.nc] = 1;
+      o.cidx[o.nc] = e;
+      o.cdig[o.nc] = 0;
+      ++o.nc;
+    }
+    const int npair = nop;
+    for (int m = 0; m < M; ++m) {
+      int host = -1;
+      for (int k = 0; absorb && k < npair; ++k) {
+        const TrOp& o = P.op[h][k];
+        if (o.mi == m || o.mj == m) {
+          host = k;
+          if (h == 0) break;                       // first operation on m (pass 1), else last
+        }
+      }
+      if (host < 0) {
+        TrOp& o = lone[nlone++];
+        o = TrOp{};
+        o.kind = 0;
+        o.mi = o.mj = m;
+        o.nc = 1;
+        o.ctype[0] = 0;
+        o.cidx[0] = m;
+        continue;
+      }
+      TrOp& o = P.op[h][host];
+      const int dg = o.mi == m ? 0 : 1;
+      if (h == 0) {                                // acts first: prepend
+        for (int c = o.nc; c > 0; --c) {
+          o.ctype[c] = o.ctype[c - 1];
+          o.cidx[c] = o.cidx[c - 1];
+          o.cdig[c] = o.cdig[c - 1];
+        }
+        o.ctype[0] = 0;
+        o.cidx[0] = m;
+        o.cdig[0] = dg;
+      } else {                                     // acts last: append
+        o.ctype[o.nc] = 0;
+        o.cidx[o.nc] = m;
+        o.cdig[o.nc] = dg;
+      }
+      ++o.nc;
+    }
+    // lone single-mode operations act first in the first pass, last in the
+    // second, in the order of the unfused sequence
+    for (int k = 0; k < npair; ++k) {
+      TrOp& o = P.op[h][k];
+      o.stat = 1;
+      for (int c = 0; c < o.nc; ++c) o.stat &= o.ctype[c] == 1;
+    }
+    if (h == 0) {
+      for (int k = npair - 1; k >= 0; --k) P.op[h][k + nlone] = P.op[h][k];
+      for (int k = 0; k < nlone; ++k) P.op[h][k] = lone[k];
+    } else {
+      for (int k = 0; k < nlone; ++k) P.op[h][npair + k] = lone[nlone - 1 - k];
+    }
+    P.nop[h] = nop + nlone;
+  }
+  // static slots: operations with the same factors in the same order share one
+  P.nslot = 0;
+  for (int h = 0; h < H; ++h)
+    for (int o = 0; o < P.nop[h]; ++o) {
+      TrOp& a = P.op[h][o];
+      if (!a.stat) continue;
+      a.own = 1;
+      a.sid = P.nslot;
+      for (int h2 = 0; h2 <= h && a.own; ++h2)
+        for (int o2 = 0; o2 < (h2 == h ? o : P.nop[h2]); ++o2) {
+          const TrOp& b = P.op[h2][o2];
+          bool same = b.stat && b.own && b.mi == a.mi && b.mj == a.mj && b.nc == a.nc;
+          for (int c = 0; same && c < a.nc; ++c) same = b.cidx[c] == a.cidx[c];
+          if (same) {
+            a.own = 0;
+            a.sid = b.sid;
+            break;
+          }
+        }
+      if (a.own) ++P.nslot;
+    }
+}
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -408,6 +606,22 @@ TrLayout tr_layout(const scp_system* sys, int order) {
   TrLayout L{};
   L.r = order == SCP_TROTTER_Q4 ? 3 : (order == SCP_TROTTER_Q4J ? 2 : 1);
   L.sym = order != SCP_TROTTER_Q1;
+  L.H = L.sym ? 2 : 1;
+  {
+    // split forms need a second column buffer; single-mode gates are
+    // absorbed into pair operations exactly when pair gates run split
+    const int64_t D = sys->D, dg = sys->d, E0 = (int64_t)sys->coup.size();
+    const bool two = 2 * D * (int64_t)sizeof(double2) <= TR_MAXLDS;
+    const int64_t nf1 = D / dg, nf2 = D / (dg * dg);
+    L.mode2 = (!two || E0 == 0 || nf2 >= TR_THREADS) ? 0 : (nf2 * dg >= TR_THREADS ? 2 : 1);
+    L.P = TrPlan{};
+    build_plan(sys, L.H, L.mode2 != 0, L.P);
+    bool any_single = false;
+    for (int h = 0; h < L.H; ++h)
+      for (int o = 0; o < L.P.nop[h]; ++o) any_single |= L.P.op[h][o].kind == 0;
+    L.mode1 = (two && any_single && nf1 < TR_THREADS) ? 1 : 0;
+  }
+  L.nopmax = std::max(L.P.nop[0], L.H > 1 ? L.P.nop[1] : 0);
   L.npar = 0;
   for (const Drive& R : sys->drives) L.npar += (int)R.par.size();
   const size_t d = sys->d, M = sys->n_modes, E = sys->coup.size();
@@ -418,10 +632,16 @@ TrLayout tr_layout(const scp_system* sys, int order) {
   o = align256(o + M * 2 * d * d * sizeof(double2));
   L.par = o;
   o = align256(o + std::max(1, L.npar) * sizeof(double));
+  L.plan = o;
+  o = align256(o + sizeof(TrPlan));
   L.pg = o;
   o = align256(o + (size_t)L.r * std::max<size_t>(1, E) * d * d * d * d * sizeof(double2));
   L.sg = o;
   o = align256(o + (size_t)sys->n_steps * L.r * M * d * d * sizeof(double2));
+  L.fg = o;
+  o = align256(o + (size_t)sys->n_steps * L.r * L.H * L.nopmax * d * d * d * d * sizeof(double2));
+  L.fs = o;
+  o = align256(o + (size_t)L.r * std::max(1, L.P.nslot) * d * d * d * d * sizeof(double2));
   L.total = o;
   return L;
 }
@@ -453,6 +673,7 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
   double* ieps = reinterpret_cast<double*>(in.data() + W.eps);
   double2* iops = reinterpret_cast<double2*>(in.data() + W.ops);
   double* ipar = reinterpret_cast<double*>(in.data() + W.par);
+  std::memcpy(in.data() + W.plan, &W.P, sizeof(TrPlan));
   for (int m = 0; m < M; ++m) {
     for (int a = 0; a < d; ++a) ieps[m * d + a] = sys->modes[m].eps[a];
     for (int op = 0; op < 2; ++op)
@@ -522,37 +743,51 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
                      4 * d * d * sizeof(double2) + TR_MAXDRV * sizeof(double), st, G, deps, dops, dpar,
                      sg);
   HIPCHK(hipGetLastError());
+  double2* fg = reinterpret_cast<double2*>(base + W.fg);
+  double2* fs = reinterpret_cast<double2*>(base + W.fs);
+  {
+    const size_t blocks = (size_t)N * W.r * W.H * W.nopmax;
+    const int n = d * d;
+    hipLaunchKernelGGL(tr_fuse_kernel, dim3((unsigned)blocks), dim3(256), 2 * n * n * sizeof(double2), st,
+                       d, W.r, W.H, W.nopmax, M, E, reinterpret_cast<const TrPlan*>(base + W.plan), sg,
+                       pg, fg, fs);
+    HIPCHK(hipGetLastError());
+  }
   TrRun R{};
   R.M = M;
   R.E = E;
   R.N = N;
   R.r = W.r;
   R.sym = W.sym;
-  R.D = (int)sys->D;
-  {
-    const bool two = 2 * sys->D * (int64_t)sizeof(double2) <= TR_MAXLDS;
-    const int64_t nf1 = sys->D / d, nf2 = sys->D / (d * d);
-    R.mode1 = (two && nf1 < TR_THREADS) ? 1 : 0;
-    R.mode2 = (!two || E == 0 || nf2 >= TR_THREADS) ? 0 : (nf2 * d >= TR_THREADS ? 2 : 1);
+  R.H = W.H;
+  R.nopmax = W.nopmax;
+  R.nslot = W.P.nslot;
+  for (int h = 0; h < W.H; ++h) {
+    R.nop[h] = W.P.nop[h];
+    for (int o = 0; o < W.P.nop[h]; ++o) {
+      R.opk[h][o] = W.P.op[h][o].kind;
+      R.opi[h][o] = W.P.op[h][o].mi;
+      R.opj[h][o] = W.P.op[h][o].mj;
+      R.ops[h][o] = W.P.op[h][o].stat ? W.P.op[h][o].sid + 1 : 0;
+    }
   }
+  R.D = (int)sys->D;
+  R.mode1 = W.mode1;
+  R.mode2 = W.mode2;
   int s = 1;
   for (int m = M - 1; m >= 0; --m) {
     R.stride[m] = s;
     s *= d;
-  }
-  for (int e = 0; e < E; ++e) {
-    R.ci[e] = sys->coup[e].i;
-    R.cj[e] = sys->coup[e].j;
   }
   const double twopi = 6.283185307179586476925286766559;
   for (int m = 0; m < M; ++m)
     for (int a = 0; a < d; ++a) R.fT[m][a] = std::remainder(sys->modes[m].frame[a] * N * sys->h, twopi);
   hipError_t e;
   switch (d) {
-    case 2: e = run_trotter<2>(R, S, psi0, psiT, sg, pg, st); break;
-    case 3: e = run_trotter<3>(R, S, psi0, psiT, sg, pg, st); break;
-    case 4: e = run_trotter<4>(R, S, psi0, psiT, sg, pg, st); break;
-    default: e = run_trotter<5>(R, S, psi0, psiT, sg, pg, st); break;
+    case 2: e = run_trotter<2>(R, S, psi0, psiT, fg, fs, sg, st); break;
+    case 3: e = run_trotter<3>(R, S, psi0, psiT, fg, fs, sg, st); break;
+    case 4: e = run_trotter<4>(R, S, psi0, psiT, fg, fs, sg, st); break;
+    default: e = run_trotter<5>(R, S, psi0, psiT, fg, fs, sg, st); break;
   }
   HIPCHK(e);
   return SCP_OK;
