@@ -224,7 +224,9 @@ def trotter_flop(desc, order):
     complex multiply-add.  Executed: after the library's fusion, which merges
     adjacent couplings on the same ordered mode pair and, when pair gates run
     split (32 D bytes fit in 160 KiB and D / d^2 < 512 fibres), absorbs every
-    coupled mode's single-mode gate into a pair operation."""
+    coupled mode's single-mode gate into a pair operation.  (Where pair gates
+    run in place, single-mode gates are applied in registers next to them:
+    fewer passes over the state, the same arithmetic.)"""
     d = desc["modes"][0]["trunc"]
     M = len(desc["modes"])
     pairs = [(c["i"], c["j"]) for c in desc["couplings"]]

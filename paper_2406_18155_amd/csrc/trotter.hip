@@ -73,6 +73,8 @@ struct TrOp {
   int kind, mi, mj, nc;
   int stat;   // no single-mode factor: the same gate every step, in static slot sid
   int sid, own;   // own: this operation forms the slot (equal products share one)
+  int s0, s1;     // register form: mode + 1 of the single-mode gate on digit 0 / 1 (0: none),
+                  // applied before the pair product in the first pass, after it in the second
   int ctype[TR_MAXC], cidx[TR_MAXC], cdig[TR_MAXC];
 };
 struct TrPlan {
@@ -85,11 +87,14 @@ struct TrRun {
   int nop[2];
   int opk[2][TR_MAXOPS], opi[2][TR_MAXOPS], opj[2][TR_MAXOPS];
   int ops[2][TR_MAXOPS];   // static slot + 1, or 0
+  int opa[2][TR_MAXOPS];   // register form: (s0) | (s1 << 8), see TrOp
   int mode1;                   // single-mode gates: 0 in place, 1 one output row per item
   int mode2;                   // pair gates: 0 in place, 1 one row, 2 d rows per item
   int stride[SCP_MAX_MODES];   // stride of mode m inside a column (mode 0 slowest)
   double fT[SCP_MAX_MODES][SCP_MAX_TRUNC];   // frame energy times T, reduced mod 2 pi
 };
+
+static_assert(sizeof(TrRun) <= 4000, "TrRun is passed by value as a kernel argument");
 
 __device__ inline double wrap_2pi(double x) {
   const double twopi = 6.283185307179586476925286766559;
@@ -337,9 +342,35 @@ __device__ inline void tr_apply1(double2* L, int D, int s, const double2* __rest
   }
 }
 
-// In place: a thread owns whole fibres of a pair gate.
+// A d x d gate on digit 0 (dg = 0) or digit 1 of a fibre x[a * d + b] in registers.
+template <int d, int dg>
+__device__ inline void single_on_digit(const double2* __restrict__ S, double2* x) {
+#pragma unroll
+  for (int u = 0; u < d; ++u) {
+    double2 t[d];
+#pragma unroll
+    for (int a = 0; a < d; ++a) {
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int k = 0; k < d; ++k) {
+        const double2 g = S[a * d + k], v = dg == 0 ? x[k * d + u] : x[u * d + k];
+        re += g.x * v.x - g.y * v.y;
+        im += g.x * v.y + g.y * v.x;
+      }
+      t[a] = make_double2(re, im);
+    }
+#pragma unroll
+    for (int a = 0; a < d; ++a) (dg == 0 ? x[a * d + u] : x[u * d + a]) = t[a];
+  }
+}
+
+// In place: a thread owns whole fibres of a pair gate.  For d <= 3 the
+// single-mode gates S0 (digit 0) and S1 (digit 1), when not null, are
+// applied in registers before the pair gate (post = 0) or after it.
 template <int d>
-__device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double2* __restrict__ Gt) {
+__device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double2* __restrict__ Gt,
+                                 const double2* __restrict__ S0, const double2* __restrict__ S1,
+                                 int post) {
   constexpr int dd = d * d;
   const int sp = si > sj ? si : sj, sq = si > sj ? sj : si, w = sp / (sq * d);
   const double isq = 1.0 / sq, iw = 1.0 / w;
@@ -351,6 +382,23 @@ __device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double
     for (int a = 0; a < d; ++a)
 #pragma unroll
       for (int b = 0; b < d; ++b) x[a * d + b] = L[base + a * si + b * sj];
+    if constexpr (d <= 3) {
+      if (!post) {
+        if (S0) single_on_digit<d, 0>(S0, x);
+        if (S1) single_on_digit<d, 1>(S1, x);
+      } else if (S0 || S1) {
+        double2 y[dd];
+#pragma unroll
+        for (int r = 0; r < dd; ++r) y[r] = crow<d>(Gt + r * dd, x, dd);
+        if (S0) single_on_digit<d, 0>(S0, y);
+        if (S1) single_on_digit<d, 1>(S1, y);
+#pragma unroll
+        for (int a = 0; a < d; ++a)
+#pragma unroll
+          for (int b = 0; b < d; ++b) L[base + a * si + b * sj] = y[a * d + b];
+        continue;
+      }
+    }
 #pragma unroll
     for (int a = 0; a < d; ++a)
 #pragma unroll
@@ -446,7 +494,9 @@ __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const doub
               tr_apply2_rows<d, 1>(L, Lo, R.D, si, sj, gt);
               swap = true;
             } else {
-              tr_apply2<d>(L, R.D, si, sj, gt);
+              const int pa = R.opa[h][o], a0 = pa & 255, a1 = pa >> 8;
+              tr_apply2<d>(L, R.D, si, sj, gt, a0 ? sgj + (size_t)(a0 - 1) * dd : nullptr,
+                           a1 ? sgj + (size_t)(a1 - 1) * dd : nullptr, h);
             }
           }
           if (swap) {
@@ -498,9 +548,11 @@ struct TrLayout {
 // last pair operation on its mode and joins it as its last factor.  Without
 // it, or for a mode without a coupling, a single-mode gate stays an
 // operation of its own, where the unfused sequence has it.  Absorbing halves
-// the operations per step but makes the pair operations step-dependent
-// tables; it pays where a step is latency-bound (few fibres per gate).
-void build_plan(const scp_system* sys, int H, bool absorb, TrPlan& P) {
+// the operations per step.  Formed into the fused tables it makes the pair
+// operations step-dependent, which pays where a step is latency-bound (few
+// fibres per gate); with ``regs`` the absorbed gates instead stay separate
+// (TrOp::s0, s1) and are applied in registers next to a static pair product.
+void build_plan(const scp_system* sys, int H, bool absorb, bool regs, TrPlan& P) {
   const int M = sys->n_modes, E = (int)sys->coup.size();
   for (int h = 0; h < H; ++h) {
     int nop = 0;
@@ -562,6 +614,22 @@ void build_plan(const scp_system* sys, int H, bool absorb, TrPlan& P) {
       }
       ++o.nc;
     }
+    // register form: the absorbed single-mode gates leave the factor list
+    for (int k = 0; regs && k < npair; ++k) {
+      TrOp& o = P.op[h][k];
+      int nc = 0;
+      for (int c = 0; c < o.nc; ++c) {
+        if (o.ctype[c] == 0) {
+          (o.cdig[c] == 0 ? o.s0 : o.s1) = o.cidx[c] + 1;
+          continue;
+        }
+        o.ctype[nc] = o.ctype[c];
+        o.cidx[nc] = o.cidx[c];
+        o.cdig[nc] = o.cdig[c];
+        ++nc;
+      }
+      o.nc = nc;
+    }
     // lone single-mode operations act first in the first pass, last in the
     // second, in the order of the unfused sequence
     for (int k = 0; k < npair; ++k) {
@@ -614,8 +682,11 @@ TrLayout tr_layout(const scp_system* sys, int order) {
     const bool two = 2 * D * (int64_t)sizeof(double2) <= TR_MAXLDS;
     const int64_t nf1 = D / dg, nf2 = D / (dg * dg);
     L.mode2 = (!two || E0 == 0 || nf2 >= TR_THREADS) ? 0 : (nf2 * dg >= TR_THREADS ? 2 : 1);
+    // where pair gates run in place (large D, d <= 3) the single-mode gates
+    // are absorbed in registers instead, next to static pair products
+    const bool regs = L.mode2 == 0 && E0 > 0 && dg <= 3;
     L.P = TrPlan{};
-    build_plan(sys, L.H, L.mode2 != 0, L.P);
+    build_plan(sys, L.H, L.mode2 != 0 || regs, regs, L.P);
     bool any_single = false;
     for (int h = 0; h < L.H; ++h)
       for (int o = 0; o < L.P.nop[h]; ++o) any_single |= L.P.op[h][o].kind == 0;
@@ -769,6 +840,7 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
       R.opi[h][o] = W.P.op[h][o].mi;
       R.opj[h][o] = W.P.op[h][o].mj;
       R.ops[h][o] = W.P.op[h][o].stat ? W.P.op[h][o].sid + 1 : 0;
+      R.opa[h][o] = W.P.op[h][o].s0 | (W.P.op[h][o].s1 << 8);
     }
   }
   R.D = (int)sys->D;

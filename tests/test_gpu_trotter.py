@@ -171,3 +171,21 @@ def test_trotter_x6_fluxonium_workload_sampled_columns(scp):
         U = out[pick].cpu().numpy().T
         ref = trotter.propagate(o, order, psi0=np.eye(o.D)[:, cols])
         assert np.abs(U - ref).max() <= TOL, order
+
+
+@pytest.mark.parametrize("order", trotter.ORDERS)
+def test_trotter_ring8_register_form_every_order(scp, order):
+    # The ring's pair gates run in place with its single-mode gates applied in
+    # registers (before the pair gate in the first pass, after it in the
+    # second): every order over its first 20 steps, 4 sampled columns.
+    desc = _prefix(si.config5(), 20)
+    print(f"[trotter] ring 8 x d3, 256 columns, 20 steps, {order}", flush=True)
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, desc["columns"], dtype=torch.complex128)
+    out = g.propagate_trotter(psi0, order)
+    torch.cuda.synchronize()
+    pick = si.sampled_columns(len(desc["columns"]), n_sample=4)
+    U = out[pick].cpu().numpy().T
+    o = OracleSystem(desc)
+    ref = trotter.propagate(o, order, psi0=np.eye(o.D)[:, np.asarray(desc["columns"])[pick]])
+    assert np.abs(U - ref).max() <= TOL
