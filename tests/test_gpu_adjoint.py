@@ -9,7 +9,7 @@ import pytest
 
 import scp_inputs as si
 from oracle.system import OracleSystem
-from oracle.adjoint import loss_and_grad, param_names
+from oracle.adjoint import gradient, loss_and_grad, param_names
 from oracle.fd import fd_gradient
 
 torch = pytest.importorskip("torch")
@@ -355,3 +355,29 @@ def test_zcomp_gradient_matches_oracle(scp, name):
     _, F2, _, _, go = loss_and_grad(OracleSystem(d2))
     assert abs(F2 - Fo) <= 1e-12
     check_grad(grad, go)
+
+
+def test_x6_chain_gradient_from_a_random_costate(scp):
+    # The shape of the paper's X^(x)6 benchmark (6-fluxonium multipath chain,
+    # d = 4, D = 4096, 148 parameters) at its step of 0.01 ns, over 30 steps
+    # and 8 of its 64 columns: the adjoint's gradient for a seeded random
+    # costate of the final state against the oracle's for the same costate.
+    full = si.fluxonium6_x6()
+    dt = full["T"] / full["n_steps"]
+    desc = dict(full, n_steps=30, T=30 * dt)
+    print("[adjoint] X6 chain 6 x d4, 30 steps, 8 columns, random costate", flush=True)
+    cols = [int(c) for c in np.asarray(desc["columns"])[si.sampled_columns(len(desc["columns"]))]]
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, cols)
+    opts = g.opts(len(cols), with_ckpt=1)
+    ws = g.workspace(opts, with_grad=True)
+    g.propagate(psi0, opts=opts, workspace=ws)
+    rng = np.random.default_rng(2406018155)
+    lam = (rng.normal(size=(g.D, len(cols))) + 1j * rng.normal(size=(g.D, len(cols))))
+    lam = lam.astype(np.complex64).astype(np.complex128)      # the costate the device sees
+    cot = torch.tensor(lam.T.copy(), dtype=torch.complex64, device="cuda")
+    grad = g.adjoint(cot, opts, ws)
+    g.close()
+    o = OracleSystem(desc)
+    ref, _ = gradient(o, lam, psi0=np.eye(o.D)[:, cols])
+    check_grad(grad, ref)
