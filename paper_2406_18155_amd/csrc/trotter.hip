@@ -24,15 +24,19 @@
 //      matrix, twenty-five years later", SIAM Review 2003, Sec. 3): halve
 //      until the 1-norm is at most 1/2, sum the series to degree 18
 //      (truncation below 1e-22 relative), square back;
-//   2. the propagation: one workgroup per state column keeps the column in
-//      LDS (16 D bytes) for all steps and applies the gates in sequence, one
-//      barrier between gates.  A gate kind with at least as many fibres as
-//      threads runs in place, a thread owning whole fibres of the contracted
-//      mode(s).  With fewer fibres (small D, pair gates) and room for a second
-//      column buffer (32 D bytes <= 160 KiB), a work item computes d output
-//      rows (pair gates, when that fills the block) or one output row of one
-//      fibre from one buffer into the other, which keeps up to d^2 times more
-//      threads busy; the buffers swap after such a gate.
+//   2. fusion (build_plan, tr_fuse_kernel): adjacent couplings on the same
+//      mode pair become one operation, and single-mode gates join pair
+//      operations (as table products where pair gates run split, in
+//      registers where they run in place);
+//   3. the propagation: one workgroup per state column keeps the column in
+//      LDS (16 D bytes) for all steps and applies the operations in
+//      sequence, one barrier between operations.  An operation kind with at
+//      least as many fibres as threads runs in place, a thread owning whole
+//      fibres of the contracted mode(s).  With fewer fibres (small D) and
+//      room for a second column buffer (32 D bytes <= 160 KiB), a work item
+//      computes d output rows (pair operations, when that fills the block)
+//      or one output row of one fibre from one buffer into the other, which
+//      keeps up to d^2 times more threads busy; the buffers then swap.
 #include <cmath>
 #include <cstring>
 
@@ -57,7 +61,7 @@ struct TrDrive {
 };
 
 struct TrGen {
-  int d, M, E, N, r, sym, ndrives;
+  int d, M, E, N, r, ndrives;
   double dt, T, tau;
   double a_re[TR_MAXPIECE], a_im[TR_MAXPIECE], mid[TR_MAXPIECE];
   TrDrive dr[TR_MAXDRV];
@@ -83,7 +87,7 @@ struct TrPlan {
 };
 
 struct TrRun {
-  int M, E, N, r, sym, D, H, nopmax, nslot;
+  int M, N, r, D, H, nopmax, nslot;
   int nop[2];
   int opk[2][TR_MAXOPS], opi[2][TR_MAXOPS], opj[2][TR_MAXOPS];
   int ops[2][TR_MAXOPS];   // static slot + 1, or 0
@@ -759,7 +763,6 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
   G.E = E;
   G.N = N;
   G.r = W.r;
-  G.sym = W.sym;
   G.ndrives = (int)sys->drives.size();
   G.dt = sys->h;
   G.T = sys->T;
@@ -826,10 +829,8 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
   }
   TrRun R{};
   R.M = M;
-  R.E = E;
   R.N = N;
   R.r = W.r;
-  R.sym = W.sym;
   R.H = W.H;
   R.nopmax = W.nopmax;
   R.nslot = W.P.nslot;
