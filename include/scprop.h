@@ -271,8 +271,10 @@ scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, vo
 enum { SCP_TROTTER_Q1 = 0, SCP_TROTTER_Q2 = 1, SCP_TROTTER_Q4 = 2, SCP_TROTTER_Q4J = 3 };
 
 /* Device workspace bytes of scp_propagate_trotter: inputs, the pair gates
- * of every (piece, coupling) and the single-mode gates of every (step,
- * piece, mode), all complex FP64.  SCP_EINVAL for an unknown order or a
+ * of every (piece, coupling), the single-mode gates of every (step, piece,
+ * mode) and the fused operations (adjacent couplings on one mode pair, and
+ * for small D the single-mode gates joined to them) of every (step, piece,
+ * pass), all complex FP64.  Grows linearly with n_steps.  SCP_EINVAL for an unknown order or a
  * system outside the path's limits (d = 2..5, 16 D bytes <= 160 KiB,
  * <= 48 couplings, <= 32 drives). */
 scp_status scp_trotter_workspace_size(const scp_system* sys, int32_t order, size_t* bytes);
@@ -281,8 +283,8 @@ scp_status scp_trotter_workspace_size(const scp_system* sys, int32_t order, size
  * column-major) over the system's n_steps steps of dt = T / n_steps with
  * the product formula ``order`` into psiT (same layout; may alias psi0).
  * Everything is complex FP64 on the device: the gates are formed by Taylor
- * scaling and squaring, and one workgroup per column keeps the column in
- * LDS.  The result is rotated into the frame of scp_propagate,
+ * scaling and squaring and fused (the result is the same product up to
+ * rounding), and one workgroup per column keeps the column in LDS.  The result is rotated into the frame of scp_propagate,
  * psi_I(T) = exp(i H_f T) psi_lab(T), so both paths compare directly.
  * workspace: device, scp_trotter_workspace_size bytes, caller-owned.
  * Synchronises the stream once, before the first kernel (upload of the
