@@ -321,12 +321,20 @@ __device__ inline int fibre2(int f, int sp, int sq, int w, double inv_sq, double
   return hi * sp * d + (t - hi * w) * sq * d + (f - t * sq);
 }
 
+// (re, im) += g v as four fused multiply-adds (written as a difference of
+// products the compiler keeps a separate multiply and add per component).
+__device__ inline void cmac(double& re, double& im, double2 g, double2 v) {
+  re = fma(g.x, v.x, re);
+  re = fma(-g.y, v.y, re);
+  im = fma(g.x, v.y, im);
+  im = fma(g.y, v.x, im);
+}
+
 template <int d>
 __device__ inline double2 crow(const double2* __restrict__ g, const double2* x, int n) {
   double re = 0.0, im = 0.0;
   for (int c = 0; c < n; ++c) {
-    re += g[c].x * x[c].x - g[c].y * x[c].y;
-    im += g[c].x * x[c].y + g[c].y * x[c].x;
+    cmac(re, im, g[c], x[c]);
   }
   return make_double2(re, im);
 }
@@ -357,9 +365,7 @@ __device__ inline void single_on_digit(const double2* __restrict__ S, double2* x
       double re = 0.0, im = 0.0;
 #pragma unroll
       for (int k = 0; k < d; ++k) {
-        const double2 g = S[a * d + k], v = dg == 0 ? x[k * d + u] : x[u * d + k];
-        re += g.x * v.x - g.y * v.y;
-        im += g.x * v.y + g.y * v.x;
+        cmac(re, im, S[a * d + k], dg == 0 ? x[k * d + u] : x[u * d + k]);
       }
       t[a] = make_double2(re, im);
     }
