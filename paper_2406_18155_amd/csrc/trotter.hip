@@ -435,9 +435,12 @@ __device__ inline void tr_apply1_rows(const double2* in, double2* out, int D, in
 
 // Pair gate, RPI output rows per work item: RPI = d computes the rows
 // (a, 0..d-1) of one fibre (w = a * nf + f), RPI = 1 one row (w = r * nf + f).
-template <int d, int RPI>
-__device__ inline void tr_apply2_rows(const double2* in, double2* out, int D, int si, int sj,
-                                      const double2* __restrict__ Gt) {
+// UNI: nf is a multiple of 64, so the 64 items of a wave (w from a multiple
+// of 64, stepping by the block size) share their row group; taking it from
+// the first lane makes the gate rows wave-uniform (scalar loads).
+template <int d, int RPI, bool UNI>
+__device__ inline void tr_apply2_rows_as(const double2* in, double2* out, int D, int si, int sj,
+                                         const double2* __restrict__ Gt) {
   constexpr int dd = d * d;
   const int sp = si > sj ? si : sj, sq = si > sj ? sj : si, w0 = sp / (sq * d);
   const double isq = 1.0 / sq, iw = 1.0 / w0;
@@ -445,7 +448,8 @@ __device__ inline void tr_apply2_rows(const double2* in, double2* out, int D, in
   const double inf = 1.0 / nf;
   const int items = nf * (dd / RPI);
   for (int w = threadIdx.x; w < items; w += blockDim.x) {
-    const int g = qdiv(w, inf);               // row group
+    int g = qdiv(w, inf);                     // row group
+    if constexpr (UNI) g = __builtin_amdgcn_readfirstlane(g);
     const int base = fibre2<d>(w - g * nf, sp, sq, w0, isq, iw);
     double2 x[dd];
 #pragma unroll
@@ -458,6 +462,15 @@ __device__ inline void tr_apply2_rows(const double2* in, double2* out, int D, in
       out[base + (r / d) * si + (r % d) * sj] = crow<d>(Gt + r * dd, x, dd);
     }
   }
+}
+
+template <int d, int RPI>
+__device__ inline void tr_apply2_rows(const double2* in, double2* out, int D, int si, int sj,
+                                      const double2* __restrict__ Gt) {
+  if ((D / (d * d)) % 64 == 0)
+    tr_apply2_rows_as<d, RPI, true>(in, out, D, si, sj, Gt);
+  else
+    tr_apply2_rows_as<d, RPI, false>(in, out, D, si, sj, Gt);
 }
 
 // Workgroup = one column; fg: fused gates [N][r][H][nopmax][d^4] of pair
