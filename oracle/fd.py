@@ -53,12 +53,14 @@ def _perturbed(base, idx, delta):
     return d
 
 
-def fd_gradient(desc, indices, step=2e-6 * np.pi):
-    """Central differences dL/dtheta_i for the parameter positions ``indices``."""
+def fd_gradient(desc, indices, step=2e-6 * np.pi, loss_fn=None):
+    """Central differences dL/dtheta_i for the parameter positions ``indices``
+    (loss_fn(desc) -> L; default the RK4 gate infidelity)."""
     base = frozen_desc(desc)
+    f = loss if loss_fn is None else loss_fn
     out = {}
     for i in indices:
-        lp = loss(_perturbed(base, i, step))
-        lm = loss(_perturbed(base, i, -step))
+        lp = f(_perturbed(base, i, step))
+        lm = f(_perturbed(base, i, -step))
         out[i] = (lp - lm) / (2.0 * step)
     return out
