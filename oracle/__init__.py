@@ -13,13 +13,14 @@ from .single_mode import (build_mode, transmon_basis, fluxonium_basis,
                           displacement_matrix, dressed_truncation, mode_derivatives)
 from .system import OracleSystem, build_system
 from .rk4 import propagate, apply_generator
-from .fidelity import fidelity, cotangent
+from .fidelity import fidelity, cotangent, state_fidelity, state_cotangent
 from .adjoint import gradient, loss_and_grad, param_names
 from .fd import fd_gradient
 
 __all__ = [
     "build_mode", "transmon_basis", "fluxonium_basis", "displacement_matrix",
     "dressed_truncation", "mode_derivatives", "OracleSystem", "build_system",
-    "propagate", "apply_generator", "fidelity", "cotangent", "gradient",
+    "propagate", "apply_generator", "fidelity", "cotangent", "state_fidelity",
+    "state_cotangent", "gradient",
     "loss_and_grad", "param_names", "fd_gradient",
 ]

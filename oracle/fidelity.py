@@ -115,3 +115,25 @@ def zcomp_target(target, a, c):
     th = bits @ np.asarray(a, dtype=np.float64)
     ch = bits @ np.asarray(c, dtype=np.float64)
     return np.asarray(target) * np.exp(-1j * th)[:, None] * np.exp(-1j * ch)[None, :]
+
+
+def state_fidelity(U, targets):
+    """Composite state-transfer cost of Sec. 4.1 (eq. for the composite state
+    cost): F = |(1/S) sum_s <phi_s|psi_s>|^2 and L = 1 - F, where psi_s are the
+    S columns of U (D x S) and phi_s the columns of ``targets`` (D x S), full
+    target states rather than a computational block.  Returns (F, tau) with
+    tau = sum_s <phi_s|psi_s>."""
+    U = np.asarray(U)
+    targets = np.asarray(targets)
+    assert U.shape == targets.shape
+    S = U.shape[1]
+    tau = complex(np.sum(np.conj(targets) * U))
+    return abs(tau) ** 2 / S ** 2, tau
+
+
+def state_cotangent(targets, tau):
+    """Costate of the composite state cost with dL = 2 Re <lambda, dU>:
+    dL = -2 Re(conj(tau) <phi, dU>) / S^2, so lambda = -(tau / S^2) phi."""
+    targets = np.asarray(targets, dtype=np.complex128)
+    S = targets.shape[1]
+    return -(tau / S ** 2) * targets

@@ -211,6 +211,13 @@ def sampled_columns(n_cols: int, n_sample: int = 8, seed: int = BASE_SEED + 5):
     return sorted([0, n_cols - 1] + [int(v) for v in rest])
 
 
+def random_states(D: int, S: int, seed: int = BASE_SEED + 55):
+    """Seeded complex Gaussian vectors (D x S), unnormalised: the direction by
+    which a state target is moved off the oracle's own final states."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.normal(size=(D, S)) + 1j * rng.normal(size=(D, S))
+
+
 def serving_request(r: int):
     """Request ``r`` of the serving stream: family uniform over {transmon chain,
     transmon ring (>= 3 modes), fluxonium chain}; 2..6 modes; d in {3,4,5}

@@ -2,6 +2,8 @@
 
     python tests/golden/make_oracle_refs.py            # config3_oracle.json
     python tests/golden/make_oracle_refs.py config5    # config5_sampled_oracle.json
+    python tests/golden/make_oracle_refs.py config5_state
+        # config5_state_target.npy + config5_state_oracle.json
 
 config3_oracle.json: loss, fidelity and the full gradient of the config-3
 workload (4-fluxonium chain, CZ(q0,q1) x I x I target, 5000 RK4 steps),
@@ -18,7 +20,9 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import scp_inputs as si  # noqa: E402
 from oracle.system import OracleSystem  # noqa: E402
-from oracle.adjoint import loss_and_grad, param_names  # noqa: E402
+from oracle.adjoint import gradient, loss_and_grad, param_names  # noqa: E402
+from oracle.fidelity import state_cotangent, state_fidelity  # noqa: E402
+from oracle.rk4 import basis_columns, propagate  # noqa: E402
 
 
 def main():
@@ -40,8 +44,10 @@ if __name__ == "__main__" and len(sys.argv) == 1:
 def config5_sampled():
     """Oracle F and gradient for the 8 seeded sampled columns of the 8-transmon
     ring (fidelity restricted to the sampled computational states), for two
-    targets: CZ(q0,q1) restricted to them, and the nearest unitary to the
-    oracle's own computational block (F ~ 1, where |dF| is most sensitive)."""
+    targets: CZ(q0,q1) restricted to them (F ~ 5e-7), and the nearest unitary
+    to the oracle's own 8 x 8 computational block ("block_target"; F ~ 5e-3,
+    since the sampled columns carry little weight on the sampled rows).  The
+    F ~ 1 case is config5_state below."""
     desc = sampled_config5_desc()
     sys_ = OracleSystem(desc)
     L, F, tau, U, g = loss_and_grad(sys_)
@@ -56,7 +62,7 @@ def config5_sampled():
            "columns": desc["columns"], "L": L, "F": F, "tau": [tau.real, tau.imag],
            "param_names": param_names(sys_), "grad": [float(v) for v in g],
            "block_re": block.real.tolist(), "block_im": block.imag.tolist(),
-           "near_unit": {"target_re": t1.real.tolist(), "target_im": t1.imag.tolist(),
+           "block_target": {"target_re": t1.real.tolist(), "target_im": t1.imag.tolist(),
                          "L": L1, "F": F1, "tau": [tau1.real, tau1.imag],
                          "grad": [float(v) for v in g1]}}
     with open(os.path.join(HERE, "config5_sampled_oracle.json"), "w") as f:
@@ -76,3 +82,35 @@ def sampled_config5_desc():
 
 if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "config5":
     config5_sampled()
+
+
+def config5_state():
+    """Composite state cost (Sec. 4.1) of the 8 seeded sampled columns of the
+    8-transmon ring at F close to 1: each target state is the oracle's own
+    normalised final state moved by 0.1 (relative) along a seeded random
+    direction and normalised again, so F_oracle ~ 0.99 and the gradient is not
+    zero.  Writes the targets (D x 8 complex128, column j for sampled column j)
+    and the oracle's F, tau and gradient."""
+    desc = sampled_config5_desc()
+    sys_ = OracleSystem(desc)
+    psi0 = basis_columns(sys_.D, desc["columns"])
+    U = propagate(sys_, psi0)
+    r = si.random_states(sys_.D, U.shape[1])
+    phi = U / np.linalg.norm(U, axis=0)[None, :] + 0.1 * r / np.linalg.norm(r, axis=0)[None, :]
+    phi = phi / np.linalg.norm(phi, axis=0)[None, :]
+    F, tau = state_fidelity(U, phi)
+    lam = state_cotangent(phi, tau)
+    g, _ = gradient(sys_, lam, psi0)
+    np.save(os.path.join(HERE, "config5_state_target.npy"), phi, allow_pickle=False)
+    out = {"workload": "config5 sampled: 8-transmon ring d=3, T=60 ns, 3000 steps, 8 sampled "
+                       "computational columns, composite state cost against "
+                       "config5_state_target.npy (the oracle's final states moved by 0.1)",
+           "generator": "tests/golden/make_oracle_refs.py config5_state (oracle only)",
+           "columns": desc["columns"], "L": 1.0 - F, "F": F, "tau": [tau.real, tau.imag],
+           "param_names": param_names(sys_), "grad": [float(v) for v in g]}
+    with open(os.path.join(HERE, "config5_state_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "config5_state":
+    config5_state()

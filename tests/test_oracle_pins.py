@@ -19,7 +19,8 @@ from oracle.single_mode import (DegenerateSpectrum, build_mode, displacement_mat
                                 transmon_basis)
 from oracle.system import OracleSystem
 from oracle.rk4 import basis_columns, propagate
-from oracle.fidelity import average_gate_fidelity, cotangent, fidelity
+from oracle.fidelity import (average_gate_fidelity, cotangent, fidelity, state_cotangent,
+                             state_fidelity)
 from oracle.adjoint import gradient, loss_and_grad, param_names
 from oracle.fd import fd_gradient
 
@@ -275,6 +276,54 @@ def test_cotangent_is_the_wirtinger_gradient():
     Lp = 1 - fidelity(U + e * dU, rows, cols, T)[0]
     Lm = 1 - fidelity(U - e * dU, rows, cols, T)[0]
     assert (Lp - Lm) / (2 * e) == pytest.approx(2 * np.vdot(lam, dU).real, rel=1e-7)
+
+
+def test_state_cost_closed_forms():
+    # one column: |<phi|psi>|^2 with phi = cos a |0> + e^{ib} sin a |1>, psi = |0>
+    for a, b in ((0.3, 0.0), (1.1, 2.0), (math.pi / 2, 0.7)):
+        phi = np.array([[math.cos(a)], [np.exp(1j * b) * math.sin(a)], [0.0]])
+        psi = np.array([[1.0], [0.0], [0.0]], dtype=complex)
+        assert state_fidelity(psi, phi)[0] == pytest.approx(math.cos(a) ** 2, abs=1e-15)
+    # normalised columns against themselves: F = 1; a common phase drops out;
+    # per-column phases that differ do not
+    rng = np.random.default_rng(21)
+    U = rng.normal(size=(9, 4)) + 1j * rng.normal(size=(9, 4))
+    U /= np.linalg.norm(U, axis=0)[None, :]
+    assert state_fidelity(U, U)[0] == pytest.approx(1.0, abs=1e-14)
+    assert state_fidelity(U * np.exp(0.8j), U)[0] == pytest.approx(1.0, abs=1e-14)
+    ph = np.exp(1j * np.array([0.0, 0.5, 1.0, 1.5]))
+    assert state_fidelity(U * ph[None, :], U)[0] == pytest.approx(abs(ph.sum()) ** 2 / 16,
+                                                                  abs=1e-14)
+
+
+def test_state_cost_over_a_basis_is_the_gate_fidelity():
+    # Sec. 4.1: with target states U_t|e_s> over a complete basis the composite
+    # state cost is the gate fidelity |Tr(U_t^dag U)|^2 / d^2 (here the basis
+    # states sit on rows 1, 3, 4, 6 of a 7-dimensional space)
+    rng = np.random.default_rng(22)
+    Ut = _haar(4, rng)
+    rows = [1, 3, 4, 6]
+    U = rng.normal(size=(7, 4)) + 1j * rng.normal(size=(7, 4))
+    phi = np.zeros((7, 4), dtype=complex)
+    phi[rows, :] = Ut
+    F_state, tau_state = state_fidelity(U, phi)
+    tr = np.trace(Ut.conj().T @ U[rows, :])
+    assert F_state == pytest.approx(abs(tr) ** 2 / 16, rel=1e-13)
+    assert tau_state == pytest.approx(tr, rel=1e-13)
+
+
+def test_state_cotangent_is_the_wirtinger_gradient():
+    rng = np.random.default_rng(23)
+    U = rng.normal(size=(6, 3)) + 1j * rng.normal(size=(6, 3))
+    phi = rng.normal(size=(6, 3)) + 1j * rng.normal(size=(6, 3))
+    F, tau = state_fidelity(U, phi)
+    lam = state_cotangent(phi, tau)
+    for _ in range(3):
+        dU = rng.normal(size=U.shape) + 1j * rng.normal(size=U.shape)
+        e = 1e-6
+        Lp = 1 - state_fidelity(U + e * dU, phi)[0]
+        Lm = 1 - state_fidelity(U - e * dU, phi)[0]
+        assert (Lp - Lm) / (2 * e) == pytest.approx(2 * np.vdot(lam, dU).real, rel=1e-7)
 
 
 # ----------------------------------------------------------------------------
