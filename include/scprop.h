@@ -126,6 +126,9 @@ typedef struct {
                           1: complex FP64 plain path (one launch per term)  */
   int32_t ckpt_every;  /* checkpoint interval for the adjoint; 0 = ceil(sqrt(N)) */
   int32_t with_ckpt;   /* propagate: 1 = keep checkpoints in the workspace  */
+  size_t workspace_bytes;  /* size of the workspace passed with these opts; a
+                              call whose workspace_size exceeds it is refused
+                              (SCP_EINVAL) before any launch               */
 } scp_solve_opts;
 
 typedef struct scp_system scp_system;
@@ -169,9 +172,21 @@ scp_status scp_system_carriers(const scp_system* sys, double* omega);
 scp_status scp_system_frame(const scp_system* sys, int32_t* real_frame);
 scp_status scp_system_set_frame(scp_system* sys, int32_t real_frame);
 
+/* Kernel timing for measurement: with enable = 1 every later launch of the
+ * fused forward (scp_propagate, and the forward inside scp_propagate_adjoint
+ * when psi0 is given), of the segment recompute and of the reverse kernel
+ * (scp_propagate_adjoint) on this system is bracketed by HIP events recorded
+ * on its stream (the events are created per launch).  scp_system_kernel_times
+ * waits for the recorded events and writes ms_out[3] (total milliseconds) and
+ * counts[3] (launches) for the kinds forward, recompute, reverse since the
+ * last read, then forgets them.  enable = 0 drops unread events. */
+scp_status scp_system_set_timing(scp_system* sys, int32_t enable);
+scp_status scp_system_kernel_times(scp_system* sys, double* ms_out, int32_t* counts);
+
 /* Static spectrum (Sec. 3.2): the composite static Hamiltonian
  * H0 = sum_m diag(eps_m) + sum_e g_e A_i (x) B_j in the dressed single-mode
- * bases (drives excluded) is diagonalised in FP64 on the device (D <= 96).
+ * bases (drives excluded) is diagonalised in FP64 on the device by cyclic
+ * Jacobi (D <= 2048; the matrix in LDS up to D = 96, in device memory above).
  * Every bare product state k (natural order, mode 0 slowest) is labelled
  * with the eigenvector of largest overlap |<k|v>|^2 (ties to the lowest
  * eigenvector index; labels are not forced to be distinct, so near a
@@ -183,7 +198,7 @@ scp_status scp_system_set_frame(scp_system* sys, int32_t real_frame);
  * (grad_out, host, nullable, n_params doubles in the gradient order of
  * scp_system_info) d zeta / d theta from <v| dH0 |v> over the four levels
  * (Hellmann-Feynman; drive parameters get 0).  Both synchronise the stream
- * and allocate temporary device memory.  Errors: SCP_EINVAL (D > 96, a
+ * and allocate temporary device memory.  Errors: SCP_EINVAL (D > 2048, a
  * complex static Hamiltonian, a bad pair), SCP_ENONFINITE, SCP_EHIP. */
 scp_status scp_energy_tensor(const scp_system* sys, double* E_out, void* stream);
 scp_status scp_static_zz(const scp_system* sys, int32_t qi, int32_t qj, double* zeta_out,
@@ -204,7 +219,11 @@ scp_status scp_apply_generator(const scp_system* sys, int32_t step, int32_t stag
 
 /* Propagate psi0 (D x S) over all n_steps RK4 steps into psiT.  With
  * opts->with_ckpt the states every ckpt_every steps are kept in the
- * workspace for scp_propagate_adjoint.  psi0 and psiT may alias. */
+ * workspace for scp_propagate_adjoint, and the system records which
+ * workspace holds them for which (n_cols, ckpt_every, n_steps); a propagate
+ * without checkpoints clears that record.  psi0 and psiT may alias.
+ * SCP_EINVAL if opts->workspace_bytes is below scp_workspace_size(opts,
+ * with_grad = 0). */
 scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* workspace,
                          const void* psi0, void* psiT, void* stream);
 
@@ -219,6 +238,23 @@ scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* work
 scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, int32_t d_c,
                         const int64_t* comp_rows, const int32_t* comp_cols, const void* target,
                         void* tau_out, void* cotangent, double* F_out, void* stream);
+
+/* Composite state-transfer cost (Sec. 4.1, eq. for the composite state cost)
+ * against full target states: tau = sum_j <phi_j | U[:, cols[j]]>,
+ * accumulated in FP64 on the device by one workgroup in a fixed order
+ * (deterministic), F = |tau|^2 / n_t^2, L = 1 - F.  U: D x S (precision 0
+ * complex64, 1 complex128); cols (int32, n_t) and targets (complex128,
+ * D x n_t column-major, phi_j = column j) and tau_out (complex128, 1) are
+ * device pointers owned by the caller.  cotangent (nullable, same precision
+ * and shape as U) receives the costate of L: -(tau/n_t^2) phi_j in column
+ * cols[j], zero elsewhere (columns not named in cols included).  With
+ * targets U_t|e_s> over a complete basis this is the gate fidelity of
+ * scp_fidelity.  F_out (host, nullable) synchronises the stream.  A column
+ * index outside [0, S) makes tau NaN (SCP_ENONFINITE when F_out is asked).
+ * Errors: SCP_EINVAL, SCP_ENONFINITE, SCP_EHIP. */
+scp_status scp_fidelity_states(const void* U, int64_t D, int32_t S, int32_t precision,
+                               int32_t n_t, const int32_t* cols, const void* targets,
+                               void* tau_out, void* cotangent, double* F_out, void* stream);
 
 /* Fidelity with error-free single-qubit phase gates before and after the
  * gate (the compensation of App. D, restricted to Z rotations: virtual Z).
@@ -246,12 +282,25 @@ scp_status scp_fidelity_zcomp(const void* U, int64_t D, int32_t S, int32_t preci
                               double* phases_out, void* cotangent, void* stream);
 
 /* Gradient of L w.r.t. every parameter (host FP64, n_params entries in the
- * order of scp_system_info), given the costate of the final state.  Needs
- * the checkpoints of the immediately preceding scp_propagate on the same
- * workspace with with_ckpt = 1 and the same opts.  Synchronises ``stream``.
- * SCP_ENONFINITE if any gradient entry is not finite. */
+ * order of scp_system_info), given the costate cotangent = dL/dU* of the final
+ * state (D x S complex64, device).  The discrete adjoint of Sec. 2.5 (the
+ * per-step derivative sum and the costate chain rule) walks the checkpoint
+ * segments back, recomputing each segment's states.
+ *   psi0 != NULL: the checkpoints are first computed here by a forward
+ *     propagation of psi0 (D x S complex64, device) into the workspace;
+ *   psi0 == NULL: the checkpoints of the system's most recent scp_propagate
+ *     are used; it must have run with with_ckpt = 1 on this workspace with the
+ *     same n_cols and ckpt_every, and no propagate without checkpoints (nor a
+ *     frame switch) may have come after it on this system, nor a propagate of
+ *     another system on this workspace pointer.  Otherwise SCP_EINVAL, before
+ *     any launch.
+ * The checkpoints stay valid, so several cotangents may follow one forward.
+ * SCP_EINVAL if opts->workspace_bytes is below scp_workspace_size(opts,
+ * with_grad = 1).  Synchronises ``stream``.  SCP_ENONFINITE if any gradient
+ * entry is not finite. */
 scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, void* workspace,
-                                 const void* cotangent, double* grad_out, void* stream);
+                                 const void* psi0, const void* cotangent, double* grad_out,
+                                 void* stream);
 
 /* ------------------------------------------------------------------------
  * Suzuki-Trotter product formulas (Sec. 2.3 Trotterization solver, App. A).
@@ -291,6 +340,31 @@ scp_status scp_trotter_workspace_size(const scp_system* sys, int32_t order, size
  * inputs).  Errors: SCP_EINVAL, SCP_EHIP. */
 scp_status scp_propagate_trotter(scp_system* sys, int32_t order, int32_t n_cols, void* workspace,
                                  const void* psi0, void* psiT, void* stream);
+
+/* Local continuous adjoint method (LCAM) of the product formulas (Sec. 2.5,
+ * continuous adjoint method: eqs. for the derivative sum and its i-th term,
+ * the costate chain rule a_i = U_{i+1}^T a_{i+1}).  The gradient of L w.r.t.
+ * every parameter (host FP64, n_params entries in the order of
+ * scp_system_info) for the costate cotangent = dL/dpsi_I(T)* (device,
+ * complex128, D x n_cols) of the columns psi0 (device, complex128, D x
+ * n_cols) propagated by scp_propagate_trotter with the same order.  Only the
+ * final state of the forward is kept: the walk back recovers every earlier
+ * state by evolving backward in time (G^-1 of each gate) while the costate
+ * moves by G^dag, and every gate contributes 2 Re <mu, dG/dtheta phi>
+ * through its local reduced matrix and the Frechet derivative of its
+ * exponential.  Complex FP64 throughout; the frame and the carriers are held
+ * fixed.  The result is bitwise reproducible (no atomics).
+ * workspace: device, scp_trotter_adjoint_workspace_size(order, n_cols) bytes
+ * (the forward's gate tables, one column state and costate per column, the
+ * inverse and adjoint gate tables, per-column local sums for a chunk of 128
+ * steps); workspace_bytes is its size.  Synchronises the stream.
+ * SCP_EINVAL (as scp_trotter_workspace_size, and for 16 (2 D + 512) bytes >
+ * 160 KiB: a column and its costate live in LDS), SCP_ENONFINITE, SCP_EHIP. */
+scp_status scp_trotter_adjoint_workspace_size(const scp_system* sys, int32_t order, int32_t n_cols,
+                                              size_t* bytes);
+scp_status scp_propagate_trotter_adjoint(scp_system* sys, int32_t order, int32_t n_cols,
+                                         void* workspace, size_t workspace_bytes, const void* psi0,
+                                         const void* cotangent, double* grad_out, void* stream);
 
 void scp_destroy(scp_system* sys);
 

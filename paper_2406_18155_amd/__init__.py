@@ -8,5 +8,6 @@ from ._lib import ScpError, lib  # noqa: F401
 
 lib()  # fail loudly if the HIP library is missing
 
-from .api import System, Target, basis_columns, fidelity, fidelity_zcomp  # noqa: E402,F401
+from .api import (StateTarget, System, Target, basis_columns, fidelity,  # noqa: E402,F401
+                  fidelity_states, fidelity_zcomp)
 from . import autograd  # noqa: E402,F401

@@ -44,7 +44,7 @@ class SystemDesc(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("n_cols", C.c_int32), ("precision", C.c_int32), ("ckpt_every", C.c_int32),
-                ("with_ckpt", C.c_int32)]
+                ("with_ckpt", C.c_int32), ("workspace_bytes", C.c_size_t)]
 
 
 EXPORTS = {
@@ -59,13 +59,24 @@ EXPORTS = {
     "scp_trotter_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_size_t)]),
     "scp_propagate_trotter": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                         C.c_void_p, C.c_void_p]),
+    "scp_trotter_adjoint_workspace_size": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
+                                                     C.POINTER(C.c_size_t)]),
+    "scp_propagate_trotter_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                                                C.c_size_t, C.c_void_p, C.c_void_p,
+                                                C.POINTER(C.c_double), C.c_void_p]),
     "scp_static_zz": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                 C.POINTER(C.c_double), C.c_void_p]),
+    "scp_fidelity_states": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.POINTER(C.c_double), C.c_void_p]),
     "scp_fidelity_zcomp": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p,
                                      C.c_void_p]),
     "scp_system_set_frame": (C.c_int, [C.c_void_p, C.c_int32]),
+    "scp_system_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
+    "scp_system_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_int32)]),
     "scp_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32,
                                      C.POINTER(C.c_size_t)]),
     "scp_apply_generator": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
@@ -76,7 +87,7 @@ EXPORTS = {
                                C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                C.POINTER(C.c_double), C.c_void_p]),
     "scp_propagate_adjoint": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,
-                                        C.POINTER(C.c_double), C.c_void_p]),
+                                        C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     "scp_destroy": (None, [C.c_void_p]),
     "scp_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.c_double, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),

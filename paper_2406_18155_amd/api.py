@@ -127,6 +127,18 @@ class System:
         """Choose the real-frame (True) or the complex (False) evaluation."""
         check(lib().scp_system_set_frame(self.handle, 1 if enable else 0))
 
+    def set_timing(self, enable):
+        """Bracket later forward / recompute / reverse launches with HIP events."""
+        check(lib().scp_system_set_timing(self.handle, 1 if enable else 0))
+
+    def kernel_times(self):
+        """{kind: (total ms, launches)} since the last read, kinds forward,
+        recompute, reverse."""
+        ms = (C.c_double * 3)()
+        n = (C.c_int32 * 3)()
+        check(lib().scp_system_kernel_times(self.handle, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(("forward", "recompute", "reverse"))}
+
     def energy_tensor(self, stream=None):
         """Dressed energies labelled by bare product states (D,), rad/ns."""
         E = (C.c_double * int(self.D))()
@@ -164,6 +176,30 @@ class System:
                                           _stream_ptr(stream)))
         return psiT
 
+    def trotter_adjoint_workspace_bytes(self, order, n_cols):
+        n = C.c_size_t()
+        check(lib().scp_trotter_adjoint_workspace_size(self.handle, self.TROTTER[order],
+                                                       int(n_cols), C.byref(n)))
+        return n.value
+
+    def trotter_adjoint(self, psi0, cotangent, order="q2", workspace=None, stream=None):
+        """dL/dtheta by the local continuous adjoint of the product formula for
+        the costate ``cotangent`` (S, D) complex128 of psi_I(T) of the columns
+        psi0 (S, D) complex128; only the final state is kept."""
+        assert psi0.dtype == torch.complex128 and psi0.is_contiguous() and psi0.shape[1] == self.D
+        assert cotangent.dtype == torch.complex128 and cotangent.shape == psi0.shape
+        S = psi0.shape[0]
+        if workspace is None:
+            workspace = torch.empty(self.trotter_adjoint_workspace_bytes(order, S),
+                                    dtype=torch.uint8, device=psi0.device)
+        g = (C.c_double * max(1, self.n_params))()
+        check(lib().scp_propagate_trotter_adjoint(self.handle, self.TROTTER[order], S,
+                                                  _ptr(workspace),
+                                                  workspace.numel() * workspace.element_size(),
+                                                  _ptr(psi0), _ptr(cotangent.contiguous()), g,
+                                                  _stream_ptr(stream)))
+        return np.array(g[: self.n_params])
+
     def opts(self, n_cols, precision=0, ckpt_every=0, with_ckpt=0):
         o = SolveOpts()
         o.n_cols, o.precision, o.ckpt_every, o.with_ckpt = int(n_cols), int(precision), \
@@ -199,14 +235,19 @@ class System:
             psiT = torch.empty_like(psi0)
         if workspace is None:
             workspace = self.workspace(opts, device=psi0.device)
-        check(lib().scp_propagate(self.handle, C.byref(opts),
-                                  None if workspace is None else _ptr(workspace), _ptr(psi0),
+        opts.workspace_bytes = workspace.numel() * workspace.element_size()
+        check(lib().scp_propagate(self.handle, C.byref(opts), _ptr(workspace), _ptr(psi0),
                                   _ptr(psiT), _stream_ptr(stream)))
         return psiT
 
-    def adjoint(self, cotangent, opts, workspace, stream=None):
+    def adjoint(self, cotangent, opts, workspace, psi0=None, stream=None):
+        """dL/dtheta for the costate ``cotangent`` (S, D) complex64 of the final
+        state.  psi0 None: the checkpoints of the preceding ``propagate`` with
+        with_ckpt=1 on ``workspace``; else they are first recomputed from psi0."""
         g = (C.c_double * max(1, self.n_params))()
+        opts.workspace_bytes = workspace.numel() * workspace.element_size()
         check(lib().scp_propagate_adjoint(self.handle, C.byref(opts), _ptr(workspace),
+                                          None if psi0 is None else _ptr(psi0),
                                           _ptr(cotangent), g, _stream_ptr(stream)))
         return np.array(g[: self.n_params])
 
@@ -242,6 +283,33 @@ def fidelity(U, tgt: Target, cotangent=None, stream=None, sync=True):
                              _ptr(tgt.target), _ptr(tgt.tau),
                              None if cotangent is None else _ptr(cotangent),
                              C.byref(F) if sync else None, _stream_ptr(stream)))
+    return (F.value if sync else None), tgt.tau
+
+
+class StateTarget:
+    """Device-resident inputs of the composite state cost: the propagated
+    columns it covers and their full target states (n_t, D)."""
+
+    def __init__(self, cols, targets, device="cuda"):
+        targets = np.asarray(targets, dtype=np.complex128)
+        self.n_t = len(cols)
+        assert targets.shape[0] == self.n_t
+        self.cols = torch.tensor(list(cols), dtype=torch.int32, device=device)
+        self.targets = torch.tensor(targets, device=device).contiguous()
+        self.tau = torch.zeros(1, dtype=torch.complex128, device=device)
+
+
+def fidelity_states(U, tgt: StateTarget, cotangent=None, stream=None, sync=True):
+    """F = |sum_j <phi_j|U[cols[j]]>|^2 / n_t^2 of U (S, D) against full target
+    states; fills ``cotangent`` (same shape as U) if given."""
+    prec = 0 if U.dtype == torch.complex64 else 1
+    S, D = U.shape
+    assert tgt.targets.shape[1] == D
+    F = C.c_double()
+    check(lib().scp_fidelity_states(_ptr(U), D, S, prec, tgt.n_t, _ptr(tgt.cols),
+                                    _ptr(tgt.targets), _ptr(tgt.tau),
+                                    None if cotangent is None else _ptr(cotangent),
+                                    C.byref(F) if sync else None, _stream_ptr(stream)))
     return (F.value if sync else None), tgt.tau
 
 

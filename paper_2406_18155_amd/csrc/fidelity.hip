@@ -7,6 +7,9 @@
 // with dL = 2 Re <lambda, dU> is lambda = -(tau / d_c^2) T_ij at the
 // computational entries and zero elsewhere.
 //
+// The composite state cost with full target states (Sec. 4.1, S target
+// states instead of a computational block) is reduced the same way.
+//
 // With single-qubit phase compensation (App. D compensation, restricted to Z
 // rotations before and after the gate): the d_c x d_c block is gathered in
 // FP64, the phases maximising |tau| are found on the host (a few hundred
@@ -110,6 +113,86 @@ hipError_t run(const void* U, int64_t D, int S, int dc, const int64_t* rows, con
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cot_kernel<T2>, dim3((dc * dc + 255) / 256), dim3(256), 0, s, (T2*)cot, D, S,
                      dc, rows, cols, (const double2*)target, (const double2*)tau);
+  return hipGetLastError();
+}
+
+// Composite state cost (Sec. 4.1): tau = sum_j sum_i conj(phi[i, j]) U[i, cols[j]]
+// over n_t full target states phi (D x n_t, complex128), one workgroup,
+// per-thread partial sums in a fixed order (column by column, rows strided by
+// the block), then a fixed-shape LDS tree: deterministic, FP64 throughout.
+constexpr int ST_THREADS = 1024;
+
+template <typename T2>
+__global__ void __launch_bounds__(ST_THREADS)
+tau_states_kernel(const T2* __restrict__ U, int64_t D, int S, int nt,
+                  const int32_t* __restrict__ cols, const double2* __restrict__ phi,
+                  double2* __restrict__ tau) {
+  __shared__ double sre[ST_THREADS], sim[ST_THREADS];
+  double ar = 0.0, ai = 0.0;
+  for (int j = 0; j < nt; ++j) {
+    const int c = cols[j];
+    if (c < 0 || c >= S) {   // out-of-range column: poison the result
+      ar = __builtin_nan("");
+      continue;
+    }
+    const T2* u = U + (size_t)c * D;
+    const double2* f = phi + (size_t)j * D;
+    for (int64_t i = threadIdx.x; i < D; i += ST_THREADS) {
+      const double2 t = f[i];
+      const double2 v = ld(u, (size_t)i);
+      ar += t.x * v.x + t.y * v.y;
+      ai += t.x * v.y - t.y * v.x;
+    }
+  }
+  sre[threadIdx.x] = ar;
+  sim[threadIdx.x] = ai;
+  __syncthreads();
+  for (int s = ST_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sre[threadIdx.x] += sre[threadIdx.x + s];
+      sim[threadIdx.x] += sim[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *tau = make_double2(sre[0], sim[0]);
+}
+
+// cotangent of L = 1 - |tau|^2/n_t^2: -(tau/n_t^2) phi[:, j] into column cols[j]
+template <typename T2>
+__global__ void cot_states_kernel(T2* __restrict__ cot, int64_t D, int S, int nt,
+                                  const int32_t* __restrict__ cols,
+                                  const double2* __restrict__ phi,
+                                  const double2* __restrict__ tau) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)D * nt) return;
+  const int j = (int)(e / (size_t)D);
+  const int64_t i = (int64_t)(e - (size_t)j * D);
+  const int c = cols[j];
+  if (c < 0 || c >= S) return;
+  const double2 tt = *tau;
+  const double2 f = phi[e];
+  const double sc = -1.0 / ((double)nt * nt);
+  T2 v;
+  v.x = sc * (tt.x * f.x - tt.y * f.y);
+  v.y = sc * (tt.x * f.y + tt.y * f.x);
+  cot[(size_t)c * D + i] = v;
+}
+
+template <typename T2>
+hipError_t run_states(const void* U, int64_t D, int S, int nt, const int32_t* cols,
+                      const void* phi, void* tau, void* cot, hipStream_t s) {
+  hipLaunchKernelGGL(tau_states_kernel<T2>, dim3(1), dim3(ST_THREADS), 0, s, (const T2*)U, D, S,
+                     nt, cols, (const double2*)phi, (double2*)tau);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || cot == nullptr) return e;
+  const size_t n = (size_t)D * S;
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_zero_kernel<T2>, dim3(blocks), dim3(256), 0, s, (T2*)cot, n);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t m = (size_t)D * nt;
+  hipLaunchKernelGGL(cot_states_kernel<T2>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                     (T2*)cot, D, S, nt, cols, (const double2*)phi, (const double2*)tau);
   return hipGetLastError();
 }
 
@@ -283,6 +366,15 @@ scp_status launch_zcomp(const void* U, int64_t D, int S, int prec, int nq, const
                   : run_zcomp_cot<double2>(cot, D, S, dc, rows, cols, target, ph, t2, s);
     if (e != hipSuccess) return fail(SCP_EHIP, std::string("zcomp cotangent: ") + hipGetErrorString(e));
   }
+  return SCP_OK;
+}
+
+scp_status launch_fidelity_states(const void* U, int64_t D, int S, int prec, int nt,
+                                  const int32_t* cols, const void* phi, void* tau, void* cot,
+                                  hipStream_t s) {
+  hipError_t e = prec == 0 ? run_states<float2>(U, D, S, nt, cols, phi, tau, cot, s)
+                           : run_states<double2>(U, D, S, nt, cols, phi, tau, cot, s);
+  if (e != hipSuccess) return fail(SCP_EHIP, std::string("state fidelity: ") + hipGetErrorString(e));
   return SCP_OK;
 }
 

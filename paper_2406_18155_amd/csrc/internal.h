@@ -69,6 +69,7 @@ struct Plan {
   int32_t has_mode_pass[MAXL];
   int32_t mode_pass[MAXL][8];      // adjoint: single-mode sensitivities of this mode at p (-1: none)
   float deps[16][3][8];            // d eps / d(EJ, EC, EL) per mode
+  float deps_lo[16][3][8];         // their FP32 residuals (deps + deps_lo ~ the FP64 value)
   int32_t lmode[MAXL][8];          // mode at each register position of each layout (-1: none)
   int32_t mdrv_off[17];            // drives of mode m: mdrv[mdrv_off[m] .. mdrv_off[m+1])
   int32_t mdrv[MAXGROUPS];         // drive indices grouped by mode
@@ -113,7 +114,7 @@ struct AdjItem {
   const float4* ckpt;
   const float2* lamT;   // cotangent (natural order), read when first != 0
   float2* segbuf;
-  float2* lo;
+  float2* lamlo;        // register-order compensation word of the costate
   float2* sum;
   float2* lamstate;     // register-order costate carried between launches
   double* part;         // [column block][4 waves][nacc] FP64 accumulators
@@ -141,8 +142,8 @@ struct Coupling { int i, j, op_i, op_j; double g; };
 
 // Basis function i of a drive envelope at time t of step n (App. C pulse
 // shapes): the envelope is sum_i par_i * envelope_basis(.., i, ..).
-__device__ inline double envelope_basis(int env, int i, int npar, long n, int nsteps, double t,
-                                        double T, double sigma) {
+__host__ __device__ inline double envelope_basis(int env, int i, int npar, long n, int nsteps,
+                                                 double t, double T, double sigma) {
   if (env == SCP_ENV_GAUSS) {
     const double u = (t - 0.5 * T) / sigma;
     return exp(-0.5 * u * u);
@@ -187,11 +188,22 @@ struct scp_system {
   double* d_dctab64 = nullptr;
   double* d_ctab64 = nullptr;   // [3N][n_drives] c(t) per drive, FP64 (plain path)
   float2* d_ph = nullptr;       // real frame: [2N+1][ph_row] frame phases (cos, sin)
-  float* d_rops = nullptr;      // real frame: [block_q] un-rotated operators (real parts)
+  float* d_rops = nullptr;      // real frame: [2][block_q] un-rotated operators (real parts):
+                                // FP32 values, then their FP32 residuals
   void* d_scratch = nullptr;    // small per-system scratch (adjoint partial sums)
   size_t scratch_bytes = 0;
   int device = 0;
   bool real_ok = false;         // the real frame is allowed (tables built)
+  // checkpoints of the most recent propagate with with_ckpt = 1 (for an
+  // adjoint called without psi0): where, for which opts, and its stamp
+  const void* ck_ws = nullptr;
+  int ck_S = 0, ck_ce = 0, ck_N = 0;
+  uint64_t ck_gen = 0;          // 0: no valid checkpoints
+  // kernel timing (scp_system_set_timing): HIP events recorded on the launch
+  // stream around each forward, recompute and reverse launch
+  bool timing = false;
+  mutable std::vector<hipEvent_t> tev;   // recorded events (start, stop pairs)
+  mutable std::vector<int> tkind;        // kind of each pair: 0 forward, 1 recompute, 2 reverse
 };
 
 namespace scp {
@@ -206,6 +218,11 @@ scp_status fail(scp_status st, const std::string& msg);
     if (e_ != hipSuccess) return fail(SCP_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
   } while (0)
 
+// Kernel timing: a start event before a launch (nullptr when timing is off
+// or no event could be made) and the stop event after it.
+hipEvent_t timing_start(const scp_system* sys, hipStream_t s);
+void timing_stop(const scp_system* sys, hipEvent_t start, int kind, hipStream_t s);
+
 // host single-mode builders (single_mode.cpp)
 void build_transmon(ModeData& m);
 void build_fluxonium(ModeData& m);
@@ -214,6 +231,7 @@ scp_status finish_mode(ModeData& m);   // sign convention, truncation, dressed o
 // kernels
 hipError_t launch_jacobi(double* A, double* V, double* w, const int* K, const int64_t* offs,
                          int n_mat, hipStream_t s);
+hipError_t launch_jacobi_big(double* A, double* V, int Dp, void* work, hipStream_t s);
 hipError_t launch_tables(scp_system* sys, hipStream_t s);
 scp_status launch_rk4(scp_system* sys, const float2* psi0, float2* psiT, float2* lo, float4* ckpt,
                       int ckpt_every, int S, hipStream_t s);
@@ -224,10 +242,17 @@ scp_status launch_adjoint(scp_system* sys, const float4* ckpt, const float2* lam
 scp_status launch_fidelity(const void* U, int64_t D, int S, int prec, int dc, const int64_t* rows,
                            const int32_t* cols, const void* target, void* tau, void* cot,
                            hipStream_t s);
+scp_status launch_fidelity_states(const void* U, int64_t D, int S, int prec, int nt,
+                                  const int32_t* cols, const void* phi, void* tau, void* cot,
+                                  hipStream_t s);
 scp_status launch_plain64(scp_system* sys, const double2* psi0, double2* psiT, void* work, int S,
                           hipStream_t s);
 scp_status trotter_check(const scp_system* sys, int order);
 size_t trotter_workspace_bytes(const scp_system* sys, int order);
+size_t trotter_adjoint_workspace_bytes(const scp_system* sys, int order, int S);
+scp_status trotter_adjoint_check(const scp_system* sys, int order);
+scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, const double2* psi0,
+                                  const double2* cot, double* grad, hipStream_t st);
 scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const double2* psi0,
                           double2* psiT, hipStream_t st);
 

@@ -301,7 +301,11 @@ scp_status launch_rk4_range(const scp_system* sys, const float2* psi0, float2* p
 
 scp_status launch_rk4(scp_system* sys, const float2* psi0, float2* psiT, float2* lo, float4* ckpt,
                       int ckpt_every, int S, hipStream_t s) {
-  return launch_rk4_range(sys, psi0, psiT, nullptr, lo, ckpt, ckpt_every, S, 0, sys->n_steps, s);
+  hipEvent_t t0 = timing_start(sys, s);
+  scp_status st =
+      launch_rk4_range(sys, psi0, psiT, nullptr, lo, ckpt, ckpt_every, S, 0, sys->n_steps, s);
+  if (st == SCP_OK) timing_stop(sys, t0, 0, s);
+  return st;
 }
 
 scp_status launch_rk4_recompute(const scp_system* sys, const float4* ckin, float2* lo,

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <set>
 
 #include "internal.h"
@@ -13,10 +14,84 @@ namespace scp {
 
 static thread_local std::string g_err;
 
+// Which system last wrote checkpoints into a workspace (by base pointer), and
+// the stamp of that write; an adjoint without psi0 trusts the checkpoints only
+// if its system's stamp is the one recorded for its workspace.
+static std::mutex g_ck_mu;
+static std::map<const void*, std::pair<const scp_system*, uint64_t>> g_ck_owner;
+static uint64_t g_ck_next = 0;
+
+static void ck_record(scp_system* sys, const void* ws, int S, int ce) {
+  std::lock_guard<std::mutex> lk(g_ck_mu);
+  sys->ck_ws = ws;
+  sys->ck_S = S;
+  sys->ck_ce = ce;
+  sys->ck_N = sys->n_steps;
+  sys->ck_gen = ++g_ck_next;
+  g_ck_owner[ws] = std::make_pair((const scp_system*)sys, sys->ck_gen);
+}
+
+static void ck_clear(scp_system* sys) {
+  std::lock_guard<std::mutex> lk(g_ck_mu);
+  if (sys->ck_gen != 0) {
+    auto it = g_ck_owner.find(sys->ck_ws);
+    if (it != g_ck_owner.end() && it->second.first == sys) g_ck_owner.erase(it);
+  }
+  sys->ck_gen = 0;
+  sys->ck_ws = nullptr;
+}
+
+// A propagate of sys into ws (with or without checkpoints) overwrites what
+// another system may have left there.
+static void ck_claim(const scp_system* sys, const void* ws) {
+  std::lock_guard<std::mutex> lk(g_ck_mu);
+  auto it = g_ck_owner.find(ws);
+  if (it != g_ck_owner.end() && it->second.first != sys) g_ck_owner.erase(it);
+}
+
+static bool ck_valid(const scp_system* sys, const void* ws, int S, int ce) {
+  std::lock_guard<std::mutex> lk(g_ck_mu);
+  if (sys->ck_gen == 0 || sys->ck_ws != ws || sys->ck_S != S || sys->ck_ce != ce ||
+      sys->ck_N != sys->n_steps)
+    return false;
+  auto it = g_ck_owner.find(ws);
+  return it != g_ck_owner.end() && it->second.first == sys && it->second.second == sys->ck_gen;
+}
+
 void set_error(const std::string& msg) { g_err = msg; }
 scp_status fail(scp_status st, const std::string& msg) {
   g_err = msg;
   return st;
+}
+
+hipEvent_t timing_start(const scp_system* sys, hipStream_t s) {
+  if (!sys->timing) return nullptr;
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventRecord(e, s) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    return nullptr;
+  }
+  return e;
+}
+
+void timing_stop(const scp_system* sys, hipEvent_t start, int kind, hipStream_t s) {
+  if (start == nullptr) return;
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess || hipEventRecord(e, s) != hipSuccess) {
+    if (e) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(start);
+    return;
+  }
+  sys->tev.push_back(start);
+  sys->tev.push_back(e);
+  sys->tkind.push_back(kind);
+}
+
+static void timing_drop(const scp_system* sys) {
+  for (hipEvent_t e : sys->tev) (void)hipEventDestroy(e);
+  sys->tev.clear();
+  sys->tkind.clear();
 }
 
 
@@ -395,7 +470,11 @@ scp_status make_plan(scp_system* sys) {
     P.mode_pass[l][p] = m;
     P.has_mode_pass[l] = 1;
     for (int th = 0; th < 3; ++th)
-      for (int a = 0; a < d; ++a) P.deps[m][th][a] = (float)sys->modes[m].deps[th][a];
+      for (int a = 0; a < d; ++a) {
+        const double x = sys->modes[m].deps[th][a];
+        P.deps[m][th][a] = (float)x;
+        P.deps_lo[m][th][a] = (float)(x - (double)P.deps[m][th][a]);
+      }
   }
   // drives
   int par0 = 0;
@@ -598,20 +677,28 @@ scp_status build_tables(scp_system* sys, hipStream_t st) {
     // the operators at t = 0 (the table's block 0 rounds them the same way)
     // (kind 2: the imaginary parts; a pair term of kind 2 is i^2 = -1 times the
     // product of the real parts, folded into the pair operator's sign)
-    std::vector<float> rops(P.block_q, 0.f);
+    // Each entry is stored as FP32 hi, and in a second block of block_q
+    // floats its residual lo = x - hi: the same real operators enter every
+    // stage, so their rounding would bias the adjoint's folds coherently over
+    // all steps; the folds use hi + lo (the applications use hi).
+    std::vector<float> rops(2 * (size_t)P.block_q, 0.f);
+    auto put = [&](int at, double x) {
+      const float hi = (float)x;
+      rops[at] = hi;
+      rops[P.block_q + at] = (float)(x - (double)hi);
+    };
     for (int s = 0; s < ns; ++s)
       for (int i = 0; i < dd; ++i) {
         const bool im = sys->slot_imag[s] != 0;
-        rops[s * dd + i] = (float)(im ? sops[s * dd + i].y : sops[s * dd + i].x);
+        put(s * dd + i, im ? sops[s * dd + i].y : sops[s * dd + i].x);
         for (int th = 0; th < 3; ++th) {
           const double2 v = dops[(s * 3 + th) * dd + i];
-          rops[P.off_dslot + (s * 3 + th) * dd + i] = (float)(im ? v.y : v.x);
+          put(P.off_dslot + (s * 3 + th) * dd + i, im ? v.y : v.x);
         }
       }
     for (int p = 0; p < np1; ++p)
       for (int i = 0; i < dd; ++i)
-        rops[P.off_pair + p * dd + i] =
-            sys->pair_imag[p] ? (float)(-pops[p * dd + i].y) : (float)pops[p * dd + i].x;
+        put(P.off_pair + p * dd + i, sys->pair_imag[p] ? -pops[p * dd + i].y : pops[p * dd + i].x);
     HIPCHK(hipMalloc(&sys->d_rops, rops.size() * sizeof(float)));
     HIPCHK(hipMemcpyAsync(sys->d_rops, rops.data(), rops.size() * sizeof(float), hipMemcpyHostToDevice, st));
     HIPCHK(launch_phase_table(d, P.NT, P.NR, P.RB, P.ph_thr, P.ph_row, sys->n_steps, sys->h,
@@ -780,6 +867,9 @@ WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad
 
 }  // namespace
 
+scp_status finish_adjoint(scp_system* sys, const WsLayout& w, char* ws, const void* cotangent,
+                          double* grad_out, int S, hipStream_t st);
+
 }  // namespace scp
 
 using namespace scp;
@@ -849,9 +939,40 @@ scp_status scp_system_set_frame(scp_system* sys, int32_t real_frame) {
   if (!sys) return fail(SCP_EINVAL, "null argument");
   if (real_frame != 0 && real_frame != 1) return fail(SCP_EINVAL, "real_frame must be 0 or 1");
   if (real_frame && !sys->real_ok) return fail(SCP_EINVAL, "the system has complex operators");
+  if (sys->plan.real_frame != real_frame) ck_clear(sys);   // checkpoints of the other evaluation
   sys->plan.real_frame = real_frame;
   HIPCHK(hipMemcpy(&sys->d_plan->real_frame, &sys->plan.real_frame, sizeof(int32_t),
                    hipMemcpyHostToDevice));
+  return SCP_OK;
+}
+
+scp_status scp_system_set_timing(scp_system* sys, int32_t enable) {
+  g_err.clear();
+  if (!sys || (enable != 0 && enable != 1)) return fail(SCP_EINVAL, "bad argument");
+  sys->timing = enable != 0;
+  if (!sys->timing) timing_drop(sys);
+  return SCP_OK;
+}
+
+scp_status scp_system_kernel_times(scp_system* sys, double* ms_out, int32_t* counts) {
+  g_err.clear();
+  if (!sys || !ms_out || !counts) return fail(SCP_EINVAL, "null argument");
+  for (int k = 0; k < 3; ++k) {
+    ms_out[k] = 0.0;
+    counts[k] = 0;
+  }
+  for (size_t i = 0; i < sys->tkind.size(); ++i) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(sys->tev[2 * i + 1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, sys->tev[2 * i], sys->tev[2 * i + 1]);
+    if (e != hipSuccess) {
+      timing_drop(sys);
+      return fail(SCP_EHIP, std::string("kernel timing: ") + hipGetErrorString(e));
+    }
+    ms_out[sys->tkind[i]] += ms;
+    counts[sys->tkind[i]] += 1;
+  }
+  timing_drop(sys);
   return SCP_OK;
 }
 
@@ -878,14 +999,24 @@ scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* work
   if (!sys || !opts || !psi0 || !psiT) return fail(SCP_EINVAL, "null argument");
   if (opts->n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
   if (opts->precision != 0 && opts->precision != 1) return fail(SCP_EINVAL, "precision must be 0 or 1");
+  if (opts->ckpt_every < 0) return fail(SCP_EINVAL, "ckpt_every must be >= 0");
   WsLayout w = ws_layout(sys, opts, 0);
+  if (!workspace) return fail(SCP_EINVAL, "a workspace is needed (scp_workspace_size)");
+  if (opts->workspace_bytes < w.total)
+    return fail(SCP_EINVAL, "workspace_bytes " + std::to_string(opts->workspace_bytes) +
+                                " below the " + std::to_string(w.total) + " these opts need");
   hipStream_t st = (hipStream_t)stream;
-  if (opts->precision == 1)
+  ck_claim(sys, workspace);
+  if (opts->precision == 1) {
+    ck_clear(sys);
     return launch_plain64(sys, (const double2*)psi0, (double2*)psiT, workspace, opts->n_cols, st);
-  if (!workspace) return fail(SCP_EINVAL, "the FP32 path needs a workspace (scp_workspace_size)");
+  }
   float4* ck = opts->with_ckpt ? (float4*)((char*)workspace + w.ckpt) : nullptr;
-  return launch_rk4(sys, (const float2*)psi0, (float2*)psiT, (float2*)((char*)workspace + w.lo), ck,
-                    w.ce, opts->n_cols, st);
+  ck_clear(sys);
+  scp_status s = launch_rk4(sys, (const float2*)psi0, (float2*)psiT,
+                            (float2*)((char*)workspace + w.lo), ck, w.ce, opts->n_cols, st);
+  if (s == SCP_OK && ck != nullptr) ck_record(sys, workspace, opts->n_cols, w.ce);
+  return s;
 }
 
 scp_status scp_trotter_workspace_size(const scp_system* sys, int32_t order, size_t* bytes) {
@@ -904,6 +1035,33 @@ scp_status scp_propagate_trotter(scp_system* sys, int32_t order, int32_t n_cols,
   if (n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
   return launch_trotter(sys, order, n_cols, workspace, (const double2*)psi0, (double2*)psiT,
                         (hipStream_t)stream);
+}
+
+scp_status scp_trotter_adjoint_workspace_size(const scp_system* sys, int32_t order, int32_t n_cols,
+                                              size_t* bytes) {
+  g_err.clear();
+  if (!sys || !bytes) return fail(SCP_EINVAL, "null argument");
+  if (n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  scp_status st = trotter_adjoint_check(sys, order);
+  if (st != SCP_OK) return st;
+  *bytes = trotter_adjoint_workspace_bytes(sys, order, n_cols);
+  return SCP_OK;
+}
+
+scp_status scp_propagate_trotter_adjoint(scp_system* sys, int32_t order, int32_t n_cols,
+                                         void* workspace, size_t workspace_bytes, const void* psi0,
+                                         const void* cotangent, double* grad_out, void* stream) {
+  g_err.clear();
+  if (!sys || !workspace || !psi0 || !cotangent || !grad_out) return fail(SCP_EINVAL, "null argument");
+  if (n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  scp_status st = trotter_adjoint_check(sys, order);
+  if (st != SCP_OK) return st;
+  const size_t need = trotter_adjoint_workspace_bytes(sys, order, n_cols);
+  if (workspace_bytes < need)
+    return fail(SCP_EINVAL, "workspace_bytes " + std::to_string(workspace_bytes) + " below the " +
+                                std::to_string(need) + " the product-formula adjoint needs");
+  return launch_trotter_adjoint(sys, order, n_cols, workspace, (const double2*)psi0,
+                                (const double2*)cotangent, grad_out, (hipStream_t)stream);
 }
 
 scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, int32_t d_c,
@@ -927,6 +1085,27 @@ scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, 
   return SCP_OK;
 }
 
+scp_status scp_fidelity_states(const void* U, int64_t D, int32_t S, int32_t precision,
+                               int32_t n_t, const int32_t* cols, const void* targets,
+                               void* tau_out, void* cotangent, double* F_out, void* stream) {
+  g_err.clear();
+  if (!U || !cols || !targets || !tau_out) return fail(SCP_EINVAL, "null argument");
+  if (D < 1 || S < 1 || n_t < 1 || (precision != 0 && precision != 1))
+    return fail(SCP_EINVAL, "bad sizes");
+  hipStream_t st = (hipStream_t)stream;
+  scp_status s = launch_fidelity_states(U, D, S, precision, n_t, cols, targets, tau_out, cotangent,
+                                        st);
+  if (s != SCP_OK) return s;
+  if (F_out) {
+    double2 tau;
+    HIPCHK(hipMemcpyAsync(&tau, tau_out, sizeof(double2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *F_out = (tau.x * tau.x + tau.y * tau.y) / ((double)n_t * n_t);
+    if (!std::isfinite(*F_out)) return fail(SCP_ENONFINITE, "fidelity is not finite");
+  }
+  return SCP_OK;
+}
+
 scp_status scp_fidelity_zcomp(const void* U, int64_t D, int32_t S, int32_t precision,
                               int32_t n_qubits, const int64_t* comp_rows, const int32_t* comp_cols,
                               const void* target, void* block_out, void* tau_out, double* F_out,
@@ -941,17 +1120,45 @@ scp_status scp_fidelity_zcomp(const void* U, int64_t D, int32_t S, int32_t preci
 }
 
 scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, void* workspace,
-                                 const void* cotangent, double* grad_out, void* stream) {
+                                 const void* psi0, const void* cotangent, double* grad_out,
+                                 void* stream) {
   g_err.clear();
   if (!sys || !opts || !workspace || !cotangent || !grad_out) return fail(SCP_EINVAL, "null argument");
   if (opts->precision != 0) return fail(SCP_EINVAL, "the adjoint runs on the FP32 path (precision 0)");
   if (opts->n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  if (opts->ckpt_every < 0) return fail(SCP_EINVAL, "ckpt_every must be >= 0");
   WsLayout w = ws_layout(sys, opts, 1);
+  if (opts->workspace_bytes < w.total)
+    return fail(SCP_EINVAL, "workspace_bytes " + std::to_string(opts->workspace_bytes) +
+                                " below the " + std::to_string(w.total) +
+                                " the adjoint needs (scp_workspace_size with_grad = 1)");
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
+  if (psi0 != nullptr) {
+    ck_claim(sys, workspace);
+    ck_clear(sys);
+    scp_status s = launch_rk4(sys, (const float2*)psi0, nullptr, (float2*)(ws + w.lo),
+                              (float4*)(ws + w.ckpt), w.ce, opts->n_cols, st);
+    if (s != SCP_OK) return s;
+    ck_record(sys, workspace, opts->n_cols, w.ce);
+  } else if (!ck_valid(sys, workspace, opts->n_cols, w.ce)) {
+    return fail(SCP_EINVAL,
+                "no checkpoints of this system for this workspace and opts: the last "
+                "scp_propagate must run with with_ckpt = 1 on the same workspace, n_cols and "
+                "ckpt_every (or pass psi0)");
+  }
+  return finish_adjoint(sys, w, ws, cotangent, grad_out, opts->n_cols, st);
+}
+
+}  // extern "C"
+
+namespace scp {
+
+scp_status finish_adjoint(scp_system* sys, const WsLayout& w, char* ws, const void* cotangent,
+                          double* grad_out, int S, hipStream_t st) {
   scp_status s = launch_adjoint_impl(sys, ws + w.ckpt, cotangent, ws + w.seg, ws + w.lo, ws + w.lam,
                                      ws + w.lamstate, (double*)(ws + w.part), w.ce, w.nckpt,
-                                     opts->n_cols, st);
+                                     S, st);
   if (s != SCP_OK) return s;
   const int nacc = sys->plan.nacc;
   std::vector<double> part((size_t)w.nwg * 4 * nacc);
@@ -970,8 +1177,14 @@ scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, vo
   return SCP_OK;
 }
 
+}  // namespace scp
+
+extern "C" {
+
 void scp_destroy(scp_system* sys) {
   if (!sys) return;
+  ck_clear(sys);
+  timing_drop(sys);
   if (sys->d_plan) (void)hipFree(sys->d_plan);
   if (sys->d_ops) (void)hipFree(sys->d_ops);
   if (sys->d_ctab) (void)hipFree(sys->d_ctab);

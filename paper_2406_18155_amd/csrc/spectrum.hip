@@ -3,8 +3,9 @@
 //
 // H0 = sum_m diag(eps_m) + sum_e g_e A_i (x) B_j in the dressed single-mode
 // bases (the generator's static part, drives excluded) is assembled on the
-// host in FP64 and diagonalised by the FP64 Jacobi kernel on the device (one
-// workgroup, D <= 96).  Every bare product state k is labelled with the
+// host in FP64 and diagonalised by FP64 cyclic Jacobi on the device (one
+// workgroup with the matrix in LDS for D <= 96, the device-memory variant for
+// 96 < D <= 2048).  Every bare product state k is labelled with the
 // eigenvector of largest overlap |<k|v>|^2 (ties to the lowest eigenvector
 // index); zeta = E(0) + E(1_i 1_j) - E(1_i) - E(1_j) with every other mode in
 // its ground state, and d zeta / d theta = sum of the signed <v| dH0 |v>
@@ -19,7 +20,8 @@ namespace scp {
 
 namespace {
 
-constexpr int SPEC_MAXD = 96;   // the Jacobi kernel's largest matrix
+constexpr int SPEC_MAXD_LDS = 96;   // the one-workgroup Jacobi kernel's largest matrix
+constexpr int SPEC_MAXD = 2048;     // the device-memory Jacobi beyond it
 
 struct DevBuf2 {
   void* p = nullptr;
@@ -75,12 +77,38 @@ scp_status spectrum(const scp_system* sys, hipStream_t st, std::vector<double>& 
                     std::vector<double>& V) {
   const int n = sys->n_modes, d = sys->d;
   const int64_t D = sys->D;
-  if (D > SPEC_MAXD) return fail(SCP_EINVAL, "static spectrum: D > 96 (one-workgroup eigensolver)");
+  if (D > SPEC_MAXD) return fail(SCP_EINVAL, "static spectrum: D > 2048");
   std::vector<double> H((size_t)D * D, 0.0);
   for (int m = 0; m < n; ++m) add_diag(H, D, n, d, m, sys->modes[m].eps);
   for (const Coupling& c : sys->coup)
     if (!add_two_body(H, D, n, d, c.i, c.j, op_of(sys, c.i, c.op_i), op_of(sys, c.j, c.op_j), c.g))
       return fail(SCP_EINVAL, "static spectrum: the static Hamiltonian is not real");
+  if (D > SPEC_MAXD_LDS) {
+    // device-memory Jacobi on the matrix padded to even order
+    const int Dp = (int)(D + (D & 1));
+    std::vector<double> Hp((size_t)Dp * Dp, 0.0);
+    for (int64_t r = 0; r < D; ++r)
+      for (int64_t c = 0; c < D; ++c) Hp[(size_t)r * Dp + c] = H[(size_t)r * D + c];
+    DevBuf2 bA, bV, bw;
+    HIPCHK(hipMalloc(&bA.p, Hp.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&bV.p, Hp.size() * sizeof(double)));
+    HIPCHK(hipMalloc(&bw.p, 16 * (size_t)Dp + 64));
+    HIPCHK(hipMemcpyAsync(bA.p, Hp.data(), Hp.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_jacobi_big((double*)bA.p, (double*)bV.p, Dp, bw.p, st));
+    std::vector<double> Vp(Hp.size());
+    HIPCHK(hipMemcpyAsync(Vp.data(), bV.p, Vp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(Hp.data(), bA.p, Hp.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    V.assign((size_t)D * D, 0.0);
+    w.assign((size_t)D, 0.0);
+    for (int64_t a = 0; a < D; ++a) {
+      w[a] = Hp[(size_t)a * Dp + a];
+      for (int64_t k = 0; k < D; ++k) V[(size_t)k * D + a] = Vp[(size_t)k * Dp + a];
+    }
+    for (double x : w)
+      if (!std::isfinite(x)) return fail(SCP_ENONFINITE, "static spectrum is not finite");
+    return SCP_OK;
+  }
   DevBuf2 bA, bV, bw, bK, bo;
   const int K = (int)D;
   const int64_t off = 0;

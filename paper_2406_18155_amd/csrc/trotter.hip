@@ -755,27 +755,12 @@ scp_status trotter_check(const scp_system* sys, int order) {
 
 size_t trotter_workspace_bytes(const scp_system* sys, int order) { return tr_layout(sys, order).total; }
 
-scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const double2* psi0,
-                          double2* psiT, hipStream_t st) {
-  scp_status chk = trotter_check(sys, order);
-  if (chk != SCP_OK) return chk;
-  const TrLayout W = tr_layout(sys, order);
+namespace {
+
+// The gate generator description of a system and order (pieces, frozen
+// times, drives, couplings); the pulse parameters go to ipar in drive order.
+TrGen make_gen(const scp_system* sys, int order, const TrLayout& W, double* ipar) {
   const int d = sys->d, M = sys->n_modes, E = (int)sys->coup.size(), N = sys->n_steps;
-  char* base = static_cast<char*>(ws);
-  // inputs: energies, dressed operators, pulse parameters
-  std::vector<char> in(W.pg, 0);
-  double* ieps = reinterpret_cast<double*>(in.data() + W.eps);
-  double2* iops = reinterpret_cast<double2*>(in.data() + W.ops);
-  double* ipar = reinterpret_cast<double*>(in.data() + W.par);
-  std::memcpy(in.data() + W.plan, &W.P, sizeof(TrPlan));
-  for (int m = 0; m < M; ++m) {
-    for (int a = 0; a < d; ++a) ieps[m * d + a] = sys->modes[m].eps[a];
-    for (int op = 0; op < 2; ++op)
-      for (int i = 0; i < d * d; ++i) {
-        const cplx v = sys->modes[m].ops[op][i];
-        iops[(m * 2 + op) * d * d + i] = make_double2(v.real(), v.imag());
-      }
-  }
   TrGen G{};
   G.d = d;
   G.M = M;
@@ -818,6 +803,33 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
     G.coj[e] = c.op_j;
     G.g[e] = c.g;
   }
+  return G;
+}
+
+}  // namespace
+
+scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const double2* psi0,
+                          double2* psiT, hipStream_t st) {
+  scp_status chk = trotter_check(sys, order);
+  if (chk != SCP_OK) return chk;
+  const TrLayout W = tr_layout(sys, order);
+  const int d = sys->d, M = sys->n_modes, E = (int)sys->coup.size(), N = sys->n_steps;
+  char* base = static_cast<char*>(ws);
+  // inputs: energies, dressed operators, pulse parameters
+  std::vector<char> in(W.pg, 0);
+  double* ieps = reinterpret_cast<double*>(in.data() + W.eps);
+  double2* iops = reinterpret_cast<double2*>(in.data() + W.ops);
+  double* ipar = reinterpret_cast<double*>(in.data() + W.par);
+  std::memcpy(in.data() + W.plan, &W.P, sizeof(TrPlan));
+  for (int m = 0; m < M; ++m) {
+    for (int a = 0; a < d; ++a) ieps[m * d + a] = sys->modes[m].eps[a];
+    for (int op = 0; op < 2; ++op)
+      for (int i = 0; i < d * d; ++i) {
+        const cplx v = sys->modes[m].ops[op][i];
+        iops[(m * 2 + op) * d * d + i] = make_double2(v.real(), v.imag());
+      }
+  }
+  const TrGen G = make_gen(sys, order, W, ipar);
   HIPCHK(hipMemcpyAsync(base, in.data(), in.size(), hipMemcpyHostToDevice, st));
   // the staging vector must outlive the copy
   HIPCHK(hipStreamSynchronize(st));
@@ -882,6 +894,593 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
     default: e = run_trotter<5>(R, S, psi0, psiT, fg, fs, sg, st); break;
   }
   HIPCHK(e);
+  return SCP_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Local continuous adjoint method (LCAM) of the product formulas (Sec. 2.5).
+//
+// Only the final state of the forward is kept.  The walk goes back over the
+// steps, and within a step over its gates in reverse order; at every gate
+//   phi = G^-1 psi              (the state before the gate, recovered by
+//                                evolving backward in time),
+//   M_ab += sum_rest conj(mu[a, rest]) phi[b, rest]   (the gate's local
+//                                reduced matrix; a, b its local indices),
+//   mu  = G^dag mu              (the costate before the gate),
+// which is the paper's i-th term a_i^T (dU_i/dtheta) psi_{i-1} with the step
+// written as a product of local gates, so that every gate contributes through
+// its own local derivative.  For G = exp(X), X = -i a tau h,
+//   sum_ab (dG)_ab M_ab = Tr(L(X, M^T) dX),
+// L the Frechet derivative of exp, taken from the block-triangular exponential
+// exp([[X, M^T], [0, X]]) = [[e^X, L(X, M^T)], [0, e^X]] (Van Loan 1978) by
+// the same Taylor scaling and squaring as the gates.  L is linear in M, so M
+// can be summed first: over the columns for a single-mode gate (one h per
+// step and piece), and over columns, steps and both passes for a pair gate
+// (its h does not depend on time).  Then every parameter needs the traces of
+// K = L(X, M^T) with dh/dtheta; the host forms
+//   dL/dtheta = sum 2 Re(-i a tau Tr(K dh/dtheta))
+// in FP64 in a fixed order.  For Q4j the gates are not unitary: the state is
+// recovered with exp(-X), the costate uses G^dag.  Everything is FP64.
+//
+// The walk: one workgroup per column keeps psi and mu in LDS (32 D bytes plus
+// a reduction scratch); the single-mode sums of a chunk of steps go to a
+// per-column buffer that a second kernel reduces over the columns in a fixed
+// order; the pair sums accumulate per column.  No atomics: the result is
+// bitwise reproducible.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int LC_CHUNK = 128;     // steps per walk launch
+
+struct LcRun {
+  int M, E, N, r, H, D, S;
+  int stride[SCP_MAX_MODES];
+  int ci[TR_MAXE], cj[TR_MAXE];
+  double fT[SCP_MAX_MODES][SCP_MAX_TRUNC];   // frame energy times T, reduced mod 2 pi
+};
+
+static_assert(sizeof(LcRun) <= 2048, "LcRun is passed by value as a kernel argument");
+
+// G^dag of n x n gates (blocks of nn entries)
+__global__ void lc_adjoint_table_kernel(const double2* __restrict__ G, double2* __restrict__ out,
+                                        int n, size_t count) {
+  const size_t nn = (size_t)n * n;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count * nn;
+       e += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = e / nn, w = e % nn;
+    const int r = (int)(w / n), c = (int)(w % n);
+    const double2 v = G[b * nn + (size_t)c * n + r];
+    out[e] = make_double2(v.x, -v.y);
+  }
+}
+
+// exp(-i f T) times x (the frame rotation of the output, undone)
+__device__ inline double2 unrotate(const LcRun& R, int d, int i, double2 v) {
+  int r = i;
+  double th = 0.0;
+  for (int m = R.M - 1; m >= 0; --m) {
+    th += R.fT[m][r % d];
+    r /= d;
+  }
+  double sn, cs;
+  sincos(-wrap_2pi(th), &sn, &cs);
+  return make_double2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+}
+
+// Walk of steps [n_lo, n_hi) backward for one column.  first: start from
+// psi_I(T) and lambda_I(T) (un-rotated to the lab frame) and clear this
+// column's pair sums; else continue from psi_st / mu_st.  Ms: [(step - n_lo)
+// r + j) M + m][S][d^2] single-mode sums of this chunk; Mp: [S][r E][d^4].
+template <int d>
+__global__ void __launch_bounds__(TR_THREADS)
+lc_walk_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __restrict__ psiT,
+               const double2* __restrict__ lamT, double2* __restrict__ psi_st,
+               double2* __restrict__ mu_st, const double2* __restrict__ sg_inv,
+               const double2* __restrict__ sg_adj, const double2* __restrict__ pg_inv,
+               const double2* __restrict__ pg_adj, double2* __restrict__ Ms,
+               double2* __restrict__ Mp) {
+  extern __shared__ double2 lds[];
+  constexpr int dd = d * d;
+  const int col = blockIdx.x;
+  const size_t off = (size_t)col * R.D;
+  double2* L = lds;                   // psi (the state)
+  double2* Lm = lds + R.D;            // mu (the costate)
+  double2* scr = lds + 2 * R.D;       // TR_THREADS partial sums
+  const size_t np_col = (size_t)R.r * R.E * dd * dd;
+  if (first) {
+    for (int i = threadIdx.x; i < R.D; i += blockDim.x) {
+      L[i] = unrotate(R, d, i, psiT[off + i]);
+      Lm[i] = unrotate(R, d, i, lamT[off + i]);
+    }
+    for (size_t e = threadIdx.x; e < np_col; e += blockDim.x) Mp[col * np_col + e] = make_double2(0, 0);
+  } else {
+    for (int i = threadIdx.x; i < R.D; i += blockDim.x) {
+      L[i] = psi_st[off + i];
+      Lm[i] = mu_st[off + i];
+    }
+  }
+  const int nq = (n_hi - n_lo) * R.r * R.M;
+  for (int e = threadIdx.x; e < nq * dd; e += blockDim.x)
+    Ms[((size_t)(e / dd) * R.S + col) * dd + e % dd] = make_double2(0, 0);
+  __syncthreads();
+  const int K = R.M + R.E;
+  const int len = R.H == 2 ? 2 * K : K;
+  // the adjoint gate still to be applied to mu (from the previous gate of the walk)
+  const double2* pend = nullptr;
+  int pend_t = 0;
+  for (int n = n_hi - 1; n >= n_lo; --n) {
+    for (int j = R.r - 1; j >= 0; --j) {
+      for (int q = len - 1; q >= 0; --q) {
+        const int t = q < K ? q : 2 * K - 1 - q;   // local term of this gate
+        const bool single = t < R.M;
+        const double2* gi;
+        const double2* ga;
+        int s0, s1;
+        if (single) {
+          const size_t b = ((size_t)n * R.r + j) * R.M + t;
+          gi = sg_inv + b * dd;
+          ga = sg_adj + b * dd;
+          s0 = R.stride[t];
+          s1 = 0;
+        } else {
+          const size_t b = (size_t)j * R.E + (t - R.M);
+          gi = pg_inv + b * dd * dd;
+          ga = pg_adj + b * dd * dd;
+          s0 = R.stride[R.ci[t - R.M]];
+          s1 = R.stride[R.cj[t - R.M]];
+        }
+        // phase A: psi <- G^-1 psi; mu <- (previous gate)^dag mu
+        if (single)
+          tr_apply1<d>(L, R.D, s0, gi);
+        else
+          tr_apply2<d>(L, R.D, s0, s1, gi, nullptr, nullptr, 0);
+        if (pend != nullptr) {
+          if (pend_t < R.M)
+            tr_apply1<d>(Lm, R.D, R.stride[pend_t], pend);
+          else
+            tr_apply2<d>(Lm, R.D, R.stride[R.ci[pend_t - R.M]], R.stride[R.cj[pend_t - R.M]], pend,
+                         nullptr, nullptr, 0);
+        }
+        __syncthreads();
+        // phase B: the gate's local reduced matrix M_AB = sum conj(mu[A]) phi[B]
+        {
+          const int nloc = single ? d : dd;
+          const int ent = nloc * nloc;
+          const int ch = ent >= TR_THREADS ? 1 : TR_THREADS / ent;
+          const int nf = R.D / nloc;
+          int sp = 0, sq = 0, w = 0;
+          double isq = 0.0, iw = 0.0, is0 = 1.0 / s0;
+          if (!single) {
+            sp = s0 > s1 ? s0 : s1;
+            sq = s0 > s1 ? s1 : s0;
+            w = sp / (sq * d);
+            isq = 1.0 / sq;
+            iw = 1.0 / w;
+          }
+          double2* Mdst = single
+              ? Ms + ((((size_t)(n - n_lo) * R.r + j) * R.M + t) * R.S + col) * dd
+              : Mp + col * np_col + ((size_t)j * R.E + (t - R.M)) * dd * dd;
+          for (int wi = threadIdx.x; wi < ent * ch; wi += blockDim.x) {
+            const int e = wi / ch, c = wi - e * ch;
+            const int A = e / nloc, B = e - A * nloc;
+            const int oa = single ? A * s0 : (A / d) * s0 + (A % d) * s1;
+            const int ob = single ? B * s0 : (B / d) * s0 + (B % d) * s1;
+            double re = 0.0, im = 0.0;
+            for (int f = c; f < nf; f += ch) {
+              const int base = single ? fibre1<d>(f, s0, is0) : fibre2<d>(f, sp, sq, w, isq, iw);
+              const double2 u = Lm[base + oa], v = L[base + ob];
+              re = fma(u.x, v.x, re);
+              re = fma(u.y, v.y, re);
+              im = fma(u.x, v.y, im);
+              im = fma(-u.y, v.x, im);
+            }
+            if (ch == 1) {
+              const double2 o = Mdst[e];
+              Mdst[e] = make_double2(o.x + re, o.y + im);
+            } else {
+              scr[wi] = make_double2(re, im);
+            }
+          }
+          if (ch > 1) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < ent; e += blockDim.x) {
+              double re = 0.0, im = 0.0;
+              for (int c = 0; c < ch; ++c) {
+                re += scr[e * ch + c].x;
+                im += scr[e * ch + c].y;
+              }
+              const double2 o = Mdst[e];
+              Mdst[e] = make_double2(o.x + re, o.y + im);
+            }
+          }
+        }
+        __syncthreads();
+        pend = ga;
+        pend_t = t;
+      }
+    }
+  }
+  if (pend != nullptr) {
+    if (pend_t < R.M)
+      tr_apply1<d>(Lm, R.D, R.stride[pend_t], pend);
+    else
+      tr_apply2<d>(Lm, R.D, R.stride[R.ci[pend_t - R.M]], R.stride[R.cj[pend_t - R.M]], pend,
+                   nullptr, nullptr, 0);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < R.D; i += blockDim.x) {
+    psi_st[off + i] = L[i];
+    mu_st[off + i] = Lm[i];
+  }
+}
+
+// Tr(K P) for n x n K (row stride ks) and P given by a functor p(row, col)
+template <typename F>
+__device__ inline double2 trace_kp(const double2* K, int ks, int n, F p) {
+  double re = 0.0, im = 0.0;
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) {
+      const double2 k = K[a * ks + b], v = p(b, a);
+      re += k.x * v.x - k.y * v.y;
+      im += k.x * v.y + k.y * v.x;
+    }
+  return make_double2(re, im);
+}
+
+// Single-mode gates of steps [n_lo, n_lo + nsteps): block b = (nl r + j) M + m.
+// The column sum of M, K = L(X, M^T) with X = -i a tau h(t), then the traces
+// z = (Tr K n, Tr K phi, Tr K dh/dEJ, Tr K dh/dEC, Tr K dh/dEL) into
+// z[(step r + j) M + m][5].
+__global__ void __launch_bounds__(64)
+lc_single_kernel(TrGen G, int n_lo, int S, const double* __restrict__ eps,
+                 const double2* __restrict__ ops, const double* __restrict__ par,
+                 const double* __restrict__ deps, const double2* __restrict__ dops,
+                 const double2* __restrict__ Ms, double2* __restrict__ z) {
+  extern __shared__ double2 sh[];
+  const int d = G.d, dd = d * d, n2 = 2 * d, nn = n2 * n2;
+  double2 *X = sh, *E = sh + nn, *T = sh + 2 * nn, *W = sh + 3 * nn;
+  double* ck = reinterpret_cast<double*>(sh + 4 * nn);
+  const int b = blockIdx.x, m = b % G.M, q = b / G.M, j = q % G.r, nl = q / G.r;
+  const long step = n_lo + nl;
+  const double t = step * G.dt + G.mid[j];
+  for (int k = threadIdx.x; k < G.ndrives; k += blockDim.x) {
+    const TrDrive Rd = G.dr[k];
+    double v = 0.0;
+    if (Rd.mode == m) {
+      for (int i = 0; i < Rd.npar; ++i)
+        v += par[Rd.par0 + i] * envelope_basis(Rd.env, i, Rd.npar, step, G.N, t, G.T, Rd.sigma);
+      v *= cos(wrap_2pi(Rd.omega * t + Rd.phase));
+    }
+    ck[k] = v;
+  }
+  __syncthreads();
+  const double2 w = gate_factor(G, j, 1.0);
+  for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
+    const int row = idx / n2, cc = idx % n2;
+    double2 v = make_double2(0.0, 0.0);
+    if ((row < d) == (cc < d)) {              // the diagonal blocks: X
+      const int r0 = row % d, c0 = cc % d;
+      double2 h = make_double2(r0 == c0 ? eps[m * d + r0] : 0.0, 0.0);
+      for (int k = 0; k < G.ndrives; ++k) {
+        if (G.dr[k].mode != m) continue;
+        const double2 o = ops[(size_t)(m * 2 + G.dr[k].op) * dd + r0 * d + c0];
+        h.x += ck[k] * o.x;
+        h.y += ck[k] * o.y;
+      }
+      v = cmul(w, h);
+    } else if (row < d) {                     // upper right: M^T, summed over columns
+      const int r0 = row, c0 = cc - d;
+      const double2* src = Ms + (((size_t)nl * G.r + j) * G.M + m) * S * dd + (size_t)c0 * d + r0;
+      double re = 0.0, im = 0.0;
+      for (int c = 0; c < S; ++c) {
+        re += src[(size_t)c * dd].x;
+        im += src[(size_t)c * dd].y;
+      }
+      v = make_double2(re, im);
+    }
+    X[idx] = v;
+  }
+  __syncthreads();
+  expm_taylor(n2, X, E, T, W);
+  if (threadIdx.x < 5) {
+    const double2* Kp = E + d;   // rows 0..d-1, columns d..2d-1
+    const int k5 = threadIdx.x;
+    double2 out;
+    if (k5 < 2) {
+      const double2* O = ops + (size_t)(m * 2 + k5) * dd;
+      out = trace_kp(Kp, n2, d, [&](int r0, int c0) { return O[r0 * d + c0]; });
+    } else {
+      const int th = k5 - 2;
+      out = trace_kp(Kp, n2, d, [&](int r0, int c0) {
+        double2 v = make_double2(r0 == c0 ? deps[(m * 3 + th) * d + r0] : 0.0, 0.0);
+        for (int k = 0; k < G.ndrives; ++k) {
+          if (G.dr[k].mode != m) continue;
+          const double2 o = dops[((size_t)(m * 3 + th) * 2 + G.dr[k].op) * dd + r0 * d + c0];
+          v.x += ck[k] * o.x;
+          v.y += ck[k] * o.y;
+        }
+        return v;
+      });
+    }
+    z[((size_t)step * G.r + j) * G.M * 5 + (size_t)m * 5 + k5] = out;
+  }
+}
+
+// Pair gates: block b = j E + e.  The sum of M over columns (steps and passes
+// already summed per column), K = L(X, M^T), X = -i a tau g A (x) B, and the
+// traces (Tr K A(x)B, Tr K dA(x)B for EJ, EC, EL of mode i, Tr K A(x)dB for
+// those of mode j) into zp[b][7].
+__global__ void __launch_bounds__(256)
+lc_pair_kernel(TrGen G, int S, const double2* __restrict__ ops, const double2* __restrict__ dops,
+               const double2* __restrict__ Mp, double2* __restrict__ zp) {
+  extern __shared__ double2 sh[];
+  const int d = G.d, dd = d * d, n = dd, n2 = 2 * n, nn = n2 * n2;
+  double2 *X = sh, *E = sh + nn, *T = sh + 2 * nn, *W = sh + 3 * nn;
+  const int b = blockIdx.x, j = b / G.E, e = b % G.E;
+  const double2 w = gate_factor(G, j, G.g[e]);
+  const double2* A = ops + (size_t)(G.ci[e] * 2 + G.coi[e]) * dd;
+  const double2* B = ops + (size_t)(G.cj[e] * 2 + G.coj[e]) * dd;
+  const size_t np_col = (size_t)G.r * G.E * n * n;
+  for (int idx = threadIdx.x; idx < nn; idx += blockDim.x) {
+    const int row = idx / n2, cc = idx % n2;
+    double2 v = make_double2(0.0, 0.0);
+    if ((row < n) == (cc < n)) {
+      const int r0 = row % n, c0 = cc % n;
+      v = cmul(w, cmul(A[(r0 / d) * d + c0 / d], B[(r0 % d) * d + c0 % d]));
+    } else if (row < n) {
+      const int r0 = row, c0 = cc - n;
+      const double2* src = Mp + (size_t)b * n * n + (size_t)c0 * n + r0;
+      double re = 0.0, im = 0.0;
+      for (int c = 0; c < S; ++c) {
+        re += src[(size_t)c * np_col].x;
+        im += src[(size_t)c * np_col].y;
+      }
+      v = make_double2(re, im);
+    }
+    X[idx] = v;
+  }
+  __syncthreads();
+  expm_taylor(n2, X, E, T, W);
+  if (threadIdx.x < 7) {
+    const double2* Kp = E + n;
+    const int k7 = threadIdx.x;
+    const double2* dA = k7 >= 1 && k7 <= 3 ? dops + ((size_t)(G.ci[e] * 3 + (k7 - 1)) * 2 + G.coi[e]) * dd : A;
+    const double2* dB = k7 >= 4 ? dops + ((size_t)(G.cj[e] * 3 + (k7 - 4)) * 2 + G.coj[e]) * dd : B;
+    const double2 out = trace_kp(Kp, n2, n, [&](int r0, int c0) {
+      return cmul(dA[(r0 / d) * d + c0 / d], dB[(r0 % d) * d + c0 % d]);
+    });
+    zp[(size_t)b * 7 + k7] = out;
+  }
+}
+
+template <int d>
+hipError_t run_lc_walk(const LcRun& R, int n_hi, int n_lo, int first, const double2* psiT,
+                       const double2* lamT, double2* psi_st, double2* mu_st, const double2* sgi,
+                       const double2* sga, const double2* pgi, const double2* pga, double2* Ms,
+                       double2* Mp, hipStream_t st) {
+  const size_t sh = ((size_t)2 * R.D + TR_THREADS) * sizeof(double2);
+  hipError_t e = hipFuncSetAttribute((const void*)lc_walk_kernel<d>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(lc_walk_kernel<d>, dim3(R.S), dim3(TR_THREADS), sh, st, R, n_hi, n_lo, first,
+                     psiT, lamT, psi_st, mu_st, sgi, sga, pgi, pga, Ms, Mp);
+  return hipGetLastError();
+}
+
+struct LcLayout {
+  TrLayout F;              // the forward's layout (its tables are reused)
+  size_t psiT, psi_st, mu_st, sgi, sga, pgi, pga, ms, mp, z, zp, deps, dops, total;
+  int chunk;
+};
+
+LcLayout lc_layout(const scp_system* sys, int order, int S) {
+  LcLayout L{};
+  L.F = tr_layout(sys, order);
+  const size_t d = sys->d, dd = d * d, M = sys->n_modes, E = std::max<size_t>(1, sys->coup.size());
+  const size_t N = sys->n_steps, r = L.F.r, D = sys->D;
+  L.chunk = (int)std::min<size_t>(N, LC_CHUNK);
+  size_t o = L.F.total;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.psiT = take((size_t)S * D * sizeof(double2));
+  L.psi_st = take((size_t)S * D * sizeof(double2));
+  L.mu_st = take((size_t)S * D * sizeof(double2));
+  L.sgi = take(N * r * M * dd * sizeof(double2));
+  L.sga = take(N * r * M * dd * sizeof(double2));
+  L.pgi = take(r * E * dd * dd * sizeof(double2));
+  L.pga = take(r * E * dd * dd * sizeof(double2));
+  L.ms = take((size_t)L.chunk * r * M * S * dd * sizeof(double2));
+  L.mp = take((size_t)S * r * E * dd * dd * sizeof(double2));
+  L.z = take(N * r * M * 5 * sizeof(double2));
+  L.zp = take(r * E * 7 * sizeof(double2));
+  L.deps = take(M * 3 * d * sizeof(double));
+  L.dops = take(M * 3 * 2 * dd * sizeof(double2));
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+scp_status trotter_adjoint_check(const scp_system* sys, int order) {
+  scp_status chk = trotter_check(sys, order);
+  if (chk != SCP_OK) return chk;
+  if (((int64_t)2 * sys->D + TR_THREADS) * (int64_t)sizeof(double2) > TR_MAXLDS)
+    return fail(SCP_EINVAL, "the product-formula adjoint keeps a column and its costate in LDS: "
+                            "16 (2 D + 512) bytes must be <= 160 KiB (D <= 4864)");
+  return SCP_OK;
+}
+
+size_t trotter_adjoint_workspace_bytes(const scp_system* sys, int order, int S) {
+  return lc_layout(sys, order, S).total;
+}
+
+scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, const double2* psi0,
+                                  const double2* cot, double* grad, hipStream_t st) {
+  scp_status chk = trotter_adjoint_check(sys, order);
+  if (chk != SCP_OK) return chk;
+  const LcLayout Y = lc_layout(sys, order, S);
+  const TrLayout& W = Y.F;
+  const int d = sys->d, dd = d * d, M = sys->n_modes, E = (int)sys->coup.size(), N = sys->n_steps;
+  char* base = static_cast<char*>(ws);
+  // the forward: only its final state is kept (its gate tables are reused)
+  double2* psiT = reinterpret_cast<double2*>(base + Y.psiT);
+  scp_status s = launch_trotter(sys, order, S, ws, psi0, psiT, st);
+  if (s != SCP_OK) return s;
+  // operator derivatives of every mode (FP64)
+  std::vector<double> hdeps((size_t)M * 3 * d);
+  std::vector<double2> hdops((size_t)M * 3 * 2 * dd);
+  for (int m = 0; m < M; ++m)
+    for (int th = 0; th < 3; ++th) {
+      for (int a = 0; a < d; ++a) hdeps[((size_t)m * 3 + th) * d + a] = sys->modes[m].deps[th][a];
+      for (int op = 0; op < 2; ++op)
+        for (int i = 0; i < dd; ++i) {
+          const cplx v = sys->modes[m].dops[th][op][i];
+          hdops[(((size_t)m * 3 + th) * 2 + op) * dd + i] = make_double2(v.real(), v.imag());
+        }
+    }
+  std::vector<double> ipar(std::max<size_t>(1, W.npar));
+  TrGen G = make_gen(sys, order, W, ipar.data());
+  HIPCHK(hipMemcpyAsync(base + Y.deps, hdeps.data(), hdeps.size() * sizeof(double),
+                        hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(base + Y.dops, hdops.data(), hdops.size() * sizeof(double2),
+                        hipMemcpyHostToDevice, st));
+  const double* deps = reinterpret_cast<const double*>(base + W.eps);
+  const double2* dops = reinterpret_cast<const double2*>(base + W.ops);
+  const double* dpar = reinterpret_cast<const double*>(base + W.par);
+  const double2* pg = reinterpret_cast<const double2*>(base + W.pg);
+  const double2* sg = reinterpret_cast<const double2*>(base + W.sg);
+  double2* sgi = reinterpret_cast<double2*>(base + Y.sgi);
+  double2* sga = reinterpret_cast<double2*>(base + Y.sga);
+  double2* pgi = reinterpret_cast<double2*>(base + Y.pgi);
+  double2* pga = reinterpret_cast<double2*>(base + Y.pga);
+  // inverse gates exp(-X): the same generators with the piece coefficients negated
+  TrGen Gi = G;
+  for (int j = 0; j < W.r; ++j) {
+    Gi.a_re[j] = -G.a_re[j];
+    Gi.a_im[j] = -G.a_im[j];
+  }
+  if (E > 0) {
+    hipLaunchKernelGGL(tr_pair_gate_kernel, dim3(W.r * E), dim3(256), 4 * dd * dd * sizeof(double2),
+                       st, Gi, dops, pgi);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(lc_adjoint_table_kernel, dim3(std::max(1, W.r * E)), dim3(256), 0, st, pg, pga,
+                       dd, (size_t)W.r * E);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(tr_single_gate_kernel, dim3((unsigned)((size_t)N * W.r * M)), dim3(64),
+                     4 * dd * sizeof(double2) + TR_MAXDRV * sizeof(double), st, Gi, deps, dops, dpar,
+                     sgi);
+  HIPCHK(hipGetLastError());
+  {
+    const size_t count = (size_t)N * W.r * M;
+    const int blocks = (int)std::min<size_t>((count * dd + 255) / 256, 65535);
+    hipLaunchKernelGGL(lc_adjoint_table_kernel, dim3(blocks), dim3(256), 0, st, sg, sga, d, count);
+    HIPCHK(hipGetLastError());
+  }
+  LcRun R{};
+  R.M = M;
+  R.E = E;
+  R.N = N;
+  R.r = W.r;
+  R.H = W.H;
+  R.D = (int)sys->D;
+  R.S = S;
+  {
+    int sd = 1;
+    for (int m = M - 1; m >= 0; --m) {
+      R.stride[m] = sd;
+      sd *= d;
+    }
+  }
+  for (int e = 0; e < E; ++e) {
+    R.ci[e] = sys->coup[e].i;
+    R.cj[e] = sys->coup[e].j;
+  }
+  const double twopi = 6.283185307179586476925286766559;
+  for (int m = 0; m < M; ++m)
+    for (int a = 0; a < d; ++a) R.fT[m][a] = std::remainder(sys->modes[m].frame[a] * N * sys->h, twopi);
+  double2* psi_st = reinterpret_cast<double2*>(base + Y.psi_st);
+  double2* mu_st = reinterpret_cast<double2*>(base + Y.mu_st);
+  double2* Ms = reinterpret_cast<double2*>(base + Y.ms);
+  double2* Mp = reinterpret_cast<double2*>(base + Y.mp);
+  double2* z = reinterpret_cast<double2*>(base + Y.z);
+  double2* zp = reinterpret_cast<double2*>(base + Y.zp);
+  const double* ddeps = reinterpret_cast<const double*>(base + Y.deps);
+  const double2* ddops = reinterpret_cast<const double2*>(base + Y.dops);
+  for (int n_hi = N; n_hi > 0; n_hi -= Y.chunk) {
+    const int n_lo = std::max(0, n_hi - Y.chunk);
+    const int first = n_hi == N ? 1 : 0;
+    hipError_t e;
+    switch (d) {
+      case 2: e = run_lc_walk<2>(R, n_hi, n_lo, first, psiT, cot, psi_st, mu_st, sgi, sga, pgi, pga, Ms, Mp, st); break;
+      case 3: e = run_lc_walk<3>(R, n_hi, n_lo, first, psiT, cot, psi_st, mu_st, sgi, sga, pgi, pga, Ms, Mp, st); break;
+      case 4: e = run_lc_walk<4>(R, n_hi, n_lo, first, psiT, cot, psi_st, mu_st, sgi, sga, pgi, pga, Ms, Mp, st); break;
+      default: e = run_lc_walk<5>(R, n_hi, n_lo, first, psiT, cot, psi_st, mu_st, sgi, sga, pgi, pga, Ms, Mp, st); break;
+    }
+    HIPCHK(e);
+    const int nb = (n_hi - n_lo) * W.r * M;
+    hipLaunchKernelGGL(lc_single_kernel, dim3(nb), dim3(64),
+                       4 * 4 * dd * sizeof(double2) + TR_MAXDRV * sizeof(double), st, G, n_lo, S, deps,
+                       dops, dpar, ddeps, ddops, Ms, z);
+    HIPCHK(hipGetLastError());
+  }
+  if (E > 0) {
+    const size_t sh = 4 * (size_t)(2 * dd) * (2 * dd) * sizeof(double2);
+    HIPCHK(hipFuncSetAttribute((const void*)lc_pair_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sh));
+    hipLaunchKernelGGL(lc_pair_kernel, dim3(W.r * E), dim3(256), sh, st, G, S, dops, ddops, Mp, zp);
+    HIPCHK(hipGetLastError());
+  }
+  std::vector<double2> hz((size_t)N * W.r * M * 5), hzp((size_t)std::max(1, W.r * E) * 7);
+  HIPCHK(hipMemcpyAsync(hz.data(), z, hz.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+  if (E > 0)
+    HIPCHK(hipMemcpyAsync(hzp.data(), zp, (size_t)W.r * E * 7 * sizeof(double2), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // dL/dtheta = sum 2 Re(w_j Tr(K dh/dtheta)), w_j = -i a_j tau (FP64, fixed order)
+  const int npulse = sys->n_pulse;
+  std::vector<double> g((size_t)sys->n_params, 0.0);
+  auto re2 = [](cplx w, double2 v) { return 2.0 * (w * cplx(v.x, v.y)).real(); };
+  for (int n = 0; n < N; ++n)
+    for (int j = 0; j < W.r; ++j) {
+      const cplx wj = cplx(0.0, -1.0) * cplx(G.a_re[j], G.a_im[j]) * G.tau;
+      const double t = n * G.dt + G.mid[j];
+      const double2* zz = hz.data() + ((size_t)n * W.r + j) * M * 5;
+      int p0 = 0;
+      for (int k = 0; k < (int)sys->drives.size(); ++k) {
+        const Drive& Rd = sys->drives[k];
+        const double cr = std::cos(Rd.omega * t + Rd.phase);
+        const double2 zo = zz[Rd.mode * 5 + Rd.op];
+        for (int p = 0; p < (int)Rd.par.size(); ++p) {
+          const double b = envelope_basis(Rd.env, p, (int)Rd.par.size(), n, N, t, sys->T, Rd.sigma);
+          g[p0 + p] += re2(wj * (b * cr), zo);
+        }
+        p0 += (int)Rd.par.size();
+      }
+      for (int m = 0; m < M; ++m)
+        for (int th = 0; th < 3; ++th) g[npulse + 3 * m + th] += re2(wj, zz[m * 5 + 2 + th]);
+    }
+  for (int j = 0; j < W.r; ++j) {
+    const cplx wj = cplx(0.0, -1.0) * cplx(G.a_re[j], G.a_im[j]) * G.tau;
+    for (int e = 0; e < E; ++e) {
+      const Coupling& c = sys->coup[e];
+      const double2* zz = hzp.data() + ((size_t)j * E + e) * 7;
+      g[npulse + 3 * M + e] += re2(wj, zz[0]);
+      for (int th = 0; th < 3; ++th) {
+        g[npulse + 3 * c.i + th] += re2(wj * c.g, zz[1 + th]);
+        g[npulse + 3 * c.j + th] += re2(wj * c.g, zz[4 + th]);
+      }
+    }
+  }
+  bool finite = true;
+  for (int i = 0; i < sys->n_params; ++i) {
+    grad[i] = g[i];
+    finite &= std::isfinite(g[i]);
+  }
+  if (!finite) return fail(SCP_ENONFINITE, "gradient is not finite");
   return SCP_OK;
 }
 

@@ -280,20 +280,110 @@ def _config5_sampled_desc():
 
 def test_config5_full_length_gradient_against_stored_oracle(scp):
     """The full 3000-step config-5 gradient (40 parameters) on the sampled
-    columns against the stored FP64 oracle, for the CZ target and for the
-    near-unit block target."""
+    columns against the stored FP64 oracle, for the CZ target (F ~ 5e-7) and
+    for the nearest unitary to the oracle's 8 x 8 block (F ~ 5e-3)."""
     ref = json.load(open(os.path.join(GOLDEN, "config5_sampled_oracle.json")))
     desc = _config5_sampled_desc()
     print("[adjoint] config5 sampled, 3000 steps", flush=True)
     F, g = gpu_loss_and_grad(scp, desc)
     assert abs(F - ref["F"]) <= DF_TOL
     check_grad(g, np.array(ref["grad"]))
-    nu = ref["near_unit"]
+    nu = ref["block_target"]
     d1 = copy.deepcopy(desc)
     d1["target"] = np.array(nu["target_re"]) + 1j * np.array(nu["target_im"])
     F1, g1 = gpu_loss_and_grad(scp, d1)
     assert abs(F1 - nu["F"]) <= DF_TOL
     check_grad(g1, np.array(nu["grad"]))
+
+
+# Measured gradient error of the real-frame evaluation at F ~ 0.99 (the
+# complex evaluation meets the 1e-4 bar there, the real frame does not): near
+# F = 1 the gradient is a small remainder of terms that cancel in exact
+# arithmetic (the state and its costate are nearly parallel), so FP32 rounding
+# of the trajectory shows at the 1e-4 level.  The bound keeps the measured
+# value from growing unnoticed; it is not the north-star bar.
+REAL_FRAME_NEAR_UNIT_GRAD = 3e-4
+
+
+@pytest.mark.parametrize("real_frame", [False, True], ids=["complex", "real_frame"])
+def test_config5_state_target_near_unit_fidelity(scp, real_frame):
+    """Config 5 in the benchmark's launch configuration (all 256 columns, 3000
+    steps) with the composite state cost (Sec. 4.1) of the 8 sampled columns
+    against target states near the oracle's own final states (F_oracle ~ 0.99,
+    where a drift of the FP32 state norm would show): |dF| <= 1e-6 in both
+    evaluations, and the gradient within 1e-4 of the stored oracle's in the
+    complex evaluation (the real frame's measured 2e-4 is bounded above)."""
+    ref = json.load(open(os.path.join(GOLDEN, "config5_state_oracle.json")))
+    phi = np.load(os.path.join(GOLDEN, "config5_state_target.npy"), allow_pickle=False)
+    desc = si.config5()
+    samp = si.sampled_columns(len(desc["columns"]), 8)
+    assert [desc["columns"][j] for j in samp] == ref["columns"]
+    print(f"[adjoint] config5 all 256 columns, state target on the 8 sampled ones, "
+          f"real frame {real_frame}", flush=True)
+    g = scp.System(desc)
+    g.set_real_frame(real_frame)
+    psi0 = scp.basis_columns(g.D, desc["columns"])
+    opts = g.opts(psi0.shape[0], with_ckpt=1)
+    ws = g.workspace(opts, with_grad=True)
+    U = g.propagate(psi0, opts=opts, workspace=ws)
+    tgt = scp.StateTarget(samp, phi.T)
+    cot = torch.empty_like(U)
+    F, _ = scp.fidelity_states(U, tgt, cotangent=cot)
+    grad = g.adjoint(cot, opts, ws)
+    ref_g = np.array(ref["grad"])
+    err = np.abs(grad - ref_g).max() / np.abs(ref_g).max()
+    print(f"config5 state target: F={F:.9f} F_oracle={ref['F']:.9f} |dF|={abs(F - ref['F']):.2e} "
+          f"gradient rel err={err:.2e}", flush=True)
+    assert ref["F"] > 0.98
+    assert abs(F - ref["F"]) <= DF_TOL
+    if real_frame:
+        assert err <= REAL_FRAME_NEAR_UNIT_GRAD, err
+    else:
+        check_grad(grad, ref_g)
+    # the adjoint that recomputes the checkpoints from psi0 gives the same bits
+    grad2 = g.adjoint(cot, opts, ws, psi0=psi0)
+    assert np.array_equal(grad, grad2)
+    g.close()
+
+
+def test_adjoint_refuses_missing_or_stale_checkpoints(scp):
+    """Without psi0 the adjoint needs the checkpoints of the system's last
+    propagate on the same workspace and opts; anything else is refused with
+    SCP_EINVAL before any launch, and a workspace too small for the adjoint
+    is refused too."""
+    desc = _ring(3, 3, T=2.0, n=50)
+    g = scp.System(desc)
+    g2 = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, desc["columns"])
+    S = psi0.shape[0]
+    opts = g.opts(S, with_ckpt=1)
+    opts7 = g.opts(S, ckpt_every=7, with_ckpt=1)
+    nbytes = max(g.workspace_bytes(opts, True), g.workspace_bytes(opts7, True))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    cot = torch.zeros_like(psi0)
+    cot[0, 0] = 0.5
+    with pytest.raises(scp.ScpError, match="EINVAL.*checkpoints"):
+        g.adjoint(cot, opts, ws)                       # no propagate yet
+    g.propagate(psi0, opts=g.opts(S, with_ckpt=0), workspace=ws)
+    with pytest.raises(scp.ScpError, match="EINVAL.*checkpoints"):
+        g.adjoint(cot, opts, ws)                       # the last one kept none
+    g.propagate(psi0, opts=opts, workspace=ws)
+    ref = g.adjoint(cot, opts, ws)
+    assert np.array_equal(ref, g.adjoint(cot, opts, ws))   # checkpoints stay valid
+    with pytest.raises(scp.ScpError, match="EINVAL.*checkpoints"):
+        g.adjoint(cot, opts7, ws)                      # another checkpoint interval
+    g2.propagate(psi0, opts=g2.opts(S, with_ckpt=1), workspace=ws)
+    with pytest.raises(scp.ScpError, match="EINVAL.*checkpoints"):
+        g.adjoint(cot, opts, ws)                       # another system wrote there
+    assert np.array_equal(ref, g.adjoint(cot, opts, ws, psi0=psi0))
+    small = g.workspace(opts, with_grad=False)
+    g.propagate(psi0, opts=opts, workspace=small)
+    with pytest.raises(scp.ScpError, match="EINVAL.*workspace_bytes"):
+        g.adjoint(cot, opts, small)                    # sized for the forward only
+    with pytest.raises(scp.ScpError, match="EINVAL.*workspace_bytes"):
+        g.propagate(psi0, opts=opts, workspace=small[: small.numel() // 2])
+    g.close()
+    g2.close()
 
 
 def _wrap(x):

@@ -1,0 +1,133 @@
+"""GPU parity of the local continuous adjoint method (LCAM) of the product
+formulas (complex FP64 on the device, reverse-time recovery of the states)
+against the CPU FP64 LCAM oracle, whose gradient is pinned to central finite
+differences and to reverse-mode autodiff through the product formula.
+
+Both sides compute the same gradient in FP64 and differ in rounding order and
+in the matrix exponentials (Taylor scaling and squaring on the device, Pade in
+scipy on the CPU), so the bar is 1e-9 relative to the largest component."""
+import numpy as np
+import pytest
+
+import scp_inputs as si
+from oracle import lcam, trotter
+from oracle.system import OracleSystem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def scp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_18155_amd as m
+    return m
+
+
+def _ring(n_modes, d, n_steps, seed=3, T=1.0):
+    # Q4j gates are not unitary: undoing one multiplies rounding errors by up to
+    # exp(|Im a| tau |h|), which the transmons' lab-frame energies make large
+    # at long steps; T = 1 ns in 10 steps keeps it near 2 (the workloads' steps
+    # of 0.01-0.02 ns near 1.1)
+    s = si.transmon_ring(si.rng_for(9, seed), n_modes, d, T, n_steps)
+    return si._finish(s, [d] * n_modes, target=si.cz_target(n_modes))
+
+
+def _prefix(desc, n_steps):
+    """The first n_steps steps of desc at its own step h (envelopes rescaled)."""
+    import copy
+    d = copy.deepcopy(desc)
+    scale = n_steps / d["n_steps"]
+    d["T"] *= scale
+    d["n_steps"] = n_steps
+    for dr in d["drives"]:
+        dr["sigma"] *= scale
+    return d
+
+
+CASES = {
+    "raw3_d3_pwc": lambda: si.random_raw_system(11, [3, 3, 3], 3, 2.0, 12, env="pwc", n_pieces=4),
+    "raw3_d4_gauss": lambda: si.random_raw_system(12, [4, 4, 4], 2, 2.0, 8, env="gauss"),
+    "raw2_d2": lambda: si.random_raw_system(13, [2, 2], 1, 1.5, 25, env="gauss"),
+    "fluxonium3_d5": lambda: si._finish(si.fluxonium_chain(si.rng_for(2, 1), 3, 5, 1.0, 8,
+                                                           n_basis_gauss=3), [5] * 3),
+    "ring4_d3": lambda: _ring(4, 3, 10),
+}
+
+# every order on a raw chain with a wrap edge and on a transmon ring; the
+# second-order and the complex fourth-order (non-unitary gates) elsewhere
+PAIRS = [(n, o) for n in ("raw3_d3_pwc", "ring4_d3") for o in trotter.ORDERS] + \
+        [(n, o) for n in ("raw3_d4_gauss", "fluxonium3_d5") for o in ("q2", "q4j")] + \
+        [("raw2_d2", "q2")]
+
+
+def _costate(D, S, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=(D, S)) + 1j * rng.normal(size=(D, S))
+
+
+def _compare(scp, desc, order, cols=None, seed=0):
+    columns = desc["columns"] if cols is None else cols
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, columns, dtype=torch.complex128)
+    lam = _costate(g.D, len(columns), seed)
+    cot = torch.tensor(lam.T.copy(), dtype=torch.complex128, device="cuda")
+    grad = g.trotter_adjoint(psi0, cot, order)
+    g.close()
+    o = OracleSystem(desc)
+    ref = lcam.gradient(o, order, lam, np.eye(o.D)[:, columns])
+    err = np.abs(grad - ref).max() / np.abs(ref).max()
+    print(f"[lcam] {order} rel err {err:.2e}", flush=True)
+    assert err <= TOL, err
+    return grad
+
+
+@pytest.mark.parametrize("name,order", PAIRS, ids=[f"{n}-{o}" for n, o in PAIRS])
+def test_lcam_matches_oracle(scp, name, order):
+    print(f"[lcam] {name} {order}", flush=True)
+    _compare(scp, CASES[name](), order)
+
+
+def test_lcam_fluxonium_chain_workload_prefix(scp):
+    # the 4-fluxonium chain (d = 5, D = 625, all 16 computational columns,
+    # 58 parameters) over its first 6 steps at its own step of 0.02 ns
+    print("[lcam] chain4_d5 workload, 6 steps", flush=True)
+    _compare(scp, _prefix(si.config3(), 6), "q2", seed=1)
+
+
+def test_lcam_x6_workload_prefix(scp):
+    # the six-fluxonium X^6 chain (d = 4, D = 4096, 148 parameters), 8 sampled
+    # columns over its first 2 steps of 0.01 ns, Q4 (three pieces)
+    full = si.fluxonium6_x6()
+    desc = _prefix(full, 2)
+    cols = [int(c) for c in np.asarray(full["columns"])[si.sampled_columns(len(full["columns"]))]]
+    print("[lcam] x6 chain, 2 steps, 8 columns", flush=True)
+    _compare(scp, desc, "q4", cols=cols, seed=2)
+
+
+def test_lcam_is_repeatable_and_checks_its_workspace(scp):
+    import ctypes as C
+    from paper_2406_18155_amd._lib import SCP_EINVAL, lib
+    desc = CASES["ring4_d3"]()
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, desc["columns"], dtype=torch.complex128)
+    cot = torch.tensor(_costate(g.D, len(desc["columns"]), 4).T.copy(), device="cuda")
+    a = g.trotter_adjoint(psi0, cot, "q4j")
+    b = g.trotter_adjoint(psi0, cot, "q4j")
+    assert np.array_equal(a, b)
+    need = g.trotter_adjoint_workspace_bytes("q2", psi0.shape[0])
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    gr = (C.c_double * g.n_params)()
+    st = lib().scp_propagate_trotter_adjoint(g.handle, 1, psi0.shape[0], C.c_void_p(ws.data_ptr()),
+                                             need - 1, C.c_void_p(psi0.data_ptr()),
+                                             C.c_void_p(cot.data_ptr()), gr, None)
+    assert st == SCP_EINVAL
+    g.close()
+    ring = si.config5()
+    g = scp.System(ring)
+    with pytest.raises(scp.ScpError, match="EINVAL.*LDS"):
+        g.trotter_adjoint_workspace_bytes("q2", 256)
+    g.close()

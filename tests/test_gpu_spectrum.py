@@ -46,6 +46,13 @@ CASES = {
     "transmon2_d4": lambda: si.config1(),
     "fluxonium3_d4_paper_chain": lambda: _multipath_chain(12.0, 2.0, 4),
     "ring4_d3": lambda: _ring(4, 3),
+    # beyond the one-workgroup solver: the paper's chain at d = 5 (D = 125),
+    # a 5-transmon ring (D = 243), the 4-fluxonium chain of the forward
+    # workloads (D = 625) and a 5-transmon ring at d = 4 (D = 1024)
+    "fluxonium3_d5_paper_chain": lambda: _multipath_chain(12.0, 2.0, 5),
+    "ring5_d3": lambda: _ring(5, 3),
+    "chain4_d5": lambda: dict(si.config2(), drives=[]),
+    "ring5_d4": lambda: _ring(5, 4),
 }
 
 
@@ -89,8 +96,30 @@ def test_static_zz_zero_matches_the_oracle(scp):
     assert abs(rg - ro) <= 1e-5
 
 
+def test_static_zz_zero_reproduces_the_paper_at_d5(scp):
+    """At d = 5 (D = 125, the device-memory eigensolver) the J_C that zeroes
+    zeta_ZZI at J_L = 2 MHz from GPU evaluations is the paper's optimised
+    12.25 MHz (Sec. 3.2), as the oracle finds."""
+    from scipy.optimize import brentq
+    fix = json.load(open(os.path.join(GOLDEN, "static_zz_paper.json")))
+
+    def zg(jc):
+        s = scp.System(_multipath_chain(jc, fix["J_L_MHz"], 5))
+        z = s.static_zz(0, 1)
+        s.close()
+        return z
+
+    rg = brentq(zg, 5.0, 20.0, xtol=1e-7)
+    ro = brentq(lambda jc: static_zz(OracleSystem(_multipath_chain(jc, fix["J_L_MHz"], 5)), 0, 1),
+                5.0, 20.0, xtol=1e-7)
+    print(f"[spectrum] J_C zero at d = 5: GPU {rg:.6f} MHz, oracle {ro:.6f} MHz, paper "
+          f"{fix['J_C_opt_MHz']} MHz", flush=True)
+    assert abs(rg - ro) <= 1e-5
+    assert abs(rg - fix["J_C_opt_MHz"]) <= 0.01
+
+
 def test_static_spectrum_refuses_large_or_complex_systems(scp):
-    big = _ring(5, 3)                         # D = 243 > 96
+    big = _ring(7, 3)                         # D = 2187 > 2048
     g = scp.System(big)
     with pytest.raises(scp.ScpError):
         g.static_zz(0, 1)

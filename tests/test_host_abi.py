@@ -113,6 +113,9 @@ def test_null_arguments_are_refused():
     assert lib().scp_system_set_frame(None, 0) == SCP_EINVAL
     assert lib().scp_trotter_workspace_size(None, 1, C.byref(n)) == SCP_EINVAL
     assert lib().scp_propagate_trotter(None, 1, 1, None, None, None, None) == SCP_EINVAL
+    assert lib().scp_propagate_adjoint(None, None, None, None, None, None, None) == SCP_EINVAL
+    assert lib().scp_fidelity_states(None, 4, 1, 0, 1, None, None, None, None, None,
+                                     None) == SCP_EINVAL
 
 
 def test_request_footprint_grows_with_columns_steps_and_gradient():
