@@ -34,8 +34,7 @@
 // to the segment buffer, then one launch of the kernel here walks the segment
 // back.  Within a stage kb and y sit in LDS in natural order and every layout
 // gathers its elements; yb passes from layout to layout in natural order.
-// The costate (a compensated hi + lo pair: its per-step increments are small
-// against it), the running sum of yb and the FP64 accumulators live in device
+// The costate, the running sum of yb and the FP64 accumulators live in device
 // memory and carry between launches exactly.
 #include <algorithm>
 
@@ -291,16 +290,12 @@ __device__ __forceinline__ float im_dot(kptr<c32> X, const Mat<d>& M) {
 
 // Im( sum_ab X_ab M_ab ) with X at element offset off of the stage's complex
 // table, or (real frame) of the real table.
-// The real table holds each operator as FP32 hi, and block_q floats later its
-// residual lo: the same operators enter every stage, so the fold uses hi + lo
-// (one rounding of the table would otherwise bias every stage the same way).
 template <int d, bool RF>
-__device__ __forceinline__ float tdot(kptr<c32> ops, kptr<float> rops, int off, const Mat<d>& M,
-                                      int bq = 0) {
+__device__ __forceinline__ float tdot(kptr<c32> ops, kptr<float> rops, int off, const Mat<d>& M) {
   if constexpr (RF) {
     float s = 0.f;
 #pragma unroll
-    for (int i = 0; i < d * d; ++i) s = fmaf(rops[off + i], M.im[i], fmaf(rops[bq + off + i], M.im[i], s));
+    for (int i = 0; i < d * d; ++i) s = fmaf(rops[off + i], M.im[i], s);
     return s;
   } else {
     return im_dot<d>(ops + off, M);
@@ -377,7 +372,6 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
   constexpr int dd = d * d;
   const int L = P->L;
   const int npulse = P->npulse, N = P->N;
-  const int bqr = RF ? uni(P->block_q) : 0;   // offset of the residual table
 #pragma unroll
   for (int r = 0; r < RB; ++r) yb.re[r] = yb.im[r] = 0.f;
   // per-lane derivative sums of a mode shared by the last register position
@@ -436,17 +430,17 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
           for (int q = 0; q < nq; ++q) {
             const int e = uni(P->pair_coup[pr][q]);
             const int sj = uni(P->pair_pslot[pr][q]);
-            fold(A, accw, npulse + 3 * N + e, tdot<d, RF>(ops, rops, sj * dd, G, bqr), lane);
+            fold(A, accw, npulse + 3 * N + e, tdot<d, RF>(ops, rops, sj * dd, G), lane);
             const float ge = unif(P->coup_g[e]);
 #pragma unroll
             for (int th = 0; th < 3; ++th)
-              dacc[(p + 1) * 3 + th] += ge * tdot<d, RF>(ops, rops, offd + (sj * 3 + th) * dd, G, bqr);
+              dacc[(p + 1) * 3 + th] += ge * tdot<d, RF>(ops, rops, offd + (sj * 3 + th) * dd, G);
           }
           // real frame, first factor i times real: its folds change sign (i^2)
           const float hs = RF ? (float)uni(C.hsign) : 1.f;
 #pragma unroll
           for (int th = 0; th < 3; ++th)
-            dacc[p * 3 + th] += hs * tdot<d, RF>(ops, rops, offd + (c_slot * 3 + th) * dd, H, bqr);
+            dacc[p * 3 + th] += hs * tdot<d, RF>(ops, rops, offd + (c_slot * 3 + th) * dd, H);
         }
       });
     });
@@ -498,15 +492,13 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
 #pragma unroll
           for (int th = 0; th < 3; ++th)
 #pragma unroll
-            for (int a = 0; a < d; ++a)
-              dev[th] = fmaf(unif(P->deps[m][th][a]), K.im[a * d + a],
-                             fmaf(unif(P->deps_lo[m][th][a]), K.im[a * d + a], dev[th]));
+            for (int a = 0; a < d; ++a) dev[th] = fmaf(unif(P->deps[m][th][a]), K.im[a * d + a], dev[th]);
           const int offd = uni(P->off_dslot);
           const int k0 = uni(P->mdrv_off[m]), k1 = uni(P->mdrv_off[m + 1]);
           for (int kk = k0; kk < k1; ++kk) {
             const auto& R = P->drives[uni(P->mdrv[kk])];
             const int rslot = uni(R.slot);
-            const float s_im = wave_sum(tdot<d, RF>(ops, rops, rslot * dd, K, bqr));
+            const float s_im = wave_sum(tdot<d, RF>(ops, rops, rslot * dd, K));
             const int par0 = uni(R.par0), npar = uni(R.npar);
             for (int q = 0; q < npar; ++q)
               acc_add(A, accw, par0 + q, (double)dcq[par0 + q] * (double)s_im, lane);
@@ -514,7 +506,7 @@ __device__ __forceinline__ void adj_stage(kptr<Plan> P, c32* lds, int cbase,
               const float c = cq[uni(R.cidx)];
 #pragma unroll
               for (int th = 0; th < 3; ++th)
-                dev[th] = fmaf(c, tdot<d, RF>(ops, rops, offd + (rslot * 3 + th) * dd, K, bqr), dev[th]);
+                dev[th] = fmaf(c, tdot<d, RF>(ops, rops, offd + (rslot * 3 + th) * dd, K), dev[th]);
             }
           }
 #pragma unroll
@@ -600,7 +592,6 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   const size_t colreg = (size_t)(active ? col : 0) * D + tc;   // register-order slice
   c32* ysum = (c32*)I.sum + colreg;            // per-step sum of yb (device memory)
   c32* lst = (c32*)I.lamstate + colreg;        // costate lambda (device memory)
-  c32* lsl = (c32*)I.lamlo + colreg;           // its compensation word
   const size_t ystride = (size_t)S * D;        // between stages in the segment buffer
   c32* ycol0 = segbuf + (size_t)(active ? col : 0) * D;   // this column, natural order
   const int tbB = thread_base<d>(P, base, tc);            // base-layout addressing
@@ -608,10 +599,8 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   // the costate starts from the cotangent (natural order) on the first launch
   if (active && I.first) {
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
+    for (int r = 0; r < RB; ++r)
       lst[(size_t)r * TPC] = ((const c32*)I.lamT)[(size_t)col * D + tbB + RB_(r)];
-      lsl[(size_t)r * TPC] = c32{0.f, 0.f};
-    }
   }
 
   float pf_sink = 0.f;
@@ -704,7 +693,6 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
           // sum of the yb of this step; after its last stage lambda <- lambda + sum
           const gptr<c32> ys_p = fresh(ysum);
           const gptr<c32> lm_p = fresh(lst);
-          const gptr<c32> ll_p = fresh(lsl);
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
             float vx = yb.re[r], vy = yb.im[r];
@@ -713,17 +701,10 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
               vy = ys_p[(size_t)r * TPC].y + vy;
             }
             if (s == 0) {
-              // lambda (hi + lo) += the step's sum, compensated: the per-step
-              // increments are O(h |V|) of lambda, so plain FP32 accumulation
-              // would drift over thousands of steps
-              float hx = lm_p[(size_t)r * TPC].x, hy = lm_p[(size_t)r * TPC].y;
-              float lx = ll_p[(size_t)r * TPC].x, ly = ll_p[(size_t)r * TPC].y;
-              comp_add(hx, lx, vx);
-              comp_add(hy, ly, vy);
-              lm_p[(size_t)r * TPC].x = hx;
-              lm_p[(size_t)r * TPC].y = hy;
-              ll_p[(size_t)r * TPC].x = lx;
-              ll_p[(size_t)r * TPC].y = ly;
+              const float lx = lm_p[(size_t)r * TPC].x + vx;
+              const float ly = lm_p[(size_t)r * TPC].y + vy;
+              lm_p[(size_t)r * TPC].x = lx;
+              lm_p[(size_t)r * TPC].y = ly;
             } else {
               ys_p[(size_t)r * TPC].x = vx;
               ys_p[(size_t)r * TPC].y = vy;

@@ -69,7 +69,6 @@ struct Plan {
   int32_t has_mode_pass[MAXL];
   int32_t mode_pass[MAXL][8];      // adjoint: single-mode sensitivities of this mode at p (-1: none)
   float deps[16][3][8];            // d eps / d(EJ, EC, EL) per mode
-  float deps_lo[16][3][8];         // their FP32 residuals (deps + deps_lo ~ the FP64 value)
   int32_t lmode[MAXL][8];          // mode at each register position of each layout (-1: none)
   int32_t mdrv_off[17];            // drives of mode m: mdrv[mdrv_off[m] .. mdrv_off[m+1])
   int32_t mdrv[MAXGROUPS];         // drive indices grouped by mode
@@ -114,7 +113,7 @@ struct AdjItem {
   const float4* ckpt;
   const float2* lamT;   // cotangent (natural order), read when first != 0
   float2* segbuf;
-  float2* lamlo;        // register-order compensation word of the costate
+  float2* lo;
   float2* sum;
   float2* lamstate;     // register-order costate carried between launches
   double* part;         // [column block][4 waves][nacc] FP64 accumulators
@@ -188,8 +187,7 @@ struct scp_system {
   double* d_dctab64 = nullptr;
   double* d_ctab64 = nullptr;   // [3N][n_drives] c(t) per drive, FP64 (plain path)
   float2* d_ph = nullptr;       // real frame: [2N+1][ph_row] frame phases (cos, sin)
-  float* d_rops = nullptr;      // real frame: [2][block_q] un-rotated operators (real parts):
-                                // FP32 values, then their FP32 residuals
+  float* d_rops = nullptr;      // real frame: [block_q] un-rotated operators (real parts)
   void* d_scratch = nullptr;    // small per-system scratch (adjoint partial sums)
   size_t scratch_bytes = 0;
   int device = 0;

@@ -470,11 +470,7 @@ scp_status make_plan(scp_system* sys) {
     P.mode_pass[l][p] = m;
     P.has_mode_pass[l] = 1;
     for (int th = 0; th < 3; ++th)
-      for (int a = 0; a < d; ++a) {
-        const double x = sys->modes[m].deps[th][a];
-        P.deps[m][th][a] = (float)x;
-        P.deps_lo[m][th][a] = (float)(x - (double)P.deps[m][th][a]);
-      }
+      for (int a = 0; a < d; ++a) P.deps[m][th][a] = (float)sys->modes[m].deps[th][a];
   }
   // drives
   int par0 = 0;
@@ -677,16 +673,8 @@ scp_status build_tables(scp_system* sys, hipStream_t st) {
     // the operators at t = 0 (the table's block 0 rounds them the same way)
     // (kind 2: the imaginary parts; a pair term of kind 2 is i^2 = -1 times the
     // product of the real parts, folded into the pair operator's sign)
-    // Each entry is stored as FP32 hi, and in a second block of block_q
-    // floats its residual lo = x - hi: the same real operators enter every
-    // stage, so their rounding would bias the adjoint's folds coherently over
-    // all steps; the folds use hi + lo (the applications use hi).
-    std::vector<float> rops(2 * (size_t)P.block_q, 0.f);
-    auto put = [&](int at, double x) {
-      const float hi = (float)x;
-      rops[at] = hi;
-      rops[P.block_q + at] = (float)(x - (double)hi);
-    };
+    std::vector<float> rops(P.block_q, 0.f);
+    auto put = [&](int at, double x) { rops[at] = (float)x; };
     for (int s = 0; s < ns; ++s)
       for (int i = 0; i < dd; ++i) {
         const bool im = sys->slot_imag[s] != 0;
