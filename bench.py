@@ -509,6 +509,9 @@ def main():
     ap.add_argument("--trotter", action="store_true",
                     help="only time the Suzuki-Trotter product formulas (one JSON line each) and exit")
     ap.add_argument("--trotter-orders", default="q1,q2,q4,q4j")
+    ap.add_argument("--frame", choices=("real", "complex"), default="real",
+                    help="generator evaluation of the timed steps (the real frame where "
+                         "the system allows it, or the rotated complex operators)")
     ap.add_argument("--cpu-protocol", action="store_true",
                     help="only run the oracle's full CPU timing protocol (long) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -559,6 +562,7 @@ def main():
 
     def step(timed_kernels=False):
         g = scp.System(desc)
+        g.set_real_frame(args.frame == "real")
         if timed_kernels:
             g.set_timing(True)
         psi0 = scp.basis_columns(g.D, desc["columns"], device=dev)
@@ -617,13 +621,16 @@ def main():
                 "share_of_step": ms / args.steps / (dt * 1e3), "note": bound_note}
         return line
 
+    rf = "true" if args.frame == "real" else "false"
+    sfx = "" if args.frame == "real" else "_complex"
     kernels = {
-        "reverse": kernel_line("reverse", "adjoint_kernel<3,3,1,true>", "adjoint_ring8_d3",
+        "reverse": kernel_line("reverse", f"adjoint_kernel<3,3,1,{rf}>", "adjoint_ring8_d3" + sfx,
                                "reverse walk of one checkpoint segment: per stage C reverse "
                                "contractions + (3 per pair + 1 per mode) sensitivity contractions"),
-        "forward": kernel_line("forward", "rk4_kernel<3,3,1,false,true>", "rk4_ring8_d3",
+        "forward": kernel_line("forward", f"rk4_kernel<3,3,1,false,{rf}>", "rk4_ring8_d3" + sfx,
                                "the whole 3000-step forward in one launch, C contractions per stage"),
-        "recompute": kernel_line("recompute", "rk4_kernel<3,3,1,true,true>", "recompute_ring8_d3",
+        "recompute": kernel_line("recompute", f"rk4_kernel<3,3,1,true,{rf}>",
+                                 "recompute_ring8_d3" + sfx,
                                  "one checkpoint segment forward, stage inputs stored"),
     }
 
@@ -633,12 +640,14 @@ def main():
         st_path = os.path.join(ROOT, "tests", "golden", "config5_state_oracle.json")
         cz_path = os.path.join(ROOT, "tests", "golden", "config5_sampled_oracle.json")
         g = scp.System(desc)
+        g.set_real_frame(args.frame == "real")
         psi0 = scp.basis_columns(g.D, desc["columns"], device=dev)
         opts = g.opts(S, with_ckpt=1)
         ws = state["ws"]
         U = g.propagate(psi0, opts=opts, workspace=ws)
         cot = state["cot"]
         samp = si.sampled_columns(S, 8)
+        gc_ = None
         if os.path.exists(st_path):
             ref = json.load(open(st_path))
             phi = np.load(os.path.join(ROOT, "tests", "golden", "config5_state_target.npy"),
@@ -654,7 +663,8 @@ def main():
                                             "(F_oracle = %.6f) vs the stored FP64 oracle" % ref["F"]})
             # the same with the complex evaluation of the generator (the real
             # frame's FP32 gradient near F = 1 is above the 1e-4 bar)
-            gc_ = scp.System(desc)
+            gc_ = scp.System(desc) if args.frame == "real" else None
+        if gc_ is not None:
             gc_.set_real_frame(False)
             Uc = gc_.propagate(psi0, opts=opts, workspace=ws)
             Fc, _ = scp.fidelity_states(Uc, scp.StateTarget(samp, phi.T), cotangent=cot)
@@ -696,7 +706,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "8-transmon ring, d=3, D=6561, 256 computational columns, "
                                "T=60 ns, 3000 RK4 steps, 40 gradient parameters",
-                   "global_batch": S, "seq_len": N},
+                   "global_batch": S, "seq_len": N,
+                   "generator_evaluation": ("real frame (real operators between diagonal "
+                                            "frame rotations)" if args.frame == "real" else
+                                            "complex (rotated operators per half step)")},
         # the dominant kernel (HIP events recorded by the library on the launch stream)
         "roofline": kernels["reverse"],
         "kernels": kernels,

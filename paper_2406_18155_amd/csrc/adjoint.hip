@@ -34,7 +34,8 @@
 // to the segment buffer, then one launch of the kernel here walks the segment
 // back.  Within a stage kb and y sit in LDS in natural order and every layout
 // gathers its elements; yb passes from layout to layout in natural order.
-// The costate, the running sum of yb and the FP64 accumulators live in device
+// The costate (a compensated hi + lo pair: its per-step increments are small
+// against it), the running sum of yb and the FP64 accumulators live in device
 // memory and carry between launches exactly.
 #include <algorithm>
 
@@ -592,6 +593,7 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   const size_t colreg = (size_t)(active ? col : 0) * D + tc;   // register-order slice
   c32* ysum = (c32*)I.sum + colreg;            // per-step sum of yb (device memory)
   c32* lst = (c32*)I.lamstate + colreg;        // costate lambda (device memory)
+  c32* lsl = (c32*)I.lamlo + colreg;           // its compensation word
   const size_t ystride = (size_t)S * D;        // between stages in the segment buffer
   c32* ycol0 = segbuf + (size_t)(active ? col : 0) * D;   // this column, natural order
   const int tbB = thread_base<d>(P, base, tc);            // base-layout addressing
@@ -599,8 +601,10 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
   // the costate starts from the cotangent (natural order) on the first launch
   if (active && I.first) {
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
+    for (int r = 0; r < RB; ++r) {
       lst[(size_t)r * TPC] = ((const c32*)I.lamT)[(size_t)col * D + tbB + RB_(r)];
+      lsl[(size_t)r * TPC] = c32{0.f, 0.f};
+    }
   }
 
   float pf_sink = 0.f;
@@ -693,6 +697,7 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
           // sum of the yb of this step; after its last stage lambda <- lambda + sum
           const gptr<c32> ys_p = fresh(ysum);
           const gptr<c32> lm_p = fresh(lst);
+          const gptr<c32> ll_p = fresh(lsl);
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
             float vx = yb.re[r], vy = yb.im[r];
@@ -701,10 +706,17 @@ __device__ __forceinline__ void adjoint_block(const AdjItem& I) {
               vy = ys_p[(size_t)r * TPC].y + vy;
             }
             if (s == 0) {
-              const float lx = lm_p[(size_t)r * TPC].x + vx;
-              const float ly = lm_p[(size_t)r * TPC].y + vy;
-              lm_p[(size_t)r * TPC].x = lx;
-              lm_p[(size_t)r * TPC].y = ly;
+              // lambda (hi + lo) += the step's sum, compensated: the per-step
+              // increments are O(h |V|) of lambda, so plain FP32 accumulation
+              // would drift over thousands of steps
+              float hx = lm_p[(size_t)r * TPC].x, hy = lm_p[(size_t)r * TPC].y;
+              float lx = ll_p[(size_t)r * TPC].x, ly = ll_p[(size_t)r * TPC].y;
+              comp_add(hx, lx, vx);
+              comp_add(hy, ly, vy);
+              lm_p[(size_t)r * TPC].x = hx;
+              lm_p[(size_t)r * TPC].y = hy;
+              ll_p[(size_t)r * TPC].x = lx;
+              ll_p[(size_t)r * TPC].y = ly;
             } else {
               ys_p[(size_t)r * TPC].x = vx;
               ys_p[(size_t)r * TPC].y = vy;

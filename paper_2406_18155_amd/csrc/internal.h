@@ -113,7 +113,7 @@ struct AdjItem {
   const float4* ckpt;
   const float2* lamT;   // cotangent (natural order), read when first != 0
   float2* segbuf;
-  float2* lo;
+  float2* lamlo;        // register-order compensation word of the costate
   float2* sum;
   float2* lamstate;     // register-order costate carried between launches
   double* part;         // [column block][4 waves][nacc] FP64 accumulators
