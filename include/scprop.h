@@ -179,7 +179,8 @@ scp_status scp_system_set_frame(scp_system* sys, int32_t real_frame);
  * on its stream (the events are created per launch).  scp_system_kernel_times
  * waits for the recorded events and writes ms_out[3] (total milliseconds) and
  * counts[3] (launches) for the kinds forward, recompute, reverse since the
- * last read, then forgets them.  enable = 0 drops unread events. */
+ * last read, then forgets them.  enable = 0 drops unread events.  Not with
+ * scp_propagate_adjoint_noalloc (it refuses while timing is on). */
 scp_status scp_system_set_timing(scp_system* sys, int32_t enable);
 scp_status scp_system_kernel_times(scp_system* sys, double* ms_out, int32_t* counts);
 
@@ -301,6 +302,25 @@ scp_status scp_fidelity_zcomp(const void* U, int64_t D, int32_t S, int32_t preci
 scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, void* workspace,
                                  const void* psi0, const void* cotangent, double* grad_out,
                                  void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * gradient of scp_propagate_adjoint with psi0 given, with the workspace taken
+ * from a static device array of SCP_NOALLOC_SCRATCH_BYTES = 64 MiB (each GPU
+ * holds its own copy until the process ends) instead of a caller buffer.
+ * psi0 (D x S complex64) and cotangent (D x S complex64) are device pointers;
+ * opts->workspace_bytes is ignored.  The forward with checkpoints, the
+ * segment recomputations and the reverse walk all run in the static array;
+ * no device memory is allocated.  SCP_EINVAL if scp_workspace_size(opts,
+ * with_grad = 1) exceeds 64 MiB (e.g. the 4-fluxonium chain, D = 625,
+ * 16 columns, 5000 steps, needs about 35 MB; 256 columns of D = 6561 do not
+ * fit).  Every call on one GPU uses that GPU's one array, so calls that
+ * overlap on one GPU (other streams or threads) race and must be serialised
+ * by the caller.  Synchronises ``stream``; results are bitwise those of
+ * scp_propagate_adjoint with psi0. */
+scp_status scp_propagate_adjoint_noalloc(scp_system* sys, const scp_solve_opts* opts,
+                                         const void* psi0, const void* cotangent,
+                                         double* grad_out, void* stream);
 
 /* ------------------------------------------------------------------------
  * Suzuki-Trotter product formulas (Sec. 2.3 Trotterization solver, App. A).

@@ -251,6 +251,15 @@ class System:
                                           _ptr(cotangent), g, _stream_ptr(stream)))
         return np.array(g[: self.n_params])
 
+    def adjoint_noalloc(self, cotangent, opts, psi0, stream=None):
+        """The gradient of ``adjoint(cotangent, opts, ws, psi0)`` with the
+        workspace in the library's static 64 MiB device array (no device
+        allocation; calls that overlap on one GPU race)."""
+        g = (C.c_double * max(1, self.n_params))()
+        check(lib().scp_propagate_adjoint_noalloc(self.handle, C.byref(opts), _ptr(psi0),
+                                                  _ptr(cotangent), g, _stream_ptr(stream)))
+        return np.array(g[: self.n_params])
+
     def close(self):
         if getattr(self, "handle", None):
             lib().scp_destroy(self.handle)

@@ -1169,6 +1169,57 @@ scp_status finish_adjoint(scp_system* sys, const WsLayout& w, char* ws, const vo
 
 extern "C" {
 
+// Allocation-free adjoint: the workspace (checkpoints, segment buffer,
+// costate, FP64 partials) is a file-scope device array of fixed size.  Each
+// device holds its own copy until the process ends; the host reaches it only
+// through the address hipGetSymbolAddress returns for the current device,
+// taken once per device on the first call there.
+#define SCP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+static __device__ __align__(256) unsigned char scratch[SCP_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void*> g_scratch_ptr;   // device ordinal -> its copy of scratch
+
+static scp_status scratch_address(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (p == nullptr) return fail(SCP_EHIP, "hipGetSymbolAddress(scratch) gave a null address");
+    it = g_scratch_ptr.emplace(dev, p).first;
+  }
+  *out = it->second;
+  return SCP_OK;
+}
+
+scp_status scp_propagate_adjoint_noalloc(scp_system* sys, const scp_solve_opts* opts,
+                                         const void* psi0, const void* cotangent,
+                                         double* grad_out, void* stream) {
+  g_err.clear();
+  if (!sys || !opts || !psi0 || !cotangent || !grad_out) return fail(SCP_EINVAL, "null argument");
+  if (opts->precision != 0) return fail(SCP_EINVAL, "the adjoint runs on the FP32 path (precision 0)");
+  if (opts->n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  if (opts->ckpt_every < 0) return fail(SCP_EINVAL, "ckpt_every must be >= 0");
+  WsLayout w = ws_layout(sys, opts, 1);
+  if (w.total > SCP_NOALLOC_SCRATCH_BYTES)
+    return fail(SCP_EINVAL, "the adjoint needs " + std::to_string(w.total) +
+                                " bytes of workspace; the static scratch holds " +
+                                std::to_string(SCP_NOALLOC_SCRATCH_BYTES));
+  if (sys->timing) return fail(SCP_EINVAL, "kernel timing creates HIP events; switch it off first");
+  void* base = nullptr;
+  scp_status s = scratch_address(&base);
+  if (s != SCP_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char* ws = (char*)base;
+  s = launch_rk4(sys, (const float2*)psi0, nullptr, (float2*)(ws + w.lo), (float4*)(ws + w.ckpt),
+                 w.ce, opts->n_cols, st);
+  if (s != SCP_OK) return s;
+  return finish_adjoint(sys, w, ws, cotangent, grad_out, opts->n_cols, st);
+}
+
 void scp_destroy(scp_system* sys) {
   if (!sys) return;
   ck_clear(sys);
