@@ -282,6 +282,59 @@ scp_status scp_fidelity_zcomp(const void* U, int64_t D, int32_t S, int32_t preci
                               const void* target, void* block_out, void* tau_out, double* F_out,
                               double* phases_out, void* cotangent, void* stream);
 
+/* Multi-qubit eigenbasis (App. D, eq. for the basis transform U -> V^dag U V):
+ * the static Hamiltonian H0 of scp_energy_tensor is diagonalised (FP64,
+ * device) and each bare product state labels[j] (host int64, n of them) takes
+ * the eigenvector v_j of largest overlap |<k|v>|^2, its phase fixed by
+ * <labels[j]|v_j> > 0, with energy E_j (E_out, host, nullable).  The
+ * eigenbasis unitary is read in the frame of the dressed energies,
+ * M_ij = exp(i E_i T) <v_i|U_lab|v_j> = <w_i|psi_I,j(T)> for the columns
+ * psi_j(0) = v_j propagated by scp_propagate, with
+ * w_i = exp(i (H_f - E_i) T) v_i (H_f the frame of the propagation).
+ * Outputs (device, caller-owned, D x n column-major): psi0_out, the v_j in
+ * complex64 (precision 0) or complex128 (1), to propagate; W_out (complex128,
+ * nullable) the w_i; phi_out (complex128, nullable; needs target, host
+ * complex128 n x n row-major as (re, im) pairs) the target states
+ * phi_j = sum_i T_ij w_i, so that scp_fidelity_states of the propagated
+ * columns against phi is the eigenbasis gate fidelity |Tr(T^dag M)|^2 / n^2.
+ * The basis and energies are those of the system as built (held fixed when
+ * parameters move, like the frame).  Synchronises the stream; allocates
+ * temporary device memory.  Errors: SCP_EINVAL (as scp_energy_tensor, a
+ * label out of range), SCP_ENONFINITE, SCP_EHIP. */
+scp_status scp_eigenbasis_states(const scp_system* sys, int32_t n, const int64_t* labels,
+                                 const double* target, double T, int32_t precision,
+                                 void* psi0_out, void* phi_out, void* W_out, double* E_out,
+                                 void* stream);
+
+/* Fidelity with error-free single-qubit gates before and after the gate
+ * (App. D step 6), in the product basis or an eigenbasis.  The d_c x d_c
+ * block (d_c = 2^n_qubits, qubit 0 most significant) is
+ * M_ij = <w_i | U[:, cols[j]]> for W (device complex128, D x d_c: the w_i of
+ * scp_eigenbasis_states), or M_ij = U[comp_rows[i], cols[j]] when W is NULL;
+ * FP64 on the device.  On the host the gates maximising
+ * |tau| = |Tr(T^dag A M B)| are sought by coordinate ascent from the
+ * identity: mode 1, Z rotations (the phases of scp_fidelity_zcomp);
+ * mode 2, arbitrary single-qubit unitaries A = (x)a_q, B = (x)b_q, each set
+ * in turn to the polar optimum of its partial trace, sweeps until |tau| grows
+ * by at most 1e-14 relative or 500 sweeps (a local search: it reaches the
+ * maximum for CZ, CNOT and product targets, not always for generic entangling
+ * ones).  F_out (host, required) = |tau|^2 / d_c^2; params_out (host,
+ * nullable): mode 1, a then c phases (2 n doubles); mode 2, a_0..a_{n-1} then
+ * b_0..b_{n-1}, each 2 x 2 row-major as (re, im) pairs (16 n doubles).
+ * block_out (device complex128, 2 d_c^2, caller-owned): M, then the
+ * compensated target T' = A^dag T B^dag.  cotangent (nullable, as U): the
+ * costate of L = 1 - F at the optimum, -(tau/d_c^2) sum_i T'_ij w_i in column
+ * cols[j] (at the computational rows without W), zero elsewhere; the gates
+ * are stationary there, so scp_propagate_adjoint gives dL/dtheta of the
+ * compensated loss.  target: device complex128 d_c x d_c.  Synchronises the
+ * stream.  Errors: SCP_EINVAL (n_qubits outside 1..6, mode), SCP_ENONFINITE,
+ * SCP_EHIP. */
+scp_status scp_fidelity_local(const void* U, int64_t D, int32_t S, int32_t precision,
+                              int32_t n_qubits, const int32_t* cols, const void* W,
+                              const int64_t* comp_rows, const void* target, int32_t mode,
+                              void* block_out, void* tau_out, double* F_out, double* params_out,
+                              void* cotangent, void* stream);
+
 /* Gradient of L w.r.t. every parameter (host FP64, n_params entries in the
  * order of scp_system_info), given the costate cotangent = dL/dU* of the final
  * state (D x S complex64, device).  The discrete adjoint of Sec. 2.5 (the

@@ -9,5 +9,5 @@ from ._lib import ScpError, lib  # noqa: F401
 lib()  # fail loudly if the HIP library is missing
 
 from .api import (StateTarget, System, Target, basis_columns, fidelity,  # noqa: E402,F401
-                  fidelity_states, fidelity_zcomp)
+                  fidelity_local, fidelity_states, fidelity_zcomp)
 from . import autograd  # noqa: E402,F401

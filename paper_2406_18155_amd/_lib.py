@@ -69,6 +69,14 @@ EXPORTS = {
     "scp_fidelity_states": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.POINTER(C.c_double), C.c_void_p]),
+    "scp_eigenbasis_states": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
+                                        C.POINTER(C.c_double), C.c_double, C.c_int32, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                        C.c_void_p]),
+    "scp_fidelity_local": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.c_void_p, C.c_void_p]),
     "scp_fidelity_zcomp": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p,

@@ -139,6 +139,30 @@ class System:
         check(lib().scp_system_kernel_times(self.handle, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(("forward", "recompute", "reverse"))}
 
+    def eigenbasis_states(self, labels, target=None, T=None, dtype=torch.complex64,
+                          stream=None):
+        """(psi0 (n, D), phi (n, D) or None, W (n, D), E (n,)): the dressed
+        eigenstates of the bare labels, their dressed-frame projectors and the
+        eigenbasis target states for the target (App. D basis transform)."""
+        n = len(labels)
+        lab = (C.c_int64 * n)(*[int(k) for k in labels])
+        T = self.desc["T"] if T is None else T
+        prec = 0 if dtype == torch.complex64 else 1
+        psi0 = torch.empty((n, self.D), dtype=dtype, device="cuda")
+        W = torch.empty((n, self.D), dtype=torch.complex128, device="cuda")
+        phi = None
+        tgt = None
+        if target is not None:
+            t = np.asarray(target, dtype=np.complex128)
+            tgt = np.ascontiguousarray(np.stack([t.real, t.imag], axis=-1)).reshape(-1)
+            phi = torch.empty((n, self.D), dtype=torch.complex128, device="cuda")
+        E = (C.c_double * n)()
+        check(lib().scp_eigenbasis_states(
+            self.handle, n, lab,
+            None if tgt is None else tgt.ctypes.data_as(C.POINTER(C.c_double)), float(T), prec,
+            _ptr(psi0), None if phi is None else _ptr(phi), _ptr(W), E, _stream_ptr(stream)))
+        return psi0, phi, W, np.array(E[:])
+
     def energy_tensor(self, stream=None):
         """Dressed energies labelled by bare product states (D,), rad/ns."""
         E = (C.c_double * int(self.D))()
@@ -320,6 +344,33 @@ def fidelity_states(U, tgt: StateTarget, cotangent=None, stream=None, sync=True)
                                     None if cotangent is None else _ptr(cotangent),
                                     C.byref(F) if sync else None, _stream_ptr(stream)))
     return (F.value if sync else None), tgt.tau
+
+
+def fidelity_local(U, cols, target, n_qubits, mode="su2", W=None, comp_rows=None,
+                   cotangent=None, stream=None):
+    """Fidelity with error-free single-qubit gates before and after the gate
+    (mode "z": phases, "su2": arbitrary unitaries), in the basis of the rows of
+    W (n, D) complex128 or at comp_rows.  Returns (F, params, block, T')."""
+    prec = 0 if U.dtype == torch.complex64 else 1
+    S, D = U.shape
+    dc = 2 ** int(n_qubits)
+    colsd = torch.tensor(list(cols), dtype=torch.int32, device=U.device)
+    rows = None if comp_rows is None else torch.tensor(list(comp_rows), dtype=torch.int64,
+                                                       device=U.device)
+    tg = torch.tensor(np.asarray(target, dtype=np.complex128), device=U.device).contiguous()
+    block = torch.empty((2, dc, dc), dtype=torch.complex128, device=U.device)
+    tau = torch.zeros(1, dtype=torch.complex128, device=U.device)
+    m = {"z": 1, "su2": 2}[mode]
+    npar = 2 * int(n_qubits) if m == 1 else 16 * int(n_qubits)
+    par = (C.c_double * npar)()
+    F = C.c_double()
+    check(lib().scp_fidelity_local(_ptr(U), D, S, prec, int(n_qubits), _ptr(colsd),
+                                   None if W is None else _ptr(W),
+                                   None if rows is None else _ptr(rows), _ptr(tg), m,
+                                   _ptr(block), _ptr(tau), C.byref(F), par,
+                                   None if cotangent is None else _ptr(cotangent),
+                                   _stream_ptr(stream)))
+    return F.value, np.array(par[:]), block[0], block[1]
 
 
 def fidelity_zcomp(U, tgt: Target, n_qubits, cotangent=None, stream=None):

@@ -15,6 +15,7 @@
 // FP64, the phases maximising |tau| are found on the host (a few hundred
 // FP64 operations per phase update), and the cotangent is that of the target
 // rephased by the optimal phases (they are stationary at the optimum).
+#include <array>
 #include <complex>
 #include <vector>
 
@@ -366,6 +367,342 @@ scp_status launch_zcomp(const void* U, int64_t D, int S, int prec, int nq, const
                   : run_zcomp_cot<double2>(cot, D, S, dc, rows, cols, target, ph, t2, s);
     if (e != hipSuccess) return fail(SCP_EHIP, std::string("zcomp cotangent: ") + hipGetErrorString(e));
   }
+  return SCP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Compensated fidelity in a given basis (App. D): the block
+// M_ij = <w_i | U[:, cols[j]]> (W: D x d_c device, complex128) or, without W,
+// M_ij = U[comp_rows[i], cols[j]]; on the host the single-qubit compensation
+// (Z phases, or arbitrary SU(2) unitaries by coordinate ascent with polar
+// factors); the compensated target T' and the costate
+// -(tau/d_c^2) sum_i T'_ij w_i (or at the computational rows).
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int PB_THREADS = 256;
+
+// one workgroup per block entry (i, j): sum_k conj(W[k, i]) U[k, cols[j]] in FP64
+template <typename T2>
+__global__ void __launch_bounds__(PB_THREADS)
+proj_block_kernel(const T2* __restrict__ U, int64_t D, int S, int dc,
+                  const int32_t* __restrict__ cols, const double2* __restrict__ W,
+                  double2* __restrict__ out) {
+  __shared__ double sre[PB_THREADS], sim[PB_THREADS];
+  const int e = blockIdx.x, i = e / dc, j = e - i * dc;
+  const int c = cols[j];
+  double ar = 0.0, ai = 0.0;
+  if (c < 0 || c >= S) {
+    ar = __builtin_nan("");
+  } else {
+    const T2* u = U + (size_t)c * D;
+    const double2* w = W + (size_t)i * D;
+    for (int64_t k = threadIdx.x; k < D; k += PB_THREADS) {
+      const double2 x = w[k];
+      const double2 v = ld(u, (size_t)k);
+      ar += x.x * v.x + x.y * v.y;
+      ai += x.x * v.y - x.y * v.x;
+    }
+  }
+  sre[threadIdx.x] = ar;
+  sim[threadIdx.x] = ai;
+  __syncthreads();
+  for (int st = PB_THREADS / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sre[threadIdx.x] += sre[threadIdx.x + st];
+      sim[threadIdx.x] += sim[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[e] = make_double2(sre[0], sim[0]);
+}
+
+// cot[:, cols[j]] = -(tau/dc^2) sum_i T'_ij w_i
+template <typename T2>
+__global__ void cot_proj_kernel(T2* __restrict__ cot, int64_t D, int S, int dc,
+                                const int32_t* __restrict__ cols, const double2* __restrict__ W,
+                                const double2* __restrict__ Tp, double2 tau) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)D * dc) return;
+  const int j = (int)(e / (size_t)D);
+  const int64_t k = (int64_t)(e - (size_t)j * D);
+  const int c = cols[j];
+  if (c < 0 || c >= S) return;
+  double re = 0.0, im = 0.0;
+  for (int i = 0; i < dc; ++i) {
+    const double2 t = Tp[(size_t)i * dc + j], w = W[(size_t)i * D + k];
+    re += t.x * w.x - t.y * w.y;
+    im += t.x * w.y + t.y * w.x;
+  }
+  const double sc = -1.0 / ((double)dc * dc);
+  T2 v;
+  v.x = sc * (tau.x * re - tau.y * im);
+  v.y = sc * (tau.x * im + tau.y * re);
+  cot[(size_t)c * D + k] = v;
+}
+
+// cot[comp_rows[i], cols[j]] = -(tau/dc^2) T'_ij
+template <typename T2>
+__global__ void cot_rows_kernel(T2* __restrict__ cot, int64_t D, int S, int dc,
+                                const int64_t* __restrict__ rows, const int32_t* __restrict__ cols,
+                                const double2* __restrict__ Tp, double2 tau) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= dc * dc) return;
+  const int i = e / dc, j = e - i * dc;
+  if (rows[i] < 0 || rows[i] >= D || cols[j] < 0 || cols[j] >= S) return;
+  const double2 t = Tp[e];
+  const double sc = -1.0 / ((double)dc * dc);
+  T2 v;
+  v.x = sc * (tau.x * t.x - tau.y * t.y);
+  v.y = sc * (tau.x * t.y + tau.y * t.x);
+  cot[(size_t)cols[j] * D + rows[i]] = v;
+}
+
+using cmat = std::vector<cd>;
+
+// (x)_q mats[q] (qubit 0 most significant), dc x dc
+cmat kron_all(const std::vector<std::array<cd, 4>>& mats) {
+  cmat K(1, 1.0);
+  int n = 1;
+  for (const auto& m : mats) {
+    cmat R((size_t)4 * n * n);
+    for (int r = 0; r < n; ++r)
+      for (int c = 0; c < n; ++c)
+        for (int a = 0; a < 2; ++a)
+          for (int b = 0; b < 2; ++b)
+            R[(size_t)(r * 2 + a) * (2 * n) + (c * 2 + b)] = K[(size_t)r * n + c] * m[a * 2 + b];
+    K.swap(R);
+    n *= 2;
+  }
+  return K;
+}
+
+cmat matmul(const cmat& A, const cmat& B, int n) {
+  cmat C((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < n; ++k) {
+      const cd a = A[(size_t)i * n + k];
+      if (a == 0.0) continue;
+      for (int j = 0; j < n; ++j) C[(size_t)i * n + j] += a * B[(size_t)k * n + j];
+    }
+  return C;
+}
+
+cmat dagger(const cmat& A, int n) {
+  cmat B((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) B[(size_t)j * n + i] = std::conj(A[(size_t)i * n + j]);
+  return B;
+}
+
+cd trace(const cmat& A, int n) {
+  cd t = 0.0;
+  for (int i = 0; i < n; ++i) t += A[(size_t)i * n + i];
+  return t;
+}
+
+// X with Tr(a X) = Tr((I (x) .. a at qubit q .. (x) I) Y): the partial trace of
+// Y over every other qubit, X[r][c] = sum_rest Y[(r, rest), (c, rest)]
+std::array<cd, 4> partial_trace(const cmat& Y, int nq, int q) {
+  const int dc = 1 << nq, sh = nq - 1 - q;
+  std::array<cd, 4> X{0.0, 0.0, 0.0, 0.0};
+  for (int row = 0; row < dc; ++row) {
+    const int r = (row >> sh) & 1;
+    for (int c = 0; c < 2; ++c) {
+      const int col = (row & ~(1 << sh)) | (c << sh);
+      X[r * 2 + c] += Y[(size_t)row * dc + col];
+    }
+  }
+  return X;
+}
+
+// The unitary u maximising |Tr(u X)| for a 2 x 2 X: with X = P S Q^dag,
+// u = Q P^dag (then Tr(u X) = sum of the singular values).  The right
+// singular vectors come from the Hermitian X^dag X in closed form; a zero
+// singular value takes the unit vector orthogonal to the other.
+std::array<cd, 4> polar_opt(const std::array<cd, 4>& X) {
+  // H = X^dag X = [[p, q], [conj q, r]]
+  const double p = std::norm(X[0]) + std::norm(X[2]);
+  const double r = std::norm(X[1]) + std::norm(X[3]);
+  const cd q = std::conj(X[0]) * X[1] + std::conj(X[2]) * X[3];
+  const double m = 0.5 * (p + r), h = std::sqrt(0.25 * (p - r) * (p - r) + std::norm(q));
+  const double l1 = m + h;
+  // eigenvector of l1: (q, l1 - p) or (l1 - r, conj q), whichever is longer
+  cd v0, v1;
+  {
+    const cd a0 = q, a1 = l1 - p;
+    const cd b0 = l1 - r, b1 = std::conj(q);
+    const double na = std::norm(a0) + std::norm(a1), nb = std::norm(b0) + std::norm(b1);
+    if (na == 0.0 && nb == 0.0) {
+      v0 = 1.0;
+      v1 = 0.0;
+    } else if (na >= nb) {
+      v0 = a0 / std::sqrt(na);
+      v1 = a1 / std::sqrt(na);
+    } else {
+      v0 = b0 / std::sqrt(nb);
+      v1 = b1 / std::sqrt(nb);
+    }
+  }
+  const cd w0 = -std::conj(v1), w1 = std::conj(v0);   // the other right singular vector
+  // left singular vectors u_k = X v_k / s_k
+  cd u00 = X[0] * v0 + X[1] * v1, u10 = X[2] * v0 + X[3] * v1;
+  double s1 = std::sqrt(std::norm(u00) + std::norm(u10));
+  if (s1 == 0.0) return {1.0, 0.0, 0.0, 1.0};
+  u00 /= s1;
+  u10 /= s1;
+  cd u01 = X[0] * w0 + X[1] * w1, u11 = X[2] * w0 + X[3] * w1;
+  const double s2 = std::sqrt(std::norm(u01) + std::norm(u11));
+  if (s2 > 1e-300) {
+    u01 /= s2;
+    u11 /= s2;
+  } else {
+    u01 = -std::conj(u10);
+    u11 = std::conj(u00);
+  }
+  // u = Q P^dag, Q = [v w], P = [u_0 u_1]
+  std::array<cd, 4> out;
+  out[0] = v0 * std::conj(u00) + w0 * std::conj(u01);
+  out[1] = v0 * std::conj(u10) + w0 * std::conj(u11);
+  out[2] = v1 * std::conj(u00) + w1 * std::conj(u01);
+  out[3] = v1 * std::conj(u10) + w1 * std::conj(u11);
+  return out;
+}
+
+// tau(a, b) = Tr(T^dag (x)a M (x)b)
+cd su2_tau(const cmat& M, const cmat& Th, const std::vector<std::array<cd, 4>>& a,
+           const std::vector<std::array<cd, 4>>& b, int dc) {
+  return trace(matmul(Th, matmul(matmul(kron_all(a), M, dc), kron_all(b), dc), dc), dc);
+}
+
+}  // namespace
+
+// Arbitrary single-qubit compensation: coordinate ascent from identities over
+// a_0..a_{n-1} (after the gate), then b_0..b_{n-1} (before it), each set to the
+// polar optimum of its partial trace with the others fixed, until |tau| grows
+// by at most 1e-14 relative or after 500 sweeps.
+void su2_optimise(const cmat& M, const cmat& T, int nq, std::vector<std::array<cd, 4>>& a,
+                  std::vector<std::array<cd, 4>>& b, cd& tau) {
+  const int dc = 1 << nq;
+  const std::array<cd, 4> id{1.0, 0.0, 0.0, 1.0};
+  a.assign(nq, id);
+  b.assign(nq, id);
+  const cmat Th = dagger(T, dc);
+  double best = std::abs(su2_tau(M, Th, a, b, dc));
+  for (int sweep = 0; sweep < 500; ++sweep) {
+    for (int side = 0; side < 2; ++side)
+      for (int q = 0; q < nq; ++q) {
+        std::vector<std::array<cd, 4>> rest = side == 0 ? a : b;
+        rest[q] = id;
+        cmat Y;
+        if (side == 0)   // tau = Tr((x)a (M B T^dag))
+          Y = matmul(kron_all(rest), matmul(matmul(M, kron_all(b), dc), Th, dc), dc);
+        else             // tau = Tr((x)b (T^dag A M))
+          Y = matmul(kron_all(rest), matmul(Th, matmul(kron_all(a), M, dc), dc), dc);
+        (side == 0 ? a : b)[q] = polar_opt(partial_trace(Y, nq, q));
+      }
+    const double t = std::abs(su2_tau(M, Th, a, b, dc));
+    const bool done = t - best <= 1e-14 * std::max(1.0, t);
+    best = std::max(best, t);
+    if (done) break;
+  }
+  tau = su2_tau(M, Th, a, b, dc);
+}
+
+scp_status launch_fidelity_local(const void* U, int64_t D, int S, int prec, int nq,
+                                 const int32_t* cols, const void* W, const int64_t* rows,
+                                 const void* target, int mode, void* block, void* tau_out,
+                                 double* F_out, double* params_out, void* cot, hipStream_t s) {
+  const int dc = 1 << nq;
+  hipError_t e;
+  if (W != nullptr) {
+    if (prec == 0)
+      hipLaunchKernelGGL(proj_block_kernel<float2>, dim3(dc * dc), dim3(PB_THREADS), 0, s,
+                         (const float2*)U, D, S, dc, cols, (const double2*)W, (double2*)block);
+    else
+      hipLaunchKernelGGL(proj_block_kernel<double2>, dim3(dc * dc), dim3(PB_THREADS), 0, s,
+                         (const double2*)U, D, S, dc, cols, (const double2*)W, (double2*)block);
+    e = hipGetLastError();
+  } else {
+    e = prec == 0 ? run_zcomp_block<float2>(U, D, S, dc, rows, cols, block, s)
+                  : run_zcomp_block<double2>(U, D, S, dc, rows, cols, block, s);
+  }
+  if (e != hipSuccess) return fail(SCP_EHIP, std::string("compensated block: ") + hipGetErrorString(e));
+  cmat M((size_t)dc * dc), T((size_t)dc * dc);
+  HIPCHK(hipMemcpyAsync(M.data(), block, M.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(T.data(), target, T.size() * sizeof(cd), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (const cd& x : M)
+    if (!std::isfinite(x.real()) || !std::isfinite(x.imag()))
+      return fail(SCP_ENONFINITE, "the compensated block is not finite");
+  cmat Tp((size_t)dc * dc);
+  cd tau;
+  if (mode == 1) {
+    std::vector<cd> Wz((size_t)dc * dc);
+    for (size_t k = 0; k < Wz.size(); ++k) Wz[k] = std::conj(T[k]) * M[k];
+    std::vector<double> a, c;
+    zcomp_optimise(Wz, nq, a, c, tau);
+    for (int i = 0; i < dc; ++i)
+      for (int j = 0; j < dc; ++j) {
+        double th = 0.0, ch = 0.0;
+        for (int q = 0; q < nq; ++q) {
+          if ((i >> (nq - 1 - q)) & 1) th += a[q];
+          if ((j >> (nq - 1 - q)) & 1) ch += c[q];
+        }
+        Tp[(size_t)i * dc + j] = T[(size_t)i * dc + j] * std::polar(1.0, -(th + ch));
+      }
+    if (params_out)
+      for (int q = 0; q < nq; ++q) {
+        params_out[q] = a[q];
+        params_out[nq + q] = c[q];
+      }
+  } else {
+    std::vector<std::array<cd, 4>> a, b;
+    su2_optimise(M, T, nq, a, b, tau);
+    // T' = A^dag T B^dag
+    Tp = matmul(matmul(dagger(kron_all(a), dc), T, dc), dagger(kron_all(b), dc), dc);
+    if (params_out)
+      for (int q = 0; q < nq; ++q)
+        for (int k = 0; k < 4; ++k) {
+          params_out[(q * 4 + k) * 2] = a[q][k].real();
+          params_out[(q * 4 + k) * 2 + 1] = a[q][k].imag();
+          params_out[((nq + q) * 4 + k) * 2] = b[q][k].real();
+          params_out[((nq + q) * 4 + k) * 2 + 1] = b[q][k].imag();
+        }
+  }
+  *F_out = std::norm(tau) / ((double)dc * dc);
+  if (!std::isfinite(*F_out)) return fail(SCP_ENONFINITE, "fidelity is not finite");
+  const double2 t2 = make_double2(tau.real(), tau.imag());
+  double2* Tpd = (double2*)block + (size_t)dc * dc;
+  HIPCHK(hipMemcpyAsync(Tpd, Tp.data(), Tp.size() * sizeof(cd), hipMemcpyHostToDevice, s));
+  if (tau_out) HIPCHK(hipMemcpyAsync(tau_out, &t2, sizeof(double2), hipMemcpyHostToDevice, s));
+  if (cot) {
+    const size_t n = (size_t)D * S;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    if (prec == 0)
+      hipLaunchKernelGGL(fill_zero_kernel<float2>, dim3(blocks), dim3(256), 0, s, (float2*)cot, n);
+    else
+      hipLaunchKernelGGL(fill_zero_kernel<double2>, dim3(blocks), dim3(256), 0, s, (double2*)cot, n);
+    HIPCHK(hipGetLastError());
+    if (W != nullptr) {
+      const size_t m = (size_t)D * dc;
+      if (prec == 0)
+        hipLaunchKernelGGL(cot_proj_kernel<float2>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                           (float2*)cot, D, S, dc, cols, (const double2*)W, Tpd, t2);
+      else
+        hipLaunchKernelGGL(cot_proj_kernel<double2>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                           (double2*)cot, D, S, dc, cols, (const double2*)W, Tpd, t2);
+    } else {
+      if (prec == 0)
+        hipLaunchKernelGGL(cot_rows_kernel<float2>, dim3((dc * dc + 255) / 256), dim3(256), 0, s,
+                           (float2*)cot, D, S, dc, rows, cols, Tpd, t2);
+      else
+        hipLaunchKernelGGL(cot_rows_kernel<double2>, dim3((dc * dc + 255) / 256), dim3(256), 0, s,
+                           (double2*)cot, D, S, dc, rows, cols, Tpd, t2);
+    }
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipStreamSynchronize(s));
   return SCP_OK;
 }
 

@@ -243,6 +243,10 @@ scp_status launch_fidelity(const void* U, int64_t D, int S, int prec, int dc, co
 scp_status launch_fidelity_states(const void* U, int64_t D, int S, int prec, int nt,
                                   const int32_t* cols, const void* phi, void* tau, void* cot,
                                   hipStream_t s);
+scp_status launch_fidelity_local(const void* U, int64_t D, int S, int prec, int nq,
+                                 const int32_t* cols, const void* W, const int64_t* rows,
+                                 const void* target, int mode, void* block, void* tau_out,
+                                 double* F_out, double* params_out, void* cot, hipStream_t s);
 scp_status launch_plain64(scp_system* sys, const double2* psi0, double2* psiT, void* work, int S,
                           hipStream_t s);
 scp_status trotter_check(const scp_system* sys, int order);

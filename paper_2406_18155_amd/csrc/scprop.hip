@@ -1094,6 +1094,22 @@ scp_status scp_fidelity_states(const void* U, int64_t D, int32_t S, int32_t prec
   return SCP_OK;
 }
 
+scp_status scp_fidelity_local(const void* U, int64_t D, int32_t S, int32_t precision,
+                              int32_t n_qubits, const int32_t* cols, const void* W,
+                              const int64_t* comp_rows, const void* target, int32_t mode,
+                              void* block_out, void* tau_out, double* F_out, double* params_out,
+                              void* cotangent, void* stream) {
+  g_err.clear();
+  if (!U || !cols || !target || !block_out || !F_out || (!W && !comp_rows))
+    return fail(SCP_EINVAL, "null argument");
+  if (D < 1 || S < 1 || n_qubits < 1 || n_qubits > 6 || (precision != 0 && precision != 1))
+    return fail(SCP_EINVAL, "bad sizes (n_qubits must be 1..6)");
+  if (mode != 1 && mode != 2) return fail(SCP_EINVAL, "mode must be 1 (Z phases) or 2 (SU(2))");
+  return launch_fidelity_local(U, D, S, precision, n_qubits, cols, W, comp_rows, target, mode,
+                               block_out, tau_out, F_out, params_out, cotangent,
+                               (hipStream_t)stream);
+}
+
 scp_status scp_fidelity_zcomp(const void* U, int64_t D, int32_t S, int32_t precision,
                               int32_t n_qubits, const int64_t* comp_rows, const int32_t* comp_cols,
                               const void* target, void* block_out, void* tau_out, double* F_out,

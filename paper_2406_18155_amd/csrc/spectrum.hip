@@ -161,6 +161,71 @@ using namespace scp;
 
 extern "C" {
 
+scp_status scp_eigenbasis_states(const scp_system* sys, int32_t n, const int64_t* labels,
+                                 const double* target, double T, int32_t precision,
+                                 void* psi0_out, void* phi_out, void* W_out, double* E_out,
+                                 void* stream) {
+  set_error("");
+  if (!sys || !labels || !psi0_out || n < 1 || (precision != 0 && precision != 1))
+    return fail(SCP_EINVAL, "bad argument");
+  if (phi_out && !target) return fail(SCP_EINVAL, "phi_out needs the target");
+  const int64_t D = sys->D;
+  for (int j = 0; j < n; ++j)
+    if (labels[j] < 0 || labels[j] >= D) return fail(SCP_EINVAL, "label out of range");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> w, V;
+  scp_status s = spectrum(sys, st, w, V);
+  if (s != SCP_OK) return s;
+  const int nm = sys->n_modes, d = sys->d;
+  // H_f on the product basis
+  std::vector<double> f((size_t)D, 0.0);
+  {
+    std::vector<int> a(nm);
+    for (int64_t k = 0; k < D; ++k) {
+      digits(k, nm, d, a.data());
+      for (int m = 0; m < nm; ++m) f[k] += sys->modes[m].frame[a[m]];
+    }
+  }
+  // dressed state of each label: the eigenvector of largest overlap, <k|v> > 0
+  std::vector<cplx> Vc((size_t)D * n), Wc((size_t)D * n);
+  std::vector<double> Ec(n);
+  for (int j = 0; j < n; ++j) {
+    const int v = label(V, D, labels[j]);
+    const double sgn = V[(size_t)labels[j] * D + v] < 0.0 ? -1.0 : 1.0;
+    Ec[j] = w[v];
+    for (int64_t k = 0; k < D; ++k) {
+      const double x = sgn * V[(size_t)k * D + v];
+      Vc[(size_t)j * D + k] = x;
+      Wc[(size_t)j * D + k] = std::polar(x, (f[k] - Ec[j]) * T);
+    }
+  }
+  if (E_out)
+    for (int j = 0; j < n; ++j) E_out[j] = Ec[j];
+  if (precision == 0) {
+    std::vector<float2> h((size_t)D * n);
+    for (size_t i = 0; i < h.size(); ++i) h[i] = make_float2((float)Vc[i].real(), 0.f);
+    HIPCHK(hipMemcpyAsync(psi0_out, h.data(), h.size() * sizeof(float2), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+  } else {
+    HIPCHK(hipMemcpyAsync(psi0_out, Vc.data(), Vc.size() * sizeof(cplx), hipMemcpyHostToDevice, st));
+  }
+  if (W_out)
+    HIPCHK(hipMemcpyAsync(W_out, Wc.data(), Wc.size() * sizeof(cplx), hipMemcpyHostToDevice, st));
+  std::vector<cplx> phi;
+  if (phi_out) {
+    // phi_j = sum_i T_ij w_i (target row-major, (re, im) pairs)
+    phi.assign((size_t)D * n, 0.0);
+    for (int j = 0; j < n; ++j)
+      for (int i = 0; i < n; ++i) {
+        const cplx t(target[2 * ((size_t)i * n + j)], target[2 * ((size_t)i * n + j) + 1]);
+        for (int64_t k = 0; k < D; ++k) phi[(size_t)j * D + k] += t * Wc[(size_t)i * D + k];
+      }
+    HIPCHK(hipMemcpyAsync(phi_out, phi.data(), phi.size() * sizeof(cplx), hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  return SCP_OK;
+}
+
 scp_status scp_energy_tensor(const scp_system* sys, double* E_out, void* stream) {
   set_error("");
   if (!sys || !E_out) return fail(SCP_EINVAL, "null argument");
