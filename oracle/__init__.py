@@ -3,7 +3,8 @@
 Plain, slow, obviously-correct numpy implementation of what the HIP library
 computes: single-mode Hamiltonians and their dressed truncation, the
 Kronecker-structured generator, fixed-step RK4 in the interaction picture,
-the gate fidelity and its discrete adjoint gradient.  It shares no code with
+the gate fidelity and its discrete adjoint gradient, and (lindblad.py) the
+open-system master equation with its channel fidelity and gradient.  It shares no code with
 the GPU path; only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s
 ``cpu_baseline`` leg may import it.  Nothing in the product path calls it.
 

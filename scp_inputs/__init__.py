@@ -203,6 +203,46 @@ def config5(seed_offset: int = 0):
     return _finish(s, [3] * 8, target=cz_target(8, (0, 1)))
 
 
+def open_rates(rng, n_modes, t1_us=(20.0, 60.0), tphi_us=(20.0, 60.0)):
+    """Per-mode relaxation and pure-dephasing rates (1/ns) from T1, T_phi in us."""
+    out = []
+    for _ in range(n_modes):
+        t1 = _u(rng, *t1_us) * 1e3
+        tp = _u(rng, *tphi_us) * 1e3
+        out.append((1.0 / t1, 1.0 / tp))
+    return out
+
+
+def with_rates(system, rates):
+    """Copy of ``system`` whose modes carry ``gamma1`` / ``gammaphi`` (1/ns)."""
+    s = dict(system)
+    s["modes"] = [dict(m, gamma1=float(g1), gammaphi=float(gp))
+                  for m, (g1, gp) in zip(system["modes"], rates)]
+    return s
+
+
+def open_chain(seed_offset: int = 0, d: int = 3, n_steps: int = 5000):
+    """Open-system workload: config 2's 4-fluxonium chain (n(x)n and phi(x)phi
+    per edge, 2 phi-channels with 20-Gaussian envelopes, T = 100 ns) truncated
+    to ``d`` levels per mode, CZ target on modes 0 and 1, each mode with
+    T1, T_phi ~ U[20, 60] us.  The channel acts on the 16 computational
+    states, so 256 matrix units are propagated (D^2 = d^8 each)."""
+    rng = rng_for(2, seed_offset)
+    s = fluxonium_chain(rng, 4, d, 100.0, n_steps)
+    s = _finish(s, [d] * 4, target=cz_target(4))
+    return with_rates(s, open_rates(rng_for(20, seed_offset), 4))
+
+
+def open_pair(seed_offset: int = 0, d: int = 4, n_steps: int = 2000):
+    """Open-system small case: config 1's two coupled transmons (d = 4, T = 40 ns,
+    Gaussian drive on mode 0) with its 4 computational states as the channel
+    input (16 matrix units), CZ target, T1, T_phi ~ U[20, 60] us."""
+    s = config1(seed_offset)
+    s = dict(s, n_steps=int(n_steps))
+    s = _finish(s, [d, d], target=cz_target(2))
+    return with_rates(s, open_rates(rng_for(21, seed_offset), 2))
+
+
 def sampled_columns(n_cols: int, n_sample: int = 8, seed: int = BASE_SEED + 5):
     """Seeded sample of propagated-column positions, always containing the
     first (|0...0>) and the last (|1...1>) computational column."""
