@@ -20,13 +20,15 @@ kernel (about 60 % of a step); the forward and the recompute kernels follow in
 launch stream around every launch (scp_system_set_timing).
 
 Beside the timed steps (not part of ``value``): one forward of the same
-workload on the plain complex FP64 GPU path (the speedup denominator), and a
-serving replay of the first requests of the mixed request stream (2-6 modes,
+workload on the plain complex FP64 GPU path (the speedup denominator), the
+open-system (Lindblad) propagation of a 4-fluxonium chain's 256 computational
+matrix units (``open_system``), and a serving replay of the first requests of the mixed request stream (2-6 modes,
 d in {3,4,5}, T in [20,200] ns, half with gradients): saturated throughput,
 then Poisson arrivals at 0.5x and 0.9x that throughput, with p50/p99 latency.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--serve-requests R] [--no-plain64]
+                    [--serve-requests R] [--no-plain64] [--no-lindblad]
+    python bench.py --lindblad | --trotter | --configs | --cpu-protocol
 """
 from __future__ import annotations
 
@@ -384,6 +386,73 @@ def static_spectrum_line(scp, np):
             "note": "the oracle at d=5 gives 12.250 MHz (pinned); d=4 truncates the chain"}
 
 
+def lindblad_macs(desc):
+    """Complex multiply-adds per density-matrix element and RK4 stage of the
+    open-system kernel: the static diagonal (1), one relaxation jump per mode
+    where both digits can be raised ((d-1)^2/d^2 of the elements), per driven
+    mode a d-term contraction on the ket and on the bra digits, per coupled
+    mode pair a d^2-term contraction on each side."""
+    d = desc["modes"][0]["trunc"]
+    M = len(desc["modes"])
+    driven = {dr["mode"] for dr in desc["drives"]}
+    pairs = {tuple(sorted((c["i"], c["j"]))) for c in desc["couplings"]}
+    relax = sum(1 for m in desc["modes"] if m.get("gamma1", 0.0) > 0)
+    return 1 + relax * (d - 1) ** 2 / d ** 2 + len(driven) * 2 * d + len(pairs) * 2 * d * d
+
+
+def lindblad_line(scp, si, torch, np, reps=3):
+    """Open-system propagation of the 4-fluxonium chain truncated to d = 3
+    (D = 81, the vectorised density matrix has D^2 = 6561 entries), its 256
+    computational matrix units, T = 100 ns, 5000 RK4 steps, T1/T_phi per mode:
+    call time from HIP events on the launch stream, the channel's average gate
+    fidelity, the algorithmic FP32 rate against the vector peak (8 FLOP per
+    complex multiply-add of ``lindblad_macs``), and the oracle on a bounded
+    sample (one matrix unit, 5 steps)."""
+    from oracle import lindblad as olb
+    from oracle.system import OracleSystem
+    desc = si.open_chain()
+    g = scp.System(desc)
+    st = [desc["columns"][c] for c in desc["comp_cols"]]
+    S = len(st) ** 2
+    DD = g.D * g.D
+    N = desc["n_steps"]
+    rho0 = scp.matrix_units(g.D, st)
+    ws = torch.empty(g.lindblad_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    rhoT = g.propagate_lindblad(rho0, workspace=ws)
+    stream = torch.cuda.current_stream()
+    ms = []
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        g.propagate_lindblad(rho0, rhoT=rhoT, workspace=ws)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    t = min(ms)
+    F, _ = scp.fidelity_channel(rhoT, scp.ChannelTarget(desc["comp_rows"], desc["target"]))
+    g.close()
+    flop = 8.0 * lindblad_macs(desc) * DD * S * 4 * N
+    o = OracleSystem(desc)
+    t0 = time.perf_counter()
+    olb.propagate(o, olb.matrix_units(o.D, st)[:1], n_steps=5)
+    dt = time.perf_counter() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"config": "open system: 4-fluxonium chain d=3 (D=81, D^2=6561), 256 matrix units of "
+                      "the 16 computational states, T=100 ns, 5000 RK4 steps, T1/T_phi ~ U[20,60] us",
+            "call_ms": t, "F_avg": F,
+            "steps_dim2_per_s": N * DD * S / (t * 1e-3),
+            "roofline": {"bound": "alu", "achieved": flop / (t * 1e-3) / 1e12, "peak": 157.3,
+                         "unit": "TFLOP/s", "frac": flop / (t * 1e-3) / PEAK_FP32,
+                         "traffic": None,
+                         "algorithmic_flop": flop},
+            "cpu_oracle": {"steps_dim2_per_s": 5 * DD / dt, "cores": cores,
+                           "sample": "1 matrix unit, 5 of 5000 steps, dense numpy FP64"}}
+
+
 def sampled_desc(si, np):
     desc = si.config5()
     samp = si.sampled_columns(len(desc["columns"]), 8)
@@ -512,6 +581,9 @@ def main():
     ap.add_argument("--frame", choices=("real", "complex"), default="real",
                     help="generator evaluation of the timed steps (the real frame where "
                          "the system allows it, or the rotated complex operators)")
+    ap.add_argument("--lindblad", action="store_true",
+                    help="only time the open-system (Lindblad) propagation (one JSON line) and exit")
+    ap.add_argument("--no-lindblad", action="store_true")
     ap.add_argument("--cpu-protocol", action="store_true",
                     help="only run the oracle's full CPU timing protocol (long) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -545,6 +617,9 @@ def main():
     if args.trotter:
         for line in trotter_lines(scp, si, torch, np, tuple(args.trotter_orders.split(","))):
             print(json.dumps(line), flush=True)
+        return
+    if args.lindblad:
+        print(json.dumps(lindblad_line(scp, si, torch, np)), flush=True)
         return
     if args.configs:
         for line in other_configs(scp, si, torch, np):
@@ -731,6 +806,8 @@ def main():
                              "path": "complex FP64, one launch per local term"}
     if args.serve_requests > 0:
         out["serving"] = serving_leg(scp, si, torch, np, args.serve_requests)
+    if not args.no_lindblad:
+        out["open_system"] = lindblad_line(scp, si, torch, np)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(si, np)
     print(json.dumps(out))

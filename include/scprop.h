@@ -490,6 +490,59 @@ scp_status scp_server_result(scp_server* sv, int64_t id, int32_t* state, double*
 
 void scp_server_destroy(scp_server* sv);
 
+/* ------------------------------------------------------------------------
+ * Open systems: the vectorised Lindblad master equation (the superoperator
+ * of App. D's closing remark on the average fidelity; the LindbladObj
+ * component of Sec. 2).
+ *
+ * A density matrix rho (D x D) evolves in the interaction picture of the
+ * system's frame under
+ *   d rho/dt = -i [V(t), rho] + sum_m gamma1_m D[a_m(t)] rho
+ *                             + 2 gammaphi_m D[n_m] rho,
+ * D[L] rho = L rho L^dag - {L^dag L, rho}/2, V(t) the generator of
+ * scp_propagate, a_m = sum_k sqrt(k) |k-1><k| and n_m = diag(0..d-1) in mode
+ * m's dressed basis (a_m rotated into the frame), so an idle mode's excited
+ * population decays as exp(-gamma1 t) and its 0-1 coherence as
+ * exp(-gammaphi t).  Classical RK4 on the system's step grid, complex FP32
+ * with a compensated (two-word) state, one workgroup per matrix with the
+ * matrix resident in LDS: D^2 <= 6561 (d = 2: N <= 5, d = 3: N <= 4,
+ * d = 4: N <= 3, d = 5: N <= 2), every mode of one dimension.
+ * ------------------------------------------------------------------------ */
+
+/* Device workspace bytes of scp_propagate_lindblad (a small argument block
+ * and the relaxation phases of every half-step). */
+scp_status scp_lindblad_workspace_size(const scp_system* sys, size_t* bytes);
+
+/* Propagate n_cols density matrices rho0 (device, complex64, n_cols x D x D,
+ * each row-major: element (A, B) at A * D + B, A the ket and B the bra
+ * index in the system's basis order) over the system's steps into rhoT (same
+ * layout, must not alias rho0).  gamma1, gammaphi: host, n_modes rates in
+ * 1/ns each (nullable: zero), finite and >= 0.  workspace: device,
+ * scp_lindblad_workspace_size bytes, caller-owned.  Asynchronous on stream.
+ * Errors: SCP_EINVAL (unsupported shape, bad rates, small workspace), SCP_EHIP. */
+scp_status scp_propagate_lindblad(scp_system* sys, const double* gamma1, const double* gammaphi,
+                                  int32_t n_cols, void* workspace, size_t workspace_bytes,
+                                  const void* rho0, void* rhoT, void* stream);
+
+/* Average gate fidelity of a channel on the computational subspace (App. D,
+ * eq. for the average fidelity, with a unitary operator basis normalised to
+ * tr(U_j^dag U_k) = d_c delta_jk): rhoT (device, complex64, d_c^2 x D x D)
+ * holds the images of the matrix units |s_a><s_b| of the d_c input states
+ * in the order a * d_c + b;
+ *   ov = sum_ab sum_ij conj(T_ia) T_jb rhoT_ab[comp_rows[i], comp_rows[j]]
+ * is accumulated in FP64 by one workgroup in a fixed order and
+ * F = (Re ov + d_c) / (d_c (d_c + 1)); for a unitary channel W this is
+ * (|Tr(T^dag W)|^2 + d_c) / (d_c (d_c + 1)).  comp_rows (int64, d_c), target
+ * (complex128, d_c x d_c row-major T[i][a]) and overlap_out (complex128, 1)
+ * are device pointers.  cotangent (nullable, complex64, as rhoT) receives the
+ * costate of L = 1 - F, -T_ia conj(T_jb) / (2 d_c (d_c + 1)) at
+ * (a * d_c + b, comp_rows[i], comp_rows[j]) and zero elsewhere.  F_out (host,
+ * nullable) synchronises the stream.  Errors: SCP_EINVAL, SCP_ENONFINITE,
+ * SCP_EHIP. */
+scp_status scp_fidelity_channel(const void* rhoT, int64_t D, int32_t d_c, const int64_t* comp_rows,
+                                const void* target, void* overlap_out, void* cotangent,
+                                double* F_out, void* stream);
+
 /* Message of the last failing call on this thread ("" if none); valid until
  * the next call on this thread. */
 const char* scp_last_error(void);

@@ -8,6 +8,7 @@ from ._lib import ScpError, lib  # noqa: F401
 
 lib()  # fail loudly if the HIP library is missing
 
-from .api import (StateTarget, System, Target, basis_columns, fidelity,  # noqa: E402,F401
-                  fidelity_local, fidelity_states, fidelity_zcomp)
+from .api import (ChannelTarget, StateTarget, System, Target, basis_columns,  # noqa: E402,F401
+                  fidelity, fidelity_channel, fidelity_local, fidelity_states, fidelity_zcomp,
+                  matrix_units)
 from . import autograd  # noqa: E402,F401

@@ -224,6 +224,38 @@ class System:
                                                   _stream_ptr(stream)))
         return np.array(g[: self.n_params])
 
+    # -- open systems (vectorised Lindblad equation) --------------------------
+    def rates(self):
+        """Per-mode (gamma1, gammaphi) of the descriptor (1/ns; absent: 0)."""
+        g1 = [float(m.get("gamma1", 0.0)) for m in self.desc["modes"]]
+        gp = [float(m.get("gammaphi", 0.0)) for m in self.desc["modes"]]
+        return g1, gp
+
+    def lindblad_workspace_bytes(self):
+        n = C.c_size_t()
+        check(lib().scp_lindblad_workspace_size(self.handle, C.byref(n)))
+        return n.value
+
+    def propagate_lindblad(self, rho0, rhoT=None, rates=None, workspace=None, stream=None):
+        """rho_I(T) of the density matrices rho0 (S, D, D) complex64 under the
+        Lindblad equation with per-mode (gamma1, gammaphi) ``rates`` (default:
+        the descriptor's)."""
+        assert rho0.dtype == torch.complex64 and rho0.is_contiguous()
+        assert rho0.shape[1:] == (self.D, self.D)
+        if rhoT is None:
+            rhoT = torch.empty_like(rho0)
+        if workspace is None:
+            workspace = torch.empty(self.lindblad_workspace_bytes(), dtype=torch.uint8,
+                                    device=rho0.device)
+        g1, gp = self.rates() if rates is None else rates
+        n = self.n_modes
+        a1 = (C.c_double * n)(*[float(v) for v in g1])
+        ap = (C.c_double * n)(*[float(v) for v in gp])
+        check(lib().scp_propagate_lindblad(self.handle, a1, ap, rho0.shape[0], _ptr(workspace),
+                                           workspace.numel() * workspace.element_size(),
+                                           _ptr(rho0), _ptr(rhoT), _stream_ptr(stream)))
+        return rhoT
+
     def opts(self, n_cols, precision=0, ckpt_every=0, with_ckpt=0):
         o = SolveOpts()
         o.n_cols, o.precision, o.ckpt_every, o.with_ckpt = int(n_cols), int(precision), \
@@ -344,6 +376,40 @@ def fidelity_states(U, tgt: StateTarget, cotangent=None, stream=None, sync=True)
                                     None if cotangent is None else _ptr(cotangent),
                                     C.byref(F) if sync else None, _stream_ptr(stream)))
     return (F.value if sync else None), tgt.tau
+
+
+class ChannelTarget:
+    """Device-resident inputs of the channel fidelity: the computational rows
+    and the target (d_c x d_c)."""
+
+    def __init__(self, comp_rows, target, device="cuda"):
+        self.dc = len(comp_rows)
+        self.rows = torch.tensor(list(comp_rows), dtype=torch.int64, device=device)
+        self.target = torch.tensor(np.asarray(target, dtype=np.complex128), device=device).contiguous()
+        self.ov = torch.zeros(1, dtype=torch.complex128, device=device)
+
+
+def matrix_units(D, states, dtype=torch.complex64, device="cuda"):
+    """The d_c^2 input matrices |s_a><s_b| (order a d_c + b), (d_c^2, D, D)."""
+    dc = len(states)
+    out = torch.zeros(dc * dc, D, D, dtype=dtype, device=device)
+    for a in range(dc):
+        for b in range(dc):
+            out[a * dc + b, states[a], states[b]] = 1.0
+    return out
+
+
+def fidelity_channel(rhoT, tgt: ChannelTarget, cotangent=None, stream=None, sync=True):
+    """Average gate fidelity (Re ov + d_c) / (d_c (d_c + 1)) of the channel whose
+    matrix-unit images are rhoT (d_c^2, D, D); fills ``cotangent`` if given."""
+    assert rhoT.dtype == torch.complex64 and rhoT.is_contiguous()
+    S, D, D2 = rhoT.shape
+    assert D == D2 and S == tgt.dc * tgt.dc
+    F = C.c_double()
+    check(lib().scp_fidelity_channel(_ptr(rhoT), D, tgt.dc, _ptr(tgt.rows), _ptr(tgt.target),
+                                     _ptr(tgt.ov), None if cotangent is None else _ptr(cotangent),
+                                     C.byref(F) if sync else None, _stream_ptr(stream)))
+    return (F.value if sync else None), tgt.ov
 
 
 def fidelity_local(U, cols, target, n_qubits, mode="su2", W=None, comp_rows=None,

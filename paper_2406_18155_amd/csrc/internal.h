@@ -257,5 +257,12 @@ scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, c
                                   const double2* cot, double* grad, hipStream_t st);
 scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const double2* psi0,
                           double2* psiT, hipStream_t st);
+size_t lindblad_workspace_bytes(const scp_system* sys);
+scp_status lindblad_check(const scp_system* sys);
+scp_status launch_lindblad(scp_system* sys, const double* gamma1, const double* gammaphi, int S,
+                           void* ws, size_t ws_bytes, const float2* rho0, float2* rhoT,
+                           hipStream_t st);
+scp_status launch_fidelity_channel(const void* rhoT, int64_t D, int dc, const int64_t* rows,
+                                   const void* target, void* ov, void* cot, hipStream_t st);
 
 }  // namespace scp

@@ -1025,6 +1025,43 @@ scp_status scp_propagate_trotter(scp_system* sys, int32_t order, int32_t n_cols,
                         (hipStream_t)stream);
 }
 
+scp_status scp_lindblad_workspace_size(const scp_system* sys, size_t* bytes) {
+  g_err.clear();
+  if (!sys || !bytes) return fail(SCP_EINVAL, "null argument");
+  const scp_status st = lindblad_check(sys);
+  if (st != SCP_OK) return st;
+  *bytes = lindblad_workspace_bytes(sys);
+  return SCP_OK;
+}
+
+scp_status scp_propagate_lindblad(scp_system* sys, const double* gamma1, const double* gammaphi,
+                                  int32_t n_cols, void* workspace, size_t workspace_bytes,
+                                  const void* rho0, void* rhoT, void* stream) {
+  g_err.clear();
+  if (!sys || !workspace || !rho0 || !rhoT) return fail(SCP_EINVAL, "null argument");
+  if (n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  if (rho0 == rhoT) return fail(SCP_EINVAL, "rhoT must not alias rho0");
+  return launch_lindblad(sys, gamma1, gammaphi, n_cols, workspace, workspace_bytes,
+                         (const float2*)rho0, (float2*)rhoT, (hipStream_t)stream);
+}
+
+scp_status scp_fidelity_channel(const void* rhoT, int64_t D, int32_t d_c, const int64_t* comp_rows,
+                                const void* target, void* overlap_out, void* cotangent,
+                                double* F_out, void* stream) {
+  g_err.clear();
+  if (!rhoT || !comp_rows || !target || !overlap_out) return fail(SCP_EINVAL, "null argument");
+  if (D < 1 || d_c < 1 || d_c > D) return fail(SCP_EINVAL, "need 1 <= d_c <= D");
+  hipStream_t st = (hipStream_t)stream;
+  scp_status s = launch_fidelity_channel(rhoT, D, d_c, comp_rows, target, overlap_out, cotangent, st);
+  if (s != SCP_OK || !F_out) return s;
+  double ov[2];
+  HIPCHK(hipMemcpyAsync(ov, overlap_out, sizeof(ov), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (!std::isfinite(ov[0]) || !std::isfinite(ov[1])) return fail(SCP_ENONFINITE, "non-finite overlap");
+  *F_out = (ov[0] + d_c) / ((double)d_c * (d_c + 1.0));
+  return SCP_OK;
+}
+
 scp_status scp_trotter_adjoint_workspace_size(const scp_system* sys, int32_t order, int32_t n_cols,
                                               size_t* bytes) {
   g_err.clear();

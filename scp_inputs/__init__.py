@@ -258,6 +258,21 @@ def random_states(D: int, S: int, seed: int = BASE_SEED + 55):
     return rng.normal(size=(D, S)) + 1j * rng.normal(size=(D, S))
 
 
+def random_density_matrices(D: int, S: int, rank: int = 3, seed: int = BASE_SEED + 66):
+    """Seeded mixed states (S, D, D): each a random convex mix of ``rank``
+    normalised complex Gaussian vectors (Hermitian, positive, trace 1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.zeros((S, D, D), dtype=np.complex128)
+    for s in range(S):
+        w = rng.uniform(0.1, 1.0, rank)
+        w = w / w.sum()
+        for k in range(rank):
+            v = rng.normal(size=D) + 1j * rng.normal(size=D)
+            v = v / np.linalg.norm(v)
+            out[s] += w[k] * np.outer(v, v.conj())
+    return out
+
+
 def serving_request(r: int):
     """Request ``r`` of the serving stream: family uniform over {transmon chain,
     transmon ring (>= 3 modes), fluxonium chain}; 2..6 modes; d in {3,4,5}

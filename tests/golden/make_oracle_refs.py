@@ -4,6 +4,8 @@
     python tests/golden/make_oracle_refs.py config5    # config5_sampled_oracle.json
     python tests/golden/make_oracle_refs.py config5_state
         # config5_state_target.npy + config5_state_oracle.json
+    python tests/golden/make_oracle_refs.py lindblad_chain
+        # lindblad_chain_oracle.json
 
 config3_oracle.json: loss, fidelity and the full gradient of the config-3
 workload (4-fluxonium chain, CZ(q0,q1) x I x I target, 5000 RK4 steps),
@@ -114,3 +116,36 @@ def config5_state():
 
 if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "config5_state":
     config5_state()
+
+
+LINDBLAD_SAMPLES = [(0, 0), (5, 5), (3, 12), (15, 9)]
+
+
+def lindblad_chain():
+    """Open-system workload (4-fluxonium chain truncated to d = 3, T = 100 ns,
+    5000 RK4 steps, T1 and T_phi per mode): the oracle's images of four
+    sampled matrix units |s_a><s_b|, each stored as its computational 16 x 16
+    block plus 64 seeded entries elsewhere (about five minutes of CPU time)."""
+    from oracle import lindblad as lb
+    desc = si.open_chain()
+    sys_ = OracleSystem(desc)
+    st = lb.input_states(desc)
+    rho0 = np.stack([lb.matrix_units(sys_.D, st)[a * len(st) + b] for a, b in LINDBLAD_SAMPLES])
+    R = lb.propagate(sys_, rho0)
+    rng = np.random.Generator(np.random.PCG64(si.BASE_SEED + 77))
+    idx = rng.integers(0, sys_.D, size=(64, 2))
+    rows = desc["comp_rows"]
+    out = {"workload": "open chain: 4 fluxonium chain d=3, T=100 ns, 5000 RK4 steps, "
+                       "T1/T_phi per mode, 4 sampled matrix units",
+           "generator": "tests/golden/make_oracle_refs.py lindblad_chain (oracle only)",
+           "samples": [list(p) for p in LINDBLAD_SAMPLES], "entries": idx.tolist(),
+           "block_re": [R[k][np.ix_(rows, rows)].real.tolist() for k in range(len(R))],
+           "block_im": [R[k][np.ix_(rows, rows)].imag.tolist() for k in range(len(R))],
+           "entries_re": [[float(R[k][i, j].real) for i, j in idx] for k in range(len(R))],
+           "entries_im": [[float(R[k][i, j].imag) for i, j in idx] for k in range(len(R))]}
+    with open(os.path.join(HERE, "lindblad_chain_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "lindblad_chain":
+    lindblad_chain()
