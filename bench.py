@@ -85,13 +85,22 @@ def kernel_flops(desc, S):
     return {"forward": per * c_fwd, "recompute": per * c_fwd, "reverse": per * (c_fwd + sens)}
 
 
-def kernel_sources_sha():
-    """SHA-256 over the HIP/C++ sources of the library (sorted by name)."""
+# Source files that define each profiled kernel (its own file, the shared
+# device building blocks and the structures it reads).
+KERNEL_SOURCES = {
+    "rk4": ("rk4.hip", "kernel_common.h", "internal.h"),
+    "recompute": ("rk4.hip", "kernel_common.h", "internal.h"),
+    "adjoint": ("adjoint.hip", "kernel_common.h", "internal.h"),
+    "lindblad": ("lindblad.hip", "kernel_common.h", "internal.h"),
+}
+
+
+def kernel_sources_sha(kind):
+    """SHA-256 over the sources of one kernel family (names and contents, in order)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2406_18155_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(os.path.basename(f).encode())
-            h.update(open(f, "rb").read())
+    for name in KERNEL_SOURCES[kind]:
+        h.update(name.encode())
+        h.update(open(os.path.join(ROOT, "paper_2406_18155_amd", "csrc", name), "rb").read())
     return h.hexdigest()
 
 
@@ -107,7 +116,7 @@ def profile_value(fname, key):
         if ":" in line:
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("sources_sha256") != kernel_sources_sha():
+    if kv.get("sources_sha256") != kernel_sources_sha(fname.split("_", 1)[0]):
         return None
     try:
         return float(kv[key])
@@ -432,6 +441,7 @@ def lindblad_line(scp, si, torch, np, reps=3):
     F, _ = scp.fidelity_channel(rhoT, scp.ChannelTarget(desc["comp_rows"], desc["target"]))
     g.close()
     flop = 8.0 * lindblad_macs(desc) * DD * S * 4 * N
+    ex = executed_flop("lindblad_open_chain_d3")
     o = OracleSystem(desc)
     t0 = time.perf_counter()
     olb.propagate(o, olb.matrix_units(o.D, st)[:1], n_steps=5)
@@ -447,8 +457,10 @@ def lindblad_line(scp, si, torch, np, reps=3):
             "steps_dim2_per_s": N * DD * S / (t * 1e-3),
             "roofline": {"bound": "alu", "achieved": flop / (t * 1e-3) / 1e12, "peak": 157.3,
                          "unit": "TFLOP/s", "frac": flop / (t * 1e-3) / PEAK_FP32,
-                         "traffic": None,
-                         "algorithmic_flop": flop},
+                         "traffic": measured_traffic("lindblad_open_chain_d3"),
+                         "kernel": "lb_rk4_kernel<3,4>", "algorithmic_flop": flop,
+                         "executed_tflops": None if ex is None else ex / (t * 1e-3) / 1e12,
+                         "executed_frac": None if ex is None else ex / (t * 1e-3) / PEAK_FP32},
             "cpu_oracle": {"steps_dim2_per_s": 5 * DD / dt, "cores": cores,
                            "sample": "1 matrix unit, 5 of 5000 steps, dense numpy FP64"}}
 
