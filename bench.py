@@ -91,7 +91,8 @@ KERNEL_SOURCES = {
     "rk4": ("rk4.hip", "kernel_common.h", "internal.h"),
     "recompute": ("rk4.hip", "kernel_common.h", "internal.h"),
     "adjoint": ("adjoint.hip", "kernel_common.h", "internal.h"),
-    "lindblad": ("lindblad.hip", "kernel_common.h", "internal.h"),
+    "lindblad": ("gather.hip", "kernel_common.h", "internal.h"),
+    "gather": ("gather.hip", "kernel_common.h", "internal.h"),
 }
 
 
@@ -230,11 +231,23 @@ def other_configs(scp, si, torch, np):
             res.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
         fwd_ms = min(r[0] for r in res)
         grad_ms = min(r[1] for r in res)
+        # forward alone (no checkpoints: the gather engine where the system
+        # has few columns of a small device)
+        fo = []
+        for rep in range(3):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record(stream)
+            Uf = g.propagate(psi0)
+            ev[1].record(stream)
+            torch.cuda.synchronize()
+            fo.append(ev[0].elapsed_time(ev[1]))
+        Ff, _ = scp.fidelity(Uf, tgt)
         N = desc["n_steps"]
         fwd_flop, adj_flop = flops(desc, S)
         # the plain FP64 path (one launch per local term) only for the small devices
         p64 = plain64_forward_ms(scp, si, torch, desc, S) if g.D <= 1000 else None
         out = {"config": name, "forward_ms": fwd_ms, "fidelity_and_gradient_ms": grad_ms,
+               "forward_only_ms": min(fo), "F_forward_only": Ff,
                "steps_dim2_per_s_forward": N * g.D * S / (fwd_ms * 1e-3),
                "forward_tflops": fwd_flop / (fwd_ms * 1e-3) / 1e12,
                "plain_fp64_forward_ms": p64, "F": F, "n_params": len(grad)}

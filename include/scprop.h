@@ -223,6 +223,12 @@ scp_status scp_apply_generator(const scp_system* sys, int32_t step, int32_t stag
  * workspace for scp_propagate_adjoint, and the system records which
  * workspace holds them for which (n_cols, ckpt_every, n_steps); a propagate
  * without checkpoints clears that record.  psi0 and psiT may alias.
+ * Precision 0 runs the fused register-layout stepper, except a forward
+ * without checkpoints of a system whose columns would occupy fewer than 64
+ * of its workgroups (few columns of a small device, 64 <= D <= 4096, at
+ * most 10 modes): that
+ * one runs on the gather engine, one workgroup per column in LDS, with the
+ * same RK4 arithmetic (compensated FP32 state, FP32 stage tables).
  * SCP_EINVAL if opts->workspace_bytes is below scp_workspace_size(opts,
  * with_grad = 0). */
 scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* workspace,

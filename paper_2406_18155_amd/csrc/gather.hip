@@ -1,0 +1,732 @@
+// Gather engine: classical RK4 with one column per workgroup, the column held
+// in LDS for the whole propagation and every thread evaluating the generator
+// on its own elements by gathering their neighbours along the contracted
+// digits.  Two uses:
+//
+// Closed systems (OPEN = false): a state column psi of D = d^N amplitudes
+// (element A, the multi-index of the N modes, mode 0 slowest) under the
+// interaction-picture generator of Sec. 2.1's local decomposition,
+//   k_A = -i [ delta(A) y_A + sum (one- and two-mode contractions of V) ],
+// for devices whose columns are too few to fill the chip with the register-
+// layout stepper (the 4-fluxonium chain: 16 columns of 625).
+//
+// Open systems (OPEN = true): the vectorised Lindblad master equation (the
+// superoperator form of App. D's closing remark; the LindbladObj component of
+// Sec. 2).  rho (D x D) is the rank-2N tensor rho[a_0..a_{N-1}, b_0..b_{N-1}]
+// stored row-major: element A*D + B, A the ket and B the bra multi-index.  In
+// the interaction picture of the frame,
+//   d rho/dt = -i (V rho - rho V) + sum_m g1_m D[a_m(t)] rho + 2 gphi_m D[n_m] rho,
+// D[L] rho = L rho L^dag - {L^dag L, rho}/2, a the ladder and n the number
+// operator of mode m in its dressed basis.  Per element (A, B):
+//   k_AB = dg_AB rho_AB                                       static diagonal
+//        + sum_m g1_m J_m(t)[a_m][b_m] rho_{A+e_m, B+e_m}      relaxation jump
+//        - i (ket contractions of V) + i (bra contractions of conj V),
+//   dg_AB = -i sum_m (delta_m[a_m] - delta_m[b_m]) - sum_m g1_m (a_m + b_m)/2
+//           - sum_m gphi_m (a_m - b_m)^2,
+//   J_m(t)[a][b] = sqrt((a+1)(b+1)) exp(i (f_a - f_{a+1} - f_b + f_{b+1}) t),
+// delta = eps - f the diagonal left by the frame f.
+//
+// The Hamiltonian enters as one-mode contractions (per driven mode the sum of
+// c_k(t) O_k(t) of its drives) and two-mode contractions (per coupled pair of
+// modes the d^2 x d^2 operator sum_e g_e O_i(t) (x) O_j(t)), along the ket
+// digits with the operator and (open systems) along the bra digits with its
+// complex conjugate.  These stage tables are precomputed for every stage row
+// of the step grid (3 per step, as the drive coefficients) by one kernel; the
+// stepper loads the next stage's table into registers while the current stage
+// runs and stores it into LDS after.  LDS holds two stage-input buffers (a
+// stage reads y_s from one and writes y_{s+1} into the other), the static
+// diagonal and two stage tables; each thread keeps its elements' state
+// (compensated hi + lo) and the RK4 accumulator in registers.  One barrier
+// per stage.
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+#include "kernel_common.h"
+
+namespace scp {
+
+constexpr int GA_MAXM = 10;      // modes (three-bit digits, 2N (open) or N in one word)
+constexpr int GA_MAXDM = 5;      // driven modes
+constexpr int GA_MAXPR = 10;     // coupled mode pairs
+constexpr int GA_MAXC = 4;       // operators summed into one table entry
+constexpr int GA_MAXTAB = 4096;  // complex entries of a stage table
+constexpr int GA_PRE = 4;        // table entries each thread prefetches per stage
+
+// Static description of one gather-engine propagation (device copy in the
+// workspace, read through the scalar path where uniform).
+struct GArgs {
+  const float2* optab;   // [2N+1][block_q] rotated slot operators of the system
+  const float* ctab;     // [3N][ngroups] drive coefficients
+  const float2* jtab;    // [2N+1][N][d*d] unit-rate relaxation band (open systems)
+  const float2* gtab;    // [3N][ntab] stage tables (built by gtab_kernel)
+  const float2* x0;      // [S][L] input columns
+  float2* xT;            // [S][L] output columns
+  int block_q, ngroups, nsteps, S;
+  float h;
+  int ndm, npr, ntab, has_jump, off_p, off_j;
+  int kst[GA_MAXM], bst[GA_MAXM];                    // strides of ket / bra digits in a column
+  int dm_mode[GA_MAXDM], dm_n[GA_MAXDM];
+  int dm_slot[GA_MAXDM][GA_MAXC], dm_cidx[GA_MAXDM][GA_MAXC];
+  int pr_i[GA_MAXPR], pr_j[GA_MAXPR], pr_n[GA_MAXPR];
+  int pr_si[GA_MAXPR][GA_MAXC], pr_sj[GA_MAXPR][GA_MAXC];
+  float pr_g[GA_MAXPR][GA_MAXC];
+  float g1[GA_MAXM], gp[GA_MAXM];
+  float delta[GA_MAXM][8];
+};
+
+#define SCP_TRY(expr)                  \
+  do {                                 \
+    const scp_status st_ = (expr);     \
+    if (st_ != SCP_OK) return st_;     \
+  } while (0)
+
+namespace {
+
+constexpr int cpow(int b, int e) { return e == 0 ? 1 : b * cpow(b, e - 1); }
+
+// Geometry of one column: N modes of dimension d; a state (L = D) or a
+// vectorised density matrix (L = D^2).
+template <int d, int N, bool OPEN>
+struct GShape {
+  static constexpr int D = cpow(d, N);
+  static constexpr int L = OPEN ? D * D : D;
+  static constexpr int T = L >= 1024 ? 1024 : ((L + 63) / 64) * 64;   // threads
+  static constexpr int E = (L + T - 1) / T;                           // elements per thread
+  static constexpr int st(int m) { return cpow(d, N - 1 - m); }       // stride in A or B
+};
+
+__device__ __forceinline__ int ket_digit(uint32_t pk, int m) { return (pk >> (3 * m)) & 7; }
+__device__ __forceinline__ int bra_digit(uint32_t pk, int m, int N) {
+  return (pk >> (3 * (N + m))) & 7;
+}
+
+__device__ __forceinline__ void cmac(float& sr, float& si, c32 a, c32 b) {
+  sr = fmaf(a.x, b.x, sr);
+  sr = fmaf(-a.y, b.y, sr);
+  si = fmaf(a.x, b.y, si);
+  si = fmaf(a.y, b.x, si);
+}
+// s += conj(a) b
+__device__ __forceinline__ void cmac_conj(float& sr, float& si, c32 a, c32 b) {
+  sr = fmaf(a.x, b.x, sr);
+  sr = fmaf(a.y, b.y, sr);
+  si = fmaf(a.x, b.y, si);
+  si = fmaf(-a.y, b.x, si);
+}
+
+// Row of the drive table of step-grid row r (3 per step: t_n, t_n + h/2,
+// t_n + h) and the half-step of its operators.
+__device__ __forceinline__ int row_q(int r) { return 2 * (r / 3) + r % 3; }
+
+// Stage table of step-grid row r: [driven-mode operators sum_k c_k O_k]
+// [pair operators sum_e g_e O_i (x) O_j][relaxation bands g1_m J_m], from the
+// FP32 rotated operators and coefficients.
+__global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* __restrict__ out) {
+  const GArgs& A = *Ag;
+  const int r = blockIdx.x;
+  const int q = row_q(r);
+  const int dd = d * d;
+  const c32* ops = (const c32*)A.optab + (size_t)q * A.block_q;
+  const float* cq = A.ctab + (size_t)r * A.ngroups;
+  for (int t = threadIdx.x; t < A.ntab; t += blockDim.x) {
+    float vr = 0.f, vi = 0.f;
+    if (t < A.off_p) {
+      const int dm = t / dd, ab = t - dm * dd;
+      for (int k = 0; k < A.dm_n[dm]; ++k) {
+        const float c = cq[A.dm_cidx[dm][k]];
+        const c32 o = ops[A.dm_slot[dm][k] * dd + ab];
+        vr = fmaf(c, o.x, vr);
+        vi = fmaf(c, o.y, vi);
+      }
+    } else if (t < A.off_j) {
+      const int u = t - A.off_p;
+      const int p = u / (dd * dd), rr = u - p * dd * dd;
+      const int row = rr / dd, col = rr - row * dd;
+      const int ai = row / d, aj = row - ai * d, x = col / d, z = col - x * d;
+      for (int k = 0; k < A.pr_n[p]; ++k) {
+        const c32 oi = ops[A.pr_si[p][k] * dd + ai * d + x];
+        const c32 oj = ops[A.pr_sj[p][k] * dd + aj * d + z];
+        const float g = A.pr_g[p][k];
+        vr = fmaf(g, oi.x * oj.x - oi.y * oj.y, vr);
+        vi = fmaf(g, oi.x * oj.y + oi.y * oj.x, vi);
+      }
+    } else {
+      const int u = t - A.off_j;
+      const int m = u / dd;
+      const c32 j = ((const c32*)A.jtab)[((size_t)q * N) * dd + u];
+      vr = A.g1[m] * j.x;
+      vi = A.g1[m] * j.y;
+    }
+    out[(size_t)r * A.ntab + t] = make_float2(vr, vi);
+  }
+}
+
+// k = G(t) y for one element; y read from LDS (neighbours), the own value
+// from the caller.
+template <int d, int N, bool OPEN>
+__device__ __forceinline__ void g_apply(kptr<GArgs> A, const c32* __restrict__ yb,
+                                        const c32* __restrict__ tab, int e, uint32_t pk,
+                                        float dgr, float dgi, float yr, float yi, float& kr,
+                                        float& ki) {
+  using Sh = GShape<d, N, OPEN>;
+  constexpr int D = Sh::D, dd = d * d;
+  kr = dgr * yr - dgi * yi;
+  ki = fmaf(dgr, yi, dgi * yr);
+  if (OPEN && uni(A->has_jump)) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      const int am = ket_digit(pk, m), bm = bra_digit(pk, m, N);
+      if (am < d - 1 && bm < d - 1) {
+        const c32 J = tab[A->off_j + m * dd + am * d + bm];
+        const c32 v = yb[e + (D + 1) * Sh::st(m)];
+        cmac(kr, ki, J, v);
+      }
+    }
+  }
+  // driven modes: ket -i Hd y, bra +i y Hd
+  const int ndm = uni(A->ndm);
+  for (int dmv = 0; dmv < ndm; ++dmv) {
+    const int dm = uni(dmv);
+    const int m = uni(A->dm_mode[dm]);
+    {
+      const int sm = uni(A->kst[m]);
+      const int am = ket_digit(pk, m);
+      const c32* row = tab + dm * dd + am * d;
+      const c32* y0 = yb + e - am * sm;
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int x = 0; x < d; ++x) cmac(sr, si, row[x], y0[x * sm]);
+      kr += si;
+      ki -= sr;
+    }
+    if (OPEN) {
+      const int sm = uni(A->bst[m]);
+      const int bm = bra_digit(pk, m, N);
+      const c32* row = tab + dm * dd + bm * d;
+      const c32* y0 = yb + e - bm * sm;
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int x = 0; x < d; ++x) cmac_conj(sr, si, row[x], y0[x * sm]);
+      kr -= si;
+      ki += sr;
+    }
+  }
+  // coupled pairs
+  const int npr = uni(A->npr);
+  for (int pv = 0; pv < npr; ++pv) {
+    const int p = uni(pv);
+    const int i = uni(A->pr_i[p]), j = uni(A->pr_j[p]);
+    const c32* P = tab + A->off_p + p * dd * dd;
+    {
+      const int si_ = uni(A->kst[i]), sj_ = uni(A->kst[j]);
+      const int ai = ket_digit(pk, i), aj = ket_digit(pk, j);
+      const c32* row = P + (ai * d + aj) * dd;
+      const c32* y0 = yb + e - (ai * si_ + aj * sj_);
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int x = 0; x < d; ++x)
+#pragma unroll
+        for (int z = 0; z < d; ++z) cmac(sr, si, row[x * d + z], y0[x * si_ + z * sj_]);
+      kr += si;
+      ki -= sr;
+    }
+    if (OPEN) {
+      const int si_ = uni(A->bst[i]), sj_ = uni(A->bst[j]);
+      const int bi = bra_digit(pk, i, N), bj = bra_digit(pk, j, N);
+      const c32* row = P + (bi * d + bj) * dd;
+      const c32* y0 = yb + e - (bi * si_ + bj * sj_);
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int x = 0; x < d; ++x)
+#pragma unroll
+        for (int z = 0; z < d; ++z) cmac_conj(sr, si, row[x * d + z], y0[x * si_ + z * sj_]);
+      kr -= si;
+      ki += sr;
+    }
+  }
+}
+
+template <int d, int N, bool OPEN>
+__global__ void __launch_bounds__((GShape<d, N, OPEN>::T)) g_rk4_kernel(const GArgs* __restrict__ Ag) {
+  using Sh = GShape<d, N, OPEN>;
+  constexpr int L = Sh::L, T = Sh::T, E = Sh::E;
+  // LDS: two stage-input buffers, the static diagonal, two stage tables
+  extern __shared__ c32 lds[];
+  kptr<GArgs> A = kconst(Ag);
+  const int ntab = A->ntab;
+  c32* dgb = lds + 2 * L;
+  const c32* gtab = (const c32*)A->gtab;
+  const int tid = threadIdx.x;
+  const int col = blockIdx.x;
+  const float h = A->h;
+  const int nsteps = A->nsteps;
+  uint32_t pk[E];
+  float hr[E], hm[E], lr[E], lm[E], ar[E], am_[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = tid + r * T;
+    const bool ok = e < L;
+    const int Ai = OPEN ? e / Sh::D : e, Bi = OPEN ? e - Ai * Sh::D : 0;
+    uint32_t p = 0;
+    float gr = 0.f, gi = 0.f;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      const int a = (Ai / Sh::st(m)) % d;
+      p |= (uint32_t)a << (3 * m);
+      if (OPEN) {
+        const int b = (Bi / Sh::st(m)) % d;
+        p |= (uint32_t)b << (3 * (N + m));
+        gi -= A->delta[m][a] - A->delta[m][b];
+        gr -= 0.5f * A->g1[m] * (float)(a + b) + A->gp[m] * (float)((a - b) * (a - b));
+      } else {
+        gi -= A->delta[m][a];
+      }
+    }
+    pk[r] = p;
+    c32 v;
+    v.x = v.y = 0.f;
+    if (ok) v = ((const c32*)A->x0)[(size_t)col * L + e];
+    hr[r] = v.x;
+    hm[r] = v.y;
+    lr[r] = lm[r] = 0.f;
+    ar[r] = am_[r] = 0.f;
+    if (ok) {
+      lds[e] = v;
+      c32 g;
+      g.x = gr;
+      g.y = gi;
+      dgb[e] = g;
+    }
+  }
+  for (int t = tid; t < ntab; t += T) lds[3 * L + t] = gtab[t];
+  __syncthreads();
+  int cur = 0;
+#pragma unroll 1
+  for (int n = 0; n < nsteps; ++n) {
+#pragma unroll 1
+    for (int s = 0; s < 4; ++s) {
+      const float w = (s == 0 || s == 3) ? 1.f : 2.f;
+      const float ch = (s == 2) ? h : 0.5f * h;
+      const c32* yc = lds + cur * L;
+      const c32* tc = lds + 3 * L + cur * ntab;
+      c32* yn = lds + (cur ^ 1) * L;
+      // the next stage's table, loaded now and stored after this stage
+      const int n2 = s < 3 ? n : n + 1, s2 = s < 3 ? s + 1 : 0;
+      const bool more = n2 < nsteps;
+      const c32* gnext = gtab + (size_t)stage_c(n2, s2) * ntab;
+      c32 pre[GA_PRE];
+#pragma unroll
+      for (int k = 0; k < GA_PRE; ++k) {
+        const int t = tid + k * T;
+        if (more && t < ntab) pre[k] = gnext[t];
+      }
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        int e = tid + r * T;
+        uint32_t p = pk[r];
+        // opaque per stage: the element's LDS offsets are then formed inside
+        // the stage instead of being hoisted out of the step loop (which
+        // would hold E sets of them in registers)
+        asm volatile("" : "+v"(e), "+v"(p));
+        if (e < L) {
+          const c32 g = dgb[e], ye = yc[e];
+          float kr, ki;
+          g_apply<d, N, OPEN>(A, yc, tc, e, p, g.x, g.y, ye.x, ye.y, kr, ki);
+          if (s == 0) {
+            ar[r] = kr;
+            am_[r] = ki;
+          } else {
+            ar[r] = fmaf(w, kr, ar[r]);
+            am_[r] = fmaf(w, ki, am_[r]);
+          }
+          c32 v;
+          if (s < 3) {
+            v.x = fmaf(ch, kr, hr[r]);
+            v.y = fmaf(ch, ki, hm[r]);
+          } else {
+            const float h6 = h * (1.0f / 6.0f);
+            comp_add(hr[r], lr[r], h6 * ar[r]);
+            comp_add(hm[r], lm[r], h6 * am_[r]);
+            v.x = hr[r];
+            v.y = hm[r];
+          }
+          yn[e] = v;
+        }
+        // one element at a time: keeps the live registers of the unrolled
+        // element loop from piling up across elements
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (more) {
+        c32* tn = lds + 3 * L + (cur ^ 1) * ntab;
+#pragma unroll
+        for (int k = 0; k < GA_PRE; ++k) {
+          const int t = tid + k * T;
+          if (t < ntab) tn[t] = pre[k];
+        }
+        for (int t = tid + GA_PRE * T; t < ntab; t += T) tn[t] = gnext[t];
+      }
+      __syncthreads();
+      cur ^= 1;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = tid + r * T;
+    if (e < L) {
+      c32 v;
+      v.x = hr[r] + lr[r];
+      v.y = hm[r] + lm[r];
+      ((c32*)A->xT)[(size_t)col * L + e] = v;
+    }
+  }
+}
+
+// Unit-rate relaxation band of every mode at every half-step q (t = q h/2):
+// sqrt((a+1)(b+1)) exp(i (f_a - f_{a+1} - f_b + f_{b+1}) t) for a, b < d - 1,
+// zero otherwise; FP64 angle reduced modulo 2 pi, stored FP32.
+struct JtabStatic {
+  int d, N, nq;
+  double h;
+  double f[GA_MAXM][8];
+};
+
+__global__ void jtab_kernel(JtabStatic js, float2* __restrict__ out) {
+  const int q = blockIdx.x;
+  const int dd = js.d * js.d;
+  const double t = q * (0.5 * js.h);
+  const double twopi = 6.283185307179586476925286766559;
+  for (int u = threadIdx.x; u < js.N * dd; u += blockDim.x) {
+    const int m = u / dd, ab = u - m * dd, a = ab / js.d, b = ab - a * js.d;
+    float2 v = make_float2(0.f, 0.f);
+    if (a < js.d - 1 && b < js.d - 1) {
+      double x = (js.f[m][a] - js.f[m][a + 1] - js.f[m][b] + js.f[m][b + 1]) * t;
+      x -= twopi * rint(x / twopi);
+      double sn, cs;
+      sincos(x, &sn, &cs);
+      const double r = sqrt((double)((a + 1) * (b + 1)));
+      v = make_float2((float)(r * cs), (float)(r * sn));
+    }
+    out[(size_t)q * js.N * dd + u] = v;
+  }
+}
+
+__global__ void store_args_kernel(GArgs a, GArgs* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = a;
+}
+
+template <int d, int N, bool OPEN>
+size_t g_lds_bytes(int ntab) {
+  return sizeof(c32) * (3 * (size_t)GShape<d, N, OPEN>::L + 2 * (size_t)ntab);
+}
+
+template <int d, int N, bool OPEN>
+hipError_t g_launch(const GArgs* dargs, int S, int ntab, hipStream_t s) {
+  using Sh = GShape<d, N, OPEN>;
+  const size_t sh = g_lds_bytes<d, N, OPEN>(ntab);
+  (void)hipFuncSetAttribute((const void*)g_rk4_kernel<d, N, OPEN>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  hipLaunchKernelGGL((g_rk4_kernel<d, N, OPEN>), dim3(S), dim3(Sh::T), sh, s, dargs);
+  return hipGetLastError();
+}
+
+// Shapes with a compiled stepper: open systems D^2 <= 6561, closed systems
+// 64 <= D <= 4096 with at most 10 modes.
+#define GA_OPEN_SHAPES(X) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(3, 1) X(3, 2) X(3, 3) X(3, 4) \
+  X(4, 1) X(4, 2) X(4, 3) X(5, 1) X(5, 2)
+#define GA_CLOSED_SHAPES(X) X(2, 6) X(2, 7) X(2, 8) X(2, 9) X(2, 10) X(3, 4) X(3, 5) X(3, 6) \
+  X(3, 7) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(5, 3) X(5, 4) X(5, 5)
+
+hipError_t g_dispatch(int d, int N, bool open, const GArgs* dargs, int S, int ntab, hipStream_t s) {
+#define GA_CASE_O(dd_, nn_) \
+  if (open && d == dd_ && N == nn_) return g_launch<dd_, nn_, true>(dargs, S, ntab, s);
+#define GA_CASE_C(dd_, nn_) \
+  if (!open && d == dd_ && N == nn_) return g_launch<dd_, nn_, false>(dargs, S, ntab, s);
+  GA_OPEN_SHAPES(GA_CASE_O)
+  GA_CLOSED_SHAPES(GA_CASE_C)
+#undef GA_CASE_O
+#undef GA_CASE_C
+  return hipErrorInvalidValue;
+}
+
+bool g_supported(int d, int N, bool open) {
+#define GA_HAS_O(dd_, nn_) if (open && d == dd_ && N == nn_) return true;
+#define GA_HAS_C(dd_, nn_) if (!open && d == dd_ && N == nn_) return true;
+  GA_OPEN_SHAPES(GA_HAS_O)
+  GA_CLOSED_SHAPES(GA_HAS_C)
+#undef GA_HAS_O
+#undef GA_HAS_C
+  return false;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+// Fill the static description from the system and (open systems) the rates.
+static scp_status g_args(const scp_system* sys, bool open, const double* gamma1,
+                         const double* gammaphi, GArgs& A) {
+  std::memset(&A, 0, sizeof(A));
+  const Plan& P = sys->plan;
+  const int N = sys->n_modes, d = sys->d, dd = d * d;
+  if (N > GA_MAXM || (open && 2 * N > GA_MAXM) || d > 7)
+    return fail(SCP_EINVAL, "gather engine: too many modes");
+  const int D = (int)sys->D;
+  A.block_q = P.block_q;
+  A.ngroups = std::max(1, P.ngroups);
+  A.nsteps = sys->n_steps;
+  A.h = (float)sys->h;
+  for (int m = 0; m < N; ++m) {
+    int st = 1;
+    for (int q = m + 1; q < N; ++q) st *= d;
+    A.kst[m] = open ? st * D : st;
+    A.bst[m] = st;
+    const double g1 = (open && gamma1) ? gamma1[m] : 0.0;
+    const double gp = (open && gammaphi) ? gammaphi[m] : 0.0;
+    if (!(g1 >= 0.0) || !(gp >= 0.0) || !std::isfinite(g1) || !std::isfinite(gp))
+      return fail(SCP_EINVAL, "decay rates must be finite and non-negative");
+    A.g1[m] = (float)g1;
+    A.gp[m] = (float)gp;
+    A.has_jump |= g1 > 0.0;
+    for (int a = 0; a < d; ++a) A.delta[m][a] = P.delta[m][a];
+  }
+  // driven modes: the distinct (slot, coefficient group) pairs of each mode
+  for (int k = 0; k < P.ndrives; ++k) {
+    const int s = P.drives[k].slot, g = P.drives[k].cidx, m = P.slot_mode[s];
+    int dm = -1;
+    for (int q = 0; q < A.ndm; ++q)
+      if (A.dm_mode[q] == m) dm = q;
+    if (dm < 0) {
+      if (A.ndm >= GA_MAXDM) return fail(SCP_EINVAL, "gather engine: too many driven modes");
+      dm = A.ndm++;
+      A.dm_mode[dm] = m;
+    }
+    bool seen = false;
+    for (int q = 0; q < A.dm_n[dm]; ++q) seen |= A.dm_slot[dm][q] == s;
+    if (seen) continue;
+    if (A.dm_n[dm] >= GA_MAXC)
+      return fail(SCP_EINVAL, "gather engine: too many drive operators on one mode");
+    A.dm_slot[dm][A.dm_n[dm]] = s;
+    A.dm_cidx[dm][A.dm_n[dm]++] = g;
+  }
+  // coupled pairs (i < j)
+  for (int e = 0; e < P.ncoup; ++e) {
+    const int si = P.coup_slot_i[e], sj = P.coup_slot_j[e];
+    int i = P.slot_mode[si], j = P.slot_mode[sj];
+    int ssi = si, ssj = sj;
+    if (i > j) {
+      std::swap(i, j);
+      std::swap(ssi, ssj);
+    }
+    int p = -1;
+    for (int q = 0; q < A.npr; ++q)
+      if (A.pr_i[q] == i && A.pr_j[q] == j) p = q;
+    if (p < 0) {
+      if (A.npr >= GA_MAXPR) return fail(SCP_EINVAL, "gather engine: too many coupled pairs");
+      p = A.npr++;
+      A.pr_i[p] = i;
+      A.pr_j[p] = j;
+    }
+    if (A.pr_n[p] >= GA_MAXC) return fail(SCP_EINVAL, "gather engine: too many couplings on one pair");
+    A.pr_si[p][A.pr_n[p]] = ssi;
+    A.pr_sj[p][A.pr_n[p]] = ssj;
+    A.pr_g[p][A.pr_n[p]++] = (float)sys->coup[e].g;
+  }
+  A.off_p = A.ndm * dd;
+  A.off_j = A.off_p + A.npr * dd * dd;
+  A.ntab = A.off_j + (A.has_jump ? N * dd : 0);
+  if (A.ntab > GA_MAXTAB) return fail(SCP_EINVAL, "gather engine: stage table too large");
+  const size_t L = open ? (size_t)D * D : (size_t)D;
+  if ((3 * L + 2 * (size_t)A.ntab) * sizeof(float2) > 163840)
+    return fail(SCP_EINVAL, "gather engine: column and stage tables exceed the LDS");
+  return SCP_OK;
+}
+
+// Workspace: [GArgs][stage tables [3N][ntab]][open: jump bands [2N+1][N][d*d]].
+static size_t g_ws_bytes(const scp_system* sys, bool open, int ntab) {
+  const size_t dd = (size_t)sys->d * sys->d;
+  size_t b = align256(sizeof(GArgs)) + align256(3 * (size_t)sys->n_steps * ntab * sizeof(float2));
+  if (open) b += align256((2 * (size_t)sys->n_steps + 1) * sys->n_modes * dd * sizeof(float2));
+  return b;
+}
+
+static scp_status g_run(scp_system* sys, bool open, const double* gamma1, const double* gammaphi,
+                        int S, void* ws, size_t ws_bytes, const float2* x0, float2* xT,
+                        hipStream_t st) {
+  GArgs A;
+  SCP_TRY(g_args(sys, open, gamma1, gammaphi, A));
+  if (ws_bytes < g_ws_bytes(sys, open, A.ntab)) return fail(SCP_EINVAL, "workspace too small");
+  char* w = static_cast<char*>(ws);
+  GArgs* dargs = reinterpret_cast<GArgs*>(w);
+  w += align256(sizeof(GArgs));
+  float2* gtab = reinterpret_cast<float2*>(w);
+  w += align256(3 * (size_t)sys->n_steps * A.ntab * sizeof(float2));
+  float2* jtab = open ? reinterpret_cast<float2*>(w) : nullptr;
+  A.optab = sys->d_ops;
+  A.ctab = sys->d_ctab;
+  A.jtab = jtab;
+  A.gtab = gtab;
+  A.x0 = x0;
+  A.xT = xT;
+  A.S = S;
+  const int N = sys->n_modes, d = sys->d;
+  if (A.has_jump) {
+    JtabStatic js;
+    std::memset(&js, 0, sizeof(js));
+    js.d = d;
+    js.N = N;
+    js.nq = 2 * sys->n_steps + 1;
+    js.h = sys->h;
+    for (int m = 0; m < N; ++m)
+      for (int a = 0; a < d; ++a) js.f[m][a] = sys->modes[m].frame[a];
+    hipLaunchKernelGGL(jtab_kernel, dim3(js.nq), dim3(64), 0, st, js, jtab);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(store_args_kernel, dim3(1), dim3(64), 0, st, A, dargs);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(gtab_kernel, dim3(3 * sys->n_steps), dim3(256), 0, st, dargs, d, N, gtab);
+  HIPCHK(hipGetLastError());
+  if (S == 0) return SCP_OK;
+  hipEvent_t t0 = timing_start(sys, st);
+  HIPCHK(g_dispatch(d, N, open, dargs, S, A.ntab, st));
+  timing_stop(sys, t0, 0, st);
+  return SCP_OK;
+}
+
+// --- open systems ----------------------------------------------------------
+scp_status lindblad_check(const scp_system* sys) {
+  if (!g_supported(sys->d, sys->n_modes, true))
+    return fail(SCP_EINVAL, "open-system path: the density matrix must fit in LDS (d=2: N<=5, "
+                            "d=3: N<=4, d=4: N<=3, d=5: N<=2)");
+  GArgs A;
+  return g_args(sys, true, nullptr, nullptr, A);
+}
+
+size_t lindblad_workspace_bytes(const scp_system* sys) {
+  GArgs A;
+  std::vector<double> one(sys->n_modes, 1.0);   // the largest table: relaxation on
+  if (g_args(sys, true, one.data(), nullptr, A) != SCP_OK) return 0;
+  return g_ws_bytes(sys, true, A.ntab);
+}
+
+scp_status launch_lindblad(scp_system* sys, const double* gamma1, const double* gammaphi, int S,
+                           void* ws, size_t ws_bytes, const float2* rho0, float2* rhoT,
+                           hipStream_t st) {
+  SCP_TRY(lindblad_check(sys));
+  return g_run(sys, true, gamma1, gammaphi, S, ws, ws_bytes, rho0, rhoT, st);
+}
+
+// --- closed systems ----------------------------------------------------------
+// The gather engine takes a closed-system forward (no checkpoints) when the
+// system has a compiled shape and its columns would leave most of the chip
+// idle in the register-layout stepper: fewer columns than 256 workgroups'
+// worth (each gather workgroup holds one column).
+bool gather_preferred(const scp_system* sys, int S) {
+  if (!g_supported(sys->d, sys->n_modes, false) || S > 256) return false;
+  GArgs A;
+  if (g_args(sys, false, nullptr, nullptr, A) != SCP_OK) {
+    set_error("");
+    return false;
+  }
+  const int fused_wg = (S + sys->plan.CPW - 1) / sys->plan.CPW;
+  return fused_wg < 64;
+}
+
+size_t gather_workspace_bytes(const scp_system* sys) {
+  GArgs A;
+  if (g_args(sys, false, nullptr, nullptr, A) != SCP_OK) {
+    set_error("");
+    return 0;
+  }
+  return g_ws_bytes(sys, false, A.ntab);
+}
+
+scp_status launch_gather_forward(scp_system* sys, int S, void* ws, size_t ws_bytes,
+                                 const float2* psi0, float2* psiT, hipStream_t st) {
+  return g_run(sys, false, nullptr, nullptr, S, ws, ws_bytes, psi0, psiT, st);
+}
+
+// ---------------------------------------------------------------------------
+// average gate fidelity of the channel on the computational subspace
+// ---------------------------------------------------------------------------
+namespace {
+
+// ov = sum_ab sum_ij conj(T_ia) T_jb rho_ab[r_i, r_j] in FP64 by one
+// workgroup in a fixed order.
+__global__ void __launch_bounds__(1024) chan_overlap_kernel(const c32* __restrict__ rho, int64_t D,
+                                                            int dc, const int64_t* __restrict__ rows,
+                                                            const double2* __restrict__ Tm,
+                                                            double2* __restrict__ ov) {
+  __shared__ double red[2][1024];
+  const int64_t n = (int64_t)dc * dc * dc * dc;
+  double sr = 0.0, si = 0.0;
+  for (int64_t u = threadIdx.x; u < n; u += blockDim.x) {
+    const int64_t ab = u / ((int64_t)dc * dc), ij = u - ab * dc * dc;
+    const int a = (int)(ab / dc), b = (int)(ab - (int64_t)a * dc);
+    const int i = (int)(ij / dc), j = (int)(ij - (int64_t)i * dc);
+    const double2 ta = Tm[(size_t)i * dc + a], tb = Tm[(size_t)j * dc + b];
+    // w = conj(ta) tb
+    const double wr = ta.x * tb.x + ta.y * tb.y, wi = ta.x * tb.y - ta.y * tb.x;
+    const c32 v = rho[(size_t)ab * D * D + (size_t)rows[i] * D + rows[j]];
+    sr += wr * v.x - wi * v.y;
+    si += wr * v.y + wi * v.x;
+  }
+  red[0][threadIdx.x] = sr;
+  red[1][threadIdx.x] = si;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + w];
+      red[1][threadIdx.x] += red[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ov[0] = make_double2(red[0][0], red[1][0]);
+}
+
+// cotangent of 1 - F: -T_ia conj(T_jb) / (2 dc (dc + 1)) at (ab, r_i, r_j), zero elsewhere
+__global__ void chan_cot_kernel(c32* __restrict__ cot, int64_t D, int dc,
+                                const int64_t* __restrict__ rows, const double2* __restrict__ Tm) {
+  const int64_t total = (int64_t)dc * dc * D * D;
+  const double c = -1.0 / (2.0 * dc * (dc + 1.0));
+  for (int64_t u = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; u < total;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ab = u / (D * D), rem = u - ab * D * D;
+    const int64_t R = rem / D, C = rem - R * D;
+    const int a = (int)(ab / dc), b = (int)(ab - (int64_t)a * dc);
+    int i = -1, j = -1;
+    for (int q = 0; q < dc; ++q) {
+      if (rows[q] == R) i = q;
+      if (rows[q] == C) j = q;
+    }
+    c32 v;
+    v.x = v.y = 0.f;
+    if (i >= 0 && j >= 0) {
+      const double2 ta = Tm[(size_t)i * dc + a], tb = Tm[(size_t)j * dc + b];
+      // ta conj(tb)
+      v.x = (float)(c * (ta.x * tb.x + ta.y * tb.y));
+      v.y = (float)(c * (ta.y * tb.x - ta.x * tb.y));
+    }
+    cot[u] = v;
+  }
+}
+
+}  // namespace
+
+scp_status launch_fidelity_channel(const void* rhoT, int64_t D, int dc, const int64_t* rows,
+                                   const void* target, void* ov, void* cot, hipStream_t st) {
+  hipLaunchKernelGGL(chan_overlap_kernel, dim3(1), dim3(1024), 0, st, (const c32*)rhoT, D, dc, rows,
+                     (const double2*)target, (double2*)ov);
+  HIPCHK(hipGetLastError());
+  if (cot) {
+    const int64_t total = (int64_t)dc * dc * D * D;
+    const int blocks = (int)std::min<int64_t>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(chan_cot_kernel, dim3(std::max(1, blocks)), dim3(256), 0, st, (c32*)cot, D,
+                       dc, rows, (const double2*)target);
+    HIPCHK(hipGetLastError());
+  }
+  return SCP_OK;
+}
+
+}  // namespace scp

@@ -264,5 +264,9 @@ scp_status launch_lindblad(scp_system* sys, const double* gamma1, const double* 
                            hipStream_t st);
 scp_status launch_fidelity_channel(const void* rhoT, int64_t D, int dc, const int64_t* rows,
                                    const void* target, void* ov, void* cot, hipStream_t st);
+bool gather_preferred(const scp_system* sys, int S);
+size_t gather_workspace_bytes(const scp_system* sys);
+scp_status launch_gather_forward(scp_system* sys, int S, void* ws, size_t ws_bytes,
+                                 const float2* psi0, float2* psiT, hipStream_t st);
 
 }  // namespace scp

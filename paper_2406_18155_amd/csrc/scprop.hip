@@ -818,6 +818,7 @@ scp_status build(const scp_system_desc* ds, hipStream_t st, scp_system* sys) {
 struct WsLayout {
   size_t lo = 0, ckpt = 0, seg = 0, part = 0, lam = 0, lamstate = 0, total = 0;
   int nckpt = 0, ce = 0, nwg = 0;
+  bool gather = false;   // a forward-only FP32 solve on the gather engine (workspace from 0)
 };
 
 WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad) {
@@ -828,7 +829,10 @@ WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad
   const size_t S = (size_t)o->n_cols, D = (size_t)sys->D;
   size_t off = 0;
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  if (o->precision == 0) {
+  if (o->precision == 0 && !o->with_ckpt && !with_grad && gather_preferred(sys, (int)S)) {
+    w.gather = true;
+    off = gather_workspace_bytes(sys);
+  } else if (o->precision == 0) {
     w.lo = off;
     off = align(off + S * D * sizeof(float2));
     if (o->with_ckpt || with_grad) {
@@ -998,6 +1002,11 @@ scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* work
   if (opts->precision == 1) {
     ck_clear(sys);
     return launch_plain64(sys, (const double2*)psi0, (double2*)psiT, workspace, opts->n_cols, st);
+  }
+  if (w.gather) {
+    ck_clear(sys);
+    return launch_gather_forward(sys, opts->n_cols, workspace, opts->workspace_bytes,
+                                 (const float2*)psi0, (float2*)psiT, st);
   }
   float4* ck = opts->with_ckpt ? (float4*)((char*)workspace + w.ckpt) : nullptr;
   ck_clear(sys);

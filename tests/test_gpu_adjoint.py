@@ -259,7 +259,7 @@ def test_autograd_function_follows_theta(scp):
         U1 = scp.autograd.propagate(model, torch.tensor(th1), psi0)
         U2 = scp.autograd.propagate(model, torch.tensor(th2), psi0)
     sysm = scp.System(model.desc_at(th1))
-    U1e = sysm.propagate(psi0.clone())
+    U1e = sysm.propagate(psi0.clone(), opts=sysm.opts(psi0.shape[0], with_ckpt=1))
     sysm.close()
     assert torch.equal(U1, U1e)
     fd = (_torch_infidelity(U1, desc).item() - _torch_infidelity(U2, desc).item()) / (2 * h)

@@ -107,11 +107,14 @@ def test_apply_generator_matches_oracle(scp, name):
     g.close()
 
 
-def _gpu_propagate(scp, desc, S_cols=None):
+def _gpu_propagate(scp, desc, S_cols=None, fused=False):
+    """Forward of the columns; ``fused``: with checkpoints, which always runs
+    the register-layout stepper (a forward without them runs on the gather
+    engine when the system has few columns of a small device)."""
     g = scp.System(desc)
     cols = desc["columns"] if S_cols is None else S_cols
     psi0 = scp.basis_columns(g.D, cols)
-    U = g.propagate(psi0)
+    U = g.propagate(psi0, opts=g.opts(len(cols), with_ckpt=1) if fused else None)
     torch.cuda.synchronize()
     return g, U
 
@@ -135,39 +138,41 @@ PROP_CASES = {
 @pytest.mark.parametrize("name", list(PROP_CASES))
 def test_propagate_matches_oracle(scp, name):
     desc = PROP_CASES[name]()
-    print(f"[propagate] {name}", flush=True)
-    g, U = _gpu_propagate(scp, desc)
     o = OracleSystem(desc)
     Uo = oracle_propagate(o)                                   # (D, S)
-    Ug = U.cpu().numpy().T.astype(np.complex128)
-    assert np.abs(Ug - Uo).max() <= 2e-5, np.abs(Ug - Uo).max()
-    Fg = _gpu_fid(scp, U, desc)
-    Fo, _ = oracle_fidelity(Uo, desc["comp_rows"], desc["comp_cols"], desc["target"])
-    assert abs(Fg - Fo) <= DF_TOL, (Fg, Fo)
-    # F ~ 1 case: target = the oracle's own computational block (nearest unitary)
     P = Uo[np.ix_(desc["comp_rows"], desc["comp_cols"])]
     u, _, vh = np.linalg.svd(P)
     d2 = dict(desc, target=u @ vh)
-    Fg1 = _gpu_fid(scp, U, d2)
-    Fo1, _ = oracle_fidelity(Uo, desc["comp_rows"], desc["comp_cols"], d2["target"])
-    assert Fo1 > 0.9
-    assert abs(Fg1 - Fo1) <= DF_TOL, (Fg1, Fo1)
-    g.close()
+    for fused in (False, True):
+        print(f"[propagate] {name} fused={fused}", flush=True)
+        g, U = _gpu_propagate(scp, desc, fused=fused)
+        Ug = U.cpu().numpy().T.astype(np.complex128)
+        assert np.abs(Ug - Uo).max() <= 2e-5, (fused, np.abs(Ug - Uo).max())
+        Fg = _gpu_fid(scp, U, desc)
+        Fo, _ = oracle_fidelity(Uo, desc["comp_rows"], desc["comp_cols"], desc["target"])
+        assert abs(Fg - Fo) <= DF_TOL, (fused, Fg, Fo)
+        # F ~ 1 case: target = the oracle's own computational block (nearest unitary)
+        Fg1 = _gpu_fid(scp, U, d2)
+        Fo1, _ = oracle_fidelity(Uo, desc["comp_rows"], desc["comp_cols"], d2["target"])
+        assert Fo1 > 0.9
+        assert abs(Fg1 - Fo1) <= DF_TOL, (fused, Fg1, Fo1)
+        g.close()
 
 
 def test_config2_full_near_unit_fidelity(scp):
     desc = si.config2()
-    print("[propagate] config2 full", flush=True)
-    g, U = _gpu_propagate(scp, desc)
     Uo = oracle_propagate(OracleSystem(desc))
     P = Uo[np.ix_(desc["comp_rows"], desc["comp_cols"])]
     u, _, vh = np.linalg.svd(P)
-    for tgt in (desc["target"], u @ vh):
-        d2 = dict(desc, target=tgt)
-        Fg = _gpu_fid(scp, U, d2)
-        Fo, _ = oracle_fidelity(Uo, desc["comp_rows"], desc["comp_cols"], tgt)
-        assert abs(Fg - Fo) <= DF_TOL, (Fg, Fo)
-    g.close()
+    for fused in (False, True):
+        print(f"[propagate] config2 full fused={fused}", flush=True)
+        g, U = _gpu_propagate(scp, desc, fused=fused)
+        for tgt in (desc["target"], u @ vh):
+            d2 = dict(desc, target=tgt)
+            Fg = _gpu_fid(scp, U, d2)
+            Fo, _ = oracle_fidelity(Uo, desc["comp_rows"], desc["comp_cols"], tgt)
+            assert abs(Fg - Fo) <= DF_TOL, (fused, Fg, Fo)
+        g.close()
 
 
 def test_longest_serving_run_keeps_fidelity_near_one(scp):
