@@ -451,7 +451,21 @@ def lindblad_line(scp, si, torch, np, reps=3):
         torch.cuda.synchronize()
         ms.append(ev[0].elapsed_time(ev[1]))
     t = min(ms)
-    F, _ = scp.fidelity_channel(rhoT, scp.ChannelTarget(desc["comp_rows"], desc["target"]))
+    cot = torch.empty_like(rhoT)
+    F, _ = scp.fidelity_channel(rhoT, scp.ChannelTarget(desc["comp_rows"], desc["target"]),
+                                cotangent=cot)
+    # gradient: the adjoint call recomputes the forward with checkpoints, then
+    # walks the segments in reverse (drive parameters, couplings, decay rates)
+    wsa = torch.empty(g.lindblad_adjoint_workspace_bytes(S), dtype=torch.uint8, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    grad = g.lindblad_adjoint(rho0, cot, workspace=wsa)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    tg = ev[0].elapsed_time(ev[1])
+    m_fwd = 2 * rho0.numel() * rho0.element_size()
+    m_grad = m_fwd + wsa.numel()
+    del wsa
     g.close()
     flop = 8.0 * lindblad_macs(desc) * DD * S * 4 * N
     ex = executed_flop("lindblad_open_chain_d3")
@@ -467,11 +481,15 @@ def lindblad_line(scp, si, torch, np, reps=3):
     return {"config": "open system: 4-fluxonium chain d=3 (D=81, D^2=6561), 256 matrix units of "
                       "the 16 computational states, T=100 ns, 5000 RK4 steps, T1/T_phi ~ U[20,60] us",
             "call_ms": t, "F_avg": F,
+            "gradient_call_ms": tg, "n_grad_params": int(len(grad)),
+            "O_t": tg / t, "O_m": m_grad / m_fwd,
+            "O_note": "gradient call (forward with checkpoints + reverse) / forward; "
+                      "gradient-run device bytes / forward-only matrix bytes",
             "steps_dim2_per_s": N * DD * S / (t * 1e-3),
             "roofline": {"bound": "alu", "achieved": flop / (t * 1e-3) / 1e12, "peak": 157.3,
                          "unit": "TFLOP/s", "frac": flop / (t * 1e-3) / PEAK_FP32,
                          "traffic": measured_traffic("lindblad_open_chain_d3"),
-                         "kernel": "lb_rk4_kernel<3,4>", "algorithmic_flop": flop,
+                         "kernel": "g_rk4_kernel<3,4,true,false>", "algorithmic_flop": flop,
                          "executed_tflops": None if ex is None else ex / (t * 1e-3) / 1e12,
                          "executed_frac": None if ex is None else ex / (t * 1e-3) / PEAK_FP32},
             "cpu_oracle": {"steps_dim2_per_s": 5 * DD / dt, "cores": cores,

@@ -530,6 +530,33 @@ scp_status scp_propagate_lindblad(scp_system* sys, const double* gamma1, const d
                                   int32_t n_cols, void* workspace, size_t workspace_bytes,
                                   const void* rho0, void* rhoT, void* stream);
 
+/* Device workspace bytes of scp_lindblad_adjoint for n_cols matrices: the
+ * stage tables, checkpoints (hi and lo words) every ceil(sqrt(n_steps))
+ * steps, one segment of stage inputs and the costate, per matrix. */
+scp_status scp_lindblad_adjoint_workspace_size(const scp_system* sys, int32_t n_cols,
+                                               size_t* bytes);
+
+/* Gradient of a loss of the propagated density matrices by the discrete
+ * adjoint of the Lindblad RK4 steps (the closed system's adjoint, Sec. 2.5,
+ * carried over to open systems as App. D's closing remark says): given the
+ * cotangent of rhoT (device, complex64, as rho0; convention
+ * dLoss = 2 Re sum conj(cotangent) d rhoT, e.g. scp_fidelity_channel's),
+ * grad_out (host) receives dLoss/dtheta for, in this order, the drive
+ * parameters (drive order, then parameter order), the coupling strengths,
+ * then (gamma1_m, gammaphi_m) of every mode: n_pulse + n_couplings + 2 n_modes
+ * values.  The device parameters (E_J, E_C, E_L) are not differentiated here.
+ * The forward is recomputed from rho0 with checkpoints, then each
+ * checkpoint segment is recomputed (its stage inputs stored) and walked in
+ * reverse, one workgroup per matrix; per-matrix FP64 partial sums are added
+ * on the host in a fixed order.  rho0, gamma1, gammaphi as for
+ * scp_propagate_lindblad.  Synchronises the stream.  Errors: SCP_EINVAL
+ * (shape, rates, workspace, more than 4 drive operators, 8 drives or 16
+ * couplings), SCP_ENONFINITE, SCP_EHIP. */
+scp_status scp_lindblad_adjoint(scp_system* sys, const double* gamma1, const double* gammaphi,
+                                int32_t n_cols, void* workspace, size_t workspace_bytes,
+                                const void* rho0, const void* cotangent, double* grad_out,
+                                void* stream);
+
 /* Average gate fidelity of a channel on the computational subspace (App. D,
  * eq. for the average fidelity, with a unitary operator basis normalised to
  * tr(U_j^dag U_k) = d_c delta_jk): rhoT (device, complex64, d_c^2 x D x D)

@@ -68,6 +68,11 @@ EXPORTS = {
     "scp_propagate_lindblad": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,
                                          C.c_void_p, C.c_void_p]),
+    "scp_lindblad_adjoint_workspace_size": (C.c_int, [C.c_void_p, C.c_int32,
+                                                      C.POINTER(C.c_size_t)]),
+    "scp_lindblad_adjoint": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                       C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p,
+                                       C.POINTER(C.c_double), C.c_void_p]),
     "scp_fidelity_channel": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p, C.c_void_p,
                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                        C.c_void_p]),

@@ -256,6 +256,32 @@ class System:
                                            _ptr(rho0), _ptr(rhoT), _stream_ptr(stream)))
         return rhoT
 
+    def lindblad_adjoint_workspace_bytes(self, n_cols):
+        n = C.c_size_t()
+        check(lib().scp_lindblad_adjoint_workspace_size(self.handle, int(n_cols), C.byref(n)))
+        return n.value
+
+    def lindblad_adjoint(self, rho0, cotangent, rates=None, workspace=None, stream=None):
+        """dLoss/dtheta (drive parameters, couplings, then (gamma1, gammaphi)
+        per mode) for the cotangent (S, D, D) complex64 of rho_I(T) of rho0."""
+        assert rho0.dtype == torch.complex64 and rho0.is_contiguous()
+        assert cotangent.dtype == torch.complex64 and cotangent.shape == rho0.shape
+        S = rho0.shape[0]
+        if workspace is None:
+            workspace = torch.empty(self.lindblad_adjoint_workspace_bytes(S), dtype=torch.uint8,
+                                    device=rho0.device)
+        g1, gp = self.rates() if rates is None else rates
+        n = self.n_modes
+        a1 = (C.c_double * n)(*[float(v) for v in g1])
+        ap = (C.c_double * n)(*[float(v) for v in gp])
+        npar = self.n_params - 3 * n + 2 * n     # pulse + couplings + 2 rates per mode
+        g = (C.c_double * max(1, npar))()
+        check(lib().scp_lindblad_adjoint(self.handle, a1, ap, S, _ptr(workspace),
+                                         workspace.numel() * workspace.element_size(),
+                                         _ptr(rho0), _ptr(cotangent.contiguous()), g,
+                                         _stream_ptr(stream)))
+        return np.array(g[:npar])
+
     def opts(self, n_cols, precision=0, ckpt_every=0, with_ckpt=0):
         o = SolveOpts()
         o.n_cols, o.precision, o.ckpt_every, o.with_ckpt = int(n_cols), int(precision), \

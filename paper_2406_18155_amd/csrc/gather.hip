@@ -53,6 +53,10 @@ constexpr int GA_MAXPR = 10;     // coupled mode pairs
 constexpr int GA_MAXC = 4;       // operators summed into one table entry
 constexpr int GA_MAXTAB = 4096;  // complex entries of a stage table
 constexpr int GA_PRE = 4;        // table entries each thread prefetches per stage
+constexpr int GA_MAXSL = 16;     // slots in a gradient table
+constexpr int GA_MAXDS = 4;      // distinct drive slots (gradient)
+constexpr int GA_MAXDR = 8;      // drives (gradient)
+constexpr int GA_MAXCP = 16;     // couplings (gradient)
 
 // Static description of one gather-engine propagation (device copy in the
 // workspace, read through the scalar path where uniform).
@@ -74,6 +78,24 @@ struct GArgs {
   float pr_g[GA_MAXPR][GA_MAXC];
   float g1[GA_MAXM], gp[GA_MAXM];
   float delta[GA_MAXM][8];
+  // gradient (open systems): the table gains the rotated slot operators and
+  // the unit-rate relaxation bands
+  int grad, ntabg, off_s, off_u, nsl;
+  int sl_slot[GA_MAXSL];                             // system slot of each table slot
+  int nds, ds_sl[GA_MAXDS], ds_mode[GA_MAXDS];       // distinct drive slots
+  int ndr, dr_ds[GA_MAXDR], dr_par0[GA_MAXDR], dr_npar[GA_MAXDR];
+  int ncp, cp_i[GA_MAXCP], cp_j[GA_MAXCP], cp_si[GA_MAXCP], cp_sj[GA_MAXCP];
+};
+
+// Checkpoints, costate and gradient buffers of an open-system adjoint.
+struct GAdj {
+  float4* ck;            // [S][nck][L] (hi re, hi im, lo re, lo im) at steps g * ce
+  const float2* cot;     // [S][L] cotangent of the final columns
+  float2* seg;           // [S][ce][4][L] stage inputs of the current segment
+  const double* dctab;   // [3N][npulse] dc/dpar
+  double* part;          // [S][nacc] gradient partial sums
+  float4* lam;           // [S][L] costate (hi, lo) between reverse walks
+  int ce, nck, npulse, nacc;
 };
 
 #define SCP_TRY(expr)                  \
@@ -130,9 +152,22 @@ __global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* 
   const int dd = d * d;
   const c32* ops = (const c32*)A.optab + (size_t)q * A.block_q;
   const float* cq = A.ctab + (size_t)r * A.ngroups;
-  for (int t = threadIdx.x; t < A.ntab; t += blockDim.x) {
+  const int ntot = A.grad ? A.ntabg : A.ntab;
+  for (int t = threadIdx.x; t < ntot; t += blockDim.x) {
     float vr = 0.f, vi = 0.f;
-    if (t < A.off_p) {
+    if (t >= A.ntab) {
+      if (t < A.off_u) {            // rotated slot operator
+        const int u = t - A.off_s;
+        const int k = u / dd, ab = u - k * dd;
+        const c32 o = ops[A.sl_slot[k] * dd + ab];
+        vr = o.x;
+        vi = o.y;
+      } else {                      // unit-rate relaxation band
+        const c32 j = ((const c32*)A.jtab)[((size_t)q * N) * dd + (t - A.off_u)];
+        vr = j.x;
+        vi = j.y;
+      }
+    } else if (t < A.off_p) {
       const int dm = t / dd, ab = t - dm * dd;
       for (int k = 0; k < A.dm_n[dm]; ++k) {
         const float c = cq[A.dm_cidx[dm][k]];
@@ -159,7 +194,7 @@ __global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* 
       vr = A.g1[m] * j.x;
       vi = A.g1[m] * j.y;
     }
-    out[(size_t)r * A.ntab + t] = make_float2(vr, vi);
+    out[(size_t)r * ntot + t] = make_float2(vr, vi);
   }
 }
 
@@ -248,14 +283,16 @@ __device__ __forceinline__ void g_apply(kptr<GArgs> A, const c32* __restrict__ y
   }
 }
 
-template <int d, int N, bool OPEN>
-__global__ void __launch_bounds__((GShape<d, N, OPEN>::T)) g_rk4_kernel(const GArgs* __restrict__ Ag) {
+template <int d, int N, bool OPEN, bool CK>
+__global__ void __launch_bounds__((GShape<d, N, OPEN>::T))
+g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
   using Sh = GShape<d, N, OPEN>;
   constexpr int L = Sh::L, T = Sh::T, E = Sh::E;
   // LDS: two stage-input buffers, the static diagonal, two stage tables
   extern __shared__ c32 lds[];
   kptr<GArgs> A = kconst(Ag);
   const int ntab = A->ntab;
+  const int nrow = A->grad ? A->ntabg : ntab;   // table row stride in gtab
   c32* dgb = lds + 2 * L;
   const c32* gtab = (const c32*)A->gtab;
   const int tid = threadIdx.x;
@@ -305,6 +342,18 @@ __global__ void __launch_bounds__((GShape<d, N, OPEN>::T)) g_rk4_kernel(const GA
   int cur = 0;
 #pragma unroll 1
   for (int n = 0; n < nsteps; ++n) {
+    if (CK) {
+      kptr<GAdj> B = kconst(Bg);
+      const int ce = B->ce;
+      if (n % ce == 0) {
+        float4* ck = B->ck + ((size_t)col * B->nck + n / ce) * L;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const int e = tid + r * T;
+          if (e < L) ck[e] = make_float4(hr[r], hm[r], lr[r], lm[r]);
+        }
+      }
+    }
 #pragma unroll 1
     for (int s = 0; s < 4; ++s) {
       const float w = (s == 0 || s == 3) ? 1.f : 2.f;
@@ -315,7 +364,7 @@ __global__ void __launch_bounds__((GShape<d, N, OPEN>::T)) g_rk4_kernel(const GA
       // the next stage's table, loaded now and stored after this stage
       const int n2 = s < 3 ? n : n + 1, s2 = s < 3 ? s + 1 : 0;
       const bool more = n2 < nsteps;
-      const c32* gnext = gtab + (size_t)stage_c(n2, s2) * ntab;
+      const c32* gnext = gtab + (size_t)stage_c(n2, s2) * nrow;
       c32 pre[GA_PRE];
 #pragma unroll
       for (int k = 0; k < GA_PRE; ++k) {
@@ -371,6 +420,7 @@ __global__ void __launch_bounds__((GShape<d, N, OPEN>::T)) g_rk4_kernel(const GA
       cur ^= 1;
     }
   }
+  if (A->xT == nullptr) return;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int e = tid + r * T;
@@ -381,6 +431,489 @@ __global__ void __launch_bounds__((GShape<d, N, OPEN>::T)) g_rk4_kernel(const GA
       ((c32*)A->xT)[(size_t)col * L + e] = v;
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// open-system adjoint (discrete adjoint of the RK4 steps, as the closed
+// system's: kb_s from the costate, yb_s = L_s^dag kb_s, lambda += sum yb_s,
+// dLoss/dtheta += 2 Re <kb_s, dL_s/dtheta y_s>), one workgroup per column
+// walking the checkpoint segments backwards: each segment is recomputed from
+// its checkpoint with its stage inputs stored, then walked in reverse.
+// ---------------------------------------------------------------------------
+
+// L^dag x for one element: the Hamiltonian part with the opposite sign, the
+// static diagonal conjugated, the relaxation jump transposed
+// (conj(J[a-1][b-1]) x_{A-e_m, B-e_m}).
+template <int d, int N>
+__device__ __forceinline__ void g_apply_adj(kptr<GArgs> A, const c32* __restrict__ xb,
+                                            const c32* __restrict__ tab, int e, uint32_t pk,
+                                            float dgr, float dgi, float xr, float xi, float& yr,
+                                            float& yi) {
+  using Sh = GShape<d, N, true>;
+  constexpr int D = Sh::D, dd = d * d;
+  yr = dgr * xr + dgi * xi;
+  yi = dgr * xi - dgi * xr;
+  if (uni(A->has_jump)) {
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      const int am = ket_digit(pk, m), bm = bra_digit(pk, m, N);
+      if (am > 0 && bm > 0) {
+        const c32 J = tab[A->off_j + m * dd + (am - 1) * d + (bm - 1)];
+        const c32 v = xb[e - (D + 1) * Sh::st(m)];
+        cmac_conj(yr, yi, J, v);
+      }
+    }
+  }
+  const int ndm = uni(A->ndm);
+  for (int dmv = 0; dmv < ndm; ++dmv) {
+    const int dm = uni(dmv);
+    const int m = uni(A->dm_mode[dm]);
+    {
+      const int sm = uni(A->kst[m]);
+      const int am = ket_digit(pk, m);
+      const c32* row = tab + dm * dd + am * d;
+      const c32* x0 = xb + e - am * sm;
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int x = 0; x < d; ++x) cmac(sr, si, row[x], x0[x * sm]);
+      yr -= si;
+      yi += sr;
+    }
+    {
+      const int sm = uni(A->bst[m]);
+      const int bm = bra_digit(pk, m, N);
+      const c32* row = tab + dm * dd + bm * d;
+      const c32* x0 = xb + e - bm * sm;
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int x = 0; x < d; ++x) cmac_conj(sr, si, row[x], x0[x * sm]);
+      yr += si;
+      yi -= sr;
+    }
+  }
+  const int npr = uni(A->npr);
+  for (int pv = 0; pv < npr; ++pv) {
+    const int p = uni(pv);
+    const int i = uni(A->pr_i[p]), j = uni(A->pr_j[p]);
+    const c32* P = tab + A->off_p + p * dd * dd;
+    {
+      const int si_ = uni(A->kst[i]), sj_ = uni(A->kst[j]);
+      const int ai = ket_digit(pk, i), aj = ket_digit(pk, j);
+      const c32* row = P + (ai * d + aj) * dd;
+      const c32* x0 = xb + e - (ai * si_ + aj * sj_);
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int x = 0; x < d; ++x)
+#pragma unroll
+        for (int z = 0; z < d; ++z) cmac(sr, si, row[x * d + z], x0[x * si_ + z * sj_]);
+      yr -= si;
+      yi += sr;
+    }
+    {
+      const int si_ = uni(A->bst[i]), sj_ = uni(A->bst[j]);
+      const int bi = bra_digit(pk, i, N), bj = bra_digit(pk, j, N);
+      const c32* row = P + (bi * d + bj) * dd;
+      const c32* x0 = xb + e - (bi * si_ + bj * sj_);
+      float sr = 0.f, si = 0.f;
+#pragma unroll
+      for (int x = 0; x < d; ++x)
+#pragma unroll
+        for (int z = 0; z < d; ++z) cmac_conj(sr, si, row[x * d + z], x0[x * si_ + z * sj_]);
+      yr += si;
+      yi -= sr;
+    }
+  }
+}
+
+// z = (O kb - kb O) at one element for a one-mode operator O (table rows at
+// `rows`, O Hermitian): the commutator's ket gather minus its bra gather.
+template <int d, int N>
+__device__ __forceinline__ c32 comm1(const c32* __restrict__ kb, const c32* __restrict__ rows,
+                                     int e, int am, int bm, int ks, int bs) {
+  float kr = 0.f, ki = 0.f, br = 0.f, bi = 0.f;
+  const c32* k0 = kb + e - am * ks;
+  const c32* b0 = kb + e - bm * bs;
+#pragma unroll
+  for (int x = 0; x < d; ++x) {
+    cmac(kr, ki, rows[am * d + x], k0[x * ks]);
+    cmac_conj(br, bi, rows[bm * d + x], b0[x * bs]);
+  }
+  c32 z;
+  z.x = kr - br;
+  z.y = ki - bi;
+  return z;
+}
+
+// z = (P kb - kb P) at one element for P = Oi (x) Oj on modes (i, j).
+template <int d, int N>
+__device__ __forceinline__ c32 comm2(const c32* __restrict__ kb, const c32* __restrict__ Ri,
+                                     const c32* __restrict__ Rj, int e, int ai, int aj, int bi,
+                                     int bj, int ksi, int ksj, int bsi, int bsj) {
+  float kr = 0.f, ki = 0.f, br = 0.f, bim = 0.f;
+  const c32* k0 = kb + e - ai * ksi - aj * ksj;
+  const c32* b0 = kb + e - bi * bsi - bj * bsj;
+#pragma unroll
+  for (int x = 0; x < d; ++x) {
+    float ir = 0.f, ii = 0.f, jr = 0.f, ji = 0.f;
+#pragma unroll
+    for (int z = 0; z < d; ++z) {
+      cmac(ir, ii, Rj[aj * d + z], k0[x * ksi + z * ksj]);
+      cmac_conj(jr, ji, Rj[bj * d + z], b0[x * bsi + z * bsj]);
+    }
+    c32 u, w;
+    u.x = ir;
+    u.y = ii;
+    w.x = jr;
+    w.y = ji;
+    cmac(kr, ki, Ri[ai * d + x], u);
+    cmac_conj(br, bim, Ri[bi * d + x], w);
+  }
+  c32 z;
+  z.x = kr - br;
+  z.y = ki - bim;
+  return z;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int d, int N>
+__global__ void __launch_bounds__((GShape<d, N, true>::T))
+g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
+  using Sh = GShape<d, N, true>;
+  constexpr int L = Sh::L, T = Sh::T, E = Sh::E, D = Sh::D, dd = d * d;
+  constexpr int NW = T / 64;
+  extern __shared__ c32 lds[];
+  kptr<GArgs> A = kconst(Ag);
+  kptr<GAdj> B = kconst(Bg);
+  const int ntab = A->ntab, ntabg = A->ntabg;
+  const int nacc = B->nacc, npulse = B->npulse;
+  // LDS: two column buffers (stage inputs while recomputing, kb while
+  // reversing), two stage tables (gradient width), FP64 accumulators, and
+  // per-wave partial sums of the drive-slot terms (two stage parities)
+  c32* tb0 = lds + 2 * L;
+  double* acc = (double*)(lds + 2 * L + 2 * ntabg);
+  float* wsum = (float*)(acc + ((nacc + 1) & ~1));
+  const c32* gtab = (const c32*)A->gtab;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = blockIdx.x;
+  const float h = A->h;
+  const int nsteps = A->nsteps, ce = B->ce, nck = B->nck;
+  const int nds = uni(A->nds), ncp = uni(A->ncp);
+  for (int t = tid; t < nacc; t += T) acc[t] = 0.0;
+  uint32_t pk[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int e = tid + r * T;
+    const int Ai = e / D, Bi = e - Ai * D;
+    uint32_t p = 0;
+#pragma unroll
+    for (int m = 0; m < N; ++m) {
+      p |= (uint32_t)((Ai / Sh::st(m)) % d) << (3 * m);
+      p |= (uint32_t)((Bi / Sh::st(m)) % d) << (3 * (N + m));
+    }
+    pk[r] = p;
+  }
+  // the costate lives in registers only during the reverse walks; between
+  // them (while a segment is recomputed) it waits in device memory
+  float4* lsave = B->lam + (size_t)col * L;
+  c32* segc = (c32*)B->seg + (size_t)col * ce * 4 * L;
+  int prev_row = -1;   // step-grid row of the stage whose drive-slot sums wait in wsum
+  int par = 0;         // parity of the wsum buffer being filled
+  __syncthreads();
+#pragma unroll 1
+  for (int g = nck - 1; g >= 0; --g) {
+    const int n0 = g * ce, n1 = min(nsteps, n0 + ce);
+    // ---- recompute the segment from its checkpoint, storing the stage inputs
+    {
+      float hr[E], hm[E], lr[E], lm[E], ar[E], am_[E];
+      const float4* ck = B->ck + ((size_t)col * nck + g) * L;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const int e = tid + r * T;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (e < L) v = ck[e];
+        hr[r] = v.x;
+        hm[r] = v.y;
+        lr[r] = v.z;
+        lm[r] = v.w;
+        ar[r] = am_[r] = 0.f;
+        if (e < L) {
+          c32 u;
+          u.x = v.x;
+          u.y = v.y;
+          lds[e] = u;
+        }
+      }
+      {
+        const c32* g0 = gtab + (size_t)stage_c(n0, 0) * ntabg;
+        for (int t = tid; t < ntab; t += T) tb0[t] = g0[t];
+      }
+      __syncthreads();
+      int cur = 0;
+#pragma unroll 1
+      for (int n = n0; n < n1; ++n) {
+#pragma unroll 1
+        for (int s = 0; s < 4; ++s) {
+          const float w = (s == 0 || s == 3) ? 1.f : 2.f;
+          const float ch = (s == 2) ? h : 0.5f * h;
+          const c32* yc = lds + cur * L;
+          const c32* tc = tb0 + cur * ntabg;
+          c32* yn = lds + (cur ^ 1) * L;
+          c32* ys = segc + ((size_t)(n - n0) * 4 + s) * L;
+          const int n2 = s < 3 ? n : n + 1, s2 = s < 3 ? s + 1 : 0;
+          const bool more = n2 < n1;
+          const c32* gnext = gtab + (size_t)stage_c(n2, s2) * ntabg;
+          c32 pre[GA_PRE];
+#pragma unroll
+          for (int k = 0; k < GA_PRE; ++k) {
+            const int t = tid + k * T;
+            if (more && t < ntab) pre[k] = gnext[t];
+          }
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            int e = tid + r * T;
+            uint32_t p = pk[r];
+            asm volatile("" : "+v"(e), "+v"(p));
+            if (e < L) {
+              float gr = 0.f, gi = 0.f;
+#pragma unroll
+              for (int m = 0; m < N; ++m) {
+                const int a = ket_digit(p, m), b = bra_digit(p, m, N);
+                gi -= A->delta[m][a] - A->delta[m][b];
+                gr -= 0.5f * A->g1[m] * (float)(a + b) + A->gp[m] * (float)((a - b) * (a - b));
+              }
+              const c32 ye = yc[e];
+              ys[e] = ye;
+              float kr, ki;
+              g_apply<d, N, true>(A, yc, tc, e, p, gr, gi, ye.x, ye.y, kr, ki);
+              if (s == 0) {
+                ar[r] = kr;
+                am_[r] = ki;
+              } else {
+                ar[r] = fmaf(w, kr, ar[r]);
+                am_[r] = fmaf(w, ki, am_[r]);
+              }
+              c32 v;
+              if (s < 3) {
+                v.x = fmaf(ch, kr, hr[r]);
+                v.y = fmaf(ch, ki, hm[r]);
+              } else {
+                const float h6 = h * (1.0f / 6.0f);
+                comp_add(hr[r], lr[r], h6 * ar[r]);
+                comp_add(hm[r], lm[r], h6 * am_[r]);
+                v.x = hr[r];
+                v.y = hm[r];
+              }
+              yn[e] = v;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          if (more) {
+            c32* tn = tb0 + (cur ^ 1) * ntabg;
+#pragma unroll
+            for (int k = 0; k < GA_PRE; ++k) {
+              const int t = tid + k * T;
+              if (t < ntab) tn[t] = pre[k];
+            }
+            for (int t = tid + GA_PRE * T; t < ntab; t += T) tn[t] = gnext[t];
+          }
+          __syncthreads();
+          cur ^= 1;
+        }
+      }
+    }
+    // ---- reverse walk of the segment
+    float lhr[E], lhm[E], llr[E], llm[E];   // costate (hi, lo)
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int e = tid + r * T;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < L) {
+        if (g == nck - 1) {
+          const c32 c = ((const c32*)B->cot)[(size_t)col * L + e];
+          v = make_float4(c.x, c.y, 0.f, 0.f);
+        } else {
+          v = lsave[e];
+        }
+      }
+      lhr[r] = v.x;
+      lhm[r] = v.y;
+      llr[r] = v.z;
+      llm[r] = v.w;
+    }
+    int cur = 0;
+#pragma unroll 1
+    for (int n = n1 - 1; n >= n0; --n) {
+      // yb_{s+1}; the step's increments sum_s yb_s gather in the costate's lo
+      // word (kb_s reads only hi) and are folded into hi at the step's end
+      float ybr[E], ybm[E];
+#pragma unroll
+      for (int r = 0; r < E; ++r) ybr[r] = ybm[r] = 0.f;
+#pragma unroll 1
+      for (int s = 3; s >= 0; --s) {
+        const float cs = (s == 0 || s == 3) ? h * (1.0f / 6.0f) : h * (1.0f / 3.0f);
+        const float cy = (s == 3) ? 0.f : (s == 2 ? h : 0.5f * h);
+        const int row = stage_c(n, s);
+        c32* kbw = lds + cur * L;
+        c32* tw = tb0 + cur * ntabg;
+        // kb_s (own elements) and the stage table into this stage's buffers
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const int e = tid + r * T;
+          if (e < L) {
+            c32 v;
+            v.x = fmaf(cs, lhr[r], cy * ybr[r]);
+            v.y = fmaf(cs, lhm[r], cy * ybm[r]);
+            kbw[e] = v;
+          }
+        }
+        {
+          const c32* gr_ = gtab + (size_t)row * ntabg;
+          for (int t = tid; t < ntabg; t += T) tw[t] = gr_[t];
+        }
+        __syncthreads();
+        // the previous stage's drive-slot sums are complete: fold them into
+        // the pulse-parameter accumulators (one thread per drive)
+        if (prev_row >= 0 && tid < A->ndr) {
+          const int k = tid, ds = A->dr_ds[k];
+          float G = 0.f;
+          for (int w = 0; w < NW; ++w) G += wsum[((par ^ 1) * NW + w) * GA_MAXDS + ds];
+          const double* dct = B->dctab + (size_t)prev_row * npulse;
+          for (int p = A->dr_par0[k]; p < A->dr_par0[k] + A->dr_npar[k]; ++p)
+            acc[p] += dct[p] * (double)G;
+        }
+        const c32* ys = segc + ((size_t)(n - n0) * 4 + s) * L;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          int e = tid + r * T;
+          uint32_t p = pk[r];
+          asm volatile("" : "+v"(e), "+v"(p));
+          if (e < L) {
+            float gr = 0.f, gi = 0.f;
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+              const int a = ket_digit(p, m), b = bra_digit(p, m, N);
+              gi -= A->delta[m][a] - A->delta[m][b];
+              gr -= 0.5f * A->g1[m] * (float)(a + b) + A->gp[m] * (float)((a - b) * (a - b));
+            }
+            const c32 kbe = kbw[e];
+            float yr_, yi_;
+            g_apply_adj<d, N>(A, kbw, tw, e, p, gr, gi, kbe.x, kbe.y, yr_, yi_);
+            ybr[r] = yr_;
+            ybm[r] = yi_;
+            llr[r] += yr_;
+            llm[r] += yi_;
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        // drive slots: 2 Im <O kb - kb O, y>, one sum per wave
+#pragma unroll 1
+        for (int k = 0; k < nds; ++k) {
+          const int m = uni(A->ds_mode[k]);
+          const c32* rows = tw + A->off_s + uni(A->ds_sl[k]) * dd;
+          const int ks = uni(A->kst[m]), bs = uni(A->bst[m]);
+          float v = 0.f;
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            const int e = tid + r * T;
+            if (e < L) {
+              const c32 z = comm1<d, N>(kbw, rows, e, ket_digit(pk[r], m), bra_digit(pk[r], m, N),
+                                        ks, bs);
+              const c32 y = ys[e];
+              v += 2.f * (z.x * y.y - z.y * y.x);
+            }
+          }
+          v = wave_sum(v);
+          if (lane == 0) wsum[(par * NW + wave) * GA_MAXDS + k] = v;
+        }
+        // couplings: 2 Im <P kb - kb P, y>, added to the FP64 sums per wave
+#pragma unroll 1
+        for (int c = 0; c < ncp; ++c) {
+          const int i = uni(A->cp_i[c]), j = uni(A->cp_j[c]);
+          const c32* Ri = tw + A->off_s + uni(A->cp_si[c]) * dd;
+          const c32* Rj = tw + A->off_s + uni(A->cp_sj[c]) * dd;
+          const int ksi = uni(A->kst[i]), ksj = uni(A->kst[j]);
+          const int bsi = uni(A->bst[i]), bsj = uni(A->bst[j]);
+          float v = 0.f;
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            const int e = tid + r * T;
+            if (e < L) {
+              const uint32_t p = pk[r];
+              const c32 z = comm2<d, N>(kbw, Ri, Rj, e, ket_digit(p, i), ket_digit(p, j),
+                                        bra_digit(p, i, N), bra_digit(p, j, N), ksi, ksj, bsi, bsj);
+              const c32 y = ys[e];
+              v += 2.f * (z.x * y.y - z.y * y.x);
+            }
+          }
+          v = wave_sum(v);
+          if (lane == 0) atomicAdd(&acc[npulse + c], (double)v);
+        }
+        // rates: 2 Re <D[a_m]^dag kb, y> and 2 Re <-(a - b)^2 kb, y>
+#pragma unroll 1
+        for (int m = 0; m < N; ++m) {
+          const int sm = (D + 1) * uni(A->bst[m]);
+          const c32* Ju = tw + A->off_u + m * dd;
+          float v1 = 0.f, v2 = 0.f;
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            const int e = tid + r * T;
+            if (e < L) {
+              const int a = ket_digit(pk[r], m), b = bra_digit(pk[r], m, N);
+              const c32 kbe = kbw[e];
+              float zr = -0.5f * (float)(a + b) * kbe.x, zi = -0.5f * (float)(a + b) * kbe.y;
+              if (a > 0 && b > 0) cmac_conj(zr, zi, Ju[(a - 1) * d + (b - 1)], kbw[e - sm]);
+              const c32 y = ys[e];
+              v1 += 2.f * (zr * y.x + zi * y.y);
+              v2 -= 2.f * (float)((a - b) * (a - b)) * (kbe.x * y.x + kbe.y * y.y);
+            }
+          }
+          v1 = wave_sum(v1);
+          v2 = wave_sum(v2);
+          if (lane == 0) {
+            atomicAdd(&acc[npulse + ncp + 2 * m], (double)v1);
+            atomicAdd(&acc[npulse + ncp + 2 * m + 1], (double)v2);
+          }
+        }
+        prev_row = row;
+        par ^= 1;
+        cur ^= 1;
+      }
+      // lambda_n = lambda_{n+1} + sum_s yb_s: fold lo (holding the old lo and
+      // the increments, small next to hi) into hi exactly (fast two-sum)
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        float t = lhr[r] + llr[r];
+        llr[r] -= t - lhr[r];
+        lhr[r] = t;
+        t = lhm[r] + llm[r];
+        llm[r] -= t - lhm[r];
+        lhm[r] = t;
+      }
+    }
+    if (g > 0) {
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const int e = tid + r * T;
+        if (e < L) lsave[e] = make_float4(lhr[r], lhm[r], llr[r], llm[r]);
+      }
+    }
+    __syncthreads();
+  }
+  // the last stage's drive-slot sums
+  if (prev_row >= 0 && tid < A->ndr) {
+    const int k = tid, ds = A->dr_ds[k];
+    float G = 0.f;
+    for (int w = 0; w < NW; ++w) G += wsum[((par ^ 1) * NW + w) * GA_MAXDS + ds];
+    const double* dct = B->dctab + (size_t)prev_row * npulse;
+    for (int p = A->dr_par0[k]; p < A->dr_par0[k] + A->dr_npar[k]; ++p) acc[p] += dct[p] * (double)G;
+  }
+  __syncthreads();
+  for (int t = tid; t < nacc; t += T) B->part[(size_t)col * nacc + t] = acc[t];
 }
 
 // Unit-rate relaxation band of every mode at every half-step q (t = q h/2):
@@ -422,12 +955,23 @@ size_t g_lds_bytes(int ntab) {
 }
 
 template <int d, int N, bool OPEN>
-hipError_t g_launch(const GArgs* dargs, int S, int ntab, hipStream_t s) {
+hipError_t g_launch(const GArgs* dargs, const GAdj* dadj, int S, int ntab, hipStream_t s) {
   using Sh = GShape<d, N, OPEN>;
   const size_t sh = g_lds_bytes<d, N, OPEN>(ntab);
-  (void)hipFuncSetAttribute((const void*)g_rk4_kernel<d, N, OPEN>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL((g_rk4_kernel<d, N, OPEN>), dim3(S), dim3(Sh::T), sh, s, dargs);
+  if constexpr (OPEN) {
+    if (dadj != nullptr) {
+      (void)hipFuncSetAttribute((const void*)g_rk4_kernel<d, N, OPEN, true>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+      hipLaunchKernelGGL((g_rk4_kernel<d, N, OPEN, true>), dim3(S), dim3(Sh::T), sh, s, dargs,
+                         dadj);
+      return hipGetLastError();
+    }
+  }
+  {
+    (void)hipFuncSetAttribute((const void*)g_rk4_kernel<d, N, OPEN, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((g_rk4_kernel<d, N, OPEN, false>), dim3(S), dim3(Sh::T), sh, s, dargs, dadj);
+  }
   return hipGetLastError();
 }
 
@@ -438,11 +982,12 @@ hipError_t g_launch(const GArgs* dargs, int S, int ntab, hipStream_t s) {
 #define GA_CLOSED_SHAPES(X) X(2, 6) X(2, 7) X(2, 8) X(2, 9) X(2, 10) X(3, 4) X(3, 5) X(3, 6) \
   X(3, 7) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(5, 3) X(5, 4) X(5, 5)
 
-hipError_t g_dispatch(int d, int N, bool open, const GArgs* dargs, int S, int ntab, hipStream_t s) {
+hipError_t g_dispatch(int d, int N, bool open, const GArgs* dargs, const GAdj* dadj, int S, int ntab,
+                      hipStream_t s) {
 #define GA_CASE_O(dd_, nn_) \
-  if (open && d == dd_ && N == nn_) return g_launch<dd_, nn_, true>(dargs, S, ntab, s);
+  if (open && d == dd_ && N == nn_) return g_launch<dd_, nn_, true>(dargs, dadj, S, ntab, s);
 #define GA_CASE_C(dd_, nn_) \
-  if (!open && d == dd_ && N == nn_) return g_launch<dd_, nn_, false>(dargs, S, ntab, s);
+  if (!open && d == dd_ && N == nn_) return g_launch<dd_, nn_, false>(dargs, dadj, S, ntab, s);
   GA_OPEN_SHAPES(GA_CASE_O)
   GA_CLOSED_SHAPES(GA_CASE_C)
 #undef GA_CASE_O
@@ -458,6 +1003,45 @@ bool g_supported(int d, int N, bool open) {
 #undef GA_HAS_O
 #undef GA_HAS_C
   return false;
+}
+
+__global__ void store_adj_kernel(GAdj a, GAdj* out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *out = a;
+}
+
+template <int d, int N>
+size_t g_adj_lds_bytes(int ntabg, int nacc) {
+  using Sh = GShape<d, N, true>;
+  return sizeof(c32) * (2 * (size_t)Sh::L + 2 * (size_t)ntabg) +
+         sizeof(double) * (size_t)((nacc + 1) & ~1) + sizeof(float) * 2 * (Sh::T / 64) * GA_MAXDS;
+}
+
+template <int d, int N>
+hipError_t g_adj_launch(const GArgs* dargs, const GAdj* dadj, int S, int ntabg, int nacc,
+                        hipStream_t s) {
+  using Sh = GShape<d, N, true>;
+  const size_t sh = g_adj_lds_bytes<d, N>(ntabg, nacc);
+  if (sh > 163840) return hipErrorInvalidValue;
+  (void)hipFuncSetAttribute((const void*)g_adj_kernel<d, N>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  hipLaunchKernelGGL((g_adj_kernel<d, N>), dim3(S), dim3(Sh::T), sh, s, dargs, dadj);
+  return hipGetLastError();
+}
+
+size_t g_adj_lds(int d, int N, int ntabg, int nacc) {
+#define GA_ADJ_LDS(dd_, nn_) if (d == dd_ && N == nn_) return g_adj_lds_bytes<dd_, nn_>(ntabg, nacc);
+  GA_OPEN_SHAPES(GA_ADJ_LDS)
+#undef GA_ADJ_LDS
+  return ~(size_t)0;
+}
+
+hipError_t g_adj_dispatch(int d, int N, const GArgs* dargs, const GAdj* dadj, int S, int ntabg,
+                          int nacc, hipStream_t s) {
+#define GA_ADJ_CASE(dd_, nn_) \
+  if (d == dd_ && N == nn_) return g_adj_launch<dd_, nn_>(dargs, dadj, S, ntabg, nacc, s);
+  GA_OPEN_SHAPES(GA_ADJ_CASE)
+#undef GA_ADJ_CASE
+  return hipErrorInvalidValue;
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -540,6 +1124,57 @@ static scp_status g_args(const scp_system* sys, bool open, const double* gamma1,
   const size_t L = open ? (size_t)D * D : (size_t)D;
   if ((3 * L + 2 * (size_t)A.ntab) * sizeof(float2) > 163840)
     return fail(SCP_EINVAL, "gather engine: column and stage tables exceed the LDS");
+  A.ntabg = A.ntab;
+  return SCP_OK;
+}
+
+// Gradient description (open systems): table slots, drive slots, drives and
+// couplings; the table rows widen by the slot operators and the unit bands.
+static scp_status g_args_grad(const scp_system* sys, GArgs& A) {
+  const Plan& P = sys->plan;
+  const int N = sys->n_modes, dd = sys->d * sys->d;
+  auto tslot = [&](int s) -> int {
+    for (int k = 0; k < A.nsl; ++k)
+      if (A.sl_slot[k] == s) return k;
+    if (A.nsl >= GA_MAXSL) return -1;
+    A.sl_slot[A.nsl] = s;
+    return A.nsl++;
+  };
+  if (P.ndrives > GA_MAXDR) return fail(SCP_EINVAL, "open-system gradient: too many drives");
+  if (P.ncoup > GA_MAXCP) return fail(SCP_EINVAL, "open-system gradient: too many couplings");
+  A.ndr = P.ndrives;
+  for (int k = 0; k < P.ndrives; ++k) {
+    const int s = P.drives[k].slot;
+    int ds = -1;
+    for (int q = 0; q < A.nds; ++q)
+      if (A.sl_slot[A.ds_sl[q]] == s) ds = q;
+    if (ds < 0) {
+      if (A.nds >= GA_MAXDS) return fail(SCP_EINVAL, "open-system gradient: too many drive operators");
+      const int t = tslot(s);
+      if (t < 0) return fail(SCP_EINVAL, "open-system gradient: too many operator slots");
+      ds = A.nds++;
+      A.ds_sl[ds] = t;
+      A.ds_mode[ds] = P.slot_mode[s];
+    }
+    A.dr_ds[k] = ds;
+    A.dr_par0[k] = P.drives[k].par0;
+    A.dr_npar[k] = P.drives[k].npar;
+  }
+  A.ncp = P.ncoup;
+  for (int e = 0; e < P.ncoup; ++e) {
+    const int si = P.coup_slot_i[e], sj = P.coup_slot_j[e];
+    const int ti = tslot(si), tj = tslot(sj);
+    if (ti < 0 || tj < 0) return fail(SCP_EINVAL, "open-system gradient: too many operator slots");
+    A.cp_i[e] = P.slot_mode[si];
+    A.cp_j[e] = P.slot_mode[sj];
+    A.cp_si[e] = ti;
+    A.cp_sj[e] = tj;
+  }
+  A.grad = 1;
+  A.off_s = A.ntab;
+  A.off_u = A.off_s + A.nsl * dd;
+  A.ntabg = A.off_u + N * dd;
+  if (A.ntabg > GA_MAXTAB) return fail(SCP_EINVAL, "open-system gradient: stage table too large");
   return SCP_OK;
 }
 
@@ -589,7 +1224,7 @@ static scp_status g_run(scp_system* sys, bool open, const double* gamma1, const 
   HIPCHK(hipGetLastError());
   if (S == 0) return SCP_OK;
   hipEvent_t t0 = timing_start(sys, st);
-  HIPCHK(g_dispatch(d, N, open, dargs, S, A.ntab, st));
+  HIPCHK(g_dispatch(d, N, open, dargs, nullptr, S, A.ntab, st));
   timing_stop(sys, t0, 0, st);
   return SCP_OK;
 }
@@ -615,6 +1250,130 @@ scp_status launch_lindblad(scp_system* sys, const double* gamma1, const double* 
                            hipStream_t st) {
   SCP_TRY(lindblad_check(sys));
   return g_run(sys, true, gamma1, gammaphi, S, ws, ws_bytes, rho0, rhoT, st);
+}
+
+// Open-system gradient.  Workspace: [GArgs][GAdj][stage tables [3N][ntabg]]
+// [unit bands [2N+1][N][d*d]][checkpoints [S][nck][L] float4]
+// [stage inputs [S][ce][4][L]][partial sums [S][nacc] double][costate [S][L] float4].
+struct LbAdjLayout {
+  size_t args, adj, gtab, jtab, ck, seg, part, lam, total;
+  int ce, nck, nacc, ntabg;
+};
+
+static scp_status lb_adj_layout(const scp_system* sys, int S, LbAdjLayout& w, GArgs* Aout) {
+  GArgs A;
+  std::vector<double> one(sys->n_modes, 1.0);   // the widest table: relaxation on
+  SCP_TRY(g_args(sys, true, one.data(), nullptr, A));
+  SCP_TRY(g_args_grad(sys, A));
+  const Plan& P = sys->plan;
+  const size_t L = (size_t)sys->D * sys->D, dd = (size_t)sys->d * sys->d;
+  const int N = sys->n_steps;
+  w.ce = (int)std::ceil(std::sqrt((double)N));
+  w.nck = (N + w.ce - 1) / w.ce;
+  w.nacc = P.npulse + P.ncoup + 2 * sys->n_modes;
+  w.ntabg = A.ntabg;
+  size_t off = 0;
+  w.args = off;
+  off += align256(sizeof(GArgs));
+  w.adj = off;
+  off += align256(sizeof(GAdj));
+  w.gtab = off;
+  off += align256(3 * (size_t)N * A.ntabg * sizeof(float2));
+  w.jtab = off;
+  off += align256((2 * (size_t)N + 1) * sys->n_modes * dd * sizeof(float2));
+  w.ck = off;
+  off += align256((size_t)S * w.nck * L * sizeof(float4));
+  w.seg = off;
+  off += align256((size_t)S * w.ce * 4 * L * sizeof(float2));
+  w.part = off;
+  off += align256((size_t)S * w.nacc * sizeof(double));
+  w.lam = off;
+  off += align256((size_t)S * L * sizeof(float4));
+  w.total = off;
+  if (g_adj_lds(sys->d, sys->n_modes, A.ntabg, w.nacc) > 163840)
+    return fail(SCP_EINVAL, "open-system gradient: column and tables exceed the LDS");
+  if (Aout) *Aout = A;
+  return SCP_OK;
+}
+
+scp_status lindblad_adjoint_workspace_bytes(const scp_system* sys, int S, size_t* bytes) {
+  SCP_TRY(lindblad_check(sys));
+  LbAdjLayout w;
+  SCP_TRY(lb_adj_layout(sys, S, w, nullptr));
+  *bytes = w.total;
+  return SCP_OK;
+}
+
+scp_status launch_lindblad_adjoint(scp_system* sys, const double* gamma1, const double* gammaphi,
+                                   int S, void* ws, size_t ws_bytes, const float2* rho0,
+                                   const float2* cot, double* grad, hipStream_t st) {
+  SCP_TRY(lindblad_check(sys));
+  LbAdjLayout w;
+  SCP_TRY(lb_adj_layout(sys, S, w, nullptr));
+  if (ws_bytes < w.total) return fail(SCP_EINVAL, "workspace too small");
+  GArgs A;
+  SCP_TRY(g_args(sys, true, gamma1, gammaphi, A));
+  SCP_TRY(g_args_grad(sys, A));
+  char* base = static_cast<char*>(ws);
+  GArgs* dargs = reinterpret_cast<GArgs*>(base + w.args);
+  GAdj* dadj = reinterpret_cast<GAdj*>(base + w.adj);
+  float2* gtab = reinterpret_cast<float2*>(base + w.gtab);
+  float2* jtab = reinterpret_cast<float2*>(base + w.jtab);
+  const int N = sys->n_modes, d = sys->d;
+  A.optab = sys->d_ops;
+  A.ctab = sys->d_ctab;
+  A.jtab = jtab;
+  A.gtab = gtab;
+  A.x0 = rho0;
+  A.xT = nullptr;
+  A.S = S;
+  GAdj B;
+  std::memset(&B, 0, sizeof(B));
+  B.ck = reinterpret_cast<float4*>(base + w.ck);
+  B.cot = cot;
+  B.seg = reinterpret_cast<float2*>(base + w.seg);
+  B.dctab = sys->d_dctab64;
+  B.part = reinterpret_cast<double*>(base + w.part);
+  B.lam = reinterpret_cast<float4*>(base + w.lam);
+  B.ce = w.ce;
+  B.nck = w.nck;
+  B.npulse = sys->plan.npulse;
+  B.nacc = w.nacc;
+  {
+    JtabStatic js;
+    std::memset(&js, 0, sizeof(js));
+    js.d = d;
+    js.N = N;
+    js.nq = 2 * sys->n_steps + 1;
+    js.h = sys->h;
+    for (int m = 0; m < N; ++m)
+      for (int a = 0; a < d; ++a) js.f[m][a] = sys->modes[m].frame[a];
+    hipLaunchKernelGGL(jtab_kernel, dim3(js.nq), dim3(64), 0, st, js, jtab);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(store_args_kernel, dim3(1), dim3(64), 0, st, A, dargs);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(store_adj_kernel, dim3(1), dim3(64), 0, st, B, dadj);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(gtab_kernel, dim3(3 * sys->n_steps), dim3(256), 0, st, dargs, d, N, gtab);
+  HIPCHK(hipGetLastError());
+  hipEvent_t t0 = timing_start(sys, st);
+  HIPCHK(g_dispatch(d, N, true, dargs, dadj, S, A.ntab, st));
+  timing_stop(sys, t0, 0, st);
+  t0 = timing_start(sys, st);
+  HIPCHK(g_adj_dispatch(d, N, dargs, dadj, S, A.ntabg, w.nacc, st));
+  timing_stop(sys, t0, 2, st);
+  std::vector<double> part((size_t)S * w.nacc);
+  HIPCHK(hipMemcpyAsync(part.data(), base + w.part, part.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < w.nacc; ++k) {
+    double v = 0.0;
+    for (int c = 0; c < S; ++c) v += part[(size_t)c * w.nacc + k];   // fixed order
+    if (!std::isfinite(v)) return fail(SCP_ENONFINITE, "non-finite gradient");
+    grad[k] = v;
+  }
+  return SCP_OK;
 }
 
 // --- closed systems ----------------------------------------------------------

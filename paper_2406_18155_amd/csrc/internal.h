@@ -264,6 +264,10 @@ scp_status launch_lindblad(scp_system* sys, const double* gamma1, const double* 
                            hipStream_t st);
 scp_status launch_fidelity_channel(const void* rhoT, int64_t D, int dc, const int64_t* rows,
                                    const void* target, void* ov, void* cot, hipStream_t st);
+scp_status lindblad_adjoint_workspace_bytes(const scp_system* sys, int S, size_t* bytes);
+scp_status launch_lindblad_adjoint(scp_system* sys, const double* gamma1, const double* gammaphi,
+                                   int S, void* ws, size_t ws_bytes, const float2* rho0,
+                                   const float2* cot, double* grad, hipStream_t st);
 bool gather_preferred(const scp_system* sys, int S);
 size_t gather_workspace_bytes(const scp_system* sys);
 scp_status launch_gather_forward(scp_system* sys, int S, void* ws, size_t ws_bytes,

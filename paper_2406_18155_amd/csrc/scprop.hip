@@ -1054,6 +1054,26 @@ scp_status scp_propagate_lindblad(scp_system* sys, const double* gamma1, const d
                          (const float2*)rho0, (float2*)rhoT, (hipStream_t)stream);
 }
 
+scp_status scp_lindblad_adjoint_workspace_size(const scp_system* sys, int32_t n_cols,
+                                               size_t* bytes) {
+  g_err.clear();
+  if (!sys || !bytes) return fail(SCP_EINVAL, "null argument");
+  if (n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  return lindblad_adjoint_workspace_bytes(sys, n_cols, bytes);
+}
+
+scp_status scp_lindblad_adjoint(scp_system* sys, const double* gamma1, const double* gammaphi,
+                                int32_t n_cols, void* workspace, size_t workspace_bytes,
+                                const void* rho0, const void* cotangent, double* grad_out,
+                                void* stream) {
+  g_err.clear();
+  if (!sys || !workspace || !rho0 || !cotangent || !grad_out) return fail(SCP_EINVAL, "null argument");
+  if (n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  return launch_lindblad_adjoint(sys, gamma1, gammaphi, n_cols, workspace, workspace_bytes,
+                                 (const float2*)rho0, (const float2*)cotangent, grad_out,
+                                 (hipStream_t)stream);
+}
+
 scp_status scp_fidelity_channel(const void* rhoT, int64_t D, int32_t d_c, const int64_t* comp_rows,
                                 const void* target, void* overlap_out, void* cotangent,
                                 double* F_out, void* stream) {

@@ -206,3 +206,102 @@ def test_refusals(scp):
     with pytest.raises(ScpError, match="LDS"):
         g.lindblad_workspace_bytes()
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# gradient (discrete adjoint of the Lindblad RK4 steps)
+# ---------------------------------------------------------------------------
+GRAD_TOL = 1e-4   # max |g - g_oracle| / max |g_oracle|
+
+GRAD_CASES = {
+    # two-level modes, piecewise-constant drives on every mode, one coupling
+    "raw_d2x2_pwc": lambda: dict(_raw(31, [2, 2], 2.0, 120, g1=0.05, gp=0.03, env="pwc"),
+                                 target=si.cz_target(2)),
+    # d = 3, Gaussian drives with carriers, two couplings (a ring of three)
+    "raw_d3x3_gauss": lambda: dict(_raw(32, [3, 3, 3], 1.5, 90, g1=0.04, gp=0.02, env="gauss"),
+                                   target=si.cz_target(3)),
+    # the coupled transmons of the open-system pair workload, 400 steps
+    "pair_strong": lambda: dict(_pair_strong(), n_steps=400, T=8.0),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GRAD_CASES))
+def test_channel_gradient_matches_oracle(scp, name):
+    desc = GRAD_CASES[name]()
+    sys_ = OracleSystem(desc)
+    st = lb.input_states(desc)
+    rho0 = lb.matrix_units(sys_.D, st)
+    L_ref, g_ref = lb.loss_and_grad(sys_)
+    g = scp.System(desc)
+    x = torch.tensor(rho0, dtype=torch.complex64, device="cuda").contiguous()
+    rhoT = g.propagate_lindblad(x)
+    cot = torch.empty_like(rhoT)
+    F, _ = scp.fidelity_channel(rhoT, scp.ChannelTarget(desc["comp_rows"], desc["target"]),
+                                cotangent=cot)
+    grad = g.lindblad_adjoint(x, cot)
+    g.close()
+    names = lb.param_names(sys_)
+    assert len(grad) == len(g_ref) == len(names)
+    err = np.abs(grad - g_ref).max() / np.abs(g_ref).max()
+    worst = names[int(np.argmax(np.abs(grad - g_ref)))]
+    print(f"{name}: L={1 - F:.6f} L_oracle={L_ref:.6f} grad rel err {err:.2e} (worst {worst})")
+    assert abs((1 - F) - L_ref) <= F_TOL
+    assert err <= GRAD_TOL, (err, worst)
+
+
+def test_gradient_of_a_general_cotangent(scp):
+    # mixed input states and a seeded cotangent (not a fidelity's): the adjoint
+    # is linear in the cotangent and exact for any of them
+    desc = _raw(33, [3, 3], 2.0, 100, g1=0.05, gp=0.02, env="gauss")
+    sys_ = OracleSystem(desc)
+    rho0 = si.random_density_matrices(sys_.D, 3, seed=si.BASE_SEED + 90)
+    rng = np.random.Generator(np.random.PCG64(si.BASE_SEED + 91))
+    lam = rng.normal(size=rho0.shape) + 1j * rng.normal(size=rho0.shape)
+    g_ref = lb.gradient(sys_, lam, rho0)
+    g = scp.System(desc)
+    x = torch.tensor(rho0, dtype=torch.complex64, device="cuda").contiguous()
+    c = torch.tensor(lam, dtype=torch.complex64, device="cuda").contiguous()
+    grad = g.lindblad_adjoint(x, c)
+    g.close()
+    err = np.abs(grad - g_ref).max() / np.abs(g_ref).max()
+    print(f"general cotangent: grad rel err {err:.2e}")
+    assert err <= GRAD_TOL
+
+
+def test_gradient_refusals(scp):
+    from paper_2406_18155_amd._lib import ScpError
+    desc = si.open_pair()
+    g = scp.System(desc)
+    x = scp.matrix_units(g.D, [0, 1])
+    small = torch.empty(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ScpError, match="workspace"):
+        g.lindblad_adjoint(x, torch.zeros_like(x), workspace=small)
+    with pytest.raises(ScpError, match="non-negative"):
+        g.lindblad_adjoint(x, torch.zeros_like(x), rates=([0.0, -1.0], [0.0, 0.0]))
+    g.close()
+
+
+def test_workload_shape_gradient_matches_oracle(scp):
+    """The open chain's shape (d = 3, four modes: 1024 threads, seven elements
+    per thread) on a shortened pulse (100 steps over 2 ns), four sampled
+    matrix units and a seeded cotangent on them."""
+    desc = si.open_chain(n_steps=100)
+    desc = dict(desc, T=2.0)
+    desc["modes"] = [dict(m, gamma1=m["gamma1"] * 1000, gammaphi=m["gammaphi"] * 1000)
+                     for m in desc["modes"]]
+    sys_ = OracleSystem(desc)
+    st = lb.input_states(desc)
+    units = lb.matrix_units(sys_.D, st)
+    pick = [0, 5 * len(st) + 5, 3 * len(st) + 12, 15 * len(st) + 9]
+    rho0 = units[pick]
+    rng = np.random.Generator(np.random.PCG64(si.BASE_SEED + 92))
+    lam = rng.normal(size=rho0.shape) + 1j * rng.normal(size=rho0.shape)
+    g_ref = lb.gradient(sys_, lam, rho0)
+    g = scp.System(desc)
+    x = torch.tensor(rho0, dtype=torch.complex64, device="cuda").contiguous()
+    c = torch.tensor(lam, dtype=torch.complex64, device="cuda").contiguous()
+    grad = g.lindblad_adjoint(x, c)
+    g.close()
+    err = np.abs(grad - g_ref).max() / np.abs(g_ref).max()
+    print(f"open chain shape: {len(grad)} params, grad rel err {err:.2e}")
+    assert err <= GRAD_TOL
