@@ -100,12 +100,12 @@ struct TrRun {
 
 static_assert(sizeof(TrRun) <= 4000, "TrRun is passed by value as a kernel argument");
 
-__device__ inline double wrap_2pi(double x) {
+__device__ __forceinline__ double wrap_2pi(double x) {
   const double twopi = 6.283185307179586476925286766559;
   return x - twopi * rint(x / twopi);
 }
 
-__device__ inline double2 cmul(double2 a, double2 b) {
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
@@ -172,7 +172,7 @@ __device__ void expm_taylor(int n, double2* X, double2* E, double2* T, double2* 
 }
 
 // -i a tau (times g for a pair gate): the factor of the generator.
-__device__ inline double2 gate_factor(const TrGen& G, int j, double g) {
+__device__ __forceinline__ double2 gate_factor(const TrGen& G, int j, double g) {
   return make_double2(G.a_im[j] * G.tau * g, -G.a_re[j] * G.tau * g);
 }
 
@@ -302,12 +302,12 @@ __global__ void __launch_bounds__(256) tr_fuse_kernel(int d, int r, int H, int n
 
 // floor(x / n) for 0 <= x, n < 2^26 from inv = 1/n: (x + 1/2) / n lies at
 // least 1/(2n) from an integer, far beyond the rounding of the product.
-__device__ inline int qdiv(int x, double inv) { return (int)(((double)x + 0.5) * inv); }
+__device__ __forceinline__ int qdiv(int x, double inv) { return (int)(((double)x + 0.5) * inv); }
 
 // Fibre f of a single-mode gate on the mode of stride s: the d amplitudes
 // base + a*s, base = hi*s*d + lo with f = hi*s + lo.
 template <int d>
-__device__ inline int fibre1(int f, int s, double inv_s) {
+__device__ __forceinline__ int fibre1(int f, int s, double inv_s) {
   const int hi = qdiv(f, inv_s);
   return hi * s * d + (f - hi * s);
 }
@@ -316,23 +316,26 @@ __device__ inline int fibre1(int f, int s, double inv_s) {
 // b), sp = max, sq = min, w = sp / (sq d): the d^2 amplitudes
 // base + a*si + b*sj, base = hi*sp*d + mid*sq*d + lo with f = (hi*w + mid)*sq + lo.
 template <int d>
-__device__ inline int fibre2(int f, int sp, int sq, int w, double inv_sq, double inv_w) {
+__device__ __forceinline__ int fibre2(int f, int sp, int sq, int w, double inv_sq, double inv_w) {
   const int t = qdiv(f, inv_sq), hi = qdiv(t, inv_w);
   return hi * sp * d + (t - hi * w) * sq * d + (f - t * sq);
 }
 
 // (re, im) += g v as four fused multiply-adds (written as a difference of
 // products the compiler keeps a separate multiply and add per component).
-__device__ inline void cmac(double& re, double& im, double2 g, double2 v) {
+__device__ __forceinline__ void cmac(double& re, double& im, double2 g, double2 v) {
   re = fma(g.x, v.x, re);
   re = fma(-g.y, v.y, re);
   im = fma(g.x, v.y, im);
   im = fma(g.y, v.x, im);
 }
 
-template <int d>
-__device__ inline double2 crow(const double2* __restrict__ g, const double2* x, int n) {
+// Row times a register vector of n entries (n compile-time: the vector stays
+// in registers).
+template <int n>
+__device__ __forceinline__ double2 crow(const double2* __restrict__ g, const double2* x) {
   double re = 0.0, im = 0.0;
+#pragma unroll
   for (int c = 0; c < n; ++c) {
     cmac(re, im, g[c], x[c]);
   }
@@ -341,7 +344,7 @@ __device__ inline double2 crow(const double2* __restrict__ g, const double2* x, 
 
 // In place: a thread owns whole fibres of a single-mode gate.
 template <int d>
-__device__ inline void tr_apply1(double2* L, int D, int s, const double2* __restrict__ Gt) {
+__device__ __forceinline__ void tr_apply1(double2* L, int D, int s, const double2* __restrict__ Gt) {
   const int nf = D / d;
   const double is = 1.0 / s;
   for (int f = threadIdx.x; f < nf; f += blockDim.x) {
@@ -350,13 +353,13 @@ __device__ inline void tr_apply1(double2* L, int D, int s, const double2* __rest
 #pragma unroll
     for (int a = 0; a < d; ++a) x[a] = L[base + a * s];
 #pragma unroll
-    for (int r = 0; r < d; ++r) L[base + r * s] = crow<d>(Gt + r * d, x, d);
+    for (int r = 0; r < d; ++r) L[base + r * s] = crow<d>(Gt + r * d, x);
   }
 }
 
 // A d x d gate on digit 0 (dg = 0) or digit 1 of a fibre x[a * d + b] in registers.
 template <int d, int dg>
-__device__ inline void single_on_digit(const double2* __restrict__ S, double2* x) {
+__device__ __forceinline__ void single_on_digit(const double2* __restrict__ S, double2* x) {
 #pragma unroll
   for (int u = 0; u < d; ++u) {
     double2 t[d];
@@ -377,8 +380,8 @@ __device__ inline void single_on_digit(const double2* __restrict__ S, double2* x
 // In place: a thread owns whole fibres of a pair gate.  For d <= 3 the
 // single-mode gates S0 (digit 0) and S1 (digit 1), when not null, are
 // applied in registers before the pair gate (post = 0) or after it.
-template <int d>
-__device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double2* __restrict__ Gt,
+template <int d, bool OPAQUE = false>
+__device__ __forceinline__ void tr_apply2(double2* L, int D, int si, int sj, const double2* __restrict__ Gt,
                                  const double2* __restrict__ S0, const double2* __restrict__ S1,
                                  int post) {
   constexpr int dd = d * d;
@@ -387,6 +390,13 @@ __device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double
   const int nf = D / dd;
   for (int f = threadIdx.x; f < nf; f += blockDim.x) {
     const int base = fibre2<d>(f, sp, sq, w, isq, iw);
+    // OPAQUE: the gate pointer is made opaque per fibre, so that the d^4
+    // gate entries are loaded where they are used instead of being hoisted
+    // out of the fibre loop into registers (where the LCAM walk, with four
+    // gate kinds in one loop, ran out of them); the forward keeps the
+    // compiler's scalar loads of the read-only gate table
+    const double2* G = Gt;
+    if constexpr (OPAQUE) asm volatile("" : "+s"(G));
     double2 x[dd];
 #pragma unroll
     for (int a = 0; a < d; ++a)
@@ -399,7 +409,7 @@ __device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double
       } else if (S0 || S1) {
         double2 y[dd];
 #pragma unroll
-        for (int r = 0; r < dd; ++r) y[r] = crow<d>(Gt + r * dd, x, dd);
+        for (int r = 0; r < dd; ++r) y[r] = crow<dd>(G + r * dd, x);
         if (S0) single_on_digit<d, 0>(S0, y);
         if (S1) single_on_digit<d, 1>(S1, y);
 #pragma unroll
@@ -412,14 +422,14 @@ __device__ inline void tr_apply2(double2* L, int D, int si, int sj, const double
 #pragma unroll
     for (int a = 0; a < d; ++a)
 #pragma unroll
-      for (int b = 0; b < d; ++b) L[base + a * si + b * sj] = crow<d>(Gt + (a * d + b) * dd, x, dd);
+      for (int b = 0; b < d; ++b) L[base + a * si + b * sj] = crow<dd>(G + (a * d + b) * dd, x);
   }
 }
 
 // Split forms read ``in`` and write ``out`` (the other buffer).  Single-mode
 // gate, one output row per work item w = r * nf + f.
 template <int d>
-__device__ inline void tr_apply1_rows(const double2* in, double2* out, int D, int s,
+__device__ __forceinline__ void tr_apply1_rows(const double2* in, double2* out, int D, int s,
                                       const double2* __restrict__ Gt) {
   const int nf = D / d;
   const double is = 1.0 / s, inf = 1.0 / nf;
@@ -429,7 +439,7 @@ __device__ inline void tr_apply1_rows(const double2* in, double2* out, int D, in
     double2 x[d];
 #pragma unroll
     for (int c = 0; c < d; ++c) x[c] = in[base + c * s];
-    out[base + r * s] = crow<d>(Gt + r * d, x, d);
+    out[base + r * s] = crow<d>(Gt + r * d, x);
   }
 }
 
@@ -439,7 +449,7 @@ __device__ inline void tr_apply1_rows(const double2* in, double2* out, int D, in
 // of 64, stepping by the block size) share their row group; taking it from
 // the first lane makes the gate rows wave-uniform (scalar loads).
 template <int d, int RPI, bool UNI>
-__device__ inline void tr_apply2_rows_as(const double2* in, double2* out, int D, int si, int sj,
+__device__ __forceinline__ void tr_apply2_rows_as(const double2* in, double2* out, int D, int si, int sj,
                                          const double2* __restrict__ Gt) {
   constexpr int dd = d * d;
   const int sp = si > sj ? si : sj, sq = si > sj ? sj : si, w0 = sp / (sq * d);
@@ -459,13 +469,13 @@ __device__ inline void tr_apply2_rows_as(const double2* in, double2* out, int D,
 #pragma unroll
     for (int k = 0; k < RPI; ++k) {
       const int r = g * RPI + k;
-      out[base + (r / d) * si + (r % d) * sj] = crow<d>(Gt + r * dd, x, dd);
+      out[base + (r / d) * si + (r % d) * sj] = crow<dd>(Gt + r * dd, x);
     }
   }
 }
 
 template <int d, int RPI>
-__device__ inline void tr_apply2_rows(const double2* in, double2* out, int D, int si, int sj,
+__device__ __forceinline__ void tr_apply2_rows(const double2* in, double2* out, int D, int si, int sj,
                                       const double2* __restrict__ Gt) {
   if ((D / (d * d)) % 64 == 0)
     tr_apply2_rows_as<d, RPI, true>(in, out, D, si, sj, Gt);
@@ -956,7 +966,7 @@ __global__ void lc_adjoint_table_kernel(const double2* __restrict__ G, double2* 
 }
 
 // exp(-i f T) times x (the frame rotation of the output, undone)
-__device__ inline double2 unrotate(const LcRun& R, int d, int i, double2 v) {
+__device__ __forceinline__ double2 unrotate(const LcRun& R, int d, int i, double2 v) {
   int r = i;
   double th = 0.0;
   for (int m = R.M - 1; m >= 0; --m) {
@@ -972,6 +982,16 @@ __device__ inline double2 unrotate(const LcRun& R, int d, int i, double2 v) {
 // psi_I(T) and lambda_I(T) (un-rotated to the lab frame) and clear this
 // column's pair sums; else continue from psi_st / mu_st.  Ms: [(step - n_lo)
 // r + j) M + m][S][d^2] single-mode sums of this chunk; Mp: [S][r E][d^4].
+// Gate applications of the walk (inverse and adjoint, one- and two-mode).
+template <int d>
+__device__ __forceinline__ void lc_apply1(double2* L, int D, int s, const double2* G) {
+  tr_apply1<d>(L, D, s, G);
+}
+template <int d>
+__device__ __forceinline__ void lc_apply2(double2* L, int D, int si, int sj, const double2* G) {
+  tr_apply2<d, true>(L, D, si, sj, G, nullptr, nullptr, 0);
+}
+
 template <int d>
 __global__ void __launch_bounds__(TR_THREADS)
 lc_walk_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __restrict__ psiT,
@@ -1032,15 +1052,14 @@ lc_walk_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __restrict
         }
         // phase A: psi <- G^-1 psi; mu <- (previous gate)^dag mu
         if (single)
-          tr_apply1<d>(L, R.D, s0, gi);
+          lc_apply1<d>(L, R.D, s0, gi);
         else
-          tr_apply2<d>(L, R.D, s0, s1, gi, nullptr, nullptr, 0);
+          lc_apply2<d>(L, R.D, s0, s1, gi);
         if (pend != nullptr) {
           if (pend_t < R.M)
-            tr_apply1<d>(Lm, R.D, R.stride[pend_t], pend);
+            lc_apply1<d>(Lm, R.D, R.stride[pend_t], pend);
           else
-            tr_apply2<d>(Lm, R.D, R.stride[R.ci[pend_t - R.M]], R.stride[R.cj[pend_t - R.M]], pend,
-                         nullptr, nullptr, 0);
+            lc_apply2<d>(Lm, R.D, R.stride[R.ci[pend_t - R.M]], R.stride[R.cj[pend_t - R.M]], pend);
         }
         __syncthreads();
         // phase B: the gate's local reduced matrix M_AB = sum conj(mu[A]) phi[B]
@@ -1103,10 +1122,9 @@ lc_walk_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __restrict
   }
   if (pend != nullptr) {
     if (pend_t < R.M)
-      tr_apply1<d>(Lm, R.D, R.stride[pend_t], pend);
+      lc_apply1<d>(Lm, R.D, R.stride[pend_t], pend);
     else
-      tr_apply2<d>(Lm, R.D, R.stride[R.ci[pend_t - R.M]], R.stride[R.cj[pend_t - R.M]], pend,
-                   nullptr, nullptr, 0);
+      lc_apply2<d>(Lm, R.D, R.stride[R.ci[pend_t - R.M]], R.stride[R.cj[pend_t - R.M]], pend);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < R.D; i += blockDim.x) {
@@ -1117,7 +1135,7 @@ lc_walk_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __restrict
 
 // Tr(K P) for n x n K (row stride ks) and P given by a functor p(row, col)
 template <typename F>
-__device__ inline double2 trace_kp(const double2* K, int ks, int n, F p) {
+__device__ __forceinline__ double2 trace_kp(const double2* K, int ks, int n, F p) {
   double re = 0.0, im = 0.0;
   for (int a = 0; a < n; ++a)
     for (int b = 0; b < n; ++b) {
