@@ -172,6 +172,28 @@ scp_status scp_system_carriers(const scp_system* sys, double* omega);
 scp_status scp_system_frame(const scp_system* sys, int32_t* real_frame);
 scp_status scp_system_set_frame(scp_system* sys, int32_t real_frame);
 
+/* Engine of the FP32 solves (scp_propagate, scp_propagate_adjoint).
+ * engine 1: the fused register-layout stepper (a column spread over the
+ * threads of a workgroup, several modes per thread in registers; Sec. 2.1's
+ * local terms at compile-time register positions).  engine 2: the gather
+ * engine (one workgroup per column held in LDS, every thread evaluating the
+ * generator on its own elements by gathering their neighbours along the
+ * contracted digits), for devices with 64 <= D <= 4096 and at most 10 modes
+ * whose stage tables fit in LDS; its adjoint needs in addition at most 16
+ * drives on 10 distinct operators, 16 couplings and 16 operator slots, else
+ * that solve runs on engine 1.  engine 0 (the default): engine 2 where it
+ * runs and the columns would occupy fewer than 64 of engine 1's workgroups,
+ * else engine 1.  Both engines compute the same RK4 steps and the same
+ * discrete adjoint in FP32 with a compensated state; results differ by
+ * rounding.  scp_system_set_engine: SCP_EINVAL for engine 2 on a device the
+ * gather engine cannot run; a change forgets the recorded checkpoints.
+ * scp_solve_engine writes (host) which engine a solve with opts (and the
+ * adjoint if with_grad) runs on: 1 or 2 (0 for precision 1, the plain FP64
+ * path).  Not while a call on the system is in flight. */
+scp_status scp_system_set_engine(scp_system* sys, int32_t engine);
+scp_status scp_solve_engine(const scp_system* sys, const scp_solve_opts* opts, int32_t with_grad,
+                            int32_t* engine);
+
 /* Kernel timing for measurement: with enable = 1 every later launch of the
  * fused forward (scp_propagate, and the forward inside scp_propagate_adjoint
  * when psi0 is given), of the segment recompute and of the reverse kernel
@@ -223,14 +245,12 @@ scp_status scp_apply_generator(const scp_system* sys, int32_t step, int32_t stag
  * workspace for scp_propagate_adjoint, and the system records which
  * workspace holds them for which (n_cols, ckpt_every, n_steps); a propagate
  * without checkpoints clears that record.  psi0 and psiT may alias.
- * Precision 0 runs the fused register-layout stepper, except a forward
- * without checkpoints of a system whose columns would occupy fewer than 64
- * of its workgroups (few columns of a small device, 64 <= D <= 4096, at
- * most 10 modes): that
- * one runs on the gather engine, one workgroup per column in LDS, with the
- * same RK4 arithmetic (compensated FP32 state, FP32 stage tables).
- * SCP_EINVAL if opts->workspace_bytes is below scp_workspace_size(opts,
- * with_grad = 0). */
+ * Precision 0 runs on the engine scp_solve_engine names (the fused
+ * register-layout stepper, or for few columns of a small device the gather
+ * engine, one workgroup per column in LDS, with the same RK4 arithmetic:
+ * compensated FP32 state, FP32 stage tables).  The workspace layout is the
+ * engine's.  SCP_EINVAL if opts->workspace_bytes is below
+ * scp_workspace_size(opts, with_grad = 0). */
 scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* workspace,
                          const void* psi0, void* psiT, void* stream);
 
@@ -345,13 +365,16 @@ scp_status scp_fidelity_local(const void* U, int64_t D, int32_t S, int32_t preci
  * order of scp_system_info), given the costate cotangent = dL/dU* of the final
  * state (D x S complex64, device).  The discrete adjoint of Sec. 2.5 (the
  * per-step derivative sum and the costate chain rule) walks the checkpoint
- * segments back, recomputing each segment's states.
+ * segments back, recomputing each segment's states, on the engine
+ * scp_solve_engine(opts, with_grad = 1) names.  The gather engine's reverse
+ * walk is one launch per column for all segments; its per-stage sums are
+ * folded in a fixed order, so both engines' gradients are deterministic.
  *   psi0 != NULL: the checkpoints are first computed here by a forward
  *     propagation of psi0 (D x S complex64, device) into the workspace;
  *   psi0 == NULL: the checkpoints of the system's most recent scp_propagate
  *     are used; it must have run with with_ckpt = 1 on this workspace with the
  *     same n_cols and ckpt_every, and no propagate without checkpoints (nor a
- *     frame switch) may have come after it on this system, nor a propagate of
+ *     frame or engine switch) may have come after it on this system, nor a propagate of
  *     another system on this workspace pointer.  Otherwise SCP_EINVAL, before
  *     any launch.
  * The checkpoints stay valid, so several cotangents may follow one forward.
@@ -375,8 +398,9 @@ scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, vo
  * 16 columns, 5000 steps, needs about 35 MB; 256 columns of D = 6561 do not
  * fit).  Every call on one GPU uses that GPU's one array, so calls that
  * overlap on one GPU (other streams or threads) race and must be serialised
- * by the caller.  Synchronises ``stream``; results are bitwise those of
- * scp_propagate_adjoint with psi0. */
+ * by the caller.  It always runs the register-layout engine (engine 1 of
+ * scp_system_set_engine).  Synchronises ``stream``; results are bitwise those
+ * of scp_propagate_adjoint with psi0 on that engine. */
 scp_status scp_propagate_adjoint_noalloc(scp_system* sys, const scp_solve_opts* opts,
                                          const void* psi0, const void* cotangent,
                                          double* grad_out, void* stream);
@@ -550,7 +574,7 @@ scp_status scp_lindblad_adjoint_workspace_size(const scp_system* sys, int32_t n_
  * reverse, one workgroup per matrix; per-matrix FP64 partial sums are added
  * on the host in a fixed order.  rho0, gamma1, gammaphi as for
  * scp_propagate_lindblad.  Synchronises the stream.  Errors: SCP_EINVAL
- * (shape, rates, workspace, more than 4 drive operators, 8 drives or 16
+ * (shape, rates, workspace, more than 10 drive operators, 16 drives or 16
  * couplings), SCP_ENONFINITE, SCP_EHIP. */
 scp_status scp_lindblad_adjoint(scp_system* sys, const double* gamma1, const double* gammaphi,
                                 int32_t n_cols, void* workspace, size_t workspace_bytes,

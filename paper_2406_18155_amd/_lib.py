@@ -94,6 +94,9 @@ EXPORTS = {
                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p,
                                      C.c_void_p]),
     "scp_system_set_frame": (C.c_int, [C.c_void_p, C.c_int32]),
+    "scp_system_set_engine": (C.c_int, [C.c_void_p, C.c_int32]),
+    "scp_solve_engine": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32,
+                                   C.POINTER(C.c_int32)]),
     "scp_system_set_timing": (C.c_int, [C.c_void_p, C.c_int32]),
     "scp_system_kernel_times": (C.c_int, [C.c_void_p, C.POINTER(C.c_double),
                                           C.POINTER(C.c_int32)]),

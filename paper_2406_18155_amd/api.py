@@ -127,6 +127,21 @@ class System:
         """Choose the real-frame (True) or the complex (False) evaluation."""
         check(lib().scp_system_set_frame(self.handle, 1 if enable else 0))
 
+    ENGINES = {"auto": 0, "register": 1, "gather": 2}
+
+    def set_engine(self, engine):
+        """Engine of the FP32 solves: "auto" (the gather engine for few columns
+        of a small device), "register" (the register-layout stepper) or
+        "gather" (the gather engine wherever it runs)."""
+        check(lib().scp_system_set_engine(self.handle, self.ENGINES[engine]))
+
+    def engine(self, opts, with_grad=False):
+        """"register" or "gather": the engine a solve with these opts runs on
+        ("plain64" for precision 1)."""
+        v = C.c_int32()
+        check(lib().scp_solve_engine(self.handle, C.byref(opts), int(with_grad), C.byref(v)))
+        return {0: "plain64", 1: "register", 2: "gather"}[v.value]
+
     def set_timing(self, enable):
         """Bracket later forward / recompute / reverse launches with HIP events."""
         check(lib().scp_system_set_timing(self.handle, 1 if enable else 0))

@@ -38,8 +38,10 @@
 // diagonal and two stage tables; each thread keeps its elements' state
 // (compensated hi + lo) and the RK4 accumulator in registers.  One barrier
 // per stage.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <vector>
 #include <string>
 
 #include "internal.h"
@@ -54,9 +56,12 @@ constexpr int GA_MAXC = 4;       // operators summed into one table entry
 constexpr int GA_MAXTAB = 4096;  // complex entries of a stage table
 constexpr int GA_PRE = 4;        // table entries each thread prefetches per stage
 constexpr int GA_MAXSL = 16;     // slots in a gradient table
-constexpr int GA_MAXDS = 4;      // distinct drive slots (gradient)
-constexpr int GA_MAXDR = 8;      // drives (gradient)
+constexpr int GA_MAXDS = 10;     // distinct drive slots (gradient)
+constexpr int GA_MAXDR = 16;     // drives (gradient)
 constexpr int GA_MAXCP = 16;     // couplings (gradient)
+constexpr int GA_MAXME = 24;     // coupling ends (closed-system gradient)
+// per-wave partial sums of one stage: drive slots | 3 per mode | couplings
+constexpr int GA_NV = GA_MAXDS + 3 * GA_MAXM + GA_MAXCP;
 
 // Static description of one gather-engine propagation (device copy in the
 // workspace, read through the scalar path where uniform).
@@ -85,6 +90,18 @@ struct GArgs {
   int nds, ds_sl[GA_MAXDS], ds_mode[GA_MAXDS];       // distinct drive slots
   int ndr, dr_ds[GA_MAXDR], dr_par0[GA_MAXDR], dr_npar[GA_MAXDR];
   int ncp, cp_i[GA_MAXCP], cp_j[GA_MAXCP], cp_si[GA_MAXCP], cp_sj[GA_MAXCP];
+  // gradient (closed systems, grad = 2): the table gains the rotated slot
+  // operators, per mode and device parameter the one-mode derivative operator
+  // (sum_k c_k dO_k + d delta), and the derivative slot operators
+  int off_m, off_d, off_dslot;
+  int mdm[GA_MAXM];                                  // driven-mode index of a mode (-1: none)
+  float deps[GA_MAXM][3][8];                         // d delta / d(EJ, EC, EL)
+  float cp_g[GA_MAXCP];
+  // coupling ends grouped by mode and own table slot: me_beg[m] .. me_beg[m+1]
+  // packed (coupling | own slot << 5 | partner slot << 10 | partner mode << 15 |
+  // first side << 20 | last of its own-slot group << 21)
+  int me_beg[GA_MAXM + 1];
+  int me[GA_MAXME];
 };
 
 // Checkpoints, costate and gradient buffers of an open-system adjoint.
@@ -156,16 +173,35 @@ __global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* 
   for (int t = threadIdx.x; t < ntot; t += blockDim.x) {
     float vr = 0.f, vi = 0.f;
     if (t >= A.ntab) {
-      if (t < A.off_u) {            // rotated slot operator
+      if (t < A.off_s + A.nsl * dd) {   // rotated slot operator
         const int u = t - A.off_s;
         const int k = u / dd, ab = u - k * dd;
         const c32 o = ops[A.sl_slot[k] * dd + ab];
         vr = o.x;
         vi = o.y;
-      } else {                      // unit-rate relaxation band
+      } else if (A.grad == 1) {         // unit-rate relaxation band
         const c32 j = ((const c32*)A.jtab)[((size_t)q * N) * dd + (t - A.off_u)];
         vr = j.x;
         vi = j.y;
+      } else if (t < A.off_d) {         // d/dtheta of mode m's one-mode terms
+        const int u = t - A.off_m;
+        const int m = u / (3 * dd), th = (u / dd) % 3, ab = u % dd;
+        const int a = ab / d, b = ab - a * d;
+        if (a == b) vr = A.deps[m][th][a];
+        const int dm = A.mdm[m];
+        if (dm >= 0)
+          for (int k = 0; k < A.dm_n[dm]; ++k) {
+            const float c = cq[A.dm_cidx[dm][k]];
+            const c32 o = ops[A.off_dslot + (A.dm_slot[dm][k] * 3 + th) * dd + ab];
+            vr = fmaf(c, o.x, vr);
+            vi = fmaf(c, o.y, vi);
+          }
+      } else {                          // derivative slot operator
+        const int u = t - A.off_d;
+        const int k = u / (3 * dd), th = (u / dd) % 3, ab = u % dd;
+        const c32 o = ops[A.off_dslot + (A.sl_slot[k] * 3 + th) * dd + ab];
+        vr = o.x;
+        vi = o.y;
       }
     } else if (t < A.off_p) {
       const int dm = t / dd, ab = t - dm * dd;
@@ -443,17 +479,17 @@ g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
 
 // L^dag x for one element: the Hamiltonian part with the opposite sign, the
 // static diagonal conjugated, the relaxation jump transposed
-// (conj(J[a-1][b-1]) x_{A-e_m, B-e_m}).
-template <int d, int N>
+// (conj(J[a-1][b-1]) x_{A-e_m, B-e_m}).  Closed systems: G^dag = i (delta + H).
+template <int d, int N, bool OPEN>
 __device__ __forceinline__ void g_apply_adj(kptr<GArgs> A, const c32* __restrict__ xb,
                                             const c32* __restrict__ tab, int e, uint32_t pk,
                                             float dgr, float dgi, float xr, float xi, float& yr,
                                             float& yi) {
-  using Sh = GShape<d, N, true>;
+  using Sh = GShape<d, N, OPEN>;
   constexpr int D = Sh::D, dd = d * d;
   yr = dgr * xr + dgi * xi;
   yi = dgr * xi - dgi * xr;
-  if (uni(A->has_jump)) {
+  if (OPEN && uni(A->has_jump)) {
 #pragma unroll
     for (int m = 0; m < N; ++m) {
       const int am = ket_digit(pk, m), bm = bra_digit(pk, m, N);
@@ -479,7 +515,7 @@ __device__ __forceinline__ void g_apply_adj(kptr<GArgs> A, const c32* __restrict
       yr -= si;
       yi += sr;
     }
-    {
+    if (OPEN) {
       const int sm = uni(A->bst[m]);
       const int bm = bra_digit(pk, m, N);
       const c32* row = tab + dm * dd + bm * d;
@@ -509,7 +545,7 @@ __device__ __forceinline__ void g_apply_adj(kptr<GArgs> A, const c32* __restrict
       yr -= si;
       yi += sr;
     }
-    {
+    if (OPEN) {
       const int si_ = uni(A->bst[i]), sj_ = uni(A->bst[j]);
       const int bi = bra_digit(pk, i, N), bj = bra_digit(pk, j, N);
       const c32* row = P + (bi * d + bj) * dd;
@@ -580,40 +616,59 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
-template <int d, int N>
-__global__ void __launch_bounds__((GShape<d, N, true>::T))
+// s = sum_x row[x] v[x]
+template <int d>
+__device__ __forceinline__ c32 rowdot(const c32* __restrict__ row, const c32 (&v)[d]) {
+  float sr = 0.f, si = 0.f;
+#pragma unroll
+  for (int x = 0; x < d; ++x) cmac(sr, si, row[x], v[x]);
+  c32 z;
+  z.x = sr;
+  z.y = si;
+  return z;
+}
+
+// Im(conj(a) b)
+__device__ __forceinline__ float im_conj(c32 a, c32 b) { return a.x * b.y - a.y * b.x; }
+
+template <int d, int N, bool OPEN>
+__global__ void __launch_bounds__((GShape<d, N, OPEN>::T))
 g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
-  using Sh = GShape<d, N, true>;
+  using Sh = GShape<d, N, OPEN>;
   constexpr int L = Sh::L, T = Sh::T, E = Sh::E, D = Sh::D, dd = d * d;
   constexpr int NW = T / 64;
+  constexpr int WS = OPEN ? GA_MAXDS : GA_NV;   // per-wave sums of one stage
   extern __shared__ c32 lds[];
   kptr<GArgs> A = kconst(Ag);
   kptr<GAdj> B = kconst(Bg);
   const int ntab = A->ntab, ntabg = A->ntabg;
   const int nacc = B->nacc, npulse = B->npulse;
   // LDS: two column buffers (stage inputs while recomputing, kb while
-  // reversing), two stage tables (gradient width), FP64 accumulators, and
-  // per-wave partial sums of the drive-slot terms (two stage parities)
-  c32* tb0 = lds + 2 * L;
-  double* acc = (double*)(lds + 2 * L + 2 * ntabg);
+  // reversing), for closed systems two more (y while reversing), two stage
+  // tables (gradient width), FP64 accumulators, and per-wave partial sums of
+  // a stage (two stage parities)
+  c32* yb0 = lds + 2 * L;
+  c32* tb0 = lds + (OPEN ? 2 : 4) * L;
+  double* acc = (double*)(tb0 + 2 * ntabg);
   float* wsum = (float*)(acc + ((nacc + 1) & ~1));
   const c32* gtab = (const c32*)A->gtab;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = blockIdx.x;
   const float h = A->h;
   const int nsteps = A->nsteps, ce = B->ce, nck = B->nck;
-  const int nds = uni(A->nds), ncp = uni(A->ncp);
+  const int nds = uni(A->nds), ncp = uni(A->ncp), ndr = uni(A->ndr);
+  const int nv = OPEN ? 0 : 3 * N + ncp;   // closed: device-parameter and coupling sums
   for (int t = tid; t < nacc; t += T) acc[t] = 0.0;
   uint32_t pk[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int e = tid + r * T;
-    const int Ai = e / D, Bi = e - Ai * D;
+    const int Ai = OPEN ? e / D : e, Bi = OPEN ? e - Ai * D : 0;
     uint32_t p = 0;
 #pragma unroll
     for (int m = 0; m < N; ++m) {
       p |= (uint32_t)((Ai / Sh::st(m)) % d) << (3 * m);
-      p |= (uint32_t)((Bi / Sh::st(m)) % d) << (3 * (N + m));
+      if (OPEN) p |= (uint32_t)((Bi / Sh::st(m)) % d) << (3 * (N + m));
     }
     pk[r] = p;
   }
@@ -621,8 +676,27 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
   // them (while a segment is recomputed) it waits in device memory
   float4* lsave = B->lam + (size_t)col * L;
   c32* segc = (c32*)B->seg + (size_t)col * ce * 4 * L;
-  int prev_row = -1;   // step-grid row of the stage whose drive-slot sums wait in wsum
+  int prev_row = -1;   // step-grid row of the stage whose sums wait in wsum
   int par = 0;         // parity of the wsum buffer being filled
+  // fold the previous stage's per-wave sums in a fixed order: the drive slots
+  // into the pulse parameters (one thread per drive, times dc/dpar of that
+  // stage), closed systems' device-parameter and coupling sums as they are
+  auto fold_prev = [&]() {
+    for (int t = tid; t < ndr + nv; t += T) {
+      if (t < ndr) {
+        const int ds = A->dr_ds[t];
+        double G = 0.0;
+        for (int w = 0; w < NW; ++w) G += (double)wsum[((par ^ 1) * NW + w) * WS + ds];
+        const double* dct = B->dctab + (size_t)prev_row * npulse;
+        for (int p = A->dr_par0[t]; p < A->dr_par0[t] + A->dr_npar[t]; ++p) acc[p] += dct[p] * G;
+      } else {
+        const int k = t - ndr;
+        double G = 0.0;
+        for (int w = 0; w < NW; ++w) G += (double)wsum[((par ^ 1) * NW + w) * WS + GA_MAXDS + k];
+        acc[npulse + k] += G;
+      }
+    }
+  };
   __syncthreads();
 #pragma unroll 1
   for (int g = nck - 1; g >= 0; --g) {
@@ -682,14 +756,19 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
               float gr = 0.f, gi = 0.f;
 #pragma unroll
               for (int m = 0; m < N; ++m) {
-                const int a = ket_digit(p, m), b = bra_digit(p, m, N);
-                gi -= A->delta[m][a] - A->delta[m][b];
-                gr -= 0.5f * A->g1[m] * (float)(a + b) + A->gp[m] * (float)((a - b) * (a - b));
+                const int a = ket_digit(p, m);
+                if (OPEN) {
+                  const int b = bra_digit(p, m, N);
+                  gi -= A->delta[m][a] - A->delta[m][b];
+                  gr -= 0.5f * A->g1[m] * (float)(a + b) + A->gp[m] * (float)((a - b) * (a - b));
+                } else {
+                  gi -= A->delta[m][a];
+                }
               }
               const c32 ye = yc[e];
               ys[e] = ye;
               float kr, ki;
-              g_apply<d, N, true>(A, yc, tc, e, p, gr, gi, ye.x, ye.y, kr, ki);
+              g_apply<d, N, OPEN>(A, yc, tc, e, p, gr, gi, ye.x, ye.y, kr, ki);
               if (s == 0) {
                 ar[r] = kr;
                 am_[r] = ki;
@@ -759,8 +838,11 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
         const float cy = (s == 3) ? 0.f : (s == 2 ? h : 0.5f * h);
         const int row = stage_c(n, s);
         c32* kbw = lds + cur * L;
+        c32* ybw = yb0 + cur * L;   // closed systems
         c32* tw = tb0 + cur * ntabg;
-        // kb_s (own elements) and the stage table into this stage's buffers
+        const c32* ys = segc + ((size_t)(n - n0) * 4 + s) * L;
+        // kb_s (own elements), closed systems y_s too, and the stage table
+        // into this stage's buffers
 #pragma unroll
         for (int r = 0; r < E; ++r) {
           const int e = tid + r * T;
@@ -769,6 +851,7 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
             v.x = fmaf(cs, lhr[r], cy * ybr[r]);
             v.y = fmaf(cs, lhm[r], cy * ybm[r]);
             kbw[e] = v;
+            if (!OPEN) ybw[e] = ys[e];
           }
         }
         {
@@ -776,17 +859,8 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
           for (int t = tid; t < ntabg; t += T) tw[t] = gr_[t];
         }
         __syncthreads();
-        // the previous stage's drive-slot sums are complete: fold them into
-        // the pulse-parameter accumulators (one thread per drive)
-        if (prev_row >= 0 && tid < A->ndr) {
-          const int k = tid, ds = A->dr_ds[k];
-          float G = 0.f;
-          for (int w = 0; w < NW; ++w) G += wsum[((par ^ 1) * NW + w) * GA_MAXDS + ds];
-          const double* dct = B->dctab + (size_t)prev_row * npulse;
-          for (int p = A->dr_par0[k]; p < A->dr_par0[k] + A->dr_npar[k]; ++p)
-            acc[p] += dct[p] * (double)G;
-        }
-        const c32* ys = segc + ((size_t)(n - n0) * 4 + s) * L;
+        // the previous stage's sums are complete
+        if (prev_row >= 0) fold_prev();
 #pragma unroll
         for (int r = 0; r < E; ++r) {
           int e = tid + r * T;
@@ -796,13 +870,18 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
             float gr = 0.f, gi = 0.f;
 #pragma unroll
             for (int m = 0; m < N; ++m) {
-              const int a = ket_digit(p, m), b = bra_digit(p, m, N);
-              gi -= A->delta[m][a] - A->delta[m][b];
-              gr -= 0.5f * A->g1[m] * (float)(a + b) + A->gp[m] * (float)((a - b) * (a - b));
+              const int a = ket_digit(p, m);
+              if (OPEN) {
+                const int b = bra_digit(p, m, N);
+                gi -= A->delta[m][a] - A->delta[m][b];
+                gr -= 0.5f * A->g1[m] * (float)(a + b) + A->gp[m] * (float)((a - b) * (a - b));
+              } else {
+                gi -= A->delta[m][a];
+              }
             }
             const c32 kbe = kbw[e];
             float yr_, yi_;
-            g_apply_adj<d, N>(A, kbw, tw, e, p, gr, gi, kbe.x, kbe.y, yr_, yi_);
+            g_apply_adj<d, N, OPEN>(A, kbw, tw, e, p, gr, gi, kbe.x, kbe.y, yr_, yi_);
             ybr[r] = yr_;
             ybm[r] = yi_;
             llr[r] += yr_;
@@ -810,7 +889,7 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
           }
           __builtin_amdgcn_sched_barrier(0);
         }
-        // drive slots: 2 Im <O kb - kb O, y>, one sum per wave
+        // drive slots: 2 Im <O kb - kb O, y> (closed: 2 Im <O kb, y>), one sum per wave
 #pragma unroll 1
         for (int k = 0; k < nds; ++k) {
           const int m = uni(A->ds_mode[k]);
@@ -821,62 +900,151 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
           for (int r = 0; r < E; ++r) {
             const int e = tid + r * T;
             if (e < L) {
-              const c32 z = comm1<d, N>(kbw, rows, e, ket_digit(pk[r], m), bra_digit(pk[r], m, N),
-                                        ks, bs);
-              const c32 y = ys[e];
-              v += 2.f * (z.x * y.y - z.y * y.x);
+              c32 z, y;
+              if constexpr (OPEN) {
+                z = comm1<d, N>(kbw, rows, e, ket_digit(pk[r], m), bra_digit(pk[r], m, N), ks, bs);
+                y = ys[e];
+              } else {
+                const int am = ket_digit(pk[r], m);
+                c32 kv[d];
+#pragma unroll
+                for (int x = 0; x < d; ++x) kv[x] = kbw[e + (x - am) * ks];
+                z = rowdot<d>(rows + am * d, kv);
+                y = ybw[e];
+              }
+              v += 2.f * im_conj(z, y);
             }
           }
           v = wave_sum(v);
-          if (lane == 0) wsum[(par * NW + wave) * GA_MAXDS + k] = v;
+          if (lane == 0) wsum[(par * NW + wave) * WS + k] = v;
         }
-        // couplings: 2 Im <P kb - kb P, y>, added to the FP64 sums per wave
+        if constexpr (OPEN) {
+          // couplings: 2 Im <P kb - kb P, y>, added to the FP64 sums per wave
 #pragma unroll 1
-        for (int c = 0; c < ncp; ++c) {
-          const int i = uni(A->cp_i[c]), j = uni(A->cp_j[c]);
-          const c32* Ri = tw + A->off_s + uni(A->cp_si[c]) * dd;
-          const c32* Rj = tw + A->off_s + uni(A->cp_sj[c]) * dd;
-          const int ksi = uni(A->kst[i]), ksj = uni(A->kst[j]);
-          const int bsi = uni(A->bst[i]), bsj = uni(A->bst[j]);
-          float v = 0.f;
+          for (int c = 0; c < ncp; ++c) {
+            const int i = uni(A->cp_i[c]), j = uni(A->cp_j[c]);
+            const c32* Ri = tw + A->off_s + uni(A->cp_si[c]) * dd;
+            const c32* Rj = tw + A->off_s + uni(A->cp_sj[c]) * dd;
+            const int ksi = uni(A->kst[i]), ksj = uni(A->kst[j]);
+            const int bsi = uni(A->bst[i]), bsj = uni(A->bst[j]);
+            float v = 0.f;
 #pragma unroll
-          for (int r = 0; r < E; ++r) {
-            const int e = tid + r * T;
-            if (e < L) {
-              const uint32_t p = pk[r];
-              const c32 z = comm2<d, N>(kbw, Ri, Rj, e, ket_digit(p, i), ket_digit(p, j),
-                                        bra_digit(p, i, N), bra_digit(p, j, N), ksi, ksj, bsi, bsj);
-              const c32 y = ys[e];
-              v += 2.f * (z.x * y.y - z.y * y.x);
+            for (int r = 0; r < E; ++r) {
+              const int e = tid + r * T;
+              if (e < L) {
+                const uint32_t p = pk[r];
+                const c32 z = comm2<d, N>(kbw, Ri, Rj, e, ket_digit(p, i), ket_digit(p, j),
+                                          bra_digit(p, i, N), bra_digit(p, j, N), ksi, ksj, bsi,
+                                          bsj);
+                const c32 y = ys[e];
+                v += 2.f * (z.x * y.y - z.y * y.x);
+              }
+            }
+            v = wave_sum(v);
+            if (lane == 0) atomicAdd(&acc[npulse + c], (double)v);
+          }
+          // rates: 2 Re <D[a_m]^dag kb, y> and 2 Re <-(a - b)^2 kb, y>
+#pragma unroll 1
+          for (int m = 0; m < N; ++m) {
+            const int sm = (D + 1) * uni(A->bst[m]);
+            const c32* Ju = tw + A->off_u + m * dd;
+            float v1 = 0.f, v2 = 0.f;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+              const int e = tid + r * T;
+              if (e < L) {
+                const int a = ket_digit(pk[r], m), b = bra_digit(pk[r], m, N);
+                const c32 kbe = kbw[e];
+                float zr = -0.5f * (float)(a + b) * kbe.x, zi = -0.5f * (float)(a + b) * kbe.y;
+                if (a > 0 && b > 0) cmac_conj(zr, zi, Ju[(a - 1) * d + (b - 1)], kbw[e - sm]);
+                const c32 y = ys[e];
+                v1 += 2.f * (zr * y.x + zi * y.y);
+                v2 -= 2.f * (float)((a - b) * (a - b)) * (kbe.x * y.x + kbe.y * y.y);
+              }
+            }
+            v1 = wave_sum(v1);
+            v2 = wave_sum(v2);
+            if (lane == 0) {
+              atomicAdd(&acc[npulse + ncp + 2 * m], (double)v1);
+              atomicAdd(&acc[npulse + ncp + 2 * m + 1], (double)v2);
             }
           }
-          v = wave_sum(v);
-          if (lane == 0) atomicAdd(&acc[npulse + c], (double)v);
-        }
-        // rates: 2 Re <D[a_m]^dag kb, y> and 2 Re <-(a - b)^2 kb, y>
+        } else {
+          // Device parameters of mode m and couplings.  <kb, dH y> with dH a
+          // one-mode operator Q on m: 2 Im <Q kb, y> from kb gathered along m.
+          // A two-mode term P_i (x) P_j factors as <(P_i (x) 1) kb, (1 (x) P_j) y>,
+          // so each coupling end needs kb gathered along its own mode and y
+          // along the partner's; the device derivative on the own side is
+          // g (dP_own (x) P_partner), summed over the ends sharing dP_own.
 #pragma unroll 1
-        for (int m = 0; m < N; ++m) {
-          const int sm = (D + 1) * uni(A->bst[m]);
-          const c32* Ju = tw + A->off_u + m * dd;
-          float v1 = 0.f, v2 = 0.f;
+          for (int mv = 0; mv < N; ++mv) {
+            const int m = uni(mv);
+            const int ks = uni(A->kst[m]);
+            const c32* Dm = tw + uni(A->off_m) + m * 3 * dd;
+            c32 kv[E][d];
+            c32 C[E];
+            float v0 = 0.f, v1 = 0.f, v2 = 0.f;
 #pragma unroll
-          for (int r = 0; r < E; ++r) {
-            const int e = tid + r * T;
-            if (e < L) {
-              const int a = ket_digit(pk[r], m), b = bra_digit(pk[r], m, N);
-              const c32 kbe = kbw[e];
-              float zr = -0.5f * (float)(a + b) * kbe.x, zi = -0.5f * (float)(a + b) * kbe.y;
-              if (a > 0 && b > 0) cmac_conj(zr, zi, Ju[(a - 1) * d + (b - 1)], kbw[e - sm]);
-              const c32 y = ys[e];
-              v1 += 2.f * (zr * y.x + zi * y.y);
-              v2 -= 2.f * (float)((a - b) * (a - b)) * (kbe.x * y.x + kbe.y * y.y);
+            for (int r = 0; r < E; ++r) {
+              const int e = tid + r * T;
+              C[r].x = C[r].y = 0.f;
+              if (e < L) {
+                const int am = ket_digit(pk[r], m);
+#pragma unroll
+                for (int x = 0; x < d; ++x) kv[r][x] = kbw[e + (x - am) * ks];
+                const c32 y = ybw[e];
+                v0 += 2.f * im_conj(rowdot<d>(Dm + am * d, kv[r]), y);
+                v1 += 2.f * im_conj(rowdot<d>(Dm + dd + am * d, kv[r]), y);
+                v2 += 2.f * im_conj(rowdot<d>(Dm + 2 * dd + am * d, kv[r]), y);
+              }
             }
-          }
-          v1 = wave_sum(v1);
-          v2 = wave_sum(v2);
-          if (lane == 0) {
-            atomicAdd(&acc[npulse + ncp + 2 * m], (double)v1);
-            atomicAdd(&acc[npulse + ncp + 2 * m + 1], (double)v2);
+            const int k0 = uni(A->me_beg[m]), k1 = uni(A->me_beg[m + 1]);
+#pragma unroll 1
+            for (int kq = k0; kq < k1; ++kq) {
+              const int pkd = uni(A->me[kq]);
+              const int c = pkd & 31, own = (pkd >> 5) & 31, psl = (pkd >> 10) & 31;
+              const int pm = (pkd >> 15) & 31;
+              const bool first = (pkd >> 20) & 1, last = (pkd >> 21) & 1;
+              const float gc = unif(A->cp_g[c]);
+              const int ps = uni(A->kst[pm]);
+              const c32* Ro = tw + A->off_s + own * dd;
+              const c32* Rp = tw + A->off_s + psl * dd;
+              const c32* dR = tw + A->off_d + own * 3 * dd;
+              float vc = 0.f;
+#pragma unroll
+              for (int r = 0; r < E; ++r) {
+                const int e = tid + r * T;
+                if (e < L) {
+                  const int am = ket_digit(pk[r], m), ap = ket_digit(pk[r], pm);
+                  c32 yv[d];
+#pragma unroll
+                  for (int z = 0; z < d; ++z) yv[z] = ybw[e + (z - ap) * ps];
+                  const c32 cp = rowdot<d>(Rp + ap * d, yv);
+                  C[r].x = fmaf(gc, cp.x, C[r].x);
+                  C[r].y = fmaf(gc, cp.y, C[r].y);
+                  if (first) vc += 2.f * im_conj(rowdot<d>(Ro + am * d, kv[r]), cp);
+                  if (last) {
+                    v0 += 2.f * im_conj(rowdot<d>(dR + am * d, kv[r]), C[r]);
+                    v1 += 2.f * im_conj(rowdot<d>(dR + dd + am * d, kv[r]), C[r]);
+                    v2 += 2.f * im_conj(rowdot<d>(dR + 2 * dd + am * d, kv[r]), C[r]);
+                    C[r].x = C[r].y = 0.f;
+                  }
+                }
+              }
+              if (first) {
+                vc = wave_sum(vc);
+                if (lane == 0) wsum[(par * NW + wave) * WS + GA_MAXDS + 3 * N + c] = vc;
+              }
+            }
+            v0 = wave_sum(v0);
+            v1 = wave_sum(v1);
+            v2 = wave_sum(v2);
+            if (lane == 0) {
+              float* wv = wsum + (par * NW + wave) * WS + GA_MAXDS + 3 * m;
+              wv[0] = v0;
+              wv[1] = v1;
+              wv[2] = v2;
+            }
           }
         }
         prev_row = row;
@@ -904,14 +1072,8 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
     }
     __syncthreads();
   }
-  // the last stage's drive-slot sums
-  if (prev_row >= 0 && tid < A->ndr) {
-    const int k = tid, ds = A->dr_ds[k];
-    float G = 0.f;
-    for (int w = 0; w < NW; ++w) G += wsum[((par ^ 1) * NW + w) * GA_MAXDS + ds];
-    const double* dct = B->dctab + (size_t)prev_row * npulse;
-    for (int p = A->dr_par0[k]; p < A->dr_par0[k] + A->dr_npar[k]; ++p) acc[p] += dct[p] * (double)G;
-  }
+  // the last stage's sums
+  if (prev_row >= 0) fold_prev();
   __syncthreads();
   for (int t = tid; t < nacc; t += T) B->part[(size_t)col * nacc + t] = acc[t];
 }
@@ -958,14 +1120,11 @@ template <int d, int N, bool OPEN>
 hipError_t g_launch(const GArgs* dargs, const GAdj* dadj, int S, int ntab, hipStream_t s) {
   using Sh = GShape<d, N, OPEN>;
   const size_t sh = g_lds_bytes<d, N, OPEN>(ntab);
-  if constexpr (OPEN) {
-    if (dadj != nullptr) {
-      (void)hipFuncSetAttribute((const void*)g_rk4_kernel<d, N, OPEN, true>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-      hipLaunchKernelGGL((g_rk4_kernel<d, N, OPEN, true>), dim3(S), dim3(Sh::T), sh, s, dargs,
-                         dadj);
-      return hipGetLastError();
-    }
+  if (dadj != nullptr) {
+    (void)hipFuncSetAttribute((const void*)g_rk4_kernel<d, N, OPEN, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((g_rk4_kernel<d, N, OPEN, true>), dim3(S), dim3(Sh::T), sh, s, dargs, dadj);
+    return hipGetLastError();
   }
   {
     (void)hipFuncSetAttribute((const void*)g_rk4_kernel<d, N, OPEN, false>,
@@ -1009,38 +1168,49 @@ __global__ void store_adj_kernel(GAdj a, GAdj* out) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *out = a;
 }
 
-template <int d, int N>
+template <int d, int N, bool OPEN>
 size_t g_adj_lds_bytes(int ntabg, int nacc) {
-  using Sh = GShape<d, N, true>;
-  return sizeof(c32) * (2 * (size_t)Sh::L + 2 * (size_t)ntabg) +
-         sizeof(double) * (size_t)((nacc + 1) & ~1) + sizeof(float) * 2 * (Sh::T / 64) * GA_MAXDS;
+  using Sh = GShape<d, N, OPEN>;
+  return sizeof(c32) * ((OPEN ? 2 : 4) * (size_t)Sh::L + 2 * (size_t)ntabg) +
+         sizeof(double) * (size_t)((nacc + 1) & ~1) +
+         sizeof(float) * 2 * (Sh::T / 64) * (OPEN ? GA_MAXDS : GA_NV);
 }
 
-template <int d, int N>
+template <int d, int N, bool OPEN>
 hipError_t g_adj_launch(const GArgs* dargs, const GAdj* dadj, int S, int ntabg, int nacc,
                         hipStream_t s) {
-  using Sh = GShape<d, N, true>;
-  const size_t sh = g_adj_lds_bytes<d, N>(ntabg, nacc);
+  using Sh = GShape<d, N, OPEN>;
+  const size_t sh = g_adj_lds_bytes<d, N, OPEN>(ntabg, nacc);
   if (sh > 163840) return hipErrorInvalidValue;
-  (void)hipFuncSetAttribute((const void*)g_adj_kernel<d, N>,
+  (void)hipFuncSetAttribute((const void*)g_adj_kernel<d, N, OPEN>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL((g_adj_kernel<d, N>), dim3(S), dim3(Sh::T), sh, s, dargs, dadj);
+  hipLaunchKernelGGL((g_adj_kernel<d, N, OPEN>), dim3(S), dim3(Sh::T), sh, s, dargs, dadj);
   return hipGetLastError();
 }
 
-size_t g_adj_lds(int d, int N, int ntabg, int nacc) {
-#define GA_ADJ_LDS(dd_, nn_) if (d == dd_ && N == nn_) return g_adj_lds_bytes<dd_, nn_>(ntabg, nacc);
-  GA_OPEN_SHAPES(GA_ADJ_LDS)
-#undef GA_ADJ_LDS
+size_t g_adj_lds(int d, int N, bool open, int ntabg, int nacc) {
+#define GA_ADJ_LDS_O(dd_, nn_) \
+  if (open && d == dd_ && N == nn_) return g_adj_lds_bytes<dd_, nn_, true>(ntabg, nacc);
+#define GA_ADJ_LDS_C(dd_, nn_) \
+  if (!open && d == dd_ && N == nn_) return g_adj_lds_bytes<dd_, nn_, false>(ntabg, nacc);
+  GA_OPEN_SHAPES(GA_ADJ_LDS_O)
+  GA_CLOSED_SHAPES(GA_ADJ_LDS_C)
+#undef GA_ADJ_LDS_O
+#undef GA_ADJ_LDS_C
   return ~(size_t)0;
 }
 
-hipError_t g_adj_dispatch(int d, int N, const GArgs* dargs, const GAdj* dadj, int S, int ntabg,
-                          int nacc, hipStream_t s) {
-#define GA_ADJ_CASE(dd_, nn_) \
-  if (d == dd_ && N == nn_) return g_adj_launch<dd_, nn_>(dargs, dadj, S, ntabg, nacc, s);
-  GA_OPEN_SHAPES(GA_ADJ_CASE)
-#undef GA_ADJ_CASE
+hipError_t g_adj_dispatch(int d, int N, bool open, const GArgs* dargs, const GAdj* dadj, int S,
+                          int ntabg, int nacc, hipStream_t s) {
+#define GA_ADJ_CASE_O(dd_, nn_) \
+  if (open && d == dd_ && N == nn_) return g_adj_launch<dd_, nn_, true>(dargs, dadj, S, ntabg, nacc, s);
+#define GA_ADJ_CASE_C(dd_, nn_) \
+  if (!open && d == dd_ && N == nn_)   \
+    return g_adj_launch<dd_, nn_, false>(dargs, dadj, S, ntabg, nacc, s);
+  GA_OPEN_SHAPES(GA_ADJ_CASE_O)
+  GA_CLOSED_SHAPES(GA_ADJ_CASE_C)
+#undef GA_ADJ_CASE_O
+#undef GA_ADJ_CASE_C
   return hipErrorInvalidValue;
 }
 
@@ -1128,11 +1298,14 @@ static scp_status g_args(const scp_system* sys, bool open, const double* gamma1,
   return SCP_OK;
 }
 
-// Gradient description (open systems): table slots, drive slots, drives and
-// couplings; the table rows widen by the slot operators and the unit bands.
-static scp_status g_args_grad(const scp_system* sys, GArgs& A) {
+// Gradient description: table slots, drive slots, drives and couplings.  Open
+// systems: the table rows widen by the slot operators and the unit bands.
+// Closed systems: by the slot operators, the one-mode derivative operators of
+// every mode and the derivative slot operators; the coupling ends are grouped
+// by mode and own slot.
+static scp_status g_args_grad(const scp_system* sys, bool open, GArgs& A) {
   const Plan& P = sys->plan;
-  const int N = sys->n_modes, dd = sys->d * sys->d;
+  const int N = sys->n_modes, d = sys->d, dd = d * d;
   auto tslot = [&](int s) -> int {
     for (int k = 0; k < A.nsl; ++k)
       if (A.sl_slot[k] == s) return k;
@@ -1140,8 +1313,8 @@ static scp_status g_args_grad(const scp_system* sys, GArgs& A) {
     A.sl_slot[A.nsl] = s;
     return A.nsl++;
   };
-  if (P.ndrives > GA_MAXDR) return fail(SCP_EINVAL, "open-system gradient: too many drives");
-  if (P.ncoup > GA_MAXCP) return fail(SCP_EINVAL, "open-system gradient: too many couplings");
+  if (P.ndrives > GA_MAXDR) return fail(SCP_EINVAL, "gather-engine gradient: too many drives");
+  if (P.ncoup > GA_MAXCP) return fail(SCP_EINVAL, "gather-engine gradient: too many couplings");
   A.ndr = P.ndrives;
   for (int k = 0; k < P.ndrives; ++k) {
     const int s = P.drives[k].slot;
@@ -1149,9 +1322,10 @@ static scp_status g_args_grad(const scp_system* sys, GArgs& A) {
     for (int q = 0; q < A.nds; ++q)
       if (A.sl_slot[A.ds_sl[q]] == s) ds = q;
     if (ds < 0) {
-      if (A.nds >= GA_MAXDS) return fail(SCP_EINVAL, "open-system gradient: too many drive operators");
+      if (A.nds >= GA_MAXDS)
+        return fail(SCP_EINVAL, "gather-engine gradient: too many drive operators");
       const int t = tslot(s);
-      if (t < 0) return fail(SCP_EINVAL, "open-system gradient: too many operator slots");
+      if (t < 0) return fail(SCP_EINVAL, "gather-engine gradient: too many operator slots");
       ds = A.nds++;
       A.ds_sl[ds] = t;
       A.ds_mode[ds] = P.slot_mode[s];
@@ -1164,17 +1338,53 @@ static scp_status g_args_grad(const scp_system* sys, GArgs& A) {
   for (int e = 0; e < P.ncoup; ++e) {
     const int si = P.coup_slot_i[e], sj = P.coup_slot_j[e];
     const int ti = tslot(si), tj = tslot(sj);
-    if (ti < 0 || tj < 0) return fail(SCP_EINVAL, "open-system gradient: too many operator slots");
+    if (ti < 0 || tj < 0) return fail(SCP_EINVAL, "gather-engine gradient: too many operator slots");
     A.cp_i[e] = P.slot_mode[si];
     A.cp_j[e] = P.slot_mode[sj];
     A.cp_si[e] = ti;
     A.cp_sj[e] = tj;
+    A.cp_g[e] = (float)sys->coup[e].g;
   }
-  A.grad = 1;
   A.off_s = A.ntab;
-  A.off_u = A.off_s + A.nsl * dd;
-  A.ntabg = A.off_u + N * dd;
-  if (A.ntabg > GA_MAXTAB) return fail(SCP_EINVAL, "open-system gradient: stage table too large");
+  if (open) {
+    A.grad = 1;
+    A.off_u = A.off_s + A.nsl * dd;
+    A.ntabg = A.off_u + N * dd;
+  } else {
+    A.grad = 2;
+    A.off_dslot = P.off_dslot;
+    for (int m = 0; m < N; ++m) A.mdm[m] = -1;
+    for (int q = 0; q < A.ndm; ++q) A.mdm[A.dm_mode[q]] = q;
+    for (int m = 0; m < N; ++m)
+      for (int th = 0; th < 3; ++th)
+        for (int a = 0; a < d; ++a) A.deps[m][th][a] = (float)sys->modes[m].deps[th][a];
+    // coupling ends of each mode, grouped by the own table slot
+    int k = 0;
+    for (int m = 0; m < N; ++m) {
+      A.me_beg[m] = k;
+      struct End { int own, c, psl, pm, first; };
+      std::vector<End> ends;
+      for (int e = 0; e < P.ncoup; ++e) {
+        if (A.cp_i[e] == m) ends.push_back({A.cp_si[e], e, A.cp_sj[e], A.cp_j[e], 1});
+        if (A.cp_j[e] == m) ends.push_back({A.cp_sj[e], e, A.cp_si[e], A.cp_i[e], 0});
+      }
+      std::stable_sort(ends.begin(), ends.end(),
+                       [](const End& x, const End& y) { return x.own < y.own; });
+      for (size_t q = 0; q < ends.size(); ++q) {
+        if (k >= GA_MAXME) return fail(SCP_EINVAL, "gather-engine gradient: too many coupling ends");
+        const End& x = ends[q];
+        const int last = (q + 1 == ends.size() || ends[q + 1].own != x.own) ? 1 : 0;
+        A.me[k++] = x.c | (x.own << 5) | (x.psl << 10) | (x.pm << 15) | (x.first << 20) |
+                    (last << 21);
+      }
+    }
+    A.me_beg[N] = k;
+    A.off_m = A.off_s + A.nsl * dd;
+    A.off_d = A.off_m + 3 * N * dd;
+    A.off_u = A.off_m;
+    A.ntabg = A.off_d + 3 * A.nsl * dd;
+  }
+  if (A.ntabg > GA_MAXTAB) return fail(SCP_EINVAL, "gather-engine gradient: stage table too large");
   return SCP_OK;
 }
 
@@ -1264,7 +1474,7 @@ static scp_status lb_adj_layout(const scp_system* sys, int S, LbAdjLayout& w, GA
   GArgs A;
   std::vector<double> one(sys->n_modes, 1.0);   // the widest table: relaxation on
   SCP_TRY(g_args(sys, true, one.data(), nullptr, A));
-  SCP_TRY(g_args_grad(sys, A));
+  SCP_TRY(g_args_grad(sys, true, A));
   const Plan& P = sys->plan;
   const size_t L = (size_t)sys->D * sys->D, dd = (size_t)sys->d * sys->d;
   const int N = sys->n_steps;
@@ -1290,7 +1500,7 @@ static scp_status lb_adj_layout(const scp_system* sys, int S, LbAdjLayout& w, GA
   w.lam = off;
   off += align256((size_t)S * L * sizeof(float4));
   w.total = off;
-  if (g_adj_lds(sys->d, sys->n_modes, A.ntabg, w.nacc) > 163840)
+  if (g_adj_lds(sys->d, sys->n_modes, true, A.ntabg, w.nacc) > 163840)
     return fail(SCP_EINVAL, "open-system gradient: column and tables exceed the LDS");
   if (Aout) *Aout = A;
   return SCP_OK;
@@ -1313,7 +1523,7 @@ scp_status launch_lindblad_adjoint(scp_system* sys, const double* gamma1, const 
   if (ws_bytes < w.total) return fail(SCP_EINVAL, "workspace too small");
   GArgs A;
   SCP_TRY(g_args(sys, true, gamma1, gammaphi, A));
-  SCP_TRY(g_args_grad(sys, A));
+  SCP_TRY(g_args_grad(sys, true, A));
   char* base = static_cast<char*>(ws);
   GArgs* dargs = reinterpret_cast<GArgs*>(base + w.args);
   GAdj* dadj = reinterpret_cast<GAdj*>(base + w.adj);
@@ -1361,7 +1571,7 @@ scp_status launch_lindblad_adjoint(scp_system* sys, const double* gamma1, const 
   HIPCHK(g_dispatch(d, N, true, dargs, dadj, S, A.ntab, st));
   timing_stop(sys, t0, 0, st);
   t0 = timing_start(sys, st);
-  HIPCHK(g_adj_dispatch(d, N, dargs, dadj, S, A.ntabg, w.nacc, st));
+  HIPCHK(g_adj_dispatch(d, N, true, dargs, dadj, S, A.ntabg, w.nacc, st));
   timing_stop(sys, t0, 2, st);
   std::vector<double> part((size_t)S * w.nacc);
   HIPCHK(hipMemcpyAsync(part.data(), base + w.part, part.size() * sizeof(double),
@@ -1392,6 +1602,16 @@ bool gather_preferred(const scp_system* sys, int S) {
   return fused_wg < 64;
 }
 
+bool gather_supported(const scp_system* sys) {
+  if (!g_supported(sys->d, sys->n_modes, false)) return false;
+  GArgs A;
+  if (g_args(sys, false, nullptr, nullptr, A) != SCP_OK) {
+    set_error("");
+    return false;
+  }
+  return true;
+}
+
 size_t gather_workspace_bytes(const scp_system* sys) {
   GArgs A;
   if (g_args(sys, false, nullptr, nullptr, A) != SCP_OK) {
@@ -1404,6 +1624,146 @@ size_t gather_workspace_bytes(const scp_system* sys) {
 scp_status launch_gather_forward(scp_system* sys, int S, void* ws, size_t ws_bytes,
                                  const float2* psi0, float2* psiT, hipStream_t st) {
   return g_run(sys, false, nullptr, nullptr, S, ws, ws_bytes, psi0, psiT, st);
+}
+
+// Closed-system gradient on the gather engine.  Workspace: [GArgs][GAdj]
+// [stage tables [3N][ntabg]][checkpoints [S][nck][D] float4] and, for the
+// adjoint, [stage inputs [S][ce][4][D]][partial sums [S][nacc] double]
+// [costate [S][D] float4].  The forward with checkpoints and the adjoint
+// share the offsets of the first four.
+struct GcLayout {
+  size_t args, adj, gtab, ck, seg, part, lam, total;
+  int nck, nacc;
+};
+
+static scp_status gc_layout(const scp_system* sys, int S, int ce, bool with_grad, GcLayout& w,
+                            GArgs* Aout) {
+  if (!g_supported(sys->d, sys->n_modes, false))
+    return fail(SCP_EINVAL, "gather engine: no compiled stepper for this d and mode count");
+  GArgs A;
+  SCP_TRY(g_args(sys, false, nullptr, nullptr, A));
+  SCP_TRY(g_args_grad(sys, false, A));
+  const size_t L = (size_t)sys->D;
+  const int N = sys->n_steps;
+  w.nck = (N + ce - 1) / ce;
+  w.nacc = sys->plan.npulse + 3 * sys->n_modes + sys->plan.ncoup;
+  size_t off = 0;
+  w.args = off;
+  off += align256(sizeof(GArgs));
+  w.adj = off;
+  off += align256(sizeof(GAdj));
+  w.gtab = off;
+  off += align256(3 * (size_t)N * A.ntabg * sizeof(float2));
+  w.ck = off;
+  off += align256((size_t)S * w.nck * L * sizeof(float4));
+  w.seg = w.part = w.lam = off;
+  if (with_grad) {
+    w.seg = off;
+    off += align256((size_t)S * ce * 4 * L * sizeof(float2));
+    w.part = off;
+    off += align256((size_t)S * w.nacc * sizeof(double));
+    w.lam = off;
+    off += align256((size_t)S * L * sizeof(float4));
+  }
+  w.total = off;
+  if (g_adj_lds(sys->d, sys->n_modes, false, A.ntabg, w.nacc) > 163840)
+    return fail(SCP_EINVAL, "gather-engine gradient: column and tables exceed the LDS");
+  if (Aout) *Aout = A;
+  return SCP_OK;
+}
+
+scp_status gather_grad_check(const scp_system* sys) {
+  GcLayout w;
+  return gc_layout(sys, 1, 1, true, w, nullptr);
+}
+
+size_t gather_grad_workspace_bytes(const scp_system* sys, int S, int ce, bool with_grad) {
+  GcLayout w;
+  if (gc_layout(sys, S, ce, with_grad, w, nullptr) != SCP_OK) {
+    set_error("");
+    return 0;
+  }
+  return w.total;
+}
+
+// Args and adjoint description into the workspace (and the stage tables when
+// `tables`).
+static scp_status gc_prepare(scp_system* sys, int S, int ce, bool with_grad, char* base,
+                             size_t ws_bytes, const float2* x0, float2* xT, const float2* cot,
+                             bool tables, GcLayout& w, GArgs& A, hipStream_t st) {
+  SCP_TRY(gc_layout(sys, S, ce, with_grad, w, &A));
+  if (ws_bytes < w.total) return fail(SCP_EINVAL, "workspace too small");
+  GArgs* dargs = reinterpret_cast<GArgs*>(base + w.args);
+  GAdj* dadj = reinterpret_cast<GAdj*>(base + w.adj);
+  float2* gtab = reinterpret_cast<float2*>(base + w.gtab);
+  A.optab = sys->d_ops;
+  A.ctab = sys->d_ctab;
+  A.jtab = nullptr;
+  A.gtab = gtab;
+  A.x0 = x0;
+  A.xT = xT;
+  A.S = S;
+  GAdj B;
+  std::memset(&B, 0, sizeof(B));
+  B.ck = reinterpret_cast<float4*>(base + w.ck);
+  B.cot = cot;
+  B.seg = with_grad ? reinterpret_cast<float2*>(base + w.seg) : nullptr;
+  B.dctab = sys->d_dctab64;
+  B.part = with_grad ? reinterpret_cast<double*>(base + w.part) : nullptr;
+  B.lam = with_grad ? reinterpret_cast<float4*>(base + w.lam) : nullptr;
+  B.ce = ce;
+  B.nck = w.nck;
+  B.npulse = sys->plan.npulse;
+  B.nacc = w.nacc;
+  hipLaunchKernelGGL(store_args_kernel, dim3(1), dim3(64), 0, st, A, dargs);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(store_adj_kernel, dim3(1), dim3(64), 0, st, B, dadj);
+  HIPCHK(hipGetLastError());
+  if (tables) {
+    hipLaunchKernelGGL(gtab_kernel, dim3(3 * sys->n_steps), dim3(256), 0, st, dargs, sys->d,
+                       sys->n_modes, gtab);
+    HIPCHK(hipGetLastError());
+  }
+  return SCP_OK;
+}
+
+scp_status launch_gather_ckpt_forward(scp_system* sys, int S, int ce, void* ws, size_t ws_bytes,
+                                      const float2* psi0, float2* psiT, hipStream_t st) {
+  char* base = static_cast<char*>(ws);
+  GcLayout w;
+  GArgs A;
+  SCP_TRY(gc_prepare(sys, S, ce, false, base, ws_bytes, psi0, psiT, nullptr, true, w, A, st));
+  hipEvent_t t0 = timing_start(sys, st);
+  HIPCHK(g_dispatch(sys->d, sys->n_modes, false, reinterpret_cast<GArgs*>(base + w.args),
+                    reinterpret_cast<GAdj*>(base + w.adj), S, A.ntab, st));
+  timing_stop(sys, t0, 0, st);
+  return SCP_OK;
+}
+
+// The reverse walk from the checkpoints (and stage tables) that
+// launch_gather_ckpt_forward left in the same workspace; the gradient is the
+// fixed-order sum of the columns' partial sums.
+scp_status launch_gather_adjoint(scp_system* sys, int S, int ce, void* ws, size_t ws_bytes,
+                                 const float2* cot, double* grad, hipStream_t st) {
+  char* base = static_cast<char*>(ws);
+  GcLayout w;
+  GArgs A;
+  SCP_TRY(gc_prepare(sys, S, ce, true, base, ws_bytes, nullptr, nullptr, cot, false, w, A, st));
+  hipEvent_t t0 = timing_start(sys, st);
+  HIPCHK(g_adj_dispatch(sys->d, sys->n_modes, false, reinterpret_cast<GArgs*>(base + w.args),
+                        reinterpret_cast<GAdj*>(base + w.adj), S, A.ntabg, w.nacc, st));
+  timing_stop(sys, t0, 2, st);
+  std::vector<double> part((size_t)S * w.nacc);
+  HIPCHK(hipMemcpyAsync(part.data(), base + w.part, part.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < w.nacc; ++k) {
+    double v = 0.0;
+    for (int c = 0; c < S; ++c) v += part[(size_t)c * w.nacc + k];   // fixed order
+    if (!std::isfinite(v)) return fail(SCP_ENONFINITE, "gradient is not finite");
+    grad[k] = v;
+  }
+  return SCP_OK;
 }
 
 // ---------------------------------------------------------------------------

@@ -200,6 +200,9 @@ struct scp_system {
   // kernel timing (scp_system_set_timing): HIP events recorded on the launch
   // stream around each forward, recompute and reverse launch
   bool timing = false;
+  // engine of the FP32 solves (scp_system_set_engine): 0 automatic, 1 the
+  // register-layout stepper, 2 the gather engine where it runs
+  int engine = 0;
   mutable std::vector<hipEvent_t> tev;   // recorded events (start, stop pairs)
   mutable std::vector<int> tkind;        // kind of each pair: 0 forward, 1 recompute, 2 reverse
 };
@@ -269,8 +272,15 @@ scp_status launch_lindblad_adjoint(scp_system* sys, const double* gamma1, const 
                                    int S, void* ws, size_t ws_bytes, const float2* rho0,
                                    const float2* cot, double* grad, hipStream_t st);
 bool gather_preferred(const scp_system* sys, int S);
+bool gather_supported(const scp_system* sys);
 size_t gather_workspace_bytes(const scp_system* sys);
 scp_status launch_gather_forward(scp_system* sys, int S, void* ws, size_t ws_bytes,
                                  const float2* psi0, float2* psiT, hipStream_t st);
+scp_status gather_grad_check(const scp_system* sys);
+size_t gather_grad_workspace_bytes(const scp_system* sys, int S, int ce, bool with_grad);
+scp_status launch_gather_ckpt_forward(scp_system* sys, int S, int ce, void* ws, size_t ws_bytes,
+                                      const float2* psi0, float2* psiT, hipStream_t st);
+scp_status launch_gather_adjoint(scp_system* sys, int S, int ce, void* ws, size_t ws_bytes,
+                                 const float2* cot, double* grad, hipStream_t st);
 
 }  // namespace scp

@@ -818,10 +818,15 @@ scp_status build(const scp_system_desc* ds, hipStream_t st, scp_system* sys) {
 struct WsLayout {
   size_t lo = 0, ckpt = 0, seg = 0, part = 0, lam = 0, lamstate = 0, total = 0;
   int nckpt = 0, ce = 0, nwg = 0;
-  bool gather = false;   // a forward-only FP32 solve on the gather engine (workspace from 0)
+  bool gather = false;        // a forward-only FP32 solve on the gather engine (workspace from 0)
+  bool gather_grad = false;   // checkpoints / adjoint on the gather engine (its own layout)
 };
 
-WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad) {
+// Which engine runs an FP32 solve: the system's choice, else (automatic) the
+// gather engine when the register-layout stepper would leave most of the chip
+// idle.  allow_gather = false keeps the register-layout engine.
+WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad,
+                   bool allow_gather = true) {
   WsLayout w;
   const int N = sys->n_steps;
   w.ce = o->ckpt_every > 0 ? o->ckpt_every : (int)std::ceil(std::sqrt((double)N));
@@ -829,9 +834,20 @@ WsLayout ws_layout(const scp_system* sys, const scp_solve_opts* o, int with_grad
   const size_t S = (size_t)o->n_cols, D = (size_t)sys->D;
   size_t off = 0;
   auto align = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  if (o->precision == 0 && !o->with_ckpt && !with_grad && gather_preferred(sys, (int)S)) {
+  const int engine = allow_gather ? sys->engine : 1;
+  bool want = false;
+  if (o->precision == 0 && engine != 1)
+    want = engine == 2 ? gather_supported(sys) : gather_preferred(sys, (int)S);
+  if (want && (o->with_ckpt || with_grad)) {
+    want = gather_grad_check(sys) == SCP_OK;
+    if (!want) set_error("");
+  }
+  if (want && !o->with_ckpt && !with_grad) {
     w.gather = true;
     off = gather_workspace_bytes(sys);
+  } else if (want) {
+    w.gather_grad = true;
+    off = gather_grad_workspace_bytes(sys, (int)S, w.ce, with_grad != 0);
   } else if (o->precision == 0) {
     w.lo = off;
     off = align(off + S * D * sizeof(float2));
@@ -938,6 +954,32 @@ scp_status scp_system_set_frame(scp_system* sys, int32_t real_frame) {
   return SCP_OK;
 }
 
+scp_status scp_system_set_engine(scp_system* sys, int32_t engine) {
+  g_err.clear();
+  if (!sys) return fail(SCP_EINVAL, "null argument");
+  if (engine < 0 || engine > 2) return fail(SCP_EINVAL, "engine must be 0, 1 or 2");
+  if (engine == 2 && !gather_supported(sys))
+    return fail(SCP_EINVAL, "the gather engine has no stepper for this device (64 <= D <= 4096, "
+                            "at most 10 modes, tables within the LDS)");
+  if (sys->engine != engine) ck_clear(sys);   // checkpoints of the other engine's layout
+  sys->engine = engine;
+  return SCP_OK;
+}
+
+scp_status scp_solve_engine(const scp_system* sys, const scp_solve_opts* opts, int32_t with_grad,
+                            int32_t* engine) {
+  g_err.clear();
+  if (!sys || !opts || !engine) return fail(SCP_EINVAL, "null argument");
+  if (opts->n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  if (opts->precision != 0) {
+    *engine = 0;
+    return SCP_OK;
+  }
+  const WsLayout w = ws_layout(sys, opts, with_grad);
+  *engine = (w.gather || w.gather_grad) ? 2 : 1;
+  return SCP_OK;
+}
+
 scp_status scp_system_set_timing(scp_system* sys, int32_t enable) {
   g_err.clear();
   if (!sys || (enable != 0 && enable != 1)) return fail(SCP_EINVAL, "bad argument");
@@ -1007,6 +1049,14 @@ scp_status scp_propagate(scp_system* sys, const scp_solve_opts* opts, void* work
     ck_clear(sys);
     return launch_gather_forward(sys, opts->n_cols, workspace, opts->workspace_bytes,
                                  (const float2*)psi0, (float2*)psiT, st);
+  }
+  if (w.gather_grad) {
+    ck_clear(sys);
+    scp_status s = launch_gather_ckpt_forward(sys, opts->n_cols, w.ce, workspace,
+                                              opts->workspace_bytes, (const float2*)psi0,
+                                              (float2*)psiT, st);
+    if (s == SCP_OK) ck_record(sys, workspace, opts->n_cols, w.ce);
+    return s;
   }
   float4* ck = opts->with_ckpt ? (float4*)((char*)workspace + w.ckpt) : nullptr;
   ck_clear(sys);
@@ -1204,6 +1254,24 @@ scp_status scp_propagate_adjoint(scp_system* sys, const scp_solve_opts* opts, vo
                                 " the adjoint needs (scp_workspace_size with_grad = 1)");
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
+  if (w.gather_grad) {
+    if (psi0 != nullptr) {
+      ck_claim(sys, workspace);
+      ck_clear(sys);
+      scp_status s = launch_gather_ckpt_forward(sys, opts->n_cols, w.ce, workspace,
+                                                opts->workspace_bytes, (const float2*)psi0,
+                                                nullptr, st);
+      if (s != SCP_OK) return s;
+      ck_record(sys, workspace, opts->n_cols, w.ce);
+    } else if (!ck_valid(sys, workspace, opts->n_cols, w.ce)) {
+      return fail(SCP_EINVAL,
+                  "no checkpoints of this system for this workspace and opts: the last "
+                  "scp_propagate must run with with_ckpt = 1 on the same workspace, n_cols and "
+                  "ckpt_every (or pass psi0)");
+    }
+    return launch_gather_adjoint(sys, opts->n_cols, w.ce, workspace, opts->workspace_bytes,
+                                 (const float2*)cotangent, grad_out, st);
+  }
   if (psi0 != nullptr) {
     ck_claim(sys, workspace);
     ck_clear(sys);
@@ -1285,7 +1353,7 @@ scp_status scp_propagate_adjoint_noalloc(scp_system* sys, const scp_solve_opts* 
   if (opts->precision != 0) return fail(SCP_EINVAL, "the adjoint runs on the FP32 path (precision 0)");
   if (opts->n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
   if (opts->ckpt_every < 0) return fail(SCP_EINVAL, "ckpt_every must be >= 0");
-  WsLayout w = ws_layout(sys, opts, 1);
+  WsLayout w = ws_layout(sys, opts, 1, false);
   if (w.total > SCP_NOALLOC_SCRATCH_BYTES)
     return fail(SCP_EINVAL, "the adjoint needs " + std::to_string(w.total) +
                                 " bytes of workspace; the static scratch holds " +

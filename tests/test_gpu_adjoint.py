@@ -47,10 +47,13 @@ def _chain(n_modes, d, T, n, seed=0):
     return si._finish(s, [d] * n_modes, target=si.cz_target(n_modes))
 
 
-def gpu_loss_and_grad(scp, desc, ckpt_every=0):
+def gpu_loss_and_grad(scp, desc, ckpt_every=0, engine="auto"):
     g = scp.System(desc)
+    g.set_engine(engine)
     psi0 = scp.basis_columns(g.D, desc["columns"])
     opts = g.opts(psi0.shape[0], ckpt_every=ckpt_every, with_ckpt=1)
+    if engine != "auto":
+        assert g.engine(opts, with_grad=True) == engine
     ws = g.workspace(opts, with_grad=True)
     U = g.propagate(psi0, opts=opts, workspace=ws)
     tgt = scp.Target(desc["comp_rows"], desc["comp_cols"], desc["target"])
@@ -113,11 +116,17 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("name", list(CASES))
-def test_adjoint_matches_oracle_gradient(scp, name):
+# devices the gather engine runs (64 <= D <= 4096): their gradient is checked
+# on both engines
+GATHER_CASES = ("fluxonium4_d5", "ring3_d4", "ring5_d3", "chain3_d5")
+ENGINE_CASES = [(n, "register") for n in CASES] + [(n, "gather") for n in GATHER_CASES]
+
+
+@pytest.mark.parametrize("name,engine", ENGINE_CASES)
+def test_adjoint_matches_oracle_gradient(scp, name, engine):
     desc = CASES[name]()
-    print(f"[adjoint] {name}", flush=True)
-    F, g = gpu_loss_and_grad(scp, desc)
+    print(f"[adjoint] {name} engine={engine}", flush=True)
+    F, g = gpu_loss_and_grad(scp, desc, engine=engine)
     L, Fo, tau, U, go = loss_and_grad(OracleSystem(desc))
     assert abs(F - Fo) <= DF_TOL
     assert g.shape == go.shape
@@ -133,22 +142,62 @@ def test_adjoint_matches_central_differences(scp):
     check_grad(g, ref)
 
 
-def test_checkpoint_interval_is_bitwise_invariant_and_deterministic(scp):
+@pytest.mark.parametrize("engine", ["register", "gather"])
+def test_checkpoint_interval_is_bitwise_invariant_and_deterministic(scp, engine):
     desc = _ring(4, 3, 4.0, 49)
-    print("[adjoint] ckpt invariance", flush=True)
-    gs = [gpu_loss_and_grad(scp, desc, ce)[1] for ce in (1, 7, 49, 7)]
+    print(f"[adjoint] ckpt invariance engine={engine}", flush=True)
+    gs = [gpu_loss_and_grad(scp, desc, ce, engine=engine)[1] for ce in (1, 7, 49, 7)]
     for gi in gs[1:]:
         assert np.array_equal(gs[0], gi)
 
 
-def test_config3_full_gradient_against_stored_oracle(scp):
+@pytest.mark.parametrize("engine", ["register", "gather"])
+def test_config3_full_gradient_against_stored_oracle(scp, engine):
     path = os.path.join(GOLDEN, "config3_oracle.json")
     ref = json.load(open(path))
     desc = si.config3()
-    print("[adjoint] config3 full", flush=True)
-    F, g = gpu_loss_and_grad(scp, desc)
+    print(f"[adjoint] config3 full engine={engine}", flush=True)
+    F, g = gpu_loss_and_grad(scp, desc, engine=engine)
     assert abs(F - ref["F"]) <= DF_TOL
     check_grad(g, np.array(ref["grad"]))
+
+
+def test_engine_choice_and_refusal(scp):
+    """Automatic choice: the gather engine for the 4-fluxonium chain's 16
+    columns (forward and gradient), the register-layout stepper for the ring's
+    256; a device below D = 64 has no gather stepper."""
+    g = scp.System(si.config3())
+    for wg in (False, True):
+        assert g.engine(g.opts(16, with_ckpt=int(wg)), with_grad=wg) == "gather"
+    g.set_engine("register")
+    assert g.engine(g.opts(16, with_ckpt=1), with_grad=True) == "register"
+    g.close()
+    g = scp.System(si.config5())
+    assert g.engine(g.opts(256, with_ckpt=1), with_grad=True) == "register"
+    g.close()
+    g = scp.System(si.config1())
+    with pytest.raises(scp.ScpError, match="EINVAL"):
+        g.set_engine("gather")
+    assert g.engine(g.opts(4, with_ckpt=1), with_grad=True) == "register"
+    g.close()
+
+
+def test_engine_switch_forgets_checkpoints(scp):
+    desc = _ring(4, 3, 2.0, 20)
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, desc["columns"])
+    opts = g.opts(psi0.shape[0], with_ckpt=1)
+    nbytes = []
+    for e in ("register", "gather"):
+        g.set_engine(e)
+        nbytes.append(g.workspace_bytes(opts, with_grad=True))
+    ws = torch.empty(max(nbytes), dtype=torch.uint8, device="cuda")
+    U = g.propagate(psi0, opts=opts, workspace=ws)        # gather engine, checkpoints kept
+    g.adjoint(torch.zeros_like(U), opts, ws)              # valid
+    g.set_engine("register")
+    with pytest.raises(scp.ScpError, match="EINVAL.*checkpoints"):
+        g.adjoint(torch.zeros_like(U), opts, ws)
+    g.close()
 
 
 def _loss_grad_frame(scp, desc, real_frame):

@@ -107,16 +107,30 @@ def test_apply_generator_matches_oracle(scp, name):
     g.close()
 
 
-def _gpu_propagate(scp, desc, S_cols=None, fused=False):
-    """Forward of the columns; ``fused``: with checkpoints, which always runs
-    the register-layout stepper (a forward without them runs on the gather
-    engine when the system has few columns of a small device)."""
+def _gpu_propagate(scp, desc, S_cols=None, engine="register"):
+    """Forward of the columns on the register-layout stepper or the gather
+    engine (one workgroup per column in LDS)."""
     g = scp.System(desc)
+    g.set_engine(engine)
     cols = desc["columns"] if S_cols is None else S_cols
     psi0 = scp.basis_columns(g.D, cols)
-    U = g.propagate(psi0, opts=g.opts(len(cols), with_ckpt=1) if fused else None)
+    U = g.propagate(psi0)
     torch.cuda.synchronize()
     return g, U
+
+
+def _engines(scp, desc):
+    """The engines that run this device: always the register-layout stepper,
+    the gather engine where it has a stepper (64 <= D <= 4096)."""
+    out = ["register"]
+    g = scp.System(desc)
+    try:
+        g.set_engine("gather")
+        out.append("gather")
+    except scp.ScpError:
+        pass
+    g.close()
+    return out
 
 
 def _gpu_fid(scp, U, desc):
@@ -143,19 +157,19 @@ def test_propagate_matches_oracle(scp, name):
     P = Uo[np.ix_(desc["comp_rows"], desc["comp_cols"])]
     u, _, vh = np.linalg.svd(P)
     d2 = dict(desc, target=u @ vh)
-    for fused in (False, True):
-        print(f"[propagate] {name} fused={fused}", flush=True)
-        g, U = _gpu_propagate(scp, desc, fused=fused)
+    for engine in _engines(scp, desc):
+        print(f"[propagate] {name} engine={engine}", flush=True)
+        g, U = _gpu_propagate(scp, desc, engine=engine)
         Ug = U.cpu().numpy().T.astype(np.complex128)
-        assert np.abs(Ug - Uo).max() <= 2e-5, (fused, np.abs(Ug - Uo).max())
+        assert np.abs(Ug - Uo).max() <= 2e-5, (engine, np.abs(Ug - Uo).max())
         Fg = _gpu_fid(scp, U, desc)
         Fo, _ = oracle_fidelity(Uo, desc["comp_rows"], desc["comp_cols"], desc["target"])
-        assert abs(Fg - Fo) <= DF_TOL, (fused, Fg, Fo)
+        assert abs(Fg - Fo) <= DF_TOL, (engine, Fg, Fo)
         # F ~ 1 case: target = the oracle's own computational block (nearest unitary)
         Fg1 = _gpu_fid(scp, U, d2)
         Fo1, _ = oracle_fidelity(Uo, desc["comp_rows"], desc["comp_cols"], d2["target"])
         assert Fo1 > 0.9
-        assert abs(Fg1 - Fo1) <= DF_TOL, (fused, Fg1, Fo1)
+        assert abs(Fg1 - Fo1) <= DF_TOL, (engine, Fg1, Fo1)
         g.close()
 
 
@@ -164,14 +178,14 @@ def test_config2_full_near_unit_fidelity(scp):
     Uo = oracle_propagate(OracleSystem(desc))
     P = Uo[np.ix_(desc["comp_rows"], desc["comp_cols"])]
     u, _, vh = np.linalg.svd(P)
-    for fused in (False, True):
-        print(f"[propagate] config2 full fused={fused}", flush=True)
-        g, U = _gpu_propagate(scp, desc, fused=fused)
+    for engine in _engines(scp, desc):
+        print(f"[propagate] config2 full engine={engine}", flush=True)
+        g, U = _gpu_propagate(scp, desc, engine=engine)
         for tgt in (desc["target"], u @ vh):
             d2 = dict(desc, target=tgt)
             Fg = _gpu_fid(scp, U, d2)
             Fo, _ = oracle_fidelity(Uo, desc["comp_rows"], desc["comp_cols"], tgt)
-            assert abs(Fg - Fo) <= DF_TOL, (fused, Fg, Fo)
+            assert abs(Fg - Fo) <= DF_TOL, (engine, Fg, Fo)
         g.close()
 
 

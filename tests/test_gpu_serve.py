@@ -37,6 +37,7 @@ def short_request(r, T=4.0):
 
 def direct(scp, desc, want_grad):
     g = scp.System(desc)
+    g.set_engine("register")   # the server's batched kernels are the register-layout stepper's
     psi0 = scp.basis_columns(g.D, desc["columns"])
     opts = g.opts(psi0.shape[0], with_ckpt=1)
     ws = g.workspace(opts, with_grad=True)

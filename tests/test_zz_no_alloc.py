@@ -28,6 +28,7 @@ def _ring(n_modes, d, T, n, seed):
 
 def _both(scp, desc):
     g = scp.System(desc)
+    g.set_engine("register")   # the allocation-free adjoint's engine
     psi0 = scp.basis_columns(g.D, desc["columns"])
     opts = g.opts(psi0.shape[0], with_ckpt=1)
     ws = g.workspace(opts, with_grad=True)
