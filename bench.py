@@ -217,13 +217,11 @@ def other_configs(scp, si, torch, np):
               "the paper: forward 2.02 s, gradient 8.55 s on a 32-core CPU, Trotter Q2 + LCAM)",
               si.fluxonium6_x6(), None)]
     stream = torch.cuda.current_stream()
-    for name, desc, ref_path in cases:
-        g = scp.System(desc)
-        S = len(desc["columns"])
-        psi0 = scp.basis_columns(g.D, desc["columns"])
+    def timed_gradient(g, psi0, tgt, S):
+        """Forward with checkpoints, then fidelity + adjoint: min of 3 each,
+        on the engine the system is set to."""
         opts = g.opts(S, with_ckpt=1)
         ws = g.workspace(opts, with_grad=True)
-        tgt = scp.Target(desc["comp_rows"], desc["comp_cols"], desc["target"])
         cot = torch.empty_like(psi0)
         res = []
         for rep in range(3):
@@ -236,8 +234,24 @@ def other_configs(scp, si, torch, np):
             ev[2].record(stream)
             torch.cuda.synchronize()
             res.append((ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])))
-        fwd_ms = min(r[0] for r in res)
-        grad_ms = min(r[1] for r in res)
+        eng = g.engine(opts, with_grad=True)
+        del ws
+        return min(r[0] for r in res), min(r[1] for r in res), F, grad, U, cot, eng
+
+    for name, desc, ref_path in cases:
+        g = scp.System(desc)
+        S = len(desc["columns"])
+        psi0 = scp.basis_columns(g.D, desc["columns"])
+        tgt = scp.Target(desc["comp_rows"], desc["comp_cols"], desc["target"])
+        fwd_ms, grad_ms, F, grad, U, cot, eng = timed_gradient(g, psi0, tgt, S)
+        other = None
+        if eng == "gather":
+            # the same on the register-layout stepper, for comparison
+            g.set_engine("register")
+            r_fwd, r_grad, r_F, r_g, _, _, _ = timed_gradient(g, psi0, tgt, S)
+            other = {"forward_ms": r_fwd, "fidelity_and_gradient_ms": r_grad, "F": r_F,
+                     "grad": r_g}
+            g.set_engine("auto")
         # forward alone (no checkpoints: the gather engine where the system
         # has few columns of a small device)
         fo = []
@@ -253,8 +267,10 @@ def other_configs(scp, si, torch, np):
         fwd_flop, adj_flop = flops(desc, S)
         # the plain FP64 path (one launch per local term) only for the small devices
         p64 = plain64_forward_ms(scp, si, torch, desc, S) if g.D <= 1000 else None
-        out = {"config": name, "forward_ms": fwd_ms, "fidelity_and_gradient_ms": grad_ms,
+        out = {"config": name, "engine": eng, "forward_ms": fwd_ms,
+               "fidelity_and_gradient_ms": grad_ms,
                "forward_only_ms": min(fo), "F_forward_only": Ff,
+               "O_t": (fwd_ms + grad_ms) / min(fo),
                "steps_dim2_per_s_forward": N * g.D * S / (fwd_ms * 1e-3),
                "forward_tflops": fwd_flop / (fwd_ms * 1e-3) / 1e12,
                "plain_fp64_forward_ms": p64, "F": F, "n_params": len(grad)}
@@ -276,6 +292,13 @@ def other_configs(scp, si, torch, np):
             gref = np.array(ref["grad"])
             out.update({"dF": abs(F - ref["F"]),
                         "grad_rel_err": float(np.abs(grad - gref).max() / np.abs(gref).max())})
+            if other is not None:
+                other["dF"] = abs(other["F"] - ref["F"])
+                other["grad_rel_err"] = float(np.abs(other["grad"] - gref).max() /
+                                              np.abs(gref).max())
+        if other is not None:
+            other.pop("grad")
+            out["register_engine"] = other
         g.close()
         lines.append(out)
     lines.append(static_spectrum_line(scp, np))

@@ -610,10 +610,24 @@ __device__ __forceinline__ c32 comm2(const c32* __restrict__ kb, const c32* __re
   return z;
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float lane_f(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+// Sum over the wave (all 64 lanes active), the same in every lane, in a fixed
+// order: within each row of 16 lanes by DPP (quad exchanges, then the half-row
+// and row mirrors), then the four row sums.  DPP stays on the vector ALU
+// (a shuffle would use the LDS crossbar these kernels are bound by).
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_f<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  v += dpp_f<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  v += dpp_f<0x141>(v);   // row_half_mirror
+  v += dpp_f<0x140>(v);   // row_mirror
+  return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
 }
 
 // s = sum_x row[x] v[x]
@@ -889,36 +903,26 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
           }
           __builtin_amdgcn_sched_barrier(0);
         }
-        // drive slots: 2 Im <O kb - kb O, y> (closed: 2 Im <O kb, y>), one sum per wave
-#pragma unroll 1
-        for (int k = 0; k < nds; ++k) {
-          const int m = uni(A->ds_mode[k]);
-          const c32* rows = tw + A->off_s + uni(A->ds_sl[k]) * dd;
-          const int ks = uni(A->kst[m]), bs = uni(A->bst[m]);
-          float v = 0.f;
-#pragma unroll
-          for (int r = 0; r < E; ++r) {
-            const int e = tid + r * T;
-            if (e < L) {
-              c32 z, y;
-              if constexpr (OPEN) {
-                z = comm1<d, N>(kbw, rows, e, ket_digit(pk[r], m), bra_digit(pk[r], m, N), ks, bs);
-                y = ys[e];
-              } else {
-                const int am = ket_digit(pk[r], m);
-                c32 kv[d];
-#pragma unroll
-                for (int x = 0; x < d; ++x) kv[x] = kbw[e + (x - am) * ks];
-                z = rowdot<d>(rows + am * d, kv);
-                y = ybw[e];
-              }
-              v += 2.f * im_conj(z, y);
-            }
-          }
-          v = wave_sum(v);
-          if (lane == 0) wsum[(par * NW + wave) * WS + k] = v;
-        }
         if constexpr (OPEN) {
+          // drive slots: 2 Im <O kb - kb O, y>, one sum per wave
+#pragma unroll 1
+          for (int k = 0; k < nds; ++k) {
+            const int m = uni(A->ds_mode[k]);
+            const c32* rows = tw + A->off_s + uni(A->ds_sl[k]) * dd;
+            const int ks = uni(A->kst[m]), bs = uni(A->bst[m]);
+            float v = 0.f;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+              const int e = tid + r * T;
+              if (e < L) {
+                const c32 z =
+                    comm1<d, N>(kbw, rows, e, ket_digit(pk[r], m), bra_digit(pk[r], m, N), ks, bs);
+                v += 2.f * im_conj(z, ys[e]);
+              }
+            }
+            v = wave_sum(v);
+            if (lane == 0) wsum[(par * NW + wave) * WS + k] = v;
+          }
           // couplings: 2 Im <P kb - kb P, y>, added to the FP64 sums per wave
 #pragma unroll 1
           for (int c = 0; c < ncp; ++c) {
@@ -981,7 +985,11 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
             const int m = uni(mv);
             const int ks = uni(A->kst[m]);
             const c32* Dm = tw + uni(A->off_m) + m * 3 * dd;
-            c32 kv[E][d];
+            // kb along m: kept in registers for the whole mode when small,
+            // else gathered again at each use (keeps the E = 4 shapes out of
+            // scratch)
+            constexpr bool KC = E * d <= 12;
+            c32 kv[KC ? E : 1][d];
             c32 C[E];
             float v0 = 0.f, v1 = 0.f, v2 = 0.f;
 #pragma unroll
@@ -990,13 +998,49 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
               C[r].x = C[r].y = 0.f;
               if (e < L) {
                 const int am = ket_digit(pk[r], m);
+                c32 kt[d];
 #pragma unroll
-                for (int x = 0; x < d; ++x) kv[r][x] = kbw[e + (x - am) * ks];
+                for (int x = 0; x < d; ++x) kt[x] = kbw[e + (x - am) * ks];
+                if constexpr (KC) {
+#pragma unroll
+                  for (int x = 0; x < d; ++x) kv[r][x] = kt[x];
+                }
                 const c32 y = ybw[e];
-                v0 += 2.f * im_conj(rowdot<d>(Dm + am * d, kv[r]), y);
-                v1 += 2.f * im_conj(rowdot<d>(Dm + dd + am * d, kv[r]), y);
-                v2 += 2.f * im_conj(rowdot<d>(Dm + 2 * dd + am * d, kv[r]), y);
+                v0 += 2.f * im_conj(rowdot<d>(Dm + am * d, kt), y);
+                v1 += 2.f * im_conj(rowdot<d>(Dm + dd + am * d, kt), y);
+                v2 += 2.f * im_conj(rowdot<d>(Dm + 2 * dd + am * d, kt), y);
               }
+              __builtin_amdgcn_sched_barrier(0);
+            }
+            // kb along m of element r (registers or LDS)
+            auto kb_of = [&](int r, int e, int am, c32(&kt)[d]) {
+              if constexpr (KC) {
+#pragma unroll
+                for (int x = 0; x < d; ++x) kt[x] = kv[KC ? r : 0][x];
+              } else {
+#pragma unroll
+                for (int x = 0; x < d; ++x) kt[x] = kbw[e + (x - am) * ks];
+              }
+            };
+            // drive slots on this mode: 2 Im <O kb, y>, one sum per wave (the
+            // large shapes take them in a loop of their own, below)
+#pragma unroll 1
+            for (int k = 0; k < (KC ? nds : 0); ++k) {
+              if (uni(A->ds_mode[k]) != m) continue;
+              const c32* rows = tw + A->off_s + uni(A->ds_sl[k]) * dd;
+              float v = 0.f;
+#pragma unroll
+              for (int r = 0; r < E; ++r) {
+                const int e = tid + r * T;
+                if (e < L) {
+                  const int am = ket_digit(pk[r], m);
+                  c32 kt[d];
+                  kb_of(r, e, am, kt);
+                  v += 2.f * im_conj(rowdot<d>(rows + am * d, kt), ybw[e]);
+                }
+              }
+              v = wave_sum(v);
+              if (lane == 0) wsum[(par * NW + wave) * WS + k] = v;
             }
             const int k0 = uni(A->me_beg[m]), k1 = uni(A->me_beg[m + 1]);
 #pragma unroll 1
@@ -1022,12 +1066,16 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
                   const c32 cp = rowdot<d>(Rp + ap * d, yv);
                   C[r].x = fmaf(gc, cp.x, C[r].x);
                   C[r].y = fmaf(gc, cp.y, C[r].y);
-                  if (first) vc += 2.f * im_conj(rowdot<d>(Ro + am * d, kv[r]), cp);
-                  if (last) {
-                    v0 += 2.f * im_conj(rowdot<d>(dR + am * d, kv[r]), C[r]);
-                    v1 += 2.f * im_conj(rowdot<d>(dR + dd + am * d, kv[r]), C[r]);
-                    v2 += 2.f * im_conj(rowdot<d>(dR + 2 * dd + am * d, kv[r]), C[r]);
-                    C[r].x = C[r].y = 0.f;
+                  if (first || last) {
+                    c32 kt[d];
+                    kb_of(r, e, am, kt);
+                    if (first) vc += 2.f * im_conj(rowdot<d>(Ro + am * d, kt), cp);
+                    if (last) {
+                      v0 += 2.f * im_conj(rowdot<d>(dR + am * d, kt), C[r]);
+                      v1 += 2.f * im_conj(rowdot<d>(dR + dd + am * d, kt), C[r]);
+                      v2 += 2.f * im_conj(rowdot<d>(dR + 2 * dd + am * d, kt), C[r]);
+                      C[r].x = C[r].y = 0.f;
+                    }
                   }
                 }
               }
@@ -1044,6 +1092,28 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
               wv[0] = v0;
               wv[1] = v1;
               wv[2] = v2;
+            }
+          }
+          if constexpr (E * d > 12) {
+#pragma unroll 1
+            for (int k = 0; k < nds; ++k) {
+              const int m = uni(A->ds_mode[k]);
+              const int ks = uni(A->kst[m]);
+              const c32* rows = tw + A->off_s + uni(A->ds_sl[k]) * dd;
+              float v = 0.f;
+#pragma unroll
+              for (int r = 0; r < E; ++r) {
+                const int e = tid + r * T;
+                if (e < L) {
+                  const int am = ket_digit(pk[r], m);
+                  c32 kt[d];
+#pragma unroll
+                  for (int x = 0; x < d; ++x) kt[x] = kbw[e + (x - am) * ks];
+                  v += 2.f * im_conj(rowdot<d>(rows + am * d, kt), ybw[e]);
+                }
+              }
+              v = wave_sum(v);
+              if (lane == 0) wsum[(par * NW + wave) * WS + k] = v;
             }
           }
         }
