@@ -203,7 +203,7 @@ def serving_leg(scp, si, torch, np, n_req):
     return out
 
 
-def other_configs(scp, si, torch, np):
+def other_configs(scp, si, torch, np, only=None, plain64=True):
     """Configs 1-3 and the X^6 chain on the GPU: forward and gradient times,
     rate, FP64 forward, and parity against the stored oracle results where
     they exist (one JSON line per config; not part of the default run)."""
@@ -216,7 +216,10 @@ def other_configs(scp, si, torch, np):
               "T=50 ns, 5000 steps of 0.01 ns, 148 params (the paper's X^6 benchmark shape; "
               "the paper: forward 2.02 s, gradient 8.55 s on a 32-core CPU, Trotter Q2 + LCAM)",
               si.fluxonium6_x6(), None)]
+    if only is not None:
+        cases = [c for c, key in zip(cases, ("config1", "chain", "x6")) if key == only]
     stream = torch.cuda.current_stream()
+
     def timed_gradient(g, psi0, tgt, S):
         """Forward with checkpoints, then fidelity + adjoint: min of 3 each,
         on the engine the system is set to."""
@@ -266,7 +269,7 @@ def other_configs(scp, si, torch, np):
         N = desc["n_steps"]
         fwd_flop, adj_flop = flops(desc, S)
         # the plain FP64 path (one launch per local term) only for the small devices
-        p64 = plain64_forward_ms(scp, si, torch, desc, S) if g.D <= 1000 else None
+        p64 = plain64_forward_ms(scp, si, torch, desc, S) if g.D <= 1000 and plain64 else None
         out = {"config": name, "engine": eng, "forward_ms": fwd_ms,
                "fidelity_and_gradient_ms": grad_ms,
                "forward_only_ms": min(fo), "F_forward_only": Ff,
@@ -301,8 +304,9 @@ def other_configs(scp, si, torch, np):
             out["register_engine"] = other
         g.close()
         lines.append(out)
-    lines.append(static_spectrum_line(scp, np))
-    lines += trotter_lines(scp, si, torch, np)
+    if only is None:
+        lines.append(static_spectrum_line(scp, np))
+        lines += trotter_lines(scp, si, torch, np)
     return lines
 
 
@@ -671,6 +675,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--configs", action="store_true",
                     help="only time configs 1-3 (one JSON line each) and exit")
+    ap.add_argument("--config-only", choices=("config1", "chain", "x6"), default=None,
+                    help="with --configs: only this case (config1; chain: the 4-fluxonium "
+                         "chain of configs 2/3; x6)")
     ap.add_argument("--trotter", action="store_true",
                     help="only time the Suzuki-Trotter product formulas (one JSON line each) and exit")
     ap.add_argument("--trotter-orders", default="q1,q2,q4,q4j")
@@ -720,7 +727,7 @@ def main():
         print(json.dumps(lindblad_line(scp, si, torch, np)), flush=True)
         return
     if args.configs:
-        for line in other_configs(scp, si, torch, np):
+        for line in other_configs(scp, si, torch, np, args.config_only, not args.no_plain64):
             print(json.dumps(line), flush=True)
         return
     dev = torch.device("cuda:0")

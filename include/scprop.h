@@ -366,8 +366,9 @@ scp_status scp_fidelity_local(const void* U, int64_t D, int32_t S, int32_t preci
  * state (D x S complex64, device).  The discrete adjoint of Sec. 2.5 (the
  * per-step derivative sum and the costate chain rule) walks the checkpoint
  * segments back, recomputing each segment's states, on the engine
- * scp_solve_engine(opts, with_grad = 1) names.  The gather engine's reverse
- * walk is one launch per column for all segments; its per-stage sums are
+ * scp_solve_engine(opts, with_grad = 1) names.  The gather engine walks one
+ * segment per launch while other workgroups of the same launch recompute the
+ * next segment's states (two stage-input buffers); its per-stage sums are
  * folded in a fixed order, so both engines' gradients are deterministic.
  *   psi0 != NULL: the checkpoints are first computed here by a forward
  *     propagation of psi0 (D x S complex64, device) into the workspace;

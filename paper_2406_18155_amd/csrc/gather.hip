@@ -647,7 +647,7 @@ __device__ __forceinline__ float im_conj(c32 a, c32 b) { return a.x * b.y - a.y 
 
 template <int d, int N, bool OPEN>
 __global__ void __launch_bounds__((GShape<d, N, OPEN>::T))
-g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
+g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int gseg) {
   using Sh = GShape<d, N, OPEN>;
   constexpr int L = Sh::L, T = Sh::T, E = Sh::E, D = Sh::D, dd = d * d;
   constexpr int NW = T / 64;
@@ -667,12 +667,23 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
   float* wsum = (float*)(acc + ((nacc + 1) & ~1));
   const c32* gtab = (const c32*)A->gtab;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int col = blockIdx.x;
   const float h = A->h;
   const int nsteps = A->nsteps, ce = B->ce, nck = B->nck;
+  // Open systems: one launch walks every segment (recompute, then reverse).
+  // Closed systems: one launch per segment, 2S workgroups: the first S walk
+  // segment gseg back while the other S recompute segment gseg - 1 into the
+  // other stage-input buffer, so the recompute hides behind the reverse walk.
+  const int S = A->S;
+  const bool rev_role = OPEN || (int)blockIdx.x < S;
+  const int col = (OPEN || rev_role) ? (int)blockIdx.x : (int)blockIdx.x - S;
+  const int g_hi = OPEN ? nck - 1 : (rev_role ? gseg : gseg - 1);
+  const int g_lo = OPEN ? 0 : g_hi;
+  if (!OPEN && (g_hi < 0 || g_hi >= nck)) return;
   const int nds = uni(A->nds), ncp = uni(A->ncp), ndr = uni(A->ndr);
   const int nv = OPEN ? 0 : 3 * N + ncp;   // closed: device-parameter and coupling sums
-  for (int t = tid; t < nacc; t += T) acc[t] = 0.0;
+  // closed systems continue the accumulators of the later segments
+  const bool resume = !OPEN && rev_role && g_hi < nck - 1;
+  for (int t = tid; t < nacc; t += T) acc[t] = resume ? B->part[(size_t)col * nacc + t] : 0.0;
   uint32_t pk[E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
@@ -689,7 +700,6 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
   // the costate lives in registers only during the reverse walks; between
   // them (while a segment is recomputed) it waits in device memory
   float4* lsave = B->lam + (size_t)col * L;
-  c32* segc = (c32*)B->seg + (size_t)col * ce * 4 * L;
   int prev_row = -1;   // step-grid row of the stage whose sums wait in wsum
   int par = 0;         // parity of the wsum buffer being filled
   // fold the previous stage's per-wave sums in a fixed order: the drive slots
@@ -713,10 +723,13 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
   };
   __syncthreads();
 #pragma unroll 1
-  for (int g = nck - 1; g >= 0; --g) {
+  for (int g = g_hi; g >= g_lo; --g) {
     const int n0 = g * ce, n1 = min(nsteps, n0 + ce);
+    // stage inputs of the segment: one buffer per column (open systems), two
+    // alternating by segment (closed systems)
+    c32* segc = (c32*)B->seg + ((size_t)col * (OPEN ? 1 : 2) + (OPEN ? 0 : (g & 1))) * ce * 4 * L;
     // ---- recompute the segment from its checkpoint, storing the stage inputs
-    {
+    if (OPEN || !rev_role) {
       float hr[E], hm[E], lr[E], lm[E], ar[E], am_[E];
       const float4* ck = B->ck + ((size_t)col * nck + g) * L;
 #pragma unroll
@@ -819,6 +832,7 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
         }
       }
     }
+    if (!OPEN && !rev_role) return;
     // ---- reverse walk of the segment
     float lhr[E], lhm[E], llr[E], llm[E];   // costate (hi, lo)
 #pragma unroll
@@ -839,6 +853,24 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
       llm[r] = v.w;
     }
     int cur = 0;
+    // closed systems: the next stage's y and the first GP table entries per
+    // thread are loaded into registers while the current stage runs
+    constexpr int GP = OPEN ? 1 : 8;
+    c32 pre_t[GP], pre_y[OPEN ? 1 : E];
+    if constexpr (!OPEN) {   // the walk's first stage: (n1 - 1, 3)
+      const c32* ysn = segc + ((size_t)(n1 - 1 - n0) * 4 + 3) * L;
+      const c32* grn = gtab + (size_t)stage_c(n1 - 1, 3) * ntabg;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const int e = tid + r * T;
+        if (e < L) pre_y[r] = ysn[e];
+      }
+#pragma unroll
+      for (int k = 0; k < GP; ++k) {
+        const int t = tid + k * T;
+        if (t < ntabg) pre_t[k] = grn[t];
+      }
+    }
 #pragma unroll 1
     for (int n = n1 - 1; n >= n0; --n) {
       // yb_{s+1}; the step's increments sum_s yb_s gather in the costate's lo
@@ -855,6 +887,7 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
         c32* ybw = yb0 + cur * L;   // closed systems
         c32* tw = tb0 + cur * ntabg;
         const c32* ys = segc + ((size_t)(n - n0) * 4 + s) * L;
+        const c32* gr_ = gtab + (size_t)row * ntabg;
         // kb_s (own elements), closed systems y_s too, and the stage table
         // into this stage's buffers
 #pragma unroll
@@ -865,14 +898,38 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
             v.x = fmaf(cs, lhr[r], cy * ybr[r]);
             v.y = fmaf(cs, lhm[r], cy * ybm[r]);
             kbw[e] = v;
-            if (!OPEN) ybw[e] = ys[e];
+            if (!OPEN) ybw[e] = pre_y[OPEN ? 0 : r];
           }
         }
-        {
-          const c32* gr_ = gtab + (size_t)row * ntabg;
+        if (!OPEN) {
+#pragma unroll
+          for (int k = 0; k < GP; ++k) {
+            const int t = tid + k * T;
+            if (t < ntabg) tw[t] = pre_t[k];
+          }
+          for (int t = tid + GP * T; t < ntabg; t += T) tw[t] = gr_[t];
+        } else {
           for (int t = tid; t < ntabg; t += T) tw[t] = gr_[t];
         }
         __syncthreads();
+        if constexpr (!OPEN) {
+          // the next stage of the walk: (n, s - 1), else (n - 1, 3) within the segment
+          const int nn = s > 0 ? n : n - 1, sn = s > 0 ? s - 1 : 3;
+          if (nn >= n0) {
+            const c32* ysn = segc + ((size_t)(nn - n0) * 4 + sn) * L;
+            const c32* grn = gtab + (size_t)stage_c(nn, sn) * ntabg;
+#pragma unroll
+            for (int r = 0; r < E; ++r) {
+              const int e = tid + r * T;
+              if (e < L) pre_y[r] = ysn[e];
+            }
+#pragma unroll
+            for (int k = 0; k < GP; ++k) {
+              const int t = tid + k * T;
+              if (t < ntabg) pre_t[k] = grn[t];
+            }
+          }
+        }
         // the previous stage's sums are complete
         if (prev_row >= 0) fold_prev();
 #pragma unroll
@@ -1246,15 +1303,18 @@ size_t g_adj_lds_bytes(int ntabg, int nacc) {
          sizeof(float) * 2 * (Sh::T / 64) * (OPEN ? GA_MAXDS : GA_NV);
 }
 
+// Open systems: one launch (gseg unused).  Closed systems: launch gseg = nck
+// down to 0 in order on one stream, 2S workgroups each (see the kernel).
 template <int d, int N, bool OPEN>
 hipError_t g_adj_launch(const GArgs* dargs, const GAdj* dadj, int S, int ntabg, int nacc,
-                        hipStream_t s) {
+                        int gseg, hipStream_t s) {
   using Sh = GShape<d, N, OPEN>;
   const size_t sh = g_adj_lds_bytes<d, N, OPEN>(ntabg, nacc);
   if (sh > 163840) return hipErrorInvalidValue;
   (void)hipFuncSetAttribute((const void*)g_adj_kernel<d, N, OPEN>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-  hipLaunchKernelGGL((g_adj_kernel<d, N, OPEN>), dim3(S), dim3(Sh::T), sh, s, dargs, dadj);
+  hipLaunchKernelGGL((g_adj_kernel<d, N, OPEN>), dim3(OPEN ? S : 2 * S), dim3(Sh::T), sh, s,
+                     dargs, dadj, gseg);
   return hipGetLastError();
 }
 
@@ -1271,12 +1331,13 @@ size_t g_adj_lds(int d, int N, bool open, int ntabg, int nacc) {
 }
 
 hipError_t g_adj_dispatch(int d, int N, bool open, const GArgs* dargs, const GAdj* dadj, int S,
-                          int ntabg, int nacc, hipStream_t s) {
+                          int ntabg, int nacc, int gseg, hipStream_t s) {
 #define GA_ADJ_CASE_O(dd_, nn_) \
-  if (open && d == dd_ && N == nn_) return g_adj_launch<dd_, nn_, true>(dargs, dadj, S, ntabg, nacc, s);
+  if (open && d == dd_ && N == nn_)  \
+    return g_adj_launch<dd_, nn_, true>(dargs, dadj, S, ntabg, nacc, gseg, s);
 #define GA_ADJ_CASE_C(dd_, nn_) \
   if (!open && d == dd_ && N == nn_)   \
-    return g_adj_launch<dd_, nn_, false>(dargs, dadj, S, ntabg, nacc, s);
+    return g_adj_launch<dd_, nn_, false>(dargs, dadj, S, ntabg, nacc, gseg, s);
   GA_OPEN_SHAPES(GA_ADJ_CASE_O)
   GA_CLOSED_SHAPES(GA_ADJ_CASE_C)
 #undef GA_ADJ_CASE_O
@@ -1641,7 +1702,7 @@ scp_status launch_lindblad_adjoint(scp_system* sys, const double* gamma1, const 
   HIPCHK(g_dispatch(d, N, true, dargs, dadj, S, A.ntab, st));
   timing_stop(sys, t0, 0, st);
   t0 = timing_start(sys, st);
-  HIPCHK(g_adj_dispatch(d, N, true, dargs, dadj, S, A.ntabg, w.nacc, st));
+  HIPCHK(g_adj_dispatch(d, N, true, dargs, dadj, S, A.ntabg, w.nacc, -1, st));
   timing_stop(sys, t0, 2, st);
   std::vector<double> part((size_t)S * w.nacc);
   HIPCHK(hipMemcpyAsync(part.data(), base + w.part, part.size() * sizeof(double),
@@ -1698,7 +1759,7 @@ scp_status launch_gather_forward(scp_system* sys, int S, void* ws, size_t ws_byt
 
 // Closed-system gradient on the gather engine.  Workspace: [GArgs][GAdj]
 // [stage tables [3N][ntabg]][checkpoints [S][nck][D] float4] and, for the
-// adjoint, [stage inputs [S][ce][4][D]][partial sums [S][nacc] double]
+// adjoint, [stage inputs [S][2][ce][4][D]][partial sums [S][nacc] double]
 // [costate [S][D] float4].  The forward with checkpoints and the adjoint
 // share the offsets of the first four.
 struct GcLayout {
@@ -1728,8 +1789,8 @@ static scp_status gc_layout(const scp_system* sys, int S, int ce, bool with_grad
   off += align256((size_t)S * w.nck * L * sizeof(float4));
   w.seg = w.part = w.lam = off;
   if (with_grad) {
-    w.seg = off;
-    off += align256((size_t)S * ce * 4 * L * sizeof(float2));
+    w.seg = off;   // two stage-input buffers per column (segments alternate)
+    off += align256((size_t)S * 2 * ce * 4 * L * sizeof(float2));
     w.part = off;
     off += align256((size_t)S * w.nacc * sizeof(double));
     w.lam = off;
@@ -1819,10 +1880,12 @@ scp_status launch_gather_adjoint(scp_system* sys, int S, int ce, void* ws, size_
   GcLayout w;
   GArgs A;
   SCP_TRY(gc_prepare(sys, S, ce, true, base, ws_bytes, nullptr, nullptr, cot, false, w, A, st));
-  hipEvent_t t0 = timing_start(sys, st);
-  HIPCHK(g_adj_dispatch(sys->d, sys->n_modes, false, reinterpret_cast<GArgs*>(base + w.args),
-                        reinterpret_cast<GAdj*>(base + w.adj), S, A.ntabg, w.nacc, st));
-  timing_stop(sys, t0, 2, st);
+  for (int gs = w.nck; gs >= 0; --gs) {
+    hipEvent_t t0 = timing_start(sys, st);
+    HIPCHK(g_adj_dispatch(sys->d, sys->n_modes, false, reinterpret_cast<GArgs*>(base + w.args),
+                          reinterpret_cast<GAdj*>(base + w.adj), S, A.ntabg, w.nacc, gs, st));
+    timing_stop(sys, t0, 2, st);
+  }
   std::vector<double> part((size_t)S * w.nacc);
   HIPCHK(hipMemcpyAsync(part.data(), base + w.part, part.size() * sizeof(double),
                         hipMemcpyDeviceToHost, st));
