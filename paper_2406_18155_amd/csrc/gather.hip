@@ -645,6 +645,28 @@ __device__ __forceinline__ c32 rowdot(const c32* __restrict__ row, const c32 (&v
 // Im(conj(a) b)
 __device__ __forceinline__ float im_conj(c32 a, c32 b) { return a.x * b.y - a.y * b.x; }
 
+// w[x] = conj(v[x]) b
+template <int d>
+__device__ __forceinline__ void conj_scale(const c32 (&v)[d], c32 b, c32 (&w)[d]) {
+#pragma unroll
+  for (int x = 0; x < d; ++x) {
+    w[x].x = fmaf(v[x].x, b.x, v[x].y * b.y);
+    w[x].y = fmaf(v[x].x, b.y, -v[x].y * b.x);
+  }
+}
+
+// Im(conj(sum_x row[x] v[x]) b) = sum_x Im(conj(row[x]) w[x]) with w = conj(v) b
+template <int d>
+__device__ __forceinline__ float im_rowdot(const c32* __restrict__ row, const c32 (&w)[d]) {
+  float s = 0.f;
+#pragma unroll
+  for (int x = 0; x < d; ++x) {
+    s = fmaf(row[x].x, w[x].y, s);
+    s = fmaf(-row[x].y, w[x].x, s);
+  }
+  return s;
+}
+
 template <int d, int N, bool OPEN>
 __global__ void __launch_bounds__((GShape<d, N, OPEN>::T))
 g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int gseg) {
@@ -1062,10 +1084,11 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int gseg
 #pragma unroll
                   for (int x = 0; x < d; ++x) kv[r][x] = kt[x];
                 }
-                const c32 y = ybw[e];
-                v0 += 2.f * im_conj(rowdot<d>(Dm + am * d, kt), y);
-                v1 += 2.f * im_conj(rowdot<d>(Dm + dd + am * d, kt), y);
-                v2 += 2.f * im_conj(rowdot<d>(Dm + 2 * dd + am * d, kt), y);
+                c32 w[d];
+                conj_scale<d>(kt, ybw[e], w);
+                v0 += 2.f * im_rowdot<d>(Dm + am * d, w);
+                v1 += 2.f * im_rowdot<d>(Dm + dd + am * d, w);
+                v2 += 2.f * im_rowdot<d>(Dm + 2 * dd + am * d, w);
               }
               __builtin_amdgcn_sched_barrier(0);
             }
@@ -1128,9 +1151,11 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int gseg
                     kb_of(r, e, am, kt);
                     if (first) vc += 2.f * im_conj(rowdot<d>(Ro + am * d, kt), cp);
                     if (last) {
-                      v0 += 2.f * im_conj(rowdot<d>(dR + am * d, kt), C[r]);
-                      v1 += 2.f * im_conj(rowdot<d>(dR + dd + am * d, kt), C[r]);
-                      v2 += 2.f * im_conj(rowdot<d>(dR + 2 * dd + am * d, kt), C[r]);
+                      c32 w[d];
+                      conj_scale<d>(kt, C[r], w);
+                      v0 += 2.f * im_rowdot<d>(dR + am * d, w);
+                      v1 += 2.f * im_rowdot<d>(dR + dd + am * d, w);
+                      v2 += 2.f * im_rowdot<d>(dR + 2 * dd + am * d, w);
                       C[r].x = C[r].y = 0.f;
                     }
                   }
