@@ -79,18 +79,21 @@ struct TrOp {
   int sid, own;   // own: this operation forms the slot (equal products share one)
   int s0, s1;     // register form: mode + 1 of the single-mode gate on digit 0 / 1 (0: none),
                   // applied before the pair product in the first pass, after it in the second
+  int dix;        // pair operation with a single-mode factor: its index in the per-step
+                  // fused-gate table (-1 otherwise)
   int ctype[TR_MAXC], cidx[TR_MAXC], cdig[TR_MAXC];
 };
 struct TrPlan {
   int nop[2], nslot;
+  int ndyn;       // pair operations re-formed every step (fused-gate table width)
   TrOp op[2][TR_MAXOPS];
 };
 
 struct TrRun {
-  int M, N, r, D, H, nopmax, nslot;
+  int M, N, r, D, H, nopmax, nslot, ndyn;
   int nop[2];
   int opk[2][TR_MAXOPS], opi[2][TR_MAXOPS], opj[2][TR_MAXOPS];
-  int ops[2][TR_MAXOPS];   // static slot + 1, or 0
+  int ops[2][TR_MAXOPS];   // pair operations: static slot + 1, or -(fused-gate index + 1)
   int opa[2][TR_MAXOPS];   // register form: (s0) | (s1 << 8), see TrOp
   int mode1;                   // single-mode gates: 0 in place, 1 one output row per item
   int mode2;                   // pair gates: 0 in place, 1 one row, 2 d rows per item
@@ -239,7 +242,9 @@ __global__ void __launch_bounds__(64) tr_single_gate_kernel(TrGen G, const doubl
 
 // Fused gates: block b = ((step * r + j) * H + h) * nopmax + o multiplies the
 // constituents of operation o of pass h, in action order, into a d^2 x d^2
-// (pair) or d x d (single) matrix at slot b (d^4 complex per slot).
+// (pair) or d x d (single) matrix: a static operation into its slot of the
+// static table (step 0 only), the others into [step][j][dix] of the per-step
+// table (d^4 complex per slot).
 __global__ void __launch_bounds__(256) tr_fuse_kernel(int d, int r, int H, int nopmax, int M, int E,
                                                       const TrPlan* __restrict__ plan,
                                                       const double2* __restrict__ sg,
@@ -257,7 +262,7 @@ __global__ void __launch_bounds__(256) tr_fuse_kernel(int d, int r, int H, int n
   // static operation is formed once, into the table of (piece, pass, operation)
   if (op.kind == 0 || (op.stat && (step > 0 || !op.own))) return;
   double2* slot = op.stat ? out_static + ((size_t)j * plan->nslot + op.sid) * dd * dd
-                          : out + (size_t)b * dd * dd;
+                          : out + (((size_t)step * r + j) * plan->ndyn + op.dix) * dd * dd;
   const int n = op.kind ? dd : d, nn = n * n;
   double2 *A = sh, *W = sh + nn;
   for (int e = threadIdx.x; e < nn; e += blockDim.x)
@@ -483,7 +488,7 @@ __device__ __forceinline__ void tr_apply2_rows(const double2* in, double2* out, 
     tr_apply2_rows_as<d, RPI, false>(in, out, D, si, sj, Gt);
 }
 
-// Workgroup = one column; fg: fused gates [N][r][H][nopmax][d^4] of pair
+// Workgroup = one column; fg: fused gates [N][r][ndyn][d^4] of pair
 // operations with a single-mode factor, fs: [r][nslot][d^4] of the static
 // ones, sg: [N][r][M][d^2] single-mode gates (lone single-mode operations).
 template <int d>
@@ -502,13 +507,13 @@ __global__ void __launch_bounds__(TR_THREADS) trotter_kernel(TrRun R, const doub
   for (int n = 0; n < R.N; ++n) {
     for (int j = 0; j < R.r; ++j) {
       for (int h = 0; h < R.H; ++h) {
-        const double2* fgh = fg + (((size_t)n * R.r + j) * R.H + h) * R.nopmax * dd * dd;
+        const double2* fgh = fg + ((size_t)n * R.r + j) * R.ndyn * dd * dd;
         const double2* fsj = fs + (size_t)j * R.nslot * dd * dd;
         const double2* sgj = sg + ((size_t)n * R.r + j) * R.M * dd;
         for (int o = 0; o < R.nop[h]; ++o) {
           const double2* gt = !R.opk[h][o]  ? sgj + (size_t)R.opi[h][o] * dd
-                              : R.ops[h][o] ? fsj + (size_t)(R.ops[h][o] - 1) * dd * dd
-                                            : fgh + (size_t)o * dd * dd;
+                              : R.ops[h][o] > 0 ? fsj + (size_t)(R.ops[h][o] - 1) * dd * dd
+                                                : fgh + (size_t)(-R.ops[h][o] - 1) * dd * dd;
           bool swap = false;
           if (!R.opk[h][o]) {
             const int sm = R.stride[R.opi[h][o]];
@@ -726,6 +731,14 @@ TrLayout tr_layout(const scp_system* sys, int order) {
     L.mode1 = (two && any_single && nf1 < TR_THREADS) ? 1 : 0;
   }
   L.nopmax = std::max(L.P.nop[0], L.H > 1 ? L.P.nop[1] : 0);
+  // the per-step fused-gate table holds only the pair operations with a
+  // single-mode factor (the static ones are formed once)
+  L.P.ndyn = 0;
+  for (int h = 0; h < L.H; ++h)
+    for (int o = 0; o < L.P.nop[h]; ++o) {
+      TrOp& op = L.P.op[h][o];
+      op.dix = (op.kind == 1 && !op.stat) ? L.P.ndyn++ : -1;
+    }
   L.npar = 0;
   for (const Drive& R : sys->drives) L.npar += (int)R.par.size();
   const size_t d = sys->d, M = sys->n_modes, E = sys->coup.size();
@@ -743,7 +756,7 @@ TrLayout tr_layout(const scp_system* sys, int order) {
   L.sg = o;
   o = align256(o + (size_t)sys->n_steps * L.r * M * d * d * sizeof(double2));
   L.fg = o;
-  o = align256(o + (size_t)sys->n_steps * L.r * L.H * L.nopmax * d * d * d * d * sizeof(double2));
+  o = align256(o + (size_t)sys->n_steps * L.r * L.P.ndyn * d * d * d * d * sizeof(double2));
   L.fs = o;
   o = align256(o + (size_t)L.r * std::max(1, L.P.nslot) * d * d * d * d * sizeof(double2));
   L.total = o;
@@ -861,7 +874,9 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
   double2* fg = reinterpret_cast<double2*>(base + W.fg);
   double2* fs = reinterpret_cast<double2*>(base + W.fs);
   {
-    const size_t blocks = (size_t)N * W.r * W.H * W.nopmax;
+    // every step only where some pair operation is re-formed per step; else
+    // step 0, which forms the static operations
+    const size_t blocks = (size_t)(W.P.ndyn > 0 ? N : 1) * W.r * W.H * W.nopmax;
     const int n = d * d;
     hipLaunchKernelGGL(tr_fuse_kernel, dim3((unsigned)blocks), dim3(256), 2 * n * n * sizeof(double2), st,
                        d, W.r, W.H, W.nopmax, M, E, reinterpret_cast<const TrPlan*>(base + W.plan), sg,
@@ -875,13 +890,14 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
   R.H = W.H;
   R.nopmax = W.nopmax;
   R.nslot = W.P.nslot;
+  R.ndyn = W.P.ndyn;
   for (int h = 0; h < W.H; ++h) {
     R.nop[h] = W.P.nop[h];
     for (int o = 0; o < W.P.nop[h]; ++o) {
       R.opk[h][o] = W.P.op[h][o].kind;
       R.opi[h][o] = W.P.op[h][o].mi;
       R.opj[h][o] = W.P.op[h][o].mj;
-      R.ops[h][o] = W.P.op[h][o].stat ? W.P.op[h][o].sid + 1 : 0;
+      R.ops[h][o] = W.P.op[h][o].stat ? W.P.op[h][o].sid + 1 : -(W.P.op[h][o].dix + 1);
       R.opa[h][o] = W.P.op[h][o].s0 | (W.P.op[h][o].s1 << 8);
     }
   }

@@ -31,6 +31,11 @@ def _ring(n_modes, d, n_steps, seed=3):
     return si._finish(s, [d] * n_modes, target=si.cz_target(n_modes))
 
 
+def _cols(desc, k):
+    """The first k columns only (the product formula is checked column by column)."""
+    return dict(desc, columns=list(desc["columns"][:k]))
+
+
 def _short(desc, n_steps, T=None):
     desc = dict(desc, n_steps=n_steps)
     if T is not None:
@@ -52,6 +57,12 @@ CASES = {
     "ring4_d3": lambda: _ring(4, 3, 80),
     # one two-level mode, no coupling (only single-mode gates)
     "rabi_d2": lambda: si.rabi_system(0.7, 0.9, 3.0, 50),
+    # coupled two-level modes, D = 2048: pair gates in place with the single-mode
+    # gates applied in registers beside them (d = 2)
+    "raw11_d2_coupled": lambda: _cols(si.random_raw_system(15, [2] * 11, 11, 1.0, 6, env="gauss"), 8),
+    # pair gates split d rows per item with D / d^2 not a multiple of 64
+    "raw7_d3_split": lambda: _cols(si.random_raw_system(16, [3] * 7, 7, 1.0, 6, env="gauss"), 8),
+    "raw5_d5_split": lambda: _cols(si.random_raw_system(17, [5] * 5, 5, 1.0, 6, env="gauss"), 8),
 }
 
 
