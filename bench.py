@@ -203,6 +203,41 @@ def serving_leg(scp, si, torch, np, n_req):
     return out
 
 
+def probe_lines(scp, torch, np, n_wg=1024, iters=2000):
+    """The register-layout stepper's d = 3 contraction in its VALU form and in
+    two v_mfma_f32_4x4x1f32 forms (with the operand builds and register moves
+    the layout needs; issue only), timed on the device.  Algorithmic work:
+    9 fibres x 9 complex multiply-adds x 8 FLOP per lane and application."""
+    rng = np.random.default_rng(5)
+    a = rng.normal(size=(16, 3, 3)) + 1j * rng.normal(size=(16, 3, 3))
+    h = 0.1 * (a + a.conj().transpose(0, 2, 1))
+    ops = torch.tensor(np.concatenate([h.real.reshape(16, 9), h.imag.reshape(16, 9)], axis=1),
+                       dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    flop = n_wg * 256.0 * iters * 648
+    names = {0: "VALU FMA (the stepper's form)",
+             1: "MFMA 4x4x1 f32, operands built per application, outputs moved to the layout",
+             2: "MFMA 4x4x1 f32, operands built once, accumulators in place (issue and padding only)"}
+    lines, ref = [], None
+    for form in (0, 1, 2):
+        o = ops[:1] if form == 2 else ops
+        out = scp.probe_contraction(form, o, iters, n_wg)
+        ts = []
+        for rep in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            scp.probe_contraction(form, o, iters, n_wg, out=out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = min(ts)
+        lines.append({"config": "contraction probe (d = 3, 27 amplitudes per lane)", "form": form,
+                      "what": names[form], "n_wg": n_wg, "iters": iters, "ms": ms,
+                      "algorithmic_tflops": flop / (ms * 1e-3) / 1e12,
+                      "frac_of_157.3": flop / (ms * 1e-3) / 157.3e12})
+    return lines
+
+
 def other_configs(scp, si, torch, np, only=None, plain64=True):
     """Configs 1-3 and the X^6 chain on the GPU: forward and gradient times,
     rate, FP64 forward, and parity against the stored oracle results where
@@ -678,6 +713,9 @@ def main():
     ap.add_argument("--config-only", choices=("config1", "chain", "x6"), default=None,
                     help="with --configs: only this case (config1; chain: the 4-fluxonium "
                          "chain of configs 2/3; x6)")
+    ap.add_argument("--probe", action="store_true",
+                    help="only time the contraction probe (VALU and MFMA forms of the d = 3 "
+                         "contraction) and exit")
     ap.add_argument("--trotter", action="store_true",
                     help="only time the Suzuki-Trotter product formulas (one JSON line each) and exit")
     ap.add_argument("--trotter-orders", default="q1,q2,q4,q4j")
@@ -725,6 +763,10 @@ def main():
         return
     if args.lindblad:
         print(json.dumps(lindblad_line(scp, si, torch, np)), flush=True)
+        return
+    if args.probe:
+        for line in probe_lines(scp, torch, np):
+            print(json.dumps(line), flush=True)
         return
     if args.configs:
         for line in other_configs(scp, si, torch, np, args.config_only, not args.no_plain64):

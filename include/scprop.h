@@ -406,6 +406,23 @@ scp_status scp_propagate_adjoint_noalloc(scp_system* sys, const scp_solve_opts* 
                                          const void* psi0, const void* cotangent,
                                          double* grad_out, void* stream);
 
+/* Contraction probe (measurement only; no solve uses it).  The inner
+ * operation of the register-layout stepper at d = 3 -- a uniform complex 3 x 3
+ * operator applied to the 9 fibres of the 27 amplitudes each lane holds, the
+ * result accumulated -- in form 0 (VALU FMAs with the operator in scalar
+ * registers: the stepper's form), form 1 (v_mfma_f32_4x4x1f32 on the real
+ * 6 x 6 form padded to two 4-row blocks, with the per-application operand
+ * builds and register moves the stepper's layout would need) or form 2 (the
+ * same MFMAs with the operands built once and the accumulators left in
+ * place).  n_wg workgroups of 256 threads each run `iters` applications;
+ * application i uses operator i % nop of ops (device, nop x 18 floats: the
+ * real parts of the 9 entries row-major, then the imaginary parts; form 2
+ * uses operator 0 throughout).  out (device, n_wg * 256 floats) receives each
+ * lane's sum of its outputs (real parts + imaginary parts / 2).  Asynchronous
+ * on stream.  Errors: SCP_EINVAL, SCP_EHIP. */
+scp_status scp_probe_contraction(int32_t form, int32_t n_wg, int32_t iters, int32_t nop,
+                                 const void* ops, void* out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Suzuki-Trotter product formulas (Sec. 2.3 Trotterization solver, App. A).
  *

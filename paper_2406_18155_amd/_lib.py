@@ -113,6 +113,8 @@ EXPORTS = {
                                         C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     "scp_propagate_adjoint_noalloc": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p,
                                                 C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "scp_probe_contraction": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                        C.c_void_p, C.c_void_p]),
     "scp_destroy": (None, [C.c_void_p]),
     "scp_server_create": (C.c_int, [C.c_size_t, C.c_int32, C.c_double, C.c_void_p,
                                     C.POINTER(C.c_void_p)]),

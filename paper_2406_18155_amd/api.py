@@ -499,6 +499,19 @@ def fidelity_zcomp(U, tgt: Target, n_qubits, cotangent=None, stream=None):
     return F.value, np.array(ph[:n]), np.array(ph[n:])
 
 
+def probe_contraction(form, ops, iters, n_wg=1024, out=None, stream=None):
+    """The stepper's d = 3 contraction in form 0 (VALU), 1 (MFMA 4x4x1 with the
+    operand builds and moves the register layout needs) or 2 (MFMA issue
+    only); ops: (nop, 18) float32 on the device.  Returns the (n_wg * 256)
+    per-lane output sums (measurement only)."""
+    ops = ops.contiguous()
+    if out is None:
+        out = torch.empty(n_wg * 256, dtype=torch.float32, device=ops.device)
+    check(lib().scp_probe_contraction(int(form), int(n_wg), int(iters), int(ops.shape[0]),
+                                      _ptr(ops), _ptr(out), _stream_ptr(stream)))
+    return out
+
+
 def basis_columns(D, columns, dtype=torch.complex64, device="cuda"):
     psi0 = torch.zeros((len(columns), D), dtype=dtype, device=device)
     for j, c in enumerate(columns):
