@@ -129,6 +129,7 @@ EXPORTS = {
                                     C.POINTER(C.c_double), C.POINTER(C.c_double),
                                     C.POINTER(C.c_int32), C.POINTER(C.c_double),
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "scp_server_set_engine": (C.c_int, [C.c_void_p, C.c_int32]),
     "scp_server_destroy": (None, [C.c_void_p]),
     "scp_last_error": (C.c_char_p, []),
 }

@@ -321,7 +321,8 @@ __device__ __forceinline__ void g_apply(kptr<GArgs> A, const c32* __restrict__ y
 
 template <int d, int N, bool OPEN, bool CK>
 __global__ void __launch_bounds__((GShape<d, N, OPEN>::T))
-g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
+g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int n_lo, int n_hi,
+             const float4* __restrict__ st_in, float4* __restrict__ st_out) {
   using Sh = GShape<d, N, OPEN>;
   constexpr int L = Sh::L, T = Sh::T, E = Sh::E;
   // LDS: two stage-input buffers, the static diagonal, two stage tables
@@ -335,6 +336,8 @@ g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
   const int col = blockIdx.x;
   const float h = A->h;
   const int nsteps = A->nsteps;
+  // steps n_lo .. n_hi - 1; the compensated state comes from st_in (else the
+  // columns x0, lo = 0) and goes to st_out (a later call continues exactly)
   uint32_t pk[E];
   float hr[E], hm[E], lr[E], lm[E], ar[E], am_[E];
 #pragma unroll
@@ -360,10 +363,20 @@ g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
     pk[r] = p;
     c32 v;
     v.x = v.y = 0.f;
-    if (ok) v = ((const c32*)A->x0)[(size_t)col * L + e];
+    lr[r] = lm[r] = 0.f;
+    if (ok) {
+      if (st_in != nullptr) {
+        const float4 q = st_in[(size_t)col * L + e];
+        v.x = q.x;
+        v.y = q.y;
+        lr[r] = q.z;
+        lm[r] = q.w;
+      } else {
+        v = ((const c32*)A->x0)[(size_t)col * L + e];
+      }
+    }
     hr[r] = v.x;
     hm[r] = v.y;
-    lr[r] = lm[r] = 0.f;
     ar[r] = am_[r] = 0.f;
     if (ok) {
       lds[e] = v;
@@ -373,11 +386,11 @@ g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
       dgb[e] = g;
     }
   }
-  for (int t = tid; t < ntab; t += T) lds[3 * L + t] = gtab[t];
+  for (int t = tid; t < ntab; t += T) lds[3 * L + t] = gtab[(size_t)stage_c(n_lo, 0) * nrow + t];
   __syncthreads();
   int cur = 0;
 #pragma unroll 1
-  for (int n = 0; n < nsteps; ++n) {
+  for (int n = n_lo; n < n_hi; ++n) {
     if (CK) {
       kptr<GAdj> B = kconst(Bg);
       const int ce = B->ce;
@@ -399,7 +412,7 @@ g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
       c32* yn = lds + (cur ^ 1) * L;
       // the next stage's table, loaded now and stored after this stage
       const int n2 = s < 3 ? n : n + 1, s2 = s < 3 ? s + 1 : 0;
-      const bool more = n2 < nsteps;
+      const bool more = n2 < n_hi;
       const c32* gnext = gtab + (size_t)stage_c(n2, s2) * nrow;
       c32 pre[GA_PRE];
 #pragma unroll
@@ -456,7 +469,14 @@ g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg) {
       cur ^= 1;
     }
   }
-  if (A->xT == nullptr) return;
+  if (st_out != nullptr) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int e = tid + r * T;
+      if (e < L) st_out[(size_t)col * L + e] = make_float4(hr[r], hm[r], lr[r], lm[r]);
+    }
+  }
+  if (A->xT == nullptr || n_hi < nsteps) return;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int e = tid + r * T;
@@ -1268,20 +1288,25 @@ size_t g_lds_bytes(int ntab) {
   return sizeof(c32) * (3 * (size_t)GShape<d, N, OPEN>::L + 2 * (size_t)ntab);
 }
 
+// Steps [n_lo, n_hi) with the state from st_in / to st_out (nullable; see the
+// kernel); dadj != nullptr also writes the checkpoints.
 template <int d, int N, bool OPEN>
-hipError_t g_launch(const GArgs* dargs, const GAdj* dadj, int S, int ntab, hipStream_t s) {
+hipError_t g_launch(const GArgs* dargs, const GAdj* dadj, int S, int ntab, int n_lo, int n_hi,
+                    const float4* st_in, float4* st_out, hipStream_t s) {
   using Sh = GShape<d, N, OPEN>;
   const size_t sh = g_lds_bytes<d, N, OPEN>(ntab);
   if (dadj != nullptr) {
     (void)hipFuncSetAttribute((const void*)g_rk4_kernel<d, N, OPEN, true>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((g_rk4_kernel<d, N, OPEN, true>), dim3(S), dim3(Sh::T), sh, s, dargs, dadj);
+    hipLaunchKernelGGL((g_rk4_kernel<d, N, OPEN, true>), dim3(S), dim3(Sh::T), sh, s, dargs, dadj,
+                       n_lo, n_hi, st_in, st_out);
     return hipGetLastError();
   }
   {
     (void)hipFuncSetAttribute((const void*)g_rk4_kernel<d, N, OPEN, false>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    hipLaunchKernelGGL((g_rk4_kernel<d, N, OPEN, false>), dim3(S), dim3(Sh::T), sh, s, dargs, dadj);
+    hipLaunchKernelGGL((g_rk4_kernel<d, N, OPEN, false>), dim3(S), dim3(Sh::T), sh, s, dargs, dadj,
+                       n_lo, n_hi, st_in, st_out);
   }
   return hipGetLastError();
 }
@@ -1294,11 +1319,13 @@ hipError_t g_launch(const GArgs* dargs, const GAdj* dadj, int S, int ntab, hipSt
   X(3, 7) X(4, 3) X(4, 4) X(4, 5) X(4, 6) X(5, 3) X(5, 4) X(5, 5)
 
 hipError_t g_dispatch(int d, int N, bool open, const GArgs* dargs, const GAdj* dadj, int S, int ntab,
-                      hipStream_t s) {
-#define GA_CASE_O(dd_, nn_) \
-  if (open && d == dd_ && N == nn_) return g_launch<dd_, nn_, true>(dargs, dadj, S, ntab, s);
-#define GA_CASE_C(dd_, nn_) \
-  if (!open && d == dd_ && N == nn_) return g_launch<dd_, nn_, false>(dargs, dadj, S, ntab, s);
+                      int n_lo, int n_hi, const float4* st_in, float4* st_out, hipStream_t s) {
+#define GA_CASE_O(dd_, nn_)          \
+  if (open && d == dd_ && N == nn_) \
+    return g_launch<dd_, nn_, true>(dargs, dadj, S, ntab, n_lo, n_hi, st_in, st_out, s);
+#define GA_CASE_C(dd_, nn_)           \
+  if (!open && d == dd_ && N == nn_) \
+    return g_launch<dd_, nn_, false>(dargs, dadj, S, ntab, n_lo, n_hi, st_in, st_out, s);
   GA_OPEN_SHAPES(GA_CASE_O)
   GA_CLOSED_SHAPES(GA_CASE_C)
 #undef GA_CASE_O
@@ -1590,7 +1617,7 @@ static scp_status g_run(scp_system* sys, bool open, const double* gamma1, const 
   HIPCHK(hipGetLastError());
   if (S == 0) return SCP_OK;
   hipEvent_t t0 = timing_start(sys, st);
-  HIPCHK(g_dispatch(d, N, open, dargs, nullptr, S, A.ntab, st));
+  HIPCHK(g_dispatch(d, N, open, dargs, nullptr, S, A.ntab, 0, sys->n_steps, nullptr, nullptr, st));
   timing_stop(sys, t0, 0, st);
   return SCP_OK;
 }
@@ -1724,7 +1751,7 @@ scp_status launch_lindblad_adjoint(scp_system* sys, const double* gamma1, const 
   hipLaunchKernelGGL(gtab_kernel, dim3(3 * sys->n_steps), dim3(256), 0, st, dargs, d, N, gtab);
   HIPCHK(hipGetLastError());
   hipEvent_t t0 = timing_start(sys, st);
-  HIPCHK(g_dispatch(d, N, true, dargs, dadj, S, A.ntab, st));
+  HIPCHK(g_dispatch(d, N, true, dargs, dadj, S, A.ntab, 0, sys->n_steps, nullptr, nullptr, st));
   timing_stop(sys, t0, 0, st);
   t0 = timing_start(sys, st);
   HIPCHK(g_adj_dispatch(d, N, true, dargs, dadj, S, A.ntabg, w.nacc, -1, st));
@@ -1891,7 +1918,8 @@ scp_status launch_gather_ckpt_forward(scp_system* sys, int S, int ce, void* ws, 
   SCP_TRY(gc_prepare(sys, S, ce, false, base, ws_bytes, psi0, psiT, nullptr, true, w, A, st));
   hipEvent_t t0 = timing_start(sys, st);
   HIPCHK(g_dispatch(sys->d, sys->n_modes, false, reinterpret_cast<GArgs*>(base + w.args),
-                    reinterpret_cast<GAdj*>(base + w.adj), S, A.ntab, st));
+                    reinterpret_cast<GAdj*>(base + w.adj), S, A.ntab, 0, sys->n_steps, nullptr,
+                    nullptr, st));
   timing_stop(sys, t0, 0, st);
   return SCP_OK;
 }
@@ -1919,6 +1947,73 @@ scp_status launch_gather_adjoint(scp_system* sys, int S, int ce, void* ws, size_
     double v = 0.0;
     for (int c = 0; c < S; ++c) v += part[(size_t)c * w.nacc + k];   // fixed order
     if (!std::isfinite(v)) return fail(SCP_ENONFINITE, "gradient is not finite");
+    grad[k] = v;
+  }
+  return SCP_OK;
+}
+
+// --- serving: a closed-system request on the gather engine, in chunks --------
+// Workspace: the layout of gc_layout (the adjoint's when the gradient is
+// wanted) followed by the compensated state [S][D] float4 between chunks.
+size_t gather_serve_bytes(const scp_system* sys, int S, int ce, bool grad) {
+  GcLayout w;
+  if (gc_layout(sys, S, ce, grad, w, nullptr) != SCP_OK) {
+    set_error("");
+    return 0;
+  }
+  return w.total + align256((size_t)S * sys->D * sizeof(float4));
+}
+
+scp_status gather_serve_prepare(scp_system* sys, int S, int ce, bool grad, void* ws, size_t bytes,
+                                const float2* psi0, float2* psiT, const float2* cot, hipStream_t st) {
+  GcLayout w;
+  GArgs A;
+  return gc_prepare(sys, S, ce, grad, static_cast<char*>(ws), bytes, psi0, psiT, cot, true, w, A,
+                    st);
+}
+
+// Forward steps [n0, n1): from psi0 when n0 = 0, else from the saved state;
+// the state is saved after, psiT written when n1 = n_steps, checkpoints kept
+// when the gradient is wanted.
+scp_status gather_serve_forward(scp_system* sys, int S, int ce, bool grad, void* ws, int n0, int n1,
+                                hipStream_t st) {
+  GcLayout w;
+  GArgs A;
+  SCP_TRY(gc_layout(sys, S, ce, grad, w, &A));
+  char* base = static_cast<char*>(ws);
+  float4* state = reinterpret_cast<float4*>(base + w.total);
+  HIPCHK(g_dispatch(sys->d, sys->n_modes, false, reinterpret_cast<GArgs*>(base + w.args),
+                    grad ? reinterpret_cast<GAdj*>(base + w.adj) : nullptr, S, A.ntab, n0, n1,
+                    n0 == 0 ? nullptr : state, state, st));
+  return SCP_OK;
+}
+
+// One launch of the reverse walk (gs = nckpt down to 0, in order).
+scp_status gather_serve_adjoint(scp_system* sys, int S, int ce, void* ws, int gs, hipStream_t st) {
+  GcLayout w;
+  GArgs A;
+  SCP_TRY(gc_layout(sys, S, ce, true, w, &A));
+  char* base = static_cast<char*>(ws);
+  HIPCHK(g_adj_dispatch(sys->d, sys->n_modes, false, reinterpret_cast<GArgs*>(base + w.args),
+                        reinterpret_cast<GAdj*>(base + w.adj), S, A.ntabg, w.nacc, gs, st));
+  return SCP_OK;
+}
+
+int gather_serve_nckpt(const scp_system* sys, int ce) { return (sys->n_steps + ce - 1) / ce; }
+
+// The gradient after the last reverse launch (synchronises st).
+scp_status gather_serve_gradient(scp_system* sys, int S, int ce, void* ws, std::vector<double>& grad,
+                                 hipStream_t st) {
+  GcLayout w;
+  SCP_TRY(gc_layout(sys, S, ce, true, w, nullptr));
+  std::vector<double> part((size_t)S * w.nacc);
+  HIPCHK(hipMemcpyAsync(part.data(), static_cast<char*>(ws) + w.part, part.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  grad.assign(w.nacc, 0.0);
+  for (int k = 0; k < w.nacc; ++k) {
+    double v = 0.0;
+    for (int c = 0; c < S; ++c) v += part[(size_t)c * w.nacc + k];   // fixed order
     grad[k] = v;
   }
   return SCP_OK;

@@ -282,5 +282,14 @@ scp_status launch_gather_ckpt_forward(scp_system* sys, int S, int ce, void* ws, 
                                       const float2* psi0, float2* psiT, hipStream_t st);
 scp_status launch_gather_adjoint(scp_system* sys, int S, int ce, void* ws, size_t ws_bytes,
                                  const float2* cot, double* grad, hipStream_t st);
+size_t gather_serve_bytes(const scp_system* sys, int S, int ce, bool grad);
+scp_status gather_serve_prepare(scp_system* sys, int S, int ce, bool grad, void* ws, size_t bytes,
+                                const float2* psi0, float2* psiT, const float2* cot, hipStream_t st);
+scp_status gather_serve_forward(scp_system* sys, int S, int ce, bool grad, void* ws, int n0, int n1,
+                                hipStream_t st);
+scp_status gather_serve_adjoint(scp_system* sys, int S, int ce, void* ws, int gs, hipStream_t st);
+int gather_serve_nckpt(const scp_system* sys, int ce);
+scp_status gather_serve_gradient(scp_system* sys, int S, int ce, void* ws, std::vector<double>& grad,
+                                 hipStream_t st);
 
 }  // namespace scp

@@ -14,6 +14,10 @@
 //      recompute launch and a reverse launch;
 //   3. reduce the fidelity of requests whose forward completed (and seed the
 //      costate of gradient requests), finish gradients, release memory.
+// A request that the gather engine runs (few columns of a small device, as
+// for scp_propagate) is not batched: its chunk is one gather launch of its own
+// on a worker stream (a step range of the forward, its state saved between
+// chunks, or some of the reverse walk's per-segment launches).
 // The per-request state (psi hi/lo, costate, per-wave FP64 accumulators) is
 // carried between ticks exactly, so a request's result does not depend on
 // what else is in flight or on the chunk boundaries.  Every launch is bounded
@@ -107,6 +111,9 @@ struct Request {
   std::string err;
   double cost_step = 1.0;   // relative device time of one forward step of one workgroup
   hipStream_t tick_stream = nullptr;   // worker stream of this tick's launch
+  bool gather = false;      // runs on the gather engine
+  void* gws = nullptr;      // its workspace (inside dmem)
+  size_t gws_bytes = 0;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -117,6 +124,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct scp_server {
   size_t budget = 0, used = 0;
   int max_active = 64;
+  int engine = 0;                      // as scp_system_set_engine: 0 automatic, 1 register, 2 gather
   double chunk_work = 2.0e7;   // per-tick work budget per workgroup (cost units)
   hipStream_t stream = nullptr;        // admission (builds and uploads)
   static constexpr int kWork = 4;      // one per hardware queue
@@ -167,6 +175,19 @@ scp_status admit(scp_server* sv, Request* r) {
   r->ce = (int)std::ceil(std::sqrt((double)sys->n_steps));
   r->nckpt = (sys->n_steps + r->ce - 1) / r->ce;
   r->nwg = (r->S + P.CPW - 1) / P.CPW;
+  // the gather engine where scp_propagate would take it and its tables fit
+  // the budget beside what is admitted
+  r->gather = false;
+  if (sv->engine != 1 && (sv->engine == 2 ? gather_supported(sys) : gather_preferred(sys, r->S))) {
+    if (gather_grad_check(sys) == SCP_OK) {
+      r->gws_bytes = gather_serve_bytes(sys, r->S, r->ce, r->want_grad != 0);
+      r->gather = r->gws_bytes > 0 &&
+                  sv->used + r->gws_bytes + (size_t)(4 << 20) + 2 * (size_t)r->S * sys->D * 8 <=
+                      sv->budget;
+    } else {
+      set_error("");
+    }
+  }
   size_t off = 0;
   auto take = [&](size_t n) {
     size_t o = off;
@@ -176,8 +197,10 @@ scp_status admit(scp_server* sv, Request* r) {
   const size_t o_psi = take(S * D * 8), o_hi = take(S * D * 8), o_lo = take(S * D * 8),
                o_cot = take(S * D * 8), o_rows = take(r->d_c * 8), o_cols = take(r->d_c * 4),
                o_tgt = take((size_t)r->d_c * r->d_c * 16), o_tau = take(16);
-  size_t o_ck = 0, o_seg = 0, o_sum = 0, o_ls = 0, o_part = 0;
-  if (r->want_grad) {
+  size_t o_ck = 0, o_seg = 0, o_sum = 0, o_ls = 0, o_part = 0, o_g = 0;
+  if (r->gather) {
+    o_g = take(r->gws_bytes);
+  } else if (r->want_grad) {
     o_ck = take((size_t)r->nckpt * S * D * 16);
     o_seg = take((size_t)r->ce * 4 * S * D * 8);
     o_sum = take(S * D * 8);
@@ -199,7 +222,8 @@ scp_status admit(scp_server* sv, Request* r) {
   r->d_cols = (int32_t*)(b + o_cols);
   r->d_target = (double2*)(b + o_tgt);
   r->d_tau = (double2*)(b + o_tau);
-  if (r->want_grad) {
+  if (r->gather) r->gws = b + o_g;
+  if (!r->gather && r->want_grad) {
     r->ckpt = (float4*)(b + o_ck);
     r->segbuf = (float2*)(b + o_seg);
     r->sum = (float2*)(b + o_sum);
@@ -214,6 +238,11 @@ scp_status admit(scp_server* sv, Request* r) {
   hipMemcpyAsync(r->d_cols, r->cols.data(), r->cols.size() * 4, hipMemcpyHostToDevice, sv->stream);
   hipMemcpyAsync(r->d_target, r->target.data(), r->target.size() * 8, hipMemcpyHostToDevice,
                  sv->stream);
+  if (r->gather) {
+    scp_status gs = gather_serve_prepare(sys, r->S, r->ce, r->want_grad != 0, r->gws, r->gws_bytes,
+                                         r->psi, r->psi, r->cot, sv->stream);
+    if (gs != SCP_OK) return gs;
+  }
   if (hipStreamSynchronize(sv->stream) != hipSuccess) return fail(SCP_EHIP, "admission copy");
   r->cost_step = (double)P.CPW * P.D * (P.L * 2.0 + 4.0 * P.MP);
   r->state = RQ_RUNNING;
@@ -338,6 +367,7 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
     // (kind, d, NR, MP, real frame)
     std::map<std::tuple<int, int, int, int, int>, std::vector<Work>> classes;
     for (Request* r : sv->active) {
+      if (r->gather) continue;
       const Plan& P = r->sys->plan;
       const double per_wg_step = r->cost_step;
       const int steps = std::max(8, (int)(sv->chunk_work / per_wg_step));
@@ -447,6 +477,28 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
         w.r->tick_stream = st;
       }
     }
+    // gather-engine requests: one launch of their own each (a step range of
+    // the forward, or reverse-walk launches of about as many steps)
+    for (Request* r : sv->active) {
+      if (!r->gather) continue;
+      hipStream_t st = sv->work[ci++ % scp_server::kWork];
+      const int steps = std::max(8, (int)(sv->chunk_work / r->cost_step));
+      if (r->phase == 0) {
+        const int n0 = r->n_done, n1 = std::min(r->sys->n_steps, n0 + steps);
+        s = gather_serve_forward(r->sys, r->S, r->ce, r->want_grad != 0, r->gws, n0, n1, st);
+        if (s != SCP_OK) return s;
+        r->n_done = n1;
+      } else {
+        const int launches = std::max(1, steps / r->ce);
+        const int g_lo = std::max(0, r->seg_next - launches + 1);
+        for (int gs = r->seg_next; gs >= g_lo; --gs) {
+          s = gather_serve_adjoint(r->sys, r->S, r->ce, r->gws, gs, st);
+          if (s != SCP_OK) return s;
+        }
+        r->seg_next = g_lo - 1;
+      }
+      r->tick_stream = st;
+    }
     // 3. fidelity (and costate) for forward completions
     for (Request* r : sv->active)
       if (r->phase == 0 && r->n_done == r->sys->n_steps) {
@@ -467,10 +519,16 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
         r->F = (tau.x * tau.x + tau.y * tau.y) / ((double)r->d_c * r->d_c);
         if (r->want_grad) {
           r->phase = 1;
-          r->seg_next = r->nckpt - 1;
+          // the gather engine's reverse launches run nckpt down to 0 (the
+          // first recomputes the last segment only)
+          r->seg_next = r->gather ? gather_serve_nckpt(r->sys, r->ce) : r->nckpt - 1;
         } else {
           done = true;
         }
+      } else if (r->phase == 1 && r->seg_next < 0 && r->gather) {
+        s = gather_serve_gradient(r->sys, r->S, r->ce, r->gws, r->grad, sv->stream);
+        if (s != SCP_OK) return s;
+        done = true;
       } else if (r->phase == 1 && r->seg_next < 0) {
         const int nacc = r->sys->plan.nacc;
         std::vector<double> part((size_t)r->nwg * 4 * nacc);
@@ -515,6 +573,12 @@ scp_status scp_server_result(scp_server* sv, int64_t id, int32_t* state, double*
   if (t_admit) *t_admit = r->t_admit;
   if (t_done) *t_done = r->t_done;
   if (r->state == RQ_FAILED) return fail(SCP_EINVAL, "request failed: " + r->err);
+  return SCP_OK;
+}
+
+scp_status scp_server_set_engine(scp_server* sv, int32_t engine) {
+  if (!sv || engine < 0 || engine > 2) return fail(SCP_EINVAL, "engine must be 0, 1 or 2");
+  sv->engine = engine;
   return SCP_OK;
 }
 

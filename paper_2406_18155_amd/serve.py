@@ -19,12 +19,16 @@ STATE = {0: "queued", 1: "running", 2: "done", 3: "failed"}
 
 
 class Server:
-    def __init__(self, hbm_budget_bytes, max_active=64, chunk_work=0.0, stream=None):
+    ENGINES = {"auto": 0, "register": 1, "gather": 2}
+
+    def __init__(self, hbm_budget_bytes, max_active=64, chunk_work=0.0, stream=None,
+                 engine="auto"):
         h = C.c_void_p()
         check(lib().scp_server_create(int(hbm_budget_bytes), int(max_active), float(chunk_work),
                                       _stream_ptr(stream), C.byref(h)))
         self.handle = h
         self.n_params = {}
+        check(lib().scp_server_set_engine(self.handle, self.ENGINES[engine]))
 
     def submit(self, desc, want_grad):
         sd, keep = marshal(desc)

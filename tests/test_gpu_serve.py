@@ -35,11 +35,14 @@ def short_request(r, T=4.0):
     return q
 
 
-def direct(scp, desc, want_grad):
+def direct(scp, desc, want_grad, engine="auto"):
+    """The same solve through scp_propagate / scp_propagate_adjoint on the
+    engine the server uses; returns F, the gradient and that engine."""
     g = scp.System(desc)
-    g.set_engine("register")   # the server's batched kernels are the register-layout stepper's
+    g.set_engine(engine)
     psi0 = scp.basis_columns(g.D, desc["columns"])
     opts = g.opts(psi0.shape[0], with_ckpt=1)
+    used = g.engine(opts, with_grad=True)
     ws = g.workspace(opts, with_grad=True)
     U = g.propagate(psi0, opts=opts, workspace=ws)
     cot = torch.empty_like(U)
@@ -47,21 +50,28 @@ def direct(scp, desc, want_grad):
                         cotangent=cot)
     grad = g.adjoint(cot, opts, ws) if want_grad else None
     g.close()
-    return F, grad
+    return F, grad, used
 
 
-def test_server_equals_direct_path_and_oracle(scp):
+@pytest.mark.parametrize("engine", ["register", "auto"])
+def test_server_equals_direct_path_and_oracle(scp, engine):
+    # "register": every request in the batched register-layout kernels; "auto":
+    # the small devices' requests on the gather engine in chunks of their own
     reqs = [short_request(r) for r in range(6)]
-    srv = scp.serve.Server(64 << 30, max_active=8, chunk_work=3e5)
+    srv = scp.serve.Server(64 << 30, max_active=8, chunk_work=3e5, engine=engine)
     ids = [srv.submit(q, True) for q in reqs]
     res = scp.serve.drain(srv, ids)
+    used = []
     for q, rid in zip(reqs, ids):
-        print(f"[serve] {q['family']} N={len(q['modes'])} d={q['modes'][0]['trunc']}", flush=True)
         r = res[rid]
         assert r["state"] == "done"
-        F, g = direct(scp, q, True)
+        F, g, eng = direct(scp, q, True, engine)
+        used.append(eng)
+        print(f"[serve] {q['family']} N={len(q['modes'])} d={q['modes'][0]['trunc']} {eng}",
+              flush=True)
         assert r["F"] == F
         assert np.array_equal(r["grad"], g)
+    assert ("gather" in used) == (engine == "auto")
     # two of them against the oracle
     for q, rid in list(zip(reqs, ids))[:2]:
         L, Fo, tau, U, go = loss_and_grad(OracleSystem(q))
