@@ -158,20 +158,28 @@ def plain64_forward_ms(scp, si, torch, desc, S):
     return e0.elapsed_time(e1)
 
 
-def serving_leg(scp, si, torch, np, n_req):
+def serving_leg(scp, si, torch, np, n_req, poisson=True):
     """Continuous-batching replay of the first n_req requests of the mixed
-    request stream: saturated, then Poisson at 0.5x and 0.9x saturation."""
+    request stream: saturated, then Poisson at 0.5x and 0.9x saturation, on
+    the server's default engine (the batched register-layout kernels); the
+    saturated replay again with the small devices' requests batched on the
+    gather engine, for comparison."""
     from paper_2406_18155_amd import serve
     reqs = [si.serving_request(r) for r in range(n_req)]
     budget = int(0.5 * torch.cuda.mem_get_info()[0])
     keys = ("p50_s", "p99_s", "mean_s", "makespan_s", "requests_per_s", "steps_dim2_per_s",
             "failed")
-    sat = serve.run_stream(reqs, [0.0] * n_req, budget, max_active=64)
-    out = {"requests": n_req, "hbm_budget_bytes": budget, "max_active": 64,
+    sat = serve.run_stream(reqs, [0.0] * n_req, budget, max_active=64, progress_s=20.0)
+    out = {"requests": n_req, "hbm_budget_bytes": budget, "max_active": 64, "engine": "register",
            "saturated": {k: sat[k] for k in keys}}
+    gat = serve.run_stream(reqs, [0.0] * n_req, budget, max_active=64, engine="auto",
+                           progress_s=20.0)
+    out["saturated_gather_routing"] = {k: gat[k] for k in keys}
+    if not poisson:
+        return out
     for frac in (0.5, 0.9):
         arr = si.poisson_arrivals(n_req, frac * sat["requests_per_s"])
-        r = serve.run_stream(reqs, arr, budget, max_active=64)
+        r = serve.run_stream(reqs, arr, budget, max_active=64, progress_s=20.0)
         out[f"poisson_{frac}x"] = {k: r[k] for k in keys}
     # the same requests alone, FP32 fused path against the plain FP64 path
     # (forward only: the FP64 path has no adjoint), on a bounded sample
@@ -708,6 +716,9 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-plain64", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=128)
+    ap.add_argument("--serve-only", type=int, default=0,
+                    help="only replay the first N requests of the serving stream saturated (both "
+                         "engine settings) and exit")
     ap.add_argument("--configs", action="store_true",
                     help="only time configs 1-3 (one JSON line each) and exit")
     ap.add_argument("--config-only", choices=("config1", "chain", "x6"), default=None,
@@ -763,6 +774,10 @@ def main():
         return
     if args.lindblad:
         print(json.dumps(lindblad_line(scp, si, torch, np)), flush=True)
+        return
+    if args.serve_only > 0:
+        line = serving_leg(scp, si, torch, np, args.serve_only, poisson=False)
+        print(json.dumps(line), flush=True)
         return
     if args.probe:
         for line in probe_lines(scp, torch, np):

@@ -498,12 +498,15 @@ void scp_destroy(scp_system* sys);
  * scp_server_step is one tick: admit, advance every running request by one
  * chunk (forward steps, then adjoint segments) with one batched launch per
  * size class (d, register modes, pair terms per position), reduce fidelities,
- * finish gradients, release memory.  A request the gather engine would run
- * (scp_system_set_engine: few columns of a small device; the server's engine
- * setting, scp_server_set_engine, applies) takes its chunks as launches of its
- * own instead: a step range of the gather forward with its compensated state
- * saved between chunks, or some of the gather adjoint's per-segment launches,
- * when its workspace fits the budget beside what is admitted.  Work per tick
+ * finish gradients, release memory.  With scp_server_set_engine(sv, 0 or 2),
+ * requests the gather engine would run (few columns of a small device, as for
+ * scp_system_set_engine) are batched per (d, modes) on the gather engine
+ * instead, when their workspace fits the budget beside what is admitted: per
+ * tick one launch of every such request's step range of the forward (its
+ * compensated state saved between chunks) and per round one launch of the
+ * next segment of every such request's reverse walk.  The server starts with
+ * engine 1 (the register-layout kernels), which gives the higher throughput
+ * on a saturated mix.  Work per tick
  * per workgroup is about chunk_work cost units (0 = default).  A request's
  * result is bitwise the same whether it runs alone or among others, and the
  * same as scp_propagate / scp_propagate_adjoint on the same engine.  The server allocates device memory
@@ -543,8 +546,8 @@ scp_status scp_server_result(scp_server* sv, int64_t id, int32_t* state, double*
                              double* t_done);
 
 /* Engine of later admissions: 0 automatic (as scp_system_set_engine), 1 the
- * register-layout kernels only, 2 the gather engine wherever it runs.
- * SCP_EINVAL otherwise. */
+ * register-layout kernels only (the default), 2 the gather engine wherever it
+ * runs.  SCP_EINVAL otherwise. */
 scp_status scp_server_set_engine(scp_server* sv, int32_t engine);
 
 void scp_server_destroy(scp_server* sv);

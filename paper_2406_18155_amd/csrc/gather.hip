@@ -319,10 +319,12 @@ __device__ __forceinline__ void g_apply(kptr<GArgs> A, const c32* __restrict__ y
   }
 }
 
+// One column (col) of a propagation: the body of the stepper kernels.
 template <int d, int N, bool OPEN, bool CK>
-__global__ void __launch_bounds__((GShape<d, N, OPEN>::T))
-g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int n_lo, int n_hi,
-             const float4* __restrict__ st_in, float4* __restrict__ st_out) {
+__device__ __forceinline__ void g_rk4_body(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg,
+                                           int col, int n_lo, int n_hi,
+                                           const float4* __restrict__ st_in,
+                                           float4* __restrict__ st_out) {
   using Sh = GShape<d, N, OPEN>;
   constexpr int L = Sh::L, T = Sh::T, E = Sh::E;
   // LDS: two stage-input buffers, the static diagonal, two stage tables
@@ -333,7 +335,6 @@ g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int n_lo
   c32* dgb = lds + 2 * L;
   const c32* gtab = (const c32*)A->gtab;
   const int tid = threadIdx.x;
-  const int col = blockIdx.x;
   const float h = A->h;
   const int nsteps = A->nsteps;
   // steps n_lo .. n_hi - 1; the compensated state comes from st_in (else the
@@ -487,6 +488,23 @@ g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int n_lo
       ((c32*)A->xT)[(size_t)col * L + e] = v;
     }
   }
+}
+
+template <int d, int N, bool OPEN, bool CK>
+__global__ void __launch_bounds__((GShape<d, N, OPEN>::T))
+g_rk4_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int n_lo, int n_hi,
+             const float4* __restrict__ st_in, float4* __restrict__ st_out) {
+  g_rk4_body<d, N, OPEN, CK>(Ag, Bg, blockIdx.x, n_lo, n_hi, st_in, st_out);
+}
+
+// Batched (serving): every workgroup reads its own work item -- its request's
+// description, column, step range and state buffers.
+template <int d, int N, bool CK>
+__global__ void __launch_bounds__((GShape<d, N, false>::T))
+g_rk4_batched_kernel(const GItem* __restrict__ items) {
+  kptr<GItem> it = kconst(items) + blockIdx.x;
+  g_rk4_body<d, N, false, CK>((const GArgs*)it->A, (const GAdj*)it->B, it->col, it->n_lo,
+                              it->n_hi, it->st_in, it->st_out);
 }
 
 // ---------------------------------------------------------------------------
@@ -687,9 +705,10 @@ __device__ __forceinline__ float im_rowdot(const c32* __restrict__ row, const c3
   return s;
 }
 
+// Block blk of a reverse-walk launch for segment gseg (see g_adj_kernel).
 template <int d, int N, bool OPEN>
-__global__ void __launch_bounds__((GShape<d, N, OPEN>::T))
-g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int gseg) {
+__device__ __forceinline__ void g_adj_body(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg,
+                                           int gseg, int blk) {
   using Sh = GShape<d, N, OPEN>;
   constexpr int L = Sh::L, T = Sh::T, E = Sh::E, D = Sh::D, dd = d * d;
   constexpr int NW = T / 64;
@@ -716,8 +735,8 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int gseg
   // segment gseg back while the other S recompute segment gseg - 1 into the
   // other stage-input buffer, so the recompute hides behind the reverse walk.
   const int S = A->S;
-  const bool rev_role = OPEN || (int)blockIdx.x < S;
-  const int col = (OPEN || rev_role) ? (int)blockIdx.x : (int)blockIdx.x - S;
+  const bool rev_role = OPEN || blk < S;
+  const int col = (OPEN || rev_role) ? blk : blk - S;
   const int g_hi = OPEN ? nck - 1 : (rev_role ? gseg : gseg - 1);
   const int g_lo = OPEN ? 0 : g_hi;
   if (!OPEN && (g_hi < 0 || g_hi >= nck)) return;
@@ -1248,6 +1267,21 @@ g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int gseg
   if (prev_row >= 0) fold_prev();
   __syncthreads();
   for (int t = tid; t < nacc; t += T) B->part[(size_t)col * nacc + t] = acc[t];
+}
+
+template <int d, int N, bool OPEN>
+__global__ void __launch_bounds__((GShape<d, N, OPEN>::T))
+g_adj_kernel(const GArgs* __restrict__ Ag, const GAdj* __restrict__ Bg, int gseg) {
+  g_adj_body<d, N, OPEN>(Ag, Bg, gseg, blockIdx.x);
+}
+
+// Batched (serving, closed systems): item.col is the block of the request's
+// 2S-block launch, item.gseg its segment.
+template <int d, int N>
+__global__ void __launch_bounds__((GShape<d, N, false>::T))
+g_adj_batched_kernel(const GItem* __restrict__ items) {
+  kptr<GItem> it = kconst(items) + blockIdx.x;
+  g_adj_body<d, N, false>((const GArgs*)it->A, (const GAdj*)it->B, it->gseg, it->col);
 }
 
 // Unit-rate relaxation band of every mode at every half-step q (t = q h/2):
@@ -2000,6 +2034,75 @@ scp_status gather_serve_adjoint(scp_system* sys, int S, int ce, void* ws, int gs
 }
 
 int gather_serve_nckpt(const scp_system* sys, int ce) { return (sys->n_steps + ce - 1) / ce; }
+
+scp_status gather_serve_info(const scp_system* sys, int S, int ce, bool grad, void* ws,
+                             GServeInfo& out) {
+  GcLayout w;
+  GArgs A;
+  SCP_TRY(gc_layout(sys, S, ce, grad, w, &A));
+  char* base = static_cast<char*>(ws);
+  out.A = base + w.args;
+  out.B = base + w.adj;
+  out.state = reinterpret_cast<float4*>(base + w.total);
+  out.lds_fwd = sizeof(c32) * (3 * (size_t)sys->D + 2 * (size_t)A.ntab);
+  out.lds_adj = g_adj_lds(sys->d, sys->n_modes, false, A.ntabg, w.nacc);
+  out.nck = w.nck;
+  return SCP_OK;
+}
+
+namespace {
+
+template <int d, int N>
+hipError_t g_fwd_batched_launch(bool ck, const GItem* items, int n, size_t sh, hipStream_t s) {
+  using Sh = GShape<d, N, false>;
+  if (sh > 163840) return hipErrorInvalidValue;
+  if (ck) {
+    (void)hipFuncSetAttribute((const void*)g_rk4_batched_kernel<d, N, true>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((g_rk4_batched_kernel<d, N, true>), dim3(n), dim3(Sh::T), sh, s, items);
+  } else {
+    (void)hipFuncSetAttribute((const void*)g_rk4_batched_kernel<d, N, false>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    hipLaunchKernelGGL((g_rk4_batched_kernel<d, N, false>), dim3(n), dim3(Sh::T), sh, s, items);
+  }
+  return hipGetLastError();
+}
+
+template <int d, int N>
+hipError_t g_adj_batched_launch(const GItem* items, int n, size_t sh, hipStream_t s) {
+  using Sh = GShape<d, N, false>;
+  if (sh > 163840) return hipErrorInvalidValue;
+  (void)hipFuncSetAttribute((const void*)g_adj_batched_kernel<d, N>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+  hipLaunchKernelGGL((g_adj_batched_kernel<d, N>), dim3(n), dim3(Sh::T), sh, s, items);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+scp_status gather_launch_fwd_batched(int d, int N, bool ck, const GItem* items, int n, size_t lds,
+                                     hipStream_t st) {
+#define GA_FWD_B(dd_, nn_) \
+  if (d == dd_ && N == nn_) {                                                  \
+    HIPCHK((g_fwd_batched_launch<dd_, nn_>(ck, items, n, lds, st)));          \
+    return SCP_OK;                                                            \
+  }
+  GA_CLOSED_SHAPES(GA_FWD_B)
+#undef GA_FWD_B
+  return fail(SCP_EINVAL, "gather engine: no compiled stepper for this shape");
+}
+
+scp_status gather_launch_adj_batched(int d, int N, const GItem* items, int n, size_t lds,
+                                     hipStream_t st) {
+#define GA_ADJ_B(dd_, nn_) \
+  if (d == dd_ && N == nn_) {                                                  \
+    HIPCHK((g_adj_batched_launch<dd_, nn_>(items, n, lds, st)));              \
+    return SCP_OK;                                                            \
+  }
+  GA_CLOSED_SHAPES(GA_ADJ_B)
+#undef GA_ADJ_B
+  return fail(SCP_EINVAL, "gather engine: no compiled stepper for this shape");
+}
 
 // The gradient after the last reverse launch (synchronises st).
 scp_status gather_serve_gradient(scp_system* sys, int S, int ce, void* ws, std::vector<double>& grad,

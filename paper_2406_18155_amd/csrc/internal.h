@@ -282,6 +282,29 @@ scp_status launch_gather_ckpt_forward(scp_system* sys, int S, int ce, void* ws, 
                                       const float2* psi0, float2* psiT, hipStream_t st);
 scp_status launch_gather_adjoint(scp_system* sys, int S, int ce, void* ws, size_t ws_bytes,
                                  const float2* cot, double* grad, hipStream_t st);
+// A workgroup's work item of a batched gather-engine launch (serving).
+struct GItem {
+  const void* A;          // the request's description (device GArgs)
+  const void* B;          // its adjoint description (device GAdj; nullptr: no checkpoints)
+  const float4* st_in;    // forward: the saved state (nullptr: start from the columns)
+  float4* st_out;         // forward: where the state is saved
+  int col, n_lo, n_hi;    // forward: column and step range; reverse: col = block of 2S
+  int gseg;               // reverse: segment
+};
+// Device pointers and LDS needs of a request prepared by gather_serve_prepare.
+struct GServeInfo {
+  const void* A;
+  const void* B;
+  float4* state;
+  size_t lds_fwd, lds_adj;
+  int nck;
+};
+scp_status gather_serve_info(const scp_system* sys, int S, int ce, bool grad, void* ws,
+                             GServeInfo& out);
+scp_status gather_launch_fwd_batched(int d, int N, bool ck, const GItem* items, int n, size_t lds,
+                                     hipStream_t st);
+scp_status gather_launch_adj_batched(int d, int N, const GItem* items, int n, size_t lds,
+                                     hipStream_t st);
 size_t gather_serve_bytes(const scp_system* sys, int S, int ce, bool grad);
 scp_status gather_serve_prepare(scp_system* sys, int S, int ce, bool grad, void* ws, size_t bytes,
                                 const float2* psi0, float2* psiT, const float2* cot, hipStream_t st);

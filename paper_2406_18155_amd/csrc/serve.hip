@@ -14,10 +14,11 @@
 //      recompute launch and a reverse launch;
 //   3. reduce the fidelity of requests whose forward completed (and seed the
 //      costate of gradient requests), finish gradients, release memory.
-// A request that the gather engine runs (few columns of a small device, as
-// for scp_propagate) is not batched: its chunk is one gather launch of its own
-// on a worker stream (a step range of the forward, its state saved between
-// chunks, or some of the reverse walk's per-segment launches).
+// With the engine set to 0 or 2, requests that the gather engine runs (few
+// columns of a small device, as for scp_propagate) are batched per (d, modes)
+// on it instead: one launch per tick of every such request's step range of
+// the forward (its compensated state saved between chunks), and per round one
+// launch of the next segment of every such request's reverse walk.
 // The per-request state (psi hi/lo, costate, per-wave FP64 accumulators) is
 // carried between ticks exactly, so a request's result does not depend on
 // what else is in flight or on the chunk boundaries.  Every launch is bounded
@@ -114,6 +115,7 @@ struct Request {
   bool gather = false;      // runs on the gather engine
   void* gws = nullptr;      // its workspace (inside dmem)
   size_t gws_bytes = 0;
+  GServeInfo gi{};          // its device descriptions, state buffer and LDS needs
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -124,7 +126,10 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct scp_server {
   size_t budget = 0, used = 0;
   int max_active = 64;
-  int engine = 0;                      // as scp_system_set_engine: 0 automatic, 1 register, 2 gather
+  // engine of admissions, as scp_system_set_engine (0 automatic, 1 register,
+  // 2 gather); the register-layout kernels by default: batched, they give the
+  // higher throughput under load
+  int engine = 1;
   double chunk_work = 2.0e7;   // per-tick work budget per workgroup (cost units)
   hipStream_t stream = nullptr;        // admission (builds and uploads)
   static constexpr int kWork = 4;      // one per hardware queue
@@ -241,6 +246,7 @@ scp_status admit(scp_server* sv, Request* r) {
   if (r->gather) {
     scp_status gs = gather_serve_prepare(sys, r->S, r->ce, r->want_grad != 0, r->gws, r->gws_bytes,
                                          r->psi, r->psi, r->cot, sv->stream);
+    if (gs == SCP_OK) gs = gather_serve_info(sys, r->S, r->ce, r->want_grad != 0, r->gws, r->gi);
     if (gs != SCP_OK) return gs;
   }
   if (hipStreamSynchronize(sv->stream) != hipSuccess) return fail(SCP_EHIP, "admission copy");
@@ -392,6 +398,13 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
       }
       need += 2 * 256 * rounds;   // alignment of every upload
     }
+    // the gather-engine requests' items (batched below)
+    for (Request* r : sv->active)
+      if (r->gather) {
+        const int steps = std::max(8, (int)(sv->chunk_work / r->cost_step));
+        const size_t rounds = r->phase == 0 ? 1 : (size_t)std::max(1, steps / r->ce);
+        need += rounds * (2 * (size_t)r->S * sizeof(GItem) + 2 * 256);
+      }
     scp_status s = ensure_items(sv, need);
     if (s != SCP_OK) return s;
     size_t off = 0;
@@ -477,27 +490,70 @@ scp_status scp_server_step(scp_server* sv, int32_t* n_active, int32_t* n_queued)
         w.r->tick_stream = st;
       }
     }
-    // gather-engine requests: one launch of their own each (a step range of
-    // the forward, or reverse-walk launches of about as many steps)
-    for (Request* r : sv->active) {
-      if (!r->gather) continue;
-      hipStream_t st = sv->work[ci++ % scp_server::kWork];
-      const int steps = std::max(8, (int)(sv->chunk_work / r->cost_step));
-      if (r->phase == 0) {
-        const int n0 = r->n_done, n1 = std::min(r->sys->n_steps, n0 + steps);
-        s = gather_serve_forward(r->sys, r->S, r->ce, r->want_grad != 0, r->gws, n0, n1, st);
-        if (s != SCP_OK) return s;
-        r->n_done = n1;
-      } else {
-        const int launches = std::max(1, steps / r->ce);
-        const int g_lo = std::max(0, r->seg_next - launches + 1);
-        for (int gs = r->seg_next; gs >= g_lo; --gs) {
-          s = gather_serve_adjoint(r->sys, r->S, r->ce, r->gws, gs, st);
+    // gather-engine requests, batched per (kind, d, modes, checkpoints)
+    {
+      std::map<std::tuple<int, int, int, int>, std::vector<Request*>> gcls;
+      for (Request* r : sv->active)
+        if (r->gather)
+          gcls[{r->phase, r->sys->d, r->sys->n_modes, r->want_grad}].push_back(r);
+      for (auto& kv : gcls) {
+        hipStream_t st = sv->work[ci++ % scp_server::kWork];
+        const int kind = std::get<0>(kv.first), d = std::get<1>(kv.first),
+                  N = std::get<2>(kv.first);
+        const bool ck = std::get<3>(kv.first) != 0;
+        if (kind == 0) {
+          GItem* it = (GItem*)((char*)sv->h_items + off);
+          int nit = 0;
+          size_t lds = 0;
+          for (Request* r : kv.second) {
+            const int steps = std::max(8, (int)(sv->chunk_work / r->cost_step));
+            const int n0 = r->n_done, n1 = std::min(r->sys->n_steps, n0 + steps);
+            for (int c = 0; c < r->S; ++c)
+              it[nit++] = GItem{r->gi.A, ck ? r->gi.B : nullptr, n0 == 0 ? nullptr : r->gi.state,
+                                r->gi.state, c, n0, n1, 0};
+            lds = std::max(lds, r->gi.lds_fwd);
+            r->n_done = n1;
+            r->tick_stream = st;
+          }
+          void* dptr = nullptr;
+          if (!stage(it, (size_t)nit * sizeof(GItem), st, &dptr)) return fail(SCP_EHIP, "item upload");
+          s = gather_launch_fwd_batched(d, N, ck, (const GItem*)dptr, nit, lds, st);
           if (s != SCP_OK) return s;
+        } else {
+          // round j: launch seg_next - j of every request that still has one this tick
+          int rounds = 0;
+          std::vector<int> g_lo(kv.second.size());
+          for (size_t q = 0; q < kv.second.size(); ++q) {
+            Request* r = kv.second[q];
+            const int steps = std::max(8, (int)(sv->chunk_work / r->cost_step));
+            const int launches = std::max(1, steps / r->ce);
+            g_lo[q] = std::max(0, r->seg_next - launches + 1);
+            rounds = std::max(rounds, r->seg_next - g_lo[q] + 1);
+          }
+          for (int j = 0; j < rounds; ++j) {
+            GItem* it = (GItem*)((char*)sv->h_items + off);
+            int nit = 0;
+            size_t lds = 0;
+            for (size_t q = 0; q < kv.second.size(); ++q) {
+              Request* r = kv.second[q];
+              const int gs = r->seg_next - j;
+              if (gs < g_lo[q]) continue;
+              for (int b = 0; b < 2 * r->S; ++b)
+                it[nit++] = GItem{r->gi.A, r->gi.B, nullptr, nullptr, b, 0, 0, gs};
+              lds = std::max(lds, r->gi.lds_adj);
+            }
+            void* dptr = nullptr;
+            if (!stage(it, (size_t)nit * sizeof(GItem), st, &dptr))
+              return fail(SCP_EHIP, "item upload");
+            s = gather_launch_adj_batched(d, N, (const GItem*)dptr, nit, lds, st);
+            if (s != SCP_OK) return s;
+          }
+          for (size_t q = 0; q < kv.second.size(); ++q) {
+            kv.second[q]->seg_next = g_lo[q] - 1;
+            kv.second[q]->tick_stream = st;
+          }
         }
-        r->seg_next = g_lo - 1;
       }
-      r->tick_stream = st;
     }
     // 3. fidelity (and costate) for forward completions
     for (Request* r : sv->active)

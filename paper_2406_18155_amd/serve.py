@@ -7,6 +7,7 @@ throughput.  All scheduling, admission and batching happen in the library.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 import time
 
 import numpy as np
@@ -22,7 +23,7 @@ class Server:
     ENGINES = {"auto": 0, "register": 1, "gather": 2}
 
     def __init__(self, hbm_budget_bytes, max_active=64, chunk_work=0.0, stream=None,
-                 engine="auto"):
+                 engine="register"):
         h = C.c_void_p()
         check(lib().scp_server_create(int(hbm_budget_bytes), int(max_active), float(chunk_work),
                                       _stream_ptr(stream), C.byref(h)))
@@ -104,11 +105,13 @@ def drain(server, ids, timeout_s=600.0):
 
 
 def run_stream(requests, arrivals, hbm_budget_bytes, max_active=64, chunk_work=0.0,
-               timeout_s=900.0):
+               timeout_s=900.0, engine="register", progress_s=0.0):
     """Submit ``requests`` (descriptor dicts with a ``want_grad`` flag) at
     ``arrivals`` (seconds from start) and serve them; returns per-request
-    latency (completion - arrival, wall clock) and summary statistics."""
-    srv = Server(hbm_budget_bytes, max_active, chunk_work)
+    latency (completion - arrival, wall clock) and summary statistics.
+    progress_s > 0 prints a progress line to stderr at that interval."""
+    srv = Server(hbm_budget_bytes, max_active, chunk_work, engine=engine)
+    t_print = progress_s
     n = len(requests)
     ids = [None] * n
     sub_wall = [0.0] * n
@@ -133,6 +136,11 @@ def run_stream(requests, arrivals, hbm_budget_bytes, max_active=64, chunk_work=0
             if r["state"] in ("done", "failed"):
                 done_wall[i] = (tnow, r)
                 pending.discard(i)
+        if progress_s > 0 and tnow >= t_print:
+            sys.stderr.write(f"[serve] {tnow:.0f} s: {len(done_wall)} of {n} done, "
+                             f"{len(pending)} in flight\n")
+            sys.stderr.flush()
+            t_print = tnow + progress_s
         if tnow > timeout_s:
             raise TimeoutError("serving stream did not finish")
     lat = np.array([done_wall[i][0] - arrivals[i] for i in range(n)])

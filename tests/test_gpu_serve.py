@@ -80,14 +80,15 @@ def test_server_equals_direct_path_and_oracle(scp, engine):
     srv.close()
 
 
-def test_result_is_the_same_alone_and_in_a_mix(scp):
+@pytest.mark.parametrize("engine", ["register", "auto"])
+def test_result_is_the_same_alone_and_in_a_mix(scp, engine):
     target = short_request(3)
     mix = [short_request(r) for r in range(10, 22)]
-    srv = scp.serve.Server(64 << 30, max_active=4, chunk_work=2e5)
+    srv = scp.serve.Server(64 << 30, max_active=4, chunk_work=2e5, engine=engine)
     rid = srv.submit(target, True)
     alone = scp.serve.drain(srv, [rid])[rid]
     srv.close()
-    srv = scp.serve.Server(64 << 30, max_active=16, chunk_work=5e5)
+    srv = scp.serve.Server(64 << 30, max_active=16, chunk_work=5e5, engine=engine)
     ids = [srv.submit(q, q["want_grad"]) for q in mix[:6]]
     rid2 = srv.submit(target, True)
     ids += [srv.submit(q, q["want_grad"]) for q in mix[6:]]
