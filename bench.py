@@ -172,9 +172,10 @@ def serving_leg(scp, si, torch, np, n_req, poisson=True):
     sat = serve.run_stream(reqs, [0.0] * n_req, budget, max_active=64, progress_s=20.0)
     out = {"requests": n_req, "hbm_budget_bytes": budget, "max_active": 64, "engine": "register",
            "saturated": {k: sat[k] for k in keys}}
-    gat = serve.run_stream(reqs, [0.0] * n_req, budget, max_active=64, engine="auto",
-                           progress_s=20.0)
-    out["saturated_gather_routing"] = {k: gat[k] for k in keys}
+    if n_req <= 512:
+        gat = serve.run_stream(reqs, [0.0] * n_req, budget, max_active=64, engine="auto",
+                               progress_s=20.0)
+        out["saturated_gather_routing"] = {k: gat[k] for k in keys}
     if not poisson:
         return out
     for frac in (0.5, 0.9):
@@ -717,8 +718,8 @@ def main():
     ap.add_argument("--no-plain64", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=128)
     ap.add_argument("--serve-only", type=int, default=0,
-                    help="only replay the first N requests of the serving stream saturated (both "
-                         "engine settings) and exit")
+                    help="only replay the first N requests of the serving stream saturated (also "
+                         "with gather routing when N <= 512) and exit")
     ap.add_argument("--configs", action="store_true",
                     help="only time configs 1-3 (one JSON line each) and exit")
     ap.add_argument("--config-only", choices=("config1", "chain", "x6"), default=None,
