@@ -75,6 +75,8 @@ struct GArgs {
   int block_q, ngroups, nsteps, S;
   float h;
   int ndm, npr, ntab, has_jump, off_p, off_j;
+  int prow;   // stride of a pair-operator row (closed systems: d^2 rounded up to even)
+  int orow;   // stride of a driven-mode operator row (closed systems: d rounded up to even)
   int kst[GA_MAXM], bst[GA_MAXM];                    // strides of ket / bra digits in a column
   int dm_mode[GA_MAXDM], dm_n[GA_MAXDM];
   int dm_slot[GA_MAXDM][GA_MAXC], dm_cidx[GA_MAXDM][GA_MAXC];
@@ -196,7 +198,7 @@ __global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* 
             vr = fmaf(c, o.x, vr);
             vi = fmaf(c, o.y, vi);
           }
-      } else {                          // derivative slot operator
+      } else if (t < A.off_d + 3 * A.nsl * dd) {   // derivative slot operator
         const int u = t - A.off_d;
         const int k = u / (3 * dd), th = (u / dd) % 3, ab = u % dd;
         const c32 o = ops[A.off_dslot + (A.sl_slot[k] * 3 + th) * dd + ab];
@@ -204,8 +206,10 @@ __global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* 
         vi = o.y;
       }
     } else if (t < A.off_p) {
-      const int dm = t / dd, ab = t - dm * dd;
-      for (int k = 0; k < A.dm_n[dm]; ++k) {
+      const int dm = t / (d * A.orow), rr = t - dm * d * A.orow;
+      const int ra = rr / A.orow, rb = rr - ra * A.orow;   // rb >= d: row padding
+      const int ab = ra * d + rb;
+      for (int k = 0; k < (dm < A.ndm && rb < d ? A.dm_n[dm] : 0); ++k) {
         const float c = cq[A.dm_cidx[dm][k]];
         const c32 o = ops[A.dm_slot[dm][k] * dd + ab];
         vr = fmaf(c, o.x, vr);
@@ -213,17 +217,17 @@ __global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* 
       }
     } else if (t < A.off_j) {
       const int u = t - A.off_p;
-      const int p = u / (dd * dd), rr = u - p * dd * dd;
-      const int row = rr / dd, col = rr - row * dd;
+      const int p = u / (dd * A.prow), rr = u - p * dd * A.prow;
+      const int row = rr / A.prow, col = rr - row * A.prow;   // col >= dd: row padding
       const int ai = row / d, aj = row - ai * d, x = col / d, z = col - x * d;
-      for (int k = 0; k < A.pr_n[p]; ++k) {
+      for (int k = 0; k < (col < dd ? A.pr_n[p] : 0); ++k) {
         const c32 oi = ops[A.pr_si[p][k] * dd + ai * d + x];
         const c32 oj = ops[A.pr_sj[p][k] * dd + aj * d + z];
         const float g = A.pr_g[p][k];
         vr = fmaf(g, oi.x * oj.x - oi.y * oj.y, vr);
         vi = fmaf(g, oi.x * oj.y + oi.y * oj.x, vi);
       }
-    } else {
+    } else if (A.has_jump) {
       const int u = t - A.off_j;
       const int m = u / dd;
       const c32 j = ((const c32*)A.jtab)[((size_t)q * N) * dd + u];
@@ -231,6 +235,75 @@ __global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* 
       vi = A.g1[m] * j.y;
     }
     out[(size_t)r * ntot + t] = make_float2(vr, vi);
+  }
+}
+
+// Stride of a pair-operator row in the stage table: closed systems pad the d^2
+// entries to an even count so that a row starts 16-byte aligned and is read
+// two entries per LDS instruction.
+template <int d, bool OPEN>
+__host__ __device__ constexpr int pair_row() {
+  return OPEN ? d * d : d * d + ((d * d) & 1);
+}
+
+template <int d, bool OPEN>
+__host__ __device__ constexpr int one_row() {
+  return OPEN ? d : d + (d & 1);
+}
+
+// sum_x row[x] y0[x sm] over one driven-mode operator row (closed systems: the
+// row is 16-byte aligned and read two entries at a time)
+template <int d, bool OPEN>
+__device__ __forceinline__ void one_dot(const c32* __restrict__ row, const c32* __restrict__ y0,
+                                        int sm, float& sr, float& si) {
+  if constexpr (!OPEN) {
+    const float4* r4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+    for (int k = 0; k < (d + 1) / 2; ++k) {
+      const float4 q = r4[k];
+      c32 a;
+      a.x = q.x;
+      a.y = q.y;
+      cmac(sr, si, a, y0[(2 * k) * sm]);
+      if (2 * k + 1 < d) {
+        c32 b;
+        b.x = q.z;
+        b.y = q.w;
+        cmac(sr, si, b, y0[(2 * k + 1) * sm]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int x = 0; x < d; ++x) cmac(sr, si, row[x], y0[x * sm]);
+  }
+}
+
+// sum_{x,z} row[x d + z] y0[x si + z sj] over one pair-operator row
+template <int d, bool OPEN>
+__device__ __forceinline__ void pair_dot(const c32* __restrict__ row, const c32* __restrict__ y0,
+                                         int si_, int sj_, float& sr, float& si) {
+  constexpr int dd = d * d;
+  if constexpr (!OPEN) {
+    const float4* r4 = reinterpret_cast<const float4*>(row);
+#pragma unroll
+    for (int k = 0; k < (dd + 1) / 2; ++k) {
+      const float4 q = r4[k];
+      c32 a;
+      a.x = q.x;
+      a.y = q.y;
+      cmac(sr, si, a, y0[((2 * k) / d) * si_ + ((2 * k) % d) * sj_]);
+      if (2 * k + 1 < dd) {
+        c32 b;
+        b.x = q.z;
+        b.y = q.w;
+        cmac(sr, si, b, y0[((2 * k + 1) / d) * si_ + ((2 * k + 1) % d) * sj_]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int x = 0; x < d; ++x)
+#pragma unroll
+      for (int z = 0; z < d; ++z) cmac(sr, si, row[x * d + z], y0[x * si_ + z * sj_]);
   }
 }
 
@@ -264,11 +337,11 @@ __device__ __forceinline__ void g_apply(kptr<GArgs> A, const c32* __restrict__ y
     {
       const int sm = uni(A->kst[m]);
       const int am = ket_digit(pk, m);
-      const c32* row = tab + dm * dd + am * d;
+      constexpr int RD = one_row<d, OPEN>();
+      const c32* row = tab + dm * d * RD + am * RD;
       const c32* y0 = yb + e - am * sm;
       float sr = 0.f, si = 0.f;
-#pragma unroll
-      for (int x = 0; x < d; ++x) cmac(sr, si, row[x], y0[x * sm]);
+      one_dot<d, OPEN>(row, y0, sm, sr, si);
       kr += si;
       ki -= sr;
     }
@@ -289,24 +362,22 @@ __device__ __forceinline__ void g_apply(kptr<GArgs> A, const c32* __restrict__ y
   for (int pv = 0; pv < npr; ++pv) {
     const int p = uni(pv);
     const int i = uni(A->pr_i[p]), j = uni(A->pr_j[p]);
-    const c32* P = tab + A->off_p + p * dd * dd;
+    constexpr int PR = pair_row<d, OPEN>();
+    const c32* P = tab + A->off_p + p * dd * PR;
     {
       const int si_ = uni(A->kst[i]), sj_ = uni(A->kst[j]);
       const int ai = ket_digit(pk, i), aj = ket_digit(pk, j);
-      const c32* row = P + (ai * d + aj) * dd;
+      const c32* row = P + (ai * d + aj) * PR;
       const c32* y0 = yb + e - (ai * si_ + aj * sj_);
       float sr = 0.f, si = 0.f;
-#pragma unroll
-      for (int x = 0; x < d; ++x)
-#pragma unroll
-        for (int z = 0; z < d; ++z) cmac(sr, si, row[x * d + z], y0[x * si_ + z * sj_]);
+      pair_dot<d, OPEN>(row, y0, si_, sj_, sr, si);
       kr += si;
       ki -= sr;
     }
     if (OPEN) {
       const int si_ = uni(A->bst[i]), sj_ = uni(A->bst[j]);
       const int bi = bra_digit(pk, i, N), bj = bra_digit(pk, j, N);
-      const c32* row = P + (bi * d + bj) * dd;
+      const c32* row = P + (bi * d + bj) * PR;
       const c32* y0 = yb + e - (bi * si_ + bj * sj_);
       float sr = 0.f, si = 0.f;
 #pragma unroll
@@ -328,7 +399,7 @@ __device__ __forceinline__ void g_rk4_body(const GArgs* __restrict__ Ag, const G
   using Sh = GShape<d, N, OPEN>;
   constexpr int L = Sh::L, T = Sh::T, E = Sh::E;
   // LDS: two stage-input buffers, the static diagonal, two stage tables
-  extern __shared__ c32 lds[];
+  extern __shared__ __align__(16) c32 lds[];
   kptr<GArgs> A = kconst(Ag);
   const int ntab = A->ntab;
   const int nrow = A->grad ? A->ntabg : ntab;   // table row stride in gtab
@@ -341,6 +412,7 @@ __device__ __forceinline__ void g_rk4_body(const GArgs* __restrict__ Ag, const G
   // columns x0, lo = 0) and goes to st_out (a later call continues exactly)
   uint32_t pk[E];
   float hr[E], hm[E], lr[E], lm[E], ar[E], am_[E];
+  float dgr_[E], dgi_[E];   // the element's static diagonal (closed systems: in registers)
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int e = tid + r * T;
@@ -379,16 +451,26 @@ __device__ __forceinline__ void g_rk4_body(const GArgs* __restrict__ Ag, const G
     hr[r] = v.x;
     hm[r] = v.y;
     ar[r] = am_[r] = 0.f;
+    dgr_[r] = gr;
+    dgi_[r] = gi;
     if (ok) {
       lds[e] = v;
-      c32 g;
-      g.x = gr;
-      g.y = gi;
-      dgb[e] = g;
+      if (OPEN) {
+        c32 g;
+        g.x = gr;
+        g.y = gi;
+        dgb[e] = g;
+      }
     }
   }
-  for (int t = tid; t < ntab; t += T) lds[3 * L + t] = gtab[(size_t)stage_c(n_lo, 0) * nrow + t];
+  // the stage tables start 16-byte aligned (closed systems read pair rows
+  // two entries at a time)
+  constexpr int TB = 3 * L + (OPEN ? 0 : ((3 * L) & 1));
+  for (int t = tid; t < ntab; t += T) lds[TB + t] = gtab[(size_t)stage_c(n_lo, 0) * nrow + t];
   __syncthreads();
+  // closed systems move table rows two entries (16 bytes) at a time: the
+  // tables' rows and LDS buffers are 16-byte aligned and of even length
+  constexpr int GP4 = GA_PRE / 2;
   int cur = 0;
 #pragma unroll 1
   for (int n = n_lo; n < n_hi; ++n) {
@@ -409,17 +491,27 @@ __device__ __forceinline__ void g_rk4_body(const GArgs* __restrict__ Ag, const G
       const float w = (s == 0 || s == 3) ? 1.f : 2.f;
       const float ch = (s == 2) ? h : 0.5f * h;
       const c32* yc = lds + cur * L;
-      const c32* tc = lds + 3 * L + cur * ntab;
+      const c32* tc = lds + TB + cur * ntab;
       c32* yn = lds + (cur ^ 1) * L;
       // the next stage's table, loaded now and stored after this stage
       const int n2 = s < 3 ? n : n + 1, s2 = s < 3 ? s + 1 : 0;
       const bool more = n2 < n_hi;
       const c32* gnext = gtab + (size_t)stage_c(n2, s2) * nrow;
-      c32 pre[GA_PRE];
+      c32 pre[OPEN ? GA_PRE : 1];
+      float4 pre4[OPEN ? 1 : GP4];
+      if constexpr (OPEN) {
 #pragma unroll
-      for (int k = 0; k < GA_PRE; ++k) {
-        const int t = tid + k * T;
-        if (more && t < ntab) pre[k] = gnext[t];
+        for (int k = 0; k < GA_PRE; ++k) {
+          const int t = tid + k * T;
+          if (more && t < ntab) pre[k] = gnext[t];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < GP4; ++k) {
+          const int t = tid + k * T;
+          pre4[k] = (more && 2 * t < ntab) ? reinterpret_cast<const float4*>(gnext)[t]
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
       }
 #pragma unroll
       for (int r = 0; r < E; ++r) {
@@ -430,7 +522,14 @@ __device__ __forceinline__ void g_rk4_body(const GArgs* __restrict__ Ag, const G
         // would hold E sets of them in registers)
         asm volatile("" : "+v"(e), "+v"(p));
         if (e < L) {
-          const c32 g = dgb[e], ye = yc[e];
+          c32 g;
+          if (OPEN) {
+            g = dgb[e];
+          } else {
+            g.x = dgr_[r];
+            g.y = dgi_[r];
+          }
+          const c32 ye = yc[e];
           float kr, ki;
           g_apply<d, N, OPEN>(A, yc, tc, e, p, g.x, g.y, ye.x, ye.y, kr, ki);
           if (s == 0) {
@@ -458,13 +557,24 @@ __device__ __forceinline__ void g_rk4_body(const GArgs* __restrict__ Ag, const G
         __builtin_amdgcn_sched_barrier(0);
       }
       if (more) {
-        c32* tn = lds + 3 * L + (cur ^ 1) * ntab;
+        c32* tn = lds + TB + (cur ^ 1) * ntab;
+        if constexpr (OPEN) {
 #pragma unroll
-        for (int k = 0; k < GA_PRE; ++k) {
-          const int t = tid + k * T;
-          if (t < ntab) tn[t] = pre[k];
+          for (int k = 0; k < GA_PRE; ++k) {
+            const int t = tid + k * T;
+            if (t < ntab) tn[t] = pre[k];
+          }
+          for (int t = tid + GA_PRE * T; t < ntab; t += T) tn[t] = gnext[t];
+        } else {
+          float4* tn4 = reinterpret_cast<float4*>(tn);
+          const float4* gn4 = reinterpret_cast<const float4*>(gnext);
+#pragma unroll
+          for (int k = 0; k < GP4; ++k) {
+            const int t = tid + k * T;
+            if (2 * t < ntab) tn4[t] = pre4[k];
+          }
+          for (int t = tid + GP4 * T; 2 * t < ntab; t += T) tn4[t] = gn4[t];
         }
-        for (int t = tid + GA_PRE * T; t < ntab; t += T) tn[t] = gnext[t];
       }
       __syncthreads();
       cur ^= 1;
@@ -545,11 +655,11 @@ __device__ __forceinline__ void g_apply_adj(kptr<GArgs> A, const c32* __restrict
     {
       const int sm = uni(A->kst[m]);
       const int am = ket_digit(pk, m);
-      const c32* row = tab + dm * dd + am * d;
+      constexpr int RD = one_row<d, OPEN>();
+      const c32* row = tab + dm * d * RD + am * RD;
       const c32* x0 = xb + e - am * sm;
       float sr = 0.f, si = 0.f;
-#pragma unroll
-      for (int x = 0; x < d; ++x) cmac(sr, si, row[x], x0[x * sm]);
+      one_dot<d, OPEN>(row, x0, sm, sr, si);
       yr -= si;
       yi += sr;
     }
@@ -569,24 +679,22 @@ __device__ __forceinline__ void g_apply_adj(kptr<GArgs> A, const c32* __restrict
   for (int pv = 0; pv < npr; ++pv) {
     const int p = uni(pv);
     const int i = uni(A->pr_i[p]), j = uni(A->pr_j[p]);
-    const c32* P = tab + A->off_p + p * dd * dd;
+    constexpr int PR = pair_row<d, OPEN>();
+    const c32* P = tab + A->off_p + p * dd * PR;
     {
       const int si_ = uni(A->kst[i]), sj_ = uni(A->kst[j]);
       const int ai = ket_digit(pk, i), aj = ket_digit(pk, j);
-      const c32* row = P + (ai * d + aj) * dd;
+      const c32* row = P + (ai * d + aj) * PR;
       const c32* x0 = xb + e - (ai * si_ + aj * sj_);
       float sr = 0.f, si = 0.f;
-#pragma unroll
-      for (int x = 0; x < d; ++x)
-#pragma unroll
-        for (int z = 0; z < d; ++z) cmac(sr, si, row[x * d + z], x0[x * si_ + z * sj_]);
+      pair_dot<d, OPEN>(row, x0, si_, sj_, sr, si);
       yr -= si;
       yi += sr;
     }
     if (OPEN) {
       const int si_ = uni(A->bst[i]), sj_ = uni(A->bst[j]);
       const int bi = bra_digit(pk, i, N), bj = bra_digit(pk, j, N);
-      const c32* row = P + (bi * d + bj) * dd;
+      const c32* row = P + (bi * d + bj) * PR;
       const c32* x0 = xb + e - (bi * si_ + bj * sj_);
       float sr = 0.f, si = 0.f;
 #pragma unroll
@@ -713,7 +821,7 @@ __device__ __forceinline__ void g_adj_body(const GArgs* __restrict__ Ag, const G
   constexpr int L = Sh::L, T = Sh::T, E = Sh::E, D = Sh::D, dd = d * d;
   constexpr int NW = T / 64;
   constexpr int WS = OPEN ? GA_MAXDS : GA_NV;   // per-wave sums of one stage
-  extern __shared__ c32 lds[];
+  extern __shared__ __align__(16) c32 lds[];
   kptr<GArgs> A = kconst(Ag);
   kptr<GAdj> B = kconst(Bg);
   const int ntab = A->ntab, ntabg = A->ntabg;
@@ -1319,7 +1427,8 @@ __global__ void store_args_kernel(GArgs a, GArgs* out) {
 
 template <int d, int N, bool OPEN>
 size_t g_lds_bytes(int ntab) {
-  return sizeof(c32) * (3 * (size_t)GShape<d, N, OPEN>::L + 2 * (size_t)ntab);
+  constexpr size_t L = GShape<d, N, OPEN>::L;
+  return sizeof(c32) * (3 * L + (OPEN ? 0 : ((3 * L) & 1)) + 2 * (size_t)ntab);
 }
 
 // Steps [n_lo, n_hi) with the state from st_in / to st_out (nullable; see the
@@ -1504,12 +1613,17 @@ static scp_status g_args(const scp_system* sys, bool open, const double* gamma1,
     A.pr_sj[p][A.pr_n[p]] = ssj;
     A.pr_g[p][A.pr_n[p]++] = (float)sys->coup[e].g;
   }
-  A.off_p = A.ndm * dd;
-  A.off_j = A.off_p + A.npr * dd * dd;
-  A.ntab = A.off_j + (A.has_jump ? N * dd : 0);
+  // closed systems: pair rows padded to an even length, the pair block and
+  // the table starting at even entries (16-byte aligned rows)
+  auto even = [&](int x) { return open ? x : x + (x & 1); };
+  A.prow = even(dd);
+  A.orow = even(d);
+  A.off_p = even(A.ndm * d * A.orow);
+  A.off_j = A.off_p + A.npr * dd * A.prow;
+  A.ntab = even(A.off_j + (A.has_jump ? N * dd : 0));
   if (A.ntab > GA_MAXTAB) return fail(SCP_EINVAL, "gather engine: stage table too large");
   const size_t L = open ? (size_t)D * D : (size_t)D;
-  if ((3 * L + 2 * (size_t)A.ntab) * sizeof(float2) > 163840)
+  if ((3 * L + (open ? 0 : ((3 * L) & 1)) + 2 * (size_t)A.ntab) * sizeof(float2) > 163840)
     return fail(SCP_EINVAL, "gather engine: column and stage tables exceed the LDS");
   A.ntabg = A.ntab;
   return SCP_OK;
@@ -1600,6 +1714,7 @@ static scp_status g_args_grad(const scp_system* sys, bool open, GArgs& A) {
     A.off_d = A.off_m + 3 * N * dd;
     A.off_u = A.off_m;
     A.ntabg = A.off_d + 3 * A.nsl * dd;
+    A.ntabg += A.ntabg & 1;   // the second table buffer starts 16-byte aligned
   }
   if (A.ntabg > GA_MAXTAB) return fail(SCP_EINVAL, "gather-engine gradient: stage table too large");
   return SCP_OK;
@@ -2044,7 +2159,7 @@ scp_status gather_serve_info(const scp_system* sys, int S, int ce, bool grad, vo
   out.A = base + w.args;
   out.B = base + w.adj;
   out.state = reinterpret_cast<float4*>(base + w.total);
-  out.lds_fwd = sizeof(c32) * (3 * (size_t)sys->D + 2 * (size_t)A.ntab);
+  out.lds_fwd = sizeof(c32) * (3 * (size_t)sys->D + ((3 * (size_t)sys->D) & 1) + 2 * (size_t)A.ntab);
   out.lds_adj = g_adj_lds(sys->d, sys->n_modes, false, A.ntabg, w.nacc);
   out.nck = w.nck;
   return SCP_OK;
