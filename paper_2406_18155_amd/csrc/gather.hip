@@ -75,8 +75,8 @@ struct GArgs {
   int block_q, ngroups, nsteps, S;
   float h;
   int ndm, npr, ntab, has_jump, off_p, off_j;
-  int prow;   // stride of a pair-operator row (closed systems: d^2 rounded up to even)
-  int orow;   // stride of a driven-mode operator row (closed systems: d rounded up to even)
+  int prow;   // stride of a pair-operator row: d^2 rounded up to even
+  int orow;   // stride of a driven-mode operator row: d rounded up to even
   int kst[GA_MAXM], bst[GA_MAXM];                    // strides of ket / bra digits in a column
   int dm_mode[GA_MAXDM], dm_n[GA_MAXDM];
   int dm_slot[GA_MAXDM][GA_MAXC], dm_cidx[GA_MAXDM][GA_MAXC];
@@ -181,10 +181,12 @@ __global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* 
         const c32 o = ops[A.sl_slot[k] * dd + ab];
         vr = o.x;
         vi = o.y;
-      } else if (A.grad == 1) {         // unit-rate relaxation band
-        const c32 j = ((const c32*)A.jtab)[((size_t)q * N) * dd + (t - A.off_u)];
-        vr = j.x;
-        vi = j.y;
+      } else if (A.grad == 1) {         // unit-rate relaxation band (then row padding)
+        if (t - A.off_u < N * dd) {
+          const c32 j = ((const c32*)A.jtab)[((size_t)q * N) * dd + (t - A.off_u)];
+          vr = j.x;
+          vi = j.y;
+        }
       } else if (t < A.off_d) {         // d/dtheta of mode m's one-mode terms
         const int u = t - A.off_m;
         const int m = u / (3 * dd), th = (u / dd) % 3, ab = u % dd;
@@ -227,7 +229,7 @@ __global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* 
         vr = fmaf(g, oi.x * oj.x - oi.y * oj.y, vr);
         vi = fmaf(g, oi.x * oj.y + oi.y * oj.x, vi);
       }
-    } else if (A.has_jump) {
+    } else if (A.has_jump && t - A.off_j < N * dd) {   // relaxation bands (then row padding)
       const int u = t - A.off_j;
       const int m = u / dd;
       const c32 j = ((const c32*)A.jtab)[((size_t)q * N) * dd + u];
@@ -238,72 +240,75 @@ __global__ void gtab_kernel(const GArgs* __restrict__ Ag, int d, int N, float2* 
   }
 }
 
-// Stride of a pair-operator row in the stage table: closed systems pad the d^2
-// entries to an even count so that a row starts 16-byte aligned and is read
-// two entries per LDS instruction.
+// Stride of a pair-operator row in the stage table: the d^2 entries padded to
+// an even count so that a row starts 16-byte aligned and is read two entries
+// per LDS instruction.
 template <int d, bool OPEN>
 __host__ __device__ constexpr int pair_row() {
-  return OPEN ? d * d : d * d + ((d * d) & 1);
+  return d * d + ((d * d) & 1);
 }
 
 template <int d, bool OPEN>
 __host__ __device__ constexpr int one_row() {
-  return OPEN ? d : d + (d & 1);
+  return d + (d & 1);
 }
 
-// sum_x row[x] y0[x sm] over one driven-mode operator row (closed systems: the
-// row is 16-byte aligned and read two entries at a time)
-template <int d, bool OPEN>
+// sum_x row[x] y0[x sm] (CONJ: conj(row[x])) over one driven-mode operator
+// row; the row is 16-byte aligned and read two entries at a time
+template <int d, bool CONJ>
 __device__ __forceinline__ void one_dot(const c32* __restrict__ row, const c32* __restrict__ y0,
                                         int sm, float& sr, float& si) {
-  if constexpr (!OPEN) {
-    const float4* r4 = reinterpret_cast<const float4*>(row);
+  const float4* r4 = reinterpret_cast<const float4*>(row);
 #pragma unroll
-    for (int k = 0; k < (d + 1) / 2; ++k) {
-      const float4 q = r4[k];
-      c32 a;
-      a.x = q.x;
-      a.y = q.y;
+  for (int k = 0; k < (d + 1) / 2; ++k) {
+    const float4 q = r4[k];
+    c32 a;
+    a.x = q.x;
+    a.y = q.y;
+    if (CONJ)
+      cmac_conj(sr, si, a, y0[(2 * k) * sm]);
+    else
       cmac(sr, si, a, y0[(2 * k) * sm]);
-      if (2 * k + 1 < d) {
-        c32 b;
-        b.x = q.z;
-        b.y = q.w;
+    if (2 * k + 1 < d) {
+      c32 b;
+      b.x = q.z;
+      b.y = q.w;
+      if (CONJ)
+        cmac_conj(sr, si, b, y0[(2 * k + 1) * sm]);
+      else
         cmac(sr, si, b, y0[(2 * k + 1) * sm]);
-      }
     }
-  } else {
-#pragma unroll
-    for (int x = 0; x < d; ++x) cmac(sr, si, row[x], y0[x * sm]);
   }
 }
 
-// sum_{x,z} row[x d + z] y0[x si + z sj] over one pair-operator row
-template <int d, bool OPEN>
+// sum_{x,z} row[x d + z] y0[x si + z sj] (CONJ: conj(row[...])) over one
+// pair-operator row, read two entries at a time
+template <int d, bool CONJ>
 __device__ __forceinline__ void pair_dot(const c32* __restrict__ row, const c32* __restrict__ y0,
                                          int si_, int sj_, float& sr, float& si) {
   constexpr int dd = d * d;
-  if constexpr (!OPEN) {
-    const float4* r4 = reinterpret_cast<const float4*>(row);
+  const float4* r4 = reinterpret_cast<const float4*>(row);
 #pragma unroll
-    for (int k = 0; k < (dd + 1) / 2; ++k) {
-      const float4 q = r4[k];
-      c32 a;
-      a.x = q.x;
-      a.y = q.y;
-      cmac(sr, si, a, y0[((2 * k) / d) * si_ + ((2 * k) % d) * sj_]);
-      if (2 * k + 1 < dd) {
-        c32 b;
-        b.x = q.z;
-        b.y = q.w;
-        cmac(sr, si, b, y0[((2 * k + 1) / d) * si_ + ((2 * k + 1) % d) * sj_]);
-      }
+  for (int k = 0; k < (dd + 1) / 2; ++k) {
+    const float4 q = r4[k];
+    c32 a;
+    a.x = q.x;
+    a.y = q.y;
+    const c32 ya = y0[((2 * k) / d) * si_ + ((2 * k) % d) * sj_];
+    if (CONJ)
+      cmac_conj(sr, si, a, ya);
+    else
+      cmac(sr, si, a, ya);
+    if (2 * k + 1 < dd) {
+      c32 b;
+      b.x = q.z;
+      b.y = q.w;
+      const c32 yb_ = y0[((2 * k + 1) / d) * si_ + ((2 * k + 1) % d) * sj_];
+      if (CONJ)
+        cmac_conj(sr, si, b, yb_);
+      else
+        cmac(sr, si, b, yb_);
     }
-  } else {
-#pragma unroll
-    for (int x = 0; x < d; ++x)
-#pragma unroll
-      for (int z = 0; z < d; ++z) cmac(sr, si, row[x * d + z], y0[x * si_ + z * sj_]);
   }
 }
 
@@ -341,18 +346,18 @@ __device__ __forceinline__ void g_apply(kptr<GArgs> A, const c32* __restrict__ y
       const c32* row = tab + dm * d * RD + am * RD;
       const c32* y0 = yb + e - am * sm;
       float sr = 0.f, si = 0.f;
-      one_dot<d, OPEN>(row, y0, sm, sr, si);
+      one_dot<d, false>(row, y0, sm, sr, si);
       kr += si;
       ki -= sr;
     }
     if (OPEN) {
       const int sm = uni(A->bst[m]);
       const int bm = bra_digit(pk, m, N);
-      const c32* row = tab + dm * dd + bm * d;
+      constexpr int RD = one_row<d, OPEN>();
+      const c32* row = tab + dm * d * RD + bm * RD;
       const c32* y0 = yb + e - bm * sm;
       float sr = 0.f, si = 0.f;
-#pragma unroll
-      for (int x = 0; x < d; ++x) cmac_conj(sr, si, row[x], y0[x * sm]);
+      one_dot<d, true>(row, y0, sm, sr, si);
       kr -= si;
       ki += sr;
     }
@@ -370,7 +375,7 @@ __device__ __forceinline__ void g_apply(kptr<GArgs> A, const c32* __restrict__ y
       const c32* row = P + (ai * d + aj) * PR;
       const c32* y0 = yb + e - (ai * si_ + aj * sj_);
       float sr = 0.f, si = 0.f;
-      pair_dot<d, OPEN>(row, y0, si_, sj_, sr, si);
+      pair_dot<d, false>(row, y0, si_, sj_, sr, si);
       kr += si;
       ki -= sr;
     }
@@ -380,10 +385,7 @@ __device__ __forceinline__ void g_apply(kptr<GArgs> A, const c32* __restrict__ y
       const c32* row = P + (bi * d + bj) * PR;
       const c32* y0 = yb + e - (bi * si_ + bj * sj_);
       float sr = 0.f, si = 0.f;
-#pragma unroll
-      for (int x = 0; x < d; ++x)
-#pragma unroll
-        for (int z = 0; z < d; ++z) cmac_conj(sr, si, row[x * d + z], y0[x * si_ + z * sj_]);
+      pair_dot<d, true>(row, y0, si_, sj_, sr, si);
       kr -= si;
       ki += sr;
     }
@@ -463,9 +465,9 @@ __device__ __forceinline__ void g_rk4_body(const GArgs* __restrict__ Ag, const G
       }
     }
   }
-  // the stage tables start 16-byte aligned (closed systems read pair rows
-  // two entries at a time)
-  constexpr int TB = 3 * L + (OPEN ? 0 : ((3 * L) & 1));
+  // the stage tables start 16-byte aligned (operator rows are read two
+  // entries at a time)
+  constexpr int TB = 3 * L + ((3 * L) & 1);
   for (int t = tid; t < ntab; t += T) lds[TB + t] = gtab[(size_t)stage_c(n_lo, 0) * nrow + t];
   __syncthreads();
   // closed systems move table rows two entries (16 bytes) at a time: the
@@ -659,18 +661,18 @@ __device__ __forceinline__ void g_apply_adj(kptr<GArgs> A, const c32* __restrict
       const c32* row = tab + dm * d * RD + am * RD;
       const c32* x0 = xb + e - am * sm;
       float sr = 0.f, si = 0.f;
-      one_dot<d, OPEN>(row, x0, sm, sr, si);
+      one_dot<d, false>(row, x0, sm, sr, si);
       yr -= si;
       yi += sr;
     }
     if (OPEN) {
       const int sm = uni(A->bst[m]);
       const int bm = bra_digit(pk, m, N);
-      const c32* row = tab + dm * dd + bm * d;
+      constexpr int RD = one_row<d, OPEN>();
+      const c32* row = tab + dm * d * RD + bm * RD;
       const c32* x0 = xb + e - bm * sm;
       float sr = 0.f, si = 0.f;
-#pragma unroll
-      for (int x = 0; x < d; ++x) cmac_conj(sr, si, row[x], x0[x * sm]);
+      one_dot<d, true>(row, x0, sm, sr, si);
       yr += si;
       yi -= sr;
     }
@@ -687,7 +689,7 @@ __device__ __forceinline__ void g_apply_adj(kptr<GArgs> A, const c32* __restrict
       const c32* row = P + (ai * d + aj) * PR;
       const c32* x0 = xb + e - (ai * si_ + aj * sj_);
       float sr = 0.f, si = 0.f;
-      pair_dot<d, OPEN>(row, x0, si_, sj_, sr, si);
+      pair_dot<d, false>(row, x0, si_, sj_, sr, si);
       yr -= si;
       yi += sr;
     }
@@ -697,10 +699,7 @@ __device__ __forceinline__ void g_apply_adj(kptr<GArgs> A, const c32* __restrict
       const c32* row = P + (bi * d + bj) * PR;
       const c32* x0 = xb + e - (bi * si_ + bj * sj_);
       float sr = 0.f, si = 0.f;
-#pragma unroll
-      for (int x = 0; x < d; ++x)
-#pragma unroll
-        for (int z = 0; z < d; ++z) cmac_conj(sr, si, row[x * d + z], x0[x * si_ + z * sj_]);
+      pair_dot<d, true>(row, x0, si_, sj_, sr, si);
       yr += si;
       yi -= sr;
     }
@@ -1428,7 +1427,7 @@ __global__ void store_args_kernel(GArgs a, GArgs* out) {
 template <int d, int N, bool OPEN>
 size_t g_lds_bytes(int ntab) {
   constexpr size_t L = GShape<d, N, OPEN>::L;
-  return sizeof(c32) * (3 * L + (OPEN ? 0 : ((3 * L) & 1)) + 2 * (size_t)ntab);
+  return sizeof(c32) * (3 * L + ((3 * L) & 1) + 2 * (size_t)ntab);
 }
 
 // Steps [n_lo, n_hi) with the state from st_in / to st_out (nullable; see the
@@ -1613,9 +1612,9 @@ static scp_status g_args(const scp_system* sys, bool open, const double* gamma1,
     A.pr_sj[p][A.pr_n[p]] = ssj;
     A.pr_g[p][A.pr_n[p]++] = (float)sys->coup[e].g;
   }
-  // closed systems: pair rows padded to an even length, the pair block and
+  // operator rows padded to an even length, the pair block and
   // the table starting at even entries (16-byte aligned rows)
-  auto even = [&](int x) { return open ? x : x + (x & 1); };
+  auto even = [](int x) { return x + (x & 1); };
   A.prow = even(dd);
   A.orow = even(d);
   A.off_p = even(A.ndm * d * A.orow);
@@ -1623,7 +1622,7 @@ static scp_status g_args(const scp_system* sys, bool open, const double* gamma1,
   A.ntab = even(A.off_j + (A.has_jump ? N * dd : 0));
   if (A.ntab > GA_MAXTAB) return fail(SCP_EINVAL, "gather engine: stage table too large");
   const size_t L = open ? (size_t)D * D : (size_t)D;
-  if ((3 * L + (open ? 0 : ((3 * L) & 1)) + 2 * (size_t)A.ntab) * sizeof(float2) > 163840)
+  if ((3 * L + ((3 * L) & 1) + 2 * (size_t)A.ntab) * sizeof(float2) > 163840)
     return fail(SCP_EINVAL, "gather engine: column and stage tables exceed the LDS");
   A.ntabg = A.ntab;
   return SCP_OK;
@@ -1681,6 +1680,7 @@ static scp_status g_args_grad(const scp_system* sys, bool open, GArgs& A) {
     A.grad = 1;
     A.off_u = A.off_s + A.nsl * dd;
     A.ntabg = A.off_u + N * dd;
+    A.ntabg += A.ntabg & 1;   // the second table buffer starts 16-byte aligned
   } else {
     A.grad = 2;
     A.off_dslot = P.off_dslot;
