@@ -292,10 +292,13 @@ scp_status scp_fidelity_states(const void* U, int64_t D, int32_t S, int32_t prec
  * host the phases a (after the gate) and c (before it) that maximise |tau|,
  *   tau = sum_ij conj(T_ij) e^{i theta_i} M_ij e^{i chi_j},
  *   theta_i = sum_q a_q bit_q(i),  chi_j = sum_q c_q bit_q(j),
- * are found by coordinate ascent from zero: in turn a_0..a_{n-1}, then
- * c_0..c_{n-1}, each phase is set to arg A - arg B where tau = A + e^{i p} B
- * (B: the terms whose bit of that qubit is set), until |tau| grows by at most
- * 1e-14 relative or after 200 sweeps.  F_out (host, required) =
+ * are found by coordinate ascent -- in turn a_0..a_{n-1}, then c_0..c_{n-1},
+ * each phase is set to arg A - arg B where tau = A + e^{i p} B (B: the terms
+ * whose bit of that qubit is set), until |tau| grows by at most 1e-14
+ * relative or after 200 sweeps -- from each of a fixed set of starts, keeping
+ * the largest |tau|: zero for one qubit; for more, 16 starts, start k with
+ * a_q = 2 pi frac(k (q + 1) g), c_q = 2 pi frac(k (n + q + 1) g),
+ * g = 0.6180339887498949.  F_out (host, required) =
  * |tau|^2 / d_c^2; phases_out (host, 2 n_qubits, nullable): a then c;
  * tau_out (device complex128, nullable).  cotangent (nullable, as for
  * scp_fidelity) receives the costate of L = 1 - F at the optimum,

@@ -57,25 +57,37 @@ def zcomp_overlap(M, target, a, c):
     return complex(np.sum(np.exp(1j * th)[:, None] * W * np.exp(1j * ch)[None, :]))
 
 
-def zcomp_fidelity(M, target, n_q, max_sweeps=200, tol=1e-14):
-    """Fidelity with error-free single-qubit phase gates before and after the
-    gate (the compensation of App. D, restricted to Z rotations: virtual Z),
-    F = max_{a,c} |tau(a, c)|^2 / d_c^2 for the d_c x d_c computational block
-    M.  The maximum is sought by coordinate ascent from zero phases: in turn
-    a_0..a_{n-1}, then c_0..c_{n-1}, each phase is set to its optimum with the
-    others fixed.  Writing tau = A + e^{i p} B, where B collects the terms whose
-    bit of that qubit is set, |tau| is largest at p = arg A - arg B (a phase
-    whose A or B vanishes is left as it is).  Sweeps repeat until |tau| grows by
-    at most tol (relative) or max_sweeps is reached.  Returns (F, a, c, tau)."""
-    M = np.asarray(M, dtype=np.complex128)
-    target = np.asarray(target, dtype=np.complex128)
-    dc = 2 ** n_q
-    assert M.shape == (dc, dc) and target.shape == (dc, dc)
-    bits = comp_bits(n_q)
-    W = np.conj(target) * M
-    a = np.zeros(n_q)
-    c = np.zeros(n_q)
-    best = abs(zcomp_overlap(M, target, a, c))
+ZC_GOLDEN = 0.6180339887498949   # fractional part of the golden ratio
+
+
+def zcomp_starts(n_q):
+    """Starting phases of the multi-start search: 1 start (zero) for one
+    qubit, 16 otherwise; start k has a_q = 2 pi frac(k (q + 1) g) and
+    c_q = 2 pi frac(k (n_q + q + 1) g), g = ZC_GOLDEN (start 0 is zero)."""
+    K = 1 if n_q == 1 else 16
+    out = []
+    for k in range(K):
+        a = np.array([2 * np.pi * ((k * (q + 1) * ZC_GOLDEN) % 1.0) for q in range(n_q)])
+        c = np.array([2 * np.pi * ((k * (n_q + q + 1) * ZC_GOLDEN) % 1.0) for q in range(n_q)])
+        out.append((a, c))
+    return out
+
+
+def _zcomp_ascend(W, bits, a, c, max_sweeps, tol):
+    """Coordinate ascent from (a, c): in turn a_0..a_{n-1}, then
+    c_0..c_{n-1}, each phase set to its optimum with the others fixed.  With
+    tau = A + e^{i p} B, B the terms whose bit of that qubit is set, |tau| is
+    largest at p = arg A - arg B (a phase whose A or B vanishes is left as it
+    is).  Sweeps repeat until |tau| grows by at most tol (relative) or
+    max_sweeps is reached."""
+    n_q = bits.shape[1]
+    a = np.array(a, dtype=np.float64)
+    c = np.array(c, dtype=np.float64)
+
+    def tau_of(a, c):
+        return (np.exp(1j * (bits @ a))[:, None] * W * np.exp(1j * (bits @ c))[None, :]).sum()
+
+    best = abs(tau_of(a, c))
     for _ in range(max_sweeps):
         for side in (0, 1):
             for q in range(n_q):
@@ -97,11 +109,34 @@ def zcomp_fidelity(M, target, n_q, max_sweeps=200, tol=1e-14):
                         a[q] = p
                     else:
                         c[q] = p
-        t = abs(zcomp_overlap(M, target, a, c))
+        t = abs(tau_of(a, c))
         done = t - best <= tol * max(1.0, t)
         best = max(best, t)
         if done:
             break
+    return a, c
+
+
+def zcomp_fidelity(M, target, n_q, max_sweeps=200, tol=1e-14):
+    """Fidelity with error-free single-qubit phase gates before and after the
+    gate (the compensation of App. D, restricted to Z rotations: virtual Z),
+    F = max_{a,c} |tau(a, c)|^2 / d_c^2 for the d_c x d_c computational block
+    M.  The maximum is sought by coordinate ascent (_zcomp_ascend) from each
+    start of zcomp_starts; the start reaching the largest |tau| wins (the
+    earliest on a tie).  Returns (F, a, c, tau)."""
+    M = np.asarray(M, dtype=np.complex128)
+    target = np.asarray(target, dtype=np.complex128)
+    dc = 2 ** n_q
+    assert M.shape == (dc, dc) and target.shape == (dc, dc)
+    bits = comp_bits(n_q)
+    W = np.conj(target) * M
+    best = None
+    for a0, c0 in zcomp_starts(n_q):
+        a, c = _zcomp_ascend(W, bits, a0, c0, max_sweeps, tol)
+        t = abs(zcomp_overlap(M, target, a, c))
+        if best is None or t > best[0]:
+            best = (t, a, c)
+    _, a, c = best
     tau = zcomp_overlap(M, target, a, c)
     return abs(tau) ** 2 / dc ** 2, a, c, tau
 

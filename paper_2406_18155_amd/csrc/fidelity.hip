@@ -282,16 +282,16 @@ cd zcomp_tau(const std::vector<cd>& W, int nq, const std::vector<double>& a,
 
 }  // namespace
 
-// Phase compensation on the host (FP64): coordinate ascent from zero phases
-// over a_0..a_{n-1} (after the gate), then c_0..c_{n-1} (before it); each phase
-// goes to arg A - arg B, where tau = A + e^{i p} B with B the terms whose bit of
-// that qubit is set and the other phases fixed (left unchanged if A or B is
-// zero); sweeps end when |tau| grows by at most 1e-14 relative, or after 200.
-void zcomp_optimise(const std::vector<cd>& W, int nq, std::vector<double>& a,
-                    std::vector<double>& c, cd& tau) {
+namespace {
+
+// Coordinate ascent from the phases in a, c (in place): over a_0..a_{n-1}
+// (after the gate), then c_0..c_{n-1} (before it); each phase goes to
+// arg A - arg B, where tau = A + e^{i p} B with B the terms whose bit of that
+// qubit is set and the other phases fixed (left unchanged if A or B is zero);
+// sweeps end when |tau| grows by at most 1e-14 relative, or after 200.
+void zcomp_ascend(const std::vector<cd>& W, int nq, std::vector<double>& a,
+                  std::vector<double>& c) {
   const int dc = 1 << nq;
-  a.assign(nq, 0.0);
-  c.assign(nq, 0.0);
   double best = std::abs(zcomp_tau(W, nq, a, c));
   auto bit = [&](int i, int q) { return (i >> (nq - 1 - q)) & 1; };
   for (int sweep = 0; sweep < 200; ++sweep) {
@@ -319,6 +319,35 @@ void zcomp_optimise(const std::vector<cd>& W, int nq, std::vector<double>& a,
     const bool done = t - best <= 1e-14 * std::max(1.0, t);
     best = std::max(best, t);
     if (done) break;
+  }
+}
+
+}  // namespace
+
+// Phase compensation on the host (FP64): the coordinate ascent (zcomp_ascend)
+// from each of a fixed set of starts, keeping the largest |tau| (the earliest
+// start on a tie).  One start (zero) for one qubit, 16 otherwise; start k has
+// a_q = 2 pi frac(k (q + 1) g) and c_q = 2 pi frac(k (nq + q + 1) g), g the
+// fractional part of the golden ratio: one ascent from zero stalls below the
+// maximum on many three-qubit blocks far from their target.
+void zcomp_optimise(const std::vector<cd>& W, int nq, std::vector<double>& a,
+                    std::vector<double>& c, cd& tau) {
+  const double g = 0.6180339887498949, twopi = 2.0 * 3.141592653589793;
+  const int K = nq == 1 ? 1 : 16;
+  double best = -1.0;
+  std::vector<double> ak(nq), ck(nq);
+  for (int k = 0; k < K; ++k) {
+    for (int q = 0; q < nq; ++q) {
+      ak[q] = twopi * std::fmod((double)(k * (q + 1)) * g, 1.0);
+      ck[q] = twopi * std::fmod((double)(k * (nq + q + 1)) * g, 1.0);
+    }
+    zcomp_ascend(W, nq, ak, ck);
+    const double t = std::abs(zcomp_tau(W, nq, ak, ck));
+    if (t > best) {
+      best = t;
+      a = ak;
+      c = ck;
+    }
   }
   tau = zcomp_tau(W, nq, a, c);
 }
