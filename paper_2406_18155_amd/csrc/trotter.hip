@@ -949,11 +949,14 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
 // in FP64 in a fixed order.  For Q4j the gates are not unitary: the state is
 // recovered with exp(-X), the costate uses G^dag.  Everything is FP64.
 //
-// The walk: one workgroup per column keeps psi and mu in LDS (32 D bytes plus
-// a reduction scratch); the single-mode sums of a chunk of steps go to a
-// per-column buffer that a second kernel reduces over the columns in a fixed
-// order; the pair sums accumulate per column.  No atomics: the result is
-// bitwise reproducible.
+// The walk: one workgroup per column keeps psi and mu in LDS (in place, 32 D
+// bytes plus a reduction scratch, or split into two buffers each when 64 D
+// bytes and the gate tables fit, see the split walk); the single-mode reduced
+// matrices of a chunk of steps go to a per-column buffer (the visits of a
+// step summed in place, or one slot per visit in the split walk) that a
+// second kernel reduces over the visits and columns in a fixed order; the
+// pair sums accumulate per column.  No atomics: the result is bitwise
+// reproducible.
 // ---------------------------------------------------------------------------
 namespace {
 
@@ -1149,6 +1152,353 @@ lc_walk_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __restrict
   }
 }
 
+// Split walk, for columns small enough that LDS holds two buffers each of psi
+// and mu, two slots each of inverse and adjoint gate tables, two slots of
+// partial sums and three of fibre offsets (see lc_split_lds).  The in-place
+// walk above keeps only D / d^2 threads busy on a pair gate and needs three
+// barriers per gate; here a work item computes d output rows of one fibre
+// from one buffer into the other, and the interval between two barriers holds
+//   A. psi' = G_g^-1 psi and mu' = G_{g-1}^dag mu (g: position in the walk),
+//   B. the reduced matrix of gate g-1 from psi and mu (the state before that
+//      gate and the costate after it, the same buffers A reads), its fibres
+//      split over ch items whose partial sums go to an LDS slot when ch > 1,
+//   C. the sum of those partial sums for gate g-2, in a fixed order,
+//   D. the tables A needs in the next interval (G_{g+1}^-1, G_g^dag), read
+//      from memory during the interval before, are stored to the free LDS
+//      slots at the start of the interval, and the fibre offsets of gate g+1
+//      at its end,
+// so one barrier per gate.  The items of psi's A, mu's A, B and C each start
+// on a wave boundary: a wave that mixed two of them would run both codes one
+// after the other.  A single-mode gate's reduced matrix of one visit is
+// stored once (its own slot); a pair gate's is added to the column's sum,
+// whose old value is loaded at the start of the interval by the thread that
+// adds to it.  Every sum is in a fixed order: bitwise reproducible.
+// Measured on the 4-fluxonium chain (d = 5, D = 625, Q2): an interval with a
+// pair gate takes about 7.4 us, bound by the LDS reads of the gate rows and
+// fibres of A; one with single-mode gates only about 2.9 us.
+constexpr int LC_THREADS = 512;   // split-walk workgroup (2 waves per SIMD)
+
+struct LcGate {
+  const double2* gi;   // G^-1 (memory)
+  const double2* ga;   // G^dag
+  double2* m;          // this column's reduced matrix of the gate (Ms slot or Mp block)
+  int s0, s1;          // strides of the gate's digits (s1 = 0: single-mode gate)
+};
+
+// gate g of the walk over steps [n_lo, n_hi): steps backward, pieces backward,
+// the local terms of a piece backward (a symmetric piece visits every term
+// twice: visit 0 in the first half of the piece, visit 1 in the second)
+__device__ __forceinline__ LcGate lc_gate(const LcRun& R, int g, int n_hi, int n_lo, int col,
+                                          const double2* sgi, const double2* sga,
+                                          const double2* pgi, const double2* pga, double2* Ms,
+                                          double2* Mp, int dd) {
+  const int K = R.M + R.E, nvis = R.H == 2 ? 2 : 1, len = nvis * K, per = R.r * len;
+  const int ns = g / per, rem = g - ns * per, jj = rem / len;
+  const int n = n_hi - 1 - ns, j = R.r - 1 - jj, q = len - 1 - (rem - jj * len);
+  const int t = q < K ? q : 2 * K - 1 - q, vis = q < K ? 0 : 1;
+  LcGate G;
+  if (t < R.M) {
+    const size_t b = ((size_t)n * R.r + j) * R.M + t;
+    G.gi = sgi + b * dd;
+    G.ga = sga + b * dd;
+    G.m = Ms + (((((size_t)(n - n_lo) * R.r + j) * R.M + t) * nvis + vis) * R.S + col) * dd;
+    G.s0 = R.stride[t];
+    G.s1 = 0;
+  } else {
+    const size_t b = (size_t)j * R.E + (t - R.M);
+    G.gi = pgi + b * dd * dd;
+    G.ga = pga + b * dd * dd;
+    G.m = Mp + ((size_t)col * R.r * R.E + b) * dd * dd;
+    G.s0 = R.stride[R.ci[t - R.M]];
+    G.s1 = R.stride[R.cj[t - R.M]];
+  }
+  return G;
+}
+
+// partial sums per entry of a reduced matrix with ent entries over nf fibres
+__device__ __forceinline__ int lc_chunks(int ent, int nf) {
+  const int c = ent >= LC_THREADS ? 1 : LC_THREADS / ent;
+  return c < nf ? (c < 16 ? c : 16) : nf;
+}
+
+// first item of this thread in a loop whose items follow `off` earlier ones
+// (so consecutive loops of one interval fill the block in turn)
+__device__ __forceinline__ int lc_first(int off) {
+  return (int)((threadIdx.x + LC_THREADS - (unsigned)off % LC_THREADS) % LC_THREADS);
+}
+
+// fibre offsets of gate G (D/d of a single-mode gate, D/d^2 of a pair gate)
+template <int d>
+__device__ __forceinline__ void lc_fibres(const LcGate& G, int D, int* tab) {
+  if (G.s1 == 0) {
+    const double is = 1.0 / G.s0;
+    for (int f = threadIdx.x; f < D / d; f += LC_THREADS) tab[f] = fibre1<d>(f, G.s0, is);
+  } else {
+    const int sp = G.s0 > G.s1 ? G.s0 : G.s1, sq = G.s0 > G.s1 ? G.s1 : G.s0;
+    const int wd = sp / (sq * d);
+    const double isq = 1.0 / sq, iw = 1.0 / wd;
+    for (int f = threadIdx.x; f < D / (d * d); f += LC_THREADS)
+      tab[f] = fibre2<d>(f, sp, sq, wd, isq, iw);
+  }
+}
+
+// A: out = Gt in (Gt and the fibre offsets in LDS), from the item w0 on;
+// D/d items: the d rows of a fibre of a single-mode gate, or the rows
+// (a, 0..d-1) of a pair fibre
+template <int d>
+__device__ __forceinline__ void lc_split_apply(const double2* in, double2* out, const LcGate& G,
+                                               const double2* Gt, const int* tab, int D, int w0) {
+  constexpr int dd = d * d;
+  if (G.s1 == 0) {
+    const int s = G.s0;
+    for (int w = w0; w < D / d; w += LC_THREADS) {
+      const int base = tab[w];
+      double2 x[d], y[d];
+#pragma unroll
+      for (int a = 0; a < d; ++a) x[a] = in[base + a * s];
+#pragma unroll
+      for (int r = 0; r < d; ++r) y[r] = crow<d>(Gt + r * d, x);
+#pragma unroll
+      for (int r = 0; r < d; ++r) out[base + r * s] = y[r];
+    }
+  } else {
+    const int si = G.s0, sj = G.s1, nf = D / dd;
+    for (int w = w0; w < d * nf; w += LC_THREADS) {
+      const int a = w / nf, base = tab[w - a * nf];
+      double2 x[dd], y[d];
+#pragma unroll
+      for (int u = 0; u < d; ++u)
+#pragma unroll
+        for (int v = 0; v < d; ++v) x[u * d + v] = in[base + u * si + v * sj];
+#pragma unroll
+      for (int k = 0; k < d; ++k) y[k] = crow<dd>(Gt + (a * d + k) * dd, x);
+#pragma unroll
+      for (int k = 0; k < d; ++k) out[base + a * si + k * sj] = y[k];
+    }
+  }
+}
+
+__device__ __forceinline__ void lc_copy(const double2* in, double2* out, int D, int w0) {
+  for (int i = w0; i < D; i += LC_THREADS) out[i] = in[i];
+}
+
+// B for a gate of NL local levels: M_AB = sum over fibres of conj(mu[A]) psi[B];
+// item wi = c ent + e (from the item w0 on) sums the fibres f = c mod ch.
+// ch = 1: it adds old[0] (first item) or old[1] (the earlier sums this thread
+// loaded) and stores; else the partial sum goes to scr[e ch + c].
+template <int d, int NL>
+__device__ __forceinline__ void lc_split_item(const double2* mu, const double2* psi,
+                                              const LcGate& G, const int* tab, int nf, int ch,
+                                              double2* scr, double2 o, int wi) {
+  constexpr int ent = NL * NL, U = 4;   // U fibres in flight, each its own partial sum
+  const int c = wi / ent, e = wi - c * ent;
+  const int A = e / NL, B = e - A * NL;
+  const int oa = NL == d ? A * G.s0 : (A / d) * G.s0 + (A % d) * G.s1;
+  const int ob = NL == d ? B * G.s0 : (B / d) * G.s0 + (B % d) * G.s1;
+  double re[U], im[U];
+#pragma unroll
+  for (int k = 0; k < U; ++k) re[k] = im[k] = 0.0;
+  int f = c;
+  for (; f + (U - 1) * ch < nf; f += U * ch) {
+    int b[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) b[k] = tab[f + k * ch];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const double2 u = mu[b[k] + oa], v = psi[b[k] + ob];
+      re[k] = fma(u.x, v.x, re[k]);
+      re[k] = fma(u.y, v.y, re[k]);
+      im[k] = fma(u.x, v.y, im[k]);
+      im[k] = fma(-u.y, v.x, im[k]);
+    }
+  }
+  for (; f < nf; f += ch) {
+    const int base = tab[f];
+    const double2 u = mu[base + oa], v = psi[base + ob];
+    re[0] = fma(u.x, v.x, re[0]);
+    re[0] = fma(u.y, v.y, re[0]);
+    im[0] = fma(u.x, v.y, im[0]);
+    im[0] = fma(-u.y, v.x, im[0]);
+  }
+  const double sr = (re[0] + re[1]) + (re[2] + re[3]), si = (im[0] + im[1]) + (im[2] + im[3]);
+  if (ch == 1)
+    G.m[e] = make_double2(o.x + sr, o.y + si);
+  else
+    scr[e * ch + c] = make_double2(sr, si);
+}
+
+// B for a gate of NL local levels: M_AB = sum over fibres of conj(mu[A]) psi[B];
+// item wi = c ent + e (w0 and w0 + T for this thread: ent ch <= d^4 <= 2 T)
+// sums the fibres f = c mod ch.  ch = 1: it adds old[0] or old[1] (the earlier
+// sums this thread loaded) and stores; else the partial sum goes to
+// scr[e ch + c].  Straight-line code, no item loop: a loop that stores to
+// memory and uses values loaded before it makes the compiler wait for every
+// load in flight (the prefetched tables) at its entry.
+template <int d, int NL>
+__device__ __forceinline__ void lc_split_reduce_n(const double2* mu, const double2* psi,
+                                                  const LcGate& G, const int* tab, int D,
+                                                  double2* scr, const double2* old, int w0) {
+  constexpr int ent = NL * NL;
+  static_assert(ent <= 2 * LC_THREADS, "at most two B items per thread");
+  const int nf = D / NL, ch = lc_chunks(ent, nf);
+  if (w0 < ent * ch) lc_split_item<d, NL>(mu, psi, G, tab, nf, ch, scr, old[0], w0);
+  if (w0 + LC_THREADS < ent * ch)
+    lc_split_item<d, NL>(mu, psi, G, tab, nf, ch, scr, old[1], w0 + LC_THREADS);
+}
+
+// C: the partial sums of B for gate G, in the order c = 0, 1, ...; entry e
+// (< T here) is this thread's, which adds old[0] for a pair gate
+template <int d>
+__device__ __forceinline__ void lc_split_fold(const LcGate& G, int D, const double2* scr,
+                                              const double2* old, int e) {
+  const bool single = G.s1 == 0;
+  const int nloc = single ? d : d * d, ent = nloc * nloc, ch = lc_chunks(ent, D / nloc);
+  if (ch == 1 || e >= ent) return;
+  double re = 0.0, im = 0.0;
+#pragma unroll 4
+  for (int c = 0; c < ch; ++c) {
+    re += scr[e * ch + c].x;
+    im += scr[e * ch + c].y;
+  }
+  if (single) {
+    G.m[e] = make_double2(re, im);
+  } else {
+    G.m[e] = make_double2(old[0].x + re, old[0].y + im);
+  }
+}
+
+template <int d>
+__global__ void __launch_bounds__(LC_THREADS)
+lc_walk_split_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __restrict__ psiT,
+                     const double2* __restrict__ lamT, double2* __restrict__ psi_st,
+                     double2* __restrict__ mu_st, const double2* __restrict__ sg_inv,
+                     const double2* __restrict__ sg_adj, const double2* __restrict__ pg_inv,
+                     const double2* __restrict__ pg_adj, double2* __restrict__ Ms,
+                     double2* __restrict__ Mp) {
+  extern __shared__ double2 lds[];
+  constexpr int dd = d * d, NN = dd * dd;
+  static_assert(NN <= 2 * LC_THREADS, "a gate table is prefetched as two entries per thread");
+  const int col = blockIdx.x, D = R.D, tid = threadIdx.x, nft = D / d;
+  const size_t off = (size_t)col * D;
+  double2* P = lds;                  // psi: two buffers of D
+  double2* U = lds + 2 * D;          // mu: two buffers of D
+  double2* Gi = lds + 4 * D;         // inverse gates: two slots of NN
+  double2* Ga = Gi + 2 * NN;         // adjoint gates: two slots of NN
+  double2* scr = Ga + 2 * NN;        // partial sums: two slots of LC_THREADS
+  int* tab = reinterpret_cast<int*>(scr + 2 * LC_THREADS);   // fibre offsets: three slots of D/d
+  const size_t np_col = (size_t)R.r * R.E * NN;
+  const int K = R.M + R.E, len = R.H == 2 ? 2 * K : K;
+  const int ng = (n_hi - n_lo) * R.r * len;   // gates of this launch
+  auto gate = [&](int g) {
+    return lc_gate(R, g, n_hi, n_lo, col, sg_inv, sg_adj, pg_inv, pg_adj, Ms, Mp, dd);
+  };
+  auto nn_of = [&](const LcGate& G) { return G.s1 ? NN : dd; };
+  auto chunks_of = [&](const LcGate& G) {
+    const int nloc = G.s1 ? dd : d;
+    return lc_chunks(nloc * nloc, D / nloc);
+  };
+  if (first) {
+    for (int i = tid; i < D; i += LC_THREADS) {
+      P[i] = unrotate(R, d, i, psiT[off + i]);
+      U[i] = unrotate(R, d, i, lamT[off + i]);
+    }
+    for (size_t e = tid; e < np_col; e += LC_THREADS) Mp[col * np_col + e] = make_double2(0, 0);
+  } else {
+    for (int i = tid; i < D; i += LC_THREADS) {
+      P[i] = psi_st[off + i];
+      U[i] = mu_st[off + i];
+    }
+  }
+  auto ent_of = [&](const LcGate& G) { return G.s1 ? NN : dd; };
+  LcGate gc = gate(0), gn = ng > 1 ? gate(1) : gc, gp = gc, gpp = gc;
+  for (int e = tid; e < nn_of(gc); e += LC_THREADS) Gi[e] = gc.gi[e];
+  lc_fibres<d>(gc, D, tab);
+  // tables stored at the start of interval g (G_{g+1}^-1, G_g^dag), read from
+  // memory during the interval before (every gate pointer here is a valid
+  // table, so the reads are unconditional, with clamped indices)
+  // (entries tid and tid + T of each table: named registers, not arrays, which
+  // the compiler would index in scratch memory)
+  const int e0 = tid, e1 = tid + LC_THREADS;
+  auto clampi = [](int e, int n) { return e < n ? e : n - 1; };
+  double2 ri0 = gn.gi[clampi(e0, nn_of(gn))], ri1 = gn.gi[clampi(e1, nn_of(gn))];
+  double2 ra0 = gc.ga[clampi(e0, nn_of(gc))], ra1 = gc.ga[clampi(e1, nn_of(gc))];
+  __syncthreads();
+  for (int g = 0; g <= ng + 1; ++g) {
+    const int cur = g & 1, nxt = cur ^ 1;
+    const bool hasC = g < ng, hasP = g >= 1 && g <= ng, hasPP = g >= 2;
+    const bool hasN = g + 1 < ng, hasN2 = g + 2 < ng;
+    const LcGate gn2 = hasN2 ? gate(g + 2) : gn;
+    // work items of this interval, each kind from a wave boundary on, so that
+    // no wave mixes the code of two gates: psi's (A), mu's (A), B's, C's
+    const int nAp = hasC ? D / d : (g == ng ? D : 0);
+    const int nAm = hasP ? D / d : (g == 0 ? D : 0);
+    const int nB = hasP ? ent_of(gp) * chunks_of(gp) : 0;
+    const int oAm = (nAp + 63) & ~63, oB = oAm + ((nAm + 63) & ~63), oF = oB + ((nB + 63) & ~63);
+    const int wB = lc_first(oB), eF = lc_first(oF);
+    // D: the tables read during the interval before into their free slots
+    // (the slots of gates g - 1 and g - 2, which the last interval read);
+    // then the old sums this thread adds to, and the tables of the next
+    // interval into the same registers (no register copies, which would wait
+    // for the reads in flight)
+    if (hasN) {
+      if (e0 < nn_of(gn)) Gi[((g + 1) & 1) * NN + e0] = ri0;
+      if (e1 < nn_of(gn)) Gi[((g + 1) & 1) * NN + e1] = ri1;
+    }
+    if (hasC) {
+      if (e0 < nn_of(gc)) Ga[(g & 1) * NN + e0] = ra0;
+      if (e1 < nn_of(gc)) Ga[(g & 1) * NN + e1] = ra1;
+    }
+    double2 old[2];
+    const bool addP = hasP && gp.s1 != 0 && chunks_of(gp) == 1;
+    const bool addPP = hasPP && gpp.s1 != 0 && chunks_of(gpp) > 1;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int eb = wB + k * LC_THREADS;
+      old[k] = addP && eb < NN ? gp.m[eb]
+                               : (addPP && k == 0 && eF < NN ? gpp.m[eF] : make_double2(0, 0));
+    }
+    ri0 = gn2.gi[clampi(e0, nn_of(gn2))];
+    ri1 = gn2.gi[clampi(e1, nn_of(gn2))];
+    ra0 = gn.ga[clampi(e0, nn_of(gn))];
+    ra1 = gn.ga[clampi(e1, nn_of(gn))];
+    const double2 *Pc = P + cur * D, *Uc = U + cur * D;
+    double2 *Pn = P + nxt * D, *Un = U + nxt * D;
+    const int* tc = tab + (g % 3) * nft;          // gate g
+    const int* tp = tab + ((g + 2) % 3) * nft;    // gate g - 1
+    // A
+    if (hasC)
+      lc_split_apply<d>(Pc, Pn, gc, Gi + (g & 1) * NN, tc, D, tid);
+    else if (g == ng)
+      lc_copy(Pc, Pn, D, tid);
+    if (hasP)
+      lc_split_apply<d>(Uc, Un, gp, Ga + ((g - 1) & 1) * NN, tp, D, lc_first(oAm));
+    else if (g == 0)
+      lc_copy(Uc, Un, D, lc_first(oAm));
+    // B
+    if (hasP) {
+      double2* sp = scr + ((g - 1) & 1) * LC_THREADS;
+      if (gp.s1 == 0)
+        lc_split_reduce_n<d, d>(Uc, Pc, gp, tp, D, sp, old, wB);
+      else
+        lc_split_reduce_n<d, dd>(Uc, Pc, gp, tp, D, sp, old, wB);
+    }
+    // C
+    if (hasPP) lc_split_fold<d>(gpp, D, scr + (g & 1) * LC_THREADS, old, eF);
+    if (g == ng + 1) {
+      for (int i = tid; i < D; i += LC_THREADS) {
+        psi_st[off + i] = Pc[i];
+        mu_st[off + i] = Uc[i];
+      }
+    }
+    if (hasN) lc_fibres<d>(gn, D, tab + ((g + 1) % 3) * nft);
+    __syncthreads();
+    gpp = gp;
+    gp = gc;
+    gc = gn;
+    gn = gn2;
+  }
+}
+
 // Tr(K P) for n x n K (row stride ks) and P given by a functor p(row, col)
 template <typename F>
 __device__ __forceinline__ double2 trace_kp(const double2* K, int ks, int n, F p) {
@@ -1163,11 +1513,12 @@ __device__ __forceinline__ double2 trace_kp(const double2* K, int ks, int n, F p
 }
 
 // Single-mode gates of steps [n_lo, n_lo + nsteps): block b = (nl r + j) M + m.
-// The column sum of M, K = L(X, M^T) with X = -i a tau h(t), then the traces
+// The sum of M over the nvis visits and the columns (visit-major, a fixed
+// order), K = L(X, M^T) with X = -i a tau h(t), then the traces
 // z = (Tr K n, Tr K phi, Tr K dh/dEJ, Tr K dh/dEC, Tr K dh/dEL) into
 // z[(step r + j) M + m][5].
 __global__ void __launch_bounds__(64)
-lc_single_kernel(TrGen G, int n_lo, int S, const double* __restrict__ eps,
+lc_single_kernel(TrGen G, int n_lo, int S, int nvis, const double* __restrict__ eps,
                  const double2* __restrict__ ops, const double* __restrict__ par,
                  const double* __restrict__ deps, const double2* __restrict__ dops,
                  const double2* __restrict__ Ms, double2* __restrict__ z) {
@@ -1205,9 +1556,9 @@ lc_single_kernel(TrGen G, int n_lo, int S, const double* __restrict__ eps,
       v = cmul(w, h);
     } else if (row < d) {                     // upper right: M^T, summed over columns
       const int r0 = row, c0 = cc - d;
-      const double2* src = Ms + (((size_t)nl * G.r + j) * G.M + m) * S * dd + (size_t)c0 * d + r0;
+      const double2* src = Ms + (((size_t)nl * G.r + j) * G.M + m) * nvis * S * dd + (size_t)c0 * d + r0;
       double re = 0.0, im = 0.0;
-      for (int c = 0; c < S; ++c) {
+      for (int c = 0; c < nvis * S; ++c) {
         re += src[(size_t)c * dd].x;
         im += src[(size_t)c * dd].y;
       }
@@ -1288,11 +1639,29 @@ lc_pair_kernel(TrGen G, int S, const double2* __restrict__ ops, const double2* _
   }
 }
 
+// LDS of the split walk: two buffers each of psi and mu, two slots each of
+// inverse and adjoint gates (d^4 entries), two slots of partial sums
+inline size_t lc_split_lds(int64_t D, int d) {
+  const int64_t nn = (int64_t)d * d * d * d;
+  return (size_t)(4 * D + 4 * nn + 2 * LC_THREADS) * sizeof(double2) +
+         (size_t)3 * (D / d) * sizeof(int);
+}
+inline bool lc_split_fits(int64_t D, int d) { return lc_split_lds(D, d) <= (size_t)TR_MAXLDS; }
+
 template <int d>
 hipError_t run_lc_walk(const LcRun& R, int n_hi, int n_lo, int first, const double2* psiT,
                        const double2* lamT, double2* psi_st, double2* mu_st, const double2* sgi,
                        const double2* sga, const double2* pgi, const double2* pga, double2* Ms,
                        double2* Mp, hipStream_t st) {
+  if (lc_split_fits(R.D, d)) {
+    const size_t sh = lc_split_lds(R.D, d);
+    hipError_t e = hipFuncSetAttribute((const void*)lc_walk_split_kernel<d>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lc_walk_split_kernel<d>, dim3(R.S), dim3(LC_THREADS), sh, st, R, n_hi, n_lo,
+                       first, psiT, lamT, psi_st, mu_st, sgi, sga, pgi, pga, Ms, Mp);
+    return hipGetLastError();
+  }
   const size_t sh = ((size_t)2 * R.D + TR_THREADS) * sizeof(double2);
   hipError_t e = hipFuncSetAttribute((const void*)lc_walk_kernel<d>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
@@ -1327,7 +1696,7 @@ LcLayout lc_layout(const scp_system* sys, int order, int S) {
   L.sga = take(N * r * M * dd * sizeof(double2));
   L.pgi = take(r * E * dd * dd * sizeof(double2));
   L.pga = take(r * E * dd * dd * sizeof(double2));
-  L.ms = take((size_t)L.chunk * r * M * S * dd * sizeof(double2));
+  L.ms = take((size_t)L.chunk * r * M * (L.F.H == 2 ? 2 : 1) * S * dd * sizeof(double2));
   L.mp = take((size_t)S * r * E * dd * dd * sizeof(double2));
   L.z = take(N * r * M * 5 * sizeof(double2));
   L.zp = take(r * E * 7 * sizeof(double2));
@@ -1445,6 +1814,9 @@ scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, c
   double2* zp = reinterpret_cast<double2*>(base + Y.zp);
   const double* ddeps = reinterpret_cast<const double*>(base + Y.deps);
   const double2* ddops = reinterpret_cast<const double2*>(base + Y.dops);
+  // the split walk stores each visit of a single-mode gate in its own slot,
+  // the in-place walk adds the visits of a step into one
+  const int nvis = lc_split_fits(R.D, d) && W.H == 2 ? 2 : 1;
   for (int n_hi = N; n_hi > 0; n_hi -= Y.chunk) {
     const int n_lo = std::max(0, n_hi - Y.chunk);
     const int first = n_hi == N ? 1 : 0;
@@ -1458,7 +1830,8 @@ scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, c
     HIPCHK(e);
     const int nb = (n_hi - n_lo) * W.r * M;
     hipLaunchKernelGGL(lc_single_kernel, dim3(nb), dim3(64),
-                       4 * 4 * dd * sizeof(double2) + TR_MAXDRV * sizeof(double), st, G, n_lo, S, deps,
+                       4 * 4 * dd * sizeof(double2) + TR_MAXDRV * sizeof(double), st, G, n_lo, S,
+                       nvis, deps,
                        dops, dpar, ddeps, ddops, Ms, z);
     HIPCHK(hipGetLastError());
   }

@@ -98,6 +98,15 @@ def test_lcam_fluxonium_chain_workload_prefix(scp):
     _compare(scp, _prefix(si.config3(), 6), "q2", seed=1)
 
 
+@pytest.mark.parametrize("dims,n_steps,order", [([3, 3], 300, "q2"), ([2, 2, 2], 260, "q4j")],
+                         ids=["raw2_d3-300-q2", "raw3_d2-260-q4j"])
+def test_lcam_over_several_walk_launches(scp, dims, n_steps, order):
+    # more than 128 steps: the walk runs in launches of 128 steps, each one
+    # resuming from the state and costate the previous launch stored
+    print(f"[lcam] raw {dims} {n_steps} steps {order}", flush=True)
+    _compare(scp, si.random_raw_system(14, dims, 1, 3.0, n_steps, env="gauss"), order, seed=5)
+
+
 def test_lcam_x6_workload_prefix(scp):
     # the six-fluxonium X^6 chain (d = 4, D = 4096, 148 parameters), 8 sampled
     # columns over its first 2 steps of 0.01 ns, Q4 (three pieces)
