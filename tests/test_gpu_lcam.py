@@ -107,6 +107,15 @@ def test_lcam_over_several_walk_launches(scp, dims, n_steps, order):
     _compare(scp, si.random_raw_system(14, dims, 1, 3.0, n_steps, env="gauss"), order, seed=5)
 
 
+@pytest.mark.parametrize("order", ["q2", "q4j"])
+def test_lcam_single_mode_device(scp, order):
+    # one driven mode, no coupling: every reduced matrix has a single fibre
+    # (its sum is stored directly, not split) and no pair gate exists;
+    # 140 steps take two walk launches
+    print(f"[lcam] one raw mode d=4, 140 steps {order}", flush=True)
+    _compare(scp, si.random_raw_system(15, [4], 1, 3.0, 140, env="gauss"), order, seed=5)
+
+
 def test_lcam_x6_workload_prefix(scp):
     # the six-fluxonium X^6 chain (d = 4, D = 4096, 148 parameters), 8 sampled
     # columns over its first 2 steps of 0.01 ns, Q4 (three pieces)
