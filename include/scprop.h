@@ -83,11 +83,20 @@ enum {
  * RAW: trunc energies raw_eps and operators raw_ops given directly.
  * Frame energies (interaction picture) default to the dressed energies of
  * the mode as built; has_frame = 1 takes frame_eps instead (used to hold the
- * frame fixed while parameters move). */
+ * frame fixed while parameters move).
+ *
+ * Modes may have different truncations d_m.  The system then runs at d =
+ * max d_m: a mode with fewer levels carries d - d_m inert levels (zero rows
+ * and columns in n, phi and their derivatives; the open-system jump
+ * operators only lower levels), so nothing ever enters them and the d_m
+ * levels evolve exactly as in the product space of the modes' own
+ * truncations.  Their energies continue the top level spacing.  Every index below (columns, rows, labels, matrix entries) is in
+ * the uniform space: product state (a_0, ..., a_{n-1}) at sum_m a_m
+ * d^(n-1-m). */
 typedef struct {
   int32_t kind;        /* SCP_MODE_*                                           */
   int32_t basis_dim;   /* basis size before truncation (ignored for RAW)      */
-  int32_t trunc;       /* d, 2..SCP_MAX_TRUNC; equal for all modes            */
+  int32_t trunc;       /* d_m, 2..SCP_MAX_TRUNC; modes may differ (see below)  */
   int32_t has_frame;   /* 1: use frame_eps                                    */
   double EC, EJ, EL, ng, phiext;
   const double* raw_eps;  /* RAW: d energies (host)                            */
@@ -142,9 +151,10 @@ typedef struct scp_system scp_system;
  * 1e-9 relative of another level), SCP_ENOMEM, SCP_EHIP. */
 scp_status scp_build_system(const scp_system_desc* desc, void* stream, scp_system** out);
 
-/* Sizes: D, number of gradient parameters (order: drive parameters in drive
- * then par order; then (EJ, EC, EL) of every mode; then coupling g in
- * coupling order), dims (n_modes ints, nullable). */
+/* Sizes: D = d^n_modes, number of gradient parameters (order: drive
+ * parameters in drive then par order; then (EJ, EC, EL) of every mode; then
+ * coupling g in coupling order), dims (n_modes ints, nullable: the levels of
+ * every mode in the index space, d for all). */
 scp_status scp_system_info(const scp_system* sys, int64_t* D, int32_t* n_params,
                            int32_t* n_modes, int32_t* dims);
 
@@ -571,7 +581,8 @@ void scp_server_destroy(scp_server* sv);
  * exp(-gammaphi t).  Classical RK4 on the system's step grid, complex FP32
  * with a compensated (two-word) state, one workgroup per matrix with the
  * matrix resident in LDS: D^2 <= 6561 (d = 2: N <= 5, d = 3: N <= 4,
- * d = 4: N <= 3, d = 5: N <= 2), every mode of one dimension.
+ * d = 4: N <= 3, d = 5: N <= 2), d the largest truncation (see
+ * scp_mode_desc).
  * ------------------------------------------------------------------------ */
 
 /* Device workspace bytes of scp_propagate_lindblad (a small argument block

@@ -10,5 +10,5 @@ lib()  # fail loudly if the HIP library is missing
 
 from .api import (ChannelTarget, StateTarget, System, Target, basis_columns,  # noqa: E402,F401
                   fidelity, fidelity_channel, fidelity_local, fidelity_states, fidelity_zcomp,
-                  matrix_units, probe_contraction)
+                  matrix_units, padded_indices, probe_contraction)
 from . import autograd  # noqa: E402,F401

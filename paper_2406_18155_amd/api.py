@@ -93,9 +93,12 @@ class System:
         check(lib().scp_build_system(C.byref(sd), _stream_ptr(stream), C.byref(h)))
         self.handle = h
         D, npar, nm = C.c_int64(), C.c_int32(), C.c_int32()
-        check(lib().scp_system_info(h, C.byref(D), C.byref(npar), C.byref(nm), None))
+        dims = (C.c_int32 * len(desc["modes"]))()
+        check(lib().scp_system_info(h, C.byref(D), C.byref(npar), C.byref(nm), dims))
         self.D, self.n_params, self.n_modes = D.value, npar.value, nm.value
-        self.d = int(desc["modes"][0]["trunc"])
+        # levels per mode in the library's index space (the largest truncation;
+        # a mode with fewer levels is padded with inert ones)
+        self.d = int(dims[0])
         self.n_steps = int(desc["n_steps"])
 
     # -- introspection -------------------------------------------------------
@@ -509,6 +512,28 @@ def probe_contraction(form, ops, iters, n_wg=1024, out=None, stream=None):
         out = torch.empty(n_wg * 256, dtype=torch.float32, device=ops.device)
     check(lib().scp_probe_contraction(int(form), int(n_wg), int(iters), int(ops.shape[0]),
                                       _ptr(ops), _ptr(out), _stream_ptr(stream)))
+    return out
+
+
+def padded_indices(truncs, indices):
+    """Product-state indices given in the modes' own truncations (mode 0 most
+    significant) mapped to the library's index space, in which every mode has
+    the largest truncation d (a mode truncated to fewer levels carries inert
+    extra levels that no operator reaches).  Identity when all are equal."""
+    truncs = [int(v) for v in truncs]
+    d = max(truncs)
+    out = []
+    for idx in indices:
+        r, levels = int(idx), []
+        for t in reversed(truncs):
+            levels.append(r % t)
+            r //= t
+        if r:
+            raise ValueError(f"index {idx} outside the product space {truncs}")
+        v = 0
+        for a in reversed(levels):
+            v = v * d + a
+        out.append(v)
     return out
 
 

@@ -151,10 +151,8 @@ scp_status validate(const scp_system_desc* ds) {
   if (!ds->modes) return fail(SCP_EINVAL, "null modes");
   if (ds->n_couplings > 0 && !ds->couplings) return fail(SCP_EINVAL, "null couplings");
   if (ds->n_drives > 0 && !ds->drives) return fail(SCP_EINVAL, "null drives");
-  const int d = ds->modes[0].trunc;
   for (int m = 0; m < ds->n_modes; ++m) {
     const scp_mode_desc& M = ds->modes[m];
-    if (M.trunc != d) return fail(SCP_EINVAL, "all modes must share the truncation d");
     if (M.trunc < 2 || M.trunc > SCP_MAX_TRUNC) return fail(SCP_EINVAL, "trunc out of range");
     if (M.kind == SCP_MODE_TRANSMON) {
       if (M.basis_dim < 3 || M.basis_dim % 2 == 0 || M.basis_dim > 95 || M.basis_dim <= M.trunc)
@@ -697,13 +695,41 @@ scp_status build_tables(scp_system* sys, hipStream_t st) {
   return SCP_OK;
 }
 
+// A mode truncated to dm < d levels is carried at the system's d levels.  The
+// extra levels have no operator element to or from any level (zero rows and
+// columns in n, phi and their derivatives), so no amplitude ever enters them
+// and the dm levels evolve exactly as in the product space of the modes' own
+// truncations.  Their energies continue the top level spacing (distinct; in
+// a spectrum they are uncoupled states of their own).
+void pad_mode(ModeData& md, int d) {
+  const int dm = md.d;
+  if (dm >= d) return;
+  auto pad = [&](cplx* a) {
+    cplx t[SCP_MAX_TRUNC * SCP_MAX_TRUNC];
+    for (int i = 0; i < d * d; ++i) t[i] = cplx(0.0, 0.0);
+    for (int r = 0; r < dm; ++r)
+      for (int c = 0; c < dm; ++c) t[r * d + c] = a[r * dm + c];
+    std::copy(t, t + d * d, a);
+  };
+  for (int o = 0; o < 2; ++o) pad(md.ops[o]);
+  for (int p = 0; p < 3; ++p) {
+    for (int o = 0; o < 2; ++o) pad(md.dops[p][o]);
+    for (int a = dm; a < d; ++a) md.deps[p][a] = 0.0;
+  }
+  const double gap = md.eps[dm - 1] - md.eps[dm - 2];
+  for (int a = dm; a < d; ++a) md.eps[a] = md.eps[dm - 1] + (a - dm + 1) * (gap > 0 ? gap : 1.0);
+  md.d = d;
+}
+
 scp_status build(const scp_system_desc* ds, hipStream_t st, scp_system* sys) {
   scp_status v = validate(ds);
   if (v != SCP_OK) return v;
   HIPCHK(hipGetDevice(&sys->device));
   const int N = ds->n_modes;
   sys->n_modes = N;
-  sys->d = ds->modes[0].trunc;
+  // modes of different truncations run at the largest, the others padded
+  sys->d = 0;
+  for (int m = 0; m < N; ++m) sys->d = std::max(sys->d, (int)ds->modes[m].trunc);
   sys->n_steps = ds->n_steps;
   sys->T = ds->T;
   sys->h = ds->T / ds->n_steps;
@@ -782,11 +808,12 @@ scp_status build(const scp_system_desc* ds, hipStream_t st, scp_system* sys) {
       if (s != SCP_OK) return s;
     }
   }
-  // frames, couplings, drives
+  for (int m = 0; m < N; ++m) pad_mode(sys->modes[m], sys->d);
+  // frames (a padded level's frame is its energy), couplings, drives
   for (int m = 0; m < N; ++m) {
     const scp_mode_desc& M = ds->modes[m];
     for (int a = 0; a < sys->d; ++a)
-      sys->modes[m].frame[a] = M.has_frame ? M.frame_eps[a] : sys->modes[m].eps[a];
+      sys->modes[m].frame[a] = M.has_frame && a < M.trunc ? M.frame_eps[a] : sys->modes[m].eps[a];
   }
   for (int e = 0; e < ds->n_couplings; ++e) {
     const scp_coupling_desc& C = ds->couplings[e];

@@ -288,7 +288,7 @@ def test_state_fidelity_kernel_matches_oracle(scp):
 def test_invalid_arguments_are_rejected(scp):
     desc = si.config1()
     bad = copy.deepcopy(desc)
-    bad["modes"][1]["trunc"] = 3
+    bad["modes"][1]["trunc"] = 9              # above the largest truncation
     with pytest.raises(scp.ScpError, match="EINVAL"):
         scp.System(bad)
     bad = copy.deepcopy(desc)

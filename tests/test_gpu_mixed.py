@@ -1,0 +1,144 @@
+"""Devices whose modes have different truncations.  The library carries every
+mode at the largest truncation d, a mode with fewer levels padded with inert
+ones (no operator element reaches them); the oracle works in the product
+space of the modes' own truncations.  Parity: the GPU columns and rows mapped
+with padded_indices against the oracle's, the padded rows exactly empty, and
+the gradient of the same fidelity against the oracle's."""
+import copy
+
+import numpy as np
+import pytest
+
+import scp_inputs as si
+from oracle.adjoint import loss_and_grad
+from oracle.rk4 import basis_columns as oracle_cols, propagate as oracle_propagate
+from oracle.system import OracleSystem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FWD_TOL = 2e-5       # FP32 path, max abs element error (as for uniform truncations)
+PLAIN_TOL = 1e-10    # plain FP64 path
+GRAD_TOL = 1e-4      # ||g_gpu - g_oracle||_inf / ||g_oracle||_inf
+
+
+@pytest.fixture(scope="module")
+def scp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2406_18155_amd as m
+    return m
+
+
+def _transmons(truncs, T=6.0, n_steps=300, seed=0):
+    """Capacitively coupled transmons of the given truncations, a Gaussian
+    drive on mode 0 at its 0-1 carrier, CZ-style target on the computational
+    states."""
+    rng = si.rng_for(31, seed)
+    modes = [si.transmon_mode(rng, d) for d in truncs]
+    couplings = [{"i": m, "j": m + 1, "op_i": "n", "op_j": "n",
+                  "g": float(rng.uniform(5e-3, 20e-3)) * 2 * np.pi}
+                 for m in range(len(truncs) - 1)]
+    drives = [{"mode": 0, "op": "n", "env": "gauss", "params": [0.03 * 2 * np.pi],
+               "omega_d": None, "phase": 0.0, "sigma": T / 4.0}]
+    s = {"modes": modes, "couplings": couplings, "drives": drives, "T": T, "n_steps": n_steps}
+    return si._finish(s, list(truncs), target=si.cz_target(len(truncs)))
+
+
+CASES = {
+    "raw_3_2_3": lambda: si.random_raw_system(21, [3, 2, 3], 3, 2.0, 60, env="gauss"),
+    "raw_2_4": lambda: si.random_raw_system(22, [2, 4], 1, 2.0, 60, env="pwc"),
+    "transmons_3_4": lambda: _transmons([3, 4]),
+    "transmons_4_2_3": lambda: _transmons([4, 2, 3], n_steps=200),
+}
+
+
+def _gpu_desc(scp, desc):
+    """The same device with its column and row lists in the library's index space."""
+    truncs = [m["trunc"] for m in desc["modes"]]
+    g = copy.deepcopy(desc)
+    g["columns"] = scp.padded_indices(truncs, desc["columns"])
+    g["comp_rows"] = scp.padded_indices(truncs, desc["comp_rows"])
+    return g
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mixed_truncation_forward_matches_oracle(scp, name):
+    desc = CASES[name]()
+    truncs = [m["trunc"] for m in desc["modes"]]
+    print(f"[mixed] {name} truncations {truncs}", flush=True)
+    o = OracleSystem(desc)
+    ref = oracle_propagate(o, oracle_cols(o.D, desc["columns"]))        # (D, S)
+    gd = _gpu_desc(scp, desc)
+    g = scp.System(gd)
+    assert g.d == max(truncs) and g.D == max(truncs) ** len(truncs)
+    rows = scp.padded_indices(truncs, range(o.D))
+    inert = np.setdiff1d(np.arange(g.D), rows)
+    for dt, tol in ((torch.complex64, FWD_TOL), (torch.complex128, PLAIN_TOL)):
+        U = g.propagate(scp.basis_columns(g.D, gd["columns"], dtype=dt)).cpu().numpy().T
+        err = np.abs(U[rows, :] - ref).max()
+        print(f"[mixed] {name} {dt} max abs err {err:.2e}", flush=True)
+        assert err <= tol, err
+        assert np.abs(U[inert, :]).max() == 0.0      # no amplitude enters a padded level
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["raw_3_2_3", "transmons_3_4", "transmons_4_2_3"])
+def test_mixed_truncation_gradient_matches_oracle(scp, name):
+    desc = CASES[name]()
+    print(f"[mixed] {name} gradient", flush=True)
+    L, Fo, tau, Uo, go = loss_and_grad(OracleSystem(desc))
+    gd = _gpu_desc(scp, desc)
+    g = scp.System(gd)
+    psi0 = scp.basis_columns(g.D, gd["columns"])
+    opts = g.opts(psi0.shape[0], with_ckpt=1)
+    ws = g.workspace(opts, with_grad=True)
+    U = g.propagate(psi0, opts=opts, workspace=ws)
+    tgt = scp.Target(gd["comp_rows"], gd["comp_cols"], gd["target"])
+    cot = torch.empty_like(U)
+    F, _ = scp.fidelity(U, tgt, cotangent=cot)
+    grad = g.adjoint(cot, opts, ws)
+    g.close()
+    assert abs(F - Fo) <= 1e-5, (F, Fo)
+    err = np.abs(grad - go).max() / np.abs(go).max()
+    print(f"[mixed] {name} F {F:.6f} (oracle {Fo:.6f}) grad rel err {err:.2e}", flush=True)
+    assert err <= GRAD_TOL, err
+
+
+def test_mixed_truncation_mode_tables(scp):
+    # the padded levels of a mode: zero rows and columns in n and phi, energies
+    # above the kept ones and distinct
+    desc = CASES["transmons_3_4"]()
+    g = scp.System(_gpu_desc(scp, desc))
+    m0 = g.mode(0)            # truncated to 3, carried at 4
+    g.close()
+    o = OracleSystem(desc)
+    assert np.abs(m0["n"][3, :]).max() == 0.0 and np.abs(m0["n"][:, 3]).max() == 0.0
+    np.testing.assert_allclose(m0["eps"][:3], o.modes[0]["eps"], rtol=0, atol=1e-9)
+    assert m0["eps"][3] > m0["eps"][2]
+
+
+def test_mixed_truncation_open_system_matches_oracle(scp):
+    # Lindblad propagation with relaxation and dephasing: the jump operators
+    # only lower levels, so the padded levels stay empty here too
+    from oracle import lindblad as lb
+    desc = si.random_raw_system(23, [3, 2, 3], 3, 3.0, 200, env="gauss")
+    desc["modes"] = [dict(m, gamma1=0.03 * (1 + 0.3 * k), gammaphi=0.02 * (1 + 0.2 * k))
+                     for k, m in enumerate(desc["modes"])]
+    truncs = [m["trunc"] for m in desc["modes"]]
+    o = OracleSystem(desc)
+    rho0 = si.random_density_matrices(o.D, 4)
+    ref = lb.propagate(o, rho0)                                  # (4, D, D)
+    g = scp.System(_gpu_desc(scp, desc))
+    rows = np.asarray(scp.padded_indices(truncs, range(o.D)))
+    big = np.zeros((rho0.shape[0], g.D, g.D), dtype=np.complex128)
+    big[:, rows[:, None], rows[None, :]] = rho0
+    x = torch.tensor(big, dtype=torch.complex64, device="cuda").contiguous()
+    got = g.propagate_lindblad(x).cpu().numpy().astype(np.complex128)
+    g.close()
+    err = np.abs(got[:, rows[:, None], rows[None, :]] - ref).max()
+    rest = got.copy()
+    rest[:, rows[:, None], rows[None, :]] = 0.0
+    print(f"[mixed] open (3, 2, 3): max |d rho| {err:.2e}", flush=True)
+    assert err <= 5e-6, err
+    assert np.abs(rest).max() == 0.0

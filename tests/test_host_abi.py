@@ -55,8 +55,8 @@ def _bad_cases():
     base = si.config1()
     cases = []
     d = copy.deepcopy(base)
-    d["modes"][1]["trunc"] = 3
-    cases.append(("mixed truncation", d, "share the truncation"))
+    d["modes"][1]["trunc"] = 9
+    cases.append(("truncation above the maximum", d, "trunc out of range"))
     d = copy.deepcopy(base)
     d["couplings"][0]["op_i"] = "phi"
     cases.append(("transmon phase coupling", d, "phase operator"))
@@ -135,3 +135,14 @@ def test_request_footprint_grows_with_columns_steps_and_gradient():
     longer = copy.deepcopy(q)
     longer["n_steps"] *= 4
     assert nbytes(longer, S, 1) > grad
+
+
+def test_padded_indices_map_product_states_to_the_uniform_index_space():
+    # modes truncated to (3, 2, 4) run at d = 4: level a_m of mode m sits at
+    # stride 4^(2 - m); brute force over every product state
+    from paper_2406_18155_amd import padded_indices
+    exp = [(a * 4 + b) * 4 + c for a in range(3) for b in range(2) for c in range(4)]
+    assert padded_indices([3, 2, 4], range(24)) == exp
+    assert padded_indices([4, 4], range(16)) == list(range(16))
+    with pytest.raises(ValueError):
+        padded_indices([2, 3], [6])
