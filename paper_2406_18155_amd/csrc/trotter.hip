@@ -1185,16 +1185,31 @@ struct LcGate {
   int s0, s1;          // strides of the gate's digits (s1 = 0: single-mode gate)
 };
 
-// gate g of the walk over steps [n_lo, n_hi): steps backward, pieces backward,
-// the local terms of a piece backward (a symmetric piece visits every term
-// twice: visit 0 in the first half of the piece, visit 1 in the second)
-__device__ __forceinline__ LcGate lc_gate(const LcRun& R, int g, int n_hi, int n_lo, int col,
+// Position of a gate in the walk over steps [n_lo, n_hi): steps backward,
+// pieces backward, the len = nvis K local terms of a piece backward (a
+// symmetric piece visits every term twice: visit 0 in the first half of the
+// piece, visit 1 in the second).  Advanced by one gate at a time (no
+// divisions in the loop).
+struct LcPos {
+  int n, j, q;
+};
+__device__ __forceinline__ void lc_advance(LcPos& p, int r, int len) {
+  if (--p.q < 0) {
+    p.q = len - 1;
+    if (--p.j < 0) {
+      p.j = r - 1;
+      --p.n;
+    }
+  }
+}
+
+// the gate at position p
+__device__ __forceinline__ LcGate lc_gate(const LcRun& R, const LcPos& p, int n_lo, int col,
                                           const double2* sgi, const double2* sga,
                                           const double2* pgi, const double2* pga, double2* Ms,
                                           double2* Mp, int dd) {
-  const int K = R.M + R.E, nvis = R.H == 2 ? 2 : 1, len = nvis * K, per = R.r * len;
-  const int ns = g / per, rem = g - ns * per, jj = rem / len;
-  const int n = n_hi - 1 - ns, j = R.r - 1 - jj, q = len - 1 - (rem - jj * len);
+  const int K = R.M + R.E, nvis = R.H == 2 ? 2 : 1;
+  const int n = p.n, j = p.j, q = p.q;
   const int t = q < K ? q : 2 * K - 1 - q, vis = q < K ? 0 : 1;
   LcGate G;
   if (t < R.M) {
@@ -1336,11 +1351,10 @@ __device__ __forceinline__ void lc_split_item(const double2* mu, const double2* 
 // load in flight (the prefetched tables) at its entry.
 template <int d, int NL>
 __device__ __forceinline__ void lc_split_reduce_n(const double2* mu, const double2* psi,
-                                                  const LcGate& G, const int* tab, int D,
+                                                  const LcGate& G, const int* tab, int nf, int ch,
                                                   double2* scr, const double2* old, int w0) {
   constexpr int ent = NL * NL;
   static_assert(ent <= 2 * LC_THREADS, "at most two B items per thread");
-  const int nf = D / NL, ch = lc_chunks(ent, nf);
   if (w0 < ent * ch) lc_split_item<d, NL>(mu, psi, G, tab, nf, ch, scr, old[0], w0);
   if (w0 + LC_THREADS < ent * ch)
     lc_split_item<d, NL>(mu, psi, G, tab, nf, ch, scr, old[1], w0 + LC_THREADS);
@@ -1349,10 +1363,10 @@ __device__ __forceinline__ void lc_split_reduce_n(const double2* mu, const doubl
 // C: the partial sums of B for gate G, in the order c = 0, 1, ...; entry e
 // (< T here) is this thread's, which adds old[0] for a pair gate
 template <int d>
-__device__ __forceinline__ void lc_split_fold(const LcGate& G, int D, const double2* scr,
+__device__ __forceinline__ void lc_split_fold(const LcGate& G, int ch, const double2* scr,
                                               const double2* old, int e) {
   const bool single = G.s1 == 0;
-  const int nloc = single ? d : d * d, ent = nloc * nloc, ch = lc_chunks(ent, D / nloc);
+  const int ent = single ? d * d : d * d * d * d;
   if (ch == 1 || e >= ent) return;
   double re = 0.0, im = 0.0;
 #pragma unroll 4
@@ -1389,14 +1403,14 @@ lc_walk_split_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __re
   const size_t np_col = (size_t)R.r * R.E * NN;
   const int K = R.M + R.E, len = R.H == 2 ? 2 * K : K;
   const int ng = (n_hi - n_lo) * R.r * len;   // gates of this launch
-  auto gate = [&](int g) {
-    return lc_gate(R, g, n_hi, n_lo, col, sg_inv, sg_adj, pg_inv, pg_adj, Ms, Mp, dd);
+  // launch constants of the two gate kinds: fibres and partial sums per entry
+  const int nf1 = D / d, nf2 = D / dd;
+  const int ch1 = lc_chunks(dd, nf1), ch2 = lc_chunks(NN, nf2);
+  auto gate = [&](const LcPos& p) {
+    return lc_gate(R, p, n_lo, col, sg_inv, sg_adj, pg_inv, pg_adj, Ms, Mp, dd);
   };
   auto nn_of = [&](const LcGate& G) { return G.s1 ? NN : dd; };
-  auto chunks_of = [&](const LcGate& G) {
-    const int nloc = G.s1 ? dd : d;
-    return lc_chunks(nloc * nloc, D / nloc);
-  };
+  auto chunks_of = [&](const LcGate& G) { return G.s1 ? ch2 : ch1; };
   if (first) {
     for (int i = tid; i < D; i += LC_THREADS) {
       P[i] = unrotate(R, d, i, psiT[off + i]);
@@ -1410,7 +1424,11 @@ lc_walk_split_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __re
     }
   }
   auto ent_of = [&](const LcGate& G) { return G.s1 ? NN : dd; };
-  LcGate gc = gate(0), gn = ng > 1 ? gate(1) : gc, gp = gc, gpp = gc;
+  LcPos pos{n_hi - 1, R.r - 1, len - 1};   // gate 0
+  LcGate gc = gate(pos), gp = gc, gpp = gc;
+  lc_advance(pos, R.r, len);               // gate 1
+  LcGate gn = ng > 1 ? gate(pos) : gc;
+  lc_advance(pos, R.r, len);               // gate 2: gate g + 2 in interval g
   for (int e = tid; e < nn_of(gc); e += LC_THREADS) Gi[e] = gc.gi[e];
   lc_fibres<d>(gc, D, tab);
   // tables stored at the start of interval g (G_{g+1}^-1, G_g^dag), read from
@@ -1427,7 +1445,8 @@ lc_walk_split_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __re
     const int cur = g & 1, nxt = cur ^ 1;
     const bool hasC = g < ng, hasP = g >= 1 && g <= ng, hasPP = g >= 2;
     const bool hasN = g + 1 < ng, hasN2 = g + 2 < ng;
-    const LcGate gn2 = hasN2 ? gate(g + 2) : gn;
+    const LcGate gn2 = hasN2 ? gate(pos) : gn;
+    lc_advance(pos, R.r, len);
     // work items of this interval, each kind from a wave boundary on, so that
     // no wave mixes the code of two gates: psi's (A), mu's (A), B's, C's
     const int nAp = hasC ? D / d : (g == ng ? D : 0);
@@ -1478,12 +1497,12 @@ lc_walk_split_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __re
     if (hasP) {
       double2* sp = scr + ((g - 1) & 1) * LC_THREADS;
       if (gp.s1 == 0)
-        lc_split_reduce_n<d, d>(Uc, Pc, gp, tp, D, sp, old, wB);
+        lc_split_reduce_n<d, d>(Uc, Pc, gp, tp, nf1, ch1, sp, old, wB);
       else
-        lc_split_reduce_n<d, dd>(Uc, Pc, gp, tp, D, sp, old, wB);
+        lc_split_reduce_n<d, dd>(Uc, Pc, gp, tp, nf2, ch2, sp, old, wB);
     }
     // C
-    if (hasPP) lc_split_fold<d>(gpp, D, scr + (g & 1) * LC_THREADS, old, eF);
+    if (hasPP) lc_split_fold<d>(gpp, chunks_of(gpp), scr + (g & 1) * LC_THREADS, old, eF);
     if (g == ng + 1) {
       for (int i = tid; i < D; i += LC_THREADS) {
         psi_st[off + i] = Pc[i];
