@@ -150,7 +150,8 @@ namespace {
 
 // Upper bound of a request's device footprint before its plan exists.
 size_t estimate_bytes(const scp_system_desc* d, int S, int want_grad) {
-  const int dd = d->modes[0].trunc;
+  int dd = 0;   // the system runs at the largest truncation
+  for (int m = 0; m < d->n_modes; ++m) dd = std::max(dd, (int)d->modes[m].trunc);
   size_t D = 1;
   for (int m = 0; m < d->n_modes; ++m) D *= (size_t)dd;
   const size_t nslots = 2 * (size_t)d->n_couplings + d->n_drives + 1;
@@ -323,8 +324,10 @@ scp_status scp_server_submit(scp_server* sv, const scp_system_desc* desc, const 
     return fail(SCP_EINVAL, "null or empty argument");
   auto r = std::make_unique<Request>();
   r->dc.copy(desc);
+  int dmax = 0;   // the system runs at the largest truncation (see scp_mode_desc)
+  for (int m = 0; m < desc->n_modes; ++m) dmax = std::max(dmax, (int)desc->modes[m].trunc);
   int64_t D = 1;
-  for (int m = 0; m < desc->n_modes; ++m) D *= desc->modes[0].trunc;
+  for (int m = 0; m < desc->n_modes; ++m) D *= dmax;
   for (int j = 0; j < n_cols; ++j)
     if (columns[j] < 0 || columns[j] >= D) return fail(SCP_EINVAL, "column index out of range");
   for (int i = 0; i < d_c; ++i) {

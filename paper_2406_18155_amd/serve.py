@@ -145,7 +145,7 @@ def run_stream(requests, arrivals, hbm_budget_bytes, max_active=64, chunk_work=0
             raise TimeoutError("serving stream did not finish")
     lat = np.array([done_wall[i][0] - arrivals[i] for i in range(n)])
     total = max(d[0] for d in done_wall.values())
-    work = sum(q["n_steps"] * (q["modes"][0]["trunc"] ** len(q["modes"])) * len(q["columns"])
+    work = sum(q["n_steps"] * (max(m["trunc"] for m in q["modes"]) ** len(q["modes"])) * len(q["columns"])
                for q in requests)
     failed = sum(1 for d in done_wall.values() if d[1]["state"] != "done")
     srv.close()

@@ -142,3 +142,29 @@ def test_mixed_truncation_open_system_matches_oracle(scp):
     print(f"[mixed] open (3, 2, 3): max |d rho| {err:.2e}", flush=True)
     assert err <= 5e-6, err
     assert np.abs(rest).max() == 0.0
+
+
+def test_mixed_truncation_request_is_served(scp):
+    # the server sizes and checks a request in the library's index space: the
+    # result of a mixed-truncation request equals the direct path bitwise
+    from paper_2406_18155_amd import serve
+    desc = _gpu_desc(scp, CASES["transmons_4_2_3"]())
+    g = scp.System(desc)
+    g.set_engine("register")
+    psi0 = scp.basis_columns(g.D, desc["columns"])
+    opts = g.opts(psi0.shape[0], with_ckpt=1)
+    ws = g.workspace(opts, with_grad=True)
+    U = g.propagate(psi0, opts=opts, workspace=ws)
+    cot = torch.empty_like(U)
+    F, _ = scp.fidelity(U, scp.Target(desc["comp_rows"], desc["comp_cols"], desc["target"]),
+                        cotangent=cot)
+    grad = g.adjoint(cot, opts, ws)
+    g.close()
+    srv = serve.Server(8 << 30, max_active=4, chunk_work=2e5, engine="register")
+    rid = srv.submit(desc, True)
+    res = serve.drain(srv, [rid])[rid]
+    srv.close()
+    print(f"[mixed] served F {res['F']:.9f} direct {F:.9f}", flush=True)
+    assert res["state"] == "done"
+    assert res["F"] == F
+    assert np.array_equal(res["grad"], grad)
