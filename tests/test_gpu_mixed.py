@@ -168,3 +168,34 @@ def test_mixed_truncation_request_is_served(scp):
     assert res["state"] == "done"
     assert res["F"] == F
     assert np.array_equal(res["grad"], grad)
+
+
+@pytest.mark.parametrize("order", ["q2", "q4j"])
+def test_mixed_truncation_product_formula_and_lcam(scp, order):
+    # the product formulas and their LCAM gradient on the padded device:
+    # the padded levels' gates act as the identity on them and the kept block
+    # is the oracle's, to the FP64 bars of the uniform cases
+    from oracle import lcam, trotter
+    desc = si.random_raw_system(24, [3, 2, 3], 3, 2.0, 30, env="gauss")
+    truncs = [m["trunc"] for m in desc["modes"]]
+    o = OracleSystem(desc)
+    cols = desc["columns"]
+    ref = trotter.propagate(o, order, psi0=np.eye(o.D)[:, cols])          # (D, S)
+    gd = _gpu_desc(scp, desc)
+    g = scp.System(gd)
+    rows = scp.padded_indices(truncs, range(o.D))
+    psi0 = scp.basis_columns(g.D, gd["columns"], dtype=torch.complex128)
+    U = g.propagate_trotter(psi0, order).cpu().numpy().T
+    err = np.abs(U[rows, :] - ref).max()
+    rng = np.random.default_rng(8)
+    lam = rng.normal(size=(o.D, len(cols))) + 1j * rng.normal(size=(o.D, len(cols)))
+    lam_big = np.zeros((g.D, len(cols)), dtype=np.complex128)
+    lam_big[rows, :] = lam
+    cot = torch.tensor(lam_big.T.copy(), dtype=torch.complex128, device="cuda")
+    grad = g.trotter_adjoint(psi0, cot, order)
+    g.close()
+    gref = lcam.gradient(o, order, lam, np.eye(o.D)[:, cols])
+    gerr = np.abs(grad - gref).max() / np.abs(gref).max()
+    print(f"[mixed] {order} product formula err {err:.2e}, LCAM rel err {gerr:.2e}", flush=True)
+    assert err <= 1e-10, err
+    assert gerr <= 1e-9, gerr
