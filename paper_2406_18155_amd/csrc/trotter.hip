@@ -1297,10 +1297,10 @@ __device__ __forceinline__ void lc_copy(const double2* in, double2* out, int D, 
   for (int i = w0; i < D; i += LC_THREADS) out[i] = in[i];
 }
 
-// B for a gate of NL local levels: M_AB = sum over fibres of conj(mu[A]) psi[B];
-// item wi = c ent + e (from the item w0 on) sums the fibres f = c mod ch.
-// ch = 1: it adds old[0] (first item) or old[1] (the earlier sums this thread
-// loaded) and stores; else the partial sum goes to scr[e ch + c].
+// One B item of a gate of NL local levels, wi = c ent + e: the sum over the
+// fibres f = c mod ch of conj(mu[A]) psi[B] for the entry e = (A, B).  ch = 1:
+// it adds o (the entry's earlier sum, which this thread loaded) and stores;
+// else the partial sum goes to scr[e ch + c].
 template <int d, int NL>
 __device__ __forceinline__ void lc_split_item(const double2* mu, const double2* psi,
                                               const LcGate& G, const int* tab, int nf, int ch,
