@@ -6,6 +6,8 @@
         # config5_state_target.npy + config5_state_oracle.json
     python tests/golden/make_oracle_refs.py lindblad_chain
         # lindblad_chain_oracle.json
+    python tests/golden/make_oracle_refs.py lcam_chain
+        # lcam_chain_oracle.json
 
 config3_oracle.json: loss, fidelity and the full gradient of the config-3
 workload (4-fluxonium chain, CZ(q0,q1) x I x I target, 5000 RK4 steps),
@@ -149,3 +151,31 @@ def lindblad_chain():
 
 if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "lindblad_chain":
     lindblad_chain()
+
+
+LCAM_SAMPLE = 4   # columns of the chain workload in the stored LCAM gradient
+
+
+def lcam_chain():
+    """LCAM gradient (Sec. 2.5) of the Q2 product formula on the full
+    4-fluxonium chain workload (d = 5, 5000 steps of 0.02 ns, 58 parameters)
+    for 4 seeded sampled computational columns and a seeded random costate
+    (scp_inputs.random_states): the whole reverse-time walk of the workload,
+    about 20 minutes of CPU time."""
+    from oracle import lcam
+    desc = si.config3()
+    sys_ = OracleSystem(desc)
+    pos = si.sampled_columns(len(desc["columns"]), LCAM_SAMPLE)
+    cols = [int(desc["columns"][k]) for k in pos]
+    lam = si.random_states(sys_.D, len(cols), seed=si.BASE_SEED + 88)
+    g = lcam.gradient(sys_, "q2", lam, np.eye(sys_.D)[:, cols])
+    out = {"workload": "config3 shape: 4 fluxonium chain, d=5, T=100 ns, 5000 steps, Q2",
+           "generator": "tests/golden/make_oracle_refs.py lcam_chain (oracle only)",
+           "columns": cols, "costate": "scp_inputs.random_states(D, 4, seed=BASE_SEED + 88)",
+           "grad": [float(v) for v in g]}
+    with open(os.path.join(HERE, "lcam_chain_oracle.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__" and len(sys.argv) > 1 and sys.argv[1] == "lcam_chain":
+    lcam_chain()

@@ -116,6 +116,30 @@ def test_lcam_single_mode_device(scp, order):
     _compare(scp, si.random_raw_system(15, [4], 1, 3.0, 140, env="gauss"), order, seed=5)
 
 
+def test_lcam_full_chain_workload_against_stored_oracle(scp):
+    # the whole reverse-time walk of the 4-fluxonium chain workload (5000
+    # steps: 39 launches of 128 steps and a last one of 8) for 4 sampled
+    # columns and a seeded costate, against the oracle's stored gradient
+    # (tests/golden/make_oracle_refs.py lcam_chain)
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "lcam_chain_oracle.json")
+    ref = json.load(open(path))
+    desc = si.config3()
+    cols = ref["columns"]
+    print(f"[lcam] chain4_d5 full workload, 5000 steps, columns {cols}", flush=True)
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, cols, dtype=torch.complex128)
+    lam = si.random_states(g.D, len(cols), seed=si.BASE_SEED + 88)
+    cot = torch.tensor(lam.T.copy(), dtype=torch.complex128, device="cuda")
+    grad = g.trotter_adjoint(psi0, cot, "q2")
+    g.close()
+    go = np.asarray(ref["grad"])
+    err = np.abs(grad - go).max() / np.abs(go).max()
+    print(f"[lcam] full chain rel err {err:.2e}", flush=True)
+    assert err <= TOL, err
+
+
 def test_lcam_x6_workload_prefix(scp):
     # the six-fluxonium X^6 chain (d = 4, D = 4096, 148 parameters), 8 sampled
     # columns over its first 2 steps of 0.01 ns, Q4 (three pieces)
