@@ -1173,9 +1173,8 @@ lc_walk_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __restrict
 // stored once (its own slot); a pair gate's is added to the column's sum,
 // whose old value is loaded at the start of the interval by the thread that
 // adds to it.  Every sum is in a fixed order: bitwise reproducible.
-// Measured on the 4-fluxonium chain (d = 5, D = 625, Q2): an interval with a
-// pair gate takes about 7.4 us, bound by the LDS reads of the gate rows and
-// fibres of A; one with single-mode gates only about 2.9 us.
+// On the 4-fluxonium chain (d = 5, D = 625) the intervals with a pair gate
+// dominate, bound by the LDS reads of A's gate rows and fibres.
 constexpr int LC_THREADS = 512;   // split-walk workgroup (2 waves per SIMD)
 
 struct LcGate {
@@ -1484,15 +1483,22 @@ lc_walk_split_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __re
     double2 *Pn = P + nxt * D, *Un = U + nxt * D;
     const int* tc = tab + (g % 3) * nft;          // gate g
     const int* tp = tab + ((g + 2) % 3) * nft;    // gate g - 1
-    // A
-    if (hasC)
-      lc_split_apply<d>(Pc, Pn, gc, Gi + (g & 1) * NN, tc, D, tid);
-    else if (g == ng)
-      lc_copy(Pc, Pn, D, tid);
-    if (hasP)
-      lc_split_apply<d>(Uc, Un, gp, Ga + ((g - 1) & 1) * NN, tp, D, lc_first(oAm));
-    else if (g == 0)
-      lc_copy(Uc, Un, D, lc_first(oAm));
+    // A: psi' = G_g^-1 psi, then mu' = G_{g-1}^dag mu, through one copy of the
+    // code (a second inlined copy was scheduled with a wait after every LDS
+    // read of its gate rows)
+#pragma unroll 1
+    for (int v = 0; v < 2; ++v) {
+      const bool isp = v == 0;
+      const LcGate G = isp ? gc : gp;
+      const double2* in = isp ? Pc : Uc;
+      double2* out = isp ? Pn : Un;
+      const double2* Gt = isp ? Gi + (g & 1) * NN : Ga + ((g + 1) & 1) * NN;   // (g-1) & 1
+      const int w0 = isp ? tid : lc_first(oAm);
+      if (isp ? hasC : hasP)
+        lc_split_apply<d>(in, out, G, Gt, isp ? tc : tp, D, w0);
+      else if (isp ? g == ng : g == 0)
+        lc_copy(in, out, D, w0);
+    }
     // B
     if (hasP) {
       double2* sp = scr + ((g - 1) & 1) * LC_THREADS;
