@@ -1069,16 +1069,23 @@ lc_walk_kernel(LcRun R, int n_hi, int n_lo, int first, const double2* __restrict
           s0 = R.stride[R.ci[t - R.M]];
           s1 = R.stride[R.cj[t - R.M]];
         }
-        // phase A: psi <- G^-1 psi; mu <- (previous gate)^dag mu
-        if (single)
-          lc_apply1<d>(L, R.D, s0, gi);
-        else
-          lc_apply2<d>(L, R.D, s0, s1, gi);
-        if (pend != nullptr) {
-          if (pend_t < R.M)
-            lc_apply1<d>(Lm, R.D, R.stride[pend_t], pend);
+        // phase A: psi <- G^-1 psi; mu <- (previous gate)^dag mu, through one
+        // copy of the code (separately inlined copies were scheduled very
+        // differently, one with a full wait after nearly every gate read)
+#pragma unroll 1
+        for (int v = 0; v < 2; ++v) {
+          const bool isp = v == 0;
+          if (!isp && pend == nullptr) break;
+          const int pe = pend_t < R.M ? 0 : pend_t - R.M;   // pending pair gate's coupling
+          const bool one = isp ? single : pend_t < R.M;
+          const int sa = isp ? s0 : (one ? R.stride[pend_t] : R.stride[R.ci[pe]]);
+          const int sb = isp ? s1 : (one ? 0 : R.stride[R.cj[pe]]);
+          double2* Lv = isp ? L : Lm;
+          const double2* Gv = isp ? gi : pend;
+          if (one)
+            lc_apply1<d>(Lv, R.D, sa, Gv);
           else
-            lc_apply2<d>(Lm, R.D, R.stride[R.ci[pend_t - R.M]], R.stride[R.cj[pend_t - R.M]], pend);
+            lc_apply2<d>(Lv, R.D, sa, sb, Gv);
         }
         __syncthreads();
         // phase B: the gate's local reduced matrix M_AB = sum conj(mu[A]) phi[B]
