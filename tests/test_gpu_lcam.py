@@ -140,6 +140,29 @@ def test_lcam_full_chain_workload_against_stored_oracle(scp):
     assert err <= TOL, err
 
 
+@pytest.mark.parametrize("order", ["q1", "q4"])
+def test_lcam_single_column(scp, order):
+    # one column: one workgroup per walk launch (160 steps: two launches)
+    desc = si.random_raw_system(16, [3, 4], 1, 2.0, 160, env="gauss")
+    print(f"[lcam] one column, raw (3, 4) padded to d = 4, {order}", flush=True)
+    truncs = [m["trunc"] for m in desc["modes"]]
+    g = scp.System(desc)
+    col = scp.padded_indices(truncs, desc["columns"][:1])
+    psi0 = scp.basis_columns(g.D, col, dtype=torch.complex128)
+    o = OracleSystem(desc)
+    rows = scp.padded_indices(truncs, range(o.D))
+    lam = _costate(o.D, 1, 9)
+    big = np.zeros((g.D, 1), dtype=np.complex128)
+    big[rows, :] = lam
+    cot = torch.tensor(big.T.copy(), dtype=torch.complex128, device="cuda")
+    grad = g.trotter_adjoint(psi0, cot, order)
+    g.close()
+    ref = lcam.gradient(o, order, lam, np.eye(o.D)[:, desc["columns"][:1]])
+    err = np.abs(grad - ref).max() / np.abs(ref).max()
+    print(f"[lcam] one column {order} rel err {err:.2e}", flush=True)
+    assert err <= TOL, err
+
+
 def test_lcam_x6_workload_prefix(scp):
     # the six-fluxonium X^6 chain (d = 4, D = 4096, 148 parameters), 8 sampled
     # columns over its first 2 steps of 0.01 ns, Q4 (three pieces)
