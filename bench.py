@@ -439,12 +439,28 @@ def trotter_lines(scp, si, torch, np, orders=("q1", "q2", "q4", "q4j")):
                 ev[1].record(stream)
                 torch.cuda.synchronize()
                 ta = ev[0].elapsed_time(ev[1])
+                # the same gradient started from the forward's result (the
+                # walk without the gradient call's own forward)
+                g.trotter_adjoint_final(U, cot, order, workspace=wsa)
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                ev[0].record(stream)
+                g.trotter_adjoint_final(U, cot, order, workspace=wsa)
+                ev[1].record(stream)
+                torch.cuda.synchronize()
+                tf = ev[0].elapsed_time(ev[1])
+                # forward run: psi0, psi_T and its workspace; gradient run: psi0,
+                # the cotangent and its workspace, inside which it runs its own
+                # forward (the forward's workspace is not needed beside it)
                 fwd_bytes = 2 * psi0.numel() * psi0.element_size() + ws.numel()
+                grad_bytes = 2 * psi0.numel() * psi0.element_size() + wsa.numel()
                 out[-1].update({"lcam_gradient_ms": ta, "lcam_O_t": (t + ta) / t,
-                                "lcam_O_m": (fwd_bytes + wsa.numel()) / fwd_bytes,
+                                "lcam_from_final_ms": tf, "lcam_O_t_from_final": (t + tf) / t,
+                                "lcam_O_m": grad_bytes / fwd_bytes,
                                 "lcam_note": "gradient call (forward, then the reverse-time walk) "
-                                             "for a seeded costate; O_m: gradient-run device "
-                                             "bytes / forward-run device bytes"})
+                                             "for a seeded costate; from_final: the call that "
+                                             "starts from the forward's psi(T); O_m: "
+                                             "gradient-run device bytes / forward-run device "
+                                             "bytes"})
                 del wsa
             if name.startswith("x6_"):
                 out[-1]["paper_forward_s_context"] = 2.02

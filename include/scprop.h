@@ -500,6 +500,20 @@ scp_status scp_propagate_trotter_adjoint(scp_system* sys, int32_t order, int32_t
                                          void* workspace, size_t workspace_bytes, const void* psi0,
                                          const void* cotangent, double* grad_out, void* stream);
 
+/* The same LCAM gradient (Sec. 2.5) started from the forward's final state
+ * instead of its initial one: psiT (device, complex128, D x n_cols) is what
+ * scp_propagate_trotter returned for these columns with the same order, and
+ * the walk back begins there (the method needs only psi(T) and the costate at
+ * T).  The internal forward of scp_propagate_trotter_adjoint is skipped; the
+ * gate tables are rebuilt.  With psiT equal to that forward's result, the
+ * gradient is bitwise that of scp_propagate_trotter_adjoint.  Arguments,
+ * workspace size, synchronisation and errors as scp_propagate_trotter_adjoint;
+ * psiT is only read. */
+scp_status scp_propagate_trotter_adjoint_final(scp_system* sys, int32_t order, int32_t n_cols,
+                                               void* workspace, size_t workspace_bytes,
+                                               const void* psiT, const void* cotangent,
+                                               double* grad_out, void* stream);
+
 void scp_destroy(scp_system* sys);
 
 /* ------------------------------------------------------------------------

@@ -64,6 +64,10 @@ EXPORTS = {
     "scp_propagate_trotter_adjoint": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
                                                 C.c_size_t, C.c_void_p, C.c_void_p,
                                                 C.POINTER(C.c_double), C.c_void_p]),
+    "scp_propagate_trotter_adjoint_final": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32,
+                                                      C.c_void_p, C.c_size_t, C.c_void_p,
+                                                      C.c_void_p, C.POINTER(C.c_double),
+                                                      C.c_void_p]),
     "scp_lindblad_workspace_size": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t)]),
     "scp_propagate_lindblad": (C.c_int, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                          C.c_int32, C.c_void_p, C.c_size_t, C.c_void_p,

@@ -242,6 +242,24 @@ class System:
                                                   _stream_ptr(stream)))
         return np.array(g[: self.n_params])
 
+    def trotter_adjoint_final(self, psiT, cotangent, order="q2", workspace=None, stream=None):
+        """The same gradient as ``trotter_adjoint``, started from psi_I(T)
+        (S, D) complex128 as ``propagate_trotter`` returned it for the same
+        order: the internal forward is skipped."""
+        assert psiT.dtype == torch.complex128 and psiT.is_contiguous() and psiT.shape[1] == self.D
+        assert cotangent.dtype == torch.complex128 and cotangent.shape == psiT.shape
+        S = psiT.shape[0]
+        if workspace is None:
+            workspace = torch.empty(self.trotter_adjoint_workspace_bytes(order, S),
+                                    dtype=torch.uint8, device=psiT.device)
+        g = (C.c_double * max(1, self.n_params))()
+        check(lib().scp_propagate_trotter_adjoint_final(self.handle, self.TROTTER[order], S,
+                                                        _ptr(workspace),
+                                                        workspace.numel() * workspace.element_size(),
+                                                        _ptr(psiT), _ptr(cotangent.contiguous()), g,
+                                                        _stream_ptr(stream)))
+        return np.array(g[: self.n_params])
+
     # -- open systems (vectorised Lindblad equation) --------------------------
     def rates(self):
         """Per-mode (gamma1, gammaphi) of the descriptor (1/ns; absent: 0)."""

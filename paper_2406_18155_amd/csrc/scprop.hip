@@ -1191,7 +1191,24 @@ scp_status scp_propagate_trotter_adjoint(scp_system* sys, int32_t order, int32_t
   if (workspace_bytes < need)
     return fail(SCP_EINVAL, "workspace_bytes " + std::to_string(workspace_bytes) + " below the " +
                                 std::to_string(need) + " the product-formula adjoint needs");
-  return launch_trotter_adjoint(sys, order, n_cols, workspace, (const double2*)psi0,
+  return launch_trotter_adjoint(sys, order, n_cols, workspace, (const double2*)psi0, nullptr,
+                                (const double2*)cotangent, grad_out, (hipStream_t)stream);
+}
+
+scp_status scp_propagate_trotter_adjoint_final(scp_system* sys, int32_t order, int32_t n_cols,
+                                               void* workspace, size_t workspace_bytes,
+                                               const void* psiT, const void* cotangent,
+                                               double* grad_out, void* stream) {
+  g_err.clear();
+  if (!sys || !workspace || !psiT || !cotangent || !grad_out) return fail(SCP_EINVAL, "null argument");
+  if (n_cols < 1) return fail(SCP_EINVAL, "n_cols must be >= 1");
+  scp_status st = trotter_adjoint_check(sys, order);
+  if (st != SCP_OK) return st;
+  const size_t need = trotter_adjoint_workspace_bytes(sys, order, n_cols);
+  if (workspace_bytes < need)
+    return fail(SCP_EINVAL, "workspace_bytes " + std::to_string(workspace_bytes) + " below the " +
+                                std::to_string(need) + " the product-formula adjoint needs");
+  return launch_trotter_adjoint(sys, order, n_cols, workspace, nullptr, (const double2*)psiT,
                                 (const double2*)cotangent, grad_out, (hipStream_t)stream);
 }
 

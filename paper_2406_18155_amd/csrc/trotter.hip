@@ -831,6 +831,8 @@ TrGen make_gen(const scp_system* sys, int order, const TrLayout& W, double* ipar
 
 }  // namespace
 
+// psi0 == nullptr: the gate tables only (single-mode and pair gates, what
+// the adjoint reuses), no fusion and no propagation
 scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const double2* psi0,
                           double2* psiT, hipStream_t st) {
   scp_status chk = trotter_check(sys, order);
@@ -871,6 +873,7 @@ scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const dou
                      4 * d * d * sizeof(double2) + TR_MAXDRV * sizeof(double), st, G, deps, dops, dpar,
                      sg);
   HIPCHK(hipGetLastError());
+  if (psi0 == nullptr) return SCP_OK;
   double2* fg = reinterpret_cast<double2*>(base + W.fg);
   double2* fs = reinterpret_cast<double2*>(base + W.fs);
   {
@@ -1753,8 +1756,11 @@ size_t trotter_adjoint_workspace_bytes(const scp_system* sys, int order, int S) 
   return lc_layout(sys, order, S).total;
 }
 
+// psi0 given: the forward runs first (its final state into the workspace);
+// else psiT_in is that final state and only the gate tables are built
 scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, const double2* psi0,
-                                  const double2* cot, double* grad, hipStream_t st) {
+                                  const double2* psiT_in, const double2* cot, double* grad,
+                                  hipStream_t st) {
   scp_status chk = trotter_adjoint_check(sys, order);
   if (chk != SCP_OK) return chk;
   const LcLayout Y = lc_layout(sys, order, S);
@@ -1762,8 +1768,8 @@ scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, c
   const int d = sys->d, dd = d * d, M = sys->n_modes, E = (int)sys->coup.size(), N = sys->n_steps;
   char* base = static_cast<char*>(ws);
   // the forward: only its final state is kept (its gate tables are reused)
-  double2* psiT = reinterpret_cast<double2*>(base + Y.psiT);
-  scp_status s = launch_trotter(sys, order, S, ws, psi0, psiT, st);
+  const double2* psiT = psi0 ? reinterpret_cast<double2*>(base + Y.psiT) : psiT_in;
+  scp_status s = launch_trotter(sys, order, S, ws, psi0, const_cast<double2*>(psiT), st);
   if (s != SCP_OK) return s;
   // operator derivatives of every mode (FP64)
   std::vector<double> hdeps((size_t)M * 3 * d);

@@ -196,3 +196,45 @@ def test_lcam_is_repeatable_and_checks_its_workspace(scp):
     with pytest.raises(scp.ScpError, match="EINVAL.*LDS"):
         g.trotter_adjoint_workspace_bytes("q2", 256)
     g.close()
+
+
+@pytest.mark.parametrize("case", ["raw3_d3_pwc-q4j", "ring4_d3-q1", "x6-q2"])
+def test_lcam_from_final_state_matches_full_call(scp, case):
+    # the entry that starts the walk from a given psi_I(T): bitwise the full
+    # call's gradient when psi_I(T) is the product formula's own result, for
+    # the split walk (small columns) and the in-place walk (the X^6 chain);
+    # psi_I(T) is only read
+    import ctypes as C
+    from paper_2406_18155_amd._lib import SCP_EINVAL, lib
+    name, order = case.split("-")
+    if name == "x6":
+        full = si.fluxonium6_x6()
+        desc = _prefix(full, 2)
+        cols = [int(c) for c in np.asarray(full["columns"])[si.sampled_columns(len(full["columns"]))]]
+    else:
+        desc = CASES[name]()
+        cols = desc["columns"]
+    print(f"[lcam] from the final state, {name} {order}", flush=True)
+    g = scp.System(desc)
+    psi0 = scp.basis_columns(g.D, cols, dtype=torch.complex128)
+    cot = torch.tensor(_costate(g.D, len(cols), 5).T.copy(), device="cuda")
+    ref = g.trotter_adjoint(psi0, cot, order)
+    psiT = g.propagate_trotter(psi0, order)
+    keep = psiT.clone()
+    got = g.trotter_adjoint_final(psiT, cot, order)
+    assert np.array_equal(got, ref)
+    assert torch.equal(psiT, keep)
+    need = g.trotter_adjoint_workspace_bytes(order, psi0.shape[0])
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    gr = (C.c_double * g.n_params)()
+    code = g.TROTTER[order]
+    st = lib().scp_propagate_trotter_adjoint_final(g.handle, code, psi0.shape[0],
+                                                   C.c_void_p(ws.data_ptr()), need - 1,
+                                                   C.c_void_p(psiT.data_ptr()),
+                                                   C.c_void_p(cot.data_ptr()), gr, None)
+    assert st == SCP_EINVAL
+    st = lib().scp_propagate_trotter_adjoint_final(g.handle, code, psi0.shape[0],
+                                                   C.c_void_p(ws.data_ptr()), need, None,
+                                                   C.c_void_p(cot.data_ptr()), gr, None)
+    assert st == SCP_EINVAL
+    g.close()
