@@ -257,8 +257,7 @@ size_t trotter_workspace_bytes(const scp_system* sys, int order);
 size_t trotter_adjoint_workspace_bytes(const scp_system* sys, int order, int S);
 scp_status trotter_adjoint_check(const scp_system* sys, int order);
 scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, const double2* psi0,
-                                  const double2* psiT_in, const double2* cot, double* grad,
-                                  hipStream_t st);
+                                  const double2* cot, double* grad, hipStream_t st);
 scp_status launch_trotter(scp_system* sys, int order, int S, void* ws, const double2* psi0,
                           double2* psiT, hipStream_t st);
 size_t lindblad_workspace_bytes(const scp_system* sys);

@@ -9,6 +9,7 @@
 #include <set>
 
 #include "internal.h"
+#include "trotter.h"
 
 namespace scp {
 
@@ -1191,7 +1192,7 @@ scp_status scp_propagate_trotter_adjoint(scp_system* sys, int32_t order, int32_t
   if (workspace_bytes < need)
     return fail(SCP_EINVAL, "workspace_bytes " + std::to_string(workspace_bytes) + " below the " +
                                 std::to_string(need) + " the product-formula adjoint needs");
-  return launch_trotter_adjoint(sys, order, n_cols, workspace, (const double2*)psi0, nullptr,
+  return launch_trotter_adjoint(sys, order, n_cols, workspace, (const double2*)psi0,
                                 (const double2*)cotangent, grad_out, (hipStream_t)stream);
 }
 
@@ -1208,8 +1209,8 @@ scp_status scp_propagate_trotter_adjoint_final(scp_system* sys, int32_t order, i
   if (workspace_bytes < need)
     return fail(SCP_EINVAL, "workspace_bytes " + std::to_string(workspace_bytes) + " below the " +
                                 std::to_string(need) + " the product-formula adjoint needs");
-  return launch_trotter_adjoint(sys, order, n_cols, workspace, nullptr, (const double2*)psiT,
-                                (const double2*)cotangent, grad_out, (hipStream_t)stream);
+  return launch_trotter_adjoint_final(sys, order, n_cols, workspace, (const double2*)psiT,
+                                      (const double2*)cotangent, grad_out, (hipStream_t)stream);
 }
 
 scp_status scp_fidelity(const void* U, int64_t D, int32_t S, int32_t precision, int32_t d_c,

@@ -40,7 +40,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "internal.h"
+#include "trotter.h"
 
 namespace scp {
 
@@ -1758,9 +1758,9 @@ size_t trotter_adjoint_workspace_bytes(const scp_system* sys, int order, int S) 
 
 // psi0 given: the forward runs first (its final state into the workspace);
 // else psiT_in is that final state and only the gate tables are built
-scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, const double2* psi0,
-                                  const double2* psiT_in, const double2* cot, double* grad,
-                                  hipStream_t st) {
+static scp_status lc_adjoint(scp_system* sys, int order, int S, void* ws, const double2* psi0,
+                             const double2* psiT_in, const double2* cot, double* grad,
+                             hipStream_t st) {
   scp_status chk = trotter_adjoint_check(sys, order);
   if (chk != SCP_OK) return chk;
   const LcLayout Y = lc_layout(sys, order, S);
@@ -1927,6 +1927,17 @@ scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, c
   }
   if (!finite) return fail(SCP_ENONFINITE, "gradient is not finite");
   return SCP_OK;
+}
+
+scp_status launch_trotter_adjoint(scp_system* sys, int order, int S, void* ws, const double2* psi0,
+                                  const double2* cot, double* grad, hipStream_t st) {
+  return lc_adjoint(sys, order, S, ws, psi0, nullptr, cot, grad, st);
+}
+
+scp_status launch_trotter_adjoint_final(scp_system* sys, int order, int S, void* ws,
+                                        const double2* psiT, const double2* cot, double* grad,
+                                        hipStream_t st) {
+  return lc_adjoint(sys, order, S, ws, nullptr, psiT, cot, grad, st);
 }
 
 }  // namespace scp
