@@ -1,6 +1,9 @@
-"""torch.autograd front end: U = propagate(theta) whose backward is the
+"""torch.autograd front ends: U = propagate(theta) whose backward is the
 library's hand-written discrete adjoint (Sec. 2.5; checkpoints every
-ceil(sqrt(N)) steps).
+ceil(sqrt(N)) steps), and U = propagate_trotter(theta) (the product formulas,
+complex FP64) whose backward is the local continuous adjoint of Sec. 2.5,
+started from the forward's final state: nothing but U is kept between the
+two passes.
 
 theta holds the gradient parameters in the library's order: drive
 parameters (drive order, then parameter order), then (E_J, E_C, E_L) of every
@@ -12,7 +15,8 @@ picture and are inputs of the method, not parameters.
 PyTorch hands the backward 2 dL/dU* for a real loss of complex U; the library
 takes dL/dU*, so the cotangent is halved.  The backward returns dL/dtheta
 (FP64 from the library, cast to theta's dtype and device); psi0 gets no
-gradient.  Only the FP32 path (complex64 psi0) has an adjoint.
+gradient.  The RK4 adjoint exists for the FP32 path (complex64 psi0), the
+product-formula adjoint for complex128 psi0.
 """
 from __future__ import annotations
 
@@ -99,3 +103,43 @@ class _Propagate(torch.autograd.Function):
 def propagate(model: Model, theta: torch.Tensor, psi0: torch.Tensor) -> torch.Tensor:
     """U (S, D) complex64 for parameters theta; differentiable in theta."""
     return _Propagate.apply(theta, psi0, model)
+
+
+class _PropagateTrotter(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, theta, psi0, model, order):
+        if psi0.dtype != torch.complex128:
+            raise ValueError("the product formulas run in complex FP64: psi0 must be complex128")
+        g = System(model.desc_at(theta.detach().cpu().numpy()))
+        try:
+            U = g.propagate_trotter(psi0.detach().contiguous(), order)
+        except BaseException:
+            g.close()
+            raise
+        ctx.solve = (g, order)
+        # the walk back starts from exactly this state: an in-place change of
+        # U before the backward is reported by autograd
+        ctx.save_for_backward(U)
+        ctx.theta_dtype, ctx.theta_device = theta.dtype, theta.device
+        return U
+
+    @staticmethod
+    def backward(ctx, gU):
+        g, order = ctx.solve
+        (U,) = ctx.saved_tensors
+        cot = (0.5 * gU).to(torch.complex128).contiguous()
+        try:
+            grad = g.trotter_adjoint_final(U, cot, order)
+        finally:
+            g.close()
+            ctx.solve = None
+        return (torch.as_tensor(grad, dtype=ctx.theta_dtype, device=ctx.theta_device),
+                None, None, None)
+
+
+def propagate_trotter(model: Model, theta: torch.Tensor, psi0: torch.Tensor,
+                      order: str = "q2") -> torch.Tensor:
+    """psi_I(T) (S, D) complex128 of the product formula ``order`` ("q1",
+    "q2", "q4", "q4j") for parameters theta; differentiable in theta through
+    the local continuous adjoint."""
+    return _PropagateTrotter.apply(theta, psi0, model, order)

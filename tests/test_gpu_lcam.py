@@ -238,3 +238,29 @@ def test_lcam_from_final_state_matches_full_call(scp, case):
                                                    C.c_void_p(cot.data_ptr()), gr, None)
     assert st == SCP_EINVAL
     g.close()
+
+
+@pytest.mark.parametrize("name,order", [("fluxonium3_d5", "q2"), ("ring4_d3", "q4j")])
+def test_lcam_through_torch_autograd(scp, name, order):
+    # theta -> psi_I(T) through torch.autograd (backward: the LCAM walk from
+    # the forward's result), L = sum |psi_I(T) - B|^2 in torch, whose
+    # costate dL/dpsi* = psi_I(T) - B is written out for the oracle
+    desc = CASES[name]()
+    print(f"[lcam] autograd {name} {order}", flush=True)
+    model = scp.autograd.Model(desc)
+    theta = torch.tensor(model.theta0, dtype=torch.float64, requires_grad=True)
+    psi0 = scp.basis_columns(model.D, desc["columns"], dtype=torch.complex128)
+    B = torch.tensor(_costate(model.D, len(desc["columns"]), 7).T.copy(), device="cuda")
+    U = scp.autograd.propagate_trotter(model, theta, psi0, order)
+    L = ((U - B).abs() ** 2).sum()
+    L.backward()
+    g_auto = theta.grad.numpy()
+    lam = (U.detach() - B).cpu().numpy().T
+    o = OracleSystem(model.desc_at(model.theta0))
+    ref = lcam.gradient(o, order, lam, np.eye(o.D)[:, desc["columns"]])
+    err = np.abs(g_auto - ref).max() / np.abs(ref).max()
+    print(f"[lcam] autograd {order} rel err {err:.2e}", flush=True)
+    assert err <= TOL, err
+    g = scp.System(model.desc_at(model.theta0))
+    assert torch.equal(U.detach(), g.propagate_trotter(psi0, order))
+    g.close()
