@@ -29,12 +29,14 @@ launch stream around every launch (scp_system_set_timing).
 Beside the timed steps (not part of ``value``): one forward of the same
 workload on the plain complex FP64 GPU path (the speedup denominator), the
 open-system (Lindblad) propagation of a 4-fluxonium chain's 256 computational
-matrix units (``open_system``), and a serving replay of the first requests of the mixed request stream (2-6 modes,
+matrix units (``open_system``), the second-order product formula on the
+4-fluxonium chain with its LCAM gradient (``product_formula``), and a serving replay of the first requests of the mixed request stream (2-6 modes,
 d in {3,4,5}, T in [20,200] ns, half with gradients): saturated throughput,
 then Poisson arrivals at 0.5x and 0.9x that throughput, with p50/p99 latency.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
                     [--serve-requests R] [--no-plain64] [--no-lindblad]
+                    [--no-product-formula]
     python bench.py --lindblad | --trotter | --configs | --cpu-protocol
 """
 from __future__ import annotations
@@ -380,7 +382,7 @@ def trotter_flop(desc, order):
     return alg, exe
 
 
-def trotter_lines(scp, si, torch, np, orders=("q1", "q2", "q4", "q4j")):
+def trotter_lines(scp, si, torch, np, orders=("q1", "q2", "q4", "q4j"), only=None):
     """Suzuki-Trotter product formulas on the 8-transmon ring (D = 6561, 256
     columns, 3000 steps), the 4-fluxonium chain (D = 625, 16 columns, 5000
     steps) and the 6-fluxonium X^6 chain (D = 4096, 64 columns, 5000 steps):
@@ -399,6 +401,8 @@ def trotter_lines(scp, si, torch, np, orders=("q1", "q2", "q4", "q4j")):
                              ("x6_chain6_d4: 6-fluxonium multipath chain d=4, D=4096, 64 columns, "
                               "T=50 ns, 5000 steps of 0.01 ns (the paper's X^6 benchmark shape)",
                               si.fluxonium6_x6(), ("q2",))):
+        if only is not None and not name.startswith(only):
+            continue
         g = scp.System(desc)
         S = len(desc["columns"])
         psi0 = scp.basis_columns(g.D, desc["columns"], dtype=torch.complex128)
@@ -467,6 +471,8 @@ def trotter_lines(scp, si, torch, np, orders=("q1", "q2", "q4", "q4j")):
                 out[-1]["paper_context"] = ("SuperGrad Q2 forward of its X^6 task on a 32-core "
                                             "EPYC 7513, truncation not stated (Sec. 4.2 table)")
         g.close()
+    if only is not None:
+        return out
     # oracle on a bounded sample of the ring
     desc = si.config5()
     cols = np.asarray(desc["columns"])[si.sampled_columns(len(desc["columns"]))]
@@ -755,6 +761,7 @@ def main():
     ap.add_argument("--lindblad", action="store_true",
                     help="only time the open-system (Lindblad) propagation (one JSON line) and exit")
     ap.add_argument("--no-lindblad", action="store_true")
+    ap.add_argument("--no-product-formula", action="store_true")
     ap.add_argument("--cpu-protocol", action="store_true",
                     help="only run the oracle's full CPU timing protocol (long) and exit")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -1004,6 +1011,8 @@ def main():
         out["serving"] = serving_leg(scp, si, torch, np, args.serve_requests)
     if not args.no_lindblad:
         out["open_system"] = lindblad_line(scp, si, torch, np)
+    if not args.no_product_formula:
+        out["product_formula"] = trotter_lines(scp, si, torch, np, ("q2",), only="chain4_d5")[0]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(si, np)
     print(json.dumps(out))
