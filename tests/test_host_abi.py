@@ -146,3 +146,21 @@ def test_padded_indices_map_product_states_to_the_uniform_index_space():
     assert padded_indices([4, 4], range(16)) == list(range(16))
     with pytest.raises(ValueError):
         padded_indices([2, 3], [6])
+
+
+def test_header_compiles_as_c11():
+    # include/scprop.h is a C header: it compiles as C11 with every warning
+    # an error (the C ABI must not need a C++ compiler)
+    import shutil
+    import subprocess
+    import tempfile
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "h.c")
+        with open(src, "w") as f:
+            f.write('#include "scprop.h"\nint main(void) { return SCP_OK; }\n')
+        subprocess.check_call([gcc, "-std=c11", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                               "-fsyntax-only", "-I", os.path.join(root, "include"), src])
