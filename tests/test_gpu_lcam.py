@@ -198,12 +198,13 @@ def test_lcam_is_repeatable_and_checks_its_workspace(scp):
     g.close()
 
 
-@pytest.mark.parametrize("case", ["raw3_d3_pwc-q4j", "ring4_d3-q1", "x6-q2"])
+@pytest.mark.parametrize("case", ["raw3_d3_pwc-q4j", "ring4_d3-q1", "x6-q2", "raw34-q4"])
 def test_lcam_from_final_state_matches_full_call(scp, case):
     # the entry that starts the walk from a given psi_I(T): bitwise the full
     # call's gradient when psi_I(T) is the product formula's own result, for
-    # the split walk (small columns) and the in-place walk (the X^6 chain);
-    # psi_I(T) is only read
+    # the split walk (small columns) and the in-place walk (the X^6 chain),
+    # and over two walk launches (160 steps: only the first reads psi_I(T))
+    # on a (3, 4)-truncation device; psi_I(T) is only read
     import ctypes as C
     from paper_2406_18155_amd._lib import SCP_EINVAL, lib
     name, order = case.split("-")
@@ -211,6 +212,9 @@ def test_lcam_from_final_state_matches_full_call(scp, case):
         full = si.fluxonium6_x6()
         desc = _prefix(full, 2)
         cols = [int(c) for c in np.asarray(full["columns"])[si.sampled_columns(len(full["columns"]))]]
+    elif name == "raw34":
+        desc = si.random_raw_system(16, [3, 4], 1, 2.0, 160, env="gauss")
+        cols = scp.padded_indices([3, 4], desc["columns"][:2])
     else:
         desc = CASES[name]()
         cols = desc["columns"]
